@@ -1,0 +1,282 @@
+"""Pins for the oracle's lattice operators (CPU only).
+
+Each test checks the oracle against something other than itself: the Dirac and
+su(3) algebra, brute-force geometry, the free-field momentum-space form of the
+Wilson hopping term, gamma5-hermiticity, gauge covariance, a closed-form abelian
+clover background, and the dense Schur-complement / determinant identity.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_02652_amd import synth
+
+DIMS = (4, 4, 4, 4)
+
+
+def coords(dims, lex):
+    c = []
+    for L in dims:
+        c.append(lex % L)
+        lex //= L
+    return c
+
+
+# ---------------------------------------------------------------- algebra
+
+def test_gamma_algebra():
+    g = [oracle.gamma(m) for m in range(4)]
+    g5 = oracle.gamma(4)
+    for m in range(4):
+        assert np.allclose(g[m], g[m].conj().T, atol=0)
+        for n in range(4):
+            ac = g[m] @ g[n] + g[n] @ g[m]
+            assert np.allclose(ac, 2 * np.eye(4) * (m == n), atol=0)
+    assert np.allclose(g5, g[0] @ g[1] @ g[2] @ g[3], atol=0)
+    assert np.allclose(g5, np.diag([1, 1, -1, -1]), atol=0)
+    # sigma_{mu nu} = (i/2)[g_mu, g_nu] is block-diagonal in this chiral basis
+    for m, n in itertools.combinations(range(4), 2):
+        s = 0.5j * (g[m] @ g[n] - g[n] @ g[m])
+        assert np.allclose(s[:2, 2:], 0) and np.allclose(s[2:, :2], 0)
+
+
+def test_su3_generators():
+    T = [oracle.generator(a) for a in range(8)]
+    for a in range(8):
+        assert np.allclose(T[a], T[a].conj().T)
+        assert abs(np.trace(T[a])) < 1e-15
+        for b in range(8):
+            assert abs(np.trace(T[a] @ T[b]) - 0.5 * (a == b)) < 1e-15
+    # structure constant f_123 = 1: [T1, T2] = i T3
+    assert np.allclose(T[0] @ T[1] - T[1] @ T[0], 1j * T[2])
+    # f_458 = sqrt(3)/2
+    assert np.allclose(T[3] @ T[4] - T[4] @ T[3], 1j * (0.5 * T[2] + math.sqrt(3) / 2 * T[7]))
+
+
+# ---------------------------------------------------------------- geometry
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 4, 8)])
+def test_index_maps_brute_force(dims):
+    V = int(np.prod(dims))
+    lexeo, nbr, sign = oracle.index_maps(dims, tbc=-1)
+    for p in range(2):
+        got = sorted(lexeo[p])
+        want = [x for x in range(V) if sum(coords(dims, x)) % 2 == p]
+        assert got == want
+        for i in range(V // 2):
+            x = lexeo[p, i]
+            assert x // 2 == i
+            c = coords(dims, x)
+            for mu in range(4):
+                for b, step in enumerate((+1, -1)):
+                    d = list(c)
+                    d[mu] = (d[mu] + step) % dims[mu]
+                    y = d[0] + dims[0] * (d[1] + dims[1] * (d[2] + dims[2] * d[3]))
+                    j = nbr[p, i, 2 * mu + b]
+                    assert lexeo[1 - p, j] == y
+                    wraps = mu == 3 and ((step == 1 and c[3] == dims[3] - 1) or (step == -1 and c[3] == 0))
+                    assert sign[p, i, 2 * mu + b] == (-1 if wraps else 1)
+                    # the opposite hop returns
+                    assert nbr[1 - p, j, 2 * mu + (1 - b)] == i
+
+
+# ---------------------------------------------------------------- free field
+
+def plane_wave(dims, n, u, parity):
+    """e^{ipx} u on the sites of one parity, p_i = 2 pi n_i / L_i, p_t = 2 pi (n_t + 1/2) / T."""
+    lexeo, _, _ = oracle.index_maps(dims)
+    p = [2 * math.pi * n[m] / dims[m] for m in range(3)] + [2 * math.pi * (n[3] + 0.5) / dims[3]]
+    out = np.zeros((len(lexeo[parity]), 4, 3), np.complex128)
+    for i, x in enumerate(lexeo[parity]):
+        c = coords(dims, x)
+        out[i] = np.exp(1j * sum(p[m] * c[m] for m in range(4))) * u
+    return out, p
+
+
+@pytest.mark.parametrize("n", [(0, 0, 0, 0), (1, 0, 2, 1), (3, 1, 1, 2)])
+def test_free_field_plane_wave(n):
+    """U = 1: D_eo D_oe e^{ipx}u = [a^2 - |b|^2 - 2 i a (b.gamma)] e^{ipx}u,
+    a = 2 sum cos p_mu, b_mu = 2 sin p_mu (antiperiodic t momenta)."""
+    U = synth.unit_gauge(DIMS)
+    op = oracle.Operator(DIMS, U, 0.12, 1.7)
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    psi, p = plane_wave(DIMS, n, u, 0)
+    a = 2 * sum(math.cos(q) for q in p)
+    b = [2 * math.sin(q) for q in p]
+    bg = sum(b[m] * oracle.gamma(m) for m in range(4))
+    mat = (a * a - sum(x * x for x in b)) * np.eye(4) - 2j * a * bg
+    want = np.einsum("st,itc->isc", mat, psi)
+    got = op.hop_eo(0, op.hop_eo(1, psi))
+    assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want)) + 1e-13
+    # and Mhat = 1 - kappa^2 D_eo D_oe on the free field (A = 1 there)
+    gotM = op.M(psi)
+    assert np.max(np.abs(gotM - (psi - 0.12 ** 2 * want))) < 1e-12
+
+
+def test_free_field_K_extremes():
+    """Free-field Khat spectrum: eigenvalues |1 - kappa^2 (a -/+ i|b|)^2|^2 over the
+    lattice momenta; the extreme ones are eigenvalues of the oracle's Khat."""
+    kappa = 0.12
+    U = synth.unit_gauge(DIMS)
+    op = oracle.Operator(DIMS, U, kappa, 1.0)
+    best = {}
+    for n in itertools.product(*[range(L) for L in DIMS]):
+        p = [2 * math.pi * n[m] / DIMS[m] for m in range(3)] + [2 * math.pi * (n[3] + 0.5) / DIMS[3]]
+        a = 2 * sum(math.cos(q) for q in p)
+        bn = math.sqrt(sum((2 * math.sin(q)) ** 2 for q in p))
+        for sgn in (+1, -1):
+            lam = abs(1 - kappa ** 2 * (a + sgn * 1j * bn) ** 2) ** 2
+            for key, cmp in (("min", lambda x, y: x < y), ("max", lambda x, y: x > y)):
+                if key not in best or cmp(lam, best[key][0]):
+                    best[key] = (lam, n, sgn, p, bn)
+    for key in ("min", "max"):
+        lam, n, sgn, p, bn = best[key]
+        b = [2 * math.sin(q) for q in p]
+        bg = sum(b[m] * oracle.gamma(m) for m in range(4))
+        w, v = np.linalg.eigh(bg)
+        # eigenvector of b.gamma with eigenvalue -sgn*|b| gives (a + sgn i |b|)
+        idx = int(np.argmin(np.abs(w - (-sgn * bn)))) if bn > 0 else 0
+        u = np.outer(v[:, idx], [1.0, 0.3j, -0.2])
+        psi, _ = plane_wave(DIMS, n, u, 0)
+        Kpsi = op.K(psi)
+        assert np.max(np.abs(Kpsi - lam * psi)) < 1e-12
+    assert abs(best["min"][0] - 0.1475) < 5e-4 and abs(best["max"][0] - 1.399) < 5e-4
+
+
+# ---------------------------------------------------------------- symmetries
+
+@pytest.fixture(scope="module")
+def rough():
+    U = synth.random_gauge(DIMS, seed=0)
+    return U, oracle.Operator(DIMS, U, 0.12, 1.0)
+
+
+def test_gamma5_hermiticity(rough):
+    U, op = rough
+    x = synth.gaussian_spinor(128, 1)
+    y = synth.gaussian_spinor(128, 2)
+    lhs = np.vdot(x, op.M(y, dagger=True))
+    rhs = np.vdot(op.M(x), y)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    g5 = np.diag([1, 1, -1, -1])
+    g5y = np.einsum("st,itc->isc", g5, y)
+    assert np.max(np.abs(op.M(y, dagger=True) - np.einsum("st,itc->isc", g5, op.M(g5y)))) < 1e-13
+    Kx = op.K(x)
+    assert abs(np.vdot(y, Kx) - np.conj(np.vdot(x, op.K(y)))) < 1e-11 * abs(np.vdot(y, Kx))
+    assert np.vdot(x, Kx).real > 0
+
+
+def test_gauge_covariance(rough):
+    """Mhat[U^W](W psi) = W Mhat[U] psi for a random periodic gauge transform W."""
+    U, op = rough
+    V = U.shape[0]
+    W = synth.random_su3(V, seed=7)
+    lexeo, _, _ = oracle.index_maps(DIMS)
+    Ug = np.empty_like(U)
+    for x in range(V):
+        c = coords(DIMS, x)
+        for mu in range(4):
+            d = list(c)
+            d[mu] = (d[mu] + 1) % DIMS[mu]
+            y = d[0] + DIMS[0] * (d[1] + DIMS[1] * (d[2] + DIMS[2] * d[3]))
+            Ug[x, mu] = W[x] @ U[x, mu] @ W[y].conj().T
+    opg = oracle.Operator(DIMS, Ug, 0.12, 1.0)
+    psi = synth.gaussian_spinor(128, 3)
+    We = W[lexeo[0]]
+    rot = lambda f: np.einsum("iab,isb->isa", We, f)
+    assert np.max(np.abs(opg.M(rot(psi)) - rot(op.M(psi)))) < 1e-12
+    assert abs(opg.logdet_action() - op.logdet_action()) < 1e-10
+    assert abs(oracle.gauge_action(DIMS, Ug, 5.6) - oracle.gauge_action(DIMS, U, 5.6)) < 1e-9
+
+
+# ---------------------------------------------------------------- clover
+
+def test_clover_structure(rough):
+    U, op = rough
+    g5 = np.kron(np.diag([1, 1, -1, -1]), np.eye(3))
+    for x in (0, 17, 200):
+        A, Ai, ld = op.clover_at(x)
+        assert np.allclose(A, A.conj().T, atol=1e-15)
+        assert np.allclose(A @ g5, g5 @ A, atol=1e-15)        # chiral block structure
+        assert np.allclose(A @ Ai, np.eye(12), atol=1e-13)
+        w = np.linalg.eigvalsh(A)
+        assert w.min() > 0
+        assert abs(ld.real - np.sum(np.log(w))) < 1e-13 and abs(ld.imag) < 1e-12
+    Uf = synth.unit_gauge(DIMS)
+    A, _, _ = oracle.Operator(DIMS, Uf, 0.13, 2.0).clover_at(5)
+    assert np.allclose(A, np.eye(12), atol=0)
+
+
+def test_clover_abelian_background():
+    """Constant abelian field in the (x,y) plane with plaquette angle theta on
+    colour 0 (and -theta on colour 1): every leaf equals exp(i q theta), so
+    Fhat = i sin(theta) q and A = 1 - kappa csw sin(theta) q sigma_xy."""
+    dims = (4, 4, 4, 4)
+    theta = 2 * math.pi / 16           # flux quantum on the 4x4 plane
+    V = 256
+    U = synth.unit_gauge(dims)
+    for x in range(V):
+        c = coords(dims, x)
+        # U_y(x) = exp(i theta q x); the x-links across the x boundary carry
+        # exp(-i theta Lx y q) so that the wrapping plaquettes hold the same flux
+        phase_y = theta * c[0]
+        U[x, 1] = np.diag([np.exp(1j * phase_y), np.exp(-1j * phase_y), 1.0])
+        if c[0] == dims[0] - 1:
+            ph = -theta * dims[0] * c[1]
+            U[x, 0] = np.diag([np.exp(1j * ph), np.exp(-1j * ph), 1.0])
+    kappa, csw = 0.13, 1.7
+    op = oracle.Operator(dims, U, kappa, csw)
+    g = [oracle.gamma(m) for m in range(4)]
+    sxy = 0.5j * (g[0] @ g[1] - g[1] @ g[0])
+    for x in (0, 37, 255):
+        A, _, _ = op.clover_at(x)
+        q = np.diag([1.0, -1.0, 0.0])
+        want = np.eye(12) - kappa * csw * math.sin(theta) * np.kron(sxy, q)
+        assert np.allclose(A, want, atol=1e-14)
+    # only the (x,y) plaquettes carry flux: (2 cos theta + 1)/3 there, 1 elsewhere
+    assert abs(oracle.plaquette(dims, U) - (5 + (2 * math.cos(theta) + 1) / 3) / 6) < 1e-13
+
+
+# ---------------------------------------------------------------- dense Schur
+
+@pytest.mark.slow
+def test_dense_schur_and_determinant(rough):
+    """On 4^4: Mhat equals the Schur complement of the dense full M on the even
+    block, and det M = det A_oo det Mhat."""
+    U, op = rough
+    kappa = op.kappa
+    V, Vh = 256, 128
+    lexeo, _, _ = oracle.index_maps(DIMS)
+    order = np.concatenate([lexeo[0], lexeo[1]])
+    n = 12 * V
+    # dense M = A - kappa D_hop, columns from unit vectors, rows/cols ordered (even | odd)
+    Mf = np.zeros((n, n), np.complex128)
+    for j in range(n):
+        e = np.zeros((V, 4, 3), np.complex128)
+        site = order[j // 12]
+        e[site].flat[j % 12] = 1.0
+        col = -kappa * op.hop_full(e)
+        Mf[:, j] = col[order].reshape(-1)
+    for k, site in enumerate(order):
+        A, _, _ = op.clover_at(site)
+        Mf[12 * k:12 * k + 12, 12 * k:12 * k + 12] += A
+    h = 12 * Vh
+    Mee, Meo, Moe, Moo = Mf[:h, :h], Mf[:h, h:], Mf[h:, :h], Mf[h:, h:]
+    S = Mee - Meo @ np.linalg.solve(Moo, Moe)
+    Mhat = np.zeros((h, h), np.complex128)
+    for j in range(h):
+        e = np.zeros((Vh, 4, 3), np.complex128)
+        e.reshape(-1)[j] = 1.0
+        Mhat[:, j] = op.M(e).reshape(-1)
+    assert np.max(np.abs(Mhat - S)) < 1e-12
+    s1, l1 = np.linalg.slogdet(Mf)
+    s2, l2 = np.linalg.slogdet(Moo)
+    s3, l3 = np.linalg.slogdet(Mhat)
+    assert abs(l1 - (l2 + l3)) < 1e-9 * abs(l1)
+    assert abs(s1 - s2 * s3) < 1e-9
+    # -2 sum_odd ln det A equals -2 ln det A_oo
+    assert abs(op.logdet_action() - (-2 * l2)) < 1e-9
