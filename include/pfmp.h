@@ -1,0 +1,282 @@
+/*
+ * pfmp.h -- C-ABI of libpfmp, the MI355X (gfx950) hot path of polynomial-filtered
+ * mass-preconditioned Hybrid Monte Carlo for two-flavour lattice QCD
+ * (Haar, Kamleh, Zanotti, Nakamura, arXiv:1609.02652).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Return value: 0 on success, else a negative PFMP_ERR_* code; the message of
+ * the last failure on a context is returned by pfmp_last_error().
+ *
+ * Lattice: dims[4] = (Lx, Ly, Lz, Lt), every extent even and >= 4.  Sites are
+ * numbered lexicographically, lex = x + Lx*(y + Ly*(z + Lz*t)); parity =
+ * (x+y+z+t) mod 2 (0 = even); the even-odd index of a site is lex/2.  Gauge links
+ * are periodic; a fermion hop that crosses the t boundary takes the factor t_bc
+ * (-1: antiperiodic).
+ *
+ * Dirac matrices: chiral basis, g_k = [[0, -i s_k], [i s_k, 0]] (k = x,y,z),
+ * g_t = [[0, 1], [1, 0]], g_5 = diag(1, 1, -1, -1).  Lie algebra: T_a = lambda_a/2.
+ *
+ * Operators (paper Sec. 2.1 fermion matrix M, K = M^dag M; Table 3.1 "even-odd
+ * Wilson", extended by the clover term):
+ *   D_hop psi(x) = sum_mu [(1-g_mu) U_mu(x) psi(x+mu) + (1+g_mu) U_mu(x-mu)^dag psi(x-mu)]
+ *   M    = A - kappa D_hop,   A = 1 + i kappa c_sw sum_{mu<nu} sigma_mu_nu Fhat_mu_nu,
+ *   Fhat = (Q - Q^dag)/8 over the four clover leaves, sigma = (i/2)[g_mu, g_nu],
+ *   Mhat = A_ee - kappa^2 D_eo A_oo^-1 D_oe   (even sites; det M = det A_oo det Mhat),
+ *   Khat = Mhat^dag Mhat  (one "K multiplication", the paper's unit of cost).
+ * An operator is selected by a slot index 0..PFMP_MAX_OPS-1 configured with
+ * pfmp_set_operator(); the Hasenbusch operators J = W^dag W of the paper are the
+ * same operator at a heavier kappa in another slot.
+ *
+ * Memory: every field buffer is DEVICE memory owned by the caller (the library
+ * never frees it).  Fields passed to the compute calls are in the library's
+ * internal layout; pfmp_pack_* / pfmp_unpack_* convert from / to the canonical
+ * layouts:
+ *   gauge    [V][4][3][3] complex128 (lexicographic sites)
+ *   spinor   [Vh][4][3]   complex128 on one parity (even-odd index)
+ *   momenta  [V][4][8]    float64, coefficients of T_a (P = sum_a p_a T_a)
+ * pfmp_field_bytes() gives the size of an internal buffer.  The context owns only
+ * its geometry, gauge copy, per-slot clover fields and solver workspace.
+ *
+ * Ordering: every call is enqueued on the context's stream and is asynchronous,
+ * except calls that return host scalars (solver statistics, actions, dot
+ * products), which synchronise the stream before returning.
+ */
+#ifndef PFMP_H
+#define PFMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PFMP_OK 0
+#define PFMP_ERR_ARG (-1)    /* null pointer, bad extent, bad slot or size */
+#define PFMP_ERR_HIP (-2)    /* a HIP runtime call failed; see pfmp_last_error */
+#define PFMP_ERR_NOCONV (-3) /* solver reached maxiter; x holds the last iterate */
+#define PFMP_ERR_OOM (-4)    /* device allocation failed */
+#define PFMP_ERR_STATE (-5)  /* call needs a gauge field / operator not yet set */
+
+#define PFMP_MAX_OPS 8
+#define PFMP_MAX_SHIFTS 128
+
+typedef struct pfmp_ctx pfmp_ctx;
+
+/* Precision of a field buffer or of an operator application. */
+typedef enum {
+    PFMP_F64 = 0,      /* complex128 storage, FP64 arithmetic */
+    PFMP_F32 = 1,      /* complex64 storage, FP32 arithmetic */
+    PFMP_F16 = 2       /* IEEE half spinor storage with one FP32 scale per site; FP32 arithmetic */
+} pfmp_prec;
+
+/* Kinds of internal buffers for pfmp_field_bytes. */
+typedef enum {
+    PFMP_FIELD_SPINOR = 0,   /* one parity */
+    PFMP_FIELD_GAUGE = 1,    /* canonical gauge field (input of pfmp_set_gauge), V*4*9 complex128 */
+    PFMP_FIELD_MOMENTA = 2   /* momenta / forces, V*4*8 float64 */
+} pfmp_field;
+
+/* ---- context ---------------------------------------------------------------- */
+
+/* Create a context for a lattice.  stream: hipStream_t to enqueue on (NULL = the
+ * null stream).  Errors: PFMP_ERR_ARG (odd or < 4 extent), PFMP_ERR_OOM. */
+int pfmp_create(const int dims[4], int t_bc, void *stream, pfmp_ctx **out);
+int pfmp_destroy(pfmp_ctx *ctx);
+const char *pfmp_last_error(pfmp_ctx *ctx);
+/* Bytes of an internal field of the given kind and precision. */
+long long pfmp_field_bytes(pfmp_ctx *ctx, int field, int prec);
+/* Device kernel that writes the exact even-odd tables the stencil kernels use
+ * (computed by the same device index functions): lex_of_eo[2][Vh],
+ * nbr[2][Vh][8] (d = 2*mu for +mu, 2*mu+1 for -mu; even-odd index on the other
+ * parity), sign[2][Vh][8] (fermion boundary factor of that hop).  Device buffers. */
+int pfmp_index_maps(pfmp_ctx *ctx, int32_t *lex_of_eo, int32_t *nbr, int8_t *sign);
+
+/* ---- fields ----------------------------------------------------------------- */
+
+/* Upload a canonical gauge field (device buffer) into the context; rebuilds the
+ * clover fields of every configured operator slot. */
+int pfmp_set_gauge(pfmp_ctx *ctx, const void *U_canonical);
+/* Copy the context's gauge field out in canonical layout (device buffer). */
+int pfmp_get_gauge(pfmp_ctx *ctx, void *U_canonical);
+/* Configure slot op with (kappa, c_sw): builds A_ee, A_oo^-1 (per-site Cholesky
+ * of the two 6x6 chiral blocks) and ln det A_oo.  Needs a gauge field.  Errors:
+ * PFMP_ERR_ARG (slot), PFMP_ERR_STATE (no gauge), PFMP_ERR_ARG if A_oo is not
+ * positive definite. */
+int pfmp_set_operator(pfmp_ctx *ctx, int op, double kappa, double csw);
+/* Canonical spinor (complex128 [Vh][4][3]) <-> internal spinor of precision prec. */
+int pfmp_pack_spinor(pfmp_ctx *ctx, const void *canonical, void *internal, int prec);
+int pfmp_unpack_spinor(pfmp_ctx *ctx, const void *internal, void *canonical, int prec);
+/* Canonical momenta / forces (float64 [V][4][8]) <-> internal. */
+int pfmp_pack_momenta(pfmp_ctx *ctx, const double *canonical, double *internal);
+int pfmp_unpack_momenta(pfmp_ctx *ctx, const double *internal, double *canonical);
+
+/* ---- operators (paper Sec. 2.1; even-odd Schur form) ------------------------ */
+
+/* out = D_eo in (out_parity 0, input odd) or D_oe in (out_parity 1, input even);
+ * dagger: the blocks of D_hop^dag.  FP64. */
+int pfmp_apply_hop(pfmp_ctx *ctx, int out_parity, int dagger, const void *in, void *out);
+/* out = A in, or A^-1 in (inverse = 1, odd parity only), on one parity of slot op. */
+int pfmp_apply_clover(pfmp_ctx *ctx, int op, int parity, int inverse, const void *in, void *out);
+/* out = Mhat in (dagger 0) or Mhat^dag in = g5 Mhat g5 in (dagger 1). */
+int pfmp_apply_M(pfmp_ctx *ctx, int op, int dagger, const void *in, void *out, int prec);
+/* out = Khat in = Mhat^dag Mhat in. */
+int pfmp_apply_MdagM(pfmp_ctx *ctx, int op, const void *in, void *out, int prec);
+
+/* Product-form polynomial (paper App. A): out = norm * prod_k (Khat - z_k) in,
+ * the factors applied in the order given (k = 0 first).  roots: n complex
+ * numbers as 2n doubles (host); norm: complex (host).  chain: optional array of
+ * n device buffers; chain[k] receives the partial product after k factors
+ * (chain[0] = in, unscaled) -- the vectors the polynomial force needs.  FP64. */
+int pfmp_apply_poly(pfmp_ctx *ctx, int op, int n, const double *roots, const double norm[2],
+                    const void *in, void *out, void *const *chain, int prec);
+
+/* ---- solvers (paper Sec. 2.1 CG on K; App. C multi-shift) -------------------- */
+
+typedef struct {
+    double tol;          /* stop at |b - A x| <= tol |b| (relative 2-norm, recomputed in FP64 at exit) */
+    int maxiter;
+    int prec;            /* pfmp_prec of the inner operator; FP32/F16 use FP64 reliable updates */
+    double delta;        /* reliable-update trigger: residual drop factor (mixed precision); 0 = 0.1 */
+    int check_every;     /* iterations between host convergence checks (0 = automatic) */
+} pfmp_solver_params;
+
+typedef struct {
+    int iters;                  /* Krylov iterations (one Khat multiplication each) */
+    int reliable_updates;
+    double true_res;            /* FP64 |b - A x| / |b| of the (base) system at exit */
+    double shift_res[PFMP_MAX_SHIFTS];  /* FP64 true residual per shift (multi-shift) */
+    double seconds;             /* wall time of the solve */
+    long long kmults;           /* Khat multiplications spent, residual checks included */
+} pfmp_solver_stats;
+
+/* CG for Khat x = b on slot op (zero initial guess).  b, x: FP64 internal spinors.
+ * Returns PFMP_ERR_NOCONV (x = last iterate, stats filled) at maxiter. */
+int pfmp_cg_solve(pfmp_ctx *ctx, int op, const void *b, void *x, const pfmp_solver_params *p,
+                  pfmp_solver_stats *st);
+/* Multi-shift CG (Jegerlehner's shifted recurrences on Hermitian positive Khat):
+ * x_s = (Khat - z_s)^-1 b for nshift complex shifts z_s (2*nshift doubles, host),
+ * one Khat multiplication per iteration shared by all shifts.  A zero shift is
+ * allowed (it is then the base system).  FP64. */
+int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const double *z, const void *b,
+                       void *const *x, const pfmp_solver_params *p, pfmp_solver_stats *st);
+
+/* ---- BLAS-1 on internal FP64 spinors (FP64 reductions, deterministic order) -- */
+
+/* *out = <a, b> (complex, 2 doubles on the host). */
+int pfmp_dot(pfmp_ctx *ctx, const void *a, const void *b, double out[2]);
+/* y = alpha x + beta y (complex alpha, beta). */
+int pfmp_axpby(pfmp_ctx *ctx, const double alpha[2], const void *x, const double beta[2], void *y);
+
+/* ---- forces (paper App. C) and integrator updates (App. B) ------------------ */
+
+/* F += sum_p d/dw Re[ c_p X_p^dag Mhat_op Y_p ] along U_mu(x) -> exp(i w T_a) U_mu(x),
+ * for npairs pairs of FP64 internal spinors X_p, Y_p (device) with complex
+ * coefficients c_p (2*npairs doubles, host).  flags: PFMP_FORCE_HOP and/or
+ * PFMP_FORCE_CLOVER select the parts of dMhat (both = the full derivative).
+ * F: internal momenta layout, accumulated. */
+#define PFMP_FORCE_HOP 1
+#define PFMP_FORCE_CLOVER 2
+int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void *const *X, const void *const *Y,
+                       const double *coeff, int flags, double *F);
+/* F += coef * d/dw S_det, S_det = -2 sum_{x odd} ln det A(x) of slot op. */
+int pfmp_logdet_force(pfmp_ctx *ctx, int op, double coef, double *F);
+/* F += d/dw S_G, Wilson gauge action S_G = beta sum_P (1 - Re tr U_P / 3). */
+int pfmp_gauge_force(pfmp_ctx *ctx, double beta, double *F);
+/* S[eps]: P <- P - eps F (internal momenta layout). */
+int pfmp_update_momenta(pfmp_ctx *ctx, double eps, const double *F, double *P);
+/* T[eps]: U_mu(x) <- exp(i eps P_mu(x)) U_mu(x); rebuilds every configured operator. */
+int pfmp_update_gauge(pfmp_ctx *ctx, double eps, const double *P);
+
+/* ---- actions (FP64, host results) ------------------------------------------ */
+
+/* S_G of the context's gauge field. */
+int pfmp_gauge_action(pfmp_ctx *ctx, double beta, double *out);
+/* -2 sum_{x odd} ln det A(x) of slot op. */
+int pfmp_logdet_action(pfmp_ctx *ctx, int op, double *out);
+/* sum over links of tr P^2 (internal momenta). */
+int pfmp_kinetic(pfmp_ctx *ctx, const double *P, double *out);
+
+/* ---- PF-MP HMC (paper Sec. 2.1, eq. pfmp_action, App. B, App. C) ------------ */
+
+/* Filter terms of the action.  J = W^dag W is the operator of slot `op` (a
+ * heavier kappa); K_b is the operator of slot `op2`. */
+typedef enum {
+    PFMP_TERM_POLY = 0,      /* phi^dag P(J) phi, P the degree-n Chebyshev filter of App. A        */
+    PFMP_TERM_POLYCORR = 1,  /* phi^dag [J P(J)]^-1 phi (pole sum + multi-shift CG, App. C)         */
+    PFMP_TERM_RATIO = 2,     /* phi^dag W^dag K_b^-1 W phi: the Hasenbusch ratio J K_b^-1            */
+    PFMP_TERM_HEAVY = 3      /* phi^dag J^-1 phi                                                  */
+} pfmp_term_kind;
+
+#define PFMP_MAX_TERMS 16
+
+typedef struct {
+    int kind;        /* pfmp_term_kind */
+    int op;          /* slot of J (W) */
+    int op2;         /* RATIO: slot of the denominator K_b */
+    int n;           /* POLY / POLYCORR: polynomial degree (even) */
+    double mu, nu;   /* Chebyshev ellipse (mu >= nu > 0) */
+    int steps;       /* 2MN steps of this term over the trajectory */
+} pfmp_term;
+
+typedef struct {
+    double beta;          /* Wilson gauge coupling */
+    int det_op;           /* slot whose -2 ln det A_oo enters the action (-1: none) */
+    int gauge_steps;      /* 2MN steps of the gauge (and S_det) scale */
+    double tau;           /* trajectory length */
+    double lambda;        /* 2MN parameter; 0 selects 0.1931833275037836 (minimum norm) */
+    int nterms;
+    const pfmp_term *terms;
+    double tol;           /* relative residual of every solve */
+    int maxiter;
+    int exact_start;      /* 1: evaluate the filter actions at the start; 0: use eta^dag eta */
+} pfmp_hmc_spec;
+
+typedef struct {
+    double H0, H1, dH;
+    int accept;
+    int nsteps;                          /* length of the merged schedule */
+    int nforce[PFMP_MAX_TERMS + 1];      /* force evaluations: [0] gauge (+S_det), [1+j] term j */
+    long long kmults;                    /* Khat / J multiplications, the paper's N_mat unit */
+    long long solver_iters;
+    double seconds;
+    double parts0[PFMP_MAX_TERMS + 3];   /* kinetic, S_G, S_det, terms at the start */
+    double parts1[PFMP_MAX_TERMS + 3];   /* ... at the end */
+} pfmp_traj_stats;
+
+/* Pseudofermion heatbath: phi_j with density exp(-S_j) from Gaussian eta_j
+ * (density exp(-eta^dag eta)); device FP64 internal spinors, one per term. */
+int pfmp_heatbath(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const void *const *eta, void *const *phi);
+/* H = sum tr P^2 + S_G + S_det + sum_j S_j(phi_j); parts (nterms + 3 doubles) optional. */
+int pfmp_hamiltonian(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const double *P, const void *const *phi,
+                     double *H, double *parts);
+/* Molecular dynamics over tau: the per-term 2MN schemes merged by the generalized
+ * multi-scale scheme (App. B); T[eps] then the S_j of the merged step.  P
+ * (internal momenta) and the context's gauge field are updated in place. */
+int pfmp_md_evolve(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, double *P, const void *const *phi,
+                   pfmp_traj_stats *st);
+/* One trajectory from the context's gauge field: heatbath, H0, MD, H1, Metropolis
+ * with the uniform u (accept iff u < exp(-dH)); on reject the start field is
+ * restored.  P0 is not modified; P_end (optional) receives the final momenta. */
+int pfmp_trajectory(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const double *P0, const void *const *eta, double u,
+                    double *P_end, pfmp_traj_stats *st);
+
+/* ---- host-only helpers ------------------------------------------------------ */
+
+/* Chebyshev roots z_k = mu(1 - cos th_k) - i sqrt(mu^2-nu^2) sin th_k,
+ * th_k = 2 pi k/(n+1), k = 1..n, and a_n = 1/(mu prod (mu - z_k)) (paper App. A).
+ * roots: 2n doubles; norm: 2 doubles. */
+int pfmp_chebyshev(int n, double mu, double nu, double *roots, double norm[2]);
+/* Generalized multi-scale merge (paper App. B): nterms schemes given as integer
+ * tick lists T_j (time steps, first entry 0) and S_j (space steps, any values),
+ * lengths len[j], flattened one after another.  All T_j must sum to the same
+ * total.  Writes the merged T' (ticks) and S'_j (nterms x nout, row-major) and
+ * *nout.  cap = capacity of T_out (S_out holds nterms*cap).  PFMP_ERR_ARG on
+ * unequal totals or too small a capacity. */
+int pfmp_schedule_build(int nterms, const int *len, const int64_t *T_ticks, const double *S_steps,
+                        int cap, int64_t *T_out, double *S_out, int *nout);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

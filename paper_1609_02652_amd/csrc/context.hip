@@ -1,0 +1,320 @@
+// context.hip -- context lifetime, layout conversion and index tables of libpfmp.
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+// Scratch buffers of the context, one per slot:
+//   0-3 operator temporaries, 4-10 CG, 11-13 multi-shift, 14 link accumulator,
+//   15 reduction partials, 16-19 forces, 20-31 polynomial and mixed precision.
+constexpr int kWsSlots = 32;
+struct SolverWS {
+    void *buf[kWsSlots] = {};
+    size_t bytes[kWsSlots] = {};
+};
+
+int set_err(pfmp_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+// Per-context scratch buffers keyed by slot, grown on demand and owned by the context.
+void *ws_alloc(pfmp_ctx *ctx, size_t bytes, int slot)
+{
+    SolverWS *w = ctx->ws;
+    if (slot < 0 || slot >= kWsSlots) return nullptr;
+    if (w->bytes[slot] >= bytes) return w->buf[slot];
+    if (w->buf[slot]) {
+        hipStreamSynchronize(ctx->stream);
+        hipFree(w->buf[slot]);
+        w->buf[slot] = nullptr;
+        w->bytes[slot] = 0;
+    }
+    if (hipMalloc(&w->buf[slot], bytes) != hipSuccess) {
+        w->buf[slot] = nullptr;
+        return nullptr;
+    }
+    w->bytes[slot] = bytes;
+    return w->buf[slot];
+}
+
+// Buffer idx of the context's pool of FP64 spinors (allocated on first use).
+double2 *pool_get(pfmp_ctx *ctx, int idx)
+{
+    if (idx < 0) return nullptr;
+    while ((int)ctx->pool.size() <= idx) {
+        double2 *p = nullptr;
+        if (hipMalloc(&p, sizeof(double) * spinor_reals(ctx->g)) != hipSuccess) return nullptr;
+        ctx->pool.push_back(p);
+    }
+    return ctx->pool[idx];
+}
+
+namespace {
+
+// canonical gauge [V][4][3][3] complex128 -> internal [2][4][9][Vh]
+__global__ void k_pack_gauge(Geom g, const double2 *__restrict__ in, double2 *__restrict__ U, int unpack)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 2L * g.Vh) return;
+    int p = (int)(t / g.Vh), i = (int)(t % g.Vh);
+    int c[4];
+    eo_coords(g, p, i, c);
+    long lex = c[0] + (long)g.L[0] * (c[1] + (long)g.L[1] * (c[2] + (long)g.L[2] * c[3]));
+    for (int mu = 0; mu < 4; mu++)
+        for (int k = 0; k < 9; k++) {
+            long ii = ((long)(p * 4 + mu) * 9 + k) * g.Vh + i;
+            long cc = (lex * 4 + mu) * 9 + k;
+            if (unpack) ((double2 *)in)[cc] = U[ii];
+            else U[ii] = in[cc];
+        }
+}
+
+__global__ void k_gauge_f32(long n, const double2 *__restrict__ a, float2 *__restrict__ b)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) b[t] = make_float2((float)a[t].x, (float)a[t].y);
+}
+
+// canonical spinor [Vh][12] complex128 <-> internal [12][Vh]
+template <typename C>
+__global__ void k_pack_spinor(int Vh, const double2 *__restrict__ can, C *__restrict__ f, int unpack)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 12L * Vh) return;
+    int i = (int)(t / 12), k = (int)(t % 12);
+    long ii = (long)k * Vh + i;
+    if (unpack) {
+        C v = f[ii];
+        ((double2 *)can)[t] = make_double2((double)v.x, (double)v.y);
+    } else {
+        double2 v = can[t];
+        C w;
+        w.x = v.x;
+        w.y = v.y;
+        f[ii] = w;
+    }
+}
+
+// canonical momenta [V][4][8] <-> internal [2][4][8][Vh]
+__global__ void k_pack_mom(Geom g, const double *__restrict__ can, double *__restrict__ f, int unpack)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 2L * g.Vh) return;
+    int p = (int)(t / g.Vh), i = (int)(t % g.Vh);
+    int c[4];
+    eo_coords(g, p, i, c);
+    long lex = c[0] + (long)g.L[0] * (c[1] + (long)g.L[1] * (c[2] + (long)g.L[2] * c[3]));
+    for (int mu = 0; mu < 4; mu++)
+        for (int a = 0; a < 8; a++) {
+            long ii = ((long)(p * 4 + mu) * 8 + a) * g.Vh + i;
+            long cc = (lex * 4 + mu) * 8 + a;
+            if (unpack) ((double *)can)[cc] = f[ii];
+            else f[ii] = can[cc];
+        }
+}
+
+__global__ void k_index_maps(Geom g, int32_t *lexeo, int32_t *nbr, int8_t *sign)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 2L * g.Vh) return;
+    int p = (int)(t / g.Vh), i = (int)(t % g.Vh);
+    int c[4];
+    eo_coords(g, p, i, c);
+    lexeo[t] = c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+    for (int mu = 0; mu < 4; mu++)
+        for (int b = 0; b < 2; b++) {
+            int s;
+            int j = eo_neighbour(g, c, mu, b ? -1 : +1, &s);
+            nbr[t * 8 + 2 * mu + b] = j;
+            sign[t * 8 + 2 * mu + b] = (int8_t)s;
+        }
+}
+
+}  // namespace
+
+extern "C" int pfmp_create(const int dims[4], int t_bc, void *stream, pfmp_ctx **out)
+{
+    if (!dims || !out) return PFMP_ERR_ARG;
+    *out = nullptr;
+    long V = 1;
+    for (int m = 0; m < 4; m++) {
+        if (dims[m] < 4 || (dims[m] & 1)) return PFMP_ERR_ARG;
+        V *= dims[m];
+    }
+    if (V / 2 > (1L << 30)) return PFMP_ERR_ARG;
+    if (t_bc != 1 && t_bc != -1) return PFMP_ERR_ARG;
+    pfmp_ctx *ctx = new pfmp_ctx();
+    for (int m = 0; m < 4; m++) ctx->g.L[m] = dims[m];
+    ctx->g.Lh0 = dims[0] / 2;
+    ctx->g.V = (int)V;
+    ctx->g.Vh = (int)(V / 2);
+    ctx->g.tbc = t_bc;
+    ctx->stream = (hipStream_t)stream;
+    ctx->ws = new SolverWS();
+    ctx->nblk_red = 1024;
+    size_t gb = sizeof(double) * gauge_reals(ctx->g);
+    if (hipMalloc(&ctx->U, gb) != hipSuccess || hipMalloc(&ctx->Uf, gb / 2) != hipSuccess ||
+        hipMalloc(&ctx->red, sizeof(double) * 64 * 4096) != hipSuccess ||
+        hipMalloc(&ctx->scal, sizeof(double) * 8192) != hipSuccess ||
+        hipHostMalloc(&ctx->red_host, sizeof(double) * 4096, hipHostMallocDefault) != hipSuccess) {
+        pfmp_destroy(ctx);
+        return PFMP_ERR_OOM;
+    }
+    *out = ctx;
+    return 0;
+}
+
+extern "C" int pfmp_destroy(pfmp_ctx *ctx)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    hipStreamSynchronize(ctx->stream);
+    hipFree(ctx->U);
+    hipFree(ctx->Uf);
+    hipFree(ctx->red);
+    hipFree(ctx->scal);
+    if (ctx->red_host) hipHostFree(ctx->red_host);
+    for (auto &s : ctx->ops) {
+        hipFree(s.clov[0]); hipFree(s.clov[1]);
+        hipFree(s.clovf[0]); hipFree(s.clovf[1]);
+        hipFree(s.Aoo);
+    }
+    for (double2 *p : ctx->pool) hipFree(p);
+    if (ctx->ws) {
+        for (int k = 0; k < kWsSlots; k++) hipFree(ctx->ws->buf[k]);
+        delete ctx->ws;
+    }
+    delete ctx;
+    return 0;
+}
+
+extern "C" const char *pfmp_last_error(pfmp_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" long long pfmp_field_bytes(pfmp_ctx *ctx, int field, int prec)
+{
+    if (!ctx) return -1;
+    switch (field) {
+    case PFMP_FIELD_SPINOR:
+        if (prec == PFMP_F64) return 8LL * spinor_reals(ctx->g);
+        if (prec == PFMP_F32) return 4LL * spinor_reals(ctx->g);
+        if (prec == PFMP_F16) return 2LL * spinor_reals(ctx->g) + 4LL * ctx->g.Vh;
+        return -1;
+    case PFMP_FIELD_GAUGE: return 8LL * gauge_reals(ctx->g);
+    case PFMP_FIELD_MOMENTA: return 8LL * mom_reals(ctx->g);
+    }
+    return -1;
+}
+
+extern "C" int pfmp_index_maps(pfmp_ctx *ctx, int32_t *lex_of_eo, int32_t *nbr, int8_t *sign)
+{
+    if (!ctx || !lex_of_eo || !nbr || !sign) return ctx ? set_err(ctx, PFMP_ERR_ARG, "index_maps: null") : PFMP_ERR_ARG;
+    hipLaunchKernelGGL(k_index_maps, dim3(nblocks(2L * ctx->g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, ctx->g,
+                       lex_of_eo, nbr, sign);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+int rebuild_gauge_derived(pfmp_ctx *ctx)
+{
+    long n = gauge_reals(ctx->g) / 2;
+    hipLaunchKernelGGL(k_gauge_f32, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, ctx->U, ctx->Uf);
+    LAUNCHCHK(ctx);
+    for (int op = 0; op < PFMP_MAX_OPS; op++)
+        if (ctx->ops[op].valid) {
+            int rc = clover_build(ctx, op);
+            if (rc) return rc;
+        }
+    return 0;
+}
+
+extern "C" int pfmp_set_gauge(pfmp_ctx *ctx, const void *U_canonical)
+{
+    if (!ctx || !U_canonical) return ctx ? set_err(ctx, PFMP_ERR_ARG, "set_gauge: null") : PFMP_ERR_ARG;
+    hipLaunchKernelGGL(k_pack_gauge, dim3(nblocks(2L * ctx->g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, ctx->g,
+                       (const double2 *)U_canonical, ctx->U, 0);
+    LAUNCHCHK(ctx);
+    ctx->have_gauge = true;
+    return rebuild_gauge_derived(ctx);
+}
+
+extern "C" int pfmp_get_gauge(pfmp_ctx *ctx, void *U_canonical)
+{
+    if (!ctx || !U_canonical) return ctx ? set_err(ctx, PFMP_ERR_ARG, "get_gauge: null") : PFMP_ERR_ARG;
+    if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
+    hipLaunchKernelGGL(k_pack_gauge, dim3(nblocks(2L * ctx->g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, ctx->g,
+                       (const double2 *)U_canonical, ctx->U, 1);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_set_operator(pfmp_ctx *ctx, int op, double kappa, double csw)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    if (op < 0 || op >= PFMP_MAX_OPS) return set_err(ctx, PFMP_ERR_ARG, "operator slot out of range");
+    if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "set_operator needs a gauge field");
+    OpSlot &s = ctx->ops[op];
+    s.kappa = kappa;
+    s.csw = csw;
+    if (!s.clov[0]) {
+        size_t b = sizeof(double) * clover_reals(ctx->g);
+        if (hipMalloc(&s.clov[0], b) != hipSuccess || hipMalloc(&s.clov[1], b) != hipSuccess ||
+            hipMalloc(&s.clovf[0], b / 2) != hipSuccess || hipMalloc(&s.clovf[1], b / 2) != hipSuccess ||
+            hipMalloc(&s.Aoo, b) != hipSuccess)
+            return set_err(ctx, PFMP_ERR_OOM, "clover fields");
+    }
+    s.valid = true;
+    int rc = clover_build(ctx, op);
+    if (rc) s.valid = false;
+    return rc;
+}
+
+extern "C" int pfmp_pack_spinor(pfmp_ctx *ctx, const void *canonical, void *internal, int prec)
+{
+    if (!ctx || !canonical || !internal) return ctx ? set_err(ctx, PFMP_ERR_ARG, "pack_spinor: null") : PFMP_ERR_ARG;
+    dim3 grid(nblocks(12L * ctx->g.Vh, 256)), block(256);
+    if (prec == PFMP_F64)
+        hipLaunchKernelGGL((k_pack_spinor<double2>), grid, block, 0, ctx->stream, ctx->g.Vh,
+                           (const double2 *)canonical, (double2 *)internal, 0);
+    else if (prec == PFMP_F32)
+        hipLaunchKernelGGL((k_pack_spinor<float2>), grid, block, 0, ctx->stream, ctx->g.Vh,
+                           (const double2 *)canonical, (float2 *)internal, 0);
+    else
+        return set_err(ctx, PFMP_ERR_ARG, "pack_spinor: unsupported precision");
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_unpack_spinor(pfmp_ctx *ctx, const void *internal, void *canonical, int prec)
+{
+    if (!ctx || !canonical || !internal) return ctx ? set_err(ctx, PFMP_ERR_ARG, "unpack_spinor: null") : PFMP_ERR_ARG;
+    dim3 grid(nblocks(12L * ctx->g.Vh, 256)), block(256);
+    if (prec == PFMP_F64)
+        hipLaunchKernelGGL((k_pack_spinor<double2>), grid, block, 0, ctx->stream, ctx->g.Vh,
+                           (const double2 *)canonical, (double2 *)internal, 1);
+    else if (prec == PFMP_F32)
+        hipLaunchKernelGGL((k_pack_spinor<float2>), grid, block, 0, ctx->stream, ctx->g.Vh,
+                           (const double2 *)canonical, (float2 *)internal, 1);
+    else
+        return set_err(ctx, PFMP_ERR_ARG, "unpack_spinor: unsupported precision");
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_pack_momenta(pfmp_ctx *ctx, const double *canonical, double *internal)
+{
+    if (!ctx || !canonical || !internal) return ctx ? set_err(ctx, PFMP_ERR_ARG, "pack_momenta: null") : PFMP_ERR_ARG;
+    hipLaunchKernelGGL(k_pack_mom, dim3(nblocks(2L * ctx->g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, ctx->g,
+                       canonical, internal, 0);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_unpack_momenta(pfmp_ctx *ctx, const double *internal, double *canonical)
+{
+    if (!ctx || !canonical || !internal) return ctx ? set_err(ctx, PFMP_ERR_ARG, "unpack_momenta: null") : PFMP_ERR_ARG;
+    hipLaunchKernelGGL(k_pack_mom, dim3(nblocks(2L * ctx->g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, ctx->g,
+                       canonical, (double *)internal, 1);
+    LAUNCHCHK(ctx);
+    return 0;
+}

@@ -1,0 +1,236 @@
+// dslash.hip -- even-odd Wilson-clover operator kernels for gfx950 (hopping
+// term building blocks in hop.h).
+//
+// Stages (paper Sec. 2.1 operator, even-odd Schur form):
+//   hop_clovinv : out_o = [g5] A_oo^-1 D_oe [g5] in_e      (also plain D for tests)
+//   hop_xpay    : out_e = [g5] (A_ee [g5] x_e + a D_eo t_o), optional |out|^2 partials
+// Mhat = both stages (a = -kappa^2); Mhat^dag = the same with g5 on input and output.
+#include "hop.h"
+
+namespace {
+
+// out = [g5] A^-1 D in [g5], output parity pout (CLOV = 0: no clover)
+template <typename C, typename R, int CLOV>
+__global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const C *__restrict__ in,
+                                                        const C *__restrict__ U, const R *__restrict__ cl,
+                                                        C *__restrict__ out, R gin, R gout,
+                                                        const double *__restrict__ stop)
+{
+    if (stop && stop[0] != 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.Vh) return;
+    C acc[12];
+    hop_all<C>(g, pout, i, in, U, gin, acc);
+    if (CLOV) {
+        C t[12];
+        clover_apply<R, C>(cl, g.Vh, i, acc, t);
+        store_spinor(out, g.Vh, i, gout, t);
+    } else {
+        store_spinor(out, g.Vh, i, gout, acc);
+    }
+}
+
+// out = [g5] (A [g5] x + a D t), output parity pout; NORM: |out|^2 block partials
+template <typename C, typename R, int CLOV, int NORM>
+__global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const C *__restrict__ x,
+                                                     const C *__restrict__ t, const C *__restrict__ U,
+                                                     const R *__restrict__ cl, R a, C *__restrict__ out, R gs,
+                                                     double *partials, const double *__restrict__ stop)
+{
+    if (stop && stop[0] != 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double nrm = 0;
+    if (i < g.Vh) {
+        C acc[12], xv[12], ax[12];
+        hop_all<C>(g, pout, i, t, U, (R)1, acc);
+        load_spinor(x, g.Vh, i, gs, xv);
+        if (CLOV) clover_apply<R, C>(cl, g.Vh, i, xv, ax);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            C base = CLOV ? ax[k] : xv[k];
+            acc[k] = mk<C>(base.x + a * acc[k].x, base.y + a * acc[k].y);
+            if (NORM) nrm += (double)acc[k].x * acc[k].x + (double)acc[k].y * acc[k].y;
+        }
+        store_spinor(out, g.Vh, i, gs, acc);
+    }
+    if (NORM) block_sum_store<C>(nrm, partials);
+}
+
+}  // namespace
+
+template <typename C, typename R>
+int launch_clovinv(pfmp_ctx *ctx, int pout, const C *in, const C *U, const R *cl, C *out, R gin, R gout, bool clov,
+                   const double *stop)
+{
+    dim3 grid(nblocks(ctx->g.Vh, kBlock)), block(kBlock);
+    if (clov)
+        hipLaunchKernelGGL((k_hop_clovinv<C, R, 1>), grid, block, 0, ctx->stream, ctx->g, pout, in, U, cl, out, gin,
+                           gout, stop);
+    else
+        hipLaunchKernelGGL((k_hop_clovinv<C, R, 0>), grid, block, 0, ctx->stream, ctx->g, pout, in, U, cl, out, gin,
+                           gout, stop);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+template <typename C, typename R>
+int launch_xpay(pfmp_ctx *ctx, int pout, const C *x, const C *t, const C *U, const R *cl, R a, C *out, R gs,
+                bool clov, double *partials, const double *stop)
+{
+    dim3 grid(nblocks(ctx->g.Vh, kBlock)), block(kBlock);
+#define XPAY(CL, NM)                                                                                           \
+    hipLaunchKernelGGL((k_hop_xpay<C, R, CL, NM>), grid, block, 0, ctx->stream, ctx->g, pout, x, t, U, cl, a, out, \
+                       gs, partials, stop)
+    if (clov && partials) XPAY(1, 1);
+    else if (clov) XPAY(1, 0);
+    else if (partials) XPAY(0, 1);
+    else XPAY(0, 0);
+#undef XPAY
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+template int launch_clovinv<double2, double>(pfmp_ctx *, int, const double2 *, const double2 *, const double *,
+                                             double2 *, double, double, bool, const double *);
+template int launch_clovinv<float2, float>(pfmp_ctx *, int, const float2 *, const float2 *, const float *, float2 *,
+                                           float, float, bool, const double *);
+template int launch_xpay<double2, double>(pfmp_ctx *, int, const double2 *, const double2 *, const double2 *,
+                                          const double *, double, double2 *, double, bool, double *, const double *);
+template int launch_xpay<float2, float>(pfmp_ctx *, int, const float2 *, const float2 *, const float2 *,
+                                        const float *, float, float2 *, float, bool, double *, const double *);
+
+namespace {
+
+// clover (or inverse) on one parity
+template <typename C, typename R>
+__global__ __launch_bounds__(kBlock) void k_clover(Geom g, const C *__restrict__ in, const R *__restrict__ cl,
+                                                   C *__restrict__ out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.Vh) return;
+    C v[12], w[12];
+    load_spinor(in, g.Vh, i, (R)1, v);
+    clover_apply<R, C>(cl, g.Vh, i, v, w);
+    store_spinor(out, g.Vh, i, (R)1, w);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ internal API
+
+static bool op_has_clover(const OpSlot &s) { return s.csw != 0; }
+
+int op_apply_M(pfmp_ctx *ctx, int op, int dagger, const double2 *in, double2 *out, double2 *tmp_odd,
+               double *norm_partials)
+{
+    OpSlot &s = ctx->ops[op];
+    double gs = dagger ? -1.0 : 1.0;
+    bool cl = op_has_clover(s);
+    int rc = launch_clovinv<double2, double>(ctx, 1, in, ctx->U, s.clov[1], tmp_odd, gs, 1.0, cl, nullptr);
+    if (rc) return rc;
+    return launch_xpay<double2, double>(ctx, 0, in, tmp_odd, ctx->U, s.clov[0], -s.kappa * s.kappa, out, gs, cl,
+                                        norm_partials, nullptr);
+}
+
+int op_apply_K(pfmp_ctx *ctx, int op, const double2 *in, double2 *out, double2 *tmp_even, double2 *tmp_odd,
+               double *norm_partials)
+{
+    int rc = op_apply_M(ctx, op, 0, in, tmp_even, tmp_odd, norm_partials);
+    if (rc) return rc;
+    return op_apply_M(ctx, op, 1, tmp_even, out, tmp_odd, nullptr);
+}
+
+int op_apply_M_f32(pfmp_ctx *ctx, int op, int dagger, const float2 *in, float2 *out, float2 *tmp_odd,
+                   double *norm_partials)
+{
+    OpSlot &s = ctx->ops[op];
+    float gs = dagger ? -1.f : 1.f;
+    bool cl = op_has_clover(s);
+    int rc = launch_clovinv<float2, float>(ctx, 1, in, ctx->Uf, s.clovf[1], tmp_odd, gs, 1.f, cl, nullptr);
+    if (rc) return rc;
+    return launch_xpay<float2, float>(ctx, 0, in, tmp_odd, ctx->Uf, s.clovf[0], (float)(-s.kappa * s.kappa), out,
+                                      gs, cl, norm_partials, nullptr);
+}
+
+int op_apply_K_f32(pfmp_ctx *ctx, int op, const float2 *in, float2 *out, float2 *tmp_even, float2 *tmp_odd,
+                   double *norm_partials)
+{
+    int rc = op_apply_M_f32(ctx, op, 0, in, tmp_even, tmp_odd, norm_partials);
+    if (rc) return rc;
+    return op_apply_M_f32(ctx, op, 1, tmp_even, out, tmp_odd, nullptr);
+}
+
+// ------------------------------------------------------------------ C-ABI
+
+static int check_op(pfmp_ctx *ctx, int op)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    if (op < 0 || op >= PFMP_MAX_OPS) return set_err(ctx, PFMP_ERR_ARG, "operator slot out of range");
+    if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
+    if (!ctx->ops[op].valid) return set_err(ctx, PFMP_ERR_STATE, "operator slot not configured");
+    return 0;
+}
+
+extern "C" int pfmp_apply_hop(pfmp_ctx *ctx, int out_parity, int dagger, const void *in, void *out)
+{
+    if (!ctx || !in || !out || (out_parity != 0 && out_parity != 1)) return ctx ? set_err(ctx, PFMP_ERR_ARG, "apply_hop: bad argument") : PFMP_ERR_ARG;
+    if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
+    double gs = dagger ? -1.0 : 1.0;
+    return launch_clovinv<double2, double>(ctx, out_parity, (const double2 *)in, ctx->U, nullptr, (double2 *)out, gs,
+                                           gs, false, nullptr);
+}
+
+extern "C" int pfmp_apply_clover(pfmp_ctx *ctx, int op, int parity, int inverse, const void *in, void *out)
+{
+    int rc = check_op(ctx, op);
+    if (rc) return rc;
+    if (!in || !out || (parity != 0 && parity != 1)) return set_err(ctx, PFMP_ERR_ARG, "apply_clover: bad argument");
+    if (inverse != (parity == 1)) return set_err(ctx, PFMP_ERR_ARG, "apply_clover: the context holds A_ee and A_oo^-1");
+    OpSlot &s = ctx->ops[op];
+    if (!op_has_clover(s)) {
+        HIPCHK(ctx, hipMemcpyAsync(out, in, sizeof(double) * spinor_reals(ctx->g), hipMemcpyDeviceToDevice, ctx->stream));
+        return 0;
+    }
+    hipLaunchKernelGGL((k_clover<double2, double>), dim3(nblocks(ctx->g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream,
+                       ctx->g, (const double2 *)in, s.clov[parity], (double2 *)out);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_apply_M(pfmp_ctx *ctx, int op, int dagger, const void *in, void *out, int prec)
+{
+    int rc = check_op(ctx, op);
+    if (rc) return rc;
+    if (!in || !out) return set_err(ctx, PFMP_ERR_ARG, "apply_M: null buffer");
+    if (prec == PFMP_F64) {
+        double2 *tmp = (double2 *)ws_alloc(ctx, sizeof(double) * spinor_reals(ctx->g), 0);
+        if (!tmp) return set_err(ctx, PFMP_ERR_OOM, "workspace");
+        return op_apply_M(ctx, op, dagger, (const double2 *)in, (double2 *)out, tmp, nullptr);
+    }
+    if (prec == PFMP_F32) {
+        float2 *tmp = (float2 *)ws_alloc(ctx, sizeof(float) * spinor_reals(ctx->g), 1);
+        if (!tmp) return set_err(ctx, PFMP_ERR_OOM, "workspace");
+        return op_apply_M_f32(ctx, op, dagger, (const float2 *)in, (float2 *)out, tmp, nullptr);
+    }
+    return set_err(ctx, PFMP_ERR_ARG, "apply_M: unsupported precision");
+}
+
+extern "C" int pfmp_apply_MdagM(pfmp_ctx *ctx, int op, const void *in, void *out, int prec)
+{
+    int rc = check_op(ctx, op);
+    if (rc) return rc;
+    if (!in || !out) return set_err(ctx, PFMP_ERR_ARG, "apply_MdagM: null buffer");
+    if (prec == PFMP_F64) {
+        double2 *te = (double2 *)ws_alloc(ctx, sizeof(double) * spinor_reals(ctx->g), 0);
+        double2 *to = (double2 *)ws_alloc(ctx, sizeof(double) * spinor_reals(ctx->g), 2);
+        if (!te || !to) return set_err(ctx, PFMP_ERR_OOM, "workspace");
+        return op_apply_K(ctx, op, (const double2 *)in, (double2 *)out, te, to, nullptr);
+    }
+    if (prec == PFMP_F32) {
+        float2 *te = (float2 *)ws_alloc(ctx, sizeof(float) * spinor_reals(ctx->g), 1);
+        float2 *to = (float2 *)ws_alloc(ctx, sizeof(float) * spinor_reals(ctx->g), 3);
+        if (!te || !to) return set_err(ctx, PFMP_ERR_OOM, "workspace");
+        return op_apply_K_f32(ctx, op, (const float2 *)in, (float2 *)out, te, to, nullptr);
+    }
+    return set_err(ctx, PFMP_ERR_ARG, "apply_MdagM: unsupported precision");
+}

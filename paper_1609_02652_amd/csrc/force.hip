@@ -1,0 +1,562 @@
+// force.hip -- molecular-dynamics forces (paper App. C) and the atomic
+// integrator steps T and S (App. B, eq. time_update / space_update).
+//
+// Forces are Lie-algebra coefficients f_a = d/dw S along U -> exp(i w T_a) U.  For
+// every link the kernels build a 3x3 matrix Z with f_a = Re tr[i T_a Z].
+//
+// Fermion bilinear Re[c X^dag Mhat Y], Mhat = A_ee - kappa^2 D_eo A_oo^-1 D_oe:
+// with L = (X | Xo) and R = (Y | Z) on (even | odd) sites, Xo = A_oo^-1 (D_eo)^dag X,
+// Z = A_oo^-1 D_oe Y, the derivative is
+//   sum_x L^dag [ w(x) dA(x) R - kappa^2 (dD_hop R)(x) ],  w = 1 (even), kappa^2 (odd).
+// Hopping part, link U = U_mu(x) between x and x+mu with boundary factor s:
+//   Z_hop = c s (U G_A - G_B U^dag),
+//   G_A = sum_t g_t h_t^dag with g, h the (1 - g_mu) half spinors of R(x+mu), L(x),
+//   G_B = the same with (1 + g_mu) half spinors of R(x), L(x+mu).
+// Clover part: per site and plane p the colour matrix
+//   Phi_p(x) = c w i kappa c_sw sum_{s,t} sigma_p[s][t] R_t L_s^dag
+// (log-det term: -2 i kappa c_sw sum sigma_p[s][t] (A^-1)_{t s} on odd sites) so that
+// the contribution is Re tr[dFhat_p Phi_p] = Re tr[dQ_p Psi_p], Psi_p = (Phi_p - Phi_p^dag)/8;
+// each link then collects, over the 2 plaquettes x 4 corners of every plane holding
+// it, the leaf products with Psi inserted at the corner.
+#include <vector>
+
+#include "hop.h"
+#include "su3.h"
+
+namespace {
+
+// chiral-block Pauli structure of sigma_p: type (0 = x, 1 = y, 2 = z) and signs on
+// the upper / lower block; plane order (01)(02)(03)(12)(13)(23)
+__constant__ int kSigType[6] = {2, 1, 0, 0, 1, 2};
+__constant__ double kSigUp[6] = {-1, 1, 1, -1, 1, 1};
+__constant__ double kSigLo[6] = {-1, 1, -1, -1, -1, -1};
+
+// sum_{s,t} pauli[s][t] O_{st} for O_{st} given as 4 matrices O[2*s+t]
+__device__ __forceinline__ M3 pauli_contract(int type, const M3 *O)
+{
+    if (type == 0) return m3_add(O[1], O[2]);                                    // s_x
+    if (type == 1) {                                                             // s_y: -i O01 + i O10
+        M3 r;
+        for (int k = 0; k < 9; k++) r.e[k] = csub(ctimesi(O[2].e[k]), ctimesi(O[1].e[k]));
+        return r;
+    }
+    return m3_sub(O[0], O[3]);                                                   // s_z
+}
+
+// colour outer product a b^dag of two colour vectors
+__device__ __forceinline__ M3 outer(const double2 *a, const double2 *b)
+{
+    M3 r;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) r.e[3 * i + j] = cmulc(b[j], a[i]);
+    return r;
+}
+
+// ---------------------------------------------------------------- hop part
+
+template <int MU>
+__device__ __forceinline__ void hop_force_dir(const Geom &g, int p, int i, const int *c, const double2 *__restrict__ Le,
+                                              const double2 *__restrict__ Lo, const double2 *__restrict__ Re,
+                                              const double2 *__restrict__ Ro, const double2 *__restrict__ U,
+                                              double2 coef, double2 *__restrict__ Zacc)
+{
+    const double2 *Lx = p == 0 ? Le : Lo, *Rx = p == 0 ? Re : Ro;
+    const double2 *Ly = p == 0 ? Lo : Le, *Ry = p == 0 ? Ro : Re;
+    int s;
+    int j = eo_neighbour(g, c, MU, +1, &s);
+    double2 v[12], hL[6], hR[6];
+    // G_A: (1 - g) projections of R(x+mu) and L(x)
+    load_spinor(Ry, g.Vh, j, 1.0, v);
+    project<MU, -1>(v, hR);
+    load_spinor(Lx, g.Vh, i, 1.0, v);
+    project<MU, -1>(v, hL);
+    M3 GA = m3_add(outer(hR, hL), outer(hR + 3, hL + 3));
+    // G_B: (1 + g) projections of R(x) and L(x+mu)
+    load_spinor(Rx, g.Vh, i, 1.0, v);
+    project<MU, +1>(v, hR);
+    load_spinor(Ly, g.Vh, j, 1.0, v);
+    project<MU, +1>(v, hL);
+    M3 GB = m3_add(outer(hR, hL), outer(hR + 3, hL + 3));
+    M3 Uu;
+    const double2 *ub = U + ((long)(p * 4 + MU) * 9) * g.Vh + i;
+    for (int k = 0; k < 9; k++) Uu.e[k] = ub[(long)k * g.Vh];
+    M3 Z = m3_sub(m3_mul(Uu, GA), m3_mul_nd(GB, Uu));
+    double2 cs = cscale(coef, (double)s);
+    double2 *zb = Zacc + ((long)(p * 4 + MU) * 9) * g.Vh + i;
+    for (int k = 0; k < 9; k++) {
+        double2 z = zb[(long)k * g.Vh];
+        cfma(z, cs, Z.e[k]);
+        zb[(long)k * g.Vh] = z;
+    }
+}
+
+// Zacc[link] += c s (U G_A - G_B U^dag) for every link; one thread per site
+__global__ __launch_bounds__(kBlock) void k_hop_force(Geom g, const double2 *__restrict__ Le,
+                                                      const double2 *__restrict__ Lo, const double2 *__restrict__ Re,
+                                                      const double2 *__restrict__ Ro, const double2 *__restrict__ U,
+                                                      double2 coef, double2 *__restrict__ Zacc)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 2L * g.Vh) return;
+    int p = (int)(t / g.Vh), i = (int)(t % g.Vh);
+    int c[4];
+    eo_coords(g, p, i, c);
+    hop_force_dir<0>(g, p, i, c, Le, Lo, Re, Ro, U, coef, Zacc);
+    hop_force_dir<1>(g, p, i, c, Le, Lo, Re, Ro, U, coef, Zacc);
+    hop_force_dir<2>(g, p, i, c, Le, Lo, Re, Ro, U, coef, Zacc);
+    hop_force_dir<3>(g, p, i, c, Le, Lo, Re, Ro, U, coef, Zacc);
+}
+
+// ---------------------------------------------------------------- clover insertions
+
+// Phi[site][plane] layout: ((p * 6 + plane) * 9 + k) * Vh + i  (complex)
+__device__ __forceinline__ void phi_add(const Geom &g, double2 *__restrict__ Phi, int p, int i, int plane, const M3 &m)
+{
+    double2 *b = Phi + ((long)(p * 6 + plane) * 9) * g.Vh + i;
+    for (int k = 0; k < 9; k++) b[(long)k * g.Vh] = cadd(b[(long)k * g.Vh], m.e[k]);
+}
+
+// Phi_p(x) += fac * sum_{s,t} sigma_p[s][t] R_t L_s^dag on every site of both parities
+__global__ __launch_bounds__(kBlock) void k_clover_insert(Geom g, const double2 *__restrict__ Le,
+                                                          const double2 *__restrict__ Lo,
+                                                          const double2 *__restrict__ Re,
+                                                          const double2 *__restrict__ Ro, double2 fac_even,
+                                                          double2 fac_odd, double2 *__restrict__ Phi)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 2L * g.Vh) return;
+    int p = (int)(t / g.Vh), i = (int)(t % g.Vh);
+    const double2 *L = p == 0 ? Le : Lo, *R = p == 0 ? Re : Ro;
+    double2 l[12], r[12];
+    load_spinor(L, g.Vh, i, 1.0, l);
+    load_spinor(R, g.Vh, i, 1.0, r);
+    double2 fac = p == 0 ? fac_even : fac_odd;
+    M3 Oup[4], Olo[4];
+    for (int s = 0; s < 2; s++)
+        for (int u = 0; u < 2; u++) {
+            Oup[2 * s + u] = outer(r + 3 * u, l + 3 * s);           // R_t L_s^dag with t = u
+            Olo[2 * s + u] = outer(r + 6 + 3 * u, l + 6 + 3 * s);
+        }
+    for (int pl = 0; pl < 6; pl++) {
+        M3 a = m3_scale(pauli_contract(kSigType[pl], Oup), kSigUp[pl]);
+        M3 b = m3_scale(pauli_contract(kSigType[pl], Olo), kSigLo[pl]);
+        phi_add(g, Phi, p, i, pl, m3_cscale(m3_add(a, b), fac));
+    }
+}
+
+// Phi_p(x) += fac * sum_{s,t} sigma_p[s][t] (A^-1)_{(t),(s)} on odd sites (log-det term)
+__global__ __launch_bounds__(kBlock) void k_logdet_insert(Geom g, const double *__restrict__ cl, double2 fac,
+                                                          double2 *__restrict__ Phi)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.Vh) return;
+    const double2 *off = reinterpret_cast<const double2 *>(cl + 12L * g.Vh);
+    M3 O[2][4];
+    for (int b = 0; b < 2; b++) {
+        double2 A[36];
+        int m = 0;
+        for (int r = 0; r < 6; r++) {
+            A[r * 6 + r] = make_double2(cl[(long)(b * 6 + r) * g.Vh + i], 0);
+            for (int q = r + 1; q < 6; q++, m++) {
+                double2 v = off[(long)(b * 15 + m) * g.Vh + i];
+                A[r * 6 + q] = v;
+                A[q * 6 + r] = cconj(v);
+            }
+        }
+        // O[s*2+t] = colour block (t, s) of A^-1 within the chiral block
+        for (int s = 0; s < 2; s++)
+            for (int t = 0; t < 2; t++)
+                for (int a = 0; a < 3; a++)
+                    for (int bb = 0; bb < 3; bb++) O[b][2 * s + t].e[3 * a + bb] = A[(3 * t + a) * 6 + 3 * s + bb];
+    }
+    for (int pl = 0; pl < 6; pl++) {
+        M3 a = m3_scale(pauli_contract(kSigType[pl], O[0]), kSigUp[pl]);
+        M3 b = m3_scale(pauli_contract(kSigType[pl], O[1]), kSigLo[pl]);
+        phi_add(g, Phi, 1, i, pl, m3_cscale(m3_add(a, b), fac));
+    }
+}
+
+// Psi = (Phi - Phi^dag) / 8 in place
+__global__ void k_phi_to_psi(Geom g, double2 *__restrict__ Phi)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 2L * g.Vh * 6) return;
+    int i = (int)(t % g.Vh);
+    long pp = t / g.Vh;       // p * 6 + plane
+    double2 *b = Phi + pp * 9 * g.Vh + i;
+    M3 m;
+    for (int k = 0; k < 9; k++) m.e[k] = b[(long)k * g.Vh];
+    M3 r = m3_scale(m3_sub(m, m3_dag(m)), 0.125);
+    for (int k = 0; k < 9; k++) b[(long)k * g.Vh] = r.e[k];
+}
+
+__device__ __forceinline__ M3 psi_at(const Geom &g, const double2 *__restrict__ Psi, const int *c, int mu, int nu)
+{
+    int p = parity_of(c), i = eo_index(g, c);
+    int a = mu < nu ? mu : nu, b = mu < nu ? nu : mu;
+    int pl = plane_index(a, b);
+    const double2 *base = Psi + ((long)(p * 6 + pl) * 9) * g.Vh + i;
+    M3 m;
+    for (int k = 0; k < 9; k++) m.e[k] = base[(long)k * g.Vh];
+    return mu < nu ? m : m3_scale(m, -1.0);     // Psi_{nu mu} = -Psi_{mu nu}
+}
+
+// Zacc[link] += sum over the leaves holding the link (see header); one thread per link
+__global__ __launch_bounds__(kBlock) void k_clover_force(Geom g, const double2 *__restrict__ U,
+                                                         const double2 *__restrict__ Psi, double2 *__restrict__ Zacc)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 2L * g.Vh * 4) return;
+    int mu = (int)(t / (2L * g.Vh));
+    long r = t % (2L * g.Vh);
+    int p = (int)(r / g.Vh), i = (int)(r % g.Vh);
+    int y[4];
+    eo_coords(g, p, i, y);
+    M3 Uu = link_at(g, U, y, mu);
+    M3 Zsum = m3_zero();
+    int ypm[4];
+    shifted(g, y, mu, +1, ypm);
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+        int ypn[4], ypmpn[4], ymn[4], ymnpm[4];
+        shifted(g, y, nu, +1, ypn);
+        shifted(g, ypm, nu, +1, ypmpn);
+        shifted(g, y, nu, -1, ymn);
+        shifted(g, ymn, mu, +1, ymnpm);
+        // above: path after U from y+mu: A1 = U_nu(y+mu), A2 = U_mu(y+nu)^dag, A3 = U_nu(y)^dag
+        M3 A1 = link_at(g, U, ypm, nu);
+        M3 A2 = m3_dag(link_at(g, U, ypn, mu));
+        M3 A3 = m3_dag(link_at(g, U, y, nu));
+        M3 A23 = m3_mul(A2, A3), A12 = m3_mul(A1, A2);
+        M3 W = m3_mul(psi_at(g, Psi, ypm, mu, nu), m3_mul(A1, A23));
+        W = m3_add(W, m3_mul(m3_mul(A1, psi_at(g, Psi, ypmpn, mu, nu)), A23));
+        W = m3_add(W, m3_mul(m3_mul(A12, psi_at(g, Psi, ypn, mu, nu)), A3));
+        W = m3_add(W, m3_mul(m3_mul(A12, A3), psi_at(g, Psi, y, mu, nu)));
+        Zsum = m3_add(Zsum, m3_mul(Uu, W));
+        // below: after U^dag from y: B1 = U_nu(y-nu)^dag, B2 = U_mu(y-nu), B3 = U_nu(y-nu+mu)
+        M3 B1 = m3_dag(link_at(g, U, ymn, nu));
+        M3 B2 = link_at(g, U, ymn, mu);
+        M3 B3 = link_at(g, U, ymnpm, nu);
+        M3 B23 = m3_mul(B2, B3), B12 = m3_mul(B1, B2);
+        M3 Wb = m3_mul(psi_at(g, Psi, y, mu, nu), m3_mul(B1, B23));
+        Wb = m3_add(Wb, m3_mul(m3_mul(B1, psi_at(g, Psi, ymn, mu, nu)), B23));
+        Wb = m3_add(Wb, m3_mul(m3_mul(B12, psi_at(g, Psi, ymnpm, mu, nu)), B3));
+        Wb = m3_add(Wb, m3_mul(m3_mul(B12, B3), psi_at(g, Psi, ypm, mu, nu)));
+        Zsum = m3_sub(Zsum, m3_mul_nd(Wb, Uu));
+    }
+    double2 *zb = Zacc + ((long)(p * 4 + mu) * 9) * g.Vh + i;
+    for (int k = 0; k < 9; k++) zb[(long)k * g.Vh] = cadd(zb[(long)k * g.Vh], Zsum.e[k]);
+}
+
+// F[link] += coefficients of Z1 * s1 + Z2 * s2 (either may be null)
+__global__ void k_force_finish(Geom g, const double2 *__restrict__ Z1, double s1, const double2 *__restrict__ Z2,
+                               double s2, double *__restrict__ F)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 2L * g.Vh * 4) return;
+    int mu = (int)(t / (2L * g.Vh));
+    long r = t % (2L * g.Vh);
+    int p = (int)(r / g.Vh), i = (int)(r % g.Vh);
+    long base = ((long)(p * 4 + mu) * 9) * g.Vh + i;
+    M3 Z = m3_zero();
+    for (int k = 0; k < 9; k++) {
+        double2 v = make_double2(0, 0);
+        if (Z1) v = cscale(Z1[base + (long)k * g.Vh], s1);
+        if (Z2) v = cadd(v, cscale(Z2[base + (long)k * g.Vh], s2));
+        Z.e[k] = v;
+    }
+    double f[8];
+    lie_coeffs(Z, f);
+    double *fb = F + ((long)(p * 4 + mu) * 8) * g.Vh + i;
+    for (int a = 0; a < 8; a++) fb[(long)a * g.Vh] += f[a];
+}
+
+// ---------------------------------------------------------------- gauge part
+
+__global__ __launch_bounds__(kBlock) void k_gauge_force(Geom g, const double2 *__restrict__ U, double coef,
+                                                        double *__restrict__ F)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 2L * g.Vh * 4) return;
+    int mu = (int)(t / (2L * g.Vh));
+    long r = t % (2L * g.Vh);
+    int p = (int)(r / g.Vh), i = (int)(r % g.Vh);
+    int y[4], ypm[4];
+    eo_coords(g, p, i, y);
+    shifted(g, y, mu, +1, ypm);
+    M3 st = m3_zero();
+    for (int nu = 0; nu < 4; nu++) {
+        if (nu == mu) continue;
+        int ypn[4], ymn[4], ypmmn[4];
+        shifted(g, y, nu, +1, ypn);
+        shifted(g, y, nu, -1, ymn);
+        shifted(g, ypm, nu, -1, ypmmn);
+        // U_nu(y+mu) U_mu(y+nu)^dag U_nu(y)^dag
+        M3 a = m3_mul_nd(link_at(g, U, ypm, nu), m3_mul(link_at(g, U, y, nu), link_at(g, U, ypn, mu)));
+        // U_nu(y+mu-nu)^dag U_mu(y-nu)^dag U_nu(y-nu)
+        M3 b = m3_mul_dn(m3_mul(link_at(g, U, ymn, mu), link_at(g, U, ypmmn, nu)), link_at(g, U, ymn, nu));
+        st = m3_add(st, m3_add(a, b));
+    }
+    M3 Z = m3_scale(m3_mul(link_at(g, U, y, mu), st), coef);
+    double f[8];
+    lie_coeffs(Z, f);
+    double *fb = F + ((long)(p * 4 + mu) * 8) * g.Vh + i;
+    for (int a = 0; a < 8; a++) fb[(long)a * g.Vh] += f[a];
+}
+
+// ---------------------------------------------------------------- updates
+
+__global__ void k_update_momenta(long n, double eps, const double *__restrict__ F, double *__restrict__ P)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) P[t] -= eps * F[t];
+}
+
+// exp(Q) for anti-Hermitian traceless Q: scaling and squaring with a degree-14
+// Taylor polynomial (Horner) on Q / 2^k, |Q / 2^k|_F <= 1/4.
+__device__ M3 expm_ah(const M3 &Q)
+{
+    double nrm = 0;
+    for (int k = 0; k < 9; k++) nrm += Q.e[k].x * Q.e[k].x + Q.e[k].y * Q.e[k].y;
+    nrm = sqrt(nrm);
+    int sq = 0;
+    double sc = 1;
+    while (nrm * sc > 0.25 && sq < 40) { sc *= 0.5; sq++; }
+    M3 A = m3_scale(Q, sc);
+    M3 E = m3_eye();
+    for (int k = 14; k >= 1; k--) {
+        E = m3_scale(m3_mul(A, E), 1.0 / k);
+        E.e[0].x += 1; E.e[4].x += 1; E.e[8].x += 1;
+    }
+    for (int s = 0; s < sq; s++) E = m3_mul(E, E);
+    return E;
+}
+
+__global__ void k_update_gauge(Geom g, double eps, const double *__restrict__ P, double2 *__restrict__ U)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 2L * g.Vh * 4) return;
+    int mu = (int)(t / (2L * g.Vh));
+    long r = t % (2L * g.Vh);
+    int p = (int)(r / g.Vh), i = (int)(r % g.Vh);
+    double pa[8];
+    const double *pb = P + ((long)(p * 4 + mu) * 8) * g.Vh + i;
+    for (int a = 0; a < 8; a++) pa[a] = pb[(long)a * g.Vh];
+    M3 H = lie_matrix(pa);
+    M3 Q;
+    for (int k = 0; k < 9; k++) Q.e[k] = cscale(ctimesi(H.e[k]), eps);   // i eps P
+    M3 E = expm_ah(Q);
+    double2 *ub = U + ((long)(p * 4 + mu) * 9) * g.Vh + i;
+    M3 Uu;
+    for (int k = 0; k < 9; k++) Uu.e[k] = ub[(long)k * g.Vh];
+    M3 Un = m3_mul(E, Uu);
+    for (int k = 0; k < 9; k++) ub[(long)k * g.Vh] = Un.e[k];
+}
+
+// ---------------------------------------------------------------- actions
+
+__device__ __forceinline__ void block_partial(double v, double *out)
+{
+    __shared__ double sh[kBlock / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int k = 0; k < kBlock / 64; k++) s += sh[k];
+        out[blockIdx.x] = s;
+    }
+}
+
+// sum over plaquettes of (1 - Re tr U_P / 3), one thread per site
+__global__ __launch_bounds__(kBlock) void k_plaq(Geom g, const double2 *__restrict__ U, double *__restrict__ part)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    double s = 0;
+    if (t < 2L * g.Vh) {
+        int p = (int)(t / g.Vh), i = (int)(t % g.Vh);
+        int c[4];
+        eo_coords(g, p, i, c);
+        for (int mu = 0; mu < 4; mu++)
+            for (int nu = mu + 1; nu < 4; nu++) {
+                int a[4], b[4];
+                shifted(g, c, mu, +1, a);
+                shifted(g, c, nu, +1, b);
+                M3 P = m3_mul_nd(m3_mul(link_at(g, U, c, mu), link_at(g, U, a, nu)),
+                                 m3_mul(link_at(g, U, c, nu), link_at(g, U, b, mu)));
+                s += 1.0 - m3_trace(P).x / 3.0;
+            }
+    }
+    block_partial(s, part);
+}
+
+// 1/2 sum_a p_a^2 = sum tr P^2
+__global__ __launch_bounds__(kBlock) void k_kinetic(long n, const double *__restrict__ P, double *__restrict__ part)
+{
+    double s = 0;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+        s += 0.5 * P[t] * P[t];
+    block_partial(s, part);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+static int force_ws(pfmp_ctx *ctx, double2 **Zhop, double2 **Phi, double2 **Xo, double2 **Zo)
+{
+    const Geom &g = ctx->g;
+    *Zhop = (double2 *)ws_alloc(ctx, sizeof(double2) * 2L * 4 * 9 * g.Vh, 14);
+    *Phi = (double2 *)ws_alloc(ctx, sizeof(double2) * 2L * 6 * 9 * g.Vh, 16);
+    if (Xo) *Xo = (double2 *)ws_alloc(ctx, sizeof(double) * spinor_reals(g), 17);
+    if (Zo) *Zo = (double2 *)ws_alloc(ctx, sizeof(double) * spinor_reals(g), 18);
+    if (!*Zhop || !*Phi || (Xo && !*Xo) || (Zo && !*Zo)) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
+    return 0;
+}
+
+static int clover_force_finish(pfmp_ctx *ctx, double2 *Phi, double2 *Zacc)
+{
+    const Geom &g = ctx->g;
+    hipLaunchKernelGGL(k_phi_to_psi, dim3(nblocks(2L * g.Vh * 6, 256)), dim3(256), 0, ctx->stream, g, Phi);
+    hipLaunchKernelGGL(k_clover_force, dim3(nblocks(2L * g.Vh * 4, kBlock)), dim3(kBlock), 0, ctx->stream, g, ctx->U,
+                       Phi, Zacc);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void *const *X, const void *const *Y,
+                                  const double *coeff, int flags, double *F)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
+        return set_err(ctx, PFMP_ERR_STATE, "fermion_force: operator not configured");
+    if (npairs < 0 || (npairs > 0 && (!X || !Y || !coeff)) || !F)
+        return set_err(ctx, PFMP_ERR_ARG, "fermion_force: bad arguments");
+    for (int q = 0; q < npairs; q++)
+        if (!X[q] || !Y[q]) return set_err(ctx, PFMP_ERR_ARG, "fermion_force: null field");
+    if (flags == 0) flags = PFMP_FORCE_HOP | PFMP_FORCE_CLOVER;
+    const Geom &g = ctx->g;
+    OpSlot &s = ctx->ops[op];
+    const bool cl = s.csw != 0;
+    const bool do_clov = cl && (flags & PFMP_FORCE_CLOVER);
+    const bool do_hop = (flags & PFMP_FORCE_HOP) != 0;
+    double2 *Zhop, *Phi, *Xo, *Zo;
+    int rc = force_ws(ctx, &Zhop, &Phi, &Xo, &Zo);
+    if (rc) return rc;
+    HIPCHK(ctx, hipMemsetAsync(Zhop, 0, sizeof(double2) * 2L * 4 * 9 * g.Vh, ctx->stream));
+    if (do_clov) HIPCHK(ctx, hipMemsetAsync(Phi, 0, sizeof(double2) * 2L * 6 * 9 * g.Vh, ctx->stream));
+    const double k2 = s.kappa * s.kappa, kc = s.kappa * s.csw;
+    for (int q = 0; q < npairs; q++) {
+        const double2 *x = (const double2 *)X[q], *y = (const double2 *)Y[q];
+        double2 c = make_double2(coeff[2 * q], coeff[2 * q + 1]);
+        // Z = A_oo^-1 D_oe Y,  Xo = A_oo^-1 g5 D_oe g5 X = A_oo^-1 (D_eo)^dag X
+        if ((rc = launch_clovinv<double2, double>(ctx, 1, y, ctx->U, s.clov[1], Zo, 1.0, 1.0, cl, nullptr))) return rc;
+        if ((rc = launch_clovinv<double2, double>(ctx, 1, x, ctx->U, s.clov[1], Xo, -1.0, -1.0, cl, nullptr))) return rc;
+        if (do_hop)
+            hipLaunchKernelGGL(k_hop_force, dim3(nblocks(2L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, x, Xo,
+                               y, Zo, ctx->U, c, Zhop);
+        if (do_clov) {
+            // i kappa c_sw c w:  w = 1 even, kappa^2 odd
+            double2 ic = ctimesi(cscale(c, kc));
+            hipLaunchKernelGGL(k_clover_insert, dim3(nblocks(2L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, x,
+                               Xo, y, Zo, ic, cscale(ic, k2), Phi);
+        }
+        LAUNCHCHK(ctx);
+    }
+    double2 *Zcl = nullptr;
+    if (do_clov) {
+        Zcl = (double2 *)ws_alloc(ctx, sizeof(double2) * 2L * 4 * 9 * g.Vh, 19);
+        if (!Zcl) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
+        HIPCHK(ctx, hipMemsetAsync(Zcl, 0, sizeof(double2) * 2L * 4 * 9 * g.Vh, ctx->stream));
+        if ((rc = clover_force_finish(ctx, Phi, Zcl))) return rc;
+    }
+    hipLaunchKernelGGL(k_force_finish, dim3(nblocks(2L * g.Vh * 4, 256)), dim3(256), 0, ctx->stream, g,
+                       do_hop ? Zhop : nullptr, -k2, Zcl, 1.0, F);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_logdet_force(pfmp_ctx *ctx, int op, double coef, double *F)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
+        return set_err(ctx, PFMP_ERR_STATE, "logdet_force: operator not configured");
+    if (!F) return set_err(ctx, PFMP_ERR_ARG, "logdet_force: null force");
+    OpSlot &s = ctx->ops[op];
+    if (s.csw == 0) return 0;
+    const Geom &g = ctx->g;
+    double2 *Zcl, *Phi;
+    int rc = force_ws(ctx, &Zcl, &Phi, nullptr, nullptr);
+    if (rc) return rc;
+    HIPCHK(ctx, hipMemsetAsync(Zcl, 0, sizeof(double2) * 2L * 4 * 9 * g.Vh, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(Phi, 0, sizeof(double2) * 2L * 6 * 9 * g.Vh, ctx->stream));
+    double2 fac = ctimesi(make_double2(-2.0 * coef * s.kappa * s.csw, 0));
+    hipLaunchKernelGGL(k_logdet_insert, dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, s.clov[1], fac,
+                       Phi);
+    LAUNCHCHK(ctx);
+    if ((rc = clover_force_finish(ctx, Phi, Zcl))) return rc;
+    hipLaunchKernelGGL(k_force_finish, dim3(nblocks(2L * g.Vh * 4, 256)), dim3(256), 0, ctx->stream, g, Zcl, 1.0,
+                       nullptr, 0.0, F);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_gauge_force(pfmp_ctx *ctx, double beta, double *F)
+{
+    if (!ctx || !F) return ctx ? set_err(ctx, PFMP_ERR_ARG, "gauge_force: null") : PFMP_ERR_ARG;
+    if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
+    const Geom &g = ctx->g;
+    hipLaunchKernelGGL(k_gauge_force, dim3(nblocks(2L * g.Vh * 4, kBlock)), dim3(kBlock), 0, ctx->stream, g, ctx->U,
+                       -beta / 3.0, F);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_update_momenta(pfmp_ctx *ctx, double eps, const double *F, double *P)
+{
+    if (!ctx || !F || !P) return ctx ? set_err(ctx, PFMP_ERR_ARG, "update_momenta: null") : PFMP_ERR_ARG;
+    long n = mom_reals(ctx->g);
+    hipLaunchKernelGGL(k_update_momenta, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, eps, F, P);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_update_gauge(pfmp_ctx *ctx, double eps, const double *P)
+{
+    if (!ctx || !P) return ctx ? set_err(ctx, PFMP_ERR_ARG, "update_gauge: null") : PFMP_ERR_ARG;
+    if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
+    const Geom &g = ctx->g;
+    hipLaunchKernelGGL(k_update_gauge, dim3(nblocks(2L * g.Vh * 4, kBlock)), dim3(kBlock), 0, ctx->stream, g, eps, P,
+                       ctx->U);
+    LAUNCHCHK(ctx);
+    return rebuild_gauge_derived(ctx);
+}
+
+extern "C" int pfmp_gauge_action(pfmp_ctx *ctx, double beta, double *out)
+{
+    if (!ctx || !out) return ctx ? set_err(ctx, PFMP_ERR_ARG, "gauge_action: null") : PFMP_ERR_ARG;
+    if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
+    const Geom &g = ctx->g;
+    int nb = nblocks(2L * g.Vh, kBlock);
+    double *part = (double *)ws_alloc(ctx, sizeof(double) * nb, 15);
+    if (!part) return set_err(ctx, PFMP_ERR_OOM, "workspace");
+    hipLaunchKernelGGL(k_plaq, dim3(nb), dim3(kBlock), 0, ctx->stream, g, ctx->U, part);
+    LAUNCHCHK(ctx);
+    double v;
+    int rc = red_finish(ctx, part, nb, 1, &v);
+    if (rc) return rc;
+    *out = beta * v;
+    return 0;
+}
+
+extern "C" int pfmp_kinetic(pfmp_ctx *ctx, const double *P, double *out)
+{
+    if (!ctx || !P || !out) return ctx ? set_err(ctx, PFMP_ERR_ARG, "kinetic: null") : PFMP_ERR_ARG;
+    long n = mom_reals(ctx->g);
+    int nb = 1024;
+    double *part = (double *)ws_alloc(ctx, sizeof(double) * nb, 15);
+    if (!part) return set_err(ctx, PFMP_ERR_OOM, "workspace");
+    hipLaunchKernelGGL(k_kinetic, dim3(nb), dim3(kBlock), 0, ctx->stream, n, P, part);
+    LAUNCHCHK(ctx);
+    return red_finish(ctx, part, nb, 1, out);
+}

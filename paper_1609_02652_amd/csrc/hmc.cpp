@@ -1,0 +1,531 @@
+// hmc.cpp -- PF-MP HMC driver (paper Sec. 2.1 HMC, eq. pfmp_action, App. B
+// generalized multi-scale integrator, App. C forces), composed from the C-ABI
+// kernels.  Host code only: every lattice operation is a libpfmp launch.
+//
+// Action: S = S_G + S_det + sum_j S_j, with S_det = -2 sum_{x odd} ln det A(x)
+// of the target operator (det M = det A_oo det Mhat) and the filter terms
+//   POLY      phi^dag P(J) phi,         P = a_n prod_k (J - z_k)
+//   POLYCORR  phi^dag [J P(J)]^-1 phi = (1/a_n) sum_{i=1}^{n+1} r_i phi^dag (J - z_i)^-1 phi, z_{n+1} = 0
+//   RATIO     phi^dag W^dag K_b^-1 W phi
+//   HEAVY     phi^dag J^-1 phi
+// Forces (coefficients f_a = dS/dw along U -> exp(i w T_a) U), built from the
+// bilinear primitive Re[c X^dag dMhat Y] with Re[c X^dag dJ Y] =
+// Re[c (W X)^dag dW Y] + Re[conj(c) (W Y)^dag dW X]:
+//   POLY      sum_i Re[eta_i^dag dJ chi_i], chi_i = a_n prod_{j>i}(J - z_j) phi, eta_i = prod_{j<i}(J - z_j^*) phi
+//   POLYCORR  -(1/a_n) sum_i r_i x_{i*}^dag dJ x_i, x_i = (J - z_i)^-1 phi, z_{i*} = conj(z_i)
+//   RATIO     2 Re[X^dag dW phi] - 2 Re[(M_b X)^dag dM_b X], X = K_b^-1 W phi
+//   HEAVY     -2 Re[(W X)^dag dW X], X = J^-1 phi
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+constexpr double kOmelyanLambda = 0.1931833275037836;
+
+struct Scheme {
+    std::vector<int64_t> T;
+    std::vector<double> S;
+};
+
+// n-step 2MN S[lh] T[h/2] S[(1-2l)h] T[h/2] S[lh] with adjacent space steps merged;
+// time steps in ticks of tau / L (L a multiple of 2n).
+Scheme omelyan(int n, int64_t L, double tau, double lam)
+{
+    Scheme s;
+    double h = tau / n;
+    int64_t half = L / (2 * n);
+    s.T.push_back(0);
+    s.S.push_back(lam * h);
+    for (int k = 0; k < n; k++) {
+        s.T.push_back(half);
+        s.S.push_back((1 - 2 * lam) * h);
+        s.T.push_back(half);
+        s.S.push_back((k < n - 1 ? 2 * lam : lam) * h);
+    }
+    return s;
+}
+
+int64_t lcm64(int64_t a, int64_t b) { return a / std::gcd(a, b) * b; }
+
+struct Ctx {
+    pfmp_ctx *c;
+    const pfmp_hmc_spec *sp;
+    long long mhalf = 0;       // Mhat applications (2 per Khat)
+    long long iters = 0;
+};
+
+int chk_spec(pfmp_ctx *ctx, const pfmp_hmc_spec *sp)
+{
+    if (!sp || sp->nterms < 0 || sp->nterms > PFMP_MAX_TERMS || (sp->nterms > 0 && !sp->terms))
+        return set_err(ctx, PFMP_ERR_ARG, "hmc: bad spec");
+    if (sp->gauge_steps <= 0 || !(sp->tau > 0) || !(sp->tol > 0)) return set_err(ctx, PFMP_ERR_ARG, "hmc: bad spec");
+    for (int j = 0; j < sp->nterms; j++) {
+        const pfmp_term &t = sp->terms[j];
+        if (t.steps <= 0 || t.op < 0 || t.op >= PFMP_MAX_OPS || !ctx->ops[t.op].valid)
+            return set_err(ctx, PFMP_ERR_ARG, "hmc: term operator or steps");
+        if (t.kind == PFMP_TERM_RATIO && (t.op2 < 0 || t.op2 >= PFMP_MAX_OPS || !ctx->ops[t.op2].valid))
+            return set_err(ctx, PFMP_ERR_ARG, "hmc: ratio denominator");
+        if ((t.kind == PFMP_TERM_POLY || t.kind == PFMP_TERM_POLYCORR) && (t.n < 2 || (t.n & 1) || t.n + 1 > PFMP_MAX_SHIFTS))
+            return set_err(ctx, PFMP_ERR_ARG, "hmc: polynomial degree must be even, 2..126");
+    }
+    return 0;
+}
+
+void roots_of(const pfmp_term &t, std::vector<cd> &z, double &a)
+{
+    std::vector<double> r(2 * t.n);
+    double nm[2];
+    pfmp_chebyshev(t.n, t.mu, t.nu, r.data(), nm);
+    z.resize(t.n);
+    for (int k = 0; k < t.n; k++) z[k] = cd(r[2 * k], r[2 * k + 1]);
+    a = nm[0];
+}
+
+std::vector<cd> residues(const std::vector<cd> &z)
+{
+    std::vector<cd> r(z.size());
+    for (size_t i = 0; i < z.size(); i++) {
+        cd p = 1.0;
+        for (size_t j = 0; j < z.size(); j++)
+            if (j != i) p /= (z[j] - z[i]);
+        r[i] = p;
+    }
+    return r;
+}
+
+int partner(const std::vector<cd> &z, int i)
+{
+    int best = 0;
+    for (size_t j = 0; j < z.size(); j++)
+        if (std::abs(z[j] - std::conj(z[i])) < std::abs(z[best] - std::conj(z[i]))) best = (int)j;
+    return best;
+}
+
+int solve(Ctx &X, int op, const void *b, void *x)
+{
+    pfmp_solver_params p{X.sp->tol, X.sp->maxiter > 0 ? X.sp->maxiter : 100000, PFMP_F64, 0.0, 0};
+    pfmp_solver_stats st{};
+    int rc = pfmp_cg_solve(X.c, op, b, x, &p, &st);
+    X.iters += st.iters;
+    X.mhalf += 2 * st.kmults;
+    return rc;
+}
+
+int msolve(Ctx &X, int op, const std::vector<cd> &z, const void *b, std::vector<double2 *> &xs)
+{
+    std::vector<double> zz(2 * z.size());
+    for (size_t k = 0; k < z.size(); k++) {
+        zz[2 * k] = z[k].real();
+        zz[2 * k + 1] = z[k].imag();
+    }
+    pfmp_solver_params p{X.sp->tol, X.sp->maxiter > 0 ? X.sp->maxiter : 100000, PFMP_F64, 0.0, 0};
+    pfmp_solver_stats st{};
+    std::vector<void *> xv(xs.begin(), xs.end());
+    int rc = pfmp_cg_multishift(X.c, op, (int)z.size(), zz.data(), b, xv.data(), &p, &st);
+    X.iters += st.iters;
+    X.mhalf += 2 * st.kmults;
+    return rc;
+}
+
+int applyM(Ctx &X, int op, int dag, const void *in, void *out)
+{
+    X.mhalf += 1;
+    return pfmp_apply_M(X.c, op, dag, in, out, PFMP_F64);
+}
+
+int poly(Ctx &X, int op, const std::vector<cd> &roots, cd norm, const void *in, void *out, void *const *chain)
+{
+    std::vector<double> r(2 * roots.size());
+    for (size_t k = 0; k < roots.size(); k++) {
+        r[2 * k] = roots[k].real();
+        r[2 * k + 1] = roots[k].imag();
+    }
+    double nm[2] = {norm.real(), norm.imag()};
+    X.mhalf += 2 * (long long)roots.size();
+    return pfmp_apply_poly(X.c, op, (int)roots.size(), r.data(), nm, in, out, chain, PFMP_F64);
+}
+
+cd dot(Ctx &X, const void *a, const void *b, int &rc)
+{
+    double d[2] = {0, 0};
+    rc = pfmp_dot(X.c, a, b, d);
+    return cd(d[0], d[1]);
+}
+
+// pool indices: [0,16) phi of pfmp_trajectory, [16, 32) temporaries, [32, ...) chains
+constexpr int kTmp = 16, kChain = 32;
+
+// S_j(phi)
+int term_action(Ctx &X, const pfmp_term &t, const void *phi, double *S)
+{
+    pfmp_ctx *ctx = X.c;
+    int rc = 0;
+    double2 *t0 = pool_get(ctx, kTmp), *t1 = pool_get(ctx, kTmp + 1);
+    if (!t0 || !t1) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+    switch (t.kind) {
+    case PFMP_TERM_POLY: {
+        std::vector<cd> z;
+        double a;
+        roots_of(t, z, a);
+        if ((rc = poly(X, t.op, z, a, phi, t0, nullptr))) return rc;
+        *S = dot(X, phi, t0, rc).real();
+        return rc;
+    }
+    case PFMP_TERM_POLYCORR: {
+        std::vector<cd> z;
+        double a;
+        roots_of(t, z, a);
+        z.push_back(0.0);
+        std::vector<cd> r = residues(z);
+        std::vector<double2 *> xs(z.size());
+        for (size_t k = 0; k < z.size(); k++)
+            if (!(xs[k] = pool_get(ctx, kChain + (int)k))) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+        if ((rc = msolve(X, t.op, z, phi, xs))) return rc;
+        cd s = 0;
+        for (size_t k = 0; k < z.size(); k++) {
+            s += r[k] * dot(X, phi, xs[k], rc);
+            if (rc) return rc;
+        }
+        *S = (s / a).real();
+        return 0;
+    }
+    case PFMP_TERM_RATIO:
+        if ((rc = applyM(X, t.op, 0, phi, t0))) return rc;
+        if ((rc = solve(X, t.op2, t0, t1))) return rc;
+        *S = dot(X, t0, t1, rc).real();
+        return rc;
+    case PFMP_TERM_HEAVY:
+        if ((rc = solve(X, t.op, phi, t0))) return rc;
+        *S = dot(X, phi, t0, rc).real();
+        return rc;
+    }
+    return set_err(ctx, PFMP_ERR_ARG, "hmc: unknown term");
+}
+
+int term_heatbath(Ctx &X, const pfmp_term &t, const void *eta, void *phi)
+{
+    pfmp_ctx *ctx = X.c;
+    int rc = 0;
+    double2 *t0 = pool_get(ctx, kTmp), *t1 = pool_get(ctx, kTmp + 1);
+    if (!t0 || !t1) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+    switch (t.kind) {
+    case PFMP_TERM_POLY: {
+        // P = R^dag R, R = sqrt(a) prod_{k<=n/2} (J - z_k); phi = R^-1 eta by partial
+        // fractions over the n/2 poles and one multi-shift solve
+        std::vector<cd> z;
+        double a;
+        roots_of(t, z, a);
+        z.resize(t.n / 2);
+        std::vector<cd> r = residues(z);
+        std::vector<double2 *> xs(z.size());
+        for (size_t k = 0; k < z.size(); k++)
+            if (!(xs[k] = pool_get(ctx, kChain + (int)k))) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+        if ((rc = msolve(X, t.op, z, eta, xs))) return rc;
+        double zero[2] = {0, 0};
+        HIPCHK(ctx, hipMemsetAsync(phi, 0, sizeof(double) * spinor_reals(ctx->g), ctx->stream));
+        for (size_t k = 0; k < z.size(); k++) {
+            cd c = r[k] / std::sqrt(a);
+            double cc[2] = {c.real(), c.imag()}, one[2] = {1, 0};
+            if ((rc = pfmp_axpby(ctx, cc, xs[k], one, phi))) return rc;
+        }
+        (void)zero;
+        return 0;
+    }
+    case PFMP_TERM_POLYCORR: {
+        // phi = R^dag W^dag eta = sqrt(a) prod_{k<=n/2} (J - z_k^*) W^dag eta
+        std::vector<cd> z;
+        double a;
+        roots_of(t, z, a);
+        std::vector<cd> zc(t.n / 2);
+        for (int k = 0; k < t.n / 2; k++) zc[k] = std::conj(z[k]);
+        if ((rc = applyM(X, t.op, 1, eta, t0))) return rc;
+        return poly(X, t.op, zc, std::sqrt(a), t0, phi, nullptr);
+    }
+    case PFMP_TERM_RATIO:
+        // phi = J^-1 W^dag M_b^dag eta
+        if ((rc = applyM(X, t.op2, 1, eta, t0))) return rc;
+        if ((rc = applyM(X, t.op, 1, t0, t1))) return rc;
+        return solve(X, t.op, t1, phi);
+    case PFMP_TERM_HEAVY:
+        return applyM(X, t.op, 1, eta, phi);
+    }
+    return set_err(ctx, PFMP_ERR_ARG, "hmc: unknown term");
+}
+
+// F += eps * dS_j/dw
+int term_force(Ctx &X, const pfmp_term &t, const void *phi, double eps, double *F)
+{
+    pfmp_ctx *ctx = X.c;
+    int rc = 0;
+    std::vector<const void *> XX, YY;
+    std::vector<double> cc;
+    auto pair = [&](const void *x, const void *y, cd c) {
+        XX.push_back(x);
+        YY.push_back(y);
+        cc.push_back(c.real());
+        cc.push_back(c.imag());
+    };
+    switch (t.kind) {
+    case PFMP_TERM_POLY: {
+        std::vector<cd> z;
+        double a;
+        roots_of(t, z, a);
+        const int n = t.n;
+        // eta_1..eta_n from roots z_1^*..z_{n-1}^*; chi_n..chi_1 from z_n..z_2 with norm a
+        std::vector<void *> E(n), C(n), WE(n), WC(n);
+        for (int k = 0; k < n; k++) {
+            E[k] = pool_get(ctx, kChain + k);
+            C[k] = pool_get(ctx, kChain + n + k);
+            WE[k] = pool_get(ctx, kChain + 2 * n + k);
+            WC[k] = pool_get(ctx, kChain + 3 * n + k);
+            if (!E[k] || !C[k] || !WE[k] || !WC[k]) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+        }
+        std::vector<cd> re(n - 1), rc_(n - 1);
+        for (int k = 0; k < n - 1; k++) {
+            re[k] = std::conj(z[k]);
+            rc_[k] = z[n - 1 - k];
+        }
+        if ((rc = poly(X, t.op, re, 1.0, phi, E[n - 1], E.data()))) return rc;       // E[k] = eta_{k+1}
+        if ((rc = poly(X, t.op, rc_, a, phi, C[n - 1], C.data()))) return rc;        // C[k] = chi_{n-k}
+        for (int i = 1; i <= n; i++) {
+            void *eta = E[i - 1], *chi = C[n - i];
+            if ((rc = applyM(X, t.op, 0, eta, WE[i - 1]))) return rc;
+            if ((rc = applyM(X, t.op, 0, chi, WC[i - 1]))) return rc;
+            pair(WE[i - 1], chi, eps);
+            pair(WC[i - 1], eta, eps);
+        }
+        return pfmp_fermion_force(ctx, t.op, (int)XX.size(), XX.data(), YY.data(), cc.data(), 0, F);
+    }
+    case PFMP_TERM_POLYCORR: {
+        std::vector<cd> z;
+        double a;
+        roots_of(t, z, a);
+        z.push_back(0.0);
+        const int m = (int)z.size();
+        std::vector<cd> r = residues(z);
+        std::vector<double2 *> xs(m), wx(m);
+        for (int k = 0; k < m; k++) {
+            xs[k] = pool_get(ctx, kChain + k);
+            wx[k] = pool_get(ctx, kChain + m + k);
+            if (!xs[k] || !wx[k]) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+        }
+        if ((rc = msolve(X, t.op, z, phi, xs))) return rc;
+        for (int k = 0; k < m; k++)
+            if ((rc = applyM(X, t.op, 0, xs[k], wx[k]))) return rc;
+        for (int i = 0; i < m; i++) {
+            int j = partner(z, i);
+            cd c = -eps * r[i] / a;
+            // Re[c x_j^dag dJ x_i]
+            pair(wx[j], xs[i], c);
+            pair(wx[i], xs[j], std::conj(c));
+        }
+        return pfmp_fermion_force(ctx, t.op, (int)XX.size(), XX.data(), YY.data(), cc.data(), 0, F);
+    }
+    case PFMP_TERM_RATIO: {
+        double2 *t0 = pool_get(ctx, kTmp), *x = pool_get(ctx, kTmp + 1), *mx = pool_get(ctx, kTmp + 2);
+        if (!t0 || !x || !mx) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+        if ((rc = applyM(X, t.op, 0, phi, t0))) return rc;
+        if ((rc = solve(X, t.op2, t0, x))) return rc;
+        if ((rc = applyM(X, t.op2, 0, x, mx))) return rc;
+        const void *xa[1] = {x}, *ya[1] = {phi};
+        double ca[2] = {2 * eps, 0};
+        if ((rc = pfmp_fermion_force(ctx, t.op, 1, xa, ya, ca, 0, F))) return rc;
+        const void *xb[1] = {mx}, *yb[1] = {x};
+        double cb[2] = {-2 * eps, 0};
+        return pfmp_fermion_force(ctx, t.op2, 1, xb, yb, cb, 0, F);
+    }
+    case PFMP_TERM_HEAVY: {
+        double2 *x = pool_get(ctx, kTmp + 1), *wx = pool_get(ctx, kTmp + 2);
+        if (!x || !wx) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+        if ((rc = solve(X, t.op, phi, x))) return rc;
+        if ((rc = applyM(X, t.op, 0, x, wx))) return rc;
+        const void *xa[1] = {wx}, *ya[1] = {x};
+        double ca[2] = {-2 * eps, 0};
+        return pfmp_fermion_force(ctx, t.op, 1, xa, ya, ca, 0, F);
+    }
+    }
+    return set_err(ctx, PFMP_ERR_ARG, "hmc: unknown term");
+}
+
+int hamiltonian(Ctx &X, const double *P, const void *const *phi, double *parts, bool with_terms)
+{
+    pfmp_ctx *ctx = X.c;
+    const pfmp_hmc_spec *sp = X.sp;
+    int rc;
+    if ((rc = pfmp_kinetic(ctx, P, &parts[0]))) return rc;
+    if ((rc = pfmp_gauge_action(ctx, sp->beta, &parts[1]))) return rc;
+    parts[2] = 0;
+    if (sp->det_op >= 0 && (rc = pfmp_logdet_action(ctx, sp->det_op, &parts[2]))) return rc;
+    if (with_terms)
+        for (int j = 0; j < sp->nterms; j++)
+            if ((rc = term_action(X, sp->terms[j], phi[j], &parts[3 + j]))) return rc;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" int pfmp_heatbath(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const void *const *eta, void *const *phi)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    int rc = chk_spec(ctx, spec);
+    if (rc) return rc;
+    if (spec->nterms > 0 && (!eta || !phi)) return set_err(ctx, PFMP_ERR_ARG, "heatbath: null buffers");
+    Ctx X{ctx, spec};
+    for (int j = 0; j < spec->nterms; j++)
+        if ((rc = term_heatbath(X, spec->terms[j], eta[j], phi[j]))) return rc;
+    return 0;
+}
+
+extern "C" int pfmp_hamiltonian(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const double *P, const void *const *phi,
+                                double *H, double *parts)
+{
+    if (!ctx || !P || !H) return ctx ? set_err(ctx, PFMP_ERR_ARG, "hamiltonian: null") : PFMP_ERR_ARG;
+    int rc = chk_spec(ctx, spec);
+    if (rc) return rc;
+    Ctx X{ctx, spec};
+    double loc[PFMP_MAX_TERMS + 3] = {0};
+    if ((rc = hamiltonian(X, P, phi, loc, true))) return rc;
+    double s = 0;
+    for (int k = 0; k < spec->nterms + 3; k++) s += loc[k];
+    *H = s;
+    if (parts) std::memcpy(parts, loc, sizeof(double) * (spec->nterms + 3));
+    return 0;
+}
+
+static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats *st)
+{
+    pfmp_ctx *ctx = X.c;
+    const pfmp_hmc_spec *sp = X.sp;
+    const int nt = sp->nterms + 1;
+    const double lam = sp->lambda != 0 ? sp->lambda : kOmelyanLambda;
+    int64_t L = 2LL * sp->gauge_steps;
+    for (int j = 0; j < sp->nterms; j++) L = lcm64(L, 2LL * sp->terms[j].steps);
+    std::vector<Scheme> sch;
+    sch.push_back(omelyan(sp->gauge_steps, L, sp->tau, lam));
+    for (int j = 0; j < sp->nterms; j++) sch.push_back(omelyan(sp->terms[j].steps, L, sp->tau, lam));
+    std::vector<int> len(nt);
+    std::vector<int64_t> T;
+    std::vector<double> S;
+    int cap = 0;
+    for (int j = 0; j < nt; j++) {
+        len[j] = (int)sch[j].T.size();
+        cap += len[j];
+        T.insert(T.end(), sch[j].T.begin(), sch[j].T.end());
+        S.insert(S.end(), sch[j].S.begin(), sch[j].S.end());
+    }
+    std::vector<int64_t> To(cap);
+    std::vector<double> So((size_t)cap * nt);
+    int nout = 0;
+    int rc = pfmp_schedule_build(nt, len.data(), T.data(), S.data(), cap, To.data(), So.data(), &nout);
+    if (rc) return set_err(ctx, rc, "hmc: schedule merge failed");
+    double *F = (double *)ws_alloc(ctx, sizeof(double) * mom_reals(ctx->g), 24);
+    if (!F) return set_err(ctx, PFMP_ERR_OOM, "force buffer");
+    const double tick = sp->tau / (double)L;
+    if (st) {
+        st->nsteps = nout;
+        for (int j = 0; j < nt; j++) st->nforce[j] = 0;
+    }
+    for (int k = 0; k < nout; k++) {
+        if (To[k] != 0 && (rc = pfmp_update_gauge(ctx, tick * (double)To[k], P))) return rc;
+        bool any = false;
+        for (int j = 0; j < nt; j++) any = any || So[(size_t)j * cap + k] != 0.0;
+        if (!any) continue;
+        HIPCHK(ctx, hipMemsetAsync(F, 0, sizeof(double) * mom_reals(ctx->g), ctx->stream));
+        for (int j = 0; j < nt; j++) {
+            double eps = So[(size_t)j * cap + k];
+            if (eps == 0.0) continue;
+            if (st) st->nforce[j]++;
+            if (j == 0) {
+                if ((rc = pfmp_gauge_force(ctx, sp->beta * eps, F))) return rc;
+                if (sp->det_op >= 0 && (rc = pfmp_logdet_force(ctx, sp->det_op, eps, F))) return rc;
+            } else if ((rc = term_force(X, sp->terms[j - 1], phi[j - 1], eps, F))) {
+                return rc;
+            }
+        }
+        if ((rc = pfmp_update_momenta(ctx, 1.0, F, P))) return rc;
+    }
+    return 0;
+}
+
+extern "C" int pfmp_md_evolve(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, double *P, const void *const *phi,
+                              pfmp_traj_stats *st)
+{
+    if (!ctx || !P) return ctx ? set_err(ctx, PFMP_ERR_ARG, "md_evolve: null") : PFMP_ERR_ARG;
+    int rc = chk_spec(ctx, spec);
+    if (rc) return rc;
+    Ctx X{ctx, spec};
+    rc = md_evolve(X, P, phi, st);
+    if (st) {
+        st->kmults = X.mhalf / 2;
+        st->solver_iters = X.iters;
+    }
+    return rc;
+}
+
+extern "C" int pfmp_trajectory(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const double *P0, const void *const *eta,
+                               double u, double *P_end, pfmp_traj_stats *st)
+{
+    if (!ctx || !P0) return ctx ? set_err(ctx, PFMP_ERR_ARG, "trajectory: null") : PFMP_ERR_ARG;
+    int rc = chk_spec(ctx, spec);
+    if (rc) return rc;
+    if (spec->nterms > 0 && !eta) return set_err(ctx, PFMP_ERR_ARG, "trajectory: null eta");
+    auto t0 = std::chrono::steady_clock::now();
+    Ctx X{ctx, spec};
+    const Geom &g = ctx->g;
+    size_t mb = sizeof(double) * mom_reals(g), gb = sizeof(double) * gauge_reals(g);
+    double *P = (double *)ws_alloc(ctx, mb, 25);
+    double2 *U0 = (double2 *)ws_alloc(ctx, gb, 26);
+    if (!P || !U0) return set_err(ctx, PFMP_ERR_OOM, "trajectory buffers");
+    HIPCHK(ctx, hipMemcpyAsync(P, P0, mb, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(U0, ctx->U, gb, hipMemcpyDeviceToDevice, ctx->stream));
+    std::vector<void *> phi(spec->nterms);
+    for (int j = 0; j < spec->nterms; j++)
+        if (!(phi[j] = pool_get(ctx, j))) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+    for (int j = 0; j < spec->nterms; j++)
+        if ((rc = term_heatbath(X, spec->terms[j], eta[j], phi[j]))) return rc;
+    double p0[PFMP_MAX_TERMS + 3] = {0}, p1[PFMP_MAX_TERMS + 3] = {0};
+    if ((rc = hamiltonian(X, P, phi.data(), p0, spec->exact_start != 0))) return rc;
+    if (!spec->exact_start)
+        for (int j = 0; j < spec->nterms; j++) {
+            p0[3 + j] = dot(X, eta[j], eta[j], rc).real();
+            if (rc) return rc;
+        }
+    pfmp_traj_stats loc{};
+    if ((rc = md_evolve(X, P, phi.data(), &loc))) return rc;
+    if ((rc = hamiltonian(X, P, phi.data(), p1, true))) return rc;
+    double H0 = 0, H1 = 0;
+    for (int k = 0; k < spec->nterms + 3; k++) {
+        H0 += p0[k];
+        H1 += p1[k];
+    }
+    double dH = H1 - H0;
+    int acc = (dH <= 0 || u < std::exp(-dH)) ? 1 : 0;
+    if (P_end) HIPCHK(ctx, hipMemcpyAsync(P_end, P, mb, hipMemcpyDeviceToDevice, ctx->stream));
+    if (!acc) {
+        HIPCHK(ctx, hipMemcpyAsync(ctx->U, U0, gb, hipMemcpyDeviceToDevice, ctx->stream));
+        if ((rc = rebuild_gauge_derived(ctx))) return rc;
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    auto t1 = std::chrono::steady_clock::now();
+    if (st) {
+        *st = loc;
+        st->H0 = H0;
+        st->H1 = H1;
+        st->dH = dH;
+        st->accept = acc;
+        st->kmults = X.mhalf / 2;
+        st->solver_iters = X.iters;
+        st->seconds = std::chrono::duration<double>(t1 - t0).count();
+        std::memcpy(st->parts0, p0, sizeof(p0));
+        std::memcpy(st->parts1, p1, sizeof(p1));
+    }
+    return 0;
+}

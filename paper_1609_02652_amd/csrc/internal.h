@@ -1,0 +1,188 @@
+// internal.h -- shared device helpers and the context of libpfmp (gfx950).
+//
+// Internal layouts (structure of arrays, site index fastest, so that the 64 lanes
+// of a wavefront read consecutive sites):
+//   spinor (one parity)   c[12][Vh]           complex, component k = spin*3 + colour
+//   gauge                 U[2][4][9][Vh]      complex, [parity][mu][row*3+col][eo site]
+//   clover (one parity)   d[2][6][Vh] real + o[2][15][Vh] complex: the two 6x6
+//                         Hermitian chiral blocks (spins {0,1} and {2,3}), diagonal
+//                         and upper triangle (row-major i<j)
+//   momenta / forces      P[2][4][8][Vh]      real, coefficients of T_a
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pfmp.h"
+
+#define PFMP_HD __host__ __device__ __forceinline__
+
+// ------------------------------------------------------------------ complex
+
+template <typename R> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+
+template <typename C> PFMP_HD C mk(decltype(C::x) a, decltype(C::x) b) { C c; c.x = a; c.y = b; return c; }
+template <typename C> PFMP_HD C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
+template <typename C> PFMP_HD C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
+template <typename C> PFMP_HD C cmul(C a, C b) { return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// conj(a) * b
+template <typename C> PFMP_HD C cmulc(C a, C b) { return mk<C>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
+template <typename C> PFMP_HD C cconj(C a) { return mk<C>(a.x, -a.y); }
+template <typename C> PFMP_HD C cscale(C a, decltype(C::x) s) { return mk<C>(a.x * s, a.y * s); }
+template <typename C> PFMP_HD C ctimesi(C a) { return mk<C>(-a.y, a.x); }     // i a
+template <typename C> PFMP_HD C ctimesmi(C a) { return mk<C>(a.y, -a.x); }    // -i a
+template <typename C> PFMP_HD C cneg(C a) { return mk<C>(-a.x, -a.y); }
+// acc += a * b
+template <typename C> PFMP_HD void cfma(C &acc, C a, C b)
+{
+    acc.x += a.x * b.x - a.y * b.y;
+    acc.y += a.x * b.y + a.y * b.x;
+}
+// acc += conj(a) * b
+template <typename C> PFMP_HD void cfmac(C &acc, C a, C b)
+{
+    acc.x += a.x * b.x + a.y * b.y;
+    acc.y += a.x * b.y - a.y * b.x;
+}
+
+// ------------------------------------------------------------------ geometry
+
+struct Geom {
+    int L[4];
+    int Lh0;        // Lx / 2
+    int Vh;
+    int V;
+    int tbc;        // fermion factor across the t boundary
+};
+
+// Coordinates of even-odd site i of parity p: lex = 2i or 2i+1, whichever has parity p.
+__device__ __forceinline__ void eo_coords(const Geom &g, int p, int i, int c[4])
+{
+    int r = i / g.Lh0;
+    int xh = i - r * g.Lh0;
+    int y = r % g.L[1];
+    int r2 = r / g.L[1];
+    int z = r2 % g.L[2];
+    int t = r2 / g.L[2];
+    c[0] = 2 * xh + ((p + y + z + t) & 1);
+    c[1] = y;
+    c[2] = z;
+    c[3] = t;
+}
+
+// Even-odd index of the site with coordinates c (its parity is implied).
+__device__ __forceinline__ int eo_index(const Geom &g, const int c[4])
+{
+    return (c[0] >> 1) + g.Lh0 * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+}
+
+// Even-odd index of the neighbour of site c in direction mu, step +1 / -1, and
+// the fermion boundary factor of that hop.
+__device__ __forceinline__ int eo_neighbour(const Geom &g, const int c[4], int mu, int step, int *fsign)
+{
+    int d[4] = {c[0], c[1], c[2], c[3]};
+    int v = d[mu] + step;
+    int s = 1;
+    if (v == g.L[mu]) { v = 0; if (mu == 3) s = g.tbc; }
+    if (v < 0) { v = g.L[mu] - 1; if (mu == 3) s = g.tbc; }
+    d[mu] = v;
+    *fsign = s;
+    return eo_index(g, d);
+}
+
+// ------------------------------------------------------------------ context
+
+struct OpSlot {
+    bool valid = false;
+    double kappa = 0, csw = 0;
+    double *clov[2] = {nullptr, nullptr};   // FP64: A_ee on [0] (even), A_oo^-1 on [1] (odd)
+    float *clovf[2] = {nullptr, nullptr};   // FP32 copies
+    double logdet_odd = 0;                  // sum_{x odd} ln det A(x)
+    double *Aoo = nullptr;                  // A on odd sites (FP64, for the clover force)
+};
+
+struct SolverWS;
+
+struct pfmp_ctx {
+    Geom g;
+    hipStream_t stream = nullptr;
+    int nblk_red = 0;            // blocks of the reduction kernels
+    double2 *U = nullptr;        // internal FP64 gauge field
+    float2 *Uf = nullptr;        // FP32 copy
+    bool have_gauge = false;
+    OpSlot ops[PFMP_MAX_OPS];
+    double *red = nullptr;       // reduction partials
+    double *red_host = nullptr;  // pinned host mirror of a few scalars
+    double *scal = nullptr;      // device scalars for solvers
+    SolverWS *ws = nullptr;
+    std::vector<double2 *> pool;   // FP64 spinor buffers for the HMC driver, grown on demand
+    std::string err;
+};
+
+// ------------------------------------------------------------------ errors
+
+int set_err(pfmp_ctx *ctx, int code, const std::string &msg);
+
+#define HIPCHK(ctx, call)                                                                            \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return set_err((ctx), PFMP_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+#define LAUNCHCHK(ctx)                                                                                   \
+    do {                                                                                                 \
+        hipError_t e_ = hipGetLastError();                                                               \
+        if (e_ != hipSuccess)                                                                            \
+            return set_err((ctx), PFMP_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------ launch sizes
+
+constexpr int kBlock = 128;      // threads per block of the site kernels
+constexpr int kRedBlock = 256;   // threads per block of reductions
+inline int nblocks(long n, int b) { return (int)((n + b - 1) / b); }
+
+// sizes of internal fields
+inline long spinor_reals(const Geom &g) { return 24L * g.Vh; }
+inline long clover_reals(const Geom &g) { return 72L * g.Vh; }
+inline long gauge_reals(const Geom &g) { return 2L * 4 * 18 * g.Vh; }
+inline long mom_reals(const Geom &g) { return 2L * 4 * 8 * g.Vh; }
+
+// ------------------------------------------------------------------ internal API
+
+// operator stages (dslash.hip)
+int op_apply_M(pfmp_ctx *ctx, int op, int dagger, const double2 *in, double2 *out, double2 *tmp_odd,
+               double *norm_partials);
+int op_apply_K(pfmp_ctx *ctx, int op, const double2 *in, double2 *out, double2 *tmp_even, double2 *tmp_odd,
+               double *norm_partials);
+int op_apply_M_f32(pfmp_ctx *ctx, int op, int dagger, const float2 *in, float2 *out, float2 *tmp_odd,
+                   double *norm_partials);
+int op_apply_K_f32(pfmp_ctx *ctx, int op, const float2 *in, float2 *out, float2 *tmp_even, float2 *tmp_odd,
+                   double *norm_partials);
+template <typename C, typename R>
+int launch_clovinv(pfmp_ctx *ctx, int pout, const C *in, const C *U, const R *cl, C *out, R gin, R gout, bool clov,
+                   const double *stop);
+template <typename C, typename R>
+int launch_xpay(pfmp_ctx *ctx, int pout, const C *x, const C *t, const C *U, const R *cl, R a, C *out, R gs,
+                bool clov, double *partials, const double *stop);
+int rebuild_gauge_derived(pfmp_ctx *ctx);
+int red_finish_dev(pfmp_ctx *ctx, const double *partials, int nparts, int nvals, double *dev_out);
+// clover (clover.hip)
+int clover_build(pfmp_ctx *ctx, int op);
+// reductions (blas.hip)
+int red_finish(pfmp_ctx *ctx, const double *partials, int nparts, int nvals, double *host_out);
+int launch_dot(pfmp_ctx *ctx, const double2 *a, const double2 *b, long n, double *partials);
+int launch_norm2(pfmp_ctx *ctx, const double2 *a, long n, double *partials);
+void *ws_alloc(pfmp_ctx *ctx, size_t bytes, int slot);
+double2 *pool_get(pfmp_ctx *ctx, int idx);
+// polynomial (poly.hip)
+int poly_factor(pfmp_ctx *ctx, int op, const double2 *src, double2 z, double2 *dst, double2 *te, double2 *to);
+int scale_spinor(pfmp_ctx *ctx, double2 a, const double2 *x, double2 *y);
+// mixed precision (mixed.hip)
+int cg_solve_mixed(pfmp_ctx *ctx, int op, const void *b, void *x, const pfmp_solver_params *p,
+                   pfmp_solver_stats *st);

@@ -1,0 +1,248 @@
+// mixed.hip -- mixed-precision CG on Khat: FP32 inner iterations (FP32 links,
+// clover and spinors; FP64 reductions and scalars) with FP64 reliable updates.
+//
+// The inner CG runs on (xs, rs, ps) in FP32.  When its residual has dropped by
+// the factor delta since the last update, or reached the target, the device
+// flags a reliable update: the host adds xs into the FP64 solution, recomputes the
+// FP64 true residual r = b - Khat x, restarts rs from it and keeps the search
+// direction ps.  The solve ends only when the FP64 true residual meets tol.
+#include <chrono>
+#include <cmath>
+
+#include "hop.h"
+
+namespace {
+
+enum { M_RR = 0, M_THR, M_DTHR, M_PAP, M_ALPHA, M_BETA, M_ITER, M_DONE, M_MAXIT };
+constexpr int kMixBase = 4096;    // device scalar slots of this solver (ctx->scal + kMixBase)
+
+__device__ __forceinline__ double block_total_m(const double *__restrict__ partials, int nparts)
+{
+    __shared__ double sh[kRedBlock / 64];
+    double s = 0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += partials[k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0;
+    for (int k = 0; k < kRedBlock / 64; k++) t += sh[k];
+    return t;
+}
+
+// (re)start: rr = |r|^2 of the FP64 residual (partials), thresholds
+__global__ __launch_bounds__(kRedBlock) void k_m_restart(const double *__restrict__ partials, int nparts,
+                                                         double tol2bb, double delta2, int maxiter, int first,
+                                                         double *__restrict__ st)
+{
+    double rr = block_total_m(partials, nparts);
+    if (threadIdx.x == 0) {
+        st[M_RR] = rr;
+        st[M_THR] = tol2bb;
+        st[M_DTHR] = delta2 * rr;
+        if (first) st[M_ITER] = 0;
+        st[M_MAXIT] = maxiter;
+        st[M_DONE] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_m_alpha(const double *__restrict__ partials, int nparts,
+                                                       double *__restrict__ st)
+{
+    if (st[M_DONE] != 0) return;
+    double pap = block_total_m(partials, nparts);
+    if (threadIdx.x == 0) {
+        st[M_PAP] = pap;
+        st[M_ALPHA] = st[M_RR] / pap;
+    }
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_m_beta(const double *__restrict__ partials, int nparts,
+                                                      double *__restrict__ st)
+{
+    if (st[M_DONE] != 0) return;
+    double rr = block_total_m(partials, nparts);
+    if (threadIdx.x == 0) {
+        st[M_BETA] = rr / st[M_RR];
+        st[M_RR] = rr;
+        st[M_ITER] += 1;
+        // 1: inner residual at the target; 3: dropped by delta; 2: iteration limit
+        st[M_DONE] = rr <= st[M_THR] ? 1 : (rr <= st[M_DTHR] ? 3 : (st[M_ITER] >= st[M_MAXIT] ? 2 : 0));
+    }
+}
+
+// FP32 Khat p from t = Mhat p and T' (as in the FP64 solver), fused with
+// x += alpha p, r -= alpha Khat p and FP64 |r|^2 partials
+template <int CLOV>
+__global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const float2 *__restrict__ t, const float2 *__restrict__ T,
+                                                   const float2 *__restrict__ U, const float *__restrict__ cl,
+                                                   float a, const float2 *__restrict__ p, float2 *__restrict__ x,
+                                                   float2 *__restrict__ r, const double *__restrict__ st,
+                                                   double *__restrict__ partials)
+{
+    if (st[M_DONE] != 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double nrm = 0;
+    if (i < g.Vh) {
+        float2 acc[12], tv[12], at[12];
+        hop_all<float2>(g, 0, i, T, U, 1.f, acc);
+        load_spinor(t, g.Vh, i, -1.f, tv);
+        if (CLOV) clover_apply<float, float2>(cl, g.Vh, i, tv, at);
+        const float alpha = (float)st[M_ALPHA];
+        const long Vh = g.Vh;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            float2 base = CLOV ? at[k] : tv[k];
+            float2 kp = make_float2(base.x + a * acc[k].x, base.y + a * acc[k].y);
+            if (k >= 6) kp = cneg(kp);
+            float2 pv = p[k * Vh + i], xv = x[k * Vh + i], rv = r[k * Vh + i];
+            xv.x += alpha * pv.x; xv.y += alpha * pv.y;
+            rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
+            x[k * Vh + i] = xv;
+            r[k * Vh + i] = rv;
+            nrm += (double)rv.x * rv.x + (double)rv.y * rv.y;
+        }
+    }
+    block_sum_store<float2>(nrm, partials);
+}
+
+__global__ void k_m_update_p(long n, const float2 *__restrict__ r, float2 *__restrict__ p,
+                             const double *__restrict__ st)
+{
+    if (st[M_DONE] != 0) return;
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    float b = (float)st[M_BETA];
+    float2 rv = r[t], pv = p[t];
+    p[t] = make_float2(rv.x + b * pv.x, rv.y + b * pv.y);
+}
+
+// x += xs (FP64 += FP32), xs = 0
+__global__ void k_m_accum(long n, float2 *__restrict__ xs, double2 *__restrict__ x)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    float2 v = xs[t];
+    double2 w = x[t];
+    x[t] = make_double2(w.x + (double)v.x, w.y + (double)v.y);
+    xs[t] = make_float2(0.f, 0.f);
+}
+
+// r = b - Kx (FP64); rs = (float) r; optionally ps = rs; |r|^2 partials (grid-stride)
+__global__ __launch_bounds__(kRedBlock) void k_m_residual(long n, const double2 *__restrict__ b,
+                                                          const double2 *__restrict__ Kx, float2 *__restrict__ rs,
+                                                          float2 *__restrict__ ps, int set_p,
+                                                          double *__restrict__ partials)
+{
+    double s = 0;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+        double2 r = csub(b[t], Kx[t]);
+        s += r.x * r.x + r.y * r.y;
+        float2 f = make_float2((float)r.x, (float)r.y);
+        rs[t] = f;
+        if (set_p) ps[t] = f;
+    }
+    __shared__ double sh[kRedBlock / 64];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0;
+        for (int k = 0; k < kRedBlock / 64; k++) v += sh[k];
+        partials[blockIdx.x] = v;
+    }
+}
+
+}  // namespace
+
+int cg_solve_mixed(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfmp_solver_params *prm,
+                   pfmp_solver_stats *st)
+{
+    if (prm->prec != PFMP_F32) return set_err(ctx, PFMP_ERR_ARG, "cg_solve: unsupported precision");
+    auto t0 = std::chrono::steady_clock::now();
+    const Geom &g = ctx->g;
+    OpSlot &s = ctx->ops[op];
+    const long n = 12L * g.Vh;
+    const size_t vb = sizeof(double) * spinor_reals(g), fb = vb / 2;
+    const int nb = nblocks(g.Vh, kBlock);
+    double2 *Kx = (double2 *)ws_alloc(ctx, vb, 8), *te = (double2 *)ws_alloc(ctx, vb, 6),
+            *to = (double2 *)ws_alloc(ctx, vb, 7);
+    float2 *rs = (float2 *)ws_alloc(ctx, fb, 27), *ps = (float2 *)ws_alloc(ctx, fb, 28),
+           *xs = (float2 *)ws_alloc(ctx, fb, 29), *ts = (float2 *)ws_alloc(ctx, fb, 30),
+           *Ts = (float2 *)ws_alloc(ctx, fb, 31);
+    double *part_a = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64), 9);
+    double *part_b = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64), 10);
+    if (!Kx || !te || !to || !rs || !ps || !xs || !ts || !Ts || !part_a || !part_b)
+        return set_err(ctx, PFMP_ERR_OOM, "mixed solver workspace");
+    const double2 *b = (const double2 *)b_;
+    double2 *x = (double2 *)x_;
+    double *sc = ctx->scal + kMixBase;
+    const double delta = prm->delta > 0 ? prm->delta : 0.1;
+    const bool cl = s.csw != 0;
+    const float mk2 = (float)(-s.kappa * s.kappa);
+    int rc;
+    HIPCHK(ctx, hipMemsetAsync(x, 0, vb, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(xs, 0, fb, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(Kx, 0, vb, ctx->stream));
+    double bb;
+    if ((rc = launch_norm2(ctx, b, n, ctx->red))) return rc;
+    if ((rc = red_finish(ctx, ctx->red, ctx->nblk_red, 1, &bb))) return rc;
+    const double tol2bb = prm->tol * prm->tol * bb;
+    // r = b, rs = ps = (float) b
+    hipLaunchKernelGGL(k_m_residual, dim3(ctx->nblk_red), dim3(kRedBlock), 0, ctx->stream, n, b, Kx, rs, ps, 1,
+                       ctx->red);
+    hipLaunchKernelGGL(k_m_restart, dim3(1), dim3(kRedBlock), 0, ctx->stream, ctx->red, ctx->nblk_red, tol2bb,
+                       delta * delta, prm->maxiter, 1, sc);
+    LAUNCHCHK(ctx);
+    int chunk = prm->check_every > 0 ? prm->check_every : 25;
+    int updates = 0, kmults = 0;
+    double h[16], res = 0;
+    for (;;) {
+        for (int k = 0; k < chunk; k++) {
+            if ((rc = launch_clovinv<float2, float>(ctx, 1, ps, ctx->Uf, s.clovf[1], Ts, 1.f, 1.f, cl, sc + M_DONE)))
+                return rc;
+            if ((rc = launch_xpay<float2, float>(ctx, 0, ps, Ts, ctx->Uf, s.clovf[0], mk2, ts, 1.f, cl, part_a,
+                                                  sc + M_DONE)))
+                return rc;
+            hipLaunchKernelGGL(k_m_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_a, nb, sc);
+            if ((rc = launch_clovinv<float2, float>(ctx, 1, ts, ctx->Uf, s.clovf[1], Ts, -1.f, 1.f, cl, sc + M_DONE)))
+                return rc;
+            if (cl)
+                hipLaunchKernelGGL((k_m_hop4<1>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,
+                                   s.clovf[0], mk2, ps, xs, rs, sc, part_b);
+            else
+                hipLaunchKernelGGL((k_m_hop4<0>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,
+                                   s.clovf[0], mk2, ps, xs, rs, sc, part_b);
+            hipLaunchKernelGGL(k_m_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, sc);
+            hipLaunchKernelGGL(k_m_update_p, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, rs, ps, sc);
+            LAUNCHCHK(ctx);
+        }
+        HIPCHK(ctx, hipMemcpyAsync(ctx->red_host, sc, sizeof(double) * 16, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        for (int k = 0; k < 16; k++) h[k] = ctx->red_host[k];
+        if (h[M_DONE] == 0) continue;
+        // reliable update in FP64
+        hipLaunchKernelGGL(k_m_accum, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, xs, x);
+        if ((rc = op_apply_K(ctx, op, x, Kx, te, to, nullptr))) return rc;
+        kmults++;
+        updates++;
+        hipLaunchKernelGGL(k_m_residual, dim3(ctx->nblk_red), dim3(kRedBlock), 0, ctx->stream, n, b, Kx, rs, ps, 0,
+                           ctx->red);
+        double rr;
+        if ((rc = red_finish(ctx, ctx->red, ctx->nblk_red, 1, &rr))) return rc;
+        res = bb > 0 ? std::sqrt(rr / bb) : 0;
+        if (rr <= tol2bb || h[M_DONE] == 2) break;
+        hipLaunchKernelGGL(k_m_restart, dim3(1), dim3(kRedBlock), 0, ctx->stream, ctx->red, ctx->nblk_red, tol2bb,
+                           delta * delta, prm->maxiter, 0, sc);
+        LAUNCHCHK(ctx);
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    if (st) {
+        st->iters = (int)h[M_ITER];
+        st->reliable_updates = updates;
+        st->true_res = res;
+        st->seconds = std::chrono::duration<double>(t1 - t0).count();
+        st->kmults = (long long)h[M_ITER] + kmults;
+    }
+    if (!(res <= prm->tol)) return set_err(ctx, PFMP_ERR_NOCONV, "cg_solve (mixed): maxiter reached");
+    return 0;
+}

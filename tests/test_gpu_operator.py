@@ -1,0 +1,159 @@
+"""GPU parity of the operator layer against the FP64 oracle (through the C-ABI).
+
+Index maps must match bit for bit; FP64 operator applications to 1e-12 relative
+(2-norm) on seeded synthetic fields.  Lattices are chosen to span several
+128-site blocks and a ragged last block.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_02652_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(6, 4, 4, 8), (6, 6, 4, 6), (8, 8, 8, 8)]
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+@pytest.fixture(scope="module", params=DIMS, ids=lambda d: "x".join(map(str, d)))
+def setup(request):
+    from paper_1609_02652_amd.pfmp import Lattice
+    dims = request.param
+    print("case", dims, flush=True)
+    U = synth.random_gauge(dims, seed=3)
+    lat = Lattice(dims)
+    lat.set_gauge(U)
+    ops = {0: (0.1250, 1.30), 1: (0.1150, 0.0)}
+    for k, (kap, csw) in ops.items():
+        lat.set_operator(k, kap, csw)
+    oracle_ops = {k: oracle.Operator(dims, U, kap, csw) for k, (kap, csw) in ops.items()}
+    yield dims, U, lat, oracle_ops
+    lat.close()
+
+
+def test_index_maps_bit_exact(setup):
+    dims, U, lat, _ = setup
+    lexeo, nbr, sign = [t.cpu().numpy() for t in lat.index_maps()]
+    ol, on, os_ = oracle.index_maps(dims, tbc=-1)
+    assert np.array_equal(lexeo, ol)
+    assert np.array_equal(nbr, on)
+    assert np.array_equal(sign, os_)
+
+
+def test_pack_roundtrip(setup):
+    dims, U, lat, _ = setup
+    psi = synth.gaussian_spinor(lat.Vh, 5)
+    f = lat.pack_spinor(psi)
+    assert np.array_equal(lat.spinor_numpy(f), psi)
+    Ug = lat.get_gauge().cpu().numpy()
+    assert np.array_equal(Ug, U)
+
+
+@pytest.mark.parametrize("parity,dagger", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_hop(setup, parity, dagger):
+    dims, U, lat, ops = setup
+    psi = synth.gaussian_spinor(lat.Vh, 7)
+    got = lat.spinor_numpy(lat.apply_hop(parity, lat.pack_spinor(psi), dagger=bool(dagger)))
+    want = ops[0].hop_eo(parity, psi, adjoint=bool(dagger))
+    assert rel(got, want) < 1e-13
+
+
+def test_clover(setup):
+    dims, U, lat, ops = setup
+    psi = synth.gaussian_spinor(lat.Vh, 8)
+    f = lat.pack_spinor(psi)
+    got_e = lat.spinor_numpy(lat.apply_clover(0, 0, False, f))
+    got_o = lat.spinor_numpy(lat.apply_clover(0, 1, True, f))
+    assert rel(got_e, ops[0].clover(0, psi)) < 1e-13
+    assert rel(got_o, ops[0].clover(1, psi, inverse=True)) < 1e-12
+    want = ops[0].logdet_action()
+    assert abs(lat.logdet_action(0) - want) < 1e-12 * abs(want)
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_apply_M_and_K(setup, op):
+    dims, U, lat, ops = setup
+    psi = synth.gaussian_spinor(lat.Vh, 9)
+    f = lat.pack_spinor(psi)
+    assert rel(lat.spinor_numpy(lat.apply_M(op, f)), ops[op].M(psi)) < 1e-12
+    assert rel(lat.spinor_numpy(lat.apply_M(op, f, dagger=True)), ops[op].M(psi, dagger=True)) < 1e-12
+    assert rel(lat.spinor_numpy(lat.apply_MdagM(op, f)), ops[op].K(psi)) < 1e-12
+
+
+def test_apply_M_fp32_error(setup):
+    """FP32 operator: error against FP64 reported at the FP32 rounding level."""
+    from paper_1609_02652_amd.pfmp import F32
+    dims, U, lat, ops = setup
+    psi = synth.gaussian_spinor(lat.Vh, 10)
+    f = lat.pack_spinor(psi, prec=F32)
+    got = lat.spinor_numpy(lat.apply_MdagM(0, f, prec=F32), prec=F32)
+    e = rel(got, ops[0].K(psi))
+    print("fp32 Khat rel err", e)
+    assert e < 2e-6
+
+
+def test_blas(setup):
+    dims, U, lat, ops = setup
+    a = synth.gaussian_spinor(lat.Vh, 11)
+    b = synth.gaussian_spinor(lat.Vh, 12)
+    fa, fb = lat.pack_spinor(a), lat.pack_spinor(b)
+    d = lat.dot(fa, fb)
+    assert abs(d - np.vdot(a, b)) < 1e-12 * abs(np.vdot(a, b))
+    lat.axpby(0.5 - 0.25j, fa, 2.0 + 1j, fb)
+    assert rel(lat.spinor_numpy(fb), (0.5 - 0.25j) * a + (2 + 1j) * b) < 1e-15
+
+
+def test_cg(setup):
+    dims, U, lat, ops = setup
+    b = synth.gaussian_spinor(lat.Vh, 13)
+    x, st = lat.cg_solve(0, lat.pack_spinor(b), tol=1e-12, check_every=7)
+    assert st["true_res"] <= 1.1e-12
+    xo, sto = ops[0].cg(b, tol=1e-12)
+    # same Krylov recurrences in FP64: iteration counts agree up to rounding
+    assert abs(st["iters"] - sto["iters"]) <= 2
+    xg = lat.spinor_numpy(x)
+    assert rel(xg, xo) < 1e-9
+    # independent check of the returned x with the oracle's operator
+    assert rel(ops[0].K(xg), b) < 1.1e-12
+
+
+def test_cg_mixed_fp32(setup):
+    """FP32 inner CG with FP64 reliable updates reaches the FP64 true residual."""
+    from paper_1609_02652_amd.pfmp import F32
+    dims, U, lat, ops = setup
+    b = synth.gaussian_spinor(lat.Vh, 16)
+    x, st = lat.cg_solve(0, lat.pack_spinor(b), tol=1e-10, prec=F32, check_every=5)
+    assert st["true_res"] <= 1e-10 and st["reliable_updates"] >= 1
+    xg = lat.spinor_numpy(x)
+    assert rel(ops[0].K(xg), b) <= 1.05e-10
+    xo, _ = ops[0].cg(b, tol=1e-12)
+    print("mixed: iters %d, updates %d, |x - x64|/|x| = %.2e" % (st["iters"], st["reliable_updates"], rel(xg, xo)))
+
+
+def test_cg_maxiter_reports(setup):
+    from paper_1609_02652_amd.pfmp import PfmpError
+    dims, U, lat, ops = setup
+    b = lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 14))
+    with pytest.raises(PfmpError) as e:
+        lat.cg_solve(0, b, tol=1e-14, maxiter=3, check_every=2)
+    assert e.value.code == -3
+    x, st = lat.cg_solve(0, b, tol=1e-14, maxiter=3, check_every=2, check=False)
+    assert st["iters"] == 3
+
+
+def test_multishift(setup):
+    from oracle import chebyshev
+    dims, U, lat, ops = setup
+    b = synth.gaussian_spinor(lat.Vh, 15)
+    zs = chebyshev.roots(6, 1.2, 0.9) + [0j]
+    xs, st = lat.cg_multishift(1, zs, lat.pack_spinor(b), tol=1e-11, check_every=5)
+    assert max(st["shift_res"]) < 1e-10
+    for z, x in zip(zs, xs):
+        xg = lat.spinor_numpy(x)
+        # residual of the returned solution with the oracle's operator
+        r = b - (ops[1].K(xg) - z * xg)
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-10
