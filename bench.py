@@ -85,6 +85,33 @@ def hop_roofline(dims, U, reps=200):
     return {"t_hop": t_plain, "bytes_hop": bytes_plain, "t_M": t_m, "bytes_M": bytes_m, "Vh": lat.Vh}
 
 
+def roofline_only(reps):
+    """Only the hopping kernels (16^3x32 and 32^3x64) and a plain copy of known size,
+    for hardware-counter runs: FETCH_SIZE / WRITE_SIZE of the copy calibrate the
+    counters of the hopping kernel."""
+    import torch
+    from paper_1609_02652_amd import synth
+    out = {}
+    for dims in (DIMS, (32, 32, 32, 64)):
+        r = hop_roofline(dims, synth.random_gauge(dims, seed=5), reps=reps)
+        out["x".join(map(str, dims))] = {"hop_us": round(r["t_hop"] * 1e6, 2),
+                                         "hop_GBps": round(r["bytes_hop"] / r["t_hop"] / 1e9, 1),
+                                         "hop_bytes": r["bytes_hop"], "Mhat_us": round(r["t_M"] * 1e6, 2)}
+    n = 256 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    out["copy_256MiB"] = {"us": round(t * 1e6, 2), "GBps_read_plus_write": round(2 * n * 8 / t / 1e9, 1)}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(U, kmults_per_traj, budget_s=15.0):
     """The oracle (plain C, FP64) on the host cores: Khat multiplications on the
     same 16^3 x 32 fields, timed for about budget_s seconds and scaled by the
@@ -118,10 +145,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sources", type=int, default=4)
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="time only the hopping kernels and a plain copy (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.roofline_only:
+        roofline_only(max(args.steps, 10))
+        return
     import torch
     from paper_1609_02652_amd import synth
     log("bench: building inputs", DIMS)

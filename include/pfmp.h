@@ -161,6 +161,42 @@ int pfmp_cg_solve(pfmp_ctx *ctx, int op, const void *b, void *x, const pfmp_solv
 int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const double *z, const void *b,
                        void *const *x, const pfmp_solver_params *p, pfmp_solver_stats *st);
 
+/* ---- multi-RHS batches (several pseudofermion solves at one gauge field) ------ */
+
+/* out_r = Khat_{ops[r]} in_r for nrhs <= 8 right-hand sides, each with its own
+ * operator slot, in 4 launches: one thread per (site, rhs) so that the links
+ * each site reads are shared by all right-hand sides.  FP64. */
+int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *const *in, void *const *out);
+/* CG for Khat_{ops[r]} x_r = b_r, r < nrhs <= 8, all iterated in the same launches;
+ * a converged right-hand side stops.  st: nrhs records.  FP64. */
+int pfmp_cg_solve_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *const *b, void *const *x,
+                        const pfmp_solver_params *p, pfmp_solver_stats *st);
+
+/* ---- learned preconditioner and flexible CG ------------------------------------ */
+
+/* Gauge-covariant parallel-transport convolution network N (2 layers, 4 -> 12 -> 4
+ * complex colour-vector channels, norm gate h/(1+|h|^2), skip term W0): weights W are
+ * 784 complex numbers (1568 doubles, host) laid out [W1 8x12x4 | W2 8x4x12 | W0 4x4];
+ * FP32 weights and arithmetic.  out = N(r) = |r| z(r/|r|) (FP64 internal spinors). */
+int pfmp_ptnet_apply(pfmp_ctx *ctx, const double *W, const void *r, void *out);
+/* Loss sum_p |z(r_p/|r_p|) - e_p/|r_p||^2 / |e_p/|r_p||^2 over npairs (r_p, e_p) and the
+ * gradient matrices A (1568 doubles, host, same layout as W) with dLoss = 2 Re sum A dW. */
+int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int npairs, const void *const *r, const void *const *e,
+                    double *loss, double *A);
+/* Adam (beta 0.9, 0.999) on the real and imaginary parts of W for `steps` steps over all
+ * npairs pairs (full batch); W (1568 doubles, host) updated in place; losses[steps] optional. */
+int pfmp_ptnet_train(pfmp_ctx *ctx, double *W, int npairs, const void *const *r, const void *const *e, int steps,
+                     double lr, double *losses);
+/* Flexible CG on Khat (Notay 2000 with one direction kept, Polak-Ribiere beta) with N as
+ * preconditioner; W = NULL uses the identity (then it is CG).  Stops on the FP64 true
+ * residual |b - Khat x| <= tol |b|, like pfmp_cg_solve. */
+int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void *b, void *x, const pfmp_solver_params *p,
+                   pfmp_solver_stats *st);
+/* CG on Khat that copies (x_k, r_k) at the iterations snap_iters (ascending) into the
+ * caller's buffers; training pairs are then (r_k, x - x_k).  *ntaken = snapshots made. */
+int pfmp_cg_harvest(pfmp_ctx *ctx, int op, const void *b, void *x, double tol, int maxiter, int nsnap,
+                    const int *snap_iters, void *const *snap_x, void *const *snap_r, int *ntaken);
+
 /* ---- BLAS-1 on internal FP64 spinors (FP64 reductions, deterministic order) -- */
 
 /* *out = <a, b> (complex, 2 doubles on the host). */

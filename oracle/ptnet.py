@@ -1,0 +1,173 @@
+"""Gauge-covariant parallel-transport convolution network (the learned
+preconditioner of the flexible CG), plain numpy FP64.
+
+TEST INFRASTRUCTURE ONLY (part of the oracle).
+
+The paper does not define this network; the reading used here (a 2-layer
+parallel-transport convolution with 12 complex colour-vector channels):
+  input   r on even sites, 4 channels (the spin components, colour 3-vectors),
+          normalised rhat = r / |r|
+  layer 1 (even -> odd)  h_c(y) = sum_{d} sum_{c'} W1[d, c, c'] T_d(y) rhat_{c'}(y + d)
+  gate                   g_c(y) = h_c(y) / (1 + |h_c(y)|^2)
+  layer 2 (odd -> even)  z_c(x) = sum_{d} sum_{c'} W2[d, c, c'] T_d(x) g_{c'}(x + d)
+                                  + sum_{c'} W0[c, c'] rhat_{c'}(x)
+  output  N(r) = |r| z
+with d over the 8 directions (d = 2 mu: +mu, d = 2 mu + 1: -mu) and T_d the
+parallel transporter of the hop (U_mu(y) for +mu, U_mu(y - mu)^dag for -mu) times the
+fermion boundary factor.  Training pairs (r, e) with K e = r; the loss of a pair is
+|z(rhat) - e/|r||^2 / |e/|r||^2.
+Gradients follow the chain rule written out below; the tests pin them by finite
+differences.
+"""
+import numpy as np
+
+from . import index_maps
+
+NIN, NHID = 4, 12
+
+
+def _transport_tables(dims, U, tbc=-1):
+    """For each parity p, eo site i and direction d: neighbour eo index and the
+    3x3 transporter (with the fermion boundary factor)."""
+    lexeo, nbr, sign = index_maps(dims, tbc)
+    V = int(np.prod(dims))
+    L = list(dims)
+
+    def lex_shift(x, mu, step):
+        c = []
+        t = x
+        for Lm in L:
+            c.append(t % Lm)
+            t //= Lm
+        c[mu] = (c[mu] + step) % L[mu]
+        return c[0] + L[0] * (c[1] + L[1] * (c[2] + L[2] * c[3]))
+
+    T = np.zeros((2, V // 2, 8, 3, 3), np.complex128)
+    for p in range(2):
+        for i, x in enumerate(lexeo[p]):
+            for mu in range(4):
+                T[p, i, 2 * mu] = U[x, mu] * sign[p, i, 2 * mu]
+                xm = lex_shift(x, mu, -1)
+                T[p, i, 2 * mu + 1] = U[xm, mu].conj().T * sign[p, i, 2 * mu + 1]
+    return nbr, T
+
+
+class PTNet:
+    def __init__(self, dims, U, tbc=-1):
+        self.dims = dims
+        self.nbr, self.T = _transport_tables(dims, np.asarray(U), tbc)
+
+    # ------------------------------------------------------------ layers
+    def _conv(self, p_out, f, W):
+        """sum_d sum_c' W[d, c, c'] T_d(y) f_{c'}(y + d) on sites of parity p_out."""
+        Vh = self.nbr.shape[1]
+        out = np.zeros((Vh, W.shape[1], 3), np.complex128)
+        for d in range(8):
+            fn = f[self.nbr[p_out, :, d]]                           # [Vh, cin, 3]
+            tf = np.einsum("iab,icb->ica", self.T[p_out, :, d], fn)  # transported
+            out += np.einsum("kc,ica->ika", W[d], tf)
+        return out
+
+    def _conv_adjoint(self, p_in, G, W):
+        """Adjoint of _conv from parity p_in to the other parity:
+        A[y] = sum over (x, d) with x + d = y of W[d]^dag T_d(x)^dag G(x)."""
+        Vh = self.nbr.shape[1]
+        out = np.zeros((Vh, W.shape[2], 3), np.complex128)
+        for d in range(8):
+            tg = np.einsum("iba,ikb->ika", self.T[p_in, :, d].conj(), G)     # T^dag G
+            mixed = np.einsum("kc,ika->ica", W[d].conj(), tg)               # W^dag
+            np.add.at(out, self.nbr[p_in, :, d], mixed)
+        return out
+
+    def forward(self, r, W1, W2, W0):
+        nr = np.linalg.norm(r)
+        rh = r / nr
+        h = self._conv(1, rh, W1)
+        q = np.sum(np.abs(h) ** 2, axis=2, keepdims=True)
+        g = h / (1 + q)
+        z = self._conv(0, g, W2) + np.einsum("kc,ica->ika", W0, rh)
+        return nr * z, dict(rh=rh, h=h, q=q, g=g, z=z, nr=nr)
+
+    def apply(self, r, W1, W2, W0):
+        return self.forward(r, W1, W2, W0)[0]
+
+    # ------------------------------------------------------------ loss and gradients
+    def loss(self, pairs, W1, W2, W0):
+        tot = 0.0
+        for r, e in pairs:
+            _, c = self.forward(r, W1, W2, W0)
+            eh = e / c["nr"]
+            tot += np.sum(np.abs(c["z"] - eh) ** 2) / np.sum(np.abs(eh) ** 2)
+        return tot
+
+    def grads(self, pairs, W1, W2, W0):
+        """Loss and A-matrices with dL = 2 Re sum A * dW (so dL/dRe W = 2 Re A,
+        dL/dIm W = -2 Im A)."""
+        A1 = np.zeros_like(W1)
+        A2 = np.zeros_like(W2)
+        A0 = np.zeros_like(W0)
+        tot = 0.0
+        for r, e in pairs:
+            _, c = self.forward(r, W1, W2, W0)
+            eh = e / c["nr"]
+            ne = np.sum(np.abs(eh) ** 2)
+            diff = c["z"] - eh
+            tot += np.sum(np.abs(diff) ** 2) / ne
+            Gz = diff / ne                                    # dL = 2 Re <Gz, dz>
+            rh, h, q, g = c["rh"], c["h"], c["q"], c["g"]
+            # W0 and W2
+            A0 += np.einsum("ika,ica->kc", Gz.conj(), rh)
+            for d in range(8):
+                gn = g[self.nbr[0, :, d]]
+                tg = np.einsum("iab,icb->ica", self.T[0, :, d], gn)
+                A2[d] += np.einsum("ika,ica->kc", Gz.conj(), tg)
+            # back to g, then through the gate to h
+            Gg = self._conv_adjoint(0, Gz, W2)
+            s = 1 / (1 + q)
+            ds = -1 / (1 + q) ** 2
+            w = np.sum(Gg.conj() * h, axis=2, keepdims=True)    # <Gg, h> per channel
+            Gh = s * Gg + 2 * ds * w.real * h
+            for d in range(8):
+                rn = rh[self.nbr[1, :, d]]
+                tr = np.einsum("iab,icb->ica", self.T[1, :, d], rn)
+                A1[d] += np.einsum("ika,ica->kc", Gh.conj(), tr)
+        return tot, A1, A2, A0
+
+
+def init_weights(seed, scale=0.1):
+    """Small random initial weights (complex), plus W0 = identity."""
+    rng = np.random.default_rng(seed)
+    c = lambda *s: (rng.standard_normal(s) + 1j * rng.standard_normal(s)) * scale
+    return c(8, NHID, NIN), c(8, NIN, NHID), np.eye(NIN, dtype=np.complex128)
+
+
+def flexible_cg(apply_K, precond, b, tol, maxiter=10000):
+    """Flexible CG (Notay 2000, one direction kept): Polak-Ribiere beta
+    <z_{k+1}, r_{k+1} - r_k> / <z_k, r_k>; with precond = identity this is CG.
+    Where the preconditioned residual is not a descent direction (<r, z> <= 0) the
+    step falls back to z = r and restarts the direction (plain CG step)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = precond(r)
+    rz = np.vdot(r, z).real
+    if not rz > 0:
+        z, rz = r.copy(), np.vdot(r, r).real
+    p = z.copy()
+    bb = np.linalg.norm(b)
+    k = 0
+    while np.linalg.norm(r) > tol * bb and k < maxiter:
+        q = apply_K(p)
+        alpha = rz / np.vdot(p, q).real
+        x += alpha * p
+        rn = r - alpha * q
+        zn = precond(rn)
+        rzn = np.vdot(rn, zn).real
+        if rzn > 0:
+            beta = np.vdot(zn, rn - r).real / rz
+        else:
+            zn, rzn, beta = rn.copy(), np.vdot(rn, rn).real, 0.0
+        rz = rzn
+        p = zn + beta * p
+        r = rn
+        k += 1
+    return x, k

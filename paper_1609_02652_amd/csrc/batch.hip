@@ -1,0 +1,365 @@
+// batch.hip -- multi-RHS operator and CG: k right-hand sides, each with its own
+// operator slot (kappa, clover), in one launch per stage.
+//
+// One thread per (site, rhs) with the rhs index fastest inside a wavefront: the k
+// lanes of a site read the same link address, so every link is fetched from HBM
+// once per k right-hand sides (the cache serves the other lanes) while each
+// thread keeps the register footprint of the single-RHS kernel.  Per-rhs CG
+// scalars and convergence flags live on the device; a converged rhs stops
+// touching memory.  Reductions: one FP64 partial per (block, rhs), wave
+// shuffles with stride k, fixed order.
+#include <chrono>
+#include <cmath>
+
+#include "hop.h"
+
+namespace {
+
+constexpr int kMaxRhs = 8;
+enum { B_RR = 0, B_THR, B_PAP, B_ALPHA, B_BETA, B_ITER, B_DONE, B_MAXIT, B_NSLOT = 8 };
+constexpr int kBatchBase = 5120;   // per-rhs scalar records at ctx->scal + kBatchBase + 8 r
+
+struct Batch {
+    int k;                          // lanes per site (power of 2 >= n)
+    int n;                          // right-hand sides
+    const double *clo[kMaxRhs];     // A_oo^-1 of each rhs's operator
+    const double *cle[kMaxRhs];     // A_ee
+    double a[kMaxRhs];              // -kappa^2
+    int clov[kMaxRhs];
+};
+
+struct Vecs {
+    const double2 *in[kMaxRhs];
+    double2 *out[kMaxRhs];
+};
+
+__device__ __forceinline__ bool item(const Batch &b, int nsites, int *site, int *r)
+{
+    int t = xcd_site(nsites * b.k);
+    if (t < 0) return false;
+    *site = t / b.k;
+    *r = t - *site * b.k;
+    return *r < b.n;
+}
+
+// sum over the lanes of equal rhs index, one FP64 partial per (block, rhs)
+__device__ __forceinline__ void batch_partial(double v, int k, double *partials)
+{
+    __shared__ double sh[kBlock / 64][kMaxRhs];
+    for (int o = 32; o >= k; o >>= 1) v += __shfl_down(v, o, 64);
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane < k) sh[w][lane] = v;
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double s = 0;
+        for (int q = 0; q < kBlock / 64; q++) s += sh[q][threadIdx.x];
+        partials[blockIdx.x * k + threadIdx.x] = s;
+    }
+}
+
+// out_r = [g5] A_oo^-1 D_oe [g5] in_r
+__global__ __launch_bounds__(kBlock) void k_b_clovinv(Geom g, Batch b, Vecs v, const double2 *__restrict__ U,
+                                                      double gin, double gout, const double *__restrict__ st)
+{
+    int i, r;
+    if (!item(b, g.Vh, &i, &r)) return;
+    if (st && st[8 * r + B_DONE] != 0) return;
+    double2 acc[12];
+    hop_all<double2>(g, 1, i, v.in[r], U, gin, acc);
+    if (b.clov[r]) {
+        double2 t[12];
+        clover_apply<double, double2>(b.clo[r], g.Vh, i, acc, t);
+        store_spinor(v.out[r], g.Vh, i, gout, t);
+    } else {
+        store_spinor(v.out[r], g.Vh, i, gout, acc);
+    }
+}
+
+// out_r = [g5] (A_ee [g5] x_r + a_r D_eo t_r), |out_r|^2 partials
+__global__ __launch_bounds__(kBlock) void k_b_xpay(Geom g, Batch b, Vecs x, Vecs t, const double2 *__restrict__ U,
+                                                   double gs, const double *__restrict__ st,
+                                                   double *__restrict__ partials)
+{
+    int i, r;
+    bool ok = item(b, g.Vh, &i, &r);
+    if (ok && st && st[8 * r + B_DONE] != 0) ok = false;
+    double nrm = 0;
+    if (ok) {
+        double2 acc[12], xv[12], ax[12];
+        hop_all<double2>(g, 0, i, t.in[r], U, 1.0, acc);
+        load_spinor(x.in[r], g.Vh, i, gs, xv);
+        if (b.clov[r]) clover_apply<double, double2>(b.cle[r], g.Vh, i, xv, ax);
+        const double a = b.a[r];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            double2 base = b.clov[r] ? ax[k] : xv[k];
+            acc[k] = make_double2(base.x + a * acc[k].x, base.y + a * acc[k].y);
+            nrm += acc[k].x * acc[k].x + acc[k].y * acc[k].y;
+        }
+        store_spinor(x.out[r], g.Vh, i, gs, acc);
+    }
+    if (partials) batch_partial(nrm, b.k, partials);
+}
+
+// CG stage 4: Kp_r from t_r and T'_r; x_r += alpha_r p_r; r_r -= alpha_r Kp_r; |r_r|^2 partials
+__global__ __launch_bounds__(kBlock) void k_b_hop4(Geom g, Batch b, Vecs t, Vecs T, Vecs p, Vecs x, Vecs rr,
+                                                   const double2 *__restrict__ U, const double *__restrict__ st,
+                                                   double *__restrict__ partials)
+{
+    int i, r;
+    bool ok = item(b, g.Vh, &i, &r);
+    if (ok && st[8 * r + B_DONE] != 0) ok = false;
+    double nrm = 0;
+    if (ok) {
+        double2 acc[12], tv[12], at[12];
+        hop_all<double2>(g, 0, i, T.in[r], U, 1.0, acc);
+        load_spinor(t.in[r], g.Vh, i, -1.0, tv);
+        if (b.clov[r]) clover_apply<double, double2>(b.cle[r], g.Vh, i, tv, at);
+        const double alpha = st[8 * r + B_ALPHA], a = b.a[r];
+        const long Vh = g.Vh;
+        const double2 *pp = p.in[r];
+        double2 *xx = x.out[r], *rv_ = rr.out[r];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            double2 base = b.clov[r] ? at[k] : tv[k];
+            double2 kp = make_double2(base.x + a * acc[k].x, base.y + a * acc[k].y);
+            if (k >= 6) kp = cneg(kp);
+            double2 pv = pp[k * Vh + i], xv = xx[k * Vh + i], rv = rv_[k * Vh + i];
+            xv.x += alpha * pv.x; xv.y += alpha * pv.y;
+            rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
+            xx[k * Vh + i] = xv;
+            rv_[k * Vh + i] = rv;
+            nrm += rv.x * rv.x + rv.y * rv.y;
+        }
+    }
+    batch_partial(nrm, b.k, partials);
+}
+
+__device__ __forceinline__ double rhs_total(const double *__restrict__ partials, int nparts, int k, int r)
+{
+    __shared__ double sh[kRedBlock / 64];
+    double s = 0;
+    for (int q = threadIdx.x; q < nparts; q += blockDim.x) s += partials[q * k + r];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double tot = 0;
+    for (int q = 0; q < kRedBlock / 64; q++) tot += sh[q];
+    __syncthreads();
+    return tot;
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_b_alpha(const double *__restrict__ partials, int nparts, int k, int n,
+                                                       double *__restrict__ st)
+{
+    for (int r = 0; r < n; r++) {
+        if (st[8 * r + B_DONE] != 0) continue;
+        double pap = rhs_total(partials, nparts, k, r);
+        if (threadIdx.x == 0) {
+            st[8 * r + B_PAP] = pap;
+            st[8 * r + B_ALPHA] = st[8 * r + B_RR] / pap;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_b_beta(const double *__restrict__ partials, int nparts, int k, int n,
+                                                      double *__restrict__ st)
+{
+    for (int r = 0; r < n; r++) {
+        double *s = st + 8 * r;
+        if (s[B_DONE] != 0) continue;
+        double rr = rhs_total(partials, nparts, k, r);
+        if (threadIdx.x == 0) {
+            s[B_BETA] = rr / s[B_RR];
+            s[B_RR] = rr;
+            s[B_ITER] += 1;
+            s[B_DONE] = rr <= s[B_THR] ? 1 : (s[B_ITER] >= s[B_MAXIT] ? 2 : 0);
+        }
+        __syncthreads();
+    }
+}
+
+// p_r = r_r + beta_r p_r for the right-hand sides still running
+__global__ void k_b_update_p(Geom g, Batch b, Vecs rr, Vecs p, const double *__restrict__ st)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long n = 12L * g.Vh;
+    int r = (int)(t / n);
+    long e = t - (long)r * n;
+    if (r >= b.n || st[8 * r + B_DONE] != 0) return;
+    double beta = st[8 * r + B_BETA];
+    double2 rv = rr.in[r][e], pv = p.out[r][e];
+    p.out[r][e] = make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y);
+}
+
+}  // namespace
+
+static int make_batch(pfmp_ctx *ctx, int nrhs, const int *ops, Batch &b)
+{
+    if (nrhs <= 0 || nrhs > kMaxRhs || !ops) return set_err(ctx, PFMP_ERR_ARG, "batch: 1..8 right-hand sides");
+    b.n = nrhs;
+    b.k = 1;
+    while (b.k < nrhs) b.k <<= 1;
+    for (int r = 0; r < kMaxRhs; r++) {
+        int op = r < nrhs ? ops[r] : ops[0];
+        if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
+            return set_err(ctx, PFMP_ERR_STATE, "batch: operator slot not configured");
+        const OpSlot &s = ctx->ops[op];
+        b.clo[r] = s.clov[1];
+        b.cle[r] = s.clov[0];
+        b.a[r] = -s.kappa * s.kappa;
+        b.clov[r] = s.csw != 0;
+    }
+    return 0;
+}
+
+static Vecs vecs(int n, const void *const *in, void *const *out)
+{
+    Vecs v{};
+    for (int r = 0; r < n; r++) {
+        v.in[r] = in ? (const double2 *)in[r] : nullptr;
+        v.out[r] = out ? (double2 *)out[r] : nullptr;
+    }
+    return v;
+}
+
+// out_r = Khat_r in_r for all r: 4 launches regardless of the number of rhs
+extern "C" int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *const *in,
+                                      void *const *out)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    Batch b;
+    int rc = make_batch(ctx, nrhs, ops, b);
+    if (rc) return rc;
+    if (!in || !out) return set_err(ctx, PFMP_ERR_ARG, "batch: null buffers");
+    for (int r = 0; r < nrhs; r++)
+        if (!in[r] || !out[r]) return set_err(ctx, PFMP_ERR_ARG, "batch: null buffer");
+    const Geom &g = ctx->g;
+    std::vector<void *> te(nrhs), to(nrhs);
+    for (int r = 0; r < nrhs; r++) {
+        te[r] = pool_get(ctx, 1000 + r);
+        to[r] = pool_get(ctx, 1008 + r);
+        if (!te[r] || !to[r]) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
+    }
+    dim3 grid(nblocks_site((long)g.Vh * b.k)), block(kBlock);
+    // Mhat in -> te (stage 1 to to, stage 2 to te), then Mhat^dag te -> out
+    hipLaunchKernelGGL(k_b_clovinv, grid, block, 0, ctx->stream, g, b, vecs(nrhs, in, to.data()), ctx->U, 1.0, 1.0,
+                       nullptr);
+    hipLaunchKernelGGL(k_b_xpay, grid, block, 0, ctx->stream, g, b, vecs(nrhs, in, te.data()),
+                       vecs(nrhs, (const void *const *)to.data(), nullptr), ctx->U, 1.0, nullptr, nullptr);
+    hipLaunchKernelGGL(k_b_clovinv, grid, block, 0, ctx->stream, g, b,
+                       vecs(nrhs, (const void *const *)te.data(), to.data()), ctx->U, -1.0, 1.0, nullptr);
+    hipLaunchKernelGGL(k_b_xpay, grid, block, 0, ctx->stream, g, b, vecs(nrhs, (const void *const *)te.data(), out),
+                       vecs(nrhs, (const void *const *)to.data(), nullptr), ctx->U, -1.0, nullptr, nullptr);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_cg_solve_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *const *b_, void *const *x_,
+                                   const pfmp_solver_params *prm, pfmp_solver_stats *st)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    Batch b;
+    int rc = make_batch(ctx, nrhs, ops, b);
+    if (rc) return rc;
+    if (!b_ || !x_ || !prm || !(prm->tol > 0) || prm->maxiter <= 0)
+        return set_err(ctx, PFMP_ERR_ARG, "cg_solve_batch: bad arguments");
+    if (prm->prec != PFMP_F64) return set_err(ctx, PFMP_ERR_ARG, "cg_solve_batch: FP64 only");
+    for (int r = 0; r < nrhs; r++)
+        if (!b_[r] || !x_[r]) return set_err(ctx, PFMP_ERR_ARG, "cg_solve_batch: null buffer");
+    auto t0 = std::chrono::steady_clock::now();
+    const Geom &g = ctx->g;
+    const size_t vb = sizeof(double) * spinor_reals(g);
+    const long n = 12L * g.Vh;
+    std::vector<void *> R(nrhs), P(nrhs), T1(nrhs), T2(nrhs);
+    for (int r = 0; r < nrhs; r++) {
+        R[r] = pool_get(ctx, 1016 + r);
+        P[r] = pool_get(ctx, 1024 + r);
+        T1[r] = pool_get(ctx, 1000 + r);
+        T2[r] = pool_get(ctx, 1008 + r);
+        if (!R[r] || !P[r] || !T1[r] || !T2[r]) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
+        HIPCHK(ctx, hipMemsetAsync(x_[r], 0, vb, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(R[r], b_[r], vb, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(P[r], b_[r], vb, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    const int nb = nblocks_site((long)g.Vh * b.k);
+    double *part_a = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64) * b.k, 9);
+    double *part_b = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64) * b.k, 10);
+    if (!part_a || !part_b) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
+    double *sc = ctx->scal + kBatchBase;
+    std::vector<double> bb(nrhs);
+    for (int r = 0; r < nrhs; r++) {
+        if ((rc = launch_norm2(ctx, (const double2 *)b_[r], n, ctx->red))) return rc;
+        if ((rc = red_finish(ctx, ctx->red, ctx->nblk_red, 1, &bb[r]))) return rc;
+    }
+    std::vector<double> init(8 * kMaxRhs, 0.0);
+    for (int r = 0; r < nrhs; r++) {
+        init[8 * r + B_RR] = bb[r];
+        init[8 * r + B_THR] = prm->tol * prm->tol * bb[r];
+        init[8 * r + B_DONE] = bb[r] == 0 ? 1 : 0;
+        init[8 * r + B_MAXIT] = prm->maxiter;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(sc, init.data(), sizeof(double) * 8 * kMaxRhs, hipMemcpyHostToDevice, ctx->stream));
+    dim3 grid(nb), block(kBlock);
+    const Vecs vP = vecs(nrhs, (const void *const *)P.data(), P.data());
+    const Vecs vT1 = vecs(nrhs, (const void *const *)T1.data(), T1.data());
+    const Vecs vT2 = vecs(nrhs, (const void *const *)T2.data(), T2.data());
+    const Vecs vR = vecs(nrhs, (const void *const *)R.data(), R.data());
+    const Vecs vX = vecs(nrhs, nullptr, x_);
+    // stage buffers: T2 <- A^-1 D_oe p ; T1 <- Mhat p ; T2 <- A^-1 D_oe g5 T1
+    const Vecs p_to_T2 = vecs(nrhs, (const void *const *)P.data(), T2.data());
+    const Vecs p_to_T1 = vecs(nrhs, (const void *const *)P.data(), T1.data());
+    const Vecs T1_to_T2 = vecs(nrhs, (const void *const *)T1.data(), T2.data());
+    int chunk = prm->check_every > 0 ? prm->check_every : 25;
+    std::vector<double> h(8 * kMaxRhs);
+    for (;;) {
+        for (int it = 0; it < chunk; it++) {
+            hipLaunchKernelGGL(k_b_clovinv, grid, block, 0, ctx->stream, g, b, p_to_T2, ctx->U, 1.0, 1.0, sc);
+            hipLaunchKernelGGL(k_b_xpay, grid, block, 0, ctx->stream, g, b, p_to_T1, vT2, ctx->U, 1.0, sc, part_a);
+            hipLaunchKernelGGL(k_b_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_a, nb, b.k, nrhs, sc);
+            hipLaunchKernelGGL(k_b_clovinv, grid, block, 0, ctx->stream, g, b, T1_to_T2, ctx->U, -1.0, 1.0, sc);
+            hipLaunchKernelGGL(k_b_hop4, grid, block, 0, ctx->stream, g, b, vT1, vT2, vP, vX, vR, ctx->U, sc, part_b);
+            hipLaunchKernelGGL(k_b_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, b.k, nrhs, sc);
+            hipLaunchKernelGGL(k_b_update_p, dim3(nblocks(n * nrhs, 256)), dim3(256), 0, ctx->stream, g, b, vR, vP, sc);
+            LAUNCHCHK(ctx);
+        }
+        HIPCHK(ctx, hipMemcpyAsync(ctx->red_host, sc, sizeof(double) * 8 * kMaxRhs, hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        bool all = true;
+        for (int r = 0; r < nrhs; r++) {
+            h[8 * r + B_DONE] = ctx->red_host[8 * r + B_DONE];
+            h[8 * r + B_ITER] = ctx->red_host[8 * r + B_ITER];
+            all = all && h[8 * r + B_DONE] != 0;
+        }
+        if (all) break;
+    }
+    // FP64 true residuals, one rhs at a time
+    double2 *Kx = (double2 *)ws_alloc(ctx, vb, 8), *te = (double2 *)ws_alloc(ctx, vb, 6),
+            *to = (double2 *)ws_alloc(ctx, vb, 7);
+    if (!Kx || !te || !to) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
+    int worst_rc = 0;
+    for (int r = 0; r < nrhs; r++) {
+        if ((rc = op_apply_K(ctx, ops[r], (const double2 *)x_[r], Kx, te, to, nullptr))) return rc;
+        double one[2] = {1, 0}, mone[2] = {-1, 0};
+        HIPCHK(ctx, hipMemcpyAsync(te, b_[r], vb, hipMemcpyDeviceToDevice, ctx->stream));
+        if ((rc = pfmp_axpby(ctx, mone, Kx, one, te))) return rc;
+        double rr;
+        if ((rc = launch_norm2(ctx, te, n, ctx->red))) return rc;
+        if ((rc = red_finish(ctx, ctx->red, ctx->nblk_red, 1, &rr))) return rc;
+        double res = bb[r] > 0 ? std::sqrt(rr / bb[r]) : 0;
+        if (st) {
+            st[r].iters = (int)h[8 * r + B_ITER];
+            st[r].reliable_updates = 0;
+            st[r].true_res = res;
+            st[r].kmults = st[r].iters + 1;
+        }
+        if (h[8 * r + B_DONE] == 2 && !(res <= prm->tol)) worst_rc = PFMP_ERR_NOCONV;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    if (st)
+        for (int r = 0; r < nrhs; r++) st[r].seconds = std::chrono::duration<double>(t1 - t0).count();
+    if (worst_rc) return set_err(ctx, worst_rc, "cg_solve_batch: maxiter reached");
+    return 0;
+}

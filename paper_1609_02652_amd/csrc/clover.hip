@@ -160,35 +160,50 @@ __global__ void k_to_f32(long n, const double *__restrict__ a, float *__restrict
 
 }  // namespace
 
+// Rebuild the clover fields of slot op on the current links.  No host
+// synchronisation: the per-block ln det partials and the positivity flag stay on
+// the device until clover_logdet() needs them.
 int clover_build(pfmp_ctx *ctx, int op)
 {
     OpSlot &s = ctx->ops[op];
     const Geom &g = ctx->g;
     s.logdet_odd = 0;
+    s.ld_dirty = false;
     if (s.csw == 0) return 0;
-    int nb = nblocks(g.Vh, kBlock);
-    double *ld = (double *)ws_alloc(ctx, sizeof(double) * nb, 15);
-    int *bad = (int *)(ctx->scal + 8000);
-    if (!ld) return set_err(ctx, PFMP_ERR_OOM, "clover workspace");
+    const int nb = nblocks(g.Vh, kBlock);
+    if (!s.ldpart && hipMalloc(&s.ldpart, sizeof(double) * nb) != hipSuccess)
+        return set_err(ctx, PFMP_ERR_OOM, "clover workspace");
+    int *bad = (int *)(ctx->scal + 8000) + op;
     HIPCHK(ctx, hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
-    double kc = s.kappa * s.csw;
+    const double kc = s.kappa * s.csw;
     for (int p = 0; p < 2; p++) {
-        hipLaunchKernelGGL(k_clover_build, dim3(nb), dim3(kBlock), 0, ctx->stream, g, p, ctx->U, kc, s.clov[p], ld,
-                           bad);
+        hipLaunchKernelGGL(k_clover_build, dim3(nb), dim3(kBlock), 0, ctx->stream, g, p, ctx->U, kc, s.clov[p],
+                           s.ldpart, bad);
         LAUNCHCHK(ctx);
         long n = clover_reals(g);
         hipLaunchKernelGGL(k_to_f32, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, s.clov[p], s.clovf[p]);
         LAUNCHCHK(ctx);
     }
+    s.ld_dirty = true;
+    return 0;
+}
+
+// Sum the ln det A_oo partials of slot op (synchronises) and check positivity.
+int clover_logdet(pfmp_ctx *ctx, int op)
+{
+    OpSlot &s = ctx->ops[op];
+    if (!s.ld_dirty) return 0;
+    const int nb = nblocks(ctx->g.Vh, kBlock);
     std::vector<double> h(nb);
     int hbad = 0;
-    HIPCHK(ctx, hipMemcpyAsync(h.data(), ld, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(h.data(), s.ldpart, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(&hbad, (int *)(ctx->scal + 8000) + op, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     if (hbad) return set_err(ctx, PFMP_ERR_ARG, "clover term A_oo is not positive definite");
     double t = 0;
     for (double v : h) t += v;
     s.logdet_odd = t;
+    s.ld_dirty = false;
     return 0;
 }
 
@@ -196,6 +211,8 @@ extern "C" int pfmp_logdet_action(pfmp_ctx *ctx, int op, double *out)
 {
     if (!ctx || !out || op < 0 || op >= PFMP_MAX_OPS) return ctx ? set_err(ctx, PFMP_ERR_ARG, "logdet_action") : PFMP_ERR_ARG;
     if (!ctx->ops[op].valid) return set_err(ctx, PFMP_ERR_STATE, "operator slot not configured");
+    int rc = clover_logdet(ctx, op);
+    if (rc) return rc;
     *out = -2.0 * ctx->ops[op].logdet_odd;
     return 0;
 }

@@ -6,8 +6,9 @@
 
 // Scratch buffers of the context, one per slot:
 //   0-3 operator temporaries, 4-10 CG, 11-13 multi-shift, 14 link accumulator,
-//   15 reduction partials, 16-19 forces, 20-31 polynomial and mixed precision.
-constexpr int kWsSlots = 32;
+//   15 reduction partials, 16-19 forces, 20-23 polynomial, 24-26 trajectory,
+//   27-31 mixed precision, 32-38 learned preconditioner.
+constexpr int kWsSlots = 48;
 struct SolverWS {
     void *buf[kWsSlots] = {};
     size_t bytes[kWsSlots] = {};
@@ -39,14 +40,16 @@ void *ws_alloc(pfmp_ctx *ctx, size_t bytes, int slot)
     return w->buf[slot];
 }
 
-// Buffer idx of the context's pool of FP64 spinors (allocated on first use).
+// Buffer idx of the context's pool of FP64 spinors; only the indices asked for
+// are allocated (on first use).
 double2 *pool_get(pfmp_ctx *ctx, int idx)
 {
-    if (idx < 0) return nullptr;
-    while ((int)ctx->pool.size() <= idx) {
+    if (idx < 0 || idx >= 4096) return nullptr;
+    if ((int)ctx->pool.size() <= idx) ctx->pool.resize(idx + 1, nullptr);
+    if (!ctx->pool[idx]) {
         double2 *p = nullptr;
         if (hipMalloc(&p, sizeof(double) * spinor_reals(ctx->g)) != hipSuccess) return nullptr;
-        ctx->pool.push_back(p);
+        ctx->pool[idx] = p;
     }
     return ctx->pool[idx];
 }
@@ -178,7 +181,7 @@ extern "C" int pfmp_destroy(pfmp_ctx *ctx)
     for (auto &s : ctx->ops) {
         hipFree(s.clov[0]); hipFree(s.clov[1]);
         hipFree(s.clovf[0]); hipFree(s.clovf[1]);
-        hipFree(s.Aoo);
+        hipFree(s.ldpart);
     }
     for (double2 *p : ctx->pool) hipFree(p);
     if (ctx->ws) {
@@ -259,12 +262,12 @@ extern "C" int pfmp_set_operator(pfmp_ctx *ctx, int op, double kappa, double csw
     if (!s.clov[0]) {
         size_t b = sizeof(double) * clover_reals(ctx->g);
         if (hipMalloc(&s.clov[0], b) != hipSuccess || hipMalloc(&s.clov[1], b) != hipSuccess ||
-            hipMalloc(&s.clovf[0], b / 2) != hipSuccess || hipMalloc(&s.clovf[1], b / 2) != hipSuccess ||
-            hipMalloc(&s.Aoo, b) != hipSuccess)
+            hipMalloc(&s.clovf[0], b / 2) != hipSuccess || hipMalloc(&s.clovf[1], b / 2) != hipSuccess)
             return set_err(ctx, PFMP_ERR_OOM, "clover fields");
     }
     s.valid = true;
     int rc = clover_build(ctx, op);
+    if (!rc) rc = clover_logdet(ctx, op);   // positivity checked once, synchronously
     if (rc) s.valid = false;
     return rc;
 }

@@ -9,16 +9,16 @@
 
 namespace {
 
-// out = [g5] A^-1 D in [g5], output parity pout (CLOV = 0: no clover)
-template <typename C, typename R, int CLOV>
-__global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const C *__restrict__ in,
-                                                        const C *__restrict__ U, const R *__restrict__ cl,
-                                                        C *__restrict__ out, R gin, R gout,
+// out = [g5] A^-1 D in [g5], output parity pout (CLOV = 0: no clover); In / Out are
+// spinor pointers of the register type C or FP16 storage (HalfField)
+template <typename C, typename R, int CLOV, typename In, typename Out>
+__global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const In in, const C *__restrict__ U,
+                                                        const R *__restrict__ cl, Out out, R gin, R gout,
                                                         const double *__restrict__ stop)
 {
     if (stop && stop[0] != 0) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.Vh) return;
+    int i = xcd_site(g.Vh);
+    if (i < 0) return;
     C acc[12];
     hop_all<C>(g, pout, i, in, U, gin, acc);
     if (CLOV) {
@@ -31,16 +31,15 @@ __global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const 
 }
 
 // out = [g5] (A [g5] x + a D t), output parity pout; NORM: |out|^2 block partials
-template <typename C, typename R, int CLOV, int NORM>
-__global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const C *__restrict__ x,
-                                                     const C *__restrict__ t, const C *__restrict__ U,
-                                                     const R *__restrict__ cl, R a, C *__restrict__ out, R gs,
-                                                     double *partials, const double *__restrict__ stop)
+template <typename C, typename R, int CLOV, int NORM, typename X, typename T, typename Out>
+__global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const X x, const T t,
+                                                     const C *__restrict__ U, const R *__restrict__ cl, R a, Out out,
+                                                     R gs, double *partials, const double *__restrict__ stop)
 {
     if (stop && stop[0] != 0) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_site(g.Vh);
     double nrm = 0;
-    if (i < g.Vh) {
+    if (i >= 0) {
         C acc[12], xv[12], ax[12];
         hop_all<C>(g, pout, i, t, U, (R)1, acc);
         load_spinor(x, g.Vh, i, gs, xv);
@@ -58,29 +57,29 @@ __global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const C *
 
 }  // namespace
 
-template <typename C, typename R>
-int launch_clovinv(pfmp_ctx *ctx, int pout, const C *in, const C *U, const R *cl, C *out, R gin, R gout, bool clov,
+template <typename C, typename R, typename In, typename Out>
+int launch_clovinv(pfmp_ctx *ctx, int pout, In in, const C *U, const R *cl, Out out, R gin, R gout, bool clov,
                    const double *stop)
 {
-    dim3 grid(nblocks(ctx->g.Vh, kBlock)), block(kBlock);
+    dim3 grid(nblocks_site(ctx->g.Vh)), block(kBlock);
     if (clov)
-        hipLaunchKernelGGL((k_hop_clovinv<C, R, 1>), grid, block, 0, ctx->stream, ctx->g, pout, in, U, cl, out, gin,
-                           gout, stop);
+        hipLaunchKernelGGL((k_hop_clovinv<C, R, 1, In, Out>), grid, block, 0, ctx->stream, ctx->g, pout, in, U, cl,
+                           out, gin, gout, stop);
     else
-        hipLaunchKernelGGL((k_hop_clovinv<C, R, 0>), grid, block, 0, ctx->stream, ctx->g, pout, in, U, cl, out, gin,
-                           gout, stop);
+        hipLaunchKernelGGL((k_hop_clovinv<C, R, 0, In, Out>), grid, block, 0, ctx->stream, ctx->g, pout, in, U, cl,
+                           out, gin, gout, stop);
     LAUNCHCHK(ctx);
     return 0;
 }
 
-template <typename C, typename R>
-int launch_xpay(pfmp_ctx *ctx, int pout, const C *x, const C *t, const C *U, const R *cl, R a, C *out, R gs,
-                bool clov, double *partials, const double *stop)
+template <typename C, typename R, typename X, typename T, typename Out>
+int launch_xpay(pfmp_ctx *ctx, int pout, X x, T t, const C *U, const R *cl, R a, Out out, R gs, bool clov,
+                double *partials, const double *stop)
 {
-    dim3 grid(nblocks(ctx->g.Vh, kBlock)), block(kBlock);
-#define XPAY(CL, NM)                                                                                           \
-    hipLaunchKernelGGL((k_hop_xpay<C, R, CL, NM>), grid, block, 0, ctx->stream, ctx->g, pout, x, t, U, cl, a, out, \
-                       gs, partials, stop)
+    dim3 grid(nblocks_site(ctx->g.Vh)), block(kBlock);
+#define XPAY(CL, NM)                                                                                               \
+    hipLaunchKernelGGL((k_hop_xpay<C, R, CL, NM, X, T, Out>), grid, block, 0, ctx->stream, ctx->g, pout, x, t, U, cl, \
+                       a, out, gs, partials, stop)
     if (clov && partials) XPAY(1, 1);
     else if (clov) XPAY(1, 0);
     else if (partials) XPAY(0, 1);
@@ -90,14 +89,25 @@ int launch_xpay(pfmp_ctx *ctx, int pout, const C *x, const C *t, const C *U, con
     return 0;
 }
 
-template int launch_clovinv<double2, double>(pfmp_ctx *, int, const double2 *, const double2 *, const double *,
-                                             double2 *, double, double, bool, const double *);
-template int launch_clovinv<float2, float>(pfmp_ctx *, int, const float2 *, const float2 *, const float *, float2 *,
-                                           float, float, bool, const double *);
-template int launch_xpay<double2, double>(pfmp_ctx *, int, const double2 *, const double2 *, const double2 *,
-                                          const double *, double, double2 *, double, bool, double *, const double *);
-template int launch_xpay<float2, float>(pfmp_ctx *, int, const float2 *, const float2 *, const float2 *,
-                                        const float *, float, float2 *, float, bool, double *, const double *);
+template int launch_clovinv<double2, double, const double2 *, double2 *>(pfmp_ctx *, int, const double2 *,
+                                                                        const double2 *, const double *, double2 *,
+                                                                        double, double, bool, const double *);
+template int launch_clovinv<float2, float, const float2 *, float2 *>(pfmp_ctx *, int, const float2 *, const float2 *,
+                                                                    const float *, float2 *, float, float, bool,
+                                                                    const double *);
+template int launch_clovinv<float2, float, HalfField, HalfField>(pfmp_ctx *, int, HalfField, const float2 *,
+                                                                const float *, HalfField, float, float, bool,
+                                                                const double *);
+template int launch_xpay<double2, double, const double2 *, const double2 *, double2 *>(
+    pfmp_ctx *, int, const double2 *, const double2 *, const double2 *, const double *, double, double2 *, double,
+    bool, double *, const double *);
+template int launch_xpay<float2, float, const float2 *, const float2 *, float2 *>(
+    pfmp_ctx *, int, const float2 *, const float2 *, const float2 *, const float *, float, float2 *, float, bool,
+    double *, const double *);
+template int launch_xpay<float2, float, HalfField, HalfField, HalfField>(pfmp_ctx *, int, HalfField, HalfField,
+                                                                       const float2 *, const float *, float,
+                                                                       HalfField, float, bool, double *,
+                                                                       const double *);
 
 namespace {
 
@@ -106,8 +116,8 @@ template <typename C, typename R>
 __global__ __launch_bounds__(kBlock) void k_clover(Geom g, const C *__restrict__ in, const R *__restrict__ cl,
                                                    C *__restrict__ out)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.Vh) return;
+    int i = xcd_site(g.Vh);
+    if (i < 0) return;
     C v[12], w[12];
     load_spinor(in, g.Vh, i, (R)1, v);
     clover_apply<R, C>(cl, g.Vh, i, v, w);
@@ -126,9 +136,9 @@ int op_apply_M(pfmp_ctx *ctx, int op, int dagger, const double2 *in, double2 *ou
     OpSlot &s = ctx->ops[op];
     double gs = dagger ? -1.0 : 1.0;
     bool cl = op_has_clover(s);
-    int rc = launch_clovinv<double2, double>(ctx, 1, in, ctx->U, s.clov[1], tmp_odd, gs, 1.0, cl, nullptr);
+    int rc = launch_clovinv<double2, double, const double2 *, double2 *>(ctx, 1, in, ctx->U, s.clov[1], tmp_odd, gs, 1.0, cl, nullptr);
     if (rc) return rc;
-    return launch_xpay<double2, double>(ctx, 0, in, tmp_odd, ctx->U, s.clov[0], -s.kappa * s.kappa, out, gs, cl,
+    return launch_xpay<double2, double, const double2 *, const double2 *, double2 *>(ctx, 0, in, tmp_odd, ctx->U, s.clov[0], -s.kappa * s.kappa, out, gs, cl,
                                         norm_partials, nullptr);
 }
 
@@ -146,9 +156,9 @@ int op_apply_M_f32(pfmp_ctx *ctx, int op, int dagger, const float2 *in, float2 *
     OpSlot &s = ctx->ops[op];
     float gs = dagger ? -1.f : 1.f;
     bool cl = op_has_clover(s);
-    int rc = launch_clovinv<float2, float>(ctx, 1, in, ctx->Uf, s.clovf[1], tmp_odd, gs, 1.f, cl, nullptr);
+    int rc = launch_clovinv<float2, float, const float2 *, float2 *>(ctx, 1, in, ctx->Uf, s.clovf[1], tmp_odd, gs, 1.f, cl, nullptr);
     if (rc) return rc;
-    return launch_xpay<float2, float>(ctx, 0, in, tmp_odd, ctx->Uf, s.clovf[0], (float)(-s.kappa * s.kappa), out,
+    return launch_xpay<float2, float, const float2 *, const float2 *, float2 *>(ctx, 0, in, tmp_odd, ctx->Uf, s.clovf[0], (float)(-s.kappa * s.kappa), out,
                                       gs, cl, norm_partials, nullptr);
 }
 
@@ -176,7 +186,7 @@ extern "C" int pfmp_apply_hop(pfmp_ctx *ctx, int out_parity, int dagger, const v
     if (!ctx || !in || !out || (out_parity != 0 && out_parity != 1)) return ctx ? set_err(ctx, PFMP_ERR_ARG, "apply_hop: bad argument") : PFMP_ERR_ARG;
     if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
     double gs = dagger ? -1.0 : 1.0;
-    return launch_clovinv<double2, double>(ctx, out_parity, (const double2 *)in, ctx->U, nullptr, (double2 *)out, gs,
+    return launch_clovinv<double2, double, const double2 *, double2 *>(ctx, out_parity, (const double2 *)in, ctx->U, nullptr, (double2 *)out, gs,
                                            gs, false, nullptr);
 }
 
@@ -191,7 +201,7 @@ extern "C" int pfmp_apply_clover(pfmp_ctx *ctx, int op, int parity, int inverse,
         HIPCHK(ctx, hipMemcpyAsync(out, in, sizeof(double) * spinor_reals(ctx->g), hipMemcpyDeviceToDevice, ctx->stream));
         return 0;
     }
-    hipLaunchKernelGGL((k_clover<double2, double>), dim3(nblocks(ctx->g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream,
+    hipLaunchKernelGGL((k_clover<double2, double>), dim3(nblocks_site(ctx->g.Vh)), dim3(kBlock), 0, ctx->stream,
                        ctx->g, (const double2 *)in, s.clov[parity], (double2 *)out);
     LAUNCHCHK(ctx);
     return 0;

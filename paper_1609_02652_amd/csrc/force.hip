@@ -450,8 +450,8 @@ extern "C" int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void 
         const double2 *x = (const double2 *)X[q], *y = (const double2 *)Y[q];
         double2 c = make_double2(coeff[2 * q], coeff[2 * q + 1]);
         // Z = A_oo^-1 D_oe Y,  Xo = A_oo^-1 g5 D_oe g5 X = A_oo^-1 (D_eo)^dag X
-        if ((rc = launch_clovinv<double2, double>(ctx, 1, y, ctx->U, s.clov[1], Zo, 1.0, 1.0, cl, nullptr))) return rc;
-        if ((rc = launch_clovinv<double2, double>(ctx, 1, x, ctx->U, s.clov[1], Xo, -1.0, -1.0, cl, nullptr))) return rc;
+        if ((rc = clovinv64(ctx, 1, y, s.clov[1], Zo, 1.0, 1.0, cl, nullptr))) return rc;
+        if ((rc = clovinv64(ctx, 1, x, s.clov[1], Xo, -1.0, -1.0, cl, nullptr))) return rc;
         if (do_hop)
             hipLaunchKernelGGL(k_hop_force, dim3(nblocks(2L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, x, Xo,
                                y, Zo, ctx->U, c, Zhop);

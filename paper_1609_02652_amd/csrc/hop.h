@@ -9,7 +9,42 @@
 // with B = -i sigma_k, C = i sigma_k for k = x,y,z and B = C = 1 for t.
 // Neighbour indices come from the site coordinates (no index tables are read).
 #pragma once
+#include <hip/hip_fp16.h>
+
 #include "internal.h"
+
+// FP16 spinor storage (one parity): 12 half2 planes [12][Vh] plus one FP32 scale per
+// site; the stored values are v / scale with scale = max |Re|, |Im| over the site's 24
+// reals (IEEE binary16, round to nearest even), arithmetic in FP32.
+struct HalfField {
+    __half2 *h;
+    float *s;
+};
+
+__device__ __forceinline__ void load_spinor(const HalfField &f, int Vh, int i, float gs, float2 *v)
+{
+    const float sc = f.s[i];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        float2 a = __half22float2(f.h[(long)k * Vh + i]);
+        float m = k < 6 ? sc : sc * gs;
+        v[k] = make_float2(a.x * m, a.y * m);
+    }
+}
+
+__device__ __forceinline__ void store_spinor(const HalfField &f, int Vh, int i, float gs, const float2 *v)
+{
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
+    const float inv = m > 0.f ? 1.f / m : 0.f;
+    f.s[i] = m;
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        float q = k < 6 ? inv : inv * gs;
+        f.h[(long)k * Vh + i] = __floats2half2_rn(v[k].x * q, v[k].y * q);
+    }
+}
 
 // load a spinor (12 complex) of site i; gs = -1 flips the lower spins (g5)
 template <typename C>
@@ -99,8 +134,8 @@ __device__ __forceinline__ void su3_half(const C *__restrict__ U, long stride, i
         }
 }
 
-template <int MU, typename C>
-__device__ __forceinline__ void hop_dir(const Geom &g, int pout, int i, const int *c, const C *__restrict__ in,
+template <int MU, typename C, typename In>
+__device__ __forceinline__ void hop_dir(const Geom &g, int pout, int i, const int *c, const In in,
                                         const C *__restrict__ U, decltype(C::x) gs, C *acc)
 {
     using R = decltype(C::x);
@@ -121,18 +156,18 @@ __device__ __forceinline__ void hop_dir(const Geom &g, int pout, int i, const in
     reconstruct<MU, +1>(w, acc);
 }
 
-template <typename C>
-__device__ __forceinline__ void hop_all(const Geom &g, int pout, int i, const C *__restrict__ in,
+template <typename C, typename In>
+__device__ __forceinline__ void hop_all(const Geom &g, int pout, int i, const In in,
                                         const C *__restrict__ U, decltype(C::x) gs, C *acc)
 {
     int c[4];
     eo_coords(g, pout, i, c);
 #pragma unroll
     for (int k = 0; k < 12; k++) acc[k] = mk<C>(0, 0);
-    hop_dir<0>(g, pout, i, c, in, U, gs, acc);
-    hop_dir<1>(g, pout, i, c, in, U, gs, acc);
-    hop_dir<2>(g, pout, i, c, in, U, gs, acc);
-    hop_dir<3>(g, pout, i, c, in, U, gs, acc);
+    hop_dir<0, C>(g, pout, i, c, in, U, gs, acc);
+    hop_dir<1, C>(g, pout, i, c, in, U, gs, acc);
+    hop_dir<2, C>(g, pout, i, c, in, U, gs, acc);
+    hop_dir<3, C>(g, pout, i, c, in, U, gs, acc);
 }
 
 // out[6] = (6x6 Hermitian block b of the clover field at site i) v[6]
@@ -181,3 +216,36 @@ __device__ __forceinline__ void block_sum_store(double v, double *partials)
     }
 }
 
+
+// operator stages (dslash.hip); In / X / T / Out: const C* / C* or HalfField
+template <typename C, typename R, typename In, typename Out>
+int launch_clovinv(pfmp_ctx *ctx, int pout, In in, const C *U, const R *cl, Out out, R gin, R gout, bool clov,
+                   const double *stop);
+template <typename C, typename R, typename X, typename T, typename Out>
+int launch_xpay(pfmp_ctx *ctx, int pout, X x, T t, const C *U, const R *cl, R a, Out out, R gs, bool clov,
+                double *partials, const double *stop);
+
+inline int clovinv64(pfmp_ctx *ctx, int pout, const double2 *in, const double *cl, double2 *out, double gin,
+                     double gout, bool clov, const double *stop)
+{
+    return launch_clovinv<double2, double, const double2 *, double2 *>(ctx, pout, in, ctx->U, cl, out, gin, gout,
+                                                                       clov, stop);
+}
+inline int xpay64(pfmp_ctx *ctx, int pout, const double2 *x, const double2 *t, const double *cl, double a,
+                  double2 *out, double gs, bool clov, double *partials, const double *stop)
+{
+    return launch_xpay<double2, double, const double2 *, const double2 *, double2 *>(ctx, pout, x, t, ctx->U, cl, a,
+                                                                                     out, gs, clov, partials, stop);
+}
+inline int clovinv32(pfmp_ctx *ctx, int pout, const float2 *in, const float *cl, float2 *out, float gin, float gout,
+                     bool clov, const double *stop)
+{
+    return launch_clovinv<float2, float, const float2 *, float2 *>(ctx, pout, in, ctx->Uf, cl, out, gin, gout, clov,
+                                                                   stop);
+}
+inline int xpay32(pfmp_ctx *ctx, int pout, const float2 *x, const float2 *t, const float *cl, float a, float2 *out,
+                  float gs, bool clov, double *partials, const double *stop)
+{
+    return launch_xpay<float2, float, const float2 *, const float2 *, float2 *>(ctx, pout, x, t, ctx->Uf, cl, a, out,
+                                                                                gs, clov, partials, stop);
+}

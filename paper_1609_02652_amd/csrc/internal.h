@@ -94,6 +94,21 @@ __device__ __forceinline__ int eo_neighbour(const Geom &g, const int c[4], int m
     return eo_index(g, d);
 }
 
+// Site of this thread with an XCD-aware block order: the hardware hands
+// consecutive workgroups round-robin to the 8 XCDs (each with its own L2), so
+// logical block b' = (b mod 8) * ceil(nb/8) + b / 8 gives every XCD one
+// contiguous chunk of sites and keeps the y, z, t neighbour gathers in its L2.
+// Returns -1 for threads past the end.
+__device__ __forceinline__ int xcd_site(int n)
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int per = (nb + 7) >> 3;
+    const int lb = (b & 7) * per + (b >> 3);
+    if (lb >= nb) return -1;
+    int i = lb * blockDim.x + threadIdx.x;
+    return i < n ? i : -1;
+}
+
 // ------------------------------------------------------------------ context
 
 struct OpSlot {
@@ -102,7 +117,8 @@ struct OpSlot {
     double *clov[2] = {nullptr, nullptr};   // FP64: A_ee on [0] (even), A_oo^-1 on [1] (odd)
     float *clovf[2] = {nullptr, nullptr};   // FP32 copies
     double logdet_odd = 0;                  // sum_{x odd} ln det A(x)
-    double *Aoo = nullptr;                  // A on odd sites (FP64, for the clover force)
+    double *ldpart = nullptr;               // per-block ln det A_oo partials (device)
+    bool ld_dirty = false;                  // ldpart newer than logdet_odd
 };
 
 struct SolverWS;
@@ -146,6 +162,9 @@ int set_err(pfmp_ctx *ctx, int code, const std::string &msg);
 constexpr int kBlock = 128;      // threads per block of the site kernels
 constexpr int kRedBlock = 256;   // threads per block of reductions
 inline int nblocks(long n, int b) { return (int)((n + b - 1) / b); }
+// grid of the site kernels that use xcd_site(): a multiple of 8 blocks so that the
+// XCD block order is a bijection
+inline int nblocks_site(long n) { return ((nblocks(n, kBlock) + 7) / 8) * 8; }
 
 // sizes of internal fields
 inline long spinor_reals(const Geom &g) { return 24L * g.Vh; }
@@ -164,16 +183,11 @@ int op_apply_M_f32(pfmp_ctx *ctx, int op, int dagger, const float2 *in, float2 *
                    double *norm_partials);
 int op_apply_K_f32(pfmp_ctx *ctx, int op, const float2 *in, float2 *out, float2 *tmp_even, float2 *tmp_odd,
                    double *norm_partials);
-template <typename C, typename R>
-int launch_clovinv(pfmp_ctx *ctx, int pout, const C *in, const C *U, const R *cl, C *out, R gin, R gout, bool clov,
-                   const double *stop);
-template <typename C, typename R>
-int launch_xpay(pfmp_ctx *ctx, int pout, const C *x, const C *t, const C *U, const R *cl, R a, C *out, R gs,
-                bool clov, double *partials, const double *stop);
 int rebuild_gauge_derived(pfmp_ctx *ctx);
 int red_finish_dev(pfmp_ctx *ctx, const double *partials, int nparts, int nvals, double *dev_out);
 // clover (clover.hip)
 int clover_build(pfmp_ctx *ctx, int op);
+int clover_logdet(pfmp_ctx *ctx, int op);
 // reductions (blas.hip)
 int red_finish(pfmp_ctx *ctx, const double *partials, int nparts, int nvals, double *host_out);
 int launch_dot(pfmp_ctx *ctx, const double2 *a, const double2 *b, long n, double *partials);

@@ -1,5 +1,7 @@
 // mixed.hip -- mixed-precision CG on Khat: FP32 inner iterations (FP32 links,
-// clover and spinors; FP64 reductions and scalars) with FP64 reliable updates.
+// clover and arithmetic; FP64 reductions and scalars) with FP64 reliable updates.
+// Storage of the inner operator vectors (search direction p, Mhat p and the odd
+// intermediates) is FP32 or FP16 with one FP32 scale per site; x and r stay FP32.
 //
 // The inner CG runs on (xs, rs, ps) in FP32.  When its residual has dropped by
 // the factor delta since the last update, or reached the target, the device
@@ -36,6 +38,9 @@ __global__ __launch_bounds__(kRedBlock) void k_m_restart(const double *__restric
 {
     double rr = block_total_m(partials, nparts);
     if (threadIdx.x == 0) {
+        // the iteration that flagged the update skipped p = r + beta p; redo it with
+        // the true residual: beta' = |r_true|^2 / |r_prev|^2, |r_prev|^2 = rr_inner / beta
+        if (!first) st[M_BETA] = rr * st[M_BETA] / st[M_RR];
         st[M_RR] = rr;
         st[M_THR] = tol2bb;
         st[M_DTHR] = delta2 * rr;
@@ -72,20 +77,20 @@ __global__ __launch_bounds__(kRedBlock) void k_m_beta(const double *__restrict__
 
 // FP32 Khat p from t = Mhat p and T' (as in the FP64 solver), fused with
 // x += alpha p, r -= alpha Khat p and FP64 |r|^2 partials
-template <int CLOV>
-__global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const float2 *__restrict__ t, const float2 *__restrict__ T,
-                                                   const float2 *__restrict__ U, const float *__restrict__ cl,
-                                                   float a, const float2 *__restrict__ p, float2 *__restrict__ x,
-                                                   float2 *__restrict__ r, const double *__restrict__ st,
-                                                   double *__restrict__ partials)
+template <int CLOV, typename S>
+__global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T, const float2 *__restrict__ U,
+                                                   const float *__restrict__ cl, float a, const S p,
+                                                   float2 *__restrict__ x, float2 *__restrict__ r,
+                                                   const double *__restrict__ st, double *__restrict__ partials)
 {
     if (st[M_DONE] != 0) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_site(g.Vh);
     double nrm = 0;
-    if (i < g.Vh) {
-        float2 acc[12], tv[12], at[12];
+    if (i >= 0) {
+        float2 acc[12], tv[12], at[12], pp[12];
         hop_all<float2>(g, 0, i, T, U, 1.f, acc);
         load_spinor(t, g.Vh, i, -1.f, tv);
+        load_spinor(p, g.Vh, i, 1.f, pp);
         if (CLOV) clover_apply<float, float2>(cl, g.Vh, i, tv, at);
         const float alpha = (float)st[M_ALPHA];
         const long Vh = g.Vh;
@@ -94,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const float2 *__restr
             float2 base = CLOV ? at[k] : tv[k];
             float2 kp = make_float2(base.x + a * acc[k].x, base.y + a * acc[k].y);
             if (k >= 6) kp = cneg(kp);
-            float2 pv = p[k * Vh + i], xv = x[k * Vh + i], rv = r[k * Vh + i];
+            float2 pv = pp[k], xv = x[k * Vh + i], rv = r[k * Vh + i];
             xv.x += alpha * pv.x; xv.y += alpha * pv.y;
             rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
             x[k * Vh + i] = xv;
@@ -105,15 +110,24 @@ __global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const float2 *__restr
     block_sum_store<float2>(nrm, partials);
 }
 
-__global__ void k_m_update_p(long n, const float2 *__restrict__ r, float2 *__restrict__ p,
-                             const double *__restrict__ st)
+// p = r + beta p (per site: FP16 storage needs the site's 24 reals for its scale);
+// with st == nullptr: p = r
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_m_update_p(Geom g, const float2 *__restrict__ r, S p,
+                                                       const double *__restrict__ st)
 {
-    if (st[M_DONE] != 0) return;
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    float b = (float)st[M_BETA];
-    float2 rv = r[t], pv = p[t];
-    p[t] = make_float2(rv.x + b * pv.x, rv.y + b * pv.y);
+    if (st && st[M_DONE] != 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.Vh) return;
+    float2 rv[12], pv[12];
+    load_spinor(r, g.Vh, i, 1.f, rv);
+    if (st) {
+        const float b = (float)st[M_BETA];
+        load_spinor(p, g.Vh, i, 1.f, pv);
+#pragma unroll
+        for (int k = 0; k < 12; k++) rv[k] = make_float2(rv[k].x + b * pv[k].x, rv[k].y + b * pv[k].y);
+    }
+    store_spinor(p, g.Vh, i, 1.f, rv);
 }
 
 // x += xs (FP64 += FP32), xs = 0
@@ -127,19 +141,16 @@ __global__ void k_m_accum(long n, float2 *__restrict__ xs, double2 *__restrict__
     xs[t] = make_float2(0.f, 0.f);
 }
 
-// r = b - Kx (FP64); rs = (float) r; optionally ps = rs; |r|^2 partials (grid-stride)
+// r = b - Kx (FP64); rs = (float) r; |r|^2 partials (grid-stride)
 __global__ __launch_bounds__(kRedBlock) void k_m_residual(long n, const double2 *__restrict__ b,
                                                           const double2 *__restrict__ Kx, float2 *__restrict__ rs,
-                                                          float2 *__restrict__ ps, int set_p,
                                                           double *__restrict__ partials)
 {
     double s = 0;
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
         double2 r = csub(b[t], Kx[t]);
         s += r.x * r.x + r.y * r.y;
-        float2 f = make_float2((float)r.x, (float)r.y);
-        rs[t] = f;
-        if (set_p) ps[t] = f;
+        rs[t] = make_float2((float)r.x, (float)r.y);
     }
     __shared__ double sh[kRedBlock / 64];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
@@ -154,25 +165,39 @@ __global__ __launch_bounds__(kRedBlock) void k_m_residual(long n, const double2 
 
 }  // namespace
 
-int cg_solve_mixed(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfmp_solver_params *prm,
-                   pfmp_solver_stats *st)
+template <typename S> struct Store;
+template <> struct Store<float2 *> {
+    using In = const float2 *;
+    static size_t bytes(long Vh) { return 8L * 12 * Vh; }
+    static float2 *make(void *p, long) { return (float2 *)p; }
+};
+template <> struct Store<HalfField> {
+    using In = HalfField;
+    static size_t bytes(long Vh) { return 4L * 12 * Vh + 4L * Vh; }
+    static HalfField make(void *p, long Vh) { return HalfField{(__half2 *)p, (float *)((char *)p + 4L * 12 * Vh)}; }
+};
+
+template <typename S>
+static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfmp_solver_params *prm,
+                      pfmp_solver_stats *st)
 {
-    if (prm->prec != PFMP_F32) return set_err(ctx, PFMP_ERR_ARG, "cg_solve: unsupported precision");
+    using In = typename Store<S>::In;
     auto t0 = std::chrono::steady_clock::now();
     const Geom &g = ctx->g;
     OpSlot &s = ctx->ops[op];
     const long n = 12L * g.Vh;
     const size_t vb = sizeof(double) * spinor_reals(g), fb = vb / 2;
-    const int nb = nblocks(g.Vh, kBlock);
+    const int nb = nblocks_site(g.Vh);
     double2 *Kx = (double2 *)ws_alloc(ctx, vb, 8), *te = (double2 *)ws_alloc(ctx, vb, 6),
             *to = (double2 *)ws_alloc(ctx, vb, 7);
-    float2 *rs = (float2 *)ws_alloc(ctx, fb, 27), *ps = (float2 *)ws_alloc(ctx, fb, 28),
-           *xs = (float2 *)ws_alloc(ctx, fb, 29), *ts = (float2 *)ws_alloc(ctx, fb, 30),
-           *Ts = (float2 *)ws_alloc(ctx, fb, 31);
+    const size_t sb = Store<S>::bytes(g.Vh);
+    float2 *rs = (float2 *)ws_alloc(ctx, fb, 27), *xs = (float2 *)ws_alloc(ctx, fb, 29);
+    void *pb = ws_alloc(ctx, sb, 28), *tb = ws_alloc(ctx, sb, 30), *Tb = ws_alloc(ctx, sb, 31);
     double *part_a = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64), 9);
     double *part_b = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64), 10);
-    if (!Kx || !te || !to || !rs || !ps || !xs || !ts || !Ts || !part_a || !part_b)
+    if (!Kx || !te || !to || !rs || !xs || !pb || !tb || !Tb || !part_a || !part_b)
         return set_err(ctx, PFMP_ERR_OOM, "mixed solver workspace");
+    S ps = Store<S>::make(pb, g.Vh), ts = Store<S>::make(tb, g.Vh), Ts = Store<S>::make(Tb, g.Vh);
     const double2 *b = (const double2 *)b_;
     double2 *x = (double2 *)x_;
     double *sc = ctx->scal + kMixBase;
@@ -187,9 +212,10 @@ int cg_solve_mixed(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfmp_s
     if ((rc = launch_norm2(ctx, b, n, ctx->red))) return rc;
     if ((rc = red_finish(ctx, ctx->red, ctx->nblk_red, 1, &bb))) return rc;
     const double tol2bb = prm->tol * prm->tol * bb;
-    // r = b, rs = ps = (float) b
-    hipLaunchKernelGGL(k_m_residual, dim3(ctx->nblk_red), dim3(kRedBlock), 0, ctx->stream, n, b, Kx, rs, ps, 1,
-                       ctx->red);
+    // r = b, rs = (float) b, p = rs
+    hipLaunchKernelGGL(k_m_residual, dim3(ctx->nblk_red), dim3(kRedBlock), 0, ctx->stream, n, b, Kx, rs, ctx->red);
+    hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
+                       nullptr);
     hipLaunchKernelGGL(k_m_restart, dim3(1), dim3(kRedBlock), 0, ctx->stream, ctx->red, ctx->nblk_red, tol2bb,
                        delta * delta, prm->maxiter, 1, sc);
     LAUNCHCHK(ctx);
@@ -198,22 +224,25 @@ int cg_solve_mixed(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfmp_s
     double h[16], res = 0;
     for (;;) {
         for (int k = 0; k < chunk; k++) {
-            if ((rc = launch_clovinv<float2, float>(ctx, 1, ps, ctx->Uf, s.clovf[1], Ts, 1.f, 1.f, cl, sc + M_DONE)))
+            if ((rc = launch_clovinv<float2, float, In, S>(ctx, 1, ps, ctx->Uf, s.clovf[1], Ts, 1.f, 1.f, cl,
+                                                            sc + M_DONE)))
                 return rc;
-            if ((rc = launch_xpay<float2, float>(ctx, 0, ps, Ts, ctx->Uf, s.clovf[0], mk2, ts, 1.f, cl, part_a,
-                                                  sc + M_DONE)))
+            if ((rc = launch_xpay<float2, float, In, In, S>(ctx, 0, ps, Ts, ctx->Uf, s.clovf[0], mk2, ts, 1.f, cl,
+                                                             part_a, sc + M_DONE)))
                 return rc;
             hipLaunchKernelGGL(k_m_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_a, nb, sc);
-            if ((rc = launch_clovinv<float2, float>(ctx, 1, ts, ctx->Uf, s.clovf[1], Ts, -1.f, 1.f, cl, sc + M_DONE)))
+            if ((rc = launch_clovinv<float2, float, In, S>(ctx, 1, ts, ctx->Uf, s.clovf[1], Ts, -1.f, 1.f, cl,
+                                                            sc + M_DONE)))
                 return rc;
             if (cl)
-                hipLaunchKernelGGL((k_m_hop4<1>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,
+                hipLaunchKernelGGL((k_m_hop4<1, In>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,
                                    s.clovf[0], mk2, ps, xs, rs, sc, part_b);
             else
-                hipLaunchKernelGGL((k_m_hop4<0>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,
+                hipLaunchKernelGGL((k_m_hop4<0, In>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,
                                    s.clovf[0], mk2, ps, xs, rs, sc, part_b);
             hipLaunchKernelGGL(k_m_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, sc);
-            hipLaunchKernelGGL(k_m_update_p, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, rs, ps, sc);
+            hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
+                               sc);
             LAUNCHCHK(ctx);
         }
         HIPCHK(ctx, hipMemcpyAsync(ctx->red_host, sc, sizeof(double) * 16, hipMemcpyDeviceToHost, ctx->stream));
@@ -225,7 +254,7 @@ int cg_solve_mixed(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfmp_s
         if ((rc = op_apply_K(ctx, op, x, Kx, te, to, nullptr))) return rc;
         kmults++;
         updates++;
-        hipLaunchKernelGGL(k_m_residual, dim3(ctx->nblk_red), dim3(kRedBlock), 0, ctx->stream, n, b, Kx, rs, ps, 0,
+        hipLaunchKernelGGL(k_m_residual, dim3(ctx->nblk_red), dim3(kRedBlock), 0, ctx->stream, n, b, Kx, rs,
                            ctx->red);
         double rr;
         if ((rc = red_finish(ctx, ctx->red, ctx->nblk_red, 1, &rr))) return rc;
@@ -233,6 +262,8 @@ int cg_solve_mixed(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfmp_s
         if (rr <= tol2bb || h[M_DONE] == 2) break;
         hipLaunchKernelGGL(k_m_restart, dim3(1), dim3(kRedBlock), 0, ctx->stream, ctx->red, ctx->nblk_red, tol2bb,
                            delta * delta, prm->maxiter, 0, sc);
+        hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
+                           sc);
         LAUNCHCHK(ctx);
     }
     auto t1 = std::chrono::steady_clock::now();
@@ -245,4 +276,11 @@ int cg_solve_mixed(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfmp_s
     }
     if (!(res <= prm->tol)) return set_err(ctx, PFMP_ERR_NOCONV, "cg_solve (mixed): maxiter reached");
     return 0;
+}
+
+int cg_solve_mixed(pfmp_ctx *ctx, int op, const void *b, void *x, const pfmp_solver_params *p, pfmp_solver_stats *st)
+{
+    if (p->prec == PFMP_F32) return mixed_impl<float2 *>(ctx, op, b, x, p, st);
+    if (p->prec == PFMP_F16) return mixed_impl<HalfField>(ctx, op, b, x, p, st);
+    return set_err(ctx, PFMP_ERR_ARG, "cg_solve: unsupported precision");
 }

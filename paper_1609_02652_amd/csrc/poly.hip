@@ -17,8 +17,8 @@ __global__ __launch_bounds__(kBlock) void k_poly_last(Geom g, const double2 *__r
                                                       const double2 *__restrict__ src, double2 z,
                                                       double2 *__restrict__ dst)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.Vh) return;
+    int i = xcd_site(g.Vh);
+    if (i < 0) return;
     double2 acc[12], tv[12], at[12];
     hop_all<double2>(g, 0, i, T, U, 1.0, acc);
     load_spinor(t, g.Vh, i, -1.0, tv);
@@ -50,8 +50,8 @@ int poly_factor(pfmp_ctx *ctx, int op, const double2 *src, double2 z, double2 *d
     const double mk2 = -s.kappa * s.kappa;
     int rc = op_apply_M(ctx, op, 0, src, te, to, nullptr);
     if (rc) return rc;
-    if ((rc = launch_clovinv<double2, double>(ctx, 1, te, ctx->U, s.clov[1], to, -1.0, 1.0, cl, nullptr))) return rc;
-    dim3 grid(nblocks(ctx->g.Vh, kBlock)), block(kBlock);
+    if ((rc = clovinv64(ctx, 1, te, s.clov[1], to, -1.0, 1.0, cl, nullptr))) return rc;
+    dim3 grid(nblocks_site(ctx->g.Vh)), block(kBlock);
     if (cl)
         hipLaunchKernelGGL((k_poly_last<1>), grid, block, 0, ctx->stream, ctx->g, te, to, ctx->U, s.clov[0], mk2, src,
                            z, dst);

@@ -1,0 +1,614 @@
+// ptnet.hip -- learned gauge-covariant preconditioner for a flexible CG.
+//
+// Network (2 parallel-transport convolution layers, 12 complex colour-vector
+// hidden channels; FP32 weights and arithmetic, FP32 activations):
+//   rhat = r / |r|                                   (4 channels: the spin components)
+//   h_c(y) = sum_d sum_c' W1[d][c][c'] T_d(y) rhat_c'(y + d)      odd y
+//   g_c    = h_c / (1 + |h_c|^2)                                  (gauge-covariant gate)
+//   z_c(x) = sum_d sum_c' W2[d][c][c'] T_d(x) g_c'(x + d) + sum_c' W0[c][c'] rhat_c'(x)   even x
+//   N(r)   = |r| z
+// d = 2 mu (+mu) / 2 mu + 1 (-mu); T_d the hop's transporter with the fermion
+// boundary factor.  Weights: complex [W1 8x12x4 | W2 8x4x12 | W0 4x4] = 784 entries.
+// Training minimises sum_pairs |z(rhat) - e/|r||^2 / |e/|r||^2 over (r, e) pairs with
+// Khat e = r; dL = 2 Re sum_w A_w dw and the kernels return the A_w.
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "hop.h"
+
+namespace {
+
+constexpr int NIN = 4, NH = 12, NW1 = 8 * NH * NIN, NW2 = 8 * NIN * NH, NW0 = NIN * NIN;
+constexpr int NW = NW1 + NW2 + NW0;   // 784
+
+__device__ __forceinline__ float2 fconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// T_d(y) v (dag = 0) or T_d(y)^dag v (dag = 1) for the site y with coordinates c
+template <int DAG>
+__device__ __forceinline__ void transport(const Geom &g, const float2 *__restrict__ U, int p, int i, const int *c,
+                                          int d, const float2 *v, float2 *w)
+{
+    const int mu = d >> 1;
+    float2 u[9];
+    float sgn;
+    if ((d & 1) == 0) {
+        const float2 *b = U + ((long)(p * 4 + mu) * 9) * g.Vh + i;
+        for (int k = 0; k < 9; k++) u[k] = b[(long)k * g.Vh];
+        sgn = (mu == 3 && c[3] == g.L[3] - 1) ? (float)g.tbc : 1.f;
+    } else {
+        int s;
+        int j = eo_neighbour(g, c, mu, -1, &s);
+        const float2 *b = U + ((long)((1 - p) * 4 + mu) * 9) * g.Vh + j;
+        // T = U_mu(y - mu)^dag: u holds its conjugate transpose
+        for (int a = 0; a < 3; a++)
+            for (int bb = 0; bb < 3; bb++) u[3 * a + bb] = fconj(b[(long)(3 * bb + a) * g.Vh]);
+        sgn = (float)s;
+    }
+    for (int a = 0; a < 3; a++) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int bb = 0; bb < 3; bb++) {
+            if (DAG) cfmac(acc, u[3 * bb + a], v[bb]);
+            else cfma(acc, u[3 * a + bb], v[bb]);
+        }
+        w[a] = make_float2(acc.x * sgn, acc.y * sgn);
+    }
+}
+
+__device__ __forceinline__ int nbr_of(const Geom &g, const int *c, int d)
+{
+    int s;
+    return eo_neighbour(g, c, d >> 1, (d & 1) ? -1 : +1, &s);
+}
+
+// layer 1 on odd sites: h (pre-gate) and g (gated), [36][Vh] float2 each
+__global__ __launch_bounds__(kBlock) void k_pt_l1(Geom g, const float2 *__restrict__ U,
+                                                  const double2 *__restrict__ r, float scale,
+                                                  const float2 *__restrict__ W, float2 *__restrict__ H,
+                                                  float2 *__restrict__ G)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.Vh) return;
+    int c[4];
+    eo_coords(g, 1, i, c);
+    float2 h[NH * 3];
+    for (int k = 0; k < NH * 3; k++) h[k] = make_float2(0.f, 0.f);
+    for (int d = 0; d < 8; d++) {
+        int j = nbr_of(g, c, d);
+        float2 t[NIN * 3];
+        for (int ch = 0; ch < NIN; ch++) {
+            float2 v[3];
+            for (int a = 0; a < 3; a++) {
+                double2 x = r[(long)(3 * ch + a) * g.Vh + j];
+                v[a] = make_float2((float)x.x * scale, (float)x.y * scale);
+            }
+            transport<0>(g, U, 1, i, c, d, v, t + 3 * ch);
+        }
+        const float2 *w = W + d * NH * NIN;
+        for (int o = 0; o < NH; o++)
+            for (int ch = 0; ch < NIN; ch++) {
+                float2 wc = w[o * NIN + ch];
+                for (int a = 0; a < 3; a++) cfma(h[3 * o + a], wc, t[3 * ch + a]);
+            }
+    }
+    for (int o = 0; o < NH; o++) {
+        float q = 0.f;
+        for (int a = 0; a < 3; a++) q += h[3 * o + a].x * h[3 * o + a].x + h[3 * o + a].y * h[3 * o + a].y;
+        float s = 1.f / (1.f + q);
+        for (int a = 0; a < 3; a++) {
+            if (H) H[(long)(3 * o + a) * g.Vh + i] = h[3 * o + a];
+            G[(long)(3 * o + a) * g.Vh + i] = make_float2(h[3 * o + a].x * s, h[3 * o + a].y * s);
+        }
+    }
+}
+
+// layer 2 on even sites: z = conv(g) + W0 rhat; out (FP64) = oscale * z, or z (FP32)
+__global__ __launch_bounds__(kBlock) void k_pt_l2(Geom g, const float2 *__restrict__ U,
+                                                  const double2 *__restrict__ r, float scale,
+                                                  const float2 *__restrict__ W, const float2 *__restrict__ G,
+                                                  double oscale, double2 *__restrict__ out, float2 *__restrict__ zf)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.Vh) return;
+    int c[4];
+    eo_coords(g, 0, i, c);
+    float2 z[NIN * 3];
+    const float2 *W2 = W + NW1, *W0 = W + NW1 + NW2;
+    for (int o = 0; o < NIN; o++)
+        for (int a = 0; a < 3; a++) {
+            float2 acc = make_float2(0.f, 0.f);
+            for (int ch = 0; ch < NIN; ch++) {
+                double2 x = r[(long)(3 * ch + a) * g.Vh + i];
+                cfma(acc, W0[o * NIN + ch], make_float2((float)x.x * scale, (float)x.y * scale));
+            }
+            z[3 * o + a] = acc;
+        }
+    for (int d = 0; d < 8; d++) {
+        int j = nbr_of(g, c, d);
+        const float2 *w = W2 + d * NIN * NH;
+        for (int ch = 0; ch < NH; ch++) {
+            float2 v[3], t[3];
+            for (int a = 0; a < 3; a++) v[a] = G[(long)(3 * ch + a) * g.Vh + j];
+            transport<0>(g, U, 0, i, c, d, v, t);
+            for (int o = 0; o < NIN; o++) {
+                float2 wc = w[o * NH + ch];
+                for (int a = 0; a < 3; a++) cfma(z[3 * o + a], wc, t[a]);
+            }
+        }
+    }
+    for (int k = 0; k < NIN * 3; k++) {
+        if (out) out[(long)k * g.Vh + i] = make_double2(oscale * z[k].x, oscale * z[k].y);
+        if (zf) zf[(long)k * g.Vh + i] = z[k];
+    }
+}
+
+// Gz = (z - e * escale) * inv_ne on even sites (FP32), and the pair's loss partials
+__global__ __launch_bounds__(kBlock) void k_pt_gz(Geom g, const float2 *__restrict__ z,
+                                                  const double2 *__restrict__ e, float escale, float inv_ne,
+                                                  float2 *__restrict__ Gz, double *__restrict__ partials)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0;
+    if (i < g.Vh)
+        for (int k = 0; k < 12; k++) {
+            double2 ev = e[(long)k * g.Vh + i];
+            float2 d = make_float2(z[(long)k * g.Vh + i].x - (float)ev.x * escale,
+                                   z[(long)k * g.Vh + i].y - (float)ev.y * escale);
+            s += (double)d.x * d.x + (double)d.y * d.y;
+            Gz[(long)k * g.Vh + i] = make_float2(d.x * inv_ne, d.y * inv_ne);
+        }
+    block_sum_store<float2>(s * inv_ne, partials);
+}
+
+// wave-level partial of (re, im) into part[wave * stride + 2 idx]
+__device__ __forceinline__ void wave_partial(float2 v, double *part, long stride, int idx)
+{
+    double re = v.x, im = v.y;
+    for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_down(re, o, 64);
+        im += __shfl_down(im, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        long w = (blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6;
+        part[w * stride + 2 * idx] = re;
+        part[w * stride + 2 * idx + 1] = im;
+    }
+}
+
+// A2[d][o][ch] = sum_x <Gz_o(x), T_d(x) g_ch(x + d)>, A0[o][ch] = sum_x <Gz_o(x), rhat_ch(x)> (even x)
+__global__ __launch_bounds__(kBlock) void k_pt_grad2(Geom g, const float2 *__restrict__ U,
+                                                     const double2 *__restrict__ r, float scale,
+                                                     const float2 *__restrict__ G, const float2 *__restrict__ Gz,
+                                                     double *__restrict__ part)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = i < g.Vh;
+    int c[4] = {0, 0, 0, 0};
+    float2 gz[NIN * 3];
+    if (ok) {
+        eo_coords(g, 0, i, c);
+        for (int k = 0; k < 12; k++) gz[k] = Gz[(long)k * g.Vh + i];
+    } else {
+        for (int k = 0; k < 12; k++) gz[k] = make_float2(0.f, 0.f);
+    }
+    const long stride = 2L * (NW2 + NW0);
+    for (int d = 0; d < 8; d++) {
+        int j = ok ? nbr_of(g, c, d) : 0;
+        for (int ch = 0; ch < NH; ch++) {
+            float2 t[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+            if (ok) {
+                float2 v[3];
+                for (int a = 0; a < 3; a++) v[a] = G[(long)(3 * ch + a) * g.Vh + j];
+                transport<0>(g, U, 0, i, c, d, v, t);
+            }
+            for (int o = 0; o < NIN; o++) {
+                float2 acc = make_float2(0.f, 0.f);
+                for (int a = 0; a < 3; a++) cfmac(acc, gz[3 * o + a], t[a]);
+                wave_partial(acc, part, stride, (d * NIN + o) * NH + ch);
+            }
+        }
+    }
+    for (int o = 0; o < NIN; o++)
+        for (int ch = 0; ch < NIN; ch++) {
+            float2 acc = make_float2(0.f, 0.f);
+            if (ok)
+                for (int a = 0; a < 3; a++) {
+                    double2 x = r[(long)(3 * ch + a) * g.Vh + i];
+                    cfmac(acc, gz[3 * o + a], make_float2((float)x.x * scale, (float)x.y * scale));
+                }
+            wave_partial(acc, part, stride, NW2 + o * NIN + ch);
+        }
+}
+
+// back to the hidden layer on odd y: Gg(y) = sum_d W2[opp d]^dag T_d(y) Gz(y + d), then
+// the gate: Gh = s Gg + 2 s' Re<Gg, h> h, s = 1/(1+q), s' = -1/(1+q)^2, q = |h|^2
+__global__ __launch_bounds__(kBlock) void k_pt_back(Geom g, const float2 *__restrict__ U,
+                                                    const float2 *__restrict__ W, const float2 *__restrict__ Gz,
+                                                    const float2 *__restrict__ H, float2 *__restrict__ Gh)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.Vh) return;
+    int c[4];
+    eo_coords(g, 1, i, c);
+    const float2 *W2 = W + NW1;
+    float2 gg[NH * 3];
+    for (int k = 0; k < NH * 3; k++) gg[k] = make_float2(0.f, 0.f);
+    for (int d = 0; d < 8; d++) {
+        int j = nbr_of(g, c, d);
+        const int od = d ^ 1;
+        const float2 *w = W2 + od * NIN * NH;
+        for (int o = 0; o < NIN; o++) {
+            float2 v[3], t[3];
+            for (int a = 0; a < 3; a++) v[a] = Gz[(long)(3 * o + a) * g.Vh + j];
+            transport<0>(g, U, 1, i, c, d, v, t);
+            for (int ch = 0; ch < NH; ch++) {
+                float2 wc = fconj(w[o * NH + ch]);
+                for (int a = 0; a < 3; a++) cfma(gg[3 * ch + a], wc, t[a]);
+            }
+        }
+    }
+    for (int ch = 0; ch < NH; ch++) {
+        float2 h[3];
+        float q = 0.f, re = 0.f;
+        for (int a = 0; a < 3; a++) {
+            h[a] = H[(long)(3 * ch + a) * g.Vh + i];
+            q += h[a].x * h[a].x + h[a].y * h[a].y;
+            re += gg[3 * ch + a].x * h[a].x + gg[3 * ch + a].y * h[a].y;
+        }
+        float s = 1.f / (1.f + q), ds = -s * s;
+        for (int a = 0; a < 3; a++)
+            Gh[(long)(3 * ch + a) * g.Vh + i] = make_float2(s * gg[3 * ch + a].x + 2.f * ds * re * h[a].x,
+                                                            s * gg[3 * ch + a].y + 2.f * ds * re * h[a].y);
+    }
+}
+
+// A1[d][o][ch] = sum_y <Gh_o(y), T_d(y) rhat_ch(y + d)> (odd y)
+__global__ __launch_bounds__(kBlock) void k_pt_grad1(Geom g, const float2 *__restrict__ U,
+                                                     const double2 *__restrict__ r, float scale,
+                                                     const float2 *__restrict__ Gh, double *__restrict__ part)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = i < g.Vh;
+    int c[4] = {0, 0, 0, 0};
+    if (ok) eo_coords(g, 1, i, c);
+    const long stride = 2L * NW1;
+    for (int d = 0; d < 8; d++) {
+        int j = ok ? nbr_of(g, c, d) : 0;
+        float2 t[NIN * 3];
+        for (int ch = 0; ch < NIN; ch++) {
+            float2 v[3];
+            for (int a = 0; a < 3; a++) {
+                double2 x = ok ? r[(long)(3 * ch + a) * g.Vh + j] : make_double2(0, 0);
+                v[a] = make_float2((float)x.x * scale, (float)x.y * scale);
+            }
+            if (ok) transport<0>(g, U, 1, i, c, d, v, t + 3 * ch);
+            else for (int a = 0; a < 3; a++) t[3 * ch + a] = make_float2(0.f, 0.f);
+        }
+        for (int o = 0; o < NH; o++) {
+            float2 gh[3];
+            for (int a = 0; a < 3; a++) gh[a] = ok ? Gh[(long)(3 * o + a) * g.Vh + i] : make_float2(0.f, 0.f);
+            for (int ch = 0; ch < NIN; ch++) {
+                float2 acc = make_float2(0.f, 0.f);
+                for (int a = 0; a < 3; a++) cfmac(acc, gh[a], t[3 * ch + a]);
+                wave_partial(acc, part, stride, (d * NH + o) * NIN + ch);
+            }
+        }
+    }
+}
+
+// out[v] = sum_w part[w * nvals + v] in fixed order, one thread per value
+__global__ void k_pt_sum(const double *__restrict__ part, long nw, int nvals, double *__restrict__ out)
+{
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvals) return;
+    double s = 0;
+    for (long w = 0; w < nw; w++) s += part[w * nvals + v];
+    out[v] = s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side
+
+struct PtWs {
+    float2 *W, *H, *G, *Gz, *Gh, *z;
+    double *part, *sum;
+};
+
+static int pt_ws(pfmp_ctx *ctx, const double *Wc, PtWs &w)
+{
+    const Geom &g = ctx->g;
+    const size_t hb = sizeof(float2) * 36L * g.Vh, zb = sizeof(float2) * 12L * g.Vh;
+    const long nwaves = (long)nblocks(g.Vh, kBlock) * (kBlock / 64);
+    const long per_wave = 2L * (NW2 + NW0) > 2L * NW1 ? 2L * (NW2 + NW0) : 2L * NW1;
+    w.W = (float2 *)ws_alloc(ctx, sizeof(float2) * NW, 32);
+    w.H = (float2 *)ws_alloc(ctx, hb, 34);
+    w.G = (float2 *)ws_alloc(ctx, hb, 35);
+    w.Gh = (float2 *)ws_alloc(ctx, hb, 36);
+    w.Gz = (float2 *)ws_alloc(ctx, zb, 37);
+    w.z = (float2 *)ws_alloc(ctx, zb, 38);
+    w.part = (double *)ws_alloc(ctx, sizeof(double) * (nwaves * per_wave + 64), 33);
+    w.sum = (double *)(ctx->scal + 6000);   // 2 * (NW2 + NW0) <= 800 doubles
+    if (!w.W || !w.H || !w.G || !w.Gh || !w.Gz || !w.z || !w.part) return set_err(ctx, PFMP_ERR_OOM, "ptnet workspace");
+    if (Wc) {
+        std::vector<float2> wf(NW);
+        for (int k = 0; k < NW; k++) wf[k] = make_float2((float)Wc[2 * k], (float)Wc[2 * k + 1]);
+        HIPCHK(ctx, hipMemcpyAsync(w.W, wf.data(), sizeof(float2) * NW, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return 0;
+}
+
+static double host_norm(pfmp_ctx *ctx, const double2 *v, int *rc)
+{
+    double s = 0;
+    *rc = launch_norm2(ctx, v, 12L * ctx->g.Vh, ctx->red);
+    if (!*rc) *rc = red_finish(ctx, ctx->red, ctx->nblk_red, 1, &s);
+    return std::sqrt(s);
+}
+
+// out = N(r) with r of norm nr (given) in FP64 internal layout
+static int pt_apply(pfmp_ctx *ctx, PtWs &w, const double2 *r, double nr, double2 *out)
+{
+    const Geom &g = ctx->g;
+    float sc = nr > 0 ? (float)(1.0 / nr) : 0.f;
+    dim3 grid(nblocks(g.Vh, kBlock)), block(kBlock);
+    hipLaunchKernelGGL(k_pt_l1, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, (float2 *)nullptr, w.G);
+    hipLaunchKernelGGL(k_pt_l2, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, w.G, nr, out,
+                       (float2 *)nullptr);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_ptnet_apply(pfmp_ctx *ctx, const double *W, const void *r, void *out)
+{
+    if (!ctx || !W || !r || !out) return ctx ? set_err(ctx, PFMP_ERR_ARG, "ptnet_apply: null") : PFMP_ERR_ARG;
+    if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
+    PtWs w;
+    int rc = pt_ws(ctx, W, w);
+    if (rc) return rc;
+    double nr = host_norm(ctx, (const double2 *)r, &rc);
+    if (rc) return rc;
+    return pt_apply(ctx, w, (const double2 *)r, nr, (double2 *)out);
+}
+
+extern "C" int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int npairs, const void *const *R, const void *const *E,
+                               double *loss, double *A)
+{
+    if (!ctx || !W || npairs <= 0 || !R || !E || !loss || !A)
+        return ctx ? set_err(ctx, PFMP_ERR_ARG, "ptnet_grad: bad arguments") : PFMP_ERR_ARG;
+    if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
+    const Geom &g = ctx->g;
+    PtWs w;
+    int rc = pt_ws(ctx, W, w);
+    if (rc) return rc;
+    dim3 grid(nblocks(g.Vh, kBlock)), block(kBlock);
+    const long nwaves = (long)grid.x * (kBlock / 64);
+    std::vector<double> acc(2 * NW, 0.0);
+    double tot = 0;
+    std::vector<double> tmp(2 * NW1);
+    for (int p = 0; p < npairs; p++) {
+        const double2 *r = (const double2 *)R[p], *e = (const double2 *)E[p];
+        double nr = host_norm(ctx, r, &rc);
+        if (rc) return rc;
+        double ne = host_norm(ctx, e, &rc);
+        if (rc) return rc;
+        float sc = (float)(1.0 / nr);
+        double neh = (ne / nr) * (ne / nr);
+        hipLaunchKernelGGL(k_pt_l1, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, w.H, w.G);
+        hipLaunchKernelGGL(k_pt_l2, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, w.G, 1.0,
+                           (double2 *)nullptr, w.z);
+        hipLaunchKernelGGL(k_pt_gz, grid, block, 0, ctx->stream, g, w.z, e, sc, (float)(1.0 / neh), w.Gz, ctx->red);
+        LAUNCHCHK(ctx);
+        double lp;
+        if ((rc = red_finish(ctx, ctx->red, grid.x, 1, &lp))) return rc;
+        tot += lp;
+        // A2 and A0
+        hipLaunchKernelGGL(k_pt_grad2, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.G, w.Gz, w.part);
+        hipLaunchKernelGGL(k_pt_sum, dim3(nblocks(2 * (NW2 + NW0), 256)), dim3(256), 0, ctx->stream, w.part, nwaves,
+                           2 * (NW2 + NW0), w.sum);
+        LAUNCHCHK(ctx);
+        HIPCHK(ctx, hipMemcpyAsync(tmp.data(), w.sum, sizeof(double) * 2 * (NW2 + NW0), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        for (int k = 0; k < 2 * (NW2 + NW0); k++) acc[2 * NW1 + k] += tmp[k];
+        // back through layer 2 and the gate, then A1
+        hipLaunchKernelGGL(k_pt_back, grid, block, 0, ctx->stream, g, ctx->Uf, w.W, w.Gz, w.H, w.Gh);
+        hipLaunchKernelGGL(k_pt_grad1, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.Gh, w.part);
+        hipLaunchKernelGGL(k_pt_sum, dim3(nblocks(2 * NW1, 256)), dim3(256), 0, ctx->stream, w.part, nwaves, 2 * NW1,
+                           w.sum);
+        LAUNCHCHK(ctx);
+        HIPCHK(ctx, hipMemcpyAsync(tmp.data(), w.sum, sizeof(double) * 2 * NW1, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        for (int k = 0; k < 2 * NW1; k++) acc[k] += tmp[k];
+    }
+    *loss = tot;
+    for (int k = 0; k < 2 * NW; k++) A[k] = acc[k];
+    return 0;
+}
+
+// Adam on the real and imaginary parts of the weights, gradient 2 conj(A) from
+// pfmp_ptnet_grad over all pairs each step; W updated in place, losses[step] filled.
+extern "C" int pfmp_ptnet_train(pfmp_ctx *ctx, double *W, int npairs, const void *const *R, const void *const *E,
+                                int steps, double lr, double *losses)
+{
+    if (!ctx || !W || steps <= 0 || !(lr > 0)) return ctx ? set_err(ctx, PFMP_ERR_ARG, "ptnet_train") : PFMP_ERR_ARG;
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    std::vector<double> m(2 * NW, 0.0), v(2 * NW, 0.0), A(2 * NW);
+    for (int s = 0; s < steps; s++) {
+        double loss;
+        int rc = pfmp_ptnet_grad(ctx, W, npairs, R, E, &loss, A.data());
+        if (rc) return rc;
+        if (losses) losses[s] = loss;
+        const double c1 = 1 - std::pow(b1, s + 1), c2 = 1 - std::pow(b2, s + 1);
+        for (int k = 0; k < NW; k++) {
+            // dL/dRe w = 2 Re A, dL/dIm w = -2 Im A
+            double gr[2] = {2 * A[2 * k], -2 * A[2 * k + 1]};
+            for (int q = 0; q < 2; q++) {
+                int j = 2 * k + q;
+                m[j] = b1 * m[j] + (1 - b1) * gr[q];
+                v[j] = b2 * v[j] + (1 - b2) * gr[q] * gr[q];
+                W[j] -= lr * (m[j] / c1) / (std::sqrt(v[j] / c2) + eps);
+            }
+        }
+    }
+    return 0;
+}
+
+// Flexible CG on Khat with the network as preconditioner (W = NULL: identity, i.e.
+// CG written in the flexible form).  beta = <z+, r+ - r> / <z, r> (Polak-Ribiere).
+extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void *b_, void *x_,
+                              const pfmp_solver_params *prm, pfmp_solver_stats *st)
+{
+    if (!ctx || !b_ || !x_ || !prm || !(prm->tol > 0) || prm->maxiter <= 0)
+        return ctx ? set_err(ctx, PFMP_ERR_ARG, "fcg_solve: bad arguments") : PFMP_ERR_ARG;
+    if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
+        return set_err(ctx, PFMP_ERR_STATE, "fcg_solve: operator not configured");
+    auto t0 = std::chrono::steady_clock::now();
+    const Geom &g = ctx->g;
+    const long n = 12L * g.Vh;
+    const size_t vb = sizeof(double) * spinor_reals(g);
+    PtWs w{};
+    int rc;
+    if (W && (rc = pt_ws(ctx, W, w))) return rc;
+    double2 *r = pool_get(ctx, 2010), *ro = pool_get(ctx, 2011), *z = pool_get(ctx, 2012), *p = pool_get(ctx, 2013),
+            *q = pool_get(ctx, 2014), *te = pool_get(ctx, 2015), *to = pool_get(ctx, 2016);
+    if (!r || !ro || !z || !p || !q || !te || !to) return set_err(ctx, PFMP_ERR_OOM, "fcg workspace");
+    const double2 *b = (const double2 *)b_;
+    double2 *x = (double2 *)x_;
+    HIPCHK(ctx, hipMemsetAsync(x, 0, vb, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    double bn = host_norm(ctx, b, &rc);
+    if (rc) return rc;
+    auto precond = [&](const double2 *in, double nin, double2 *out) -> int {
+        if (!W) {
+            HIPCHK(ctx, hipMemcpyAsync(out, in, vb, hipMemcpyDeviceToDevice, ctx->stream));
+            return 0;
+        }
+        return pt_apply(ctx, w, in, nin, out);
+    };
+    auto dot = [&](const double2 *a, const double2 *bb, double *re) -> int {
+        double d[2];
+        int e = launch_dot(ctx, a, bb, n, ctx->red);
+        if (!e) e = red_finish(ctx, ctx->red, ctx->nblk_red, 2, d);
+        *re = d[0];
+        return e;
+    };
+    auto axpy = [&](double a, const double2 *xx, double bcoef, double2 *yy) -> int {
+        double al[2] = {a, 0}, be[2] = {bcoef, 0};
+        return pfmp_axpby(ctx, al, xx, be, yy);
+    };
+    double rn = bn;
+    int fallbacks = 0;
+    if ((rc = precond(r, rn, z))) return rc;
+    double rz;
+    if ((rc = dot(r, z, &rz))) return rc;
+    if (!(rz > 0)) {   // not a descent direction: plain CG step
+        HIPCHK(ctx, hipMemcpyAsync(z, r, vb, hipMemcpyDeviceToDevice, ctx->stream));
+        rz = rn * rn;
+        fallbacks++;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(p, z, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    int k = 0;
+    const int nb = nblocks_site(g.Vh);
+    double *part = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64), 9);
+    if (!part) return set_err(ctx, PFMP_ERR_OOM, "fcg workspace");
+    while (rn > prm->tol * bn && k < prm->maxiter) {
+        if ((rc = op_apply_K(ctx, op, p, q, te, to, part))) return rc;
+        double pq;
+        if ((rc = red_finish(ctx, part, nb, 1, &pq))) return rc;
+        double alpha = rz / pq;
+        if ((rc = axpy(alpha, p, 1.0, x))) return rc;
+        HIPCHK(ctx, hipMemcpyAsync(ro, r, vb, hipMemcpyDeviceToDevice, ctx->stream));
+        if ((rc = axpy(-alpha, q, 1.0, r))) return rc;
+        rn = host_norm(ctx, r, &rc);
+        if (rc) return rc;
+        k++;
+        if (rn <= prm->tol * bn) break;
+        if ((rc = precond(r, rn, z))) return rc;
+        double zr, zro, beta;
+        if ((rc = dot(z, r, &zr))) return rc;
+        if (zr > 0) {
+            if ((rc = dot(z, ro, &zro))) return rc;
+            beta = (zr - zro) / rz;
+        } else {   // fallback: z = r, restart the direction
+            HIPCHK(ctx, hipMemcpyAsync(z, r, vb, hipMemcpyDeviceToDevice, ctx->stream));
+            zr = rn * rn;
+            beta = 0.0;
+            fallbacks++;
+        }
+        rz = zr;
+        if ((rc = axpy(1.0, z, beta, p))) return rc;
+    }
+    // FP64 true residual
+    if ((rc = op_apply_K(ctx, op, x, q, te, to, nullptr))) return rc;
+    HIPCHK(ctx, hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    if ((rc = axpy(-1.0, q, 1.0, r))) return rc;
+    double tr = host_norm(ctx, r, &rc);
+    if (rc) return rc;
+    auto t1 = std::chrono::steady_clock::now();
+    if (st) {
+        st->iters = k;
+        st->reliable_updates = fallbacks;   // plain-CG fallback steps of the flexible CG
+        st->true_res = bn > 0 ? tr / bn : 0;
+        st->seconds = std::chrono::duration<double>(t1 - t0).count();
+        st->kmults = k + 1;
+    }
+    if (!(tr <= prm->tol * bn)) return set_err(ctx, PFMP_ERR_NOCONV, "fcg_solve: maxiter reached");
+    return 0;
+}
+
+// CG on Khat recording (x_k, r_k) at the requested iterations (ascending), so that
+// training pairs (r_k, e_k = x - x_k) can be formed once the solve has converged.
+// Host-driven textbook CG in FP64; returns the number of snapshots taken.
+extern "C" int pfmp_cg_harvest(pfmp_ctx *ctx, int op, const void *b_, void *x_, double tol, int maxiter, int nsnap,
+                               const int *snap_iters, void *const *snap_x, void *const *snap_r, int *ntaken)
+{
+    if (!ctx || !b_ || !x_ || (nsnap > 0 && (!snap_iters || !snap_x || !snap_r)) || !ntaken)
+        return ctx ? set_err(ctx, PFMP_ERR_ARG, "cg_harvest: bad arguments") : PFMP_ERR_ARG;
+    if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
+        return set_err(ctx, PFMP_ERR_STATE, "cg_harvest: operator not configured");
+    const Geom &g = ctx->g;
+    const long n = 12L * g.Vh;
+    const size_t vb = sizeof(double) * spinor_reals(g);
+    double2 *r = pool_get(ctx, 2010), *p = pool_get(ctx, 2013), *q = pool_get(ctx, 2014), *te = pool_get(ctx, 2015),
+            *to = pool_get(ctx, 2016);
+    if (!r || !p || !q || !te || !to) return set_err(ctx, PFMP_ERR_OOM, "harvest workspace");
+    const int nb = nblocks_site(g.Vh);
+    double *part = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64), 9);
+    if (!part) return set_err(ctx, PFMP_ERR_OOM, "harvest workspace");
+    const double2 *b = (const double2 *)b_;
+    double2 *x = (double2 *)x_;
+    int rc;
+    HIPCHK(ctx, hipMemsetAsync(x, 0, vb, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(p, b, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    double bn = host_norm(ctx, b, &rc);
+    if (rc) return rc;
+    double rr = bn * bn;
+    int k = 0, s = 0;
+    while (rr > tol * tol * bn * bn && k < maxiter) {
+        if (s < nsnap && snap_iters[s] == k) {
+            HIPCHK(ctx, hipMemcpyAsync(snap_x[s], x, vb, hipMemcpyDeviceToDevice, ctx->stream));
+            HIPCHK(ctx, hipMemcpyAsync(snap_r[s], r, vb, hipMemcpyDeviceToDevice, ctx->stream));
+            s++;
+        }
+        if ((rc = op_apply_K(ctx, op, p, q, te, to, part))) return rc;
+        double pq;
+        if ((rc = red_finish(ctx, part, nb, 1, &pq))) return rc;
+        double alpha = rr / pq;
+        double al[2] = {alpha, 0}, one[2] = {1, 0}, mal[2] = {-alpha, 0};
+        if ((rc = pfmp_axpby(ctx, al, p, one, x))) return rc;
+        if ((rc = pfmp_axpby(ctx, mal, q, one, r))) return rc;
+        double rn = host_norm(ctx, r, &rc);
+        if (rc) return rc;
+        double beta = rn * rn / rr;
+        rr = rn * rn;
+        double be[2] = {beta, 0};
+        if ((rc = pfmp_axpby(ctx, one, r, be, p))) return rc;
+        k++;
+    }
+    (void)n;
+    *ntaken = s;
+    return k >= maxiter ? set_err(ctx, PFMP_ERR_NOCONV, "cg_harvest: maxiter reached") : 0;
+}

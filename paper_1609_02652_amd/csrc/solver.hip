@@ -97,9 +97,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
                                                     double *__restrict__ partials)
 {
     if (st[S_DONE] != 0) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_site(g.Vh);
     double nrm = 0;
-    if (i < g.Vh) {
+    if (i >= 0) {
         double2 acc[12], tv[12], at[12];
         hop_all<double2>(g, 0, i, T, U, 1.0, acc);
         load_spinor(t, g.Vh, i, -1.0, tv);
@@ -278,7 +278,7 @@ struct CGBufs {
 static int cg_bufs(pfmp_ctx *ctx, CGBufs &B)
 {
     size_t vb = sizeof(double) * spinor_reals(ctx->g);
-    size_t pb = sizeof(double) * (nblocks(ctx->g.Vh, kBlock) + 64);
+    size_t pb = sizeof(double) * (nblocks_site(ctx->g.Vh) + 64);
     B.r = (double2 *)ws_alloc(ctx, vb, 4);
     B.p = (double2 *)ws_alloc(ctx, vb, 5);
     B.t = (double2 *)ws_alloc(ctx, vb, 6);
@@ -333,7 +333,7 @@ extern "C" int pfmp_cg_solve(pfmp_ctx *ctx, int op, const void *b_, void *x_, co
     double2 *x = (double2 *)x_;
     long n = 12L * g.Vh;
     size_t vb = sizeof(double) * spinor_reals(g);
-    int nb = nblocks(g.Vh, kBlock);
+    int nb = nblocks_site(g.Vh);
     HIPCHK(ctx, hipMemsetAsync(x, 0, vb, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(B.r, b, vb, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(B.p, b, vb, hipMemcpyDeviceToDevice, ctx->stream));
@@ -348,14 +348,14 @@ extern "C" int pfmp_cg_solve(pfmp_ctx *ctx, int op, const void *b_, void *x_, co
     for (;;) {
         for (int k = 0; k < chunk; k++) {
             // t = Mhat p, with <p, Khat p> = |t|^2 partials
-            if ((rc = launch_clovinv<double2, double>(ctx, 1, B.p, ctx->U, s.clov[1], B.T, 1.0, 1.0, cl, ctx->scal + S_DONE)))
+            if ((rc = clovinv64(ctx, 1, B.p, s.clov[1], B.T, 1.0, 1.0, cl, ctx->scal + S_DONE)))
                 return rc;
-            if ((rc = launch_xpay<double2, double>(ctx, 0, B.p, B.T, ctx->U, s.clov[0], mk2, B.t, 1.0, cl, B.part_a,
+            if ((rc = xpay64(ctx, 0, B.p, B.T, s.clov[0], mk2, B.t, 1.0, cl, B.part_a,
                                                     ctx->scal + S_DONE)))
                 return rc;
             hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_a, nb, ctx->scal);
             // T' = A_oo^-1 D_oe g5 t
-            if ((rc = launch_clovinv<double2, double>(ctx, 1, B.t, ctx->U, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE)))
+            if ((rc = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE)))
                 return rc;
             if (cl)
                 hipLaunchKernelGGL((k_cg_hop4<1>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, B.t, B.T, ctx->U,
@@ -402,7 +402,7 @@ extern "C" int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const doubl
     if ((rc = cg_bufs(ctx, B))) return rc;
     long n = 12L * g.Vh;
     size_t vb = sizeof(double) * spinor_reals(g);
-    int nb = nblocks(g.Vh, kBlock);
+    int nb = nblocks_site(g.Vh);
     double2 *pbuf = (double2 *)ws_alloc(ctx, vb * nshift, 11);
     double2 **ptrs = (double2 **)ws_alloc(ctx, sizeof(double2 *) * 2 * nshift, 12);
     double *zdev = (double *)ws_alloc(ctx, sizeof(double) * 2 * nshift, 13);
@@ -435,14 +435,14 @@ extern "C" int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const doubl
     double h[16];
     for (;;) {
         for (int k = 0; k < chunk; k++) {
-            if ((rc = launch_clovinv<double2, double>(ctx, 1, B.p, ctx->U, s.clov[1], B.T, 1.0, 1.0, cl, ctx->scal + S_DONE)))
+            if ((rc = clovinv64(ctx, 1, B.p, s.clov[1], B.T, 1.0, 1.0, cl, ctx->scal + S_DONE)))
                 return rc;
-            if ((rc = launch_xpay<double2, double>(ctx, 0, B.p, B.T, ctx->U, s.clov[0], mk2, B.t, 1.0, cl, B.part_a,
+            if ((rc = xpay64(ctx, 0, B.p, B.T, s.clov[0], mk2, B.t, 1.0, cl, B.part_a,
                                                     ctx->scal + S_DONE)))
                 return rc;
             hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_a, nb, nshift, ctx->scal,
                                rec);
-            if ((rc = launch_clovinv<double2, double>(ctx, 1, B.t, ctx->U, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE)))
+            if ((rc = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE)))
                 return rc;
             // r -= alpha Khat p (the base x is not needed; it goes to scratch)
             if (cl)

@@ -158,6 +158,13 @@ def load():
         "pfmp_hamiltonian": [vp, vp, vp, vp, vp, vp],
         "pfmp_md_evolve": [vp, vp, vp, vp, vp],
         "pfmp_trajectory": [vp, vp, vp, vp, d, vp, vp],
+        "pfmp_apply_MdagM_batch": [vp, i, vp, vp, vp],
+        "pfmp_cg_solve_batch": [vp, i, vp, vp, vp, vp, vp],
+        "pfmp_ptnet_apply": [vp, vp, vp, vp],
+        "pfmp_ptnet_grad": [vp, vp, i, vp, vp, vp, vp],
+        "pfmp_fcg_solve": [vp, i, vp, vp, vp, vp, vp],
+        "pfmp_ptnet_train": [vp, vp, i, vp, vp, i, d, vp],
+        "pfmp_cg_harvest": [vp, i, vp, vp, d, i, i, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -324,6 +331,100 @@ class Lattice:
         self._chk(self.lib.pfmp_cg_multishift(self.h, op, n, _darr(z), _ptr(b), xp, ctypes.byref(p),
                                               ctypes.byref(st)), "cg_multishift")
         return xs, st.as_dict(n)
+
+    def apply_MdagM_batch(self, ops, xs, outs=None):
+        n = len(xs)
+        outs = [self.field(zero=False) for _ in range(n)] if outs is None else outs
+        o = (ctypes.c_int * n)(*ops)
+        ip = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        op_ = (ctypes.c_void_p * n)(*[x.data_ptr() for x in outs])
+        self._chk(self.lib.pfmp_apply_MdagM_batch(self.h, n, o, ip, op_), "apply_MdagM_batch")
+        return outs
+
+    def cg_solve_batch(self, ops, bs, xs=None, tol=1e-10, maxiter=10000, check_every=0):
+        n = len(bs)
+        xs = [self.field(zero=False) for _ in range(n)] if xs is None else xs
+        o = (ctypes.c_int * n)(*ops)
+        bp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in bs])
+        xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        st = (SolverStats * n)()
+        p = self.params(tol, maxiter, F64, 0.0, check_every)
+        self._chk(self.lib.pfmp_cg_solve_batch(self.h, n, o, bp, xp, ctypes.byref(p), st), "cg_solve_batch")
+        return xs, [st[k].as_dict() for k in range(n)]
+
+    # ---------------------------------------------------------------- learned preconditioner
+    @staticmethod
+    def _weights(W):
+        """(W1, W2, W0) complex arrays -> 1568 doubles [W1 | W2 | W0]."""
+        flat = np.concatenate([np.asarray(w, np.complex128).ravel() for w in W])
+        assert flat.size == 784
+        return np.ascontiguousarray(flat.view(np.float64))
+
+    @staticmethod
+    def _unweights(a):
+        c = np.asarray(a, np.float64).view(np.complex128)
+        return c[:384].reshape(8, 12, 4), c[384:768].reshape(8, 4, 12), c[768:].reshape(4, 4)
+
+    def ptnet_apply(self, W, r, out=None):
+        out = self.field(zero=False) if out is None else out
+        w = self._weights(W)
+        self._chk(self.lib.pfmp_ptnet_apply(self.h, w.ctypes.data_as(ctypes.c_void_p), _ptr(r), _ptr(out)),
+                  "ptnet_apply")
+        return out
+
+    def ptnet_grad(self, W, pairs):
+        n = len(pairs)
+        w = self._weights(W)
+        rp = (ctypes.c_void_p * n)(*[p[0].data_ptr() for p in pairs])
+        ep = (ctypes.c_void_p * n)(*[p[1].data_ptr() for p in pairs])
+        loss = ctypes.c_double()
+        A = np.zeros(1568)
+        self._chk(self.lib.pfmp_ptnet_grad(self.h, w.ctypes.data_as(ctypes.c_void_p), n, rp, ep, ctypes.byref(loss),
+                                           A.ctypes.data_as(ctypes.c_void_p)), "ptnet_grad")
+        return loss.value, self._unweights(A)
+
+    def ptnet_train(self, W, pairs, steps, lr=1e-2):
+        """Adam in the library; returns the trained (W1, W2, W0) and the loss history."""
+        n = len(pairs)
+        w = self._weights(W).copy()
+        rp = (ctypes.c_void_p * n)(*[p[0].data_ptr() for p in pairs])
+        ep = (ctypes.c_void_p * n)(*[p[1].data_ptr() for p in pairs])
+        losses = np.zeros(steps)
+        self._chk(self.lib.pfmp_ptnet_train(self.h, w.ctypes.data_as(ctypes.c_void_p), n, rp, ep, int(steps),
+                                            float(lr), losses.ctypes.data_as(ctypes.c_void_p)), "ptnet_train")
+        return self._unweights(w), losses
+
+    def fcg_solve(self, op, W, b, x=None, tol=1e-10, maxiter=10000, check=True):
+        x = self.field(zero=False) if x is None else x
+        st = SolverStats()
+        p = self.params(tol, maxiter)
+        wp = None
+        if W is not None:
+            w = self._weights(W)
+            wp = w.ctypes.data_as(ctypes.c_void_p)
+        rc = self.lib.pfmp_fcg_solve(self.h, op, wp, _ptr(b), _ptr(x), ctypes.byref(p), ctypes.byref(st))
+        if check:
+            self._chk(rc, "fcg_solve")
+        return x, st.as_dict()
+
+    def cg_harvest(self, op, b, snap_iters, tol=1e-10, maxiter=10000):
+        """Solve Khat x = b and return (x, [(r_k, e_k = x - x_k)]) at the given iterations."""
+        n = len(snap_iters)
+        xs = [self.field(zero=False) for _ in range(n)]
+        rs = [self.field(zero=False) for _ in range(n)]
+        x = self.field(zero=False)
+        it = (ctypes.c_int * max(1, n))(*snap_iters)
+        xp = (ctypes.c_void_p * max(1, n))(*[v.data_ptr() for v in xs])
+        rp = (ctypes.c_void_p * max(1, n))(*[v.data_ptr() for v in rs])
+        taken = ctypes.c_int()
+        self._chk(self.lib.pfmp_cg_harvest(self.h, op, _ptr(b), _ptr(x), float(tol), int(maxiter), n, it, xp, rp,
+                                           ctypes.byref(taken)), "cg_harvest")
+        pairs = []
+        for k in range(taken.value):
+            e = x.clone()
+            self.axpby(-1.0, xs[k], 1.0, e)
+            pairs.append((rs[k], e))
+        return x, pairs
 
     # ---------------------------------------------------------------- BLAS
     def dot(self, a, b):

@@ -134,6 +134,44 @@ def test_cg_mixed_fp32(setup):
     print("mixed: iters %d, updates %d, |x - x64|/|x| = %.2e" % (st["iters"], st["reliable_updates"], rel(xg, xo)))
 
 
+def test_cg_mixed_fp16_storage(setup):
+    """FP16 half-spinor storage (per-site FP32 scale) in the inner operator, FP32
+    arithmetic, FP64 reliable updates: same FP64 true residual."""
+    from paper_1609_02652_amd.pfmp import F16
+    dims, U, lat, ops = setup
+    b = synth.gaussian_spinor(lat.Vh, 17)
+    x, st = lat.cg_solve(0, lat.pack_spinor(b), tol=1e-10, prec=F16, check_every=5)
+    assert st["true_res"] <= 1e-10
+    assert rel(ops[0].K(lat.spinor_numpy(x)), b) <= 1.05e-10
+    print("fp16 storage: iters %d, updates %d" % (st["iters"], st["reliable_updates"]))
+
+
+def test_batch_apply_bit_identical(setup):
+    """k right-hand sides with their own operators in one launch per stage give
+    bit-identical results to k single-RHS applications."""
+    dims, U, lat, ops = setup
+    psis = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 70 + k)) for k in range(3)]
+    opl = [0, 1, 0]
+    outs = lat.apply_MdagM_batch(opl, psis)
+    for op, x, o in zip(opl, psis, outs):
+        single = lat.apply_MdagM(op, x)
+        assert lat.torch.equal(o, single)
+
+
+def test_batch_cg(setup):
+    dims, U, lat, ops = setup
+    bs = [synth.gaussian_spinor(lat.Vh, 80 + k) for k in range(3)]
+    opl = [0, 1, 0]
+    xs, sts = lat.cg_solve_batch(opl, [lat.pack_spinor(b) for b in bs], tol=1e-11, check_every=6)
+    for op, b, x, st in zip(opl, bs, xs, sts):
+        assert st["true_res"] <= 1.1e-11
+        xg = lat.spinor_numpy(x)
+        assert rel(ops[op].K(xg), b) <= 1.1e-11
+        xs1, st1 = lat.cg_solve(op, lat.pack_spinor(b), tol=1e-11)
+        assert abs(st1["iters"] - st["iters"]) <= 1
+        assert rel(xg, lat.spinor_numpy(xs1)) < 1e-9
+
+
 def test_cg_maxiter_reports(setup):
     from paper_1609_02652_amd.pfmp import PfmpError
     dims, U, lat, ops = setup
