@@ -266,6 +266,11 @@ typedef struct {
     double tol;           /* relative residual of every solve */
     int maxiter;
     int exact_start;      /* 1: evaluate the filter actions at the start; 0: use eta^dag eta */
+    int solver_prec;      /* pfmp_prec of the CG solves (RATIO, HEAVY): F32 / F16 use FP64 reliable updates */
+    const double *ptnet;  /* optional learned-preconditioner weights (1568 doubles): the CG solves become
+                             flexible CG with that network; NULL: plain CG */
+    int batch;            /* 1: the CG solves of all RATIO / HEAVY terms due at the same merged step run
+                             as one multi-RHS solve (the S_j commute, App. B); FP64 plain CG only */
 } pfmp_hmc_spec;
 
 typedef struct {

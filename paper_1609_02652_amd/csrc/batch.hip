@@ -58,6 +58,7 @@ __device__ __forceinline__ void batch_partial(double v, int k, double *partials)
 }
 
 // out_r = [g5] A_oo^-1 D_oe [g5] in_r
+template <int CLOV>
 __global__ __launch_bounds__(kBlock) void k_b_clovinv(Geom g, Batch b, Vecs v, const double2 *__restrict__ U,
                                                       double gin, double gout, const double *__restrict__ st)
 {
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_b_clovinv(Geom g, Batch b, Vecs v, c
     if (st && st[8 * r + B_DONE] != 0) return;
     double2 acc[12];
     hop_all<double2>(g, 1, i, v.in[r], U, gin, acc);
-    if (b.clov[r]) {
+    if (CLOV) {
         double2 t[12];
         clover_apply<double, double2>(b.clo[r], g.Vh, i, acc, t);
         store_spinor(v.out[r], g.Vh, i, gout, t);
@@ -76,6 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_b_clovinv(Geom g, Batch b, Vecs v, c
 }
 
 // out_r = [g5] (A_ee [g5] x_r + a_r D_eo t_r), |out_r|^2 partials
+template <int CLOV>
 __global__ __launch_bounds__(kBlock) void k_b_xpay(Geom g, Batch b, Vecs x, Vecs t, const double2 *__restrict__ U,
                                                    double gs, const double *__restrict__ st,
                                                    double *__restrict__ partials)
@@ -88,11 +90,11 @@ __global__ __launch_bounds__(kBlock) void k_b_xpay(Geom g, Batch b, Vecs x, Vecs
         double2 acc[12], xv[12], ax[12];
         hop_all<double2>(g, 0, i, t.in[r], U, 1.0, acc);
         load_spinor(x.in[r], g.Vh, i, gs, xv);
-        if (b.clov[r]) clover_apply<double, double2>(b.cle[r], g.Vh, i, xv, ax);
+        if (CLOV) clover_apply<double, double2>(b.cle[r], g.Vh, i, xv, ax);
         const double a = b.a[r];
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            double2 base = b.clov[r] ? ax[k] : xv[k];
+            double2 base = CLOV ? ax[k] : xv[k];
             acc[k] = make_double2(base.x + a * acc[k].x, base.y + a * acc[k].y);
             nrm += acc[k].x * acc[k].x + acc[k].y * acc[k].y;
         }
@@ -102,6 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_b_xpay(Geom g, Batch b, Vecs x, Vecs
 }
 
 // CG stage 4: Kp_r from t_r and T'_r; x_r += alpha_r p_r; r_r -= alpha_r Kp_r; |r_r|^2 partials
+template <int CLOV>
 __global__ __launch_bounds__(kBlock) void k_b_hop4(Geom g, Batch b, Vecs t, Vecs T, Vecs p, Vecs x, Vecs rr,
                                                    const double2 *__restrict__ U, const double *__restrict__ st,
                                                    double *__restrict__ partials)
@@ -114,14 +117,14 @@ __global__ __launch_bounds__(kBlock) void k_b_hop4(Geom g, Batch b, Vecs t, Vecs
         double2 acc[12], tv[12], at[12];
         hop_all<double2>(g, 0, i, T.in[r], U, 1.0, acc);
         load_spinor(t.in[r], g.Vh, i, -1.0, tv);
-        if (b.clov[r]) clover_apply<double, double2>(b.cle[r], g.Vh, i, tv, at);
+        if (CLOV) clover_apply<double, double2>(b.cle[r], g.Vh, i, tv, at);
         const double alpha = st[8 * r + B_ALPHA], a = b.a[r];
         const long Vh = g.Vh;
         const double2 *pp = p.in[r];
         double2 *xx = x.out[r], *rv_ = rr.out[r];
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            double2 base = b.clov[r] ? at[k] : tv[k];
+            double2 base = CLOV ? at[k] : tv[k];
             double2 kp = make_double2(base.x + a * acc[k].x, base.y + a * acc[k].y);
             if (k >= 6) kp = cneg(kp);
             double2 pv = pp[k * Vh + i], xv = xx[k * Vh + i], rv = rv_[k * Vh + i];
@@ -195,6 +198,13 @@ __global__ void k_b_update_p(Geom g, Batch b, Vecs rr, Vecs p, const double *__r
 
 }  // namespace
 
+// launch the CLOV = 0 / 1 instance of a batch stencil kernel
+#define BLAUNCH(K, grid, block, shm, stream, ...)                                                     \
+    do {                                                                                           \
+        if (b.clov[0]) hipLaunchKernelGGL(K<1>, grid, block, shm, stream, __VA_ARGS__);              \
+        else hipLaunchKernelGGL(K<0>, grid, block, shm, stream, __VA_ARGS__);                       \
+    } while (0)
+
 static int make_batch(pfmp_ctx *ctx, int nrhs, const int *ops, Batch &b)
 {
     if (nrhs <= 0 || nrhs > kMaxRhs || !ops) return set_err(ctx, PFMP_ERR_ARG, "batch: 1..8 right-hand sides");
@@ -211,6 +221,9 @@ static int make_batch(pfmp_ctx *ctx, int nrhs, const int *ops, Batch &b)
         b.a[r] = -s.kappa * s.kappa;
         b.clov[r] = s.csw != 0;
     }
+    for (int r = 1; r < nrhs; r++)
+        if (b.clov[r] != b.clov[0])
+            return set_err(ctx, PFMP_ERR_ARG, "batch: all operators of a batch must be clover or all Wilson");
     return 0;
 }
 
@@ -244,13 +257,13 @@ extern "C" int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, c
     }
     dim3 grid(nblocks_site((long)g.Vh * b.k)), block(kBlock);
     // Mhat in -> te (stage 1 to to, stage 2 to te), then Mhat^dag te -> out
-    hipLaunchKernelGGL(k_b_clovinv, grid, block, 0, ctx->stream, g, b, vecs(nrhs, in, to.data()), ctx->U, 1.0, 1.0,
+    BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b, vecs(nrhs, in, to.data()), ctx->U, 1.0, 1.0,
                        nullptr);
-    hipLaunchKernelGGL(k_b_xpay, grid, block, 0, ctx->stream, g, b, vecs(nrhs, in, te.data()),
+    BLAUNCH(k_b_xpay, grid, block, 0, ctx->stream, g, b, vecs(nrhs, in, te.data()),
                        vecs(nrhs, (const void *const *)to.data(), nullptr), ctx->U, 1.0, nullptr, nullptr);
-    hipLaunchKernelGGL(k_b_clovinv, grid, block, 0, ctx->stream, g, b,
+    BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b,
                        vecs(nrhs, (const void *const *)te.data(), to.data()), ctx->U, -1.0, 1.0, nullptr);
-    hipLaunchKernelGGL(k_b_xpay, grid, block, 0, ctx->stream, g, b, vecs(nrhs, (const void *const *)te.data(), out),
+    BLAUNCH(k_b_xpay, grid, block, 0, ctx->stream, g, b, vecs(nrhs, (const void *const *)te.data(), out),
                        vecs(nrhs, (const void *const *)to.data(), nullptr), ctx->U, -1.0, nullptr, nullptr);
     LAUNCHCHK(ctx);
     return 0;
@@ -315,11 +328,11 @@ extern "C" int pfmp_cg_solve_batch(pfmp_ctx *ctx, int nrhs, const int *ops, cons
     std::vector<double> h(8 * kMaxRhs);
     for (;;) {
         for (int it = 0; it < chunk; it++) {
-            hipLaunchKernelGGL(k_b_clovinv, grid, block, 0, ctx->stream, g, b, p_to_T2, ctx->U, 1.0, 1.0, sc);
-            hipLaunchKernelGGL(k_b_xpay, grid, block, 0, ctx->stream, g, b, p_to_T1, vT2, ctx->U, 1.0, sc, part_a);
+            BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b, p_to_T2, ctx->U, 1.0, 1.0, sc);
+            BLAUNCH(k_b_xpay, grid, block, 0, ctx->stream, g, b, p_to_T1, vT2, ctx->U, 1.0, sc, part_a);
             hipLaunchKernelGGL(k_b_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_a, nb, b.k, nrhs, sc);
-            hipLaunchKernelGGL(k_b_clovinv, grid, block, 0, ctx->stream, g, b, T1_to_T2, ctx->U, -1.0, 1.0, sc);
-            hipLaunchKernelGGL(k_b_hop4, grid, block, 0, ctx->stream, g, b, vT1, vT2, vP, vX, vR, ctx->U, sc, part_b);
+            BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b, T1_to_T2, ctx->U, -1.0, 1.0, sc);
+            BLAUNCH(k_b_hop4, grid, block, 0, ctx->stream, g, b, vT1, vT2, vP, vX, vR, ctx->U, sc, part_b);
             hipLaunchKernelGGL(k_b_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, b.k, nrhs, sc);
             hipLaunchKernelGGL(k_b_update_p, dim3(nblocks(n * nrhs, 256)), dim3(256), 0, ctx->stream, g, b, vR, vP, sc);
             LAUNCHCHK(ctx);

@@ -15,6 +15,7 @@
 //   POLYCORR  -(1/a_n) sum_i r_i x_{i*}^dag dJ x_i, x_i = (J - z_i)^-1 phi, z_{i*} = conj(z_i)
 //   RATIO     2 Re[X^dag dW phi] - 2 Re[(M_b X)^dag dM_b X], X = K_b^-1 W phi
 //   HEAVY     -2 Re[(W X)^dag dW X], X = J^-1 phi
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -111,9 +112,9 @@ int partner(const std::vector<cd> &z, int i)
 
 int solve(Ctx &X, int op, const void *b, void *x)
 {
-    pfmp_solver_params p{X.sp->tol, X.sp->maxiter > 0 ? X.sp->maxiter : 100000, PFMP_F64, 0.0, 0};
+    pfmp_solver_params p{X.sp->tol, X.sp->maxiter > 0 ? X.sp->maxiter : 100000, X.sp->solver_prec, 0.0, 0};
     pfmp_solver_stats st{};
-    int rc = pfmp_cg_solve(X.c, op, b, x, &p, &st);
+    int rc = X.sp->ptnet ? pfmp_fcg_solve(X.c, op, X.sp->ptnet, b, x, &p, &st) : pfmp_cg_solve(X.c, op, b, x, &p, &st);
     X.iters += st.iters;
     X.mhalf += 2 * st.kmults;
     return rc;
@@ -261,7 +262,7 @@ int term_heatbath(Ctx &X, const pfmp_term &t, const void *eta, void *phi)
 }
 
 // F += eps * dS_j/dw
-int term_force(Ctx &X, const pfmp_term &t, const void *phi, double eps, double *F)
+int term_force(Ctx &X, const pfmp_term &t, const void *phi, double eps, double *F, const void *presolved = nullptr)
 {
     pfmp_ctx *ctx = X.c;
     int rc = 0;
@@ -332,8 +333,12 @@ int term_force(Ctx &X, const pfmp_term &t, const void *phi, double eps, double *
     case PFMP_TERM_RATIO: {
         double2 *t0 = pool_get(ctx, kTmp), *x = pool_get(ctx, kTmp + 1), *mx = pool_get(ctx, kTmp + 2);
         if (!t0 || !x || !mx) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
-        if ((rc = applyM(X, t.op, 0, phi, t0))) return rc;
-        if ((rc = solve(X, t.op2, t0, x))) return rc;
+        if (presolved) {
+            x = (double2 *)presolved;
+        } else {
+            if ((rc = applyM(X, t.op, 0, phi, t0))) return rc;
+            if ((rc = solve(X, t.op2, t0, x))) return rc;
+        }
         if ((rc = applyM(X, t.op2, 0, x, mx))) return rc;
         const void *xa[1] = {x}, *ya[1] = {phi};
         double ca[2] = {2 * eps, 0};
@@ -345,7 +350,8 @@ int term_force(Ctx &X, const pfmp_term &t, const void *phi, double eps, double *
     case PFMP_TERM_HEAVY: {
         double2 *x = pool_get(ctx, kTmp + 1), *wx = pool_get(ctx, kTmp + 2);
         if (!x || !wx) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
-        if ((rc = solve(X, t.op, phi, x))) return rc;
+        if (presolved) x = (double2 *)presolved;
+        else if ((rc = solve(X, t.op, phi, x))) return rc;
         if ((rc = applyM(X, t.op, 0, x, wx))) return rc;
         const void *xa[1] = {wx}, *ya[1] = {x};
         double ca[2] = {-2 * eps, 0};
@@ -439,6 +445,60 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
         for (int j = 0; j < nt; j++) any = any || So[(size_t)j * cap + k] != 0.0;
         if (!any) continue;
         HIPCHK(ctx, hipMemsetAsync(F, 0, sizeof(double) * mom_reals(ctx->g), ctx->stream));
+        // the CG solves of the RATIO / HEAVY terms due at this step, as one multi-RHS solve
+        std::vector<const void *> pre(nt, nullptr);
+        if (sp->batch && !sp->ptnet && sp->solver_prec == PFMP_F64) {
+            std::vector<int> js, sops;
+            std::vector<const void *> rhs;
+            std::vector<void *> sol;
+            for (int j = 1; j < nt; j++) {
+                const pfmp_term &t = sp->terms[j - 1];
+                if (So[(size_t)j * cap + k] == 0.0 || (t.kind != PFMP_TERM_RATIO && t.kind != PFMP_TERM_HEAVY))
+                    continue;
+                double2 *b = pool_get(ctx, 2200 + j), *x = pool_get(ctx, 2100 + j);
+                if (!b || !x) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+                if (t.kind == PFMP_TERM_RATIO) {
+                    if ((rc = applyM(X, t.op, 0, phi[j - 1], b))) return rc;
+                    rhs.push_back(b);
+                    sops.push_back(t.op2);
+                } else {
+                    rhs.push_back(phi[j - 1]);
+                    sops.push_back(t.op);
+                }
+                sol.push_back(x);
+                js.push_back(j);
+            }
+            // one multi-RHS solve per group of operators of equal clover flag, at most 8 each
+            for (int cl = 0; cl < 2; cl++) {
+                std::vector<size_t> grp;
+                for (size_t q = 0; q < js.size(); q++)
+                    if ((ctx->ops[sops[q]].csw != 0) == (cl == 1)) grp.push_back(q);
+                for (size_t g0 = 0; g0 < grp.size(); g0 += 8) {
+                    size_t m = std::min<size_t>(8, grp.size() - g0);
+                    std::vector<int> o(m);
+                    std::vector<const void *> bb(m);
+                    std::vector<void *> xx(m);
+                    for (size_t q = 0; q < m; q++) {
+                        o[q] = sops[grp[g0 + q]];
+                        bb[q] = rhs[grp[g0 + q]];
+                        xx[q] = sol[grp[g0 + q]];
+                    }
+                    if (m == 1) {
+                        if ((rc = solve(X, o[0], bb[0], xx[0]))) return rc;
+                    } else {
+                        pfmp_solver_params p{sp->tol, sp->maxiter > 0 ? sp->maxiter : 100000, PFMP_F64, 0.0, 0};
+                        std::vector<pfmp_solver_stats> bst(m);
+                        if ((rc = pfmp_cg_solve_batch(ctx, (int)m, o.data(), bb.data(), xx.data(), &p, bst.data())))
+                            return rc;
+                        for (size_t q = 0; q < m; q++) {
+                            X.iters += bst[q].iters;
+                            X.mhalf += 2 * bst[q].kmults;
+                        }
+                    }
+                    for (size_t q = 0; q < m; q++) pre[js[grp[g0 + q]]] = xx[q];
+                }
+            }
+        }
         for (int j = 0; j < nt; j++) {
             double eps = So[(size_t)j * cap + k];
             if (eps == 0.0) continue;
@@ -446,7 +506,7 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
             if (j == 0) {
                 if ((rc = pfmp_gauge_force(ctx, sp->beta * eps, F))) return rc;
                 if (sp->det_op >= 0 && (rc = pfmp_logdet_force(ctx, sp->det_op, eps, F))) return rc;
-            } else if ((rc = term_force(X, sp->terms[j - 1], phi[j - 1], eps, F))) {
+            } else if ((rc = term_force(X, sp->terms[j - 1], phi[j - 1], eps, F, pre[j]))) {
                 return rc;
             }
         }

@@ -62,7 +62,8 @@ class HmcSpec(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("det_op", ctypes.c_int), ("gauge_steps", ctypes.c_int),
                 ("tau", ctypes.c_double), ("lam", ctypes.c_double), ("nterms", ctypes.c_int),
                 ("terms", ctypes.POINTER(Term)), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int),
-                ("exact_start", ctypes.c_int)]
+                ("exact_start", ctypes.c_int), ("solver_prec", ctypes.c_int), ("ptnet", ctypes.c_void_p),
+                ("batch", ctypes.c_int)]
 
 
 class TrajStats(ctypes.Structure):
@@ -488,14 +489,21 @@ class Lattice:
     # ---------------------------------------------------------------- HMC
     @staticmethod
     def spec(beta, terms, gauge_steps, det_op=-1, tau=1.0, lam=0.0, tol=1e-10, maxiter=100000,
-             exact_start=False):
-        """terms: list of dicts {kind, op, op2, n, mu, nu, steps}."""
+             exact_start=False, solver_prec=F64, ptnet=None, batch=False):
+        """terms: list of dicts {kind, op, op2, n, mu, nu, steps}; ptnet: (W1, W2, W0) or None;
+        batch: the solves of all ratio / heavy terms due at one merged step run as one
+        multi-RHS solve (FP64 plain CG)."""
         arr = (Term * max(1, len(terms)))()
         for k, t in enumerate(terms):
             arr[k] = Term(TERM_KINDS[t["kind"]], t["op"], t.get("op2", -1), t.get("n", 0), t.get("mu", 0.0),
                           t.get("nu", 0.0), t["steps"])
-        sp = HmcSpec(beta, det_op, gauge_steps, tau, lam, len(terms), arr, tol, maxiter, int(exact_start))
-        sp._keep = arr
+        wp, keep_w = None, None
+        if ptnet is not None:
+            keep_w = Lattice._weights(ptnet).copy()
+            wp = keep_w.ctypes.data
+        sp = HmcSpec(beta, det_op, gauge_steps, tau, lam, len(terms), arr, tol, maxiter, int(exact_start),
+                     int(solver_prec), wp, int(batch))
+        sp._keep = (arr, keep_w)
         return sp
 
     def heatbath(self, spec, etas, phis=None):

@@ -135,3 +135,30 @@ def test_exp_minus_dH_average_gpu(U0):
     print("<exp(-dH)> = %.4f +- %.4f, acceptance %.2f" % (m, err, acc / len(vals)))
     assert abs(m - 1) < 3 * err + 1e-3
     lat.close()
+
+
+def _run(lat_U, sp_kw, P0, etas, u):
+    lat = make_lattice(lat_U)
+    terms = [dict(kind="ratio", op=1, op2=0, steps=6), dict(kind="heavy", op=1, steps=6),
+             dict(kind="poly", op=1, n=4, mu=1.2, nu=0.9, steps=12)]
+    sp = lat.spec(BETA, terms, 24, det_op=0, tol=1e-12, exact_start=True, **sp_kw)
+    st = lat.trajectory(sp, lat.pack_momenta(P0), [lat.pack_spinor(e) for e in etas], u)
+    Ug = lat.get_gauge().cpu().numpy()
+    lat.close()
+    return st, Ug
+
+
+def test_batched_and_mixed_solves_in_trajectory(U0):
+    """The ratio and heavy solves due at the same merged step as one multi-RHS solve,
+    and FP32 / FP16 inner solves with FP64 reliable updates, give the FP64
+    single-RHS trajectory up to the solver tolerance."""
+    from paper_1609_02652_amd.pfmp import F32, F16
+    P0 = synth.gaussian_momenta(256, 103)
+    etas = [synth.gaussian_spinor(128, 50 + j) for j in range(3)]
+    ref, Uref = _run(U0, {}, P0, etas, 0.0)
+    for kw in (dict(batch=True), dict(solver_prec=F32), dict(solver_prec=F16)):
+        st, Ug = _run(U0, kw, P0, etas, 0.0)
+        print(kw, "dH %.12f vs %.12f, iters %d vs %d" % (st["dH"], ref["dH"], st["solver_iters"],
+                                                          ref["solver_iters"]), flush=True)
+        assert abs(st["dH"] - ref["dH"]) < 1e-8
+        assert np.max(np.abs(Ug - Uref)) < 1e-9
