@@ -44,11 +44,11 @@ def make_lattice(dims, U):
     return lat
 
 
-def pfmp_spec(lat, steps=STEPS, tol=TOL):
+def pfmp_spec(lat, steps=STEPS, tol=TOL, **kw):
     terms = [dict(kind="poly", op=1, n=4, mu=1.2, nu=0.9, steps=steps["poly"]),
              dict(kind="polycorr", op=1, n=4, mu=1.2, nu=0.9, steps=steps["corr"]),
              dict(kind="ratio", op=1, op2=0, steps=steps["ratio"])]
-    return lat.spec(BETA, terms, steps["gauge"], det_op=0, tol=tol)
+    return lat.spec(BETA, terms, steps["gauge"], det_op=0, tol=tol, **kw)
 
 
 def time_kernel(lat, fn, reps):
@@ -138,13 +138,93 @@ def cpu_baseline(U, kmults_per_traj, budget_s=15.0):
                       % (n, per_k, t_setup, kmults_per_traj)}
 
 
+def thermalise(lat, ntraj, gauge_steps=20):
+    """Quenched HMC (Wilson gauge action at BETA, 2MN, tau = 1) from the seeded start:
+    the links the solver and trajectory benchmarks run on."""
+    from paper_1609_02652_amd import synth
+    sp = lat.spec(BETA, [], gauge_steps, det_op=-1)
+    acc = 0
+    for k in range(ntraj):
+        st = lat.trajectory(sp, lat.pack_momenta(synth.gaussian_momenta(lat.V, 7000 + k)), [],
+                            synth.uniform(8000 + k)[0])
+        acc += st["accept"]
+    plaq = 1.0 - lat.gauge_action(BETA) / (BETA * 6 * lat.V)
+    log("quenched thermalisation: %d trajectories, acceptance %.2f, plaquette %.5f" % (ntraj, acc / max(ntraj, 1),
+                                                                                      plaq))
+    return {"trajectories": ntraj, "accept_rate": acc / max(ntraj, 1), "plaquette": round(plaq, 6)}
+
+
+def cg_bench(lat, nsrc):
+    """CG on Khat (kappa 0.1340) to 1e-10, one Gaussian source at a time, in FP64,
+    FP32 + FP64 reliable updates, and FP32 arithmetic with FP16 storage + FP64
+    reliable updates: median seconds, iterations and final FP64 residual."""
+    import torch
+    from paper_1609_02652_amd import synth
+    from paper_1609_02652_amd.pfmp import F64, F32, F16
+    res = {}
+    srcs = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 1 + s)) for s in range(nsrc)]
+    x = lat.field()
+    for name, prec in (("f64", F64), ("f32", F32), ("f16", F16)):
+        lat.cg_solve(0, srcs[0], x=x, tol=TOL, prec=prec)   # warm-up
+        rows = []
+        for b in srcs:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = lat.cg_solve(0, b, x=x, tol=TOL, prec=prec)
+            torch.cuda.synchronize()
+            rows.append((time.perf_counter() - t0, st["iters"], st["true_res"], st["reliable_updates"]))
+        res[name] = {"median_s": round(float(np.median([r[0] for r in rows])), 5),
+                     "iters": int(np.median([r[1] for r in rows])),
+                     "reliable_updates": int(np.median([r[3] for r in rows])),
+                     "max_true_res": float(max(r[2] for r in rows))}
+        log("cg %s: %s" % (name, res[name]))
+    return res
+
+
+def run_trajectories(lat, sp, steps, warmup, seed):
+    """warmup untimed, then exactly `steps` timed trajectories on fresh momenta and
+    pseudofermion sources; the links are restored after each so every mode sees
+    the same starting configuration."""
+    import torch
+    from paper_1609_02652_amd import synth
+    V, Vh = lat.V, lat.Vh
+    U0 = lat.get_gauge().clone()
+
+    def inputs(k):
+        P = lat.pack_momenta(synth.gaussian_momenta(V, seed + k))
+        etas = [lat.pack_spinor(synth.gaussian_spinor(Vh, seed + 10000 + 3 * k + j)) for j in range(3)]
+        return P, etas
+
+    for k in range(warmup):
+        P, etas = inputs(k)
+        st = lat.trajectory(sp, P, etas, synth.uniform(seed + k)[0])
+        log("warmup traj %d: dH %.4f %.3f s" % (k, st["dH"], st["seconds"]))
+        lat.set_gauge(U0)
+    batch = [inputs(1000 + k) for k in range(steps)]
+    us = [synth.uniform(seed + 500 + k)[0] for k in range(steps)]
+    stats, elapsed = [], 0.0
+    for k in range(steps):
+        P, etas = batch[k]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats.append(lat.trajectory(sp, P, etas, us[k]))
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        lat.set_gauge(U0)
+    for st in stats:
+        log("traj: dH %.5f accept %d %.3f s kmults %d iters %d nforce %s"
+            % (st["dH"], st["accept"], st["seconds"], st["kmults"], st["solver_iters"], st["nforce"]))
+    return elapsed / steps, stats
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sources", type=int, default=4)
+    ap.add_argument("--sources", type=int, default=32)
+    ap.add_argument("--therm", type=int, default=20, help="quenched thermalisation trajectories")
     ap.add_argument("--roofline-only", action="store_true",
                     help="time only the hopping kernels and a plain copy (for counter runs)")
     args = ap.parse_args()
@@ -154,50 +234,27 @@ def main():
     if args.roofline_only:
         roofline_only(max(args.steps, 10))
         return
-    import torch
     from paper_1609_02652_amd import synth
+    from paper_1609_02652_amd.pfmp import F64, Lattice
     log("bench: building inputs", DIMS)
-    U = synth.random_gauge(DIMS, seed=0)
-    lat = make_lattice(DIMS, U)
-    V, Vh = lat.V, lat.Vh
-    sp = pfmp_spec(lat)
+    lat = Lattice(DIMS)
+    lat.set_gauge(synth.random_gauge(DIMS, seed=0))
+    therm = thermalise(lat, args.therm)
+    lat.set_operator(0, KAPPA, CSW)
+    lat.set_operator(1, KAPPA_H, CSW)
+    U = lat.get_gauge().cpu().numpy()
 
-    # ---- CG solves at 1e-10 (FP64), Gaussian sources one at a time
-    solves = []
-    for s in range(args.sources):
-        b = lat.pack_spinor(synth.gaussian_spinor(Vh, 1 + s))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x, st = lat.cg_solve(0, b, tol=TOL)
-        torch.cuda.synchronize()
-        solves.append((time.perf_counter() - t0, st["iters"], st["true_res"]))
-        log("cg source %d: %.4f s, %d iters, res %.2e" % (s, *solves[-1]))
+    # ---- CG solves at 1e-10 in the three precisions
+    cg = cg_bench(lat, args.sources)
+    chosen_prec = min(("f32", "f16"), key=lambda k: cg[k]["median_s"])
 
-    # ---- trajectories
-    def one(k):
-        P = lat.pack_momenta(synth.gaussian_momenta(V, 100 + k))
-        etas = [lat.pack_spinor(synth.gaussian_spinor(Vh, 1000 + 3 * k + j)) for j in range(3)]
-        torch.cuda.synchronize()
-        return P, etas
-
-    for k in range(args.warmup):
-        P, etas = one(k)
-        st = lat.trajectory(sp, P, etas, synth.uniform(50 + k)[0])
-        log("warmup traj %d: dH %.4f %.3f s" % (k, st["dH"], st["seconds"]))
-    inputs = [one(1000 + k) for k in range(args.steps)]
-    stats = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        P, etas = inputs[k]
-        stats.append(lat.trajectory(sp, P, etas, synth.uniform(500 + k)[0]))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    for st in stats:
-        log("traj: dH %.5f accept %d %.3f s kmults %d iters %d nforce %s"
-            % (st["dH"], st["accept"], st["seconds"], st["kmults"], st["solver_iters"], st["nforce"]))
-    ms = elapsed / args.steps * 1e3
-    kmults = int(np.mean([s["kmults"] for s in stats]))
+    # ---- trajectories: plain FP64 form, then the chosen form (timed value)
+    from paper_1609_02652_amd.pfmp import F32, F16
+    sp_plain = pfmp_spec(lat)
+    sp_chosen = pfmp_spec(lat, solver_prec={"f32": F32, "f16": F16}[chosen_prec], batch=True)
+    t_plain, st_plain = run_trajectories(lat, sp_plain, args.steps, args.warmup, 100)
+    t_chosen, st_chosen = run_trajectories(lat, sp_chosen, args.steps, args.warmup, 100)
+    kmults = int(np.mean([s["kmults"] for s in st_plain]))
     lat.close()
 
     # ---- dominant-kernel roofline (HIP events on the library stream)
@@ -217,28 +274,35 @@ def main():
     except Exception as e:  # noqa: BLE001 -- report, do not hide
         roof["hop_32x64_error"] = str(e)
 
+    def traj_summary(t, sts):
+        return {"s_per_traj": round(t, 4), "accept_rate": float(np.mean([s["accept"] for s in sts])),
+                "dH": [round(s["dH"], 5) for s in sts], "kmults": int(np.mean([s["kmults"] for s in sts])),
+                "solver_iters": int(np.mean([s["solver_iters"] for s in sts]))}
+
     out = {
         "metric": "PF-MP trajectory s & CG solve s at 1e-10 resid, plain FP64 vs chosen; Dslash GB/s",
-        "value": round(ms / 1e3, 4),
+        "value": round(t_chosen, 4),
         "unit": "s/trajectory",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 2),
+        "ms_per_step": round(t_chosen * 1e3, 2),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if chosen_prec == "f32" else "f16-storage/f32+f64",
         "data": "synthetic",
-        "config": {"workload": "PF-MP HMC trajectory, 16^3x32 clover kappa=0.1340 c_sw=1.6, Hasenbusch kappa'=0.1300, "
-                               "degree-4 filter, 2MN steps (6,20,120,480), tol 1e-10",
-                   "lattice": "16x16x16x32", "mode": "plain FP64"},
-        "trajectory": {"accept_rate": float(np.mean([s["accept"] for s in stats])),
-                       "dH": [round(s["dH"], 5) for s in stats], "kmults": kmults,
-                       "solver_iters": int(np.mean([s["solver_iters"] for s in stats]))},
-        "cg_solve": {"prec": "f64", "tol": TOL, "median_s": round(float(np.median([s[0] for s in solves])), 4),
-                     "iters": int(np.median([s[1] for s in solves])),
-                     "max_true_res": max(s[2] for s in solves)},
+        "config": {"workload": "PF-MP HMC trajectory on the 16^3x32 mixed-precision solve lattice: links from %d "
+                               "quenched HMC trajectories at beta=5.7 from the seeded start, clover kappa=0.1340 "
+                               "c_sw=1.6, Hasenbusch kappa'=0.1300, degree-4 filter (mu,nu)=(1.2,0.9), 2MN steps "
+                               "(6,20,120,480), every solve to 1e-10" % args.therm,
+                   "lattice": "16x16x16x32",
+                   "mode": "chosen: %s inner CG with FP64 reliable updates, batched solves; all actions, dH and "
+                           "the accept in FP64" % chosen_prec},
+        "trajectory": {"chosen": traj_summary(t_chosen, st_chosen), "plain_f64": traj_summary(t_plain, st_plain),
+                       "speedup_vs_plain": round(t_plain / t_chosen, 3)},
+        "cg_solve": dict(cg, tol=TOL, sources=args.sources),
+        "thermalisation": therm,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -90,13 +90,14 @@ void roots_of(const pfmp_term &t, std::vector<cd> &z, double &a)
     a = nm[0];
 }
 
+// partial fractions: 1 / prod_k (x - z_k) = sum_i r_i / (x - z_i), r_i = prod_{j != i} 1 / (z_i - z_j)
 std::vector<cd> residues(const std::vector<cd> &z)
 {
     std::vector<cd> r(z.size());
     for (size_t i = 0; i < z.size(); i++) {
         cd p = 1.0;
         for (size_t j = 0; j < z.size(); j++)
-            if (j != i) p /= (z[j] - z[i]);
+            if (j != i) p /= (z[i] - z[j]);
         r[i] = p;
     }
     return r;
