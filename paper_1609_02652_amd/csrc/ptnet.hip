@@ -386,7 +386,7 @@ extern "C" int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int npairs, const
     const long nwaves = (long)grid.x * (kBlock / 64);
     std::vector<double> acc(2 * NW, 0.0);
     double tot = 0;
-    std::vector<double> tmp(2 * NW1);
+    std::vector<double> tmp(2 * NW);   // holds either the A2|A0 block (800) or the A1 block (768)
     for (int p = 0; p < npairs; p++) {
         const double2 *r = (const double2 *)R[p], *e = (const double2 *)E[p];
         double nr = host_norm(ctx, r, &rc);
