@@ -258,7 +258,7 @@ typedef struct {
 typedef struct {
     double beta;          /* Wilson gauge coupling */
     int det_op;           /* slot whose -2 ln det A_oo enters the action (-1: none) */
-    int gauge_steps;      /* 2MN steps of the gauge (and S_det) scale */
+    int gauge_steps;      /* 2MN steps of the gauge scale (and of S_det when det_steps is 0) */
     double tau;           /* trajectory length */
     double lambda;        /* 2MN parameter; 0 selects 0.1931833275037836 (minimum norm) */
     int nterms;
@@ -271,6 +271,8 @@ typedef struct {
                              flexible CG with that network; NULL: plain CG */
     int batch;            /* 1: the CG solves of all RATIO / HEAVY terms due at the same merged step run
                              as one multi-RHS solve (the S_j commute, App. B); FP64 plain CG only */
+    int det_steps;        /* > 0: S_det on its own 2MN scale with this many steps (one more row of the
+                             merged schedule); 0: S_det moves with the gauge action */
 } pfmp_hmc_spec;
 
 typedef struct {
@@ -283,6 +285,7 @@ typedef struct {
     double seconds;
     double parts0[PFMP_MAX_TERMS + 3];   /* kinetic, S_G, S_det, terms at the start */
     double parts1[PFMP_MAX_TERMS + 3];   /* ... at the end */
+    int nforce_det;                      /* S_det force evaluations on its own scale (det_steps > 0) */
 } pfmp_traj_stats;
 
 /* Pseudofermion heatbath: phi_j with density exp(-S_j) from Gaussian eta_j

@@ -173,15 +173,17 @@ def force(ops, term, phi, tol, F=None, links=None):
 
 
 def build_schedule(spec):
-    """Per-term 2MN schemes (gauge + S_det on the finest scale) merged per App. B."""
+    """Per-term 2MN schemes merged per App. B.  Rows: gauge, the terms, and, when
+    spec["det_steps"] > 0, S_det on its own scale as the last row (otherwise S_det
+    moves with the gauge action on the finest scale)."""
     tau = spec.get("tau", 1)
     lam = spec.get("lambda", schedule.OMELYAN_LAMBDA)
+    steps = [spec["gauge_steps"]] + [t["steps"] for t in spec["terms"]]
+    if spec.get("det_steps", 0) > 0:
+        steps.append(spec["det_steps"])
     Ts, Ss = [], []
-    T, S = schedule.omelyan_2mn(spec["gauge_steps"], tau, lam)
-    Ts.append(T)
-    Ss.append(S)
-    for t in spec["terms"]:
-        T, S = schedule.omelyan_2mn(t["steps"], tau, lam)
+    for n in steps:
+        T, S = schedule.omelyan_2mn(n, tau, lam)
         Ts.append(T)
         Ss.append(S)
     return schedule.merge(Ts, Ss)
@@ -204,6 +206,7 @@ def md_evolve(spec, U, P, phis, tol):
     dims = spec["dims"]
     newT, newS = build_schedule(spec)
     nforce = [0] * len(newS)
+    det_row = len(spec["terms"]) + 1 if spec.get("det_steps", 0) > 0 else 0
     for k, dt in enumerate(newT):
         if dt != 0:
             update_gauge(dims, float(dt), P, U)
@@ -215,6 +218,10 @@ def md_evolve(spec, U, P, phis, tol):
             nforce[j] += 1
             if j == 0:
                 F = force_gauge(dims, U, spec["beta"])
+                if spec["csw"] != 0 and det_row == 0:
+                    ops(spec["kappa"]).force_logdet(F)
+            elif j == det_row:
+                F = np.zeros_like(P)
                 if spec["csw"] != 0:
                     ops(spec["kappa"]).force_logdet(F)
             else:

@@ -215,6 +215,7 @@ static int make_batch(pfmp_ctx *ctx, int nrhs, const int *ops, Batch &b)
         int op = r < nrhs ? ops[r] : ops[0];
         if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
             return set_err(ctx, PFMP_ERR_STATE, "batch: operator slot not configured");
+        if (int rc0 = op_ready(ctx, op)) return rc0;
         const OpSlot &s = ctx->ops[op];
         b.clo[r] = s.clov[1];
         b.cle[r] = s.clov[0];

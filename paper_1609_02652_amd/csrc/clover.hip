@@ -46,146 +46,207 @@ __device__ M3 fhat(const Geom &g, const double2 *__restrict__ U, const int *c, i
     return m3_scale(m3_sub(q, m3_dag(q)), 0.125);
 }
 
-// Full 6x6 block b (row-major) of A at site c.
-__device__ void clover_block_full(const M3 *F, double kc, int b, double2 *A)
+// F-hat of one plane at one site, for both parities: thread (p, plane, i), sites fastest.
+__global__ __launch_bounds__(kBlock) void k_fhat(Geom g, const double2 *__restrict__ U, double2 *__restrict__ Fh)
 {
-    double s = b == 0 ? 1.0 : -1.0;
-    // plane order: 0:(01) 1:(02) 2:(03) 3:(12) 4:(13) 5:(23)
-    M3 Gx = m3_sub(m3_scale(F[2], s), F[3]);
-    M3 Gy = m3_add(m3_scale(F[4], s), F[1]);
-    M3 Gz = m3_sub(m3_scale(F[5], s), F[0]);
-    for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++) {
-            int k = 3 * i + j;
-            double2 gz = Gz.e[k];
-            double2 up = csub(Gx.e[k], ctimesi(Gy.e[k]));   // Gx - i Gy
-            double2 lo = cadd(Gx.e[k], ctimesi(Gy.e[k]));   // Gx + i Gy
-            // i kc * block
-            A[i * 6 + j] = cscale(ctimesi(gz), kc);
-            A[i * 6 + 3 + j] = cscale(ctimesi(up), kc);
-            A[(3 + i) * 6 + j] = cscale(ctimesi(lo), kc);
-            A[(3 + i) * 6 + 3 + j] = cscale(ctimesi(gz), -kc);
-        }
-    for (int i = 0; i < 6; i++) A[i * 6 + i].x += 1.0;
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 12L * g.Vh) return;
+    const int pp = (int)(t / g.Vh), i = (int)(t - (long)pp * g.Vh);
+    const int p = pp / 6, pl = pp - 6 * p;
+    const int mu = pl < 3 ? 0 : (pl < 5 ? 1 : 2);
+    const int nu = pl < 3 ? pl + 1 : (pl < 5 ? pl - 1 : 3);
+    int c[4];
+    eo_coords(g, p, i, c);
+    M3 f = fhat(g, U, c, mu, nu);
+    double2 *o = Fh + ((long)pp * 9) * g.Vh + i;
+    for (int k = 0; k < 9; k++) o[(long)k * g.Vh] = f.e[k];
 }
 
-// In-place Cholesky inverse of a 6x6 Hermitian positive matrix; returns ln det, or
-// NaN when a pivot is not positive.
-__device__ double herm6_inverse(double2 *A)
-{
-    double2 L[36];
-    double ld = 0;
-    for (int k = 0; k < 36; k++) L[k] = make_double2(0, 0);
-    for (int j = 0; j < 6; j++) {
-        double d = A[j * 6 + j].x;
-        for (int k = 0; k < j; k++) d -= L[j * 6 + k].x * L[j * 6 + k].x + L[j * 6 + k].y * L[j * 6 + k].y;
-        if (!(d > 0)) return __builtin_nan("");
-        double ljj = sqrt(d);
-        ld += 2.0 * log(ljj);
-        L[j * 6 + j] = make_double2(ljj, 0);
-        for (int i = j + 1; i < 6; i++) {
-            double2 s = A[i * 6 + j];
-            for (int k = 0; k < j; k++) s = csub(s, cmul(L[i * 6 + k], cconj(L[j * 6 + k])));
-            L[i * 6 + j] = cscale(s, 1.0 / ljj);
-        }
-    }
-    // W = L^-1 (lower triangular)
-    double2 W[36];
-    for (int k = 0; k < 36; k++) W[k] = make_double2(0, 0);
-    for (int i = 0; i < 6; i++) {
-        W[i * 6 + i] = make_double2(1.0 / L[i * 6 + i].x, 0);
-        for (int j = 0; j < i; j++) {
-            double2 s = make_double2(0, 0);
-            for (int k = j; k < i; k++) cfma(s, L[i * 6 + k], W[k * 6 + j]);
-            W[i * 6 + j] = cscale(s, -1.0 / L[i * 6 + i].x);
-        }
-    }
-    // A^-1 = W^dag W
-    for (int i = 0; i < 6; i++)
-        for (int j = 0; j < 6; j++) {
-            double2 s = make_double2(0, 0);
-            int k0 = i > j ? i : j;
-            for (int k = k0; k < 6; k++) cfmac(s, W[k * 6 + i], W[k * 6 + j]);
-            A[i * 6 + j] = s;
-        }
-    return ld;
-}
+__device__ __forceinline__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c; }   // c <= r
 
-__global__ __launch_bounds__(kBlock) void k_clover_build(Geom g, int parity, const double2 *__restrict__ U,
-                                                         double kc, double *__restrict__ out,
-                                                         double *__restrict__ ld_partials, int *__restrict__ bad)
+// Chiral block b of A at parity p from F-hat: thread (b, i).  INV = 0 stores A
+// (even sites); INV = 1 stores A^-1 from a packed Cholesky factorisation and sums
+// ln det A into per-block partials (odd sites).  Storage: 6 real diagonal entries
+// and the 15 upper off-diagonal entries (row-major) of each block, FP64 and FP32.
+// Each block is 1 + i kappa c_sw [[Gz, Gx - i Gy], [Gx + i Gy, -Gz]] with
+// Gx = s F_03 - F_12, Gy = s F_13 + F_02, Gz = s F_23 - F_01, s = +1 (b = 0) / -1 (b = 1).
+template <int INV>
+__global__ __launch_bounds__(kBlock) void k_clover_blocks(Geom g, int p, const double2 *__restrict__ Fh, double kc,
+                                                          double *__restrict__ out, float *__restrict__ outf,
+                                                          double *__restrict__ ld_partials, int *__restrict__ bad)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     double ld = 0;
-    if (i < g.Vh) {
-        int c[4];
-        eo_coords(g, parity, i, c);
-        M3 F[6];
-        int p = 0;
-        for (int mu = 0; mu < 4; mu++)
-            for (int nu = mu + 1; nu < 4; nu++, p++) F[p] = fhat(g, U, c, mu, nu);
-        double2 *off = reinterpret_cast<double2 *>(out + 12L * g.Vh);
-        for (int b = 0; b < 2; b++) {
-            double2 A[36];
-            clover_block_full(F, kc, b, A);
-            if (parity == 1) {
-                double l = herm6_inverse(A);
-                if (l != l) { *bad = 1; l = 0; }
-                ld += l;
+    if (t < 2L * g.Vh) {
+        const int b = (int)(t / g.Vh), i = (int)(t - (long)b * g.Vh);
+        const long Vh = g.Vh;
+        const double s = b == 0 ? 1.0 : -1.0;
+        const double2 *F = Fh + ((long)p * 6 * 9) * Vh + i;
+        auto fe = [&](int pl, int k) { return F[((long)pl * 9 + k) * Vh]; };
+        double2 a[21];   // lower triangle, row-major
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int c = 0; c <= r; c++) {
+                int k = 3 * r + c;
+                double2 gz = csub(cscale(fe(5, k), s), fe(0, k));
+                a[tri(r, c)] = cscale(ctimesi(gz), kc);
+                a[tri(3 + r, 3 + c)] = cscale(ctimesi(gz), -kc);
             }
-            for (int k = 0; k < 6; k++) out[(long)(b * 6 + k) * g.Vh + i] = A[k * 6 + k].x;
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                int k = 3 * r + c;
+                double2 gx = csub(cscale(fe(2, k), s), fe(3, k));
+                double2 gy = cadd(cscale(fe(4, k), s), fe(1, k));
+                a[tri(3 + r, c)] = cscale(ctimesi(cadd(gx, ctimesi(gy))), kc);
+            }
+#pragma unroll
+        for (int r = 0; r < 6; r++) a[tri(r, r)] = make_double2(a[tri(r, r)].x + 1.0, 0.0);
+
+        double *dg = out + (long)(b * 6) * Vh + i;
+        double2 *off = reinterpret_cast<double2 *>(out + 12L * Vh) + (long)(b * 15) * Vh + i;
+        float *dgf = outf + (long)(b * 6) * Vh + i;
+        float2 *offf = reinterpret_cast<float2 *>(outf + 12L * Vh) + (long)(b * 15) * Vh + i;
+        if (!INV) {
             int m = 0;
-            for (int r = 0; r < 6; r++)
-                for (int q = r + 1; q < 6; q++, m++) off[(long)(b * 15 + m) * g.Vh + i] = A[r * 6 + q];
+#pragma unroll
+            for (int r = 0; r < 6; r++) {
+                dg[(long)r * Vh] = a[tri(r, r)].x;
+                dgf[(long)r * Vh] = (float)a[tri(r, r)].x;
+#pragma unroll
+                for (int q = r + 1; q < 6; q++, m++) {
+                    double2 v = cconj(a[tri(q, r)]);
+                    off[(long)m * Vh] = v;
+                    offf[(long)m * Vh] = make_float2((float)v.x, (float)v.y);
+                }
+            }
+        } else {
+            // A = L L^dag in place
+            bool ok = true;
+#pragma unroll
+            for (int j = 0; j < 6; j++) {
+                double d = a[tri(j, j)].x;
+#pragma unroll
+                for (int k = 0; k < j; k++) d -= a[tri(j, k)].x * a[tri(j, k)].x + a[tri(j, k)].y * a[tri(j, k)].y;
+                ok = ok && d > 0;
+                double ljj = sqrt(d > 0 ? d : 1.0);
+                ld += 2.0 * log(ljj);
+                a[tri(j, j)] = make_double2(ljj, 0.0);
+                const double inv = 1.0 / ljj;
+#pragma unroll
+                for (int r = j + 1; r < 6; r++) {
+                    double2 v = a[tri(r, j)];
+#pragma unroll
+                    for (int k = 0; k < j; k++) v = csub(v, cmul(a[tri(r, k)], cconj(a[tri(j, k)])));
+                    a[tri(r, j)] = cscale(v, inv);
+                }
+            }
+            if (!ok) {
+                *bad = 1;
+                ld = 0;
+            }
+            // column c of A^-1: L y = e_c, then L^dag x = y; keep rows r <= c
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+                double2 y[6];
+#pragma unroll
+                for (int r = 0; r < 6; r++) {
+                    if (r < c) {
+                        y[r] = make_double2(0, 0);
+                        continue;
+                    }
+                    double2 v = make_double2(r == c ? 1.0 : 0.0, 0.0);
+#pragma unroll
+                    for (int k = c; k < r; k++) v = csub(v, cmul(a[tri(r, k)], y[k]));
+                    y[r] = cscale(v, 1.0 / a[tri(r, r)].x);
+                }
+#pragma unroll
+                for (int r = 5; r >= 0; r--) {
+                    double2 v = y[r];
+#pragma unroll
+                    for (int k = r + 1; k < 6; k++) v = csub(v, cmul(cconj(a[tri(k, r)]), y[k]));
+                    y[r] = cscale(v, 1.0 / a[tri(r, r)].x);
+                }
+                dg[(long)c * Vh] = y[c].x;
+                dgf[(long)c * Vh] = (float)y[c].x;
+#pragma unroll
+                for (int r = 0; r < c; r++) {
+                    const int m = r * 5 - r * (r - 1) / 2 + (c - r - 1);   // index of (r, c), r < c
+                    off[(long)m * Vh] = y[r];
+                    offf[(long)m * Vh] = make_float2((float)y[r].x, (float)y[r].y);
+                }
+            }
         }
     }
-    if (parity == 1) {
+    if (INV) {
         __shared__ double sh[kBlock / 64];
         for (int o = 32; o > 0; o >>= 1) ld += __shfl_down(ld, o, 64);
         if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = ld;
         __syncthreads();
         if (threadIdx.x == 0) {
-            double s = 0;
-            for (int k = 0; k < kBlock / 64; k++) s += sh[k];
-            ld_partials[blockIdx.x] = s;
+            double sum = 0;
+            for (int k = 0; k < kBlock / 64; k++) sum += sh[k];
+            ld_partials[blockIdx.x] = sum;
         }
     }
 }
 
-__global__ void k_to_f32(long n, const double *__restrict__ a, float *__restrict__ b)
-{
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t < n) b[t] = (float)a[t];
-}
-
 }  // namespace
 
-// Rebuild the clover fields of slot op on the current links.  No host
-// synchronisation: the per-block ln det partials and the positivity flag stay on
-// the device until clover_logdet() needs them.
+static int fhat_ready(pfmp_ctx *ctx)
+{
+    if (!ctx->fhat_stale) return 0;
+    const Geom &g = ctx->g;
+    if (!ctx->Fhat && hipMalloc(&ctx->Fhat, sizeof(double2) * 108L * g.Vh) != hipSuccess) {
+        ctx->Fhat = nullptr;
+        return set_err(ctx, PFMP_ERR_OOM, "clover field strength");
+    }
+    hipLaunchKernelGGL(k_fhat, dim3(nblocks(12L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, ctx->U, ctx->Fhat);
+    LAUNCHCHK(ctx);
+    ctx->fhat_stale = false;
+    return 0;
+}
+
+// Rebuild the clover fields of slot op on the current links (F-hat shared by all
+// slots).  No host synchronisation: the ln det partials and the positivity flag
+// stay on the device until clover_logdet() needs them.
 int clover_build(pfmp_ctx *ctx, int op)
 {
     OpSlot &s = ctx->ops[op];
     const Geom &g = ctx->g;
     s.logdet_odd = 0;
     s.ld_dirty = false;
+    s.stale = false;
     if (s.csw == 0) return 0;
-    const int nb = nblocks(g.Vh, kBlock);
-    if (!s.ldpart && hipMalloc(&s.ldpart, sizeof(double) * nb) != hipSuccess)
+    int rc = fhat_ready(ctx);
+    if (rc) return rc;
+    const int nb = nblocks(2L * g.Vh, kBlock);
+    if (!s.ldpart && hipMalloc(&s.ldpart, sizeof(double) * nb) != hipSuccess) {
+        s.ldpart = nullptr;
         return set_err(ctx, PFMP_ERR_OOM, "clover workspace");
+    }
     int *bad = (int *)(ctx->scal + 8000) + op;
     HIPCHK(ctx, hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
     const double kc = s.kappa * s.csw;
-    for (int p = 0; p < 2; p++) {
-        hipLaunchKernelGGL(k_clover_build, dim3(nb), dim3(kBlock), 0, ctx->stream, g, p, ctx->U, kc, s.clov[p],
-                           s.ldpart, bad);
-        LAUNCHCHK(ctx);
-        long n = clover_reals(g);
-        hipLaunchKernelGGL(k_to_f32, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, s.clov[p], s.clovf[p]);
-        LAUNCHCHK(ctx);
-    }
+    hipLaunchKernelGGL(k_clover_blocks<0>, dim3(nb), dim3(kBlock), 0, ctx->stream, g, 0, ctx->Fhat, kc, s.clov[0],
+                       s.clovf[0], s.ldpart, bad);
+    LAUNCHCHK(ctx);
+    hipLaunchKernelGGL(k_clover_blocks<1>, dim3(nb), dim3(kBlock), 0, ctx->stream, g, 1, ctx->Fhat, kc, s.clov[1],
+                       s.clovf[1], s.ldpart, bad);
+    LAUNCHCHK(ctx);
     s.ld_dirty = true;
     return 0;
+}
+
+// Slot op configured and its clover fields current for the present links.
+int op_ready(pfmp_ctx *ctx, int op)
+{
+    if (op < 0 || op >= PFMP_MAX_OPS) return set_err(ctx, PFMP_ERR_ARG, "operator slot out of range");
+    if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
+    if (!ctx->ops[op].valid) return set_err(ctx, PFMP_ERR_STATE, "operator slot not configured");
+    return ctx->ops[op].stale ? clover_build(ctx, op) : 0;
 }
 
 // Sum the ln det A_oo partials of slot op (synchronises) and check positivity.
@@ -193,7 +254,7 @@ int clover_logdet(pfmp_ctx *ctx, int op)
 {
     OpSlot &s = ctx->ops[op];
     if (!s.ld_dirty) return 0;
-    const int nb = nblocks(ctx->g.Vh, kBlock);
+    const int nb = nblocks(2L * ctx->g.Vh, kBlock);
     std::vector<double> h(nb);
     int hbad = 0;
     HIPCHK(ctx, hipMemcpyAsync(h.data(), s.ldpart, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
@@ -210,8 +271,8 @@ int clover_logdet(pfmp_ctx *ctx, int op)
 extern "C" int pfmp_logdet_action(pfmp_ctx *ctx, int op, double *out)
 {
     if (!ctx || !out || op < 0 || op >= PFMP_MAX_OPS) return ctx ? set_err(ctx, PFMP_ERR_ARG, "logdet_action") : PFMP_ERR_ARG;
-    if (!ctx->ops[op].valid) return set_err(ctx, PFMP_ERR_STATE, "operator slot not configured");
-    int rc = clover_logdet(ctx, op);
+    int rc = op_ready(ctx, op);
+    if (!rc) rc = clover_logdet(ctx, op);
     if (rc) return rc;
     *out = -2.0 * ctx->ops[op].logdet_odd;
     return 0;

@@ -175,6 +175,7 @@ extern "C" int pfmp_destroy(pfmp_ctx *ctx)
     hipStreamSynchronize(ctx->stream);
     hipFree(ctx->U);
     hipFree(ctx->Uf);
+    hipFree(ctx->Fhat);
     hipFree(ctx->red);
     hipFree(ctx->scal);
     if (ctx->red_host) hipHostFree(ctx->red_host);
@@ -218,16 +219,23 @@ extern "C" int pfmp_index_maps(pfmp_ctx *ctx, int32_t *lex_of_eo, int32_t *nbr, 
     return 0;
 }
 
+// The links changed: everything derived from them is rebuilt on first use.
 int rebuild_gauge_derived(pfmp_ctx *ctx)
 {
+    ctx->uf_stale = true;
+    ctx->fhat_stale = true;
+    for (int op = 0; op < PFMP_MAX_OPS; op++)
+        if (ctx->ops[op].valid) ctx->ops[op].stale = true;
+    return 0;
+}
+
+int gauge_f32_ready(pfmp_ctx *ctx)
+{
+    if (!ctx->uf_stale) return 0;
     long n = gauge_reals(ctx->g) / 2;
     hipLaunchKernelGGL(k_gauge_f32, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, ctx->U, ctx->Uf);
     LAUNCHCHK(ctx);
-    for (int op = 0; op < PFMP_MAX_OPS; op++)
-        if (ctx->ops[op].valid) {
-            int rc = clover_build(ctx, op);
-            if (rc) return rc;
-        }
+    ctx->uf_stale = false;
     return 0;
 }
 

@@ -178,7 +178,8 @@ static int check_op(pfmp_ctx *ctx, int op)
     if (op < 0 || op >= PFMP_MAX_OPS) return set_err(ctx, PFMP_ERR_ARG, "operator slot out of range");
     if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
     if (!ctx->ops[op].valid) return set_err(ctx, PFMP_ERR_STATE, "operator slot not configured");
-    return 0;
+    int rc = op_ready(ctx, op);
+    return rc ? rc : gauge_f32_ready(ctx);
 }
 
 extern "C" int pfmp_apply_hop(pfmp_ctx *ctx, int out_parity, int dagger, const void *in, void *out)

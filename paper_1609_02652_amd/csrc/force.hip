@@ -176,76 +176,128 @@ __global__ __launch_bounds__(kBlock) void k_logdet_insert(Geom g, const double *
     }
 }
 
-// Psi = (Phi - Phi^dag) / 8 in place
-__global__ void k_phi_to_psi(Geom g, double2 *__restrict__ Phi)
-{
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= 2L * g.Vh * 6) return;
-    int i = (int)(t % g.Vh);
-    long pp = t / g.Vh;       // p * 6 + plane
-    double2 *b = Phi + pp * 9 * g.Vh + i;
-    M3 m;
-    for (int k = 0; k < 9; k++) m.e[k] = b[(long)k * g.Vh];
-    M3 r = m3_scale(m3_sub(m, m3_dag(m)), 0.125);
-    for (int k = 0; k < 9; k++) b[(long)k * g.Vh] = r.e[k];
-}
-
-__device__ __forceinline__ M3 psi_at(const Geom &g, const double2 *__restrict__ Psi, const int *c, int mu, int nu)
+// Psi_mu_nu at the site with coordinates c, formed on load from the insertion field:
+// Psi = (Phi - Phi^dag) / 8 of the plane (min, max), with Psi_nu_mu = -Psi_mu_nu.
+// Returned as the base pointer of the 9 Phi elements and the scale +-1/8.
+__device__ __forceinline__ const double2 *psi_base(const Geom &g, const double2 *__restrict__ Phi, const int *c,
+                                                   int mu, int nu, double *sc)
 {
     int p = parity_of(c), i = eo_index(g, c);
     int a = mu < nu ? mu : nu, b = mu < nu ? nu : mu;
-    int pl = plane_index(a, b);
-    const double2 *base = Psi + ((long)(p * 6 + pl) * 9) * g.Vh + i;
-    M3 m;
-    for (int k = 0; k < 9; k++) m.e[k] = base[(long)k * g.Vh];
-    return mu < nu ? m : m3_scale(m, -1.0);     // Psi_{nu mu} = -Psi_{mu nu}
+    *sc = mu < nu ? 0.125 : -0.125;
+    return Phi + ((long)(p * 6 + plane_index(a, b)) * 9) * g.Vh + i;
 }
 
-// Zacc[link] += sum over the leaves holding the link (see header); one thread per link
-__global__ __launch_bounds__(kBlock) void k_clover_force(Geom g, const double2 *__restrict__ U,
-                                                         const double2 *__restrict__ Psi, double2 *__restrict__ Zacc)
+__device__ __forceinline__ double2 psi_el(const double2 *__restrict__ b, long st, double sc, int r, int c)
 {
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= 2L * g.Vh * 4) return;
-    int mu = (int)(t / (2L * g.Vh));
-    long r = t % (2L * g.Vh);
-    int p = (int)(r / g.Vh), i = (int)(r % g.Vh);
-    int y[4];
-    eo_coords(g, p, i, y);
-    M3 Uu = link_at(g, U, y, mu);
-    M3 Zsum = m3_zero();
-    int ypm[4];
-    shifted(g, y, mu, +1, ypm);
-    for (int nu = 0; nu < 4; nu++) {
-        if (nu == mu) continue;
-        int ypn[4], ypmpn[4], ymn[4], ymnpm[4];
-        shifted(g, y, nu, +1, ypn);
-        shifted(g, ypm, nu, +1, ypmpn);
-        shifted(g, y, nu, -1, ymn);
-        shifted(g, ymn, mu, +1, ymnpm);
-        // above: path after U from y+mu: A1 = U_nu(y+mu), A2 = U_mu(y+nu)^dag, A3 = U_nu(y)^dag
-        M3 A1 = link_at(g, U, ypm, nu);
-        M3 A2 = m3_dag(link_at(g, U, ypn, mu));
-        M3 A3 = m3_dag(link_at(g, U, y, nu));
-        M3 A23 = m3_mul(A2, A3), A12 = m3_mul(A1, A2);
-        M3 W = m3_mul(psi_at(g, Psi, ypm, mu, nu), m3_mul(A1, A23));
-        W = m3_add(W, m3_mul(m3_mul(A1, psi_at(g, Psi, ypmpn, mu, nu)), A23));
-        W = m3_add(W, m3_mul(m3_mul(A12, psi_at(g, Psi, ypn, mu, nu)), A3));
-        W = m3_add(W, m3_mul(m3_mul(A12, A3), psi_at(g, Psi, y, mu, nu)));
-        Zsum = m3_add(Zsum, m3_mul(Uu, W));
-        // below: after U^dag from y: B1 = U_nu(y-nu)^dag, B2 = U_mu(y-nu), B3 = U_nu(y-nu+mu)
-        M3 B1 = m3_dag(link_at(g, U, ymn, nu));
-        M3 B2 = link_at(g, U, ymn, mu);
-        M3 B3 = link_at(g, U, ymnpm, nu);
-        M3 B23 = m3_mul(B2, B3), B12 = m3_mul(B1, B2);
-        M3 Wb = m3_mul(psi_at(g, Psi, y, mu, nu), m3_mul(B1, B23));
-        Wb = m3_add(Wb, m3_mul(m3_mul(B1, psi_at(g, Psi, ymn, mu, nu)), B23));
-        Wb = m3_add(Wb, m3_mul(m3_mul(B12, psi_at(g, Psi, ymnpm, mu, nu)), B3));
-        Wb = m3_add(Wb, m3_mul(m3_mul(B12, B3), psi_at(g, Psi, ypm, mu, nu)));
-        Zsum = m3_sub(Zsum, m3_mul_nd(Wb, Uu));
+    return cscale(csub(b[(long)(3 * r + c) * st], cconj(b[(long)(3 * c + r) * st])), sc);
+}
+
+// Psi X, one row of Psi at a time
+__device__ __forceinline__ M3 psi_mul(const double2 *__restrict__ b, long st, double sc, const M3 &X)
+{
+    M3 r;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        double2 p0 = psi_el(b, st, sc, i, 0), p1 = psi_el(b, st, sc, i, 1), p2 = psi_el(b, st, sc, i, 2);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            double2 v = cmul(p0, X.e[k]);
+            cfma(v, p1, X.e[3 + k]);
+            cfma(v, p2, X.e[6 + k]);
+            r.e[3 * i + k] = v;
+        }
     }
-    double2 *zb = Zacc + ((long)(p * 4 + mu) * 9) * g.Vh + i;
-    for (int k = 0; k < 9; k++) zb[(long)k * g.Vh] = cadd(zb[(long)k * g.Vh], Zsum.e[k]);
+    return r;
+}
+
+// X Psi, one column of Psi at a time
+__device__ __forceinline__ M3 mul_psi(const M3 &X, const double2 *__restrict__ b, long st, double sc)
+{
+    M3 r;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        double2 p0 = psi_el(b, st, sc, 0, k), p1 = psi_el(b, st, sc, 1, k), p2 = psi_el(b, st, sc, 2, k);
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            double2 v = cmul(X.e[3 * i], p0);
+            cfma(v, X.e[3 * i + 1], p1);
+            cfma(v, X.e[3 * i + 2], p2);
+            r.e[3 * i + k] = v;
+        }
+    }
+    return r;
+}
+
+// Clover force: F[link] += coefficients of U_mu(y) S with
+//   S = sum_{nu != mu} sum_{s = +1, -1} s * sum over the 4 corners of the leaf that
+//       runs y+mu -> y+mu+s nu -> y+s nu -> y of the path with Psi inserted at the corner.
+// The leaf below the link enters as the adjoint of its own path: the coefficient map
+// Z -> Re tr[i T_a Z] is odd under Z -> Z^dag and Psi is anti-Hermitian, so
+// -W_b U^dag and U W_b^dag give the same force.  With the path L1 L2 L3 and corner
+// insertions Psi1..Psi4 the sum is taken Horner-fashion:
+//   Q = Psi1 L1 + L1 Psi2,  Q = Q L2 + (L1 L2) Psi3,  Q = Q L3 + (L1 L2 L3) Psi4.
+// Two lanes per link (the two sides s); the 8 coefficients of each leaf are
+// accumulated and the two lanes summed by a lane swap.
+__global__ __launch_bounds__(kBlock) void k_clover_force(Geom g, const double2 *__restrict__ U,
+                                                         const double2 *__restrict__ Phi, double *__restrict__ F)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long l = t >> 1;
+    const int side = (int)(t & 1);
+    const bool ok = l < 8L * g.Vh;
+    const long st = g.Vh;
+    double f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int mu = 0, p = 0, i = 0;
+    if (ok) {
+        mu = (int)(l / (2L * g.Vh));
+        const long r = l - (long)mu * 2L * g.Vh;
+        p = (int)(r / g.Vh);
+        i = (int)(r - (long)p * g.Vh);
+        int y[4], ypm[4];
+        eo_coords(g, p, i, y);
+        shifted(g, y, mu, +1, ypm);
+        const int sg = side ? -1 : 1;
+#pragma unroll 1
+        for (int nu = 0; nu < 4; nu++) {
+            if (nu == mu) continue;
+            int yn[4], ypmn[4];
+            shifted(g, y, nu, sg, yn);          // y + s nu
+            shifted(g, ypm, nu, sg, ypmn);      // y + mu + s nu
+            double sc;
+            const double2 *b;
+            // L1: y+mu -> y+mu+s nu
+            M3 L1 = side ? m3_dag(link_at(g, U, ypmn, nu)) : link_at(g, U, ypm, nu);
+            b = psi_base(g, Phi, ypm, mu, nu, &sc);
+            M3 Q = psi_mul(b, st, sc, L1);
+            b = psi_base(g, Phi, ypmn, mu, nu, &sc);
+            Q = m3_add(Q, mul_psi(L1, b, st, sc));
+            // L2: y+mu+s nu -> y+s nu
+            M3 L2 = m3_dag(link_at(g, U, yn, mu));
+            M3 R = m3_mul(L1, L2);
+            Q = m3_mul(Q, L2);
+            b = psi_base(g, Phi, yn, mu, nu, &sc);
+            Q = m3_add(Q, mul_psi(R, b, st, sc));
+            // L3: y+s nu -> y
+            M3 L3 = side ? link_at(g, U, yn, nu) : m3_dag(link_at(g, U, y, nu));
+            R = m3_mul(R, L3);
+            Q = m3_mul(Q, L3);
+            b = psi_base(g, Phi, y, mu, nu, &sc);
+            Q = m3_add(Q, mul_psi(R, b, st, sc));
+            // coefficients of s U_mu(y) Q
+            double fl[8];
+            lie_coeffs(m3_mul(link_at(g, U, y, mu), Q), fl);
+#pragma unroll
+            for (int a = 0; a < 8; a++) f[a] += side ? -fl[a] : fl[a];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 8; a++) f[a] += __shfl_xor(f[a], 1, 64);
+    if (ok && side == 0) {
+        double *fb = F + ((long)(p * 4 + mu) * 8) * g.Vh + i;
+#pragma unroll
+        for (int a = 0; a < 8; a++) fb[(long)a * g.Vh] += f[a];
+    }
 }
 
 // F[link] += coefficients of Z1 * s1 + Z2 * s2 (either may be null)
@@ -414,12 +466,12 @@ static int force_ws(pfmp_ctx *ctx, double2 **Zhop, double2 **Phi, double2 **Xo, 
     return 0;
 }
 
-static int clover_force_finish(pfmp_ctx *ctx, double2 *Phi, double2 *Zacc)
+// F += clover force of the insertion field Phi
+static int clover_force_add(pfmp_ctx *ctx, const double2 *Phi, double *F)
 {
     const Geom &g = ctx->g;
-    hipLaunchKernelGGL(k_phi_to_psi, dim3(nblocks(2L * g.Vh * 6, 256)), dim3(256), 0, ctx->stream, g, Phi);
-    hipLaunchKernelGGL(k_clover_force, dim3(nblocks(2L * g.Vh * 4, kBlock)), dim3(kBlock), 0, ctx->stream, g, ctx->U,
-                       Phi, Zacc);
+    hipLaunchKernelGGL(k_clover_force, dim3(nblocks(16L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, ctx->U,
+                       Phi, F);
     LAUNCHCHK(ctx);
     return 0;
 }
@@ -430,6 +482,7 @@ extern "C" int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void 
     if (!ctx) return PFMP_ERR_ARG;
     if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
         return set_err(ctx, PFMP_ERR_STATE, "fermion_force: operator not configured");
+    if (int rc0 = op_ready(ctx, op)) return rc0;
     if (npairs < 0 || (npairs > 0 && (!X || !Y || !coeff)) || !F)
         return set_err(ctx, PFMP_ERR_ARG, "fermion_force: bad arguments");
     for (int q = 0; q < npairs; q++)
@@ -463,16 +516,12 @@ extern "C" int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void 
         }
         LAUNCHCHK(ctx);
     }
-    double2 *Zcl = nullptr;
-    if (do_clov) {
-        Zcl = (double2 *)ws_alloc(ctx, sizeof(double2) * 2L * 4 * 9 * g.Vh, 19);
-        if (!Zcl) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
-        HIPCHK(ctx, hipMemsetAsync(Zcl, 0, sizeof(double2) * 2L * 4 * 9 * g.Vh, ctx->stream));
-        if ((rc = clover_force_finish(ctx, Phi, Zcl))) return rc;
+    if (do_clov && (rc = clover_force_add(ctx, Phi, F))) return rc;
+    if (do_hop) {
+        hipLaunchKernelGGL(k_force_finish, dim3(nblocks(2L * g.Vh * 4, 256)), dim3(256), 0, ctx->stream, g, Zhop,
+                           -k2, (const double2 *)nullptr, 0.0, F);
+        LAUNCHCHK(ctx);
     }
-    hipLaunchKernelGGL(k_force_finish, dim3(nblocks(2L * g.Vh * 4, 256)), dim3(256), 0, ctx->stream, g,
-                       do_hop ? Zhop : nullptr, -k2, Zcl, 1.0, F);
-    LAUNCHCHK(ctx);
     return 0;
 }
 
@@ -481,24 +530,20 @@ extern "C" int pfmp_logdet_force(pfmp_ctx *ctx, int op, double coef, double *F)
     if (!ctx) return PFMP_ERR_ARG;
     if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
         return set_err(ctx, PFMP_ERR_STATE, "logdet_force: operator not configured");
+    if (int rc0 = op_ready(ctx, op)) return rc0;
     if (!F) return set_err(ctx, PFMP_ERR_ARG, "logdet_force: null force");
     OpSlot &s = ctx->ops[op];
     if (s.csw == 0) return 0;
     const Geom &g = ctx->g;
-    double2 *Zcl, *Phi;
-    int rc = force_ws(ctx, &Zcl, &Phi, nullptr, nullptr);
+    double2 *Zhop, *Phi;
+    int rc = force_ws(ctx, &Zhop, &Phi, nullptr, nullptr);
     if (rc) return rc;
-    HIPCHK(ctx, hipMemsetAsync(Zcl, 0, sizeof(double2) * 2L * 4 * 9 * g.Vh, ctx->stream));
     HIPCHK(ctx, hipMemsetAsync(Phi, 0, sizeof(double2) * 2L * 6 * 9 * g.Vh, ctx->stream));
     double2 fac = ctimesi(make_double2(-2.0 * coef * s.kappa * s.csw, 0));
     hipLaunchKernelGGL(k_logdet_insert, dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, s.clov[1], fac,
                        Phi);
     LAUNCHCHK(ctx);
-    if ((rc = clover_force_finish(ctx, Phi, Zcl))) return rc;
-    hipLaunchKernelGGL(k_force_finish, dim3(nblocks(2L * g.Vh * 4, 256)), dim3(256), 0, ctx->stream, g, Zcl, 1.0,
-                       nullptr, 0.0, F);
-    LAUNCHCHK(ctx);
-    return 0;
+    return clover_force_add(ctx, Phi, F);
 }
 
 extern "C" int pfmp_gauge_force(pfmp_ctx *ctx, double beta, double *F)

@@ -413,25 +413,30 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
     const pfmp_hmc_spec *sp = X.sp;
     const int nt = sp->nterms + 1;
     const double lam = sp->lambda != 0 ? sp->lambda : kOmelyanLambda;
+    // rows: gauge, the terms, and S_det on its own scale when det_steps > 0
+    const bool det_row = sp->det_steps > 0 && sp->det_op >= 0;
+    const int nrow = nt + (det_row ? 1 : 0);
     int64_t L = 2LL * sp->gauge_steps;
     for (int j = 0; j < sp->nterms; j++) L = lcm64(L, 2LL * sp->terms[j].steps);
+    if (det_row) L = lcm64(L, 2LL * sp->det_steps);
     std::vector<Scheme> sch;
     sch.push_back(omelyan(sp->gauge_steps, L, sp->tau, lam));
     for (int j = 0; j < sp->nterms; j++) sch.push_back(omelyan(sp->terms[j].steps, L, sp->tau, lam));
-    std::vector<int> len(nt);
+    if (det_row) sch.push_back(omelyan(sp->det_steps, L, sp->tau, lam));
+    std::vector<int> len(nrow);
     std::vector<int64_t> T;
     std::vector<double> S;
     int cap = 0;
-    for (int j = 0; j < nt; j++) {
+    for (int j = 0; j < nrow; j++) {
         len[j] = (int)sch[j].T.size();
         cap += len[j];
         T.insert(T.end(), sch[j].T.begin(), sch[j].T.end());
         S.insert(S.end(), sch[j].S.begin(), sch[j].S.end());
     }
     std::vector<int64_t> To(cap);
-    std::vector<double> So((size_t)cap * nt);
+    std::vector<double> So((size_t)cap * nrow);
     int nout = 0;
-    int rc = pfmp_schedule_build(nt, len.data(), T.data(), S.data(), cap, To.data(), So.data(), &nout);
+    int rc = pfmp_schedule_build(nrow, len.data(), T.data(), S.data(), cap, To.data(), So.data(), &nout);
     if (rc) return set_err(ctx, rc, "hmc: schedule merge failed");
     double *F = (double *)ws_alloc(ctx, sizeof(double) * mom_reals(ctx->g), 24);
     if (!F) return set_err(ctx, PFMP_ERR_OOM, "force buffer");
@@ -439,11 +444,12 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
     if (st) {
         st->nsteps = nout;
         for (int j = 0; j < nt; j++) st->nforce[j] = 0;
+        st->nforce_det = 0;
     }
     for (int k = 0; k < nout; k++) {
         if (To[k] != 0 && (rc = pfmp_update_gauge(ctx, tick * (double)To[k], P))) return rc;
         bool any = false;
-        for (int j = 0; j < nt; j++) any = any || So[(size_t)j * cap + k] != 0.0;
+        for (int j = 0; j < nrow; j++) any = any || So[(size_t)j * cap + k] != 0.0;
         if (!any) continue;
         HIPCHK(ctx, hipMemsetAsync(F, 0, sizeof(double) * mom_reals(ctx->g), ctx->stream));
         // the CG solves of the RATIO / HEAVY terms due at this step, as one multi-RHS solve
@@ -506,9 +512,16 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
             if (st) st->nforce[j]++;
             if (j == 0) {
                 if ((rc = pfmp_gauge_force(ctx, sp->beta * eps, F))) return rc;
-                if (sp->det_op >= 0 && (rc = pfmp_logdet_force(ctx, sp->det_op, eps, F))) return rc;
+                if (sp->det_op >= 0 && !det_row && (rc = pfmp_logdet_force(ctx, sp->det_op, eps, F))) return rc;
             } else if ((rc = term_force(X, sp->terms[j - 1], phi[j - 1], eps, F, pre[j]))) {
                 return rc;
+            }
+        }
+        if (det_row) {
+            double eps = So[(size_t)nt * cap + k];
+            if (eps != 0.0) {
+                if (st) st->nforce_det++;
+                if ((rc = pfmp_logdet_force(ctx, sp->det_op, eps, F))) return rc;
             }
         }
         if ((rc = pfmp_update_momenta(ctx, 1.0, F, P))) return rc;

@@ -119,6 +119,7 @@ struct OpSlot {
     double logdet_odd = 0;                  // sum_{x odd} ln det A(x)
     double *ldpart = nullptr;               // per-block ln det A_oo partials (device)
     bool ld_dirty = false;                  // ldpart newer than logdet_odd
+    bool stale = false;                     // links changed since the clover fields were built
 };
 
 struct SolverWS;
@@ -130,6 +131,9 @@ struct pfmp_ctx {
     double2 *U = nullptr;        // internal FP64 gauge field
     float2 *Uf = nullptr;        // FP32 copy
     bool have_gauge = false;
+    bool uf_stale = true;        // Uf older than U
+    double2 *Fhat = nullptr;     // clover field strength [2 parities][6 planes][9][Vh], shared by all slots
+    bool fhat_stale = true;      // Fhat older than U
     OpSlot ops[PFMP_MAX_OPS];
     double *red = nullptr;       // reduction partials
     double *red_host = nullptr;  // pinned host mirror of a few scalars
@@ -187,6 +191,10 @@ int rebuild_gauge_derived(pfmp_ctx *ctx);
 int red_finish_dev(pfmp_ctx *ctx, const double *partials, int nparts, int nvals, double *dev_out);
 // clover (clover.hip)
 int clover_build(pfmp_ctx *ctx, int op);
+// slot valid and its clover fields current (rebuilt on first use after a link update)
+int op_ready(pfmp_ctx *ctx, int op);
+// FP32 copy of the links current (context.hip)
+int gauge_f32_ready(pfmp_ctx *ctx);
 int clover_logdet(pfmp_ctx *ctx, int op);
 // reductions (blas.hip)
 int red_finish(pfmp_ctx *ctx, const double *partials, int nparts, int nvals, double *host_out);

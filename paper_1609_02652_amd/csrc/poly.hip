@@ -76,6 +76,7 @@ extern "C" int pfmp_apply_poly(pfmp_ctx *ctx, int op, int n, const double *roots
     if (!ctx) return PFMP_ERR_ARG;
     if (op < 0 || op >= PFMP_MAX_OPS || !ctx->have_gauge || !ctx->ops[op].valid)
         return set_err(ctx, PFMP_ERR_STATE, "apply_poly: operator not configured");
+    if (int rc0 = op_ready(ctx, op)) return rc0;
     if (n < 0 || (n > 0 && !roots) || !norm || !in || !out)
         return set_err(ctx, PFMP_ERR_ARG, "apply_poly: bad arguments");
     if (prec != PFMP_F64) return set_err(ctx, PFMP_ERR_ARG, "apply_poly: FP64 only");

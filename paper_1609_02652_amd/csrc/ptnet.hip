@@ -317,6 +317,7 @@ struct PtWs {
 
 static int pt_ws(pfmp_ctx *ctx, const double *Wc, PtWs &w)
 {
+    if (int rc0 = gauge_f32_ready(ctx)) return rc0;
     const Geom &g = ctx->g;
     const size_t hb = sizeof(float2) * 36L * g.Vh, zb = sizeof(float2) * 12L * g.Vh;
     const long nwaves = (long)nblocks(g.Vh, kBlock) * (kBlock / 64);
@@ -464,6 +465,8 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
         return ctx ? set_err(ctx, PFMP_ERR_ARG, "fcg_solve: bad arguments") : PFMP_ERR_ARG;
     if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
         return set_err(ctx, PFMP_ERR_STATE, "fcg_solve: operator not configured");
+    if (int rc0 = op_ready(ctx, op)) return rc0;
+    if (int rc0 = gauge_f32_ready(ctx)) return rc0;
     auto t0 = std::chrono::steady_clock::now();
     const Geom &g = ctx->g;
     const long n = 12L * g.Vh;
@@ -568,6 +571,7 @@ extern "C" int pfmp_cg_harvest(pfmp_ctx *ctx, int op, const void *b_, void *x_, 
         return ctx ? set_err(ctx, PFMP_ERR_ARG, "cg_harvest: bad arguments") : PFMP_ERR_ARG;
     if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
         return set_err(ctx, PFMP_ERR_STATE, "cg_harvest: operator not configured");
+    if (int rc0 = op_ready(ctx, op)) return rc0;
     const Geom &g = ctx->g;
     const long n = 12L * g.Vh;
     const size_t vb = sizeof(double) * spinor_reals(g);

@@ -267,7 +267,8 @@ static int check_solver_args(pfmp_ctx *ctx, int op, const pfmp_solver_params *p)
     if (op < 0 || op >= PFMP_MAX_OPS) return set_err(ctx, PFMP_ERR_ARG, "operator slot out of range");
     if (!ctx->have_gauge || !ctx->ops[op].valid) return set_err(ctx, PFMP_ERR_STATE, "operator not configured");
     if (!p || !(p->tol > 0) || p->maxiter <= 0) return set_err(ctx, PFMP_ERR_ARG, "solver parameters");
-    return 0;
+    int rc = op_ready(ctx, op);
+    return rc ? rc : gauge_f32_ready(ctx);
 }
 
 struct CGBufs {

@@ -63,21 +63,22 @@ class HmcSpec(ctypes.Structure):
                 ("tau", ctypes.c_double), ("lam", ctypes.c_double), ("nterms", ctypes.c_int),
                 ("terms", ctypes.POINTER(Term)), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int),
                 ("exact_start", ctypes.c_int), ("solver_prec", ctypes.c_int), ("ptnet", ctypes.c_void_p),
-                ("batch", ctypes.c_int)]
+                ("batch", ctypes.c_int), ("det_steps", ctypes.c_int)]
 
 
 class TrajStats(ctypes.Structure):
     _fields_ = [("H0", ctypes.c_double), ("H1", ctypes.c_double), ("dH", ctypes.c_double), ("accept", ctypes.c_int),
                 ("nsteps", ctypes.c_int), ("nforce", ctypes.c_int * (MAX_TERMS + 1)), ("kmults", ctypes.c_longlong),
                 ("solver_iters", ctypes.c_longlong), ("seconds", ctypes.c_double),
-                ("parts0", ctypes.c_double * (MAX_TERMS + 3)), ("parts1", ctypes.c_double * (MAX_TERMS + 3))]
+                ("parts0", ctypes.c_double * (MAX_TERMS + 3)), ("parts1", ctypes.c_double * (MAX_TERMS + 3)),
+                ("nforce_det", ctypes.c_int)]
 
     def as_dict(self, nterms):
         return {"H0": self.H0, "H1": self.H1, "dH": self.dH, "accept": bool(self.accept), "nsteps": self.nsteps,
                 "nforce": [self.nforce[k] for k in range(nterms + 1)], "kmults": self.kmults,
                 "solver_iters": self.solver_iters, "seconds": self.seconds,
                 "parts0": [self.parts0[k] for k in range(nterms + 3)],
-                "parts1": [self.parts1[k] for k in range(nterms + 3)]}
+                "parts1": [self.parts1[k] for k in range(nterms + 3)], "nforce_det": self.nforce_det}
 
 
 _lib = None
@@ -489,10 +490,11 @@ class Lattice:
     # ---------------------------------------------------------------- HMC
     @staticmethod
     def spec(beta, terms, gauge_steps, det_op=-1, tau=1.0, lam=0.0, tol=1e-10, maxiter=100000,
-             exact_start=False, solver_prec=F64, ptnet=None, batch=False):
+             exact_start=False, solver_prec=F64, ptnet=None, batch=False, det_steps=0):
         """terms: list of dicts {kind, op, op2, n, mu, nu, steps}; ptnet: (W1, W2, W0) or None;
         batch: the solves of all ratio / heavy terms due at one merged step run as one
-        multi-RHS solve (FP64 plain CG)."""
+        multi-RHS solve (FP64 plain CG); det_steps: S_det on its own 2MN scale (0: with the
+        gauge action)."""
         arr = (Term * max(1, len(terms)))()
         for k, t in enumerate(terms):
             arr[k] = Term(TERM_KINDS[t["kind"]], t["op"], t.get("op2", -1), t.get("n", 0), t.get("mu", 0.0),
@@ -502,7 +504,7 @@ class Lattice:
             keep_w = Lattice._weights(ptnet).copy()
             wp = keep_w.ctypes.data
         sp = HmcSpec(beta, det_op, gauge_steps, tau, lam, len(terms), arr, tol, maxiter, int(exact_start),
-                     int(solver_prec), wp, int(batch))
+                     int(solver_prec), wp, int(batch), int(det_steps))
         sp._keep = (arr, keep_w)
         return sp
 

@@ -162,3 +162,22 @@ def test_batched_and_mixed_solves_in_trajectory(U0):
                                                           ref["solver_iters"]), flush=True)
         assert abs(st["dH"] - ref["dH"]) < 1e-8
         assert np.max(np.abs(Ug - Uref)) < 1e-9
+
+
+def test_trajectory_det_on_own_scale_matches_oracle(U0):
+    """S_det on its own 2MN scale (one more row of the merged schedule)."""
+    P0 = synth.gaussian_momenta(256, 104)
+    etas = [synth.gaussian_spinor(128, 60 + j) for j in range(2)]
+    ospec = oracle_spec(steps=(10, 20, 40, 80), terms=(0, 2))
+    ospec["det_steps"] = 20
+    ref = hmc.trajectory(ospec, U0, P0, etas, u=0.5, tol=1e-12)
+    lat = make_lattice(U0)
+    n_jk, n_corr, n_p, n_g = 10, 20, 40, 80
+    terms = [dict(kind="poly", op=1, n=4, mu=1.2, nu=0.9, steps=n_p), dict(kind="ratio", op=1, op2=0, steps=n_jk)]
+    sp = lat.spec(BETA, terms, n_g, det_op=0, tol=1e-12, exact_start=True, det_steps=20)
+    st = lat.trajectory(sp, lat.pack_momenta(P0), [lat.pack_spinor(e) for e in etas], 0.5)
+    print("det scale: dH gpu %.12f oracle %.12f" % (st["dH"], ref["dH"]), st["nforce"], st["nforce_det"],
+          ref["nforce"], flush=True)
+    assert st["nforce"] + [st["nforce_det"]] == ref["nforce"]
+    assert abs(st["dH"] - ref["dH"]) < 1e-7
+    lat.close()

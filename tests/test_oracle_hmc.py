@@ -226,3 +226,15 @@ def test_exp_minus_dH_average_quenched():
     m = np.mean(vals)
     err = np.std(vals) / math.sqrt(len(vals))
     assert abs(m - 1) < 3 * err + 1e-3, (m, err)
+
+
+def test_schedule_with_det_row_sums_to_tau():
+    """With S_det on its own scale the merged schedule has one more row; every
+    row's space steps and the time steps each add up to tau (App. B)."""
+    spec = dict(dims=(4, 4, 4, 4), gauge_steps=8, terms=[dict(steps=2), dict(steps=4)], det_steps=3, tau=1.0)
+    T, S = hmc.build_schedule(spec)
+    assert len(S) == 4
+    assert abs(sum(float(t) for t in T) - 1.0) < 1e-12
+    for row in S:
+        assert abs(sum(float(s) for s in row) - 1.0) < 1e-12
+    assert sum(1 for s in S[3] if s != 0) == 2 * 3 + 1  # 2MN, 3 steps: 2n + 1 space steps after merging
