@@ -10,23 +10,25 @@
 namespace {
 
 // out = [g5] A^-1 D in [g5], output parity pout (CLOV = 0: no clover); In / Out are
-// spinor pointers of the register type C or FP16 storage (HalfField)
+// spinor pointers of the register type C or FP16 storage (HalfField).  Two lanes per
+// site, lane hb writing chiral block hb.
 template <typename C, typename R, int CLOV, typename In, typename Out>
 __global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const In in, const C *__restrict__ U,
                                                         const R *__restrict__ cl, Out out, R gin, R gout,
                                                         const double *__restrict__ stop)
 {
     if (stop && stop[0] != 0) return;
-    int i = xcd_site(g.Vh);
-    if (i < 0) return;
-    C acc[12];
-    hop_all<C>(g, pout, i, in, U, gin, acc);
+    const int tt = xcd_site(2 * g.Vh);
+    if (tt < 0) return;
+    const int i = tt >> 1, hb = tt & 1;
+    C blk[6];
+    hop_pair<C>(g, pout, i, hb, in, U, gin, blk);
     if (CLOV) {
-        C t[12];
-        clover_apply<R, C>(cl, g.Vh, i, acc, t);
-        store_spinor(out, g.Vh, i, gout, t);
+        C t[6];
+        clover_block<R, C>(cl, g.Vh, i, hb, blk, t);
+        store_block(out, g.Vh, i, hb, gout, t);
     } else {
-        store_spinor(out, g.Vh, i, gout, acc);
+        store_block(out, g.Vh, i, hb, gout, blk);
     }
 }
 
@@ -37,20 +39,21 @@ __global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const X x
                                                      R gs, double *partials, const double *__restrict__ stop)
 {
     if (stop && stop[0] != 0) return;
-    int i = xcd_site(g.Vh);
+    const int tt = xcd_site(2 * g.Vh);
     double nrm = 0;
-    if (i >= 0) {
-        C acc[12], xv[12], ax[12];
-        hop_all<C>(g, pout, i, t, U, (R)1, acc);
-        load_spinor(x, g.Vh, i, gs, xv);
-        if (CLOV) clover_apply<R, C>(cl, g.Vh, i, xv, ax);
+    if (tt >= 0) {
+        const int i = tt >> 1, hb = tt & 1;
+        C acc[6], xv[6], ax[6];
+        hop_pair<C>(g, pout, i, hb, t, U, (R)1, acc);
+        load_block(x, g.Vh, i, hb, gs, xv);
+        if (CLOV) clover_block<R, C>(cl, g.Vh, i, hb, xv, ax);
 #pragma unroll
-        for (int k = 0; k < 12; k++) {
+        for (int k = 0; k < 6; k++) {
             C base = CLOV ? ax[k] : xv[k];
             acc[k] = mk<C>(base.x + a * acc[k].x, base.y + a * acc[k].y);
             if (NORM) nrm += (double)acc[k].x * acc[k].x + (double)acc[k].y * acc[k].y;
         }
-        store_spinor(out, g.Vh, i, gs, acc);
+        store_block(out, g.Vh, i, hb, gs, acc);
     }
     if (NORM) block_sum_store<C>(nrm, partials);
 }
@@ -61,7 +64,7 @@ template <typename C, typename R, typename In, typename Out>
 int launch_clovinv(pfmp_ctx *ctx, int pout, In in, const C *U, const R *cl, Out out, R gin, R gout, bool clov,
                    const double *stop)
 {
-    dim3 grid(nblocks_site(ctx->g.Vh)), block(kBlock);
+    dim3 grid(op_nparts(ctx->g)), block(kBlock);
     if (clov)
         hipLaunchKernelGGL((k_hop_clovinv<C, R, 1, In, Out>), grid, block, 0, ctx->stream, ctx->g, pout, in, U, cl,
                            out, gin, gout, stop);
@@ -76,7 +79,7 @@ template <typename C, typename R, typename X, typename T, typename Out>
 int launch_xpay(pfmp_ctx *ctx, int pout, X x, T t, const C *U, const R *cl, R a, Out out, R gs, bool clov,
                 double *partials, const double *stop)
 {
-    dim3 grid(nblocks_site(ctx->g.Vh)), block(kBlock);
+    dim3 grid(op_nparts(ctx->g)), block(kBlock);
 #define XPAY(CL, NM)                                                                                               \
     hipLaunchKernelGGL((k_hop_xpay<C, R, CL, NM, X, T, Out>), grid, block, 0, ctx->stream, ctx->g, pout, x, t, U, cl, \
                        a, out, gs, partials, stop)

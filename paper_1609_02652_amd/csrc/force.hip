@@ -43,68 +43,128 @@ __device__ __forceinline__ M3 pauli_contract(int type, const M3 *O)
     return m3_sub(O[0], O[3]);                                                   // s_z
 }
 
-// colour outer product a b^dag of two colour vectors
-__device__ __forceinline__ M3 outer(const double2 *a, const double2 *b)
-{
-    M3 r;
-    for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++) r.e[3 * i + j] = cmulc(b[j], a[i]);
-    return r;
-}
-
 // ---------------------------------------------------------------- hop part
 
+// Up to kForcePairs bilinears (X_q, Y_q) with coefficients c_q in one launch; Xo_q and
+// Zo_q are their odd-site intermediates (see the header).
+constexpr int kForcePairs = 8;
+struct PairSet {
+    int n;
+    const double2 *X[kForcePairs], *Xo[kForcePairs], *Y[kForcePairs], *Zo[kForcePairs];
+    double2 c[kForcePairs];
+};
+
+// c (U G_A) + conj(c) (U G_B^dag): the coefficient map is odd under Z -> Z^dag, so
+// this gives the force of c (U G_A - G_B U^dag)
 template <int MU>
-__device__ __forceinline__ void hop_force_dir(const Geom &g, int p, int i, const int *c, const double2 *__restrict__ Le,
-                                              const double2 *__restrict__ Lo, const double2 *__restrict__ Re,
-                                              const double2 *__restrict__ Ro, const double2 *__restrict__ U,
-                                              double2 coef, double2 *__restrict__ Zacc)
+__device__ __forceinline__ void hop_force_link(const Geom &g, int p, int i, const int *c, const PairSet &ps,
+                                               const double2 *__restrict__ U, double scale, double *__restrict__ F)
 {
-    const double2 *Lx = p == 0 ? Le : Lo, *Rx = p == 0 ? Re : Ro;
-    const double2 *Ly = p == 0 ? Lo : Le, *Ry = p == 0 ? Ro : Re;
     int s;
-    int j = eo_neighbour(g, c, MU, +1, &s);
-    double2 v[12], hL[6], hR[6];
-    // G_A: (1 - g) projections of R(x+mu) and L(x)
-    load_spinor(Ry, g.Vh, j, 1.0, v);
-    project<MU, -1>(v, hR);
-    load_spinor(Lx, g.Vh, i, 1.0, v);
-    project<MU, -1>(v, hL);
-    M3 GA = m3_add(outer(hR, hL), outer(hR + 3, hL + 3));
-    // G_B: (1 + g) projections of R(x) and L(x+mu)
-    load_spinor(Rx, g.Vh, i, 1.0, v);
-    project<MU, +1>(v, hR);
-    load_spinor(Ly, g.Vh, j, 1.0, v);
-    project<MU, +1>(v, hL);
-    M3 GB = m3_add(outer(hR, hL), outer(hR + 3, hL + 3));
+    const int j = eo_neighbour(g, c, MU, +1, &s);
+    M3 M = m3_zero();
+    for (int q = 0; q < ps.n; q++) {
+        const double2 *Lx = p == 0 ? ps.X[q] : ps.Xo[q], *Rx = p == 0 ? ps.Y[q] : ps.Zo[q];
+        const double2 *Ly = p == 0 ? ps.Xo[q] : ps.X[q], *Ry = p == 0 ? ps.Zo[q] : ps.Y[q];
+        double2 v[12], hL[6], hR[6];
+        // G_A: (1 - g) projections of R(x+mu) and L(x)
+        load_spinor(Ry, g.Vh, j, 1.0, v);
+        project<MU, -1>(v, hR);
+        load_spinor(Lx, g.Vh, i, 1.0, v);
+        project<MU, -1>(v, hL);
+        const double2 cq = ps.c[q], cc = cconj(cq);
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                double2 o = cadd(cmulc(hL[b], hR[a]), cmulc(hL[3 + b], hR[3 + a]));   // (G_A)_ab
+                cfma(M.e[3 * a + b], cq, o);
+            }
+        // G_B: (1 + g) projections of R(x) and L(x+mu); add conj(c) G_B^dag
+        load_spinor(Rx, g.Vh, i, 1.0, v);
+        project<MU, +1>(v, hR);
+        load_spinor(Ly, g.Vh, j, 1.0, v);
+        project<MU, +1>(v, hL);
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                double2 o = cadd(cmulc(hL[b], hR[a]), cmulc(hL[3 + b], hR[3 + a]));   // (G_B)_ab
+                cfma(M.e[3 * b + a], cc, cconj(o));
+            }
+    }
     M3 Uu;
     const double2 *ub = U + ((long)(p * 4 + MU) * 9) * g.Vh + i;
+#pragma unroll
     for (int k = 0; k < 9; k++) Uu.e[k] = ub[(long)k * g.Vh];
-    M3 Z = m3_sub(m3_mul(Uu, GA), m3_mul_nd(GB, Uu));
-    double2 cs = cscale(coef, (double)s);
-    double2 *zb = Zacc + ((long)(p * 4 + MU) * 9) * g.Vh + i;
-    for (int k = 0; k < 9; k++) {
-        double2 z = zb[(long)k * g.Vh];
-        cfma(z, cs, Z.e[k]);
-        zb[(long)k * g.Vh] = z;
+    double f[8];
+    lie_coeffs(m3_mul(Uu, M), f);
+    double *fb = F + ((long)(p * 4 + MU) * 8) * g.Vh + i;
+    const double sc = scale * (double)s;
+#pragma unroll
+    for (int a = 0; a < 8; a++) fb[(long)a * g.Vh] += sc * f[a];
+}
+
+// F[link] += scale * (hopping-term force of all pairs); one thread per link
+__global__ __launch_bounds__(kBlock) void k_hop_force_multi(Geom g, PairSet ps, const double2 *__restrict__ U,
+                                                            double scale, double *__restrict__ F)
+{
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 8L * g.Vh) return;
+    const int mu = (int)(t / (2L * g.Vh));
+    const long r = t - (long)mu * 2L * g.Vh;
+    const int p = (int)(r / g.Vh), i = (int)(r - (long)p * g.Vh);
+    int c[4];
+    eo_coords(g, p, i, c);
+    switch (mu) {
+    case 0: hop_force_link<0>(g, p, i, c, ps, U, scale, F); break;
+    case 1: hop_force_link<1>(g, p, i, c, ps, U, scale, F); break;
+    case 2: hop_force_link<2>(g, p, i, c, ps, U, scale, F); break;
+    default: hop_force_link<3>(g, p, i, c, ps, U, scale, F); break;
     }
 }
 
-// Zacc[link] += c s (U G_A - G_B U^dag) for every link; one thread per site
-__global__ __launch_bounds__(kBlock) void k_hop_force(Geom g, const double2 *__restrict__ Le,
-                                                      const double2 *__restrict__ Lo, const double2 *__restrict__ Re,
-                                                      const double2 *__restrict__ Ro, const double2 *__restrict__ U,
-                                                      double2 coef, double2 *__restrict__ Zacc)
+// Phi_pl(x) (+)= sum_q fac(x) c_q sum_{s,t} sigma_pl[s][t] R_t L_s^dag, fac = fe (even) / fo
+// (odd), L = (X | Xo), R = (Y | Zo); one thread per (parity, plane, site)
+__global__ __launch_bounds__(kBlock) void k_clover_insert_multi(Geom g, PairSet ps, double2 fe, double2 fo,
+                                                                int accumulate, double2 *__restrict__ Phi)
 {
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= 2L * g.Vh) return;
-    int p = (int)(t / g.Vh), i = (int)(t % g.Vh);
-    int c[4];
-    eo_coords(g, p, i, c);
-    hop_force_dir<0>(g, p, i, c, Le, Lo, Re, Ro, U, coef, Zacc);
-    hop_force_dir<1>(g, p, i, c, Le, Lo, Re, Ro, U, coef, Zacc);
-    hop_force_dir<2>(g, p, i, c, Le, Lo, Re, Ro, U, coef, Zacc);
-    hop_force_dir<3>(g, p, i, c, Le, Lo, Re, Ro, U, coef, Zacc);
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 12L * g.Vh) return;
+    const int pp = (int)(t / g.Vh), i = (int)(t - (long)pp * g.Vh);
+    const int p = pp / 6, pl = pp - 6 * p;
+    const int type = kSigType[pl];
+    const double su = kSigUp[pl], sl = kSigLo[pl];
+    M3 acc = m3_zero();
+    for (int q = 0; q < ps.n; q++) {
+        const double2 *L = p == 0 ? ps.X[q] : ps.Xo[q], *R = p == 0 ? ps.Y[q] : ps.Zo[q];
+        const double2 cq = cmul(ps.c[q], p == 0 ? fe : fo);
+#pragma unroll
+        for (int blk = 0; blk < 2; blk++) {
+            double2 r0[3], r1[3], l0[3], l1[3];
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                r0[a] = R[(long)(6 * blk + a) * g.Vh + i];
+                r1[a] = R[(long)(6 * blk + 3 + a) * g.Vh + i];
+                l0[a] = L[(long)(6 * blk + a) * g.Vh + i];
+                l1[a] = L[(long)(6 * blk + 3 + a) * g.Vh + i];
+            }
+            const double2 w = cscale(cq, blk ? sl : su);
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+#pragma unroll
+                for (int b = 0; b < 3; b++) {
+                    double2 o;
+                    if (type == 0) o = cadd(cmulc(l0[b], r1[a]), cmulc(l1[b], r0[a]));                 // s_x
+                    else if (type == 1) o = ctimesi(csub(cmulc(l1[b], r0[a]), cmulc(l0[b], r1[a])));   // s_y
+                    else o = csub(cmulc(l0[b], r0[a]), cmulc(l1[b], r1[a]));                           // s_z
+                    cfma(acc.e[3 * a + b], w, o);
+                }
+        }
+    }
+    double2 *o = Phi + ((long)pp * 9) * g.Vh + i;
+#pragma unroll
+    for (int k = 0; k < 9; k++) o[(long)k * g.Vh] = accumulate ? cadd(o[(long)k * g.Vh], acc.e[k]) : acc.e[k];
 }
 
 // ---------------------------------------------------------------- clover insertions
@@ -114,34 +174,6 @@ __device__ __forceinline__ void phi_add(const Geom &g, double2 *__restrict__ Phi
 {
     double2 *b = Phi + ((long)(p * 6 + plane) * 9) * g.Vh + i;
     for (int k = 0; k < 9; k++) b[(long)k * g.Vh] = cadd(b[(long)k * g.Vh], m.e[k]);
-}
-
-// Phi_p(x) += fac * sum_{s,t} sigma_p[s][t] R_t L_s^dag on every site of both parities
-__global__ __launch_bounds__(kBlock) void k_clover_insert(Geom g, const double2 *__restrict__ Le,
-                                                          const double2 *__restrict__ Lo,
-                                                          const double2 *__restrict__ Re,
-                                                          const double2 *__restrict__ Ro, double2 fac_even,
-                                                          double2 fac_odd, double2 *__restrict__ Phi)
-{
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= 2L * g.Vh) return;
-    int p = (int)(t / g.Vh), i = (int)(t % g.Vh);
-    const double2 *L = p == 0 ? Le : Lo, *R = p == 0 ? Re : Ro;
-    double2 l[12], r[12];
-    load_spinor(L, g.Vh, i, 1.0, l);
-    load_spinor(R, g.Vh, i, 1.0, r);
-    double2 fac = p == 0 ? fac_even : fac_odd;
-    M3 Oup[4], Olo[4];
-    for (int s = 0; s < 2; s++)
-        for (int u = 0; u < 2; u++) {
-            Oup[2 * s + u] = outer(r + 3 * u, l + 3 * s);           // R_t L_s^dag with t = u
-            Olo[2 * s + u] = outer(r + 6 + 3 * u, l + 6 + 3 * s);
-        }
-    for (int pl = 0; pl < 6; pl++) {
-        M3 a = m3_scale(pauli_contract(kSigType[pl], Oup), kSigUp[pl]);
-        M3 b = m3_scale(pauli_contract(kSigType[pl], Olo), kSigLo[pl]);
-        phi_add(g, Phi, p, i, pl, m3_cscale(m3_add(a, b), fac));
-    }
 }
 
 // Phi_p(x) += fac * sum_{s,t} sigma_p[s][t] (A^-1)_{(t),(s)} on odd sites (log-det term)
@@ -267,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_clover_force(Geom g, const double2 *
             double sc;
             const double2 *b;
             // L1: y+mu -> y+mu+s nu
-            M3 L1 = side ? m3_dag(link_at(g, U, ypmn, nu)) : link_at(g, U, ypm, nu);
+            M3 L1 = m3_dag_if(link_at(g, U, side ? ypmn : ypm, nu), side);
             b = psi_base(g, Phi, ypm, mu, nu, &sc);
             M3 Q = psi_mul(b, st, sc, L1);
             b = psi_base(g, Phi, ypmn, mu, nu, &sc);
@@ -279,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_clover_force(Geom g, const double2 *
             b = psi_base(g, Phi, yn, mu, nu, &sc);
             Q = m3_add(Q, mul_psi(R, b, st, sc));
             // L3: y+s nu -> y
-            M3 L3 = side ? link_at(g, U, yn, nu) : m3_dag(link_at(g, U, y, nu));
+            M3 L3 = m3_dag_if(link_at(g, U, side ? yn : y, nu), !side);
             R = m3_mul(R, L3);
             Q = m3_mul(Q, L3);
             b = psi_base(g, Phi, y, mu, nu, &sc);
@@ -300,60 +332,52 @@ __global__ __launch_bounds__(kBlock) void k_clover_force(Geom g, const double2 *
     }
 }
 
-// F[link] += coefficients of Z1 * s1 + Z2 * s2 (either may be null)
-__global__ void k_force_finish(Geom g, const double2 *__restrict__ Z1, double s1, const double2 *__restrict__ Z2,
-                               double s2, double *__restrict__ F)
-{
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= 2L * g.Vh * 4) return;
-    int mu = (int)(t / (2L * g.Vh));
-    long r = t % (2L * g.Vh);
-    int p = (int)(r / g.Vh), i = (int)(r % g.Vh);
-    long base = ((long)(p * 4 + mu) * 9) * g.Vh + i;
-    M3 Z = m3_zero();
-    for (int k = 0; k < 9; k++) {
-        double2 v = make_double2(0, 0);
-        if (Z1) v = cscale(Z1[base + (long)k * g.Vh], s1);
-        if (Z2) v = cadd(v, cscale(Z2[base + (long)k * g.Vh], s2));
-        Z.e[k] = v;
-    }
-    double f[8];
-    lie_coeffs(Z, f);
-    double *fb = F + ((long)(p * 4 + mu) * 8) * g.Vh + i;
-    for (int a = 0; a < 8; a++) fb[(long)a * g.Vh] += f[a];
-}
-
 // ---------------------------------------------------------------- gauge part
 
+// F[link] += coefficients of coef U_mu(y) (sum of the staples); two lanes per link, the
+// staples above (lane 0) and below (lane 1) the link, coefficients summed by a lane swap
 __global__ __launch_bounds__(kBlock) void k_gauge_force(Geom g, const double2 *__restrict__ U, double coef,
                                                         double *__restrict__ F)
 {
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= 2L * g.Vh * 4) return;
-    int mu = (int)(t / (2L * g.Vh));
-    long r = t % (2L * g.Vh);
-    int p = (int)(r / g.Vh), i = (int)(r % g.Vh);
-    int y[4], ypm[4];
-    eo_coords(g, p, i, y);
-    shifted(g, y, mu, +1, ypm);
-    M3 st = m3_zero();
-    for (int nu = 0; nu < 4; nu++) {
-        if (nu == mu) continue;
-        int ypn[4], ymn[4], ypmmn[4];
-        shifted(g, y, nu, +1, ypn);
-        shifted(g, y, nu, -1, ymn);
-        shifted(g, ypm, nu, -1, ypmmn);
-        // U_nu(y+mu) U_mu(y+nu)^dag U_nu(y)^dag
-        M3 a = m3_mul_nd(link_at(g, U, ypm, nu), m3_mul(link_at(g, U, y, nu), link_at(g, U, ypn, mu)));
-        // U_nu(y+mu-nu)^dag U_mu(y-nu)^dag U_nu(y-nu)
-        M3 b = m3_mul_dn(m3_mul(link_at(g, U, ymn, mu), link_at(g, U, ypmmn, nu)), link_at(g, U, ymn, nu));
-        st = m3_add(st, m3_add(a, b));
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long l = t >> 1;
+    const int side = (int)(t & 1);
+    const bool ok = l < 8L * g.Vh;
+    double f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int mu = 0, p = 0, i = 0;
+    if (ok) {
+        mu = (int)(l / (2L * g.Vh));
+        const long r = l - (long)mu * 2L * g.Vh;
+        p = (int)(r / g.Vh);
+        i = (int)(r - (long)p * g.Vh);
+        int y[4], ypm[4];
+        eo_coords(g, p, i, y);
+        shifted(g, y, mu, +1, ypm);
+        M3 st = m3_zero();
+        const int sg = side ? -1 : 1;
+#pragma unroll 1
+        for (int nu = 0; nu < 4; nu++) {
+            if (nu == mu) continue;
+            // path y+mu -> y+mu+s nu -> y+s nu -> y:
+            //   s = +1: U_nu(y+mu) U_mu(y+nu)^dag U_nu(y)^dag
+            //   s = -1: U_nu(y+mu-nu)^dag U_mu(y-nu)^dag U_nu(y-nu)
+            int yn[4], ypmn[4];
+            shifted(g, y, nu, sg, yn);
+            shifted(g, ypm, nu, sg, ypmn);
+            const int *a1 = side ? ypmn : ypm, *a3 = side ? yn : y;
+            M3 X1 = m3_dag_if(link_at(g, U, a1, nu), side);
+            M3 X3 = m3_dag_if(link_at(g, U, a3, nu), !side);
+            st = m3_add(st, m3_mul(X1, m3_mul_dn(link_at(g, U, yn, mu), X3)));
+        }
+        lie_coeffs(m3_scale(m3_mul(link_at(g, U, y, mu), st), coef), f);
     }
-    M3 Z = m3_scale(m3_mul(link_at(g, U, y, mu), st), coef);
-    double f[8];
-    lie_coeffs(Z, f);
-    double *fb = F + ((long)(p * 4 + mu) * 8) * g.Vh + i;
-    for (int a = 0; a < 8; a++) fb[(long)a * g.Vh] += f[a];
+#pragma unroll
+    for (int a = 0; a < 8; a++) f[a] += __shfl_xor(f[a], 1, 64);
+    if (ok && side == 0) {
+        double *fb = F + ((long)(p * 4 + mu) * 8) * g.Vh + i;
+#pragma unroll
+        for (int a = 0; a < 8; a++) fb[(long)a * g.Vh] += f[a];
+    }
 }
 
 // ---------------------------------------------------------------- updates
@@ -455,17 +479,6 @@ __global__ __launch_bounds__(kBlock) void k_kinetic(long n, const double *__rest
 
 // ---------------------------------------------------------------- host side
 
-static int force_ws(pfmp_ctx *ctx, double2 **Zhop, double2 **Phi, double2 **Xo, double2 **Zo)
-{
-    const Geom &g = ctx->g;
-    *Zhop = (double2 *)ws_alloc(ctx, sizeof(double2) * 2L * 4 * 9 * g.Vh, 14);
-    *Phi = (double2 *)ws_alloc(ctx, sizeof(double2) * 2L * 6 * 9 * g.Vh, 16);
-    if (Xo) *Xo = (double2 *)ws_alloc(ctx, sizeof(double) * spinor_reals(g), 17);
-    if (Zo) *Zo = (double2 *)ws_alloc(ctx, sizeof(double) * spinor_reals(g), 18);
-    if (!*Zhop || !*Phi || (Xo && !*Xo) || (Zo && !*Zo)) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
-    return 0;
-}
-
 // F += clover force of the insertion field Phi
 static int clover_force_add(pfmp_ctx *ctx, const double2 *Phi, double *F)
 {
@@ -493,35 +506,36 @@ extern "C" int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void 
     const bool cl = s.csw != 0;
     const bool do_clov = cl && (flags & PFMP_FORCE_CLOVER);
     const bool do_hop = (flags & PFMP_FORCE_HOP) != 0;
-    double2 *Zhop, *Phi, *Xo, *Zo;
-    int rc = force_ws(ctx, &Zhop, &Phi, &Xo, &Zo);
-    if (rc) return rc;
-    HIPCHK(ctx, hipMemsetAsync(Zhop, 0, sizeof(double2) * 2L * 4 * 9 * g.Vh, ctx->stream));
-    if (do_clov) HIPCHK(ctx, hipMemsetAsync(Phi, 0, sizeof(double2) * 2L * 6 * 9 * g.Vh, ctx->stream));
+    double2 *Phi = (double2 *)ws_alloc(ctx, sizeof(double2) * 2L * 6 * 9 * g.Vh, 16);
+    if (!Phi) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
     const double k2 = s.kappa * s.kappa, kc = s.kappa * s.csw;
-    for (int q = 0; q < npairs; q++) {
-        const double2 *x = (const double2 *)X[q], *y = (const double2 *)Y[q];
-        double2 c = make_double2(coeff[2 * q], coeff[2 * q + 1]);
-        // Z = A_oo^-1 D_oe Y,  Xo = A_oo^-1 g5 D_oe g5 X = A_oo^-1 (D_eo)^dag X
-        if ((rc = clovinv64(ctx, 1, y, s.clov[1], Zo, 1.0, 1.0, cl, nullptr))) return rc;
-        if ((rc = clovinv64(ctx, 1, x, s.clov[1], Xo, -1.0, -1.0, cl, nullptr))) return rc;
-        if (do_hop)
-            hipLaunchKernelGGL(k_hop_force, dim3(nblocks(2L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, x, Xo,
-                               y, Zo, ctx->U, c, Zhop);
-        if (do_clov) {
-            // i kappa c_sw c w:  w = 1 even, kappa^2 odd
-            double2 ic = ctimesi(cscale(c, kc));
-            hipLaunchKernelGGL(k_clover_insert, dim3(nblocks(2L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, x,
-                               Xo, y, Zo, ic, cscale(ic, k2), Phi);
+    const double2 fe = make_double2(0, kc), fo = make_double2(0, kc * k2);   // i kappa c_sw w: w = 1 even, kappa^2 odd
+    int rc = 0;
+    for (int q0 = 0; q0 < npairs; q0 += kForcePairs) {
+        PairSet ps{};
+        ps.n = npairs - q0 < kForcePairs ? npairs - q0 : kForcePairs;
+        for (int k = 0; k < ps.n; k++) {
+            const double2 *x = (const double2 *)X[q0 + k], *y = (const double2 *)Y[q0 + k];
+            double2 *xo = pool_get(ctx, 2300 + k), *zo = pool_get(ctx, 2300 + kForcePairs + k);
+            if (!xo || !zo) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
+            // Zo = A_oo^-1 D_oe Y,  Xo = A_oo^-1 g5 D_oe g5 X = A_oo^-1 (D_eo)^dag X
+            if ((rc = clovinv64(ctx, 1, y, s.clov[1], zo, 1.0, 1.0, cl, nullptr))) return rc;
+            if ((rc = clovinv64(ctx, 1, x, s.clov[1], xo, -1.0, -1.0, cl, nullptr))) return rc;
+            ps.X[k] = x;
+            ps.Y[k] = y;
+            ps.Xo[k] = xo;
+            ps.Zo[k] = zo;
+            ps.c[k] = make_double2(coeff[2 * (q0 + k)], coeff[2 * (q0 + k) + 1]);
         }
+        if (do_hop)
+            hipLaunchKernelGGL(k_hop_force_multi, dim3(nblocks(8L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g,
+                               ps, ctx->U, -k2, F);
+        if (do_clov)
+            hipLaunchKernelGGL(k_clover_insert_multi, dim3(nblocks(12L * g.Vh, kBlock)), dim3(kBlock), 0,
+                               ctx->stream, g, ps, fe, fo, q0 > 0 ? 1 : 0, Phi);
         LAUNCHCHK(ctx);
     }
-    if (do_clov && (rc = clover_force_add(ctx, Phi, F))) return rc;
-    if (do_hop) {
-        hipLaunchKernelGGL(k_force_finish, dim3(nblocks(2L * g.Vh * 4, 256)), dim3(256), 0, ctx->stream, g, Zhop,
-                           -k2, (const double2 *)nullptr, 0.0, F);
-        LAUNCHCHK(ctx);
-    }
+    if (do_clov && npairs > 0 && (rc = clover_force_add(ctx, Phi, F))) return rc;
     return 0;
 }
 
@@ -535,9 +549,8 @@ extern "C" int pfmp_logdet_force(pfmp_ctx *ctx, int op, double coef, double *F)
     OpSlot &s = ctx->ops[op];
     if (s.csw == 0) return 0;
     const Geom &g = ctx->g;
-    double2 *Zhop, *Phi;
-    int rc = force_ws(ctx, &Zhop, &Phi, nullptr, nullptr);
-    if (rc) return rc;
+    double2 *Phi = (double2 *)ws_alloc(ctx, sizeof(double2) * 2L * 6 * 9 * g.Vh, 16);
+    if (!Phi) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
     HIPCHK(ctx, hipMemsetAsync(Phi, 0, sizeof(double2) * 2L * 6 * 9 * g.Vh, ctx->stream));
     double2 fac = ctimesi(make_double2(-2.0 * coef * s.kappa * s.csw, 0));
     hipLaunchKernelGGL(k_logdet_insert, dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, s.clov[1], fac,
@@ -551,7 +564,7 @@ extern "C" int pfmp_gauge_force(pfmp_ctx *ctx, double beta, double *F)
     if (!ctx || !F) return ctx ? set_err(ctx, PFMP_ERR_ARG, "gauge_force: null") : PFMP_ERR_ARG;
     if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
     const Geom &g = ctx->g;
-    hipLaunchKernelGGL(k_gauge_force, dim3(nblocks(2L * g.Vh * 4, kBlock)), dim3(kBlock), 0, ctx->stream, g, ctx->U,
+    hipLaunchKernelGGL(k_gauge_force, dim3(nblocks(16L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, ctx->U,
                        -beta / 3.0, F);
     LAUNCHCHK(ctx);
     return 0;

@@ -170,6 +170,175 @@ __device__ __forceinline__ void hop_all(const Geom &g, int pout, int i, const In
     hop_dir<3, C>(g, pout, i, c, in, U, gs, acc);
 }
 
+// ------------------------------------------------------------------ two lanes per site
+//
+// The operator kernels run two lanes per output site (a lane pair in one wavefront).
+// Lane hb of the pair owns chiral block hb (spins 2hb, 2hb+1) of the result.  For the
+// hop it projects only half-spin hb of every neighbour: with partner lower spin q,
+//   h = psi_hb + S f psi_q,  f = sgp (i or 1),   q = 3 - hb (mu = x, y), 2 + hb (mu = z, t),
+// multiplies one SU(3) vector, adds it to its upper spin hb and S r w to lower spin q:
+//   mu = x: f = -i,            r = i
+//   mu = y: f = r = (hb ? 1 : -1)
+//   mu = z: f = (hb ? i : -i), r = -f
+//   mu = t: f = r = 1
+// (the chiral-basis projectors written per half-spin).  The two partial lower spins
+// are combined by one lane swap at the end (pair_block).
+
+template <typename C>
+__device__ __forceinline__ C load_comp(const C *__restrict__ f, int Vh, int j, int k)
+{
+    return f[(long)k * Vh + j];
+}
+__device__ __forceinline__ float2 load_comp(const HalfField &f, int Vh, int j, int k)
+{
+    float2 a = __half22float2(f.h[(long)k * Vh + j]);
+    const float sc = f.s[j];
+    return make_float2(a.x * sc, a.y * sc);
+}
+
+template <int IM, typename C>
+__device__ __forceinline__ C unit_mul(C v, decltype(C::x) sg)
+{
+    return IM ? mk<C>(-sg * v.y, sg * v.x) : mk<C>(sg * v.x, sg * v.y);
+}
+
+// w = f U h (DAG = 0) or f U^dag h (DAG = 1) for one half-spin (3 colours)
+template <int DAG, typename C>
+__device__ __forceinline__ void su3_vec(const C *__restrict__ U, long stride, int site, const C *h,
+                                        decltype(C::x) f, C *w)
+{
+    C u[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) u[k] = U[k * stride + site];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        C acc = mk<C>(0, 0);
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            if (DAG) cfmac(acc, u[3 * b + a], h[b]);
+            else cfma(acc, u[3 * a + b], h[b]);
+        }
+        w[a] = cscale(acc, f);
+    }
+}
+
+template <int MU, typename C, typename In>
+__device__ __forceinline__ void hop_dir_pair(const Geom &g, int pout, int i, const int *c, int hb, const In in,
+                                             const C *__restrict__ U, decltype(C::x) gs, C *up, C *loA, C *loB)
+{
+    using R = decltype(C::x);
+    constexpr int IM = (MU == 0 || MU == 2) ? 1 : 0;
+    const long Vh = g.Vh;
+    const R sgp = MU == 0 ? (R)-1 : (MU == 3 ? (R)1 : (hb ? (R)1 : (R)-1));
+    const R sgr = MU == 0 ? (R)1 : (MU == 2 ? -sgp : sgp);
+    const int q = MU < 2 ? 3 - hb : 2 + hb;
+    C *lo = MU < 2 ? loA : loB;
+    C h[3], w[3];
+    int sf, sb;
+    // forward: (1 - g_mu) U_mu(x) psi(x + mu)
+    const int jf = eo_neighbour(g, c, MU, +1, &sf);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        C pt = load_comp(in, g.Vh, jf, 3 * hb + a);
+        C pq = cscale(load_comp(in, g.Vh, jf, 3 * q + a), gs);
+        h[a] = csub(pt, unit_mul<IM>(pq, sgp));
+    }
+    su3_vec<0>(U + ((long)(pout * 4 + MU) * 9) * Vh, Vh, i, h, (R)sf, w);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        up[a] = cadd(up[a], w[a]);
+        lo[a] = csub(lo[a], unit_mul<IM>(w[a], sgr));
+    }
+    // backward: (1 + g_mu) U_mu(x - mu)^dag psi(x - mu)
+    const int jb = eo_neighbour(g, c, MU, -1, &sb);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        C pt = load_comp(in, g.Vh, jb, 3 * hb + a);
+        C pq = cscale(load_comp(in, g.Vh, jb, 3 * q + a), gs);
+        h[a] = cadd(pt, unit_mul<IM>(pq, sgp));
+    }
+    su3_vec<1>(U + ((long)((1 - pout) * 4 + MU) * 9) * Vh, Vh, jb, h, (R)sb, w);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        up[a] = cadd(up[a], w[a]);
+        lo[a] = cadd(lo[a], unit_mul<IM>(w[a], sgr));
+    }
+}
+
+__device__ __forceinline__ double pair_swap(double v) { return __shfl_xor(v, 1, 64); }
+__device__ __forceinline__ float pair_swap(float v) { return __shfl_xor(v, 1, 64); }
+
+// D_hop in (gs = -1 flips the lower spins of the input), chiral block hb of the
+// result at output site i of parity pout
+template <typename C, typename In>
+__device__ __forceinline__ void hop_pair(const Geom &g, int pout, int i, int hb, const In in, const C *__restrict__ U,
+                                         decltype(C::x) gs, C *blk)
+{
+    int c[4];
+    eo_coords(g, pout, i, c);
+    C up[3], loA[3], loB[3];   // upper spin hb; lower spins 3 - hb and 2 + hb
+#pragma unroll
+    for (int a = 0; a < 3; a++) up[a] = loA[a] = loB[a] = mk<C>(0, 0);
+    hop_dir_pair<0, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
+    hop_dir_pair<1, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
+    hop_dir_pair<2, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
+    hop_dir_pair<3, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
+    // lane 0 keeps spin 0 and takes spin 1 from lane 1; lane 1 sums the lower spins
+    C x[6];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        x[a] = hb ? up[a] : loB[a];       // lane 0 sends its share of spin 2
+        x[3 + a] = hb ? up[a] : loA[a];   // ... and of spin 3
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k++) x[k] = mk<C>(pair_swap(x[k].x), pair_swap(x[k].y));
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        blk[a] = hb ? cadd(loA[a], x[a]) : up[a];
+        blk[3 + a] = hb ? cadd(loB[a], x[3 + a]) : x[a];
+    }
+}
+
+// components 6 hb .. 6 hb + 5 of a spinor; gs scales them when hb = 1 (lower spins)
+template <typename C>
+__device__ __forceinline__ void load_block(const C *__restrict__ f, int Vh, int i, int hb, decltype(C::x) gs, C *v)
+{
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        C a = f[(long)(6 * hb + k) * Vh + i];
+        v[k] = hb ? cscale(a, gs) : a;
+    }
+}
+__device__ __forceinline__ void load_block(const HalfField &f, int Vh, int i, int hb, float gs, float2 *v)
+{
+    const float sc = hb ? f.s[i] * gs : f.s[i];
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        float2 a = __half22float2(f.h[(long)(6 * hb + k) * Vh + i]);
+        v[k] = make_float2(a.x * sc, a.y * sc);
+    }
+}
+
+template <typename C>
+__device__ __forceinline__ void store_block(C *__restrict__ f, int Vh, int i, int hb, decltype(C::x) gs, const C *v)
+{
+#pragma unroll
+    for (int k = 0; k < 6; k++) f[(long)(6 * hb + k) * Vh + i] = hb ? cscale(v[k], gs) : v[k];
+}
+// FP16 storage: the per-site scale is the maximum over both lanes' blocks
+__device__ __forceinline__ void store_block(const HalfField &f, int Vh, int i, int hb, float gs, const float2 *v)
+{
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 6; k++) m = fmaxf(m, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
+    m = fmaxf(m, pair_swap(m));
+    const float inv = m > 0.f ? 1.f / m : 0.f;
+    if (hb == 0) f.s[i] = m;
+    const float q = hb ? inv * gs : inv;
+#pragma unroll
+    for (int k = 0; k < 6; k++) f.h[(long)(6 * hb + k) * Vh + i] = __floats2half2_rn(v[k].x * q, v[k].y * q);
+}
+
 // out[6] = (6x6 Hermitian block b of the clover field at site i) v[6]
 template <typename R, typename C>
 __device__ __forceinline__ void clover_block(const R *__restrict__ cl, int Vh, int i, int b, const C *v, C *out)

@@ -172,6 +172,8 @@ inline int nblocks_site(long n) { return ((nblocks(n, kBlock) + 7) / 8) * 8; }
 
 // sizes of internal fields
 inline long spinor_reals(const Geom &g) { return 24L * g.Vh; }
+// grid of the operator kernels (two lanes per site) = number of block partials they write
+inline int op_nparts(const Geom &g) { return nblocks_site(2L * g.Vh); }
 inline long clover_reals(const Geom &g) { return 72L * g.Vh; }
 inline long gauge_reals(const Geom &g) { return 2L * 4 * 18 * g.Vh; }
 inline long mom_reals(const Geom &g) { return 2L * 4 * 8 * g.Vh; }

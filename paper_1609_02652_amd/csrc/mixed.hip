@@ -84,26 +84,28 @@ __global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T,
                                                    const double *__restrict__ st, double *__restrict__ partials)
 {
     if (st[M_DONE] != 0) return;
-    int i = xcd_site(g.Vh);
+    const int tt = xcd_site(2 * g.Vh);
     double nrm = 0;
-    if (i >= 0) {
-        float2 acc[12], tv[12], at[12], pp[12];
-        hop_all<float2>(g, 0, i, T, U, 1.f, acc);
-        load_spinor(t, g.Vh, i, -1.f, tv);
-        load_spinor(p, g.Vh, i, 1.f, pp);
-        if (CLOV) clover_apply<float, float2>(cl, g.Vh, i, tv, at);
+    if (tt >= 0) {
+        const int i = tt >> 1, hb = tt & 1;
+        float2 acc[6], tv[6], at[6], pp[6];
+        hop_pair<float2>(g, 0, i, hb, T, U, 1.f, acc);
+        load_block(t, g.Vh, i, hb, -1.f, tv);
+        load_block(p, g.Vh, i, hb, 1.f, pp);
+        if (CLOV) clover_block<float, float2>(cl, g.Vh, i, hb, tv, at);
         const float alpha = (float)st[M_ALPHA];
         const long Vh = g.Vh;
 #pragma unroll
-        for (int k = 0; k < 12; k++) {
+        for (int k = 0; k < 6; k++) {
             float2 base = CLOV ? at[k] : tv[k];
             float2 kp = make_float2(base.x + a * acc[k].x, base.y + a * acc[k].y);
-            if (k >= 6) kp = cneg(kp);
-            float2 pv = pp[k], xv = x[k * Vh + i], rv = r[k * Vh + i];
+            if (hb) kp = cneg(kp);
+            const long e = (long)(6 * hb + k) * Vh + i;
+            float2 pv = pp[k], xv = x[e], rv = r[e];
             xv.x += alpha * pv.x; xv.y += alpha * pv.y;
             rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
-            x[k * Vh + i] = xv;
-            r[k * Vh + i] = rv;
+            x[e] = xv;
+            r[e] = rv;
             nrm += (double)rv.x * rv.x + (double)rv.y * rv.y;
         }
     }
@@ -187,7 +189,7 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
     OpSlot &s = ctx->ops[op];
     const long n = 12L * g.Vh;
     const size_t vb = sizeof(double) * spinor_reals(g), fb = vb / 2;
-    const int nb = nblocks_site(g.Vh);
+    const int nb = op_nparts(g);
     double2 *Kx = (double2 *)ws_alloc(ctx, vb, 8), *te = (double2 *)ws_alloc(ctx, vb, 6),
             *to = (double2 *)ws_alloc(ctx, vb, 7);
     const size_t sb = Store<S>::bytes(g.Vh);

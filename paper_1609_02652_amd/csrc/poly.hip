@@ -17,20 +17,21 @@ __global__ __launch_bounds__(kBlock) void k_poly_last(Geom g, const double2 *__r
                                                       const double2 *__restrict__ src, double2 z,
                                                       double2 *__restrict__ dst)
 {
-    int i = xcd_site(g.Vh);
-    if (i < 0) return;
-    double2 acc[12], tv[12], at[12];
-    hop_all<double2>(g, 0, i, T, U, 1.0, acc);
-    load_spinor(t, g.Vh, i, -1.0, tv);
-    if (CLOV) clover_apply<double, double2>(cl, g.Vh, i, tv, at);
+    const int tt = xcd_site(2 * g.Vh);
+    if (tt < 0) return;
+    const int i = tt >> 1, hb = tt & 1;
+    double2 acc[6], tv[6], at[6];
+    hop_pair<double2>(g, 0, i, hb, T, U, 1.0, acc);
+    load_block(t, g.Vh, i, hb, -1.0, tv);
+    if (CLOV) clover_block<double, double2>(cl, g.Vh, i, hb, tv, at);
     const long Vh = g.Vh;
 #pragma unroll
-    for (int k = 0; k < 12; k++) {
+    for (int k = 0; k < 6; k++) {
         double2 base = CLOV ? at[k] : tv[k];
         double2 kv = make_double2(base.x + a * acc[k].x, base.y + a * acc[k].y);
-        if (k >= 6) kv = cneg(kv);
-        double2 s = src[k * Vh + i];
-        dst[k * Vh + i] = csub(kv, cmul(z, s));
+        if (hb) kv = cneg(kv);
+        const long e = (long)(6 * hb + k) * Vh + i;
+        dst[e] = csub(kv, cmul(z, src[e]));
     }
 }
 
@@ -51,7 +52,7 @@ int poly_factor(pfmp_ctx *ctx, int op, const double2 *src, double2 z, double2 *d
     int rc = op_apply_M(ctx, op, 0, src, te, to, nullptr);
     if (rc) return rc;
     if ((rc = clovinv64(ctx, 1, te, s.clov[1], to, -1.0, 1.0, cl, nullptr))) return rc;
-    dim3 grid(nblocks_site(ctx->g.Vh)), block(kBlock);
+    dim3 grid(op_nparts(ctx->g)), block(kBlock);
     if (cl)
         hipLaunchKernelGGL((k_poly_last<1>), grid, block, 0, ctx->stream, ctx->g, te, to, ctx->U, s.clov[0], mk2, src,
                            z, dst);

@@ -513,7 +513,7 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
     }
     HIPCHK(ctx, hipMemcpyAsync(p, z, vb, hipMemcpyDeviceToDevice, ctx->stream));
     int k = 0;
-    const int nb = nblocks_site(g.Vh);
+    const int nb = op_nparts(g);
     double *part = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64), 9);
     if (!part) return set_err(ctx, PFMP_ERR_OOM, "fcg workspace");
     while (rn > prm->tol * bn && k < prm->maxiter) {
@@ -578,7 +578,7 @@ extern "C" int pfmp_cg_harvest(pfmp_ctx *ctx, int op, const void *b_, void *x_, 
     double2 *r = pool_get(ctx, 2010), *p = pool_get(ctx, 2013), *q = pool_get(ctx, 2014), *te = pool_get(ctx, 2015),
             *to = pool_get(ctx, 2016);
     if (!r || !p || !q || !te || !to) return set_err(ctx, PFMP_ERR_OOM, "harvest workspace");
-    const int nb = nblocks_site(g.Vh);
+    const int nb = op_nparts(g);
     double *part = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64), 9);
     if (!part) return set_err(ctx, PFMP_ERR_OOM, "harvest workspace");
     const double2 *b = (const double2 *)b_;

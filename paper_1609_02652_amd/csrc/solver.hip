@@ -97,25 +97,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
                                                     double *__restrict__ partials)
 {
     if (st[S_DONE] != 0) return;
-    int i = xcd_site(g.Vh);
+    const int tt = xcd_site(2 * g.Vh);
     double nrm = 0;
-    if (i >= 0) {
-        double2 acc[12], tv[12], at[12];
-        hop_all<double2>(g, 0, i, T, U, 1.0, acc);
-        load_spinor(t, g.Vh, i, -1.0, tv);
-        if (CLOV) clover_apply<double, double2>(cl, g.Vh, i, tv, at);
+    if (tt >= 0) {
+        const int i = tt >> 1, hb = tt & 1;
+        double2 acc[6], tv[6], at[6];
+        hop_pair<double2>(g, 0, i, hb, T, U, 1.0, acc);
+        load_block(t, g.Vh, i, hb, -1.0, tv);
+        if (CLOV) clover_block<double, double2>(cl, g.Vh, i, hb, tv, at);
         const double alpha = st[S_ALPHA];
         const long Vh = g.Vh;
 #pragma unroll
-        for (int k = 0; k < 12; k++) {
+        for (int k = 0; k < 6; k++) {
             double2 base = CLOV ? at[k] : tv[k];
             double2 kp = make_double2(base.x + a * acc[k].x, base.y + a * acc[k].y);
-            if (k >= 6) kp = cneg(kp);
-            double2 pv = p[k * Vh + i], xv = x[k * Vh + i], rv = r[k * Vh + i];
+            if (hb) kp = cneg(kp);
+            const long e = (long)(6 * hb + k) * Vh + i;
+            double2 pv = p[e], xv = x[e], rv = r[e];
             xv.x += alpha * pv.x; xv.y += alpha * pv.y;
             rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
-            x[k * Vh + i] = xv;
-            r[k * Vh + i] = rv;
+            x[e] = xv;
+            r[e] = rv;
             nrm += rv.x * rv.x + rv.y * rv.y;
         }
     }
@@ -279,7 +281,7 @@ struct CGBufs {
 static int cg_bufs(pfmp_ctx *ctx, CGBufs &B)
 {
     size_t vb = sizeof(double) * spinor_reals(ctx->g);
-    size_t pb = sizeof(double) * (nblocks_site(ctx->g.Vh) + 64);
+    size_t pb = sizeof(double) * (op_nparts(ctx->g) + 64);
     B.r = (double2 *)ws_alloc(ctx, vb, 4);
     B.p = (double2 *)ws_alloc(ctx, vb, 5);
     B.t = (double2 *)ws_alloc(ctx, vb, 6);
@@ -334,7 +336,7 @@ extern "C" int pfmp_cg_solve(pfmp_ctx *ctx, int op, const void *b_, void *x_, co
     double2 *x = (double2 *)x_;
     long n = 12L * g.Vh;
     size_t vb = sizeof(double) * spinor_reals(g);
-    int nb = nblocks_site(g.Vh);
+    int nb = op_nparts(g);
     HIPCHK(ctx, hipMemsetAsync(x, 0, vb, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(B.r, b, vb, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(B.p, b, vb, hipMemcpyDeviceToDevice, ctx->stream));
@@ -403,7 +405,7 @@ extern "C" int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const doubl
     if ((rc = cg_bufs(ctx, B))) return rc;
     long n = 12L * g.Vh;
     size_t vb = sizeof(double) * spinor_reals(g);
-    int nb = nblocks_site(g.Vh);
+    int nb = op_nparts(g);
     double2 *pbuf = (double2 *)ws_alloc(ctx, vb * nshift, 11);
     double2 **ptrs = (double2 **)ws_alloc(ctx, sizeof(double2 *) * 2 * nshift, 12);
     double *zdev = (double *)ws_alloc(ctx, sizeof(double) * 2 * nshift, 13);

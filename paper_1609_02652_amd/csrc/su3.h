@@ -62,6 +62,17 @@ PFMP_HD M3 m3_dag(const M3 &a)
         for (int j = 0; j < 3; j++) r.e[3 * i + j] = cconj(a.e[3 * j + i]);
     return r;
 }
+// a^dag when dag, else a (per-lane select, no branch)
+PFMP_HD M3 m3_dag_if(const M3 &a, bool dag)
+{
+    M3 r;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double2 d = cconj(a.e[3 * j + i]), n = a.e[3 * i + j];
+            r.e[3 * i + j] = make_double2(dag ? d.x : n.x, dag ? d.y : n.y);
+        }
+    return r;
+}
 PFMP_HD M3 m3_add(const M3 &a, const M3 &b)
 {
     M3 r;
