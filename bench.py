@@ -82,10 +82,13 @@ def hop_roofline(dims, U, reps=200):
     # and the plain hop separately
     t_plain = time_kernel(lat, lambda: lat.apply_hop(1, x, out=out), reps)
     t_m = time_kernel(lat, lambda: lat.apply_M(0, x, out=out, prec=F64), reps)
-    bytes_plain = lat.Vh * (8 * 18 + 24 + 24) * 8
-    bytes_m = lat.Vh * (2 * (8 * 18 + 24 + 24) + 72 * 2 + 24) * 8
+    # links are SU(3): the kernels read 2 of the 3 rows (12 reals per link)
+    link_reals = 12 if lat.link_reconstruct() else 18
+    bytes_plain = lat.Vh * (8 * link_reals + 24 + 24) * 8
+    bytes_m = lat.Vh * (2 * (8 * link_reals + 24 + 24) + 72 * 2 + 24) * 8
     lat.close()
-    return {"t_hop": t_plain, "bytes_hop": bytes_plain, "t_M": t_m, "bytes_M": bytes_m, "Vh": lat.Vh}
+    return {"t_hop": t_plain, "bytes_hop": bytes_plain, "t_M": t_m, "bytes_M": bytes_m, "Vh": lat.Vh,
+            "link_reals": link_reals}
 
 
 def roofline_only(reps):
@@ -266,7 +269,8 @@ def main():
     # ---- dominant-kernel roofline (HIP events on the library stream)
     rf = hop_roofline(DIMS, U)
     achieved = rf["bytes_hop"] / rf["t_hop"] / 1e9
-    roof = {"kernel": "hop (D_oe, FP64, plain)", "bound": "hbm", "achieved": round(achieved, 1),
+    roof = {"kernel": "hop (D_oe, FP64, plain; links read as %d reals)" % rf["link_reals"], "bound": "hbm",
+            "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "avg_launch_us": round(rf["t_hop"] * 1e6, 2), "bytes_per_launch": rf["bytes_hop"],
             "Mhat_GBps": round(rf["bytes_M"] / rf["t_M"] / 1e9, 1),

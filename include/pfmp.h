@@ -94,11 +94,20 @@ int pfmp_index_maps(pfmp_ctx *ctx, int32_t *lex_of_eo, int32_t *nbr, int8_t *sig
 
 /* ---- fields ----------------------------------------------------------------- */
 
-/* Upload a canonical gauge field (device buffer) into the context; rebuilds the
- * clover fields of every configured operator slot. */
+/* Upload a canonical gauge field (device buffer) into the context (synchronises
+ * for the SU(3) check below).  Fields derived from the links (FP32 copy, clover
+ * fields of every configured slot) are rebuilt on first use. */
 int pfmp_set_gauge(pfmp_ctx *ctx, const void *U_canonical);
 /* Copy the context's gauge field out in canonical layout (device buffer). */
 int pfmp_get_gauge(pfmp_ctx *ctx, void *U_canonical);
+/* Link row reconstruction.  pfmp_set_gauge checks every link against SU(3)
+ * (|U U^dag - 1| and |det U - 1| below 1e-12); when they pass and reconstruction
+ * is allowed (the default), the hopping kernels read the first two rows of each
+ * link and rebuild the third as the conjugate cross product (a third fewer link
+ * bytes).  The link updates keep links in SU(3).  allow = 0 turns it off; *active
+ * reports whether it is in use. */
+int pfmp_set_link_reconstruct(pfmp_ctx *ctx, int allow);
+int pfmp_get_link_reconstruct(pfmp_ctx *ctx, int *active);
 /* Configure slot op with (kappa, c_sw): builds A_ee, A_oo^-1 (per-site Cholesky
  * of the two 6x6 chiral blocks) and ln det A_oo.  Needs a gauge field.  Errors:
  * PFMP_ERR_ARG (slot), PFMP_ERR_STATE (no gauge), PFMP_ERR_ARG if A_oo is not

@@ -239,6 +239,51 @@ int gauge_f32_ready(pfmp_ctx *ctx)
     return 0;
 }
 
+// per-block maximum over links of max(|U U^dag - 1|_max, |det U - 1|)
+__global__ __launch_bounds__(256) void k_su3_dev(Geom g, const double2 *__restrict__ U, double *__restrict__ part)
+{
+    const long n = 8L * g.Vh;
+    double m = 0;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+        const long pm = t / g.Vh, i = t - pm * g.Vh;
+        double2 u[9];
+        for (int k = 0; k < 9; k++) u[k] = U[(pm * 9 + k) * g.Vh + i];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                double2 s = make_double2(a == b ? -1.0 : 0.0, 0.0);
+                for (int c = 0; c < 3; c++) cfma(s, u[3 * a + c], cconj(u[3 * b + c]));
+                m = fmax(m, fmax(fabs(s.x), fabs(s.y)));
+            }
+        double2 d = cmul(u[0], csub(cmul(u[4], u[8]), cmul(u[5], u[7])));
+        d = csub(d, cmul(u[1], csub(cmul(u[3], u[8]), cmul(u[5], u[6]))));
+        d = cadd(d, cmul(u[2], csub(cmul(u[3], u[7]), cmul(u[4], u[6]))));
+        m = fmax(m, fmax(fabs(d.x - 1.0), fabs(d.y)));
+    }
+    __shared__ double sh[4];
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+// Links within this distance of SU(3) let the hopping kernels read rows 1, 2 only.
+constexpr double kSu3Tol = 1e-12;
+
+static int check_su3(pfmp_ctx *ctx)
+{
+    const int nb = 256;
+    hipLaunchKernelGGL(k_su3_dev, dim3(nb), dim3(256), 0, ctx->stream, ctx->g, ctx->U, ctx->red);
+    LAUNCHCHK(ctx);
+    std::vector<double> h(nb);
+    HIPCHK(ctx, hipMemcpyAsync(h.data(), ctx->red, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    double m = 0;
+    for (double v : h) m = v > m ? v : m;
+    ctx->links_su3 = m <= kSu3Tol;
+    ctx->g.recon = ctx->links_su3 && ctx->recon_allowed ? 1 : 0;
+    return 0;
+}
+
 extern "C" int pfmp_set_gauge(pfmp_ctx *ctx, const void *U_canonical)
 {
     if (!ctx || !U_canonical) return ctx ? set_err(ctx, PFMP_ERR_ARG, "set_gauge: null") : PFMP_ERR_ARG;
@@ -246,7 +291,23 @@ extern "C" int pfmp_set_gauge(pfmp_ctx *ctx, const void *U_canonical)
                        (const double2 *)U_canonical, ctx->U, 0);
     LAUNCHCHK(ctx);
     ctx->have_gauge = true;
-    return rebuild_gauge_derived(ctx);
+    int rc = check_su3(ctx);
+    return rc ? rc : rebuild_gauge_derived(ctx);
+}
+
+extern "C" int pfmp_set_link_reconstruct(pfmp_ctx *ctx, int allow)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    ctx->recon_allowed = allow != 0;
+    ctx->g.recon = ctx->links_su3 && ctx->recon_allowed ? 1 : 0;
+    return 0;
+}
+
+extern "C" int pfmp_get_link_reconstruct(pfmp_ctx *ctx, int *active)
+{
+    if (!ctx || !active) return ctx ? set_err(ctx, PFMP_ERR_ARG, "get_link_reconstruct: null") : PFMP_ERR_ARG;
+    *active = ctx->g.recon;
+    return 0;
 }
 
 extern "C" int pfmp_get_gauge(pfmp_ctx *ctx, void *U_canonical)

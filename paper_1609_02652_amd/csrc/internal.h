@@ -57,6 +57,7 @@ struct Geom {
     int Vh;
     int V;
     int tbc;        // fermion factor across the t boundary
+    int recon;      // 1: every link is in SU(3), the hopping kernels rebuild row 3 from rows 1, 2
 };
 
 // Coordinates of even-odd site i of parity p: lex = 2i or 2i+1, whichever has parity p.
@@ -134,6 +135,8 @@ struct pfmp_ctx {
     bool uf_stale = true;        // Uf older than U
     double2 *Fhat = nullptr;     // clover field strength [2 parities][6 planes][9][Vh], shared by all slots
     bool fhat_stale = true;      // Fhat older than U
+    bool recon_allowed = true;   // link row reconstruction permitted (pfmp_set_link_reconstruct)
+    bool links_su3 = false;      // the links passed the SU(3) check at set_gauge
     OpSlot ops[PFMP_MAX_OPS];
     double *red = nullptr;       // reduction partials
     double *red_host = nullptr;  // pinned host mirror of a few scalars

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kRedBlock) void k_m_beta(const double *__restrict__
 
 // FP32 Khat p from t = Mhat p and T' (as in the FP64 solver), fused with
 // x += alpha p, r -= alpha Khat p and FP64 |r|^2 partials
-template <int CLOV, typename S>
+template <int CLOV, int RC, typename S>
 __global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T, const float2 *__restrict__ U,
                                                    const float *__restrict__ cl, float a, const S p,
                                                    float2 *__restrict__ x, float2 *__restrict__ r,
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T,
     if (tt >= 0) {
         const int i = tt >> 1, hb = tt & 1;
         float2 acc[6], tv[6], at[6], pp[6];
-        hop_pair<float2>(g, 0, i, hb, T, U, 1.f, acc);
+        hop_pair<RC, float2>(g, 0, i, hb, T, U, 1.f, acc);
         load_block(t, g.Vh, i, hb, -1.f, tv);
         load_block(p, g.Vh, i, hb, 1.f, pp);
         if (CLOV) clover_block<float, float2>(cl, g.Vh, i, hb, tv, at);
@@ -236,12 +236,14 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
             if ((rc = launch_clovinv<float2, float, In, S>(ctx, 1, ts, ctx->Uf, s.clovf[1], Ts, -1.f, 1.f, cl,
                                                             sc + M_DONE)))
                 return rc;
-            if (cl)
-                hipLaunchKernelGGL((k_m_hop4<1, In>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,
-                                   s.clovf[0], mk2, ps, xs, rs, sc, part_b);
-            else
-                hipLaunchKernelGGL((k_m_hop4<0, In>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,
-                                   s.clovf[0], mk2, ps, xs, rs, sc, part_b);
+#define MHOP4(CL, RC)                                                                                       \
+    hipLaunchKernelGGL((k_m_hop4<CL, RC, In>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,     \
+                       s.clovf[0], mk2, ps, xs, rs, sc, part_b)
+            if (cl && g.recon) MHOP4(1, 1);
+            else if (cl) MHOP4(1, 0);
+            else if (g.recon) MHOP4(0, 1);
+            else MHOP4(0, 0);
+#undef MHOP4
             hipLaunchKernelGGL(k_m_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, sc);
             hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
                                sc);

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kRedBlock) void k_cg_beta(const double *__restrict_
 
 // Khat p from t = Mhat p and T' = A_oo^-1 D_oe g5 t:  Kp = g5 (A_ee g5 t - kappa^2 D_eo T');
 // then x += alpha p, r -= alpha Kp, |r|^2 partials.
-template <int CLOV>
+template <int CLOV, int RC>
 __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__restrict__ t,
                                                     const double2 *__restrict__ T, const double2 *__restrict__ U,
                                                     const double *__restrict__ cl, double a,
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
     if (tt >= 0) {
         const int i = tt >> 1, hb = tt & 1;
         double2 acc[6], tv[6], at[6];
-        hop_pair<double2>(g, 0, i, hb, T, U, 1.0, acc);
+        hop_pair<RC, double2>(g, 0, i, hb, T, U, 1.0, acc);
         load_block(t, g.Vh, i, hb, -1.0, tv);
         if (CLOV) clover_block<double, double2>(cl, g.Vh, i, hb, tv, at);
         const double alpha = st[S_ALPHA];
@@ -122,6 +122,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
         }
     }
     block_sum_store<double2>(nrm, partials);
+}
+
+void launch_cg_hop4(pfmp_ctx *ctx, bool cl, int nb, const double2 *t, const double2 *T, const double *clov,
+                    double mk2, const double2 *p, double2 *x, double2 *r, double *part)
+{
+#define HOP4(CL, RC)                                                                                             \
+    hipLaunchKernelGGL((k_cg_hop4<CL, RC>), dim3(nb), dim3(kBlock), 0, ctx->stream, ctx->g, t, T, ctx->U, clov, mk2, \
+                       p, x, r, ctx->scal, part)
+    if (cl && ctx->g.recon) HOP4(1, 1);
+    else if (cl) HOP4(1, 0);
+    else if (ctx->g.recon) HOP4(0, 1);
+    else HOP4(0, 0);
+#undef HOP4
 }
 
 __global__ void k_cg_update_p(long n, const double2 *__restrict__ r, double2 *__restrict__ p,
@@ -360,12 +373,7 @@ extern "C" int pfmp_cg_solve(pfmp_ctx *ctx, int op, const void *b_, void *x_, co
             // T' = A_oo^-1 D_oe g5 t
             if ((rc = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE)))
                 return rc;
-            if (cl)
-                hipLaunchKernelGGL((k_cg_hop4<1>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, B.t, B.T, ctx->U,
-                                   s.clov[0], mk2, B.p, x, B.r, ctx->scal, B.part_b);
-            else
-                hipLaunchKernelGGL((k_cg_hop4<0>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, B.t, B.T, ctx->U,
-                                   s.clov[0], mk2, B.p, x, B.r, ctx->scal, B.part_b);
+            launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, x, B.r, B.part_b);
             hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_b, nb, ctx->scal);
             hipLaunchKernelGGL(k_cg_update_p, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, B.r, B.p,
                                ctx->scal);
@@ -448,12 +456,7 @@ extern "C" int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const doubl
             if ((rc = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE)))
                 return rc;
             // r -= alpha Khat p (the base x is not needed; it goes to scratch)
-            if (cl)
-                hipLaunchKernelGGL((k_cg_hop4<1>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, B.t, B.T, ctx->U,
-                                   s.clov[0], mk2, B.p, B.Kx, B.r, ctx->scal, B.part_b);
-            else
-                hipLaunchKernelGGL((k_cg_hop4<0>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, B.t, B.T, ctx->U,
-                                   s.clov[0], mk2, B.p, B.Kx, B.r, ctx->scal, B.part_b);
+            launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, B.Kx, B.r, B.part_b);
             hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_b, nb, nshift, ctx->scal,
                                rec);
             hipLaunchKernelGGL(k_ms_update, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, nshift, B.r, B.p,

@@ -160,6 +160,8 @@ def load():
         "pfmp_hamiltonian": [vp, vp, vp, vp, vp, vp],
         "pfmp_md_evolve": [vp, vp, vp, vp, vp],
         "pfmp_trajectory": [vp, vp, vp, vp, d, vp, vp],
+        "pfmp_set_link_reconstruct": [vp, i],
+        "pfmp_get_link_reconstruct": [vp, vp],
         "pfmp_apply_MdagM_batch": [vp, i, vp, vp, vp],
         "pfmp_cg_solve_batch": [vp, i, vp, vp, vp, vp, vp],
         "pfmp_ptnet_apply": [vp, vp, vp, vp],
@@ -252,6 +254,15 @@ class Lattice:
         Ud = Ud.contiguous()
         self._chk(self.lib.pfmp_set_gauge(self.h, _ptr(Ud)), "set_gauge")
         self.stream.synchronize()
+
+    def link_reconstruct(self, allow=None):
+        """Allow / forbid rebuilding the third link row in the hopping kernels; returns
+        whether it is in use (only when the links passed the SU(3) check)."""
+        if allow is not None:
+            self._chk(self.lib.pfmp_set_link_reconstruct(self.h, int(bool(allow))), "set_link_reconstruct")
+        a = ctypes.c_int()
+        self._chk(self.lib.pfmp_get_link_reconstruct(self.h, ctypes.byref(a)), "get_link_reconstruct")
+        return bool(a.value)
 
     def get_gauge(self):
         out = self.torch.empty((self.V, 4, 3, 3), dtype=self.torch.complex128, device=self.device)
