@@ -188,14 +188,19 @@ int pfmp_cg_solve_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *con
  * 784 complex numbers (1568 doubles, host) laid out [W1 8x12x4 | W2 8x4x12 | W0 4x4];
  * FP32 weights and arithmetic.  out = N(r) = |r| z(r/|r|) (FP64 internal spinors). */
 int pfmp_ptnet_apply(pfmp_ctx *ctx, const double *W, const void *r, void *out);
-/* Loss sum_p |z(r_p/|r_p|) - e_p/|r_p||^2 / |e_p/|r_p||^2 over npairs (r_p, e_p) and the
- * gradient matrices A (1568 doubles, host, same layout as W) with dLoss = 2 Re sum A dW. */
-int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int npairs, const void *const *r, const void *const *e,
+/* Training loss over n training vectors r_p and its gradient matrices A (1568 doubles,
+ * host, same layout as W) with dLoss = 2 Re sum A dW.  Two objectives:
+ *   op >= 0 (preconditioned residual, on slot op's Khat in FP32):
+ *           sum_p |Khat z(rhat_p) - rhat_p|^2,  rhat_p = r_p / |r_p|;  e may be NULL;
+ *   op <  0 (solution matching, pairs with Khat e_p = r_p):
+ *           sum_p |z(rhat_p) - e_p/|r_p||^2 / |e_p/|r_p||^2. */
+int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int op, int n, const void *const *r, const void *const *e,
                     double *loss, double *A);
-/* Adam (beta 0.9, 0.999) on the real and imaginary parts of W for `steps` steps over all
- * npairs pairs (full batch); W (1568 doubles, host) updated in place; losses[steps] optional. */
-int pfmp_ptnet_train(pfmp_ctx *ctx, double *W, int npairs, const void *const *r, const void *const *e, int steps,
-                     double lr, double *losses);
+/* Adam (beta 0.9, 0.999) on the real and imaginary parts of W for `steps` full-batch
+ * steps of pfmp_ptnet_grad's objective (op as there); W (1568 doubles, host) updated in
+ * place; losses[steps] optional. */
+int pfmp_ptnet_train(pfmp_ctx *ctx, double *W, int op, int n, const void *const *r, const void *const *e,
+                     int steps, double lr, double *losses);
 /* Flexible CG on Khat (Notay 2000 with one direction kept, Polak-Ribiere beta) with N as
  * preconditioner; W = NULL uses the identity (then it is CG).  Stops on the FP64 true
  * residual |b - Khat x| <= tol |b|, like pfmp_cg_solve. */

@@ -14,8 +14,9 @@ parallel-transport convolution with 12 complex colour-vector channels):
   output  N(r) = |r| z
 with d over the 8 directions (d = 2 mu: +mu, d = 2 mu + 1: -mu) and T_d the
 parallel transporter of the hop (U_mu(y) for +mu, U_mu(y - mu)^dag for -mu) times the
-fermion boundary factor.  Training pairs (r, e) with K e = r; the loss of a pair is
-|z(rhat) - e/|r||^2 / |e/|r||^2.
+fermion boundary factor.  Two training objectives: the preconditioned residual
+|K z(rhat) - rhat|^2 of a vector r (K Hermitian), and solution matching
+|z(rhat) - e/|r||^2 / |e/|r||^2 of a pair (r, e) with K e = r.
 Gradients follow the chain rule written out below; the tests pin them by finite
 differences.
 """
@@ -92,45 +93,49 @@ class PTNet:
         return self.forward(r, W1, W2, W0)[0]
 
     # ------------------------------------------------------------ loss and gradients
-    def loss(self, pairs, W1, W2, W0):
-        tot = 0.0
-        for r, e in pairs:
-            _, c = self.forward(r, W1, W2, W0)
-            eh = e / c["nr"]
-            tot += np.sum(np.abs(c["z"] - eh) ** 2) / np.sum(np.abs(eh) ** 2)
-        return tot
+    def loss(self, pairs, W1, W2, W0, K=None):
+        return self.grads(pairs, W1, W2, W0, K=K)[0]
 
-    def grads(self, pairs, W1, W2, W0):
+    def grads(self, pairs, W1, W2, W0, K=None):
         """Loss and A-matrices with dL = 2 Re sum A * dW (so dL/dRe W = 2 Re A,
-        dL/dIm W = -2 Im A)."""
+        dL/dIm W = -2 Im A).  With K (a Hermitian operator on even-site spinors) the
+        objective is the preconditioned residual sum_r |K z(rhat) - rhat|^2 over the
+        vectors r (pairs may then be plain vectors); without it, solution matching
+        sum |z(rhat) - e/|r||^2 / |e/|r||^2 over pairs (r, e)."""
         A1 = np.zeros_like(W1)
         A2 = np.zeros_like(W2)
         A0 = np.zeros_like(W0)
         tot = 0.0
-        for r, e in pairs:
+        for item in pairs:
+            r = item[0] if isinstance(item, (tuple, list)) else item
             _, c = self.forward(r, W1, W2, W0)
-            eh = e / c["nr"]
-            ne = np.sum(np.abs(eh) ** 2)
-            diff = c["z"] - eh
-            tot += np.sum(np.abs(diff) ** 2) / ne
-            Gz = diff / ne                                    # dL = 2 Re <Gz, dz>
+            if K is not None:
+                d = K(c["z"]) - c["rh"]
+                tot += np.sum(np.abs(d) ** 2)
+                Gz = K(d)                                     # dL = 2 Re <K d, dz>
+            else:
+                eh = item[1] / c["nr"]
+                ne = np.sum(np.abs(eh) ** 2)
+                diff = c["z"] - eh
+                tot += np.sum(np.abs(diff) ** 2) / ne
+                Gz = diff / ne                                # dL = 2 Re <Gz, dz>
             rh, h, q, g = c["rh"], c["h"], c["q"], c["g"]
             # W0 and W2
             A0 += np.einsum("ika,ica->kc", Gz.conj(), rh)
-            for d in range(8):
-                gn = g[self.nbr[0, :, d]]
-                tg = np.einsum("iab,icb->ica", self.T[0, :, d], gn)
-                A2[d] += np.einsum("ika,ica->kc", Gz.conj(), tg)
+            for d_ in range(8):
+                gn = g[self.nbr[0, :, d_]]
+                tg = np.einsum("iab,icb->ica", self.T[0, :, d_], gn)
+                A2[d_] += np.einsum("ika,ica->kc", Gz.conj(), tg)
             # back to g, then through the gate to h
             Gg = self._conv_adjoint(0, Gz, W2)
             s = 1 / (1 + q)
             ds = -1 / (1 + q) ** 2
             w = np.sum(Gg.conj() * h, axis=2, keepdims=True)    # <Gg, h> per channel
             Gh = s * Gg + 2 * ds * w.real * h
-            for d in range(8):
-                rn = rh[self.nbr[1, :, d]]
-                tr = np.einsum("iab,icb->ica", self.T[1, :, d], rn)
-                A1[d] += np.einsum("ika,ica->kc", Gh.conj(), tr)
+            for d_ in range(8):
+                rn = rh[self.nbr[1, :, d_]]
+                tr = np.einsum("iab,icb->ica", self.T[1, :, d_], rn)
+                A1[d_] += np.einsum("ika,ica->kc", Gh.conj(), tr)
         return tot, A1, A2, A0
 
 

@@ -9,8 +9,12 @@
 //   N(r)   = |r| z
 // d = 2 mu (+mu) / 2 mu + 1 (-mu); T_d the hop's transporter with the fermion
 // boundary factor.  Weights: complex [W1 8x12x4 | W2 8x4x12 | W0 4x4] = 784 entries.
-// Training minimises sum_pairs |z(rhat) - e/|r||^2 / |e/|r||^2 over (r, e) pairs with
-// Khat e = r; dL = 2 Re sum_w A_w dw and the kernels return the A_w.
+// Training objectives (dL = 2 Re sum_w A_w dw; the kernels return the A_w):
+//   preconditioned residual  sum_r |Khat z(rhat) - rhat|^2   (dL/dz* = Khat (Khat z - rhat))
+//   solution matching        sum_(r,e) |z(rhat) - e/|r||^2 / |e/|r||^2, Khat e = r.
+// The first asks the network for what a local operator can give a preconditioner,
+// Khat^-1 on the high modes; the second asks for the low modes too, out of reach of a
+// two-hop network.
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -158,6 +162,24 @@ __global__ __launch_bounds__(kBlock) void k_pt_gz(Geom g, const float2 *__restri
             Gz[(long)k * g.Vh + i] = make_float2(d.x * inv_ne, d.y * inv_ne);
         }
     block_sum_store<float2>(s * inv_ne, partials);
+}
+
+// d = y - scale r on even sites (FP32) and |d|^2 block partials
+__global__ __launch_bounds__(kBlock) void k_pt_resid(Geom g, const float2 *__restrict__ y,
+                                                     const double2 *__restrict__ r, float scale,
+                                                     float2 *__restrict__ d, double *__restrict__ partials)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0;
+    if (i < g.Vh)
+        for (int k = 0; k < 12; k++) {
+            double2 rv = r[(long)k * g.Vh + i];
+            float2 v = make_float2(y[(long)k * g.Vh + i].x - (float)rv.x * scale,
+                                   y[(long)k * g.Vh + i].y - (float)rv.y * scale);
+            s += (double)v.x * v.x + (double)v.y * v.y;
+            d[(long)k * g.Vh + i] = v;
+        }
+    block_sum_store<float2>(s, partials);
 }
 
 // wave-level partial of (re, im) into part[wave * stride + 2 idx]
@@ -373,34 +395,55 @@ extern "C" int pfmp_ptnet_apply(pfmp_ctx *ctx, const double *W, const void *r, v
     return pt_apply(ctx, w, (const double2 *)r, nr, (double2 *)out);
 }
 
-extern "C" int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int npairs, const void *const *R, const void *const *E,
-                               double *loss, double *A)
+extern "C" int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int op, int npairs, const void *const *R,
+                               const void *const *E, double *loss, double *A)
 {
-    if (!ctx || !W || npairs <= 0 || !R || !E || !loss || !A)
+    if (!ctx || !W || npairs <= 0 || !R || (op < 0 && !E) || !loss || !A)
         return ctx ? set_err(ctx, PFMP_ERR_ARG, "ptnet_grad: bad arguments") : PFMP_ERR_ARG;
     if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
+    if (op >= 0)
+        if (int rc0 = op_ready(ctx, op)) return rc0;
     const Geom &g = ctx->g;
     PtWs w;
     int rc = pt_ws(ctx, W, w);
     if (rc) return rc;
+    float2 *ky = nullptr, *kte = nullptr, *kto = nullptr;
+    if (op >= 0) {
+        const size_t fb = sizeof(float2) * 12L * g.Vh;
+        ky = (float2 *)ws_alloc(ctx, fb, 39);
+        kte = (float2 *)ws_alloc(ctx, fb, 40);
+        kto = (float2 *)ws_alloc(ctx, fb, 41);
+        if (!ky || !kte || !kto) return set_err(ctx, PFMP_ERR_OOM, "ptnet workspace");
+    }
     dim3 grid(nblocks(g.Vh, kBlock)), block(kBlock);
     const long nwaves = (long)grid.x * (kBlock / 64);
     std::vector<double> acc(2 * NW, 0.0);
     double tot = 0;
     std::vector<double> tmp(2 * NW);   // holds either the A2|A0 block (800) or the A1 block (768)
     for (int p = 0; p < npairs; p++) {
-        const double2 *r = (const double2 *)R[p], *e = (const double2 *)E[p];
+        const double2 *r = (const double2 *)R[p];
         double nr = host_norm(ctx, r, &rc);
         if (rc) return rc;
-        double ne = host_norm(ctx, e, &rc);
-        if (rc) return rc;
         float sc = (float)(1.0 / nr);
-        double neh = (ne / nr) * (ne / nr);
         hipLaunchKernelGGL(k_pt_l1, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, w.H, w.G);
         hipLaunchKernelGGL(k_pt_l2, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, w.G, 1.0,
                            (double2 *)nullptr, w.z);
-        hipLaunchKernelGGL(k_pt_gz, grid, block, 0, ctx->stream, g, w.z, e, sc, (float)(1.0 / neh), w.Gz, ctx->red);
         LAUNCHCHK(ctx);
+        if (op >= 0) {
+            // y = Khat z, d = y - rhat, Gz = Khat d (Khat Hermitian)
+            if ((rc = op_apply_K_f32(ctx, op, w.z, ky, kte, kto, nullptr))) return rc;
+            hipLaunchKernelGGL(k_pt_resid, grid, block, 0, ctx->stream, g, ky, r, sc, kte, ctx->red);
+            LAUNCHCHK(ctx);
+            if ((rc = op_apply_K_f32(ctx, op, kte, w.Gz, ky, kto, nullptr))) return rc;
+        } else {
+            const double2 *e = (const double2 *)E[p];
+            double ne = host_norm(ctx, e, &rc);
+            if (rc) return rc;
+            double neh = (ne / nr) * (ne / nr);
+            hipLaunchKernelGGL(k_pt_gz, grid, block, 0, ctx->stream, g, w.z, e, sc, (float)(1.0 / neh), w.Gz,
+                               ctx->red);
+            LAUNCHCHK(ctx);
+        }
         double lp;
         if ((rc = red_finish(ctx, ctx->red, grid.x, 1, &lp))) return rc;
         tot += lp;
@@ -430,15 +473,15 @@ extern "C" int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int npairs, const
 
 // Adam on the real and imaginary parts of the weights, gradient 2 conj(A) from
 // pfmp_ptnet_grad over all pairs each step; W updated in place, losses[step] filled.
-extern "C" int pfmp_ptnet_train(pfmp_ctx *ctx, double *W, int npairs, const void *const *R, const void *const *E,
-                                int steps, double lr, double *losses)
+extern "C" int pfmp_ptnet_train(pfmp_ctx *ctx, double *W, int op, int npairs, const void *const *R,
+                                const void *const *E, int steps, double lr, double *losses)
 {
     if (!ctx || !W || steps <= 0 || !(lr > 0)) return ctx ? set_err(ctx, PFMP_ERR_ARG, "ptnet_train") : PFMP_ERR_ARG;
     const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
     std::vector<double> m(2 * NW, 0.0), v(2 * NW, 0.0), A(2 * NW);
     for (int s = 0; s < steps; s++) {
         double loss;
-        int rc = pfmp_ptnet_grad(ctx, W, npairs, R, E, &loss, A.data());
+        int rc = pfmp_ptnet_grad(ctx, W, op, npairs, R, E, &loss, A.data());
         if (rc) return rc;
         if (losses) losses[s] = loss;
         const double c1 = 1 - std::pow(b1, s + 1), c2 = 1 - std::pow(b2, s + 1);

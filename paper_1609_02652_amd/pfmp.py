@@ -165,9 +165,9 @@ def load():
         "pfmp_apply_MdagM_batch": [vp, i, vp, vp, vp],
         "pfmp_cg_solve_batch": [vp, i, vp, vp, vp, vp, vp],
         "pfmp_ptnet_apply": [vp, vp, vp, vp],
-        "pfmp_ptnet_grad": [vp, vp, i, vp, vp, vp, vp],
+        "pfmp_ptnet_grad": [vp, vp, i, i, vp, vp, vp, vp],
         "pfmp_fcg_solve": [vp, i, vp, vp, vp, vp, vp],
-        "pfmp_ptnet_train": [vp, vp, i, vp, vp, i, d, vp],
+        "pfmp_ptnet_train": [vp, vp, i, i, vp, vp, i, d, vp],
         "pfmp_cg_harvest": [vp, i, vp, vp, d, i, i, vp, vp, vp, vp],
     }
     for name, args in sig.items():
@@ -385,26 +385,40 @@ class Lattice:
                   "ptnet_apply")
         return out
 
-    def ptnet_grad(self, W, pairs):
-        n = len(pairs)
+    @staticmethod
+    def _training_set(data, op):
+        """(r pointers, e pointers or None) of a training set: vectors r (op given, the
+        preconditioned-residual objective) or pairs (r, e) with Khat e = r."""
+        if op is None:
+            rs, es = [p[0] for p in data], [p[1] for p in data]
+        else:
+            rs, es = [p[0] if isinstance(p, (tuple, list)) else p for p in data], None
+        n = len(rs)
+        rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rs])
+        ep = (ctypes.c_void_p * n)(*[e.data_ptr() for e in es]) if es is not None else None
+        return n, rp, ep
+
+    def ptnet_grad(self, W, data, op=None):
+        """Loss and gradient matrices (A1, A2, A0) of the training objective: with op, the
+        preconditioned residual sum |Khat_op z(rhat) - rhat|^2 over vectors r; without,
+        solution matching over pairs (r, e)."""
+        n, rp, ep = self._training_set(data, op)
         w = self._weights(W)
-        rp = (ctypes.c_void_p * n)(*[p[0].data_ptr() for p in pairs])
-        ep = (ctypes.c_void_p * n)(*[p[1].data_ptr() for p in pairs])
         loss = ctypes.c_double()
         A = np.zeros(1568)
-        self._chk(self.lib.pfmp_ptnet_grad(self.h, w.ctypes.data_as(ctypes.c_void_p), n, rp, ep, ctypes.byref(loss),
-                                           A.ctypes.data_as(ctypes.c_void_p)), "ptnet_grad")
+        self._chk(self.lib.pfmp_ptnet_grad(self.h, w.ctypes.data_as(ctypes.c_void_p), -1 if op is None else int(op),
+                                           n, rp, ep, ctypes.byref(loss), A.ctypes.data_as(ctypes.c_void_p)),
+                  "ptnet_grad")
         return loss.value, self._unweights(A)
 
-    def ptnet_train(self, W, pairs, steps, lr=1e-2):
+    def ptnet_train(self, W, data, steps, lr=1e-2, op=None):
         """Adam in the library; returns the trained (W1, W2, W0) and the loss history."""
-        n = len(pairs)
+        n, rp, ep = self._training_set(data, op)
         w = self._weights(W).copy()
-        rp = (ctypes.c_void_p * n)(*[p[0].data_ptr() for p in pairs])
-        ep = (ctypes.c_void_p * n)(*[p[1].data_ptr() for p in pairs])
         losses = np.zeros(steps)
-        self._chk(self.lib.pfmp_ptnet_train(self.h, w.ctypes.data_as(ctypes.c_void_p), n, rp, ep, int(steps),
-                                            float(lr), losses.ctypes.data_as(ctypes.c_void_p)), "ptnet_train")
+        self._chk(self.lib.pfmp_ptnet_train(self.h, w.ctypes.data_as(ctypes.c_void_p), -1 if op is None else int(op),
+                                            n, rp, ep, int(steps), float(lr),
+                                            losses.ctypes.data_as(ctypes.c_void_p)), "ptnet_train")
         return self._unweights(w), losses
 
     def fcg_solve(self, op, W, b, x=None, tol=1e-10, maxiter=10000, check=True):

@@ -53,6 +53,19 @@ def test_gradients_match_oracle(setup):
         assert rel(b, a) < 1e-4
 
 
+def test_residual_objective_gradients_match_oracle(setup):
+    """Preconditioned-residual objective: GPU (FP32 Khat inside) against the FP64 oracle."""
+    U, lat, net, op = setup
+    W = ptnet.init_weights(5, scale=0.3)
+    rs = [synth.gaussian_spinor(lat.Vh, 30 + k) for k in range(2)]
+    loss_o, A1, A2, A0 = net.grads(rs, *W, K=op.K)
+    loss_g, (B1, B2, B0) = lat.ptnet_grad(W, [lat.pack_spinor(r) for r in rs], op=0)
+    print("residual objective: loss gpu %.6f oracle %.6f" % (loss_g, loss_o))
+    assert abs(loss_g - loss_o) < 1e-5 * loss_o
+    for a, b in ((A1, B1), (A2, B2), (A0, B0)):
+        assert rel(b, a) < 1e-4
+
+
 def test_fcg_identity_is_cg(setup):
     U, lat, net, op = setup
     b = lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 20))
@@ -64,23 +77,31 @@ def test_fcg_identity_is_cg(setup):
 
 
 def test_train_and_precondition(setup):
-    """Pairs (r_k, e_k) harvested from CG iterates of the solver itself; Adam in the
-    library; the flexible CG with the trained network reaches the same 1e-10 true
-    residual, and its iteration count against plain CG is reported."""
+    """Training vectors: residuals harvested from CG iterates of the solver itself plus
+    Gaussian vectors; Adam in the library on the preconditioned-residual objective.  The
+    flexible CG with the trained network reaches the same 1e-10 true residual; its
+    iteration count against plain CG is the network's gain."""
     U, lat, net, op = setup
-    pairs = []
+    rs = []
     for s in range(3):
         b = lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 30 + s))
         x, pr = lat.cg_harvest(0, b, [2, 6, 10, 14], tol=1e-12)
-        pairs += pr
+        rs += [r for r, _ in pr]
+    rs += [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 60 + k)) for k in range(8)]
     W0 = ptnet.init_weights(4, scale=0.05)
-    W, losses = lat.ptnet_train(W0, pairs, steps=60, lr=2e-2)
+    W, losses = lat.ptnet_train(W0, rs, steps=150, lr=1e-2, op=0)
     print("loss %.4f -> %.4f" % (losses[0], losses[-1]))
     assert losses[-1] < 0.8 * losses[0]
-    b = lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 99))
-    xp, sp = lat.fcg_solve(0, W, b, tol=1e-10, maxiter=5000)
-    xc, sc = lat.cg_solve(0, b, tol=1e-10)
-    print("flexible CG + network: %d iters (fallbacks %d), plain CG: %d iters"
-          % (sp["iters"], sp["reliable_updates"], sc["iters"]))
-    assert sp["true_res"] <= 1e-10
-    assert rel(op.K(lat.spinor_numpy(xp)), synth.gaussian_spinor(lat.Vh, 99)) <= 1.05e-10
+    bs = [synth.gaussian_spinor(lat.Vh, 99 + k) for k in range(3)]
+    it_p, it_c = 0, 0
+    for bn in bs:
+        b = lat.pack_spinor(bn)
+        xp, sp = lat.fcg_solve(0, W, b, tol=1e-10, maxiter=5000)
+        xc, sc = lat.cg_solve(0, b, tol=1e-10)
+        assert sp["true_res"] <= 1e-10
+        assert rel(op.K(lat.spinor_numpy(xp)), bn) <= 1.05e-10
+        it_p += sp["iters"]
+        it_c += sc["iters"]
+        print("flexible CG + network: %d iters (fallbacks %d), plain CG: %d iters"
+              % (sp["iters"], sp["reliable_updates"], sc["iters"]))
+    print("network gain: %.1f%% fewer iterations" % (100.0 * (1 - it_p / it_c)))

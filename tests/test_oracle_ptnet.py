@@ -52,6 +52,30 @@ def test_gradients_match_finite_differences(setup):
                 assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (which, idx, part, fd, an)
 
 
+def test_residual_objective_gradients_match_finite_differences(setup):
+    """The preconditioned-residual objective sum |K z(rhat) - rhat|^2 (K = Khat of
+    the oracle operator): analytic gradient against central differences."""
+    U, net, op, W, rs, pairs = setup
+    K = lambda v: op.K(v)
+    loss, A1, A2, A0 = net.grads(rs, *W, K=K)
+    # the loss written out independently: |K N(r)/|r| - r/|r||^2
+    direct = sum(np.linalg.norm(K(net.apply(r, *W)) - r) ** 2 / np.linalg.norm(r) ** 2 for r in rs)
+    assert abs(loss - direct) < 1e-10 * direct
+    rng = np.random.default_rng(1)
+    for which, A in ((0, A1), (1, A2), (2, A0)):
+        for _ in range(3):
+            idx = tuple(rng.integers(0, s) for s in W[which].shape)
+            for part, dirv in (("re", 1.0), ("im", 1j)):
+                eps = 1e-6
+                Wp = [w.copy() for w in W]
+                Wm = [w.copy() for w in W]
+                Wp[which][idx] += eps * dirv
+                Wm[which][idx] -= eps * dirv
+                fd = (net.loss(rs, *Wp, K=K) - net.loss(rs, *Wm, K=K)) / (2 * eps)
+                an = 2 * A[idx].real if part == "re" else -2 * A[idx].imag
+                assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (which, idx, part, fd, an)
+
+
 def test_network_is_gauge_covariant(setup):
     U, net, op, W, rs, pairs = setup
     V = 256
