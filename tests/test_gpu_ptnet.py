@@ -105,3 +105,4 @@ def test_train_and_precondition(setup):
         print("flexible CG + network: %d iters (fallbacks %d), plain CG: %d iters"
               % (sp["iters"], sp["reliable_updates"], sc["iters"]))
     print("network gain: %.1f%% fewer iterations" % (100.0 * (1 - it_p / it_c)))
+    assert it_p < 0.8 * it_c
