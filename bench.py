@@ -190,6 +190,46 @@ def cg_bench(lat, nsrc):
     return res
 
 
+def learned_bench(lat, nsrc):
+    """The learned preconditioner on Khat (kappa 0.1340): training vectors are
+    residuals the solver itself produces (CG iterates 2, 6, 10, 14, 20, 30 of 4
+    solves) plus 8 Gaussian vectors; Adam (150 full-batch steps) on the
+    preconditioned-residual objective in the library's own forward / backward
+    kernels; then flexible CG with the trained network on the benchmark sources to
+    1e-10 (FP64 true residual), against plain FP64 CG on the same sources."""
+    import torch
+    from paper_1609_02652_amd import synth
+    rs = []
+    for s in range(4):
+        b = lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 500 + s))
+        _, pr = lat.cg_harvest(0, b, [2, 6, 10, 14, 20, 30], tol=1e-10)
+        rs += [r for r, _ in pr]
+    rs += [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 600 + k)) for k in range(8)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W, losses = lat.ptnet_train(synth.network_weights(4, scale=0.05), rs, steps=150, lr=1e-2, op=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    srcs = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 1 + s)) for s in range(nsrc)]
+    x = lat.field()
+    lat.fcg_solve(0, W, srcs[0], x=x, tol=TOL)   # warm-up
+    rows = []
+    for b in srcs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = lat.fcg_solve(0, W, b, x=x, tol=TOL)
+        torch.cuda.synchronize()
+        rows.append((time.perf_counter() - t0, st["iters"], st["true_res"], st["reliable_updates"]))
+    out = {"train_vectors": len(rs), "train_steps": 150, "train_s": round(t_train, 3),
+           "loss_first": round(float(losses[0]), 4), "loss_last": round(float(losses[-1]), 4),
+           "fcg_median_s": round(float(np.median([r[0] for r in rows])), 5),
+           "fcg_iters": int(np.median([r[1] for r in rows])),
+           "fallback_steps": int(max(r[3] for r in rows)),
+           "max_true_res": float(max(r[2] for r in rows))}
+    log("learned preconditioner: %s" % out)
+    return out, W
+
+
 def run_trajectories(lat, sp, steps, warmup, seed):
     """warmup untimed, then exactly `steps` timed trajectories on fresh momenta and
     pseudofermion sources; the links are restored after each so every mode sees
@@ -255,12 +295,20 @@ def main():
 
     # ---- CG solves at 1e-10 in the three precisions
     cg = cg_bench(lat, args.sources)
-    chosen_prec = min(("f32", "f16"), key=lambda k: cg[k]["median_s"])
+    learned, W_net = learned_bench(lat, args.sources)
+    cg["learned_fcg"] = learned
+    cg["learned_gain_iters"] = round(1 - learned["fcg_iters"] / cg["f64"]["iters"], 3)
+    cg["learned_speedup_vs_f64"] = round(cg["f64"]["median_s"] / learned["fcg_median_s"], 3)
+    times = {"f32": cg["f32"]["median_s"], "f16": cg["f16"]["median_s"], "learned": learned["fcg_median_s"]}
+    chosen_prec = min(times, key=times.get)
 
     # ---- trajectories: plain FP64 form, then the chosen form (timed value)
     from paper_1609_02652_amd.pfmp import F32, F16
     sp_plain = pfmp_spec(lat)
-    sp_chosen = pfmp_spec(lat, solver_prec={"f32": F32, "f16": F16}[chosen_prec], batch=True)
+    if chosen_prec == "learned":
+        sp_chosen = pfmp_spec(lat, ptnet=W_net, batch=True)
+    else:
+        sp_chosen = pfmp_spec(lat, solver_prec={"f32": F32, "f16": F16}[chosen_prec], batch=True)
     t_plain, st_plain = run_trajectories(lat, sp_plain, args.steps, args.warmup, 100)
     t_chosen, st_chosen = run_trajectories(lat, sp_chosen, args.steps, args.warmup, 100)
     kmults = int(np.mean([s["kmults"] for s in st_plain]))
@@ -300,7 +348,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if chosen_prec == "f32" else "f16-storage/f32+f64",
+        "dtype": {"f32": "f32+f64", "f16": "f16-storage/f32+f64", "learned": "f64+f32-net"}[chosen_prec],
         "data": "synthetic",
         "config": {"workload": "PF-MP HMC trajectory on the 16^3x32 mixed-precision solve lattice: links from %d "
                                "quenched HMC trajectories at beta=5.7 from the seeded start, clover kappa=0.1340 "
@@ -308,8 +356,11 @@ def main():
                                "(ratio, correction, filter, S_det, gauge) = (20,20,120,120,480), every solve to 1e-10"
                                % args.therm,
                    "lattice": "16x16x16x32",
-                   "mode": "chosen: %s inner CG with FP64 reliable updates, batched solves; all actions, dH and "
-                           "the accept in FP64" % chosen_prec},
+                   "mode": "chosen (fastest measured solver): %s; batched solves; all actions, dH and the "
+                           "accept in FP64" % {"f32": "FP32 inner CG with FP64 reliable updates",
+                                               "f16": "FP16-storage inner CG with FP64 reliable updates",
+                                               "learned": "flexible CG with the trained PT-conv network"}[
+                               chosen_prec]},
         "trajectory": {"chosen": traj_summary(t_chosen, st_chosen), "plain_f64": traj_summary(t_plain, st_plain),
                        "speedup_vs_plain": round(t_plain / t_chosen, 3)},
         "cg_solve": dict(cg, tol=TOL, sources=args.sources),

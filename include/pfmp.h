@@ -107,6 +107,12 @@ int pfmp_get_gauge(pfmp_ctx *ctx, void *U_canonical);
  * bytes).  The link updates keep links in SU(3).  allow = 0 turns it off; *active
  * reports whether it is in use. */
 int pfmp_set_link_reconstruct(pfmp_ctx *ctx, int allow);
+/* Site visit order of the operator kernels (a cache-blocking choice; results are the
+ * same up to the order of floating-point sums in the block partials): zt = 0 visits the
+ * sites in memory order; zt > 0 (a divisor of the z extent) visits zt z-planes of one
+ * t-slice, then the same planes of the next t-slice, and so on, so that the t
+ * neighbours of a group are still in L2 when they are reused. */
+int pfmp_set_site_order(pfmp_ctx *ctx, int zt);
 int pfmp_get_link_reconstruct(pfmp_ctx *ctx, int *active);
 /* Configure slot op with (kappa, c_sw): builds A_ee, A_oo^-1 (per-site Cholesky
  * of the two 6x6 chiral blocks) and ln det A_oo.  Needs a gauge field.  Errors:

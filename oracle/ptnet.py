@@ -140,10 +140,10 @@ class PTNet:
 
 
 def init_weights(seed, scale=0.1):
-    """Small random initial weights (complex), plus W0 = identity."""
-    rng = np.random.default_rng(seed)
-    c = lambda *s: (rng.standard_normal(s) + 1j * rng.standard_normal(s)) * scale
-    return c(8, NHID, NIN), c(8, NIN, NHID), np.eye(NIN, dtype=np.complex128)
+    """Small random initial weights (complex), plus W0 = identity (the shared seeded
+    generator)."""
+    from paper_1609_02652_amd import synth
+    return synth.network_weights(seed, scale, NIN, NHID)
 
 
 def flexible_cg(apply_K, precond, b, tol, maxiter=10000):

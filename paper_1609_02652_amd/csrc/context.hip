@@ -154,6 +154,8 @@ extern "C" int pfmp_create(const int dims[4], int t_bc, void *stream, pfmp_ctx *
     ctx->g.V = (int)V;
     ctx->g.Vh = (int)(V / 2);
     ctx->g.tbc = t_bc;
+    ctx->g.recon = 0;
+    ctx->g.zt = 0;
     ctx->stream = (hipStream_t)stream;
     ctx->ws = new SolverWS();
     ctx->nblk_red = 1024;
@@ -300,6 +302,15 @@ extern "C" int pfmp_set_link_reconstruct(pfmp_ctx *ctx, int allow)
     if (!ctx) return PFMP_ERR_ARG;
     ctx->recon_allowed = allow != 0;
     ctx->g.recon = ctx->links_su3 && ctx->recon_allowed ? 1 : 0;
+    return 0;
+}
+
+extern "C" int pfmp_set_site_order(pfmp_ctx *ctx, int zt)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    if (zt < 0 || (zt > 0 && ctx->g.L[2] % zt != 0))
+        return set_err(ctx, PFMP_ERR_ARG, "site order: zt must be 0 or divide the z extent");
+    ctx->g.zt = zt;
     return 0;
 }
 

@@ -20,7 +20,7 @@ __global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const 
     if (stop && stop[0] != 0) return;
     const int tt = xcd_site(2 * g.Vh);
     if (tt < 0) return;
-    const int i = tt >> 1, hb = tt & 1;
+    const int i = tile_site(g, tt >> 1), hb = tt & 1;
     C blk[6];
     hop_pair<RC, C>(g, pout, i, hb, in, U, gin, blk);
     if (CLOV) {
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const X x
     const int tt = xcd_site(2 * g.Vh);
     double nrm = 0;
     if (tt >= 0) {
-        const int i = tt >> 1, hb = tt & 1;
+        const int i = tile_site(g, tt >> 1), hb = tt & 1;
         C acc[6], xv[6], ax[6];
         hop_pair<RC, C>(g, pout, i, hb, t, U, (R)1, acc);
         load_block(x, g.Vh, i, hb, gs, xv);

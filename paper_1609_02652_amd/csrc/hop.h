@@ -205,20 +205,35 @@ __device__ __forceinline__ C unit_mul(C v, decltype(C::x) sg)
 // w = f U h (DAG = 0) or f U^dag h (DAG = 1) for one half-spin (3 colours).  With
 // recon the link is in SU(3) and its third row is rebuilt as the conjugate cross
 // product of the first two (6 of the 9 planes read).
+// Streaming (non-temporal) load: every link is read once per hop launch, so it should
+// not displace the neighbour spinors, which are read eight times, from the caches.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream(const double2 *p)
+{
+    nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld_stream(const float2 *p)
+{
+    nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2 *>(p));
+    return make_float2(v.x, v.y);
+}
+
 template <int DAG, int RC, typename C>
 __device__ __forceinline__ void su3_vec(const C *__restrict__ U, long stride, int site, const C *h,
                                         decltype(C::x) f, C *w)
 {
     C u[9];
 #pragma unroll
-    for (int k = 0; k < 6; k++) u[k] = U[k * stride + site];
+    for (int k = 0; k < 6; k++) u[k] = ld_stream(U + k * stride + site);
     if (RC) {
         u[6] = cconj(csub(cmul(u[1], u[5]), cmul(u[2], u[4])));
         u[7] = cconj(csub(cmul(u[2], u[3]), cmul(u[0], u[5])));
         u[8] = cconj(csub(cmul(u[0], u[4]), cmul(u[1], u[3])));
     } else {
 #pragma unroll
-        for (int k = 6; k < 9; k++) u[k] = U[k * stride + site];
+        for (int k = 6; k < 9; k++) u[k] = ld_stream(U + k * stride + site);
     }
 #pragma unroll
     for (int a = 0; a < 3; a++) {

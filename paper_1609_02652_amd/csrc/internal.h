@@ -58,6 +58,7 @@ struct Geom {
     int V;
     int tbc;        // fermion factor across the t boundary
     int recon;      // 1: every link is in SU(3), the hopping kernels rebuild row 3 from rows 1, 2
+    int zt;         // site visit order of the operator kernels: 0 natural, else groups of zt z-planes
 };
 
 // Coordinates of even-odd site i of parity p: lex = 2i or 2i+1, whichever has parity p.
@@ -93,6 +94,22 @@ __device__ __forceinline__ int eo_neighbour(const Geom &g, const int c[4], int m
     d[mu] = v;
     *fsign = s;
     return eo_index(g, d);
+}
+
+// Even-odd index of the l-th site in the visit order of the operator kernels.  With
+// zt > 0 the (x, y) planes are visited in memory order, zt z-planes at a time, then the
+// next t, and only then the next group of z-planes: the spinors of the t - 1, t, t + 1
+// slices of one group stay in L2 until their last use instead of a whole 3 t-slices.
+__device__ __forceinline__ int tile_site(const Geom &g, int l)
+{
+    if (g.zt <= 0) return l;
+    const int plane = g.Lh0 * g.L[1];
+    const int xy = l % plane;
+    int r = l / plane;
+    const int zi = r % g.zt;
+    r /= g.zt;
+    const int t = r % g.L[3], zb = r / g.L[3];
+    return xy + plane * (zb * g.zt + zi + g.L[2] * t);
 }
 
 // Site of this thread with an XCD-aware block order: the hardware hands

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
     const int tt = xcd_site(2 * g.Vh);
     double nrm = 0;
     if (tt >= 0) {
-        const int i = tt >> 1, hb = tt & 1;
+        const int i = tile_site(g, tt >> 1), hb = tt & 1;
         double2 acc[6], tv[6], at[6];
         hop_pair<RC, double2>(g, 0, i, hb, T, U, 1.0, acc);
         load_block(t, g.Vh, i, hb, -1.0, tv);

@@ -161,6 +161,7 @@ def load():
         "pfmp_md_evolve": [vp, vp, vp, vp, vp],
         "pfmp_trajectory": [vp, vp, vp, vp, d, vp, vp],
         "pfmp_set_link_reconstruct": [vp, i],
+        "pfmp_set_site_order": [vp, i],
         "pfmp_get_link_reconstruct": [vp, vp],
         "pfmp_apply_MdagM_batch": [vp, i, vp, vp, vp],
         "pfmp_cg_solve_batch": [vp, i, vp, vp, vp, vp, vp],
@@ -263,6 +264,10 @@ class Lattice:
         a = ctypes.c_int()
         self._chk(self.lib.pfmp_get_link_reconstruct(self.h, ctypes.byref(a)), "get_link_reconstruct")
         return bool(a.value)
+
+    def site_order(self, zt):
+        """Visit order of the operator kernels: 0 memory order, zt > 0 groups of zt z-planes."""
+        self._chk(self.lib.pfmp_set_site_order(self.h, int(zt)), "set_site_order")
 
     def get_gauge(self):
         out = self.torch.empty((self.V, 4, 3, 3), dtype=self.torch.complex128, device=self.device)

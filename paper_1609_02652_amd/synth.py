@@ -90,3 +90,13 @@ def gaussian_momenta(V, seed):
 def uniform(seed, n=1):
     rng = np.random.default_rng(seed)
     return rng.random(n)
+
+
+def network_weights(seed, scale=0.1, nin=4, nhid=12):
+    """Initial weights of the parallel-transport convolution network: complex
+    N(0, 2 scale^2) entries for the two transport layers [8][nhid][nin] and
+    [8][nin][nhid], and the identity for the site-local skip term [nin][nin] (so
+    the network starts close to the identity preconditioner)."""
+    rng = np.random.default_rng(seed)
+    c = lambda *s: (rng.standard_normal(s) + 1j * rng.standard_normal(s)) * scale
+    return c(8, nhid, nin), c(8, nin, nhid), np.eye(nin, dtype=np.complex128)
