@@ -75,6 +75,7 @@ def hop_roofline(dims, U, reps=200):
     output 24 + clover 72 reals."""
     from paper_1609_02652_amd.pfmp import F64
     lat = make_lattice(dims, U)
+    tune = lat.autotune(0)
     from paper_1609_02652_amd import synth
     x = lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 1))
     out = lat.field()
@@ -88,7 +89,7 @@ def hop_roofline(dims, U, reps=200):
     bytes_m = lat.Vh * (2 * (8 * link_reals + 24 + 24) + 72 * 2 + 24) * 8
     lat.close()
     return {"t_hop": t_plain, "bytes_hop": bytes_plain, "t_M": t_m, "bytes_M": bytes_m, "Vh": lat.Vh,
-            "link_reals": link_reals}
+            "link_reals": link_reals, "tune": tune}
 
 
 def roofline_only(reps):
@@ -100,7 +101,7 @@ def roofline_only(reps):
     out = {}
     for dims in (DIMS, (32, 32, 32, 64)):
         r = hop_roofline(dims, synth.random_gauge(dims, seed=5), reps=reps)
-        out["x".join(map(str, dims))] = {"hop_us": round(r["t_hop"] * 1e6, 2),
+        out["x".join(map(str, dims))] = {"hop_us": round(r["t_hop"] * 1e6, 2), "tuning": r["tune"],
                                          "hop_GBps": round(r["bytes_hop"] / r["t_hop"] / 1e9, 1),
                                          "hop_bytes": r["bytes_hop"], "Mhat_us": round(r["t_M"] * 1e6, 2)}
     n = 256 * 1024 * 1024 // 8
@@ -291,6 +292,8 @@ def main():
     therm = thermalise(lat, args.therm)
     lat.set_operator(0, KAPPA, CSW)
     lat.set_operator(1, KAPPA_H, CSW)
+    tune = lat.autotune(0)
+    log("autotune: %s" % tune)
     U = lat.get_gauge().cpu().numpy()
 
     # ---- CG solves at 1e-10 in the three precisions
@@ -321,7 +324,7 @@ def main():
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "avg_launch_us": round(rf["t_hop"] * 1e6, 2), "bytes_per_launch": rf["bytes_hop"],
-            "Mhat_GBps": round(rf["bytes_M"] / rf["t_M"] / 1e9, 1),
+            "Mhat_GBps": round(rf["bytes_M"] / rf["t_M"] / 1e9, 1), "tuning": rf["tune"],
             "note": "16^3x32 working set fits the 256 MB Infinity Cache"}
     big = (32, 32, 32, 64)
     try:
@@ -329,6 +332,8 @@ def main():
         roof["hop_32x64_GBps"] = round(rb["bytes_hop"] / rb["t_hop"] / 1e9, 1)
         roof["hop_32x64_frac"] = round(rb["bytes_hop"] / rb["t_hop"] / 1e9 / HBM_PEAK_GBS, 4)
         roof["Mhat_32x64_GBps"] = round(rb["bytes_M"] / rb["t_M"] / 1e9, 1)
+        roof["hop_32x64_us"] = round(rb["t_hop"] * 1e6, 2)
+        roof["tuning_32x64"] = rb["tune"]
     except Exception as e:  # noqa: BLE001 -- report, do not hide
         roof["hop_32x64_error"] = str(e)
 
@@ -365,6 +370,7 @@ def main():
                        "speedup_vs_plain": round(t_plain / t_chosen, 3)},
         "cg_solve": dict(cg, tol=TOL, sources=args.sources),
         "thermalisation": therm,
+        "autotune": tune,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

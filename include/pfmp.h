@@ -113,6 +113,19 @@ int pfmp_set_link_reconstruct(pfmp_ctx *ctx, int allow);
  * t-slice, then the same planes of the next t-slice, and so on, so that the t
  * neighbours of a group are still in L2 when they are reused. */
 int pfmp_set_site_order(pfmp_ctx *ctx, int zt);
+/* Streaming (non-temporal) link loads in the hopping kernels: on = 1 keeps the links,
+ * read once per launch, from displacing the neighbour spinors in the caches.  The
+ * default is on when the FP64 gauge field exceeds 128 MiB. */
+int pfmp_set_link_streaming(pfmp_ctx *ctx, int on);
+typedef struct {
+    int zt;          /* chosen site visit order (pfmp_set_site_order) */
+    int stream;      /* chosen link load mode (pfmp_set_link_streaming) */
+    double us_Mhat;  /* time of one FP64 Mhat application with that choice, microseconds */
+} pfmp_tuning;
+/* Autotuner: times one FP64 Mhat of slot op (HIP events, 10 repetitions) for every visit
+ * order (0 and each divisor of the z extent from 2 to 16) with cached and with streaming
+ * link loads and keeps the fastest for all later launches.  Synchronises. */
+int pfmp_autotune(pfmp_ctx *ctx, int op, pfmp_tuning *out);
 int pfmp_get_link_reconstruct(pfmp_ctx *ctx, int *active);
 /* Configure slot op with (kappa, c_sw): builds A_ee, A_oo^-1 (per-site Cholesky
  * of the two 6x6 chiral blocks) and ln det A_oo.  Needs a gauge field.  Errors:

@@ -156,6 +156,9 @@ extern "C" int pfmp_create(const int dims[4], int t_bc, void *stream, pfmp_ctx *
     ctx->g.tbc = t_bc;
     ctx->g.recon = 0;
     ctx->g.zt = 0;
+    // links streamed past the caches once the FP64 gauge field outgrows a good part of
+    // the last-level cache (the autotuner may revise this and the visit order)
+    ctx->g.stream = 8.0 * gauge_reals(ctx->g) > 128.0 * 1024 * 1024 ? 1 : 0;
     ctx->stream = (hipStream_t)stream;
     ctx->ws = new SolverWS();
     ctx->nblk_red = 1024;
@@ -311,6 +314,66 @@ extern "C" int pfmp_set_site_order(pfmp_ctx *ctx, int zt)
     if (zt < 0 || (zt > 0 && ctx->g.L[2] % zt != 0))
         return set_err(ctx, PFMP_ERR_ARG, "site order: zt must be 0 or divide the z extent");
     ctx->g.zt = zt;
+    return 0;
+}
+
+extern "C" int pfmp_set_link_streaming(pfmp_ctx *ctx, int on)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    ctx->g.stream = on ? 1 : 0;
+    return 0;
+}
+
+// Time stage 1 + stage 2 of Mhat (slot op, FP64) for every site visit order (memory
+// order and each divisor of the z extent up to 16) with cached and with streaming
+// link loads; keep the fastest.
+extern "C" int pfmp_autotune(pfmp_ctx *ctx, int op, pfmp_tuning *out)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    int rc = op_ready(ctx, op);
+    if (rc) return rc;
+    double2 *in = pool_get(ctx, 2400), *o = pool_get(ctx, 2401), *tmp = pool_get(ctx, 2402);
+    if (!in || !o || !tmp) return set_err(ctx, PFMP_ERR_OOM, "autotune workspace");
+    HIPCHK(ctx, hipMemsetAsync(in, 0, sizeof(double) * spinor_reals(ctx->g), ctx->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    const Geom keep = ctx->g;
+    double best = 1e30;
+    int bzt = keep.zt, bst = keep.stream;
+    const int reps = 10;
+    for (int st = 0; st < 2; st++)
+        for (int zt = 0; zt <= 16 && zt <= keep.L[2]; zt++) {
+            if (zt == 1 || (zt > 0 && keep.L[2] % zt != 0)) continue;
+            ctx->g.zt = zt;
+            ctx->g.stream = st;
+            for (int k = 0; k < 2; k++)
+                if ((rc = op_apply_M(ctx, op, 0, in, o, tmp, nullptr))) break;
+            if (!rc) rc = hipEventRecord(e0, ctx->stream) == hipSuccess ? 0 : set_err(ctx, PFMP_ERR_HIP, "event");
+            for (int k = 0; k < reps && !rc; k++) rc = op_apply_M(ctx, op, 0, in, o, tmp, nullptr);
+            if (!rc) rc = hipEventRecord(e1, ctx->stream) == hipSuccess ? 0 : set_err(ctx, PFMP_ERR_HIP, "event");
+            float ms = 0;
+            if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = set_err(ctx, PFMP_ERR_HIP, "autotune timing");
+            if (rc) break;
+            const double us = 1e3 * ms / reps;
+            if (us < best) {
+                best = us;
+                bzt = zt;
+                bst = st;
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ctx->g = keep;
+    if (rc) return rc;
+    ctx->g.zt = bzt;
+    ctx->g.stream = bst;
+    if (out) {
+        out->zt = bzt;
+        out->stream = bst;
+        out->us_Mhat = best;
+    }
     return 0;
 }
 

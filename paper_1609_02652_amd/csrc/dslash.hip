@@ -12,7 +12,7 @@ namespace {
 // out = [g5] A^-1 D in [g5], output parity pout (CLOV = 0: no clover); In / Out are
 // spinor pointers of the register type C or FP16 storage (HalfField).  Two lanes per
 // site, lane hb writing chiral block hb.
-template <typename C, typename R, int CLOV, int RC, typename In, typename Out>
+template <typename C, typename R, int CLOV, int LM, typename In, typename Out>
 __global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const In in, const C *__restrict__ U,
                                                         const R *__restrict__ cl, Out out, R gin, R gout,
                                                         const double *__restrict__ stop)
@@ -22,7 +22,7 @@ __global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const 
     if (tt < 0) return;
     const int i = tile_site(g, tt >> 1), hb = tt & 1;
     C blk[6];
-    hop_pair<RC, C>(g, pout, i, hb, in, U, gin, blk);
+    hop_pair<LM, C>(g, pout, i, hb, in, U, gin, blk);
     if (CLOV) {
         C t[6];
         clover_block<R, C>(cl, g.Vh, i, hb, blk, t);
@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const 
 }
 
 // out = [g5] (A [g5] x + a D t), output parity pout; NORM: |out|^2 block partials
-template <typename C, typename R, int CLOV, int NORM, int RC, typename X, typename T, typename Out>
+template <typename C, typename R, int CLOV, int NORM, int LM, typename X, typename T, typename Out>
 __global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const X x, const T t,
                                                      const C *__restrict__ U, const R *__restrict__ cl, R a, Out out,
                                                      R gs, double *partials, const double *__restrict__ stop)
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const X x
     if (tt >= 0) {
         const int i = tile_site(g, tt >> 1), hb = tt & 1;
         C acc[6], xv[6], ax[6];
-        hop_pair<RC, C>(g, pout, i, hb, t, U, (R)1, acc);
+        hop_pair<LM, C>(g, pout, i, hb, t, U, (R)1, acc);
         load_block(x, g.Vh, i, hb, gs, xv);
         if (CLOV) clover_block<R, C>(cl, g.Vh, i, hb, xv, ax);
 #pragma unroll
@@ -65,14 +65,16 @@ int launch_clovinv(pfmp_ctx *ctx, int pout, In in, const C *U, const R *cl, Out 
                    const double *stop)
 {
     dim3 grid(op_nparts(ctx->g)), block(kBlock);
-#define CLOVINV(CL, RC)                                                                                           \
-    hipLaunchKernelGGL((k_hop_clovinv<C, R, CL, RC, In, Out>), grid, block, 0, ctx->stream, ctx->g, pout, in, U, cl, \
+#define CLOVINV(CL, LM)                                                                                           \
+    hipLaunchKernelGGL((k_hop_clovinv<C, R, CL, LM, In, Out>), grid, block, 0, ctx->stream, ctx->g, pout, in, U, cl, \
                        out, gin, gout, stop)
-    const bool rc = ctx->g.recon != 0;
-    if (clov && rc) CLOVINV(1, 1);
-    else if (clov) CLOVINV(1, 0);
-    else if (rc) CLOVINV(0, 1);
-    else CLOVINV(0, 0);
+#define CLOVINV1(LM) CLOVINV(1, LM)
+#define CLOVINV0(LM) CLOVINV(0, LM)
+    const int lm = link_mode(ctx->g);
+    if (clov) { PFMP_LM_SWITCH(lm, CLOVINV1) }
+    else { PFMP_LM_SWITCH(lm, CLOVINV0) }
+#undef CLOVINV1
+#undef CLOVINV0
 #undef CLOVINV
     LAUNCHCHK(ctx);
     return 0;
@@ -83,17 +85,22 @@ int launch_xpay(pfmp_ctx *ctx, int pout, X x, T t, const C *U, const R *cl, R a,
                 double *partials, const double *stop)
 {
     dim3 grid(op_nparts(ctx->g)), block(kBlock);
-#define XPAY(CL, NM, RC)                                                                                           \
-    hipLaunchKernelGGL((k_hop_xpay<C, R, CL, NM, RC, X, T, Out>), grid, block, 0, ctx->stream, ctx->g, pout, x, t, U, \
+#define XPAY(CL, NM, LM)                                                                                           \
+    hipLaunchKernelGGL((k_hop_xpay<C, R, CL, NM, LM, X, T, Out>), grid, block, 0, ctx->stream, ctx->g, pout, x, t, U, \
                        cl, a, out, gs, partials, stop)
-#define XPAY2(CL, NM)                                                                                               \
-    if (ctx->g.recon) XPAY(CL, NM, 1);                                                                              \
-    else XPAY(CL, NM, 0)
-    if (clov && partials) { XPAY2(1, 1); }
-    else if (clov) { XPAY2(1, 0); }
-    else if (partials) { XPAY2(0, 1); }
-    else { XPAY2(0, 0); }
-#undef XPAY2
+#define XPAY11(LM) XPAY(1, 1, LM)
+#define XPAY10(LM) XPAY(1, 0, LM)
+#define XPAY01(LM) XPAY(0, 1, LM)
+#define XPAY00(LM) XPAY(0, 0, LM)
+    const int lm = link_mode(ctx->g);
+    if (clov && partials) { PFMP_LM_SWITCH(lm, XPAY11) }
+    else if (clov) { PFMP_LM_SWITCH(lm, XPAY10) }
+    else if (partials) { PFMP_LM_SWITCH(lm, XPAY01) }
+    else { PFMP_LM_SWITCH(lm, XPAY00) }
+#undef XPAY11
+#undef XPAY10
+#undef XPAY01
+#undef XPAY00
 #undef XPAY
     LAUNCHCHK(ctx);
     return 0;

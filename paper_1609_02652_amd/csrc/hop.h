@@ -220,20 +220,21 @@ __device__ __forceinline__ float2 ld_stream(const float2 *p)
     return make_float2(v.x, v.y);
 }
 
-template <int DAG, int RC, typename C>
+// LM (link mode): bit 0 rebuild the third row, bit 1 streaming loads
+template <int DAG, int LM, typename C>
 __device__ __forceinline__ void su3_vec(const C *__restrict__ U, long stride, int site, const C *h,
                                         decltype(C::x) f, C *w)
 {
     C u[9];
 #pragma unroll
-    for (int k = 0; k < 6; k++) u[k] = ld_stream(U + k * stride + site);
-    if (RC) {
+    for (int k = 0; k < 6; k++) u[k] = (LM & 2) ? ld_stream(U + k * stride + site) : U[k * stride + site];
+    if (LM & 1) {
         u[6] = cconj(csub(cmul(u[1], u[5]), cmul(u[2], u[4])));
         u[7] = cconj(csub(cmul(u[2], u[3]), cmul(u[0], u[5])));
         u[8] = cconj(csub(cmul(u[0], u[4]), cmul(u[1], u[3])));
     } else {
 #pragma unroll
-        for (int k = 6; k < 9; k++) u[k] = ld_stream(U + k * stride + site);
+        for (int k = 6; k < 9; k++) u[k] = (LM & 2) ? ld_stream(U + k * stride + site) : U[k * stride + site];
     }
 #pragma unroll
     for (int a = 0; a < 3; a++) {
@@ -247,7 +248,7 @@ __device__ __forceinline__ void su3_vec(const C *__restrict__ U, long stride, in
     }
 }
 
-template <int MU, int RC, typename C, typename In>
+template <int MU, int LM, typename C, typename In>
 __device__ __forceinline__ void hop_dir_pair(const Geom &g, int pout, int i, const int *c, int hb, const In in,
                                              const C *__restrict__ U, decltype(C::x) gs, C *up, C *loA, C *loB)
 {
@@ -268,7 +269,7 @@ __device__ __forceinline__ void hop_dir_pair(const Geom &g, int pout, int i, con
         C pq = cscale(load_comp(in, g.Vh, jf, 3 * q + a), gs);
         h[a] = csub(pt, unit_mul<IM>(pq, sgp));
     }
-    su3_vec<0, RC>(U + ((long)(pout * 4 + MU) * 9) * Vh, Vh, i, h, (R)sf, w);
+    su3_vec<0, LM>(U + ((long)(pout * 4 + MU) * 9) * Vh, Vh, i, h, (R)sf, w);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         up[a] = cadd(up[a], w[a]);
@@ -282,7 +283,7 @@ __device__ __forceinline__ void hop_dir_pair(const Geom &g, int pout, int i, con
         C pq = cscale(load_comp(in, g.Vh, jb, 3 * q + a), gs);
         h[a] = cadd(pt, unit_mul<IM>(pq, sgp));
     }
-    su3_vec<1, RC>(U + ((long)((1 - pout) * 4 + MU) * 9) * Vh, Vh, jb, h, (R)sb, w);
+    su3_vec<1, LM>(U + ((long)((1 - pout) * 4 + MU) * 9) * Vh, Vh, jb, h, (R)sb, w);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         up[a] = cadd(up[a], w[a]);
@@ -294,8 +295,8 @@ __device__ __forceinline__ double pair_swap(double v) { return __shfl_xor(v, 1, 
 __device__ __forceinline__ float pair_swap(float v) { return __shfl_xor(v, 1, 64); }
 
 // D_hop in (gs = -1 flips the lower spins of the input), chiral block hb of the
-// result at output site i of parity pout; RC: rebuild the third link row
-template <int RC, typename C, typename In>
+// result at output site i of parity pout; LM: link mode (see su3_vec)
+template <int LM, typename C, typename In>
 __device__ __forceinline__ void hop_pair(const Geom &g, int pout, int i, int hb, const In in, const C *__restrict__ U,
                                          decltype(C::x) gs, C *blk)
 {
@@ -304,10 +305,10 @@ __device__ __forceinline__ void hop_pair(const Geom &g, int pout, int i, int hb,
     C up[3], loA[3], loB[3];   // upper spin hb; lower spins 3 - hb and 2 + hb
 #pragma unroll
     for (int a = 0; a < 3; a++) up[a] = loA[a] = loB[a] = mk<C>(0, 0);
-    hop_dir_pair<0, RC, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
-    hop_dir_pair<1, RC, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
-    hop_dir_pair<2, RC, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
-    hop_dir_pair<3, RC, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
+    hop_dir_pair<0, LM, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
+    hop_dir_pair<1, LM, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
+    hop_dir_pair<2, LM, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
+    hop_dir_pair<3, LM, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
     // lane 0 keeps spin 0 and takes spin 1 from lane 1; lane 1 sums the lower spins
     C x[6];
 #pragma unroll

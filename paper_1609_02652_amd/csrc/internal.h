@@ -59,7 +59,18 @@ struct Geom {
     int tbc;        // fermion factor across the t boundary
     int recon;      // 1: every link is in SU(3), the hopping kernels rebuild row 3 from rows 1, 2
     int zt;         // site visit order of the operator kernels: 0 natural, else groups of zt z-planes
+    int stream;     // 1: the hopping kernels load links with streaming (non-temporal) loads
 };
+
+// link mode of the hopping kernels: bit 0 row reconstruction, bit 1 streaming loads
+inline int link_mode(const Geom &g) { return (g.recon ? 1 : 0) | (g.stream ? 2 : 0); }
+#define PFMP_LM_SWITCH(lm, M)        \
+    switch (lm) {                    \
+    case 0: M(0); break;             \
+    case 1: M(1); break;             \
+    case 2: M(2); break;             \
+    default: M(3); break;            \
+    }
 
 // Coordinates of even-odd site i of parity p: lex = 2i or 2i+1, whichever has parity p.
 __device__ __forceinline__ void eo_coords(const Geom &g, int p, int i, int c[4])

@@ -15,8 +15,24 @@
 
 namespace {
 
-enum { M_RR = 0, M_THR, M_DTHR, M_PAP, M_ALPHA, M_BETA, M_ITER, M_DONE, M_MAXIT };
+enum { M_RR = 0, M_THR, M_DTHR, M_PAP, M_ALPHA, M_BETA, M_ITER, M_DONE, M_MAXIT, M_RROLD };
 constexpr int kMixBase = 4096;    // device scalar slots of this solver (ctx->scal + kMixBase)
+
+// sum of n partials, the same in every block (fixed order); NT threads per block
+template <int NT>
+__device__ __forceinline__ double block_total_t(const double *__restrict__ part, int n)
+{
+    __shared__ double sh[NT / 64];
+    double s = 0;
+    for (int k = threadIdx.x; k < n; k += NT) s += part[k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0;
+    for (int k = 0; k < NT / 64; k++) t += sh[k];
+    __syncthreads();
+    return t;
+}
 
 __device__ __forceinline__ double block_total_m(const double *__restrict__ partials, int nparts)
 {
@@ -50,50 +66,34 @@ __global__ __launch_bounds__(kRedBlock) void k_m_restart(const double *__restric
     }
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_m_alpha(const double *__restrict__ partials, int nparts,
-                                                       double *__restrict__ st)
-{
-    if (st[M_DONE] != 0) return;
-    double pap = block_total_m(partials, nparts);
-    if (threadIdx.x == 0) {
-        st[M_PAP] = pap;
-        st[M_ALPHA] = st[M_RR] / pap;
-    }
-}
-
-__global__ __launch_bounds__(kRedBlock) void k_m_beta(const double *__restrict__ partials, int nparts,
-                                                      double *__restrict__ st)
-{
-    if (st[M_DONE] != 0) return;
-    double rr = block_total_m(partials, nparts);
-    if (threadIdx.x == 0) {
-        st[M_BETA] = rr / st[M_RR];
-        st[M_RR] = rr;
-        st[M_ITER] += 1;
-        // 1: inner residual at the target; 3: dropped by delta; 2: iteration limit
-        st[M_DONE] = rr <= st[M_THR] ? 1 : (rr <= st[M_DTHR] ? 3 : (st[M_ITER] >= st[M_MAXIT] ? 2 : 0));
-    }
-}
-
 // FP32 Khat p from t = Mhat p and T' (as in the FP64 solver), fused with
-// x += alpha p, r -= alpha Khat p and FP64 |r|^2 partials
-template <int CLOV, int RC, typename S>
+// x += alpha p, r -= alpha Khat p and FP64 |r|^2 partials.  alpha = |r|^2 / <p, Khat p>
+// is formed in every block from the stage-2 partials; block 0 keeps |r|^2 for beta.
+template <int CLOV, int LM, typename S>
 __global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T, const float2 *__restrict__ U,
                                                    const float *__restrict__ cl, float a, const S p,
                                                    float2 *__restrict__ x, float2 *__restrict__ r,
-                                                   const double *__restrict__ st, double *__restrict__ partials)
+                                                   double *__restrict__ st, double *__restrict__ partials,
+                                                   const double *__restrict__ part_pap, int npap)
 {
     if (st[M_DONE] != 0) return;
+    const double pap = block_total_t<kBlock>(part_pap, npap);
+    const double alpha_d = st[M_RR] / pap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st[M_PAP] = pap;
+        st[M_ALPHA] = alpha_d;
+        st[M_RROLD] = st[M_RR];
+    }
     const int tt = xcd_site(2 * g.Vh);
     double nrm = 0;
     if (tt >= 0) {
         const int i = tile_site(g, tt >> 1), hb = tt & 1;
         float2 acc[6], tv[6], at[6], pp[6];
-        hop_pair<RC, float2>(g, 0, i, hb, T, U, 1.f, acc);
+        hop_pair<LM, float2>(g, 0, i, hb, T, U, 1.f, acc);
         load_block(t, g.Vh, i, hb, -1.f, tv);
         load_block(p, g.Vh, i, hb, 1.f, pp);
         if (CLOV) clover_block<float, float2>(cl, g.Vh, i, hb, tv, at);
-        const float alpha = (float)st[M_ALPHA];
+        const float alpha = (float)alpha_d;
         const long Vh = g.Vh;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
@@ -113,18 +113,37 @@ __global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T,
 }
 
 // p = r + beta p (per site: FP16 storage needs the site's 24 reals for its scale);
-// with st == nullptr: p = r
+// with st == nullptr: p = r.  With part_rr: beta = |r+|^2 / |r|^2 formed in every block
+// from the stage-4 partials; every block takes the same stop decision from it (1: inner
+// residual at the target, 3: dropped by delta -> reliable update, 2: iteration limit)
+// and skips the update then, which the restart after a reliable update relies on;
+// block 0 records the state.  Without part_rr: beta from st (restart).
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_m_update_p(Geom g, const float2 *__restrict__ r, S p,
-                                                       const double *__restrict__ st)
+                                                       double *__restrict__ st, const double *__restrict__ part_rr,
+                                                       int nrr)
 {
     if (st && st[M_DONE] != 0) return;
+    double bd = st ? st[M_BETA] : 0.0;
+    if (part_rr) {
+        const double rr = block_total_t<kBlock>(part_rr, nrr);
+        const double it = st[M_ITER] + 1;
+        const int done = rr <= st[M_THR] ? 1 : (rr <= st[M_DTHR] ? 3 : (it >= st[M_MAXIT] ? 2 : 0));
+        bd = rr / st[M_RROLD];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st[M_BETA] = bd;
+            st[M_RR] = rr;
+            st[M_ITER] = it;
+            st[M_DONE] = done;
+        }
+        if (done) return;
+    }
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.Vh) return;
     float2 rv[12], pv[12];
     load_spinor(r, g.Vh, i, 1.f, rv);
     if (st) {
-        const float b = (float)st[M_BETA];
+        const float b = (float)bd;
         load_spinor(p, g.Vh, i, 1.f, pv);
 #pragma unroll
         for (int k = 0; k < 12; k++) rv[k] = make_float2(rv[k].x + b * pv[k].x, rv[k].y + b * pv[k].y);
@@ -217,12 +236,12 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
     // r = b, rs = (float) b, p = rs
     hipLaunchKernelGGL(k_m_residual, dim3(ctx->nblk_red), dim3(kRedBlock), 0, ctx->stream, n, b, Kx, rs, ctx->red);
     hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
-                       nullptr);
+                       nullptr, nullptr, 0);
     hipLaunchKernelGGL(k_m_restart, dim3(1), dim3(kRedBlock), 0, ctx->stream, ctx->red, ctx->nblk_red, tol2bb,
                        delta * delta, prm->maxiter, 1, sc);
     LAUNCHCHK(ctx);
-    int chunk = prm->check_every > 0 ? prm->check_every : 25;
-    int updates = 0, kmults = 0;
+    int chunk = prm->check_every > 0 ? prm->check_every : 16;
+    int updates = 0, kmults = 0, last_iter = 0;
     double h[16], res = 0;
     for (;;) {
         for (int k = 0; k < chunk; k++) {
@@ -232,27 +251,30 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
             if ((rc = launch_xpay<float2, float, In, In, S>(ctx, 0, ps, Ts, ctx->Uf, s.clovf[0], mk2, ts, 1.f, cl,
                                                              part_a, sc + M_DONE)))
                 return rc;
-            hipLaunchKernelGGL(k_m_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_a, nb, sc);
             if ((rc = launch_clovinv<float2, float, In, S>(ctx, 1, ts, ctx->Uf, s.clovf[1], Ts, -1.f, 1.f, cl,
                                                             sc + M_DONE)))
                 return rc;
-#define MHOP4(CL, RC)                                                                                       \
-    hipLaunchKernelGGL((k_m_hop4<CL, RC, In>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,     \
-                       s.clovf[0], mk2, ps, xs, rs, sc, part_b)
-            if (cl && g.recon) MHOP4(1, 1);
-            else if (cl) MHOP4(1, 0);
-            else if (g.recon) MHOP4(0, 1);
-            else MHOP4(0, 0);
+#define MHOP4(CL, LM)                                                                                       \
+    hipLaunchKernelGGL((k_m_hop4<CL, LM, In>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,     \
+                       s.clovf[0], mk2, ps, xs, rs, sc, part_b, part_a, nb)
+#define MHOP4_1(LM) MHOP4(1, LM)
+#define MHOP4_0(LM) MHOP4(0, LM)
+            if (cl) { PFMP_LM_SWITCH(link_mode(g), MHOP4_1) }
+            else { PFMP_LM_SWITCH(link_mode(g), MHOP4_0) }
+#undef MHOP4_1
+#undef MHOP4_0
 #undef MHOP4
-            hipLaunchKernelGGL(k_m_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, sc);
             hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
-                               sc);
+                               sc, part_b, nb);
             LAUNCHCHK(ctx);
         }
         HIPCHK(ctx, hipMemcpyAsync(ctx->red_host, sc, sizeof(double) * 16, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
         for (int k = 0; k < 16; k++) h[k] = ctx->red_host[k];
-        if (h[M_DONE] == 0) continue;
+        if (h[M_DONE] == 0) {
+            if (prm->check_every <= 0) chunk = 4;   // close in on the flagged iteration
+            continue;
+        }
         // reliable update in FP64
         hipLaunchKernelGGL(k_m_accum, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, xs, x);
         if ((rc = op_apply_K(ctx, op, x, Kx, te, to, nullptr))) return rc;
@@ -267,8 +289,14 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
         hipLaunchKernelGGL(k_m_restart, dim3(1), dim3(kRedBlock), 0, ctx->stream, ctx->red, ctx->nblk_red, tol2bb,
                            delta * delta, prm->maxiter, 0, sc);
         hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
-                           sc);
+                           sc, nullptr, 0);
         LAUNCHCHK(ctx);
+        // the next chunk: about as long as the last stretch between reliable updates
+        if (prm->check_every <= 0) {
+            const int stretch = (int)h[M_ITER] - last_iter;
+            chunk = stretch > 4 ? stretch - 1 : 4;
+        }
+        last_iter = (int)h[M_ITER];
     }
     auto t1 = std::chrono::steady_clock::now();
     if (st) {

@@ -10,7 +10,7 @@
 namespace {
 
 // dst = g5 (A_ee g5 t - kappa^2 D_eo T') - z src, with t = Mhat src, T' = A_oo^-1 D_oe g5 t
-template <int CLOV, int RC>
+template <int CLOV, int LM>
 __global__ __launch_bounds__(kBlock) void k_poly_last(Geom g, const double2 *__restrict__ t,
                                                       const double2 *__restrict__ T, const double2 *__restrict__ U,
                                                       const double *__restrict__ cl, double a,
@@ -21,7 +21,7 @@ __global__ __launch_bounds__(kBlock) void k_poly_last(Geom g, const double2 *__r
     if (tt < 0) return;
     const int i = tile_site(g, tt >> 1), hb = tt & 1;
     double2 acc[6], tv[6], at[6];
-    hop_pair<RC, double2>(g, 0, i, hb, T, U, 1.0, acc);
+    hop_pair<LM, double2>(g, 0, i, hb, T, U, 1.0, acc);
     load_block(t, g.Vh, i, hb, -1.0, tv);
     if (CLOV) clover_block<double, double2>(cl, g.Vh, i, hb, tv, at);
     const long Vh = g.Vh;
@@ -53,13 +53,15 @@ int poly_factor(pfmp_ctx *ctx, int op, const double2 *src, double2 z, double2 *d
     if (rc) return rc;
     if ((rc = clovinv64(ctx, 1, te, s.clov[1], to, -1.0, 1.0, cl, nullptr))) return rc;
     dim3 grid(op_nparts(ctx->g)), block(kBlock);
-#define LAST(CL, RC)                                                                                          \
-    hipLaunchKernelGGL((k_poly_last<CL, RC>), grid, block, 0, ctx->stream, ctx->g, te, to, ctx->U, s.clov[0], mk2, \
+#define LAST(CL, LM)                                                                                          \
+    hipLaunchKernelGGL((k_poly_last<CL, LM>), grid, block, 0, ctx->stream, ctx->g, te, to, ctx->U, s.clov[0], mk2, \
                        src, z, dst)
-    if (cl && ctx->g.recon) LAST(1, 1);
-    else if (cl) LAST(1, 0);
-    else if (ctx->g.recon) LAST(0, 1);
-    else LAST(0, 0);
+#define LAST1(LM) LAST(1, LM)
+#define LAST0(LM) LAST(0, LM)
+    if (cl) { PFMP_LM_SWITCH(link_mode(ctx->g), LAST1) }
+    else { PFMP_LM_SWITCH(link_mode(ctx->g), LAST0) }
+#undef LAST1
+#undef LAST0
 #undef LAST
     LAUNCHCHK(ctx);
     return 0;

@@ -365,7 +365,7 @@ __device__ __forceinline__ double block_total_f(const double *__restrict__ part,
 
 // q = Khat p (from t = Mhat p, T' = A_oo^-1 D_oe g5 t), alpha = rz / <p, q> (the <p, q>
 // partials come from stage 2), x += alpha p, r -= alpha q; |r|^2 partials
-template <int CLOV, int RC>
+template <int CLOV, int LM>
 __global__ __launch_bounds__(kBlock) void k_f_hop4(Geom g, const double2 *__restrict__ t,
                                                    const double2 *__restrict__ T, const double2 *__restrict__ U,
                                                    const double *__restrict__ cl, double a,
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_f_hop4(Geom g, const double2 *__rest
     if (tt >= 0) {
         const int i = tile_site(g, tt >> 1), hb = tt & 1;
         double2 acc[6], tv[6], at[6];
-        hop_pair<RC, double2>(g, 0, i, hb, T, U, 1.0, acc);
+        hop_pair<LM, double2>(g, 0, i, hb, T, U, 1.0, acc);
         load_block(t, g.Vh, i, hb, -1.0, tv);
         if (CLOV) clover_block<double, double2>(cl, g.Vh, i, hb, tv, at);
 #pragma unroll
@@ -778,13 +778,15 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
             if ((rc = clovinv64(ctx, 1, p, s.clov[1], T, 1.0, 1.0, cl, fs + F_DONE))) return rc;
             if ((rc = xpay64(ctx, 0, p, T, s.clov[0], mk2, t, 1.0, cl, part_a, fs + F_DONE))) return rc;
             if ((rc = clovinv64(ctx, 1, t, s.clov[1], T, -1.0, 1.0, cl, fs + F_DONE))) return rc;
-#define FHOP4(CL, RC)                                                                                        \
-    hipLaunchKernelGGL((k_f_hop4<CL, RC>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, t, T, ctx->U, s.clov[0], mk2, \
+#define FHOP4(CL, LM)                                                                                        \
+    hipLaunchKernelGGL((k_f_hop4<CL, LM>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, t, T, ctx->U, s.clov[0], mk2, \
                        p, q, x, r, part_a, nb, fs, part_b)
-            if (cl && g.recon) FHOP4(1, 1);
-            else if (cl) FHOP4(1, 0);
-            else if (g.recon) FHOP4(0, 1);
-            else FHOP4(0, 0);
+#define FHOP4_1(LM) FHOP4(1, LM)
+#define FHOP4_0(LM) FHOP4(0, LM)
+            if (cl) { PFMP_LM_SWITCH(link_mode(g), FHOP4_1) }
+            else { PFMP_LM_SWITCH(link_mode(g), FHOP4_0) }
+#undef FHOP4_1
+#undef FHOP4_0
 #undef FHOP4
             hipLaunchKernelGGL(k_f_norm, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, fs);
             LAUNCHCHK(ctx);

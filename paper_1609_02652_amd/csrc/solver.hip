@@ -18,7 +18,8 @@
 namespace {
 
 // device scalar slots in ctx->scal
-enum { S_RR = 0, S_THR, S_PAP, S_ALPHA, S_BETA, S_ITER, S_DONE, S_MAXIT, S_BB, S_APREV, S_BPREV, S_CACT, S_NACT };
+enum { S_RR = 0, S_THR, S_PAP, S_ALPHA, S_BETA, S_ITER, S_DONE, S_MAXIT, S_BB, S_APREV, S_BPREV, S_CACT, S_NACT,
+       S_RRB };   // S_RRB, S_RRB + 1: |r|^2 of even / odd iterations (fused CG kernels)
 constexpr int kShiftBase = 64;   // per-shift records start here
 struct ShiftRec {                // 16 doubles
     double2 sigma, zp, z, zn, as, bs;
@@ -38,6 +39,7 @@ __global__ void k_cg_init(const double *__restrict__ partials, int nparts, doubl
         double bb = 0;
         for (int k = 0; k < kRedBlock / 64; k++) bb += sh[k];
         st[S_RR] = bb;
+        st[S_RRB] = bb;
         st[S_BB] = bb;
         st[S_THR] = tol2 * bb;
         st[S_ITER] = 0;
@@ -47,6 +49,22 @@ __global__ void k_cg_init(const double *__restrict__ partials, int nparts, doubl
         st[S_BPREV] = 0;
         st[S_CACT] = 0;
     }
+}
+
+// sum of n partials, the same in every block and thread (fixed order); NT threads
+template <int NT>
+__device__ __forceinline__ double block_total_n(const double *__restrict__ part, int n)
+{
+    __shared__ double sh[NT / 64];
+    double s = 0;
+    for (int k = threadIdx.x; k < n; k += NT) s += part[k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0;
+    for (int k = 0; k < NT / 64; k++) t += sh[k];
+    __syncthreads();
+    return t;
 }
 
 __device__ __forceinline__ double block_total(const double *__restrict__ partials, int nparts)
@@ -62,50 +80,38 @@ __device__ __forceinline__ double block_total(const double *__restrict__ partial
     return t;
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_cg_alpha(const double *__restrict__ partials, int nparts,
-                                                        double *__restrict__ st)
-{
-    if (st[S_DONE] != 0) return;
-    double pap = block_total(partials, nparts);
-    if (threadIdx.x == 0) {
-        st[S_PAP] = pap;
-        st[S_ALPHA] = st[S_RR] / pap;
-    }
-}
-
-__global__ __launch_bounds__(kRedBlock) void k_cg_beta(const double *__restrict__ partials, int nparts,
-                                                       double *__restrict__ st)
-{
-    if (st[S_DONE] != 0) return;
-    double rr = block_total(partials, nparts);
-    if (threadIdx.x == 0) {
-        st[S_BETA] = rr / st[S_RR];
-        st[S_RR] = rr;
-        st[S_ITER] += 1;
-        st[S_DONE] = rr <= st[S_THR] ? 1 : (st[S_ITER] >= st[S_MAXIT] ? 2 : 0);
-    }
-}
-
 // Khat p from t = Mhat p and T' = A_oo^-1 D_oe g5 t:  Kp = g5 (A_ee g5 t - kappa^2 D_eo T');
 // then x += alpha p, r -= alpha Kp, |r|^2 partials.
-template <int CLOV, int RC>
+// SELF = 1: alpha = |r|^2 / <p, Khat p> formed in every block from the stage-2 partials
+// (part_pap, npap) and the |r|^2 of iteration parity par; SELF = 0: alpha from st.
+template <int CLOV, int LM, int SELF>
 __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__restrict__ t,
                                                     const double2 *__restrict__ T, const double2 *__restrict__ U,
                                                     const double *__restrict__ cl, double a,
                                                     const double2 *__restrict__ p, double2 *__restrict__ x,
-                                                    double2 *__restrict__ r, const double *__restrict__ st,
-                                                    double *__restrict__ partials)
+                                                    double2 *__restrict__ r, double *__restrict__ st,
+                                                    double *__restrict__ partials,
+                                                    const double *__restrict__ part_pap, int npap, int par)
 {
     if (st[S_DONE] != 0) return;
+    double alpha_self = 0;
+    if (SELF) {
+        const double pap = block_total_n<kBlock>(part_pap, npap);
+        alpha_self = st[S_RRB + par] / pap;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st[S_PAP] = pap;
+            st[S_ALPHA] = alpha_self;
+        }
+    }
     const int tt = xcd_site(2 * g.Vh);
     double nrm = 0;
     if (tt >= 0) {
         const int i = tile_site(g, tt >> 1), hb = tt & 1;
         double2 acc[6], tv[6], at[6];
-        hop_pair<RC, double2>(g, 0, i, hb, T, U, 1.0, acc);
+        hop_pair<LM, double2>(g, 0, i, hb, T, U, 1.0, acc);
         load_block(t, g.Vh, i, hb, -1.0, tv);
         if (CLOV) clover_block<double, double2>(cl, g.Vh, i, hb, tv, at);
-        const double alpha = st[S_ALPHA];
+        const double alpha = SELF ? alpha_self : st[S_ALPHA];
         const long Vh = g.Vh;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
@@ -124,29 +130,54 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
     block_sum_store<double2>(nrm, partials);
 }
 
+// stage 4; part_pap != nullptr: alpha formed in the kernel (fused CG), else from st
 void launch_cg_hop4(pfmp_ctx *ctx, bool cl, int nb, const double2 *t, const double2 *T, const double *clov,
-                    double mk2, const double2 *p, double2 *x, double2 *r, double *part)
+                    double mk2, const double2 *p, double2 *x, double2 *r, double *part, const double *part_pap,
+                    int par)
 {
-#define HOP4(CL, RC)                                                                                             \
-    hipLaunchKernelGGL((k_cg_hop4<CL, RC>), dim3(nb), dim3(kBlock), 0, ctx->stream, ctx->g, t, T, ctx->U, clov, mk2, \
-                       p, x, r, ctx->scal, part)
-    if (cl && ctx->g.recon) HOP4(1, 1);
-    else if (cl) HOP4(1, 0);
-    else if (ctx->g.recon) HOP4(0, 1);
-    else HOP4(0, 0);
+#define HOP4(CL, LM, SF)                                                                                            \
+    hipLaunchKernelGGL((k_cg_hop4<CL, LM, SF>), dim3(nb), dim3(kBlock), 0, ctx->stream, ctx->g, t, T, ctx->U, clov, \
+                       mk2, p, x, r, ctx->scal, part, part_pap, nb, par)
+#define HOP4_11(LM) HOP4(1, LM, 1)
+#define HOP4_10(LM) HOP4(1, LM, 0)
+#define HOP4_01(LM) HOP4(0, LM, 1)
+#define HOP4_00(LM) HOP4(0, LM, 0)
+    const int lm = link_mode(ctx->g);
+    if (cl && part_pap) { PFMP_LM_SWITCH(lm, HOP4_11) }
+    else if (cl) { PFMP_LM_SWITCH(lm, HOP4_10) }
+    else if (part_pap) { PFMP_LM_SWITCH(lm, HOP4_01) }
+    else { PFMP_LM_SWITCH(lm, HOP4_00) }
+#undef HOP4_11
+#undef HOP4_10
+#undef HOP4_01
+#undef HOP4_00
 #undef HOP4
 }
 
-__global__ void k_cg_update_p(long n, const double2 *__restrict__ r, double2 *__restrict__ p,
-                              const double *__restrict__ st)
+// beta = |r+|^2 / |r|^2 formed in every block from the stage-4 partials, p = r + beta p;
+// block 0 records |r+|^2 for the next parity and the convergence state
+__global__ __launch_bounds__(kRedBlock) void k_cg_update_p_fused(long n, const double2 *__restrict__ r,
+                                                                 double2 *__restrict__ p, double *__restrict__ st,
+                                                                 const double *__restrict__ part_rr, int nrr,
+                                                                 int par)
 {
     if (st[S_DONE] != 0) return;
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    double b = st[S_BETA];
-    double2 rv = r[t], pv = p[t];
-    p[t] = make_double2(rv.x + b * pv.x, rv.y + b * pv.y);
+    const double rr = block_total_n<kRedBlock>(part_rr, nrr);
+    const double b = rr / st[S_RRB + par];
+    const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (e < n) {
+        double2 rv = r[e], pv = p[e];
+        p[e] = make_double2(rv.x + b * pv.x, rv.y + b * pv.y);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st[S_BETA] = b;
+        st[S_RR] = rr;
+        st[S_RRB + (par ^ 1)] = rr;
+        st[S_ITER] += 1;
+        st[S_DONE] = rr <= st[S_THR] ? 1 : (st[S_ITER] >= st[S_MAXIT] ? 2 : 0);
+    }
 }
+
 
 __global__ void k_residual(long n, const double2 *__restrict__ b, const double2 *__restrict__ Ax, double2 zr,
                            const double2 *__restrict__ x, double2 *__restrict__ r)
@@ -325,6 +356,17 @@ static int true_residual(pfmp_ctx *ctx, int op, const double2 *b, const double2 
     return 0;
 }
 
+// Iterations to issue before the next look at the device state: the remaining count
+// predicted from the residual's decay over the last chunk, plus one (4 .. 200).
+static int next_chunk(double rr, double thr, double it, double rr_prev, double it_prev)
+{
+    if (!(rr_prev > 0) || !(rr > 0) || it <= it_prev || rr >= rr_prev) return 25;
+    const double rate = std::log(rr / rr_prev) / (it - it_prev);   // log decay per iteration
+    const double left = std::log(thr / rr) / rate;
+    const int c = (int)std::ceil(left) + 1;
+    return c < 4 ? 4 : (c > 200 ? 200 : c);
+}
+
 static int read_state(pfmp_ctx *ctx, double *h, int n)
 {
     HIPCHK(ctx, hipMemcpyAsync(ctx->red_host, ctx->scal, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
@@ -360,7 +402,8 @@ extern "C" int pfmp_cg_solve(pfmp_ctx *ctx, int op, const void *b_, void *x_, co
     const bool cl = s.csw != 0;
     const double mk2 = -s.kappa * s.kappa;
     int chunk = prm->check_every > 0 ? prm->check_every : 25;
-    double h[16];
+    int par = 0;   // iteration parity: which |r|^2 slot holds the current value
+    double h[16], rr_prev = 0, it_prev = 0;
     for (;;) {
         for (int k = 0; k < chunk; k++) {
             // t = Mhat p, with <p, Khat p> = |t|^2 partials
@@ -369,18 +412,21 @@ extern "C" int pfmp_cg_solve(pfmp_ctx *ctx, int op, const void *b_, void *x_, co
             if ((rc = xpay64(ctx, 0, B.p, B.T, s.clov[0], mk2, B.t, 1.0, cl, B.part_a,
                                                     ctx->scal + S_DONE)))
                 return rc;
-            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_a, nb, ctx->scal);
             // T' = A_oo^-1 D_oe g5 t
             if ((rc = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE)))
                 return rc;
-            launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, x, B.r, B.part_b);
-            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_b, nb, ctx->scal);
-            hipLaunchKernelGGL(k_cg_update_p, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, B.r, B.p,
-                               ctx->scal);
+            // alpha, x and r updates; then beta and p, each formed where it is used
+            launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, x, B.r, B.part_b, B.part_a, par);
+            hipLaunchKernelGGL(k_cg_update_p_fused, dim3(nblocks(n, kRedBlock)), dim3(kRedBlock), 0, ctx->stream, n,
+                               B.r, B.p, ctx->scal, B.part_b, nb, par);
             LAUNCHCHK(ctx);
+            par ^= 1;
         }
         if ((rc = read_state(ctx, h, 16))) return rc;
         if (h[S_DONE] != 0) break;
+        if (prm->check_every <= 0) chunk = next_chunk(h[S_RR], h[S_THR], h[S_ITER], rr_prev, it_prev);
+        rr_prev = h[S_RR];
+        it_prev = h[S_ITER];
     }
     int iters = (int)h[S_ITER];
     double res = 0;
@@ -456,7 +502,7 @@ extern "C" int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const doubl
             if ((rc = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE)))
                 return rc;
             // r -= alpha Khat p (the base x is not needed; it goes to scratch)
-            launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, B.Kx, B.r, B.part_b);
+            launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, B.Kx, B.r, B.part_b, nullptr, 0);
             hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_b, nb, nshift, ctx->scal,
                                rec);
             hipLaunchKernelGGL(k_ms_update, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, nshift, B.r, B.p,

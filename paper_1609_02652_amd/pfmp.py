@@ -53,6 +53,10 @@ TERM_POLY, TERM_POLYCORR, TERM_RATIO, TERM_HEAVY = 0, 1, 2, 3
 TERM_KINDS = {"poly": TERM_POLY, "polycorr": TERM_POLYCORR, "ratio": TERM_RATIO, "heavy": TERM_HEAVY}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("zt", ctypes.c_int), ("stream", ctypes.c_int), ("us_Mhat", ctypes.c_double)]
+
+
 class Term(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("op", ctypes.c_int), ("op2", ctypes.c_int), ("n", ctypes.c_int),
                 ("mu", ctypes.c_double), ("nu", ctypes.c_double), ("steps", ctypes.c_int)]
@@ -162,6 +166,8 @@ def load():
         "pfmp_trajectory": [vp, vp, vp, vp, d, vp, vp],
         "pfmp_set_link_reconstruct": [vp, i],
         "pfmp_set_site_order": [vp, i],
+        "pfmp_set_link_streaming": [vp, i],
+        "pfmp_autotune": [vp, i, vp],
         "pfmp_get_link_reconstruct": [vp, vp],
         "pfmp_apply_MdagM_batch": [vp, i, vp, vp, vp],
         "pfmp_cg_solve_batch": [vp, i, vp, vp, vp, vp, vp],
@@ -268,6 +274,15 @@ class Lattice:
     def site_order(self, zt):
         """Visit order of the operator kernels: 0 memory order, zt > 0 groups of zt z-planes."""
         self._chk(self.lib.pfmp_set_site_order(self.h, int(zt)), "set_site_order")
+
+    def link_streaming(self, on):
+        self._chk(self.lib.pfmp_set_link_streaming(self.h, int(bool(on))), "set_link_streaming")
+
+    def autotune(self, op):
+        """Pick the fastest site visit order and link load mode for Mhat of slot op."""
+        t = Tuning()
+        self._chk(self.lib.pfmp_autotune(self.h, int(op), ctypes.byref(t)), "autotune")
+        return {"zt": t.zt, "stream": t.stream, "us_Mhat": t.us_Mhat}
 
     def get_gauge(self):
         out = self.torch.empty((self.V, 4, 3, 3), dtype=self.torch.complex128, device=self.device)

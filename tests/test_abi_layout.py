@@ -14,6 +14,7 @@ STRUCTS = {
     "pfmp_term": "Term",
     "pfmp_hmc_spec": "HmcSpec",
     "pfmp_traj_stats": "TrajStats",
+    "pfmp_tuning": "Tuning",
 }
 # Python field names that differ from the header's (``lambda`` is a Python keyword)
 RENAMED = {"lam": "lambda"}

@@ -228,3 +228,26 @@ def test_non_su3_links_read_in_full(setup):
     want = oracle.Operator(dims, U, 0.1150, 0.0).M(psi)
     assert rel(lat.spinor_numpy(lat.apply_M(1, lat.pack_spinor(psi))), want) < 1e-12
     lat.close()
+
+
+@pytest.mark.parametrize("zt,stream", [(0, 1), (2, 0), (2, 1), (4, 1)])
+def test_visit_order_and_link_streaming(setup, zt, stream):
+    """Cache-blocking choices change neither the operator (to the last bits of the
+    sums) nor the solver's iterations; the autotuner picks one of them."""
+    dims, U, lat, ops = setup
+    if dims[2] % zt if zt else False:
+        pytest.skip("zt does not divide the z extent")
+    psi = synth.gaussian_spinor(lat.Vh, 23)
+    f = lat.pack_spinor(psi)
+    lat.site_order(zt)
+    lat.link_streaming(stream)
+    got = lat.spinor_numpy(lat.apply_MdagM(0, f))
+    x, st = lat.cg_solve(0, f, tol=1e-11)
+    lat.site_order(0)
+    lat.link_streaming(0)
+    assert rel(got, ops[0].K(psi)) < 1e-12
+    assert rel(ops[0].K(lat.spinor_numpy(x)), psi) < 1.1e-11
+    tune = lat.autotune(0)
+    print("autotune", dims, tune)
+    assert tune["zt"] == 0 or dims[2] % tune["zt"] == 0
+    assert rel(lat.spinor_numpy(lat.apply_MdagM(0, f)), ops[0].K(psi)) < 1e-12
