@@ -126,6 +126,11 @@ typedef struct {
  * order (0 and each divisor of the z extent from 2 to 16) with cached and with streaming
  * link loads and keeps the fastest for all later launches.  Synchronises. */
 int pfmp_autotune(pfmp_ctx *ctx, int op, pfmp_tuning *out);
+/* Solver iterations replayed as HIP graphs (on = 1, the default): the launches of one
+ * iteration are captured once per set of buffers and operator and replayed, which takes
+ * the per-launch host overhead out of the iteration.  on = 0 launches them one by one;
+ * the results are the same bit for bit. */
+int pfmp_set_graphs(pfmp_ctx *ctx, int on);
 int pfmp_get_link_reconstruct(pfmp_ctx *ctx, int *active);
 /* Configure slot op with (kappa, c_sw): builds A_ee, A_oo^-1 (per-site Cholesky
  * of the two 6x6 chiral blocks) and ln det A_oo.  Needs a gauge field.  Errors:

@@ -40,6 +40,52 @@ void *ws_alloc(pfmp_ctx *ctx, size_t bytes, int slot)
     return w->buf[slot];
 }
 
+int graph_run(pfmp_ctx *ctx, const std::vector<uint64_t> &key, int reps, const std::function<int()> &issue)
+{
+    if (!ctx->use_graphs) {
+        for (int r = 0; r < reps; r++)
+            if (int rc = issue()) return rc;
+        return 0;
+    }
+    hipGraphExec_t exec = nullptr;
+    for (size_t k = 0; k < ctx->graphs.size(); k++)
+        if (ctx->graphs[k].key == key) {
+            exec = ctx->graphs[k].exec;
+            break;
+        }
+    if (!exec) {
+        if (!ctx->cap) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+        hipStream_t orig = ctx->stream;
+        HIPCHK(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+        ctx->stream = ctx->cap;
+        int rc = issue();
+        ctx->stream = orig;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+        if (rc || e != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return rc ? rc : set_err(ctx, PFMP_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return set_err(ctx, PFMP_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        if (ctx->graphs.size() >= 32) {
+            hipGraphExecDestroy(ctx->graphs.front().exec);
+            ctx->graphs.erase(ctx->graphs.begin());
+        }
+        ctx->graphs.push_back({key, exec});
+    }
+    for (int r = 0; r < reps; r++) HIPCHK(ctx, hipGraphLaunch(exec, ctx->stream));
+    return 0;
+}
+
+extern "C" int pfmp_set_graphs(pfmp_ctx *ctx, int on)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    ctx->use_graphs = on != 0;
+    return 0;
+}
+
 // Buffer idx of the context's pool of FP64 spinors; only the indices asked for
 // are allocated (on first use).
 double2 *pool_get(pfmp_ctx *ctx, int idx)
@@ -181,6 +227,8 @@ extern "C" int pfmp_destroy(pfmp_ctx *ctx)
     hipFree(ctx->U);
     hipFree(ctx->Uf);
     hipFree(ctx->Fhat);
+    for (auto &gr : ctx->graphs) hipGraphExecDestroy(gr.exec);
+    if (ctx->cap) hipStreamDestroy(ctx->cap);
     hipFree(ctx->red);
     hipFree(ctx->scal);
     if (ctx->red_host) hipHostFree(ctx->red_host);

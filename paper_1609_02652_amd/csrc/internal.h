@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -171,6 +173,13 @@ struct pfmp_ctx {
     double *scal = nullptr;      // device scalars for solvers
     SolverWS *ws = nullptr;
     std::vector<double2 *> pool;   // FP64 spinor buffers for the HMC driver, grown on demand
+    bool use_graphs = true;        // solver iterations replayed as HIP graphs
+    hipStream_t cap = nullptr;     // private stream the graphs are captured on
+    struct Graph {
+        std::vector<uint64_t> key;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;     // captured iterations, most recent last
     std::string err;
 };
 
@@ -228,6 +237,26 @@ int clover_build(pfmp_ctx *ctx, int op);
 int op_ready(pfmp_ctx *ctx, int op);
 // FP32 copy of the links current (context.hip)
 int gauge_f32_ready(pfmp_ctx *ctx);
+// Launch `issue` (a fixed sequence of kernel launches on ctx->stream) reps times.  With
+// graphs on, the sequence is captured once as a HIP graph under `key` (every pointer and
+// value its launches use) and replayed; otherwise it is issued reps times.
+int graph_run(pfmp_ctx *ctx, const std::vector<uint64_t> &key, int reps, const std::function<int()> &issue);
+template <typename T>
+inline void key_add(std::vector<uint64_t> &k, const T &v)
+{
+    static_assert(sizeof(T) <= 8, "key entries are at most 8 bytes");
+    uint64_t u = 0;
+    std::memcpy(&u, &v, sizeof(T));
+    k.push_back(u);
+}
+inline void key_geom(std::vector<uint64_t> &k, const Geom &g)
+{
+    for (int m = 0; m < 4; m++) key_add(k, g.L[m]);
+    key_add(k, g.tbc);
+    key_add(k, g.recon);
+    key_add(k, g.zt);
+    key_add(k, g.stream);
+}
 int clover_logdet(pfmp_ctx *ctx, int op);
 // reductions (blas.hip)
 int red_finish(pfmp_ctx *ctx, const double *partials, int nparts, int nvals, double *host_out);

@@ -243,31 +243,43 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
     int chunk = prm->check_every > 0 ? prm->check_every : 16;
     int updates = 0, kmults = 0, last_iter = 0;
     double h[16], res = 0;
-    for (;;) {
-        for (int k = 0; k < chunk; k++) {
-            if ((rc = launch_clovinv<float2, float, In, S>(ctx, 1, ps, ctx->Uf, s.clovf[1], Ts, 1.f, 1.f, cl,
-                                                            sc + M_DONE)))
-                return rc;
-            if ((rc = launch_xpay<float2, float, In, In, S>(ctx, 0, ps, Ts, ctx->Uf, s.clovf[0], mk2, ts, 1.f, cl,
-                                                             part_a, sc + M_DONE)))
-                return rc;
-            if ((rc = launch_clovinv<float2, float, In, S>(ctx, 1, ts, ctx->Uf, s.clovf[1], Ts, -1.f, 1.f, cl,
-                                                            sc + M_DONE)))
-                return rc;
+    // one inner iteration: 5 launches with fixed arguments, replayed as a graph
+    auto iteration = [&]() -> int {
+        int e;
+        if ((e = launch_clovinv<float2, float, In, S>(ctx, 1, ps, ctx->Uf, s.clovf[1], Ts, 1.f, 1.f, cl, sc + M_DONE)))
+            return e;
+        if ((e = launch_xpay<float2, float, In, In, S>(ctx, 0, ps, Ts, ctx->Uf, s.clovf[0], mk2, ts, 1.f, cl, part_a,
+                                                        sc + M_DONE)))
+            return e;
+        if ((e = launch_clovinv<float2, float, In, S>(ctx, 1, ts, ctx->Uf, s.clovf[1], Ts, -1.f, 1.f, cl,
+                                                       sc + M_DONE)))
+            return e;
 #define MHOP4(CL, LM)                                                                                       \
     hipLaunchKernelGGL((k_m_hop4<CL, LM, In>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,     \
                        s.clovf[0], mk2, ps, xs, rs, sc, part_b, part_a, nb)
 #define MHOP4_1(LM) MHOP4(1, LM)
 #define MHOP4_0(LM) MHOP4(0, LM)
-            if (cl) { PFMP_LM_SWITCH(link_mode(g), MHOP4_1) }
-            else { PFMP_LM_SWITCH(link_mode(g), MHOP4_0) }
+        if (cl) { PFMP_LM_SWITCH(link_mode(g), MHOP4_1) }
+        else { PFMP_LM_SWITCH(link_mode(g), MHOP4_0) }
 #undef MHOP4_1
 #undef MHOP4_0
 #undef MHOP4
-            hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
-                               sc, part_b, nb);
-            LAUNCHCHK(ctx);
-        }
+        hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
+                           sc, part_b, nb);
+        LAUNCHCHK(ctx);
+        return 0;
+    };
+    std::vector<uint64_t> key;
+    key_add(key, 2 + (int)sizeof(S));   // mixed-precision iteration, storage type
+    key_geom(key, g);
+    for (const void *ptr : {(const void *)pb, (const void *)tb, (const void *)Tb, (const void *)xs, (const void *)rs, (const void *)part_a,
+                            (const void *)part_b, (const void *)sc, (const void *)ctx->Uf, (const void *)s.clovf[0],
+                            (const void *)s.clovf[1]})
+        key_add(key, ptr);
+    key_add(key, mk2);
+    key_add(key, (int)cl);
+    for (;;) {
+        if ((rc = graph_run(ctx, key, chunk, iteration))) return rc;
         HIPCHK(ctx, hipMemcpyAsync(ctx->red_host, sc, sizeof(double) * 16, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
         for (int k = 0; k < 16; k++) h[k] = ctx->red_host[k];

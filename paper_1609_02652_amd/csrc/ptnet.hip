@@ -32,27 +32,30 @@ __device__ __forceinline__ float2 fconj(float2 a) { return make_float2(a.x, -a.y
 constexpr int kFcgBase = 7600;
 enum { F_RZ = 0, F_PQ, F_ALPHA, F_RN2, F_THR, F_ITER, F_DONE, F_MAXIT, F_INVR, F_NR, F_BETA, F_FB, F_NFB, F_NSLOT };
 
-// T_d(y) v (dag = 0) or T_d(y)^dag v (dag = 1) for the site y with coordinates c
-template <int DAG>
-__device__ __forceinline__ void transport(const Geom &g, const float2 *__restrict__ U, int p, int i, const int *c,
-                                          int d, const float2 *v, float2 *w)
+// The transporter T_d(y) of the site y with coordinates c, loaded once per direction:
+// U_mu(y) for d = 2 mu, U_mu(y - mu)^dag for d = 2 mu + 1, and its fermion boundary factor.
+__device__ __forceinline__ void load_T(const Geom &g, const float2 *__restrict__ U, int p, int i, const int *c, int d,
+                                       float2 *u, float *sgn)
 {
     const int mu = d >> 1;
-    float2 u[9];
-    float sgn;
     if ((d & 1) == 0) {
         const float2 *b = U + ((long)(p * 4 + mu) * 9) * g.Vh + i;
         for (int k = 0; k < 9; k++) u[k] = b[(long)k * g.Vh];
-        sgn = (mu == 3 && c[3] == g.L[3] - 1) ? (float)g.tbc : 1.f;
+        *sgn = (mu == 3 && c[3] == g.L[3] - 1) ? (float)g.tbc : 1.f;
     } else {
         int s;
         int j = eo_neighbour(g, c, mu, -1, &s);
         const float2 *b = U + ((long)((1 - p) * 4 + mu) * 9) * g.Vh + j;
-        // T = U_mu(y - mu)^dag: u holds its conjugate transpose
         for (int a = 0; a < 3; a++)
             for (int bb = 0; bb < 3; bb++) u[3 * a + bb] = fconj(b[(long)(3 * bb + a) * g.Vh]);
-        sgn = (float)s;
+        *sgn = (float)s;
     }
+}
+
+// w = sgn T v (DAG = 0) or sgn T^dag v (DAG = 1)
+template <int DAG>
+__device__ __forceinline__ void apply_T(const float2 *u, float sgn, const float2 *v, float2 *w)
+{
     for (int a = 0; a < 3; a++) {
         float2 acc = make_float2(0.f, 0.f);
         for (int bb = 0; bb < 3; bb++) {
@@ -89,14 +92,16 @@ __global__ __launch_bounds__(kBlock) void k_pt_l1(Geom g, const float2 *__restri
     for (int k = 0; k < NH * 3; k++) h[k] = make_float2(0.f, 0.f);
     for (int d = 0; d < 8; d++) {
         int j = nbr_of(g, c, d);
-        float2 t[NIN * 3];
+        float2 u[9], t[NIN * 3];
+        float sgn;
+        load_T(g, U, 1, i, c, d, u, &sgn);
         for (int ch = 0; ch < NIN; ch++) {
             float2 v[3];
             for (int a = 0; a < 3; a++) {
                 double2 x = r[(long)(3 * ch + a) * g.Vh + j];
                 v[a] = make_float2((float)x.x * scale, (float)x.y * scale);
             }
-            transport<0>(g, U, 1, i, c, d, v, t + 3 * ch);
+            apply_T<0>(u, sgn, v, t + 3 * ch);
         }
         const float2 *w = W + d * NH * NIN;
         for (int o = 0; o < NH; o++)
@@ -143,17 +148,28 @@ __global__ __launch_bounds__(kBlock) void k_pt_l2(Geom g, const float2 *__restri
             }
             z[3 * o + a] = acc;
         }
+    // sum_ch W2[d][o][ch] T_d g_ch = T_d (sum_ch W2[d][o][ch] g_ch): mix the 12 channels
+    // of the neighbour into 4, then transport 4 colour vectors per direction
     for (int d = 0; d < 8; d++) {
         int j = nbr_of(g, c, d);
         const float2 *w = W2 + d * NIN * NH;
+        float2 m[NIN * 3];
+        for (int k = 0; k < NIN * 3; k++) m[k] = make_float2(0.f, 0.f);
         for (int ch = 0; ch < NH; ch++) {
-            float2 v[3], t[3];
+            float2 v[3];
             for (int a = 0; a < 3; a++) v[a] = G[(long)(3 * ch + a) * g.Vh + j];
-            transport<0>(g, U, 0, i, c, d, v, t);
             for (int o = 0; o < NIN; o++) {
                 float2 wc = w[o * NH + ch];
-                for (int a = 0; a < 3; a++) cfma(z[3 * o + a], wc, t[a]);
+                for (int a = 0; a < 3; a++) cfma(m[3 * o + a], wc, v[a]);
             }
+        }
+        float2 u[9];
+        float sgn;
+        load_T(g, U, 0, i, c, d, u, &sgn);
+        for (int o = 0; o < NIN; o++) {
+            float2 t[3];
+            apply_T<0>(u, sgn, m + 3 * o, t);
+            for (int a = 0; a < 3; a++) z[3 * o + a] = cadd(z[3 * o + a], t[a]);
         }
     }
     for (int k = 0; k < NIN * 3; k++) {
@@ -230,18 +246,25 @@ __global__ __launch_bounds__(kBlock) void k_pt_grad2(Geom g, const float2 *__res
         for (int k = 0; k < 12; k++) gz[k] = make_float2(0.f, 0.f);
     }
     const long stride = 2L * (NW2 + NW0);
+    // <Gz_o, T g_ch(x+d)> = <T^dag Gz_o, g_ch(x+d)>: 4 transports per direction, not 12
     for (int d = 0; d < 8; d++) {
         int j = ok ? nbr_of(g, c, d) : 0;
+        float2 tg[NIN * 3];
+        if (ok) {
+            float2 u[9];
+            float sgn;
+            load_T(g, U, 0, i, c, d, u, &sgn);
+            for (int o = 0; o < NIN; o++) apply_T<1>(u, sgn, gz + 3 * o, tg + 3 * o);
+        } else {
+            for (int k = 0; k < NIN * 3; k++) tg[k] = make_float2(0.f, 0.f);
+        }
         for (int ch = 0; ch < NH; ch++) {
-            float2 t[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-            if (ok) {
-                float2 v[3];
+            float2 v[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+            if (ok)
                 for (int a = 0; a < 3; a++) v[a] = G[(long)(3 * ch + a) * g.Vh + j];
-                transport<0>(g, U, 0, i, c, d, v, t);
-            }
             for (int o = 0; o < NIN; o++) {
                 float2 acc = make_float2(0.f, 0.f);
-                for (int a = 0; a < 3; a++) cfmac(acc, gz[3 * o + a], t[a]);
+                for (int a = 0; a < 3; a++) cfmac(acc, tg[3 * o + a], v[a]);
                 wave_partial(acc, part, stride, (d * NIN + o) * NH + ch);
             }
         }
@@ -275,10 +298,13 @@ __global__ __launch_bounds__(kBlock) void k_pt_back(Geom g, const float2 *__rest
         int j = nbr_of(g, c, d);
         const int od = d ^ 1;
         const float2 *w = W2 + od * NIN * NH;
+        float2 u[9];
+        float sgn;
+        load_T(g, U, 1, i, c, d, u, &sgn);
         for (int o = 0; o < NIN; o++) {
             float2 v[3], t[3];
             for (int a = 0; a < 3; a++) v[a] = Gz[(long)(3 * o + a) * g.Vh + j];
-            transport<0>(g, U, 1, i, c, d, v, t);
+            apply_T<0>(u, sgn, v, t);
             for (int ch = 0; ch < NH; ch++) {
                 float2 wc = fconj(w[o * NH + ch]);
                 for (int a = 0; a < 3; a++) cfma(gg[3 * ch + a], wc, t[a]);
@@ -312,14 +338,16 @@ __global__ __launch_bounds__(kBlock) void k_pt_grad1(Geom g, const float2 *__res
     const long stride = 2L * NW1;
     for (int d = 0; d < 8; d++) {
         int j = ok ? nbr_of(g, c, d) : 0;
-        float2 t[NIN * 3];
+        float2 t[NIN * 3], u[9];
+        float sgn = 0.f;
+        if (ok) load_T(g, U, 1, i, c, d, u, &sgn);
         for (int ch = 0; ch < NIN; ch++) {
             float2 v[3];
             for (int a = 0; a < 3; a++) {
                 double2 x = ok ? r[(long)(3 * ch + a) * g.Vh + j] : make_double2(0, 0);
                 v[a] = make_float2((float)x.x * scale, (float)x.y * scale);
             }
-            if (ok) transport<0>(g, U, 1, i, c, d, v, t + 3 * ch);
+            if (ok) apply_T<0>(u, sgn, v, t + 3 * ch);
             else for (int a = 0; a < 3; a++) t[3 * ch + a] = make_float2(0.f, 0.f);
         }
         for (int o = 0; o < NH; o++) {
@@ -772,34 +800,45 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
     LAUNCHCHK(ctx);
     const int chunk = prm->check_every > 0 ? prm->check_every : 10;
     double h[F_NSLOT];
-    for (;;) {
-        for (int k = 0; k < chunk; k++) {
-            // <p, Khat p> = |Mhat p|^2 partials, then q = Khat p fused with the x, r updates
-            if ((rc = clovinv64(ctx, 1, p, s.clov[1], T, 1.0, 1.0, cl, fs + F_DONE))) return rc;
-            if ((rc = xpay64(ctx, 0, p, T, s.clov[0], mk2, t, 1.0, cl, part_a, fs + F_DONE))) return rc;
-            if ((rc = clovinv64(ctx, 1, t, s.clov[1], T, -1.0, 1.0, cl, fs + F_DONE))) return rc;
+    // one iteration: fixed launches, replayed as a graph
+    auto iteration = [&]() -> int {
+        int e;
+        // <p, Khat p> = |Mhat p|^2 partials, then q = Khat p fused with the x, r updates
+        if ((e = clovinv64(ctx, 1, p, s.clov[1], T, 1.0, 1.0, cl, fs + F_DONE))) return e;
+        if ((e = xpay64(ctx, 0, p, T, s.clov[0], mk2, t, 1.0, cl, part_a, fs + F_DONE))) return e;
+        if ((e = clovinv64(ctx, 1, t, s.clov[1], T, -1.0, 1.0, cl, fs + F_DONE))) return e;
 #define FHOP4(CL, LM)                                                                                        \
     hipLaunchKernelGGL((k_f_hop4<CL, LM>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, t, T, ctx->U, s.clov[0], mk2, \
                        p, q, x, r, part_a, nb, fs, part_b)
 #define FHOP4_1(LM) FHOP4(1, LM)
 #define FHOP4_0(LM) FHOP4(0, LM)
-            if (cl) { PFMP_LM_SWITCH(link_mode(g), FHOP4_1) }
-            else { PFMP_LM_SWITCH(link_mode(g), FHOP4_0) }
+        if (cl) { PFMP_LM_SWITCH(link_mode(g), FHOP4_1) }
+        else { PFMP_LM_SWITCH(link_mode(g), FHOP4_0) }
 #undef FHOP4_1
 #undef FHOP4_0
 #undef FHOP4
-            hipLaunchKernelGGL(k_f_norm, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, fs);
-            LAUNCHCHK(ctx);
-            if (W) {
-                if ((rc = precondition())) return rc;
-            } else {
-                // identity: z = r is read directly
-            }
-            hipLaunchKernelGGL(k_f_dots, dim3(ndot), dim3(kBlock), 0, ctx->stream, n, W ? z : r, r, q, fs, part_b);
-            hipLaunchKernelGGL(k_f_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, ndot, 0, fs);
-            hipLaunchKernelGGL(k_f_update_p, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, W ? z : r, r, p, fs);
-            LAUNCHCHK(ctx);
-        }
+        hipLaunchKernelGGL(k_f_norm, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, fs);
+        LAUNCHCHK(ctx);
+        // z = N(r); with the identity, z = r is read directly
+        if (W && (e = precondition())) return e;
+        hipLaunchKernelGGL(k_f_dots, dim3(ndot), dim3(kBlock), 0, ctx->stream, n, W ? z : r, r, q, fs, part_b);
+        hipLaunchKernelGGL(k_f_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, ndot, 0, fs);
+        hipLaunchKernelGGL(k_f_update_p, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, W ? z : r, r, p, fs);
+        LAUNCHCHK(ctx);
+        return 0;
+    };
+    std::vector<uint64_t> key;
+    key_add(key, 4);   // flexible-CG iteration
+    key_geom(key, g);
+    for (const void *ptr : {(const void *)p, (const void *)T, (const void *)t, (const void *)q, (const void *)x,
+                            (const void *)r, (const void *)z, (const void *)part_a, (const void *)part_b,
+                            (const void *)fs, (const void *)ctx->U, (const void *)ctx->Uf, (const void *)s.clov[0],
+                            (const void *)s.clov[1], (const void *)(W ? w.W : nullptr), (const void *)w.G})
+        key_add(key, ptr);
+    key_add(key, mk2);
+    key_add(key, (int)cl);
+    for (;;) {
+        if ((rc = graph_run(ctx, key, chunk, iteration))) return rc;
         HIPCHK(ctx, hipMemcpyAsync(ctx->red_host, fs, sizeof(double) * F_NSLOT, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
         for (int k = 0; k < F_NSLOT; k++) h[k] = ctx->red_host[k];

@@ -6,9 +6,9 @@
 // turns the remaining launches of a chunk into early exits.  The host only looks
 // at the flag once per chunk of iterations.
 //
-// CG iteration (5 + 2 launches): hop1, hop2 (|Mhat p|^2 = <p, Khat p> partials),
-// alpha, hop3, hop4 fused with x += alpha p, r -= alpha Khat p and |r|^2 partials,
-// beta (convergence test), p = r + beta p.
+// CG iteration (5 launches): hop1, hop2 (|Mhat p|^2 = <p, Khat p> partials), hop3,
+// hop4 fused with alpha, x += alpha p, r -= alpha Khat p and |r|^2 partials, and
+// p = r + beta p fused with beta and the convergence test.
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -19,7 +19,7 @@ namespace {
 
 // device scalar slots in ctx->scal
 enum { S_RR = 0, S_THR, S_PAP, S_ALPHA, S_BETA, S_ITER, S_DONE, S_MAXIT, S_BB, S_APREV, S_BPREV, S_CACT, S_NACT,
-       S_RRB };   // S_RRB, S_RRB + 1: |r|^2 of even / odd iterations (fused CG kernels)
+       S_RROLD };   // |r|^2 at the start of the iteration (fused CG kernels)
 constexpr int kShiftBase = 64;   // per-shift records start here
 struct ShiftRec {                // 16 doubles
     double2 sigma, zp, z, zn, as, bs;
@@ -39,7 +39,6 @@ __global__ void k_cg_init(const double *__restrict__ partials, int nparts, doubl
         double bb = 0;
         for (int k = 0; k < kRedBlock / 64; k++) bb += sh[k];
         st[S_RR] = bb;
-        st[S_RRB] = bb;
         st[S_BB] = bb;
         st[S_THR] = tol2 * bb;
         st[S_ITER] = 0;
@@ -83,7 +82,7 @@ __device__ __forceinline__ double block_total(const double *__restrict__ partial
 // Khat p from t = Mhat p and T' = A_oo^-1 D_oe g5 t:  Kp = g5 (A_ee g5 t - kappa^2 D_eo T');
 // then x += alpha p, r -= alpha Kp, |r|^2 partials.
 // SELF = 1: alpha = |r|^2 / <p, Khat p> formed in every block from the stage-2 partials
-// (part_pap, npap) and the |r|^2 of iteration parity par; SELF = 0: alpha from st.
+// (part_pap, npap); block 0 keeps |r|^2 in S_RROLD for beta.  SELF = 0: alpha from st.
 template <int CLOV, int LM, int SELF>
 __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__restrict__ t,
                                                     const double2 *__restrict__ T, const double2 *__restrict__ U,
@@ -91,16 +90,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
                                                     const double2 *__restrict__ p, double2 *__restrict__ x,
                                                     double2 *__restrict__ r, double *__restrict__ st,
                                                     double *__restrict__ partials,
-                                                    const double *__restrict__ part_pap, int npap, int par)
+                                                    const double *__restrict__ part_pap, int npap)
 {
     if (st[S_DONE] != 0) return;
     double alpha_self = 0;
     if (SELF) {
         const double pap = block_total_n<kBlock>(part_pap, npap);
-        alpha_self = st[S_RRB + par] / pap;
+        alpha_self = st[S_RR] / pap;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st[S_PAP] = pap;
             st[S_ALPHA] = alpha_self;
+            st[S_RROLD] = st[S_RR];
         }
     }
     const int tt = xcd_site(2 * g.Vh);
@@ -132,12 +132,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
 
 // stage 4; part_pap != nullptr: alpha formed in the kernel (fused CG), else from st
 void launch_cg_hop4(pfmp_ctx *ctx, bool cl, int nb, const double2 *t, const double2 *T, const double *clov,
-                    double mk2, const double2 *p, double2 *x, double2 *r, double *part, const double *part_pap,
-                    int par)
+                    double mk2, const double2 *p, double2 *x, double2 *r, double *part, const double *part_pap)
 {
 #define HOP4(CL, LM, SF)                                                                                            \
     hipLaunchKernelGGL((k_cg_hop4<CL, LM, SF>), dim3(nb), dim3(kBlock), 0, ctx->stream, ctx->g, t, T, ctx->U, clov, \
-                       mk2, p, x, r, ctx->scal, part, part_pap, nb, par)
+                       mk2, p, x, r, ctx->scal, part, part_pap, nb)
 #define HOP4_11(LM) HOP4(1, LM, 1)
 #define HOP4_10(LM) HOP4(1, LM, 0)
 #define HOP4_01(LM) HOP4(0, LM, 1)
@@ -155,15 +154,14 @@ void launch_cg_hop4(pfmp_ctx *ctx, bool cl, int nb, const double2 *t, const doub
 }
 
 // beta = |r+|^2 / |r|^2 formed in every block from the stage-4 partials, p = r + beta p;
-// block 0 records |r+|^2 for the next parity and the convergence state
+// block 0 records |r+|^2, the iteration count and the stop flag
 __global__ __launch_bounds__(kRedBlock) void k_cg_update_p_fused(long n, const double2 *__restrict__ r,
                                                                  double2 *__restrict__ p, double *__restrict__ st,
-                                                                 const double *__restrict__ part_rr, int nrr,
-                                                                 int par)
+                                                                 const double *__restrict__ part_rr, int nrr)
 {
     if (st[S_DONE] != 0) return;
     const double rr = block_total_n<kRedBlock>(part_rr, nrr);
-    const double b = rr / st[S_RRB + par];
+    const double b = rr / st[S_RROLD];
     const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (e < n) {
         double2 rv = r[e], pv = p[e];
@@ -172,7 +170,6 @@ __global__ __launch_bounds__(kRedBlock) void k_cg_update_p_fused(long n, const d
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st[S_BETA] = b;
         st[S_RR] = rr;
-        st[S_RRB + (par ^ 1)] = rr;
         st[S_ITER] += 1;
         st[S_DONE] = rr <= st[S_THR] ? 1 : (st[S_ITER] >= st[S_MAXIT] ? 2 : 0);
     }
@@ -402,26 +399,33 @@ extern "C" int pfmp_cg_solve(pfmp_ctx *ctx, int op, const void *b_, void *x_, co
     const bool cl = s.csw != 0;
     const double mk2 = -s.kappa * s.kappa;
     int chunk = prm->check_every > 0 ? prm->check_every : 25;
-    int par = 0;   // iteration parity: which |r|^2 slot holds the current value
     double h[16], rr_prev = 0, it_prev = 0;
+    // one iteration: 5 launches with fixed arguments, replayed as a graph
+    auto iteration = [&]() -> int {
+        int e;
+        // t = Mhat p, with <p, Khat p> = |t|^2 partials
+        if ((e = clovinv64(ctx, 1, B.p, s.clov[1], B.T, 1.0, 1.0, cl, ctx->scal + S_DONE))) return e;
+        if ((e = xpay64(ctx, 0, B.p, B.T, s.clov[0], mk2, B.t, 1.0, cl, B.part_a, ctx->scal + S_DONE))) return e;
+        // T' = A_oo^-1 D_oe g5 t
+        if ((e = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE))) return e;
+        // alpha, x and r updates; then beta and p, each formed where it is used
+        launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, x, B.r, B.part_b, B.part_a);
+        hipLaunchKernelGGL(k_cg_update_p_fused, dim3(nblocks(n, kRedBlock)), dim3(kRedBlock), 0, ctx->stream, n,
+                           B.r, B.p, ctx->scal, B.part_b, nb);
+        LAUNCHCHK(ctx);
+        return 0;
+    };
+    std::vector<uint64_t> key;
+    key_add(key, 1);   // FP64 CG iteration
+    key_geom(key, g);
+    for (const void *ptr : {(const void *)B.p, (const void *)B.T, (const void *)B.t, (const void *)B.r,
+                            (const void *)B.part_a, (const void *)B.part_b, (const void *)x, (const void *)ctx->U,
+                            (const void *)ctx->scal, (const void *)s.clov[0], (const void *)s.clov[1]})
+        key_add(key, ptr);
+    key_add(key, mk2);
+    key_add(key, (int)cl);
     for (;;) {
-        for (int k = 0; k < chunk; k++) {
-            // t = Mhat p, with <p, Khat p> = |t|^2 partials
-            if ((rc = clovinv64(ctx, 1, B.p, s.clov[1], B.T, 1.0, 1.0, cl, ctx->scal + S_DONE)))
-                return rc;
-            if ((rc = xpay64(ctx, 0, B.p, B.T, s.clov[0], mk2, B.t, 1.0, cl, B.part_a,
-                                                    ctx->scal + S_DONE)))
-                return rc;
-            // T' = A_oo^-1 D_oe g5 t
-            if ((rc = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE)))
-                return rc;
-            // alpha, x and r updates; then beta and p, each formed where it is used
-            launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, x, B.r, B.part_b, B.part_a, par);
-            hipLaunchKernelGGL(k_cg_update_p_fused, dim3(nblocks(n, kRedBlock)), dim3(kRedBlock), 0, ctx->stream, n,
-                               B.r, B.p, ctx->scal, B.part_b, nb, par);
-            LAUNCHCHK(ctx);
-            par ^= 1;
-        }
+        if ((rc = graph_run(ctx, key, chunk, iteration))) return rc;
         if ((rc = read_state(ctx, h, 16))) return rc;
         if (h[S_DONE] != 0) break;
         if (prm->check_every <= 0) chunk = next_chunk(h[S_RR], h[S_THR], h[S_ITER], rr_prev, it_prev);
@@ -489,28 +493,42 @@ extern "C" int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const doubl
     const bool cl = s.csw != 0;
     const double mk2 = -s.kappa * s.kappa;
     int chunk = prm->check_every > 0 ? prm->check_every : 25;
-    double h[16];
+    double h[16], rr_prev = 0, it_prev = 0;
+    // one iteration: 7 launches with fixed arguments, replayed as a graph
+    auto iteration = [&]() -> int {
+        int e;
+        if ((e = clovinv64(ctx, 1, B.p, s.clov[1], B.T, 1.0, 1.0, cl, ctx->scal + S_DONE))) return e;
+        if ((e = xpay64(ctx, 0, B.p, B.T, s.clov[0], mk2, B.t, 1.0, cl, B.part_a, ctx->scal + S_DONE))) return e;
+        hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_a, nb, nshift, ctx->scal,
+                           rec);
+        if ((e = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE))) return e;
+        // r -= alpha Khat p (the base x is not needed; it goes to scratch)
+        launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, B.Kx, B.r, B.part_b, nullptr);
+        hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_b, nb, nshift, ctx->scal,
+                           rec);
+        hipLaunchKernelGGL(k_ms_update, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, nshift, B.r, B.p, ptrs,
+                           ptrs + nshift, rec, ctx->scal);
+        LAUNCHCHK(ctx);
+        return 0;
+    };
+    std::vector<uint64_t> key;
+    key_add(key, 3);   // multi-shift iteration
+    key_geom(key, g);
+    key_add(key, nshift);
+    for (const void *ptr : {(const void *)B.p, (const void *)B.T, (const void *)B.t, (const void *)B.r,
+                            (const void *)B.Kx, (const void *)B.part_a, (const void *)B.part_b, (const void *)ptrs,
+                            (const void *)ctx->U, (const void *)ctx->scal, (const void *)s.clov[0],
+                            (const void *)s.clov[1]})
+        key_add(key, ptr);
+    key_add(key, mk2);
+    key_add(key, (int)cl);
     for (;;) {
-        for (int k = 0; k < chunk; k++) {
-            if ((rc = clovinv64(ctx, 1, B.p, s.clov[1], B.T, 1.0, 1.0, cl, ctx->scal + S_DONE)))
-                return rc;
-            if ((rc = xpay64(ctx, 0, B.p, B.T, s.clov[0], mk2, B.t, 1.0, cl, B.part_a,
-                                                    ctx->scal + S_DONE)))
-                return rc;
-            hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_a, nb, nshift, ctx->scal,
-                               rec);
-            if ((rc = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE)))
-                return rc;
-            // r -= alpha Khat p (the base x is not needed; it goes to scratch)
-            launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, B.Kx, B.r, B.part_b, nullptr, 0);
-            hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_b, nb, nshift, ctx->scal,
-                               rec);
-            hipLaunchKernelGGL(k_ms_update, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, nshift, B.r, B.p,
-                               ptrs, ptrs + nshift, rec, ctx->scal);
-            LAUNCHCHK(ctx);
-        }
+        if ((rc = graph_run(ctx, key, chunk, iteration))) return rc;
         if ((rc = read_state(ctx, h, 16))) return rc;
         if (h[S_DONE] != 0) break;
+        if (prm->check_every <= 0) chunk = next_chunk(h[S_RR], h[S_THR], h[S_ITER], rr_prev, it_prev);
+        rr_prev = h[S_RR];
+        it_prev = h[S_ITER];
     }
     int iters = (int)h[S_ITER];
     double worst = 0;

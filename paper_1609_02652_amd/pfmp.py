@@ -168,6 +168,7 @@ def load():
         "pfmp_set_site_order": [vp, i],
         "pfmp_set_link_streaming": [vp, i],
         "pfmp_autotune": [vp, i, vp],
+        "pfmp_set_graphs": [vp, i],
         "pfmp_get_link_reconstruct": [vp, vp],
         "pfmp_apply_MdagM_batch": [vp, i, vp, vp, vp],
         "pfmp_cg_solve_batch": [vp, i, vp, vp, vp, vp, vp],
@@ -277,6 +278,10 @@ class Lattice:
 
     def link_streaming(self, on):
         self._chk(self.lib.pfmp_set_link_streaming(self.h, int(bool(on))), "set_link_streaming")
+
+    def graphs(self, on):
+        """Replay solver iterations as HIP graphs (default) or launch them one by one."""
+        self._chk(self.lib.pfmp_set_graphs(self.h, int(bool(on))), "set_graphs")
 
     def autotune(self, op):
         """Pick the fastest site visit order and link load mode for Mhat of slot op."""

@@ -251,3 +251,28 @@ def test_visit_order_and_link_streaming(setup, zt, stream):
     print("autotune", dims, tune)
     assert tune["zt"] == 0 or dims[2] % tune["zt"] == 0
     assert rel(lat.spinor_numpy(lat.apply_MdagM(0, f)), ops[0].K(psi)) < 1e-12
+
+
+def test_graph_replay_matches_eager(setup):
+    """Solver iterations replayed as HIP graphs give the eager launches' results bit for
+    bit, for several solves in a row (each replaying graphs captured earlier), with
+    eager work and synchronisations in between."""
+    from paper_1609_02652_amd.pfmp import F64, F32, F16
+    dims, U, lat, ops = setup
+    for prec in (F64, F32, F16):
+        for k in range(3):
+            b = lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 90 + k))
+            lat.graphs(False)
+            xe, se = lat.cg_solve(0, b, tol=1e-10, prec=prec)
+            xe = xe.clone()
+            lat.stream.synchronize()
+            lat.graphs(True)
+            xg, sg = lat.cg_solve(0, b, tol=1e-10, prec=prec)
+            assert sg["iters"] == se["iters"], (prec, k)
+            assert lat.torch.equal(xg, xe), (prec, k)
+    ms_e = lat.cg_multishift(1, [0.3 + 0.2j, 0.0], lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 95)), tol=1e-10)
+    lat.graphs(False)
+    ms_g = lat.cg_multishift(1, [0.3 + 0.2j, 0.0], lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 95)), tol=1e-10)
+    lat.graphs(True)
+    for a, b in zip(ms_e[0], ms_g[0]):
+        assert lat.torch.equal(a, b)

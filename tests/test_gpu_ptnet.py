@@ -106,3 +106,11 @@ def test_train_and_precondition(setup):
               % (sp["iters"], sp["reliable_updates"], sc["iters"]))
     print("network gain: %.1f%% fewer iterations" % (100.0 * (1 - it_p / it_c)))
     assert it_p < 0.8 * it_c
+    # the flexible CG replayed as graphs equals its eager launches bit for bit
+    b = lat.pack_spinor(bs[0])
+    xg, sg = lat.fcg_solve(0, W, b, tol=1e-10)
+    xg = xg.clone()
+    lat.graphs(False)
+    xe, se = lat.fcg_solve(0, W, b, tol=1e-10)
+    lat.graphs(True)
+    assert sg["iters"] == se["iters"] and lat.torch.equal(xg, xe)
