@@ -1,13 +1,13 @@
 // batch.hip -- multi-RHS operator and CG: k right-hand sides, each with its own
 // operator slot (kappa, clover), in one launch per stage.
 //
-// One thread per (site, rhs) with the rhs index fastest inside a wavefront: the k
-// lanes of a site read the same link address, so every link is fetched from HBM
-// once per k right-hand sides (the cache serves the other lanes) while each
-// thread keeps the register footprint of the single-RHS kernel.  Per-rhs CG
-// scalars and convergence flags live on the device; a converged rhs stops
-// touching memory.  Reductions: one FP64 partial per (block, rhs), wave
-// shuffles with stride k, fixed order.
+// Each workgroup serves one right-hand side (so every pointer and scalar of the rhs is
+// uniform in the workgroup) with the two-lanes-per-site kernels of the single-RHS
+// operator.  The n workgroups that cover the same block of sites for the n right-hand
+// sides are consecutive in the XCD-aware block order, so they run together on one XCD
+// and every link is fetched once into its L2 for all n.  Per-rhs CG scalars and
+// convergence flags live on the device; a converged rhs stops touching memory.
+// Reductions: one FP64 partial per workgroup (indexed site block * n + rhs), fixed order.
 #include <chrono>
 #include <cmath>
 
@@ -20,8 +20,9 @@ enum { B_RR = 0, B_THR, B_PAP, B_ALPHA, B_BETA, B_ITER, B_DONE, B_MAXIT, B_NSLOT
 constexpr int kBatchBase = 5120;   // per-rhs scalar records at ctx->scal + kBatchBase + 8 r
 
 struct Batch {
-    int k;                          // lanes per site (power of 2 >= n)
+    int k;                          // stride of the partials (= n)
     int n;                          // right-hand sides
+    int nsb;                        // site blocks (two lanes per site, kBlock lanes per block)
     const double *clo[kMaxRhs];     // A_oo^-1 of each rhs's operator
     const double *cle[kMaxRhs];     // A_ee
     double a[kMaxRhs];              // -kappa^2
@@ -33,109 +34,115 @@ struct Vecs {
     double2 *out[kMaxRhs];
 };
 
-__device__ __forceinline__ bool item(const Batch &b, int nsites, int *site, int *r)
+// logical workgroup lb = site block * n + rhs (XCD-aware order); false past the end
+__device__ __forceinline__ bool item(const Geom &g, const Batch &b, int *lb, int *site, int *r, int *hb)
 {
-    int t = xcd_site(nsites * b.k);
-    if (t < 0) return false;
-    *site = t / b.k;
-    *r = t - *site * b.k;
-    return *r < b.n;
+    const int nb = gridDim.x, bi = blockIdx.x;
+    const int per = (nb + 7) >> 3;
+    *lb = (bi & 7) * per + (bi >> 3);
+    if (*lb >= b.nsb * b.n) return false;
+    *r = *lb % b.n;
+    const int t = (*lb / b.n) * blockDim.x + threadIdx.x;
+    if (t >= 2 * g.Vh) return false;
+    *site = tile_site(g, t >> 1);
+    *hb = t & 1;
+    return true;
 }
 
-// sum over the lanes of equal rhs index, one FP64 partial per (block, rhs)
-__device__ __forceinline__ void batch_partial(double v, int k, double *partials)
+// one FP64 partial per logical workgroup (every thread of the block calls this)
+__device__ __forceinline__ void batch_partial(double v, int lb, int nlb, double *partials)
 {
-    __shared__ double sh[kBlock / 64][kMaxRhs];
-    for (int o = 32; o >= k; o >>= 1) v += __shfl_down(v, o, 64);
-    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane < k) sh[w][lane] = v;
+    __shared__ double sh[kBlock / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x < k) {
+    if (threadIdx.x == 0 && lb < nlb) {
         double s = 0;
-        for (int q = 0; q < kBlock / 64; q++) s += sh[q][threadIdx.x];
-        partials[blockIdx.x * k + threadIdx.x] = s;
+        for (int q = 0; q < kBlock / 64; q++) s += sh[q];
+        partials[lb] = s;
     }
 }
 
 // out_r = [g5] A_oo^-1 D_oe [g5] in_r
-template <int CLOV>
+template <int CLOV, int LM>
 __global__ __launch_bounds__(kBlock) void k_b_clovinv(Geom g, Batch b, Vecs v, const double2 *__restrict__ U,
                                                       double gin, double gout, const double *__restrict__ st)
 {
-    int i, r;
-    if (!item(b, g.Vh, &i, &r)) return;
+    int lb, i, r, hb;
+    if (!item(g, b, &lb, &i, &r, &hb)) return;
     if (st && st[8 * r + B_DONE] != 0) return;
-    double2 acc[12];
-    hop_all<double2>(g, 1, i, v.in[r], U, gin, acc);
+    double2 blk[6];
+    hop_pair<LM, double2>(g, 1, i, hb, v.in[r], U, gin, blk);
     if (CLOV) {
-        double2 t[12];
-        clover_apply<double, double2>(b.clo[r], g.Vh, i, acc, t);
-        store_spinor(v.out[r], g.Vh, i, gout, t);
+        double2 t[6];
+        clover_block<double, double2>(b.clo[r], g.Vh, i, hb, blk, t);
+        store_block(v.out[r], g.Vh, i, hb, gout, t);
     } else {
-        store_spinor(v.out[r], g.Vh, i, gout, acc);
+        store_block(v.out[r], g.Vh, i, hb, gout, blk);
     }
 }
 
 // out_r = [g5] (A_ee [g5] x_r + a_r D_eo t_r), |out_r|^2 partials
-template <int CLOV>
+template <int CLOV, int LM>
 __global__ __launch_bounds__(kBlock) void k_b_xpay(Geom g, Batch b, Vecs x, Vecs t, const double2 *__restrict__ U,
                                                    double gs, const double *__restrict__ st,
                                                    double *__restrict__ partials)
 {
-    int i, r;
-    bool ok = item(b, g.Vh, &i, &r);
+    int lb = 0, i = 0, r = 0, hb = 0;
+    bool ok = item(g, b, &lb, &i, &r, &hb);
     if (ok && st && st[8 * r + B_DONE] != 0) ok = false;
     double nrm = 0;
     if (ok) {
-        double2 acc[12], xv[12], ax[12];
-        hop_all<double2>(g, 0, i, t.in[r], U, 1.0, acc);
-        load_spinor(x.in[r], g.Vh, i, gs, xv);
-        if (CLOV) clover_apply<double, double2>(b.cle[r], g.Vh, i, xv, ax);
+        double2 acc[6], xv[6], ax[6];
+        hop_pair<LM, double2>(g, 0, i, hb, t.in[r], U, 1.0, acc);
+        load_block(x.in[r], g.Vh, i, hb, gs, xv);
+        if (CLOV) clover_block<double, double2>(b.cle[r], g.Vh, i, hb, xv, ax);
         const double a = b.a[r];
 #pragma unroll
-        for (int k = 0; k < 12; k++) {
+        for (int k = 0; k < 6; k++) {
             double2 base = CLOV ? ax[k] : xv[k];
             acc[k] = make_double2(base.x + a * acc[k].x, base.y + a * acc[k].y);
             nrm += acc[k].x * acc[k].x + acc[k].y * acc[k].y;
         }
-        store_spinor(x.out[r], g.Vh, i, gs, acc);
+        store_block(x.out[r], g.Vh, i, hb, gs, acc);
     }
-    if (partials) batch_partial(nrm, b.k, partials);
+    if (partials) batch_partial(nrm, lb, b.nsb * b.n, partials);
 }
 
 // CG stage 4: Kp_r from t_r and T'_r; x_r += alpha_r p_r; r_r -= alpha_r Kp_r; |r_r|^2 partials
-template <int CLOV>
+template <int CLOV, int LM>
 __global__ __launch_bounds__(kBlock) void k_b_hop4(Geom g, Batch b, Vecs t, Vecs T, Vecs p, Vecs x, Vecs rr,
                                                    const double2 *__restrict__ U, const double *__restrict__ st,
                                                    double *__restrict__ partials)
 {
-    int i, r;
-    bool ok = item(b, g.Vh, &i, &r);
+    int lb = 0, i = 0, r = 0, hb = 0;
+    bool ok = item(g, b, &lb, &i, &r, &hb);
     if (ok && st[8 * r + B_DONE] != 0) ok = false;
     double nrm = 0;
     if (ok) {
-        double2 acc[12], tv[12], at[12];
-        hop_all<double2>(g, 0, i, T.in[r], U, 1.0, acc);
-        load_spinor(t.in[r], g.Vh, i, -1.0, tv);
-        if (CLOV) clover_apply<double, double2>(b.cle[r], g.Vh, i, tv, at);
+        double2 acc[6], tv[6], at[6];
+        hop_pair<LM, double2>(g, 0, i, hb, T.in[r], U, 1.0, acc);
+        load_block(t.in[r], g.Vh, i, hb, -1.0, tv);
+        if (CLOV) clover_block<double, double2>(b.cle[r], g.Vh, i, hb, tv, at);
         const double alpha = st[8 * r + B_ALPHA], a = b.a[r];
         const long Vh = g.Vh;
         const double2 *pp = p.in[r];
         double2 *xx = x.out[r], *rv_ = rr.out[r];
 #pragma unroll
-        for (int k = 0; k < 12; k++) {
+        for (int k = 0; k < 6; k++) {
             double2 base = CLOV ? at[k] : tv[k];
             double2 kp = make_double2(base.x + a * acc[k].x, base.y + a * acc[k].y);
-            if (k >= 6) kp = cneg(kp);
-            double2 pv = pp[k * Vh + i], xv = xx[k * Vh + i], rv = rv_[k * Vh + i];
+            if (hb) kp = cneg(kp);
+            const long e = (long)(6 * hb + k) * Vh + i;
+            double2 pv = pp[e], xv = xx[e], rv = rv_[e];
             xv.x += alpha * pv.x; xv.y += alpha * pv.y;
             rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
-            xx[k * Vh + i] = xv;
-            rv_[k * Vh + i] = rv;
+            xx[e] = xv;
+            rv_[e] = rv;
             nrm += rv.x * rv.x + rv.y * rv.y;
         }
     }
-    batch_partial(nrm, b.k, partials);
+    batch_partial(nrm, lb, b.nsb * b.n, partials);
 }
 
 __device__ __forceinline__ double rhs_total(const double *__restrict__ partials, int nparts, int k, int r)
@@ -198,19 +205,29 @@ __global__ void k_b_update_p(Geom g, Batch b, Vecs rr, Vecs p, const double *__r
 
 }  // namespace
 
-// launch the CLOV = 0 / 1 instance of a batch stencil kernel
-#define BLAUNCH(K, grid, block, shm, stream, ...)                                                     \
-    do {                                                                                           \
-        if (b.clov[0]) hipLaunchKernelGGL(K<1>, grid, block, shm, stream, __VA_ARGS__);              \
-        else hipLaunchKernelGGL(K<0>, grid, block, shm, stream, __VA_ARGS__);                       \
+// launch the (CLOV, link mode) instance of a batch stencil kernel
+#define BLAUNCH(K, grid, block, shm, stream, ...)                                                        \
+    do {                                                                                              \
+        const int lm_ = link_mode(ctx->g);                                                            \
+        if (b.clov[0]) {                                                                              \
+            if (lm_ == 0) hipLaunchKernelGGL((K<1, 0>), grid, block, shm, stream, __VA_ARGS__);         \
+            else if (lm_ == 1) hipLaunchKernelGGL((K<1, 1>), grid, block, shm, stream, __VA_ARGS__);    \
+            else if (lm_ == 2) hipLaunchKernelGGL((K<1, 2>), grid, block, shm, stream, __VA_ARGS__);    \
+            else hipLaunchKernelGGL((K<1, 3>), grid, block, shm, stream, __VA_ARGS__);                  \
+        } else {                                                                                      \
+            if (lm_ == 0) hipLaunchKernelGGL((K<0, 0>), grid, block, shm, stream, __VA_ARGS__);         \
+            else if (lm_ == 1) hipLaunchKernelGGL((K<0, 1>), grid, block, shm, stream, __VA_ARGS__);    \
+            else if (lm_ == 2) hipLaunchKernelGGL((K<0, 2>), grid, block, shm, stream, __VA_ARGS__);    \
+            else hipLaunchKernelGGL((K<0, 3>), grid, block, shm, stream, __VA_ARGS__);                  \
+        }                                                                                             \
     } while (0)
 
 static int make_batch(pfmp_ctx *ctx, int nrhs, const int *ops, Batch &b)
 {
     if (nrhs <= 0 || nrhs > kMaxRhs || !ops) return set_err(ctx, PFMP_ERR_ARG, "batch: 1..8 right-hand sides");
     b.n = nrhs;
-    b.k = 1;
-    while (b.k < nrhs) b.k <<= 1;
+    b.k = nrhs;
+    b.nsb = nblocks(2L * ctx->g.Vh, kBlock);
     for (int r = 0; r < kMaxRhs; r++) {
         int op = r < nrhs ? ops[r] : ops[0];
         if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
@@ -256,7 +273,7 @@ extern "C" int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, c
         to[r] = pool_get(ctx, 1008 + r);
         if (!te[r] || !to[r]) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
     }
-    dim3 grid(nblocks_site((long)g.Vh * b.k)), block(kBlock);
+    dim3 grid(((b.nsb * nrhs + 7) / 8) * 8), block(kBlock);
     // Mhat in -> te (stage 1 to to, stage 2 to te), then Mhat^dag te -> out
     BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b, vecs(nrhs, in, to.data()), ctx->U, 1.0, 1.0,
                        nullptr);
@@ -297,7 +314,8 @@ extern "C" int pfmp_cg_solve_batch(pfmp_ctx *ctx, int nrhs, const int *ops, cons
         HIPCHK(ctx, hipMemcpyAsync(R[r], b_[r], vb, hipMemcpyDeviceToDevice, ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(P[r], b_[r], vb, hipMemcpyDeviceToDevice, ctx->stream));
     }
-    const int nb = nblocks_site((long)g.Vh * b.k);
+    const int nb = b.nsb;   // partials per rhs
+    const int ngrid = ((b.nsb * nrhs + 7) / 8) * 8;
     double *part_a = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64) * b.k, 9);
     double *part_b = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64) * b.k, 10);
     if (!part_a || !part_b) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
@@ -315,7 +333,7 @@ extern "C" int pfmp_cg_solve_batch(pfmp_ctx *ctx, int nrhs, const int *ops, cons
         init[8 * r + B_MAXIT] = prm->maxiter;
     }
     HIPCHK(ctx, hipMemcpyAsync(sc, init.data(), sizeof(double) * 8 * kMaxRhs, hipMemcpyHostToDevice, ctx->stream));
-    dim3 grid(nb), block(kBlock);
+    dim3 grid(ngrid), block(kBlock);
     const Vecs vP = vecs(nrhs, (const void *const *)P.data(), P.data());
     const Vecs vT1 = vecs(nrhs, (const void *const *)T1.data(), T1.data());
     const Vecs vT2 = vecs(nrhs, (const void *const *)T2.data(), T2.data());
@@ -327,17 +345,33 @@ extern "C" int pfmp_cg_solve_batch(pfmp_ctx *ctx, int nrhs, const int *ops, cons
     const Vecs T1_to_T2 = vecs(nrhs, (const void *const *)T1.data(), T2.data());
     int chunk = prm->check_every > 0 ? prm->check_every : 25;
     std::vector<double> h(8 * kMaxRhs);
+    // one iteration for all rhs: 7 launches with fixed arguments, replayed as a graph
+    auto iteration = [&]() -> int {
+        BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b, p_to_T2, ctx->U, 1.0, 1.0, sc);
+        BLAUNCH(k_b_xpay, grid, block, 0, ctx->stream, g, b, p_to_T1, vT2, ctx->U, 1.0, sc, part_a);
+        hipLaunchKernelGGL(k_b_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_a, nb, b.k, nrhs, sc);
+        BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b, T1_to_T2, ctx->U, -1.0, 1.0, sc);
+        BLAUNCH(k_b_hop4, grid, block, 0, ctx->stream, g, b, vT1, vT2, vP, vX, vR, ctx->U, sc, part_b);
+        hipLaunchKernelGGL(k_b_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, b.k, nrhs, sc);
+        hipLaunchKernelGGL(k_b_update_p, dim3(nblocks(n * nrhs, 256)), dim3(256), 0, ctx->stream, g, b, vR, vP, sc);
+        LAUNCHCHK(ctx);
+        return 0;
+    };
+    std::vector<uint64_t> key;
+    key_add(key, 5);   // batched CG iteration
+    key_geom(key, g);
+    key_add(key, nrhs);
+    for (int r = 0; r < nrhs; r++) {
+        for (const void *ptr : {(const void *)P[r], (const void *)T1[r], (const void *)T2[r], (const void *)R[r],
+                                (const void *)x_[r], (const void *)b.clo[r], (const void *)b.cle[r]})
+            key_add(key, ptr);
+        key_add(key, b.a[r]);
+    }
+    for (const void *ptr : {(const void *)part_a, (const void *)part_b, (const void *)sc, (const void *)ctx->U})
+        key_add(key, ptr);
+    key_add(key, b.clov[0]);
     for (;;) {
-        for (int it = 0; it < chunk; it++) {
-            BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b, p_to_T2, ctx->U, 1.0, 1.0, sc);
-            BLAUNCH(k_b_xpay, grid, block, 0, ctx->stream, g, b, p_to_T1, vT2, ctx->U, 1.0, sc, part_a);
-            hipLaunchKernelGGL(k_b_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_a, nb, b.k, nrhs, sc);
-            BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b, T1_to_T2, ctx->U, -1.0, 1.0, sc);
-            BLAUNCH(k_b_hop4, grid, block, 0, ctx->stream, g, b, vT1, vT2, vP, vX, vR, ctx->U, sc, part_b);
-            hipLaunchKernelGGL(k_b_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, b.k, nrhs, sc);
-            hipLaunchKernelGGL(k_b_update_p, dim3(nblocks(n * nrhs, 256)), dim3(256), 0, ctx->stream, g, b, vR, vP, sc);
-            LAUNCHCHK(ctx);
-        }
+        if ((rc = graph_run(ctx, key, chunk, iteration))) return rc;
         HIPCHK(ctx, hipMemcpyAsync(ctx->red_host, sc, sizeof(double) * 8 * kMaxRhs, hipMemcpyDeviceToHost,
                                    ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));

@@ -84,15 +84,18 @@ __global__ __launch_bounds__(kBlock) void k_pt_l1(Geom g, const float2 *__restri
         if (fs[F_DONE] != 0) return;
         scale = (float)fs[F_INVR];
     }
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // four lanes per site: lane q computes the hidden channels 3q .. 3q + 2
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int i = (int)(t >> 2), q = (int)(t & 3);
     if (i >= g.Vh) return;
     int c[4];
     eo_coords(g, 1, i, c);
-    float2 h[NH * 3];
-    for (int k = 0; k < NH * 3; k++) h[k] = make_float2(0.f, 0.f);
+    constexpr int NO = NH / 4;
+    float2 h[NO * 3];
+    for (int k = 0; k < NO * 3; k++) h[k] = make_float2(0.f, 0.f);
     for (int d = 0; d < 8; d++) {
         int j = nbr_of(g, c, d);
-        float2 u[9], t[NIN * 3];
+        float2 u[9], tv[NIN * 3];
         float sgn;
         load_T(g, U, 1, i, c, d, u, &sgn);
         for (int ch = 0; ch < NIN; ch++) {
@@ -101,27 +104,30 @@ __global__ __launch_bounds__(kBlock) void k_pt_l1(Geom g, const float2 *__restri
                 double2 x = r[(long)(3 * ch + a) * g.Vh + j];
                 v[a] = make_float2((float)x.x * scale, (float)x.y * scale);
             }
-            apply_T<0>(u, sgn, v, t + 3 * ch);
+            apply_T<0>(u, sgn, v, tv + 3 * ch);
         }
-        const float2 *w = W + d * NH * NIN;
-        for (int o = 0; o < NH; o++)
+        const float2 *w = W + d * NH * NIN + (NO * q) * NIN;
+        for (int o = 0; o < NO; o++)
             for (int ch = 0; ch < NIN; ch++) {
                 float2 wc = w[o * NIN + ch];
-                for (int a = 0; a < 3; a++) cfma(h[3 * o + a], wc, t[3 * ch + a]);
+                for (int a = 0; a < 3; a++) cfma(h[3 * o + a], wc, tv[3 * ch + a]);
             }
     }
-    for (int o = 0; o < NH; o++) {
-        float q = 0.f;
-        for (int a = 0; a < 3; a++) q += h[3 * o + a].x * h[3 * o + a].x + h[3 * o + a].y * h[3 * o + a].y;
-        float s = 1.f / (1.f + q);
+    for (int o = 0; o < NO; o++) {
+        const int oc = NO * q + o;
+        float qq = 0.f;
+        for (int a = 0; a < 3; a++) qq += h[3 * o + a].x * h[3 * o + a].x + h[3 * o + a].y * h[3 * o + a].y;
+        float sg = 1.f / (1.f + qq);
         for (int a = 0; a < 3; a++) {
-            if (H) H[(long)(3 * o + a) * g.Vh + i] = h[3 * o + a];
-            G[(long)(3 * o + a) * g.Vh + i] = make_float2(h[3 * o + a].x * s, h[3 * o + a].y * s);
+            if (H) H[(long)(3 * oc + a) * g.Vh + i] = h[3 * o + a];
+            G[(long)(3 * oc + a) * g.Vh + i] = make_float2(h[3 * o + a].x * sg, h[3 * o + a].y * sg);
         }
     }
 }
 
-// layer 2 on even sites: z = conv(g) + W0 rhat; out (FP64) = oscale * z, or z (FP32)
+// layer 2 on even sites: z = conv(g) + W0 rhat; out (FP64) = oscale * z, or z (FP32).
+// Four lanes per site, lane o computing output channel o:
+// sum_ch W2[d][o][ch] T_d g_ch = T_d (sum_ch W2[d][o][ch] g_ch), one transport per direction.
 __global__ __launch_bounds__(kBlock) void k_pt_l2(Geom g, const float2 *__restrict__ U,
                                                   const double2 *__restrict__ r, float scale,
                                                   const float2 *__restrict__ W, const float2 *__restrict__ G,
@@ -133,48 +139,39 @@ __global__ __launch_bounds__(kBlock) void k_pt_l2(Geom g, const float2 *__restri
         scale = (float)fs[F_INVR];
         oscale = fs[F_NR];
     }
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const int i = (int)(t >> 2), o = (int)(t & 3);
     if (i >= g.Vh) return;
     int c[4];
     eo_coords(g, 0, i, c);
-    float2 z[NIN * 3];
     const float2 *W2 = W + NW1, *W0 = W + NW1 + NW2;
-    for (int o = 0; o < NIN; o++)
-        for (int a = 0; a < 3; a++) {
-            float2 acc = make_float2(0.f, 0.f);
-            for (int ch = 0; ch < NIN; ch++) {
-                double2 x = r[(long)(3 * ch + a) * g.Vh + i];
-                cfma(acc, W0[o * NIN + ch], make_float2((float)x.x * scale, (float)x.y * scale));
-            }
-            z[3 * o + a] = acc;
+    float2 z[3];
+    for (int a = 0; a < 3; a++) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int ch = 0; ch < NIN; ch++) {
+            double2 x = r[(long)(3 * ch + a) * g.Vh + i];
+            cfma(acc, W0[o * NIN + ch], make_float2((float)x.x * scale, (float)x.y * scale));
         }
-    // sum_ch W2[d][o][ch] T_d g_ch = T_d (sum_ch W2[d][o][ch] g_ch): mix the 12 channels
-    // of the neighbour into 4, then transport 4 colour vectors per direction
+        z[a] = acc;
+    }
     for (int d = 0; d < 8; d++) {
         int j = nbr_of(g, c, d);
-        const float2 *w = W2 + d * NIN * NH;
-        float2 m[NIN * 3];
-        for (int k = 0; k < NIN * 3; k++) m[k] = make_float2(0.f, 0.f);
+        const float2 *w = W2 + d * NIN * NH + o * NH;
+        float2 m[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
         for (int ch = 0; ch < NH; ch++) {
-            float2 v[3];
-            for (int a = 0; a < 3; a++) v[a] = G[(long)(3 * ch + a) * g.Vh + j];
-            for (int o = 0; o < NIN; o++) {
-                float2 wc = w[o * NH + ch];
-                for (int a = 0; a < 3; a++) cfma(m[3 * o + a], wc, v[a]);
-            }
+            const float2 wc = w[ch];
+            for (int a = 0; a < 3; a++) cfma(m[a], wc, G[(long)(3 * ch + a) * g.Vh + j]);
         }
-        float2 u[9];
+        float2 u[9], tv[3];
         float sgn;
         load_T(g, U, 0, i, c, d, u, &sgn);
-        for (int o = 0; o < NIN; o++) {
-            float2 t[3];
-            apply_T<0>(u, sgn, m + 3 * o, t);
-            for (int a = 0; a < 3; a++) z[3 * o + a] = cadd(z[3 * o + a], t[a]);
-        }
+        apply_T<0>(u, sgn, m, tv);
+        for (int a = 0; a < 3; a++) z[a] = cadd(z[a], tv[a]);
     }
-    for (int k = 0; k < NIN * 3; k++) {
-        if (out) out[(long)k * g.Vh + i] = make_double2(oscale * z[k].x, oscale * z[k].y);
-        if (zf) zf[(long)k * g.Vh + i] = z[k];
+    for (int a = 0; a < 3; a++) {
+        const long e = (long)(3 * o + a) * g.Vh + i;
+        if (out) out[e] = make_double2(oscale * z[a].x, oscale * z[a].y);
+        if (zf) zf[e] = z[a];
     }
 }
 
@@ -616,9 +613,10 @@ static int pt_apply(pfmp_ctx *ctx, PtWs &w, const double2 *r, double nr, double2
     const Geom &g = ctx->g;
     float sc = nr > 0 ? (float)(1.0 / nr) : 0.f;
     dim3 grid(nblocks(g.Vh, kBlock)), block(kBlock);
-    hipLaunchKernelGGL(k_pt_l1, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, (float2 *)nullptr, w.G,
+    dim3 grid4(nblocks(4L * g.Vh, kBlock));
+    hipLaunchKernelGGL(k_pt_l1, grid4, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, (float2 *)nullptr, w.G,
                        (const double *)nullptr);
-    hipLaunchKernelGGL(k_pt_l2, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, w.G, nr, out,
+    hipLaunchKernelGGL(k_pt_l2, grid4, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, w.G, nr, out,
                        (float2 *)nullptr, (const double *)nullptr);
     LAUNCHCHK(ctx);
     return 0;
@@ -666,10 +664,10 @@ extern "C" int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int op, int npair
         double nr = host_norm(ctx, r, &rc);
         if (rc) return rc;
         float sc = (float)(1.0 / nr);
-        hipLaunchKernelGGL(k_pt_l1, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, w.H, w.G,
-                           (const double *)nullptr);
-        hipLaunchKernelGGL(k_pt_l2, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, w.G, 1.0,
-                           (double2 *)nullptr, w.z, (const double *)nullptr);
+        hipLaunchKernelGGL(k_pt_l1, dim3(nblocks(4L * g.Vh, kBlock)), block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W,
+                           w.H, w.G, (const double *)nullptr);
+        hipLaunchKernelGGL(k_pt_l2, dim3(nblocks(4L * g.Vh, kBlock)), block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W,
+                           w.G, 1.0, (double2 *)nullptr, w.z, (const double *)nullptr);
         LAUNCHCHK(ctx);
         if (op >= 0) {
             // y = Khat z, d = y - rhat, Gz = Khat d (Khat Hermitian)
@@ -773,7 +771,7 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
     OpSlot &s = ctx->ops[op];
     const bool cl = s.csw != 0;
     const double mk2 = -s.kappa * s.kappa;
-    dim3 pgrid(nblocks(g.Vh, kBlock)), pblock(kBlock);
+    dim3 pgrid(nblocks(4L * g.Vh, kBlock)), pblock(kBlock);
     HIPCHK(ctx, hipMemsetAsync(x, 0, vb, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, ctx->stream));
     if ((rc = launch_norm2(ctx, b, n, ctx->red))) return rc;
