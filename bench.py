@@ -92,6 +92,26 @@ def hop_roofline(dims, U, reps=200):
             "link_reals": link_reals, "tune": tune}
 
 
+def pmc_traffic(lattice):
+    """HBM bytes per launch of the plain FP64 hop from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (scaled by the counters' reading for a copy of
+    known size), or None when the kernel sources have changed since they were
+    taken."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, "profiles", "hop_fp64_pmc_traffic.md")).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
+        return rec["traffic_bytes_per_launch"].get(lattice)
+    except (OSError, ValueError, KeyError, AttributeError):
+        return None
+
+
 def roofline_only(reps):
     """Only the hopping kernels (16^3x32 and 32^3x64) and a plain copy of known size,
     for hardware-counter runs: FETCH_SIZE / WRITE_SIZE of the copy calibrate the
@@ -240,7 +260,7 @@ def learned_bench(lat, nsrc):
     rs += [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 600 + k)) for k in range(8)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    W, losses = lat.ptnet_train(synth.network_weights(4, scale=0.05), rs, steps=150, lr=1e-2, op=0)
+    W, losses = lat.ptnet_train(synth.network_weights(4, scale=0.05), rs, steps=300, lr=1e-2, op=0)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     srcs = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 1 + s)) for s in range(nsrc)]
@@ -253,7 +273,7 @@ def learned_bench(lat, nsrc):
         _, st = lat.fcg_solve(0, W, b, x=x, tol=TOL)
         torch.cuda.synchronize()
         rows.append((time.perf_counter() - t0, st["iters"], st["true_res"], st["reliable_updates"]))
-    out = {"train_vectors": len(rs), "train_steps": 150, "train_s": round(t_train, 3),
+    out = {"train_vectors": len(rs), "train_steps": 300, "train_s": round(t_train, 3),
            "loss_first": round(float(losses[0]), 4), "loss_last": round(float(losses[-1]), 4),
            "fcg_median_s": round(float(np.median([r[0] for r in rows])), 5),
            "fcg_iters": int(np.median([r[1] for r in rows])),
@@ -356,7 +376,8 @@ def main():
     achieved = rf["bytes_hop"] / rf["t_hop"] / 1e9
     roof = {"kernel": "hop (D_oe, FP64, plain; links read as %d reals)" % rf["link_reals"], "bound": "hbm",
             "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": pmc_traffic("x".join(map(str, DIMS))),
             "avg_launch_us": round(rf["t_hop"] * 1e6, 2), "bytes_per_launch": rf["bytes_hop"],
             "Mhat_GBps": round(rf["bytes_M"] / rf["t_M"] / 1e9, 1), "tuning": rf["tune"],
             "note": "16^3x32 working set fits the 256 MB Infinity Cache"}
@@ -368,6 +389,7 @@ def main():
         roof["Mhat_32x64_GBps"] = round(rb["bytes_M"] / rb["t_M"] / 1e9, 1)
         roof["hop_32x64_us"] = round(rb["t_hop"] * 1e6, 2)
         roof["tuning_32x64"] = rb["tune"]
+        roof["traffic_32x64"] = pmc_traffic("x".join(map(str, big)))
     except Exception as e:  # noqa: BLE001 -- report, do not hide
         roof["hop_32x64_error"] = str(e)
 

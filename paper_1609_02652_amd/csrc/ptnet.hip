@@ -30,7 +30,8 @@ __device__ __forceinline__ float2 fconj(float2 a) { return make_float2(a.x, -a.y
 
 // device scalars of the flexible CG (ctx->scal + kFcgBase)
 constexpr int kFcgBase = 7600;
-enum { F_RZ = 0, F_PQ, F_ALPHA, F_RN2, F_THR, F_ITER, F_DONE, F_MAXIT, F_INVR, F_NR, F_BETA, F_FB, F_NFB, F_NSLOT };
+enum { F_RZ = 0, F_PQ, F_ALPHA, F_RN2, F_THR, F_ITER, F_DONE, F_MAXIT, F_INVR, F_NR, F_BETA, F_FB, F_NFB, F_RZOLD,
+       F_NSLOT };
 
 // The transporter T_d(y) of the site y with coordinates c, loaded once per direction:
 // U_mu(y) for d = 2 mu, U_mu(y - mu)^dag for d = 2 mu + 1, and its fermion boundary factor.
@@ -84,6 +85,10 @@ __global__ __launch_bounds__(kBlock) void k_pt_l1(Geom g, const float2 *__restri
         if (fs[F_DONE] != 0) return;
         scale = (float)fs[F_INVR];
     }
+    // weights of layer 1 in LDS (uniform reads; the lanes of a site index different rows)
+    __shared__ float2 sw[NW1];
+    for (int k = threadIdx.x; k < NW1; k += blockDim.x) sw[k] = W[k];
+    __syncthreads();
     // four lanes per site: lane q computes the hidden channels 3q .. 3q + 2
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const int i = (int)(t >> 2), q = (int)(t & 3);
@@ -106,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_l1(Geom g, const float2 *__restri
             }
             apply_T<0>(u, sgn, v, tv + 3 * ch);
         }
-        const float2 *w = W + d * NH * NIN + (NO * q) * NIN;
+        const float2 *w = sw + d * NH * NIN + (NO * q) * NIN;
         for (int o = 0; o < NO; o++)
             for (int ch = 0; ch < NIN; ch++) {
                 float2 wc = w[o * NIN + ch];
@@ -132,46 +137,80 @@ __global__ __launch_bounds__(kBlock) void k_pt_l2(Geom g, const float2 *__restri
                                                   const double2 *__restrict__ r, float scale,
                                                   const float2 *__restrict__ W, const float2 *__restrict__ G,
                                                   double oscale, double2 *__restrict__ out, float2 *__restrict__ zf,
-                                                  const double *__restrict__ fs)
+                                                  const double *__restrict__ fs, const double2 *__restrict__ q,
+                                                  double *__restrict__ dots)
 {
+    // (flexible CG: with dots, also the block partials of Re<out, r> and Re<out, q>)
     if (fs) {
         if (fs[F_DONE] != 0) return;
         scale = (float)fs[F_INVR];
         oscale = fs[F_NR];
     }
+    __shared__ float2 sw[NW2 + NW0];
+    for (int k = threadIdx.x; k < NW2 + NW0; k += blockDim.x) sw[k] = W[NW1 + k];
+    __syncthreads();
+    const float2 *W2 = sw, *W0 = sw + NW2;
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const int i = (int)(t >> 2), o = (int)(t & 3);
-    if (i >= g.Vh) return;
-    int c[4];
-    eo_coords(g, 0, i, c);
-    const float2 *W2 = W + NW1, *W0 = W + NW1 + NW2;
-    float2 z[3];
-    for (int a = 0; a < 3; a++) {
-        float2 acc = make_float2(0.f, 0.f);
-        for (int ch = 0; ch < NIN; ch++) {
-            double2 x = r[(long)(3 * ch + a) * g.Vh + i];
-            cfma(acc, W0[o * NIN + ch], make_float2((float)x.x * scale, (float)x.y * scale));
+    double dzr = 0, dzq = 0;
+    if (i < g.Vh) {
+        int c[4];
+        eo_coords(g, 0, i, c);
+        float2 z[3];
+        for (int a = 0; a < 3; a++) {
+            float2 acc = make_float2(0.f, 0.f);
+            for (int ch = 0; ch < NIN; ch++) {
+                double2 x = r[(long)(3 * ch + a) * g.Vh + i];
+                cfma(acc, W0[o * NIN + ch], make_float2((float)x.x * scale, (float)x.y * scale));
+            }
+            z[a] = acc;
         }
-        z[a] = acc;
-    }
-    for (int d = 0; d < 8; d++) {
-        int j = nbr_of(g, c, d);
-        const float2 *w = W2 + d * NIN * NH + o * NH;
-        float2 m[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-        for (int ch = 0; ch < NH; ch++) {
-            const float2 wc = w[ch];
-            for (int a = 0; a < 3; a++) cfma(m[a], wc, G[(long)(3 * ch + a) * g.Vh + j]);
+        for (int d = 0; d < 8; d++) {
+            int j = nbr_of(g, c, d);
+            const float2 *w = W2 + d * NIN * NH + o * NH;
+            float2 m[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+            for (int ch = 0; ch < NH; ch++) {
+                const float2 wc = w[ch];
+                for (int a = 0; a < 3; a++) cfma(m[a], wc, G[(long)(3 * ch + a) * g.Vh + j]);
+            }
+            float2 u[9], tv[3];
+            float sgn;
+            load_T(g, U, 0, i, c, d, u, &sgn);
+            apply_T<0>(u, sgn, m, tv);
+            for (int a = 0; a < 3; a++) z[a] = cadd(z[a], tv[a]);
         }
-        float2 u[9], tv[3];
-        float sgn;
-        load_T(g, U, 0, i, c, d, u, &sgn);
-        apply_T<0>(u, sgn, m, tv);
-        for (int a = 0; a < 3; a++) z[a] = cadd(z[a], tv[a]);
+        for (int a = 0; a < 3; a++) {
+            const long e = (long)(3 * o + a) * g.Vh + i;
+            const double2 zo = make_double2(oscale * z[a].x, oscale * z[a].y);
+            if (out) out[e] = zo;
+            if (zf) zf[e] = z[a];
+            if (dots) {
+                const double2 rv = r[e], qv = q[e];
+                dzr += zo.x * rv.x + zo.y * rv.y;
+                dzq += zo.x * qv.x + zo.y * qv.y;
+            }
+        }
     }
-    for (int a = 0; a < 3; a++) {
-        const long e = (long)(3 * o + a) * g.Vh + i;
-        if (out) out[e] = make_double2(oscale * z[a].x, oscale * z[a].y);
-        if (zf) zf[e] = z[a];
+    if (dots) {
+        __shared__ double sh[2][kBlock / 64];
+        for (int off = 32; off > 0; off >>= 1) {
+            dzr += __shfl_down(dzr, off, 64);
+            dzq += __shfl_down(dzq, off, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            sh[0][threadIdx.x >> 6] = dzr;
+            sh[1][threadIdx.x >> 6] = dzq;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0, b = 0;
+            for (int k = 0; k < kBlock / 64; k++) {
+                a += sh[0][k];
+                b += sh[1][k];
+            }
+            dots[2 * blockIdx.x] = a;
+            dots[2 * blockIdx.x + 1] = b;
+        }
     }
 }
 
@@ -211,18 +250,39 @@ __global__ __launch_bounds__(kBlock) void k_pt_resid(Geom g, const float2 *__res
     block_sum_store<float2>(s, partials);
 }
 
-// wave-level partial of (re, im) into part[wave * stride + 2 idx]
-__device__ __forceinline__ void wave_partial(float2 v, double *part, long stride, int idx)
+// Wave sums of K values per lane (K a power of two, at most 64) by reduce-scatter:
+// at each butterfly level a lane keeps one half of its values and adds the other
+// lane's copy of that half, so log2(K) levels cost K - 1 shuffles in all; lane l
+// ends with the total of value l / (64 / K) and stores it to
+// part[wave * stride + base + l / (64 / K)].
+// one level: n live values, partner lane at xor distance M
+template <int N, int M, int K>
+__device__ __forceinline__ void rs_level(float (&v)[K], int lane)
 {
-    double re = v.x, im = v.y;
-    for (int o = 32; o > 0; o >>= 1) {
-        re += __shfl_down(re, o, 64);
-        im += __shfl_down(im, o, 64);
+    if constexpr (N > 1) {
+        const bool up = (lane & M) != 0;
+#pragma unroll
+        for (int j = 0; j < N / 2; j++) {
+            const float send = up ? v[j] : v[j + N / 2];
+            const float keep = up ? v[j + N / 2] : v[j];
+            v[j] = keep + __shfl_xor(send, M, 64);
+        }
+        rs_level<N / 2, M / 2>(v, lane);
     }
-    if ((threadIdx.x & 63) == 0) {
-        long w = (blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6;
-        part[w * stride + 2 * idx] = re;
-        part[w * stride + 2 * idx + 1] = im;
+}
+
+template <int K>
+__device__ __forceinline__ void wave_rs_store(float (&v)[K], double *__restrict__ part, long stride, int base)
+{
+    static_assert(K >= 1 && K <= 64 && (K & (K - 1)) == 0, "K must be a power of two <= 64");
+    const int lane = threadIdx.x & 63;
+    rs_level<K, 32>(v, lane);
+    constexpr int R = 64 / K;
+#pragma unroll
+    for (int m = R / 2; m > 0; m >>= 1) v[0] += __shfl_xor(v[0], m, 64);
+    if ((lane & (R - 1)) == 0) {
+        const long w = (blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6;
+        part[w * stride + base + lane / R] = v[0];
     }
 }
 
@@ -255,17 +315,33 @@ __global__ __launch_bounds__(kBlock) void k_pt_grad2(Geom g, const float2 *__res
         } else {
             for (int k = 0; k < NIN * 3; k++) tg[k] = make_float2(0.f, 0.f);
         }
+        // the NIN x NH values of direction d, (re, im) interleaved in index order: the
+        // first 64 floats in one reduce-scatter, the last 32 in another
+        static_assert(2 * NIN * NH == 96, "split of the values of one direction");
+        float va[64], vb[32];
+#pragma unroll
         for (int ch = 0; ch < NH; ch++) {
             float2 v[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
             if (ok)
                 for (int a = 0; a < 3; a++) v[a] = G[(long)(3 * ch + a) * g.Vh + j];
+#pragma unroll
             for (int o = 0; o < NIN; o++) {
                 float2 acc = make_float2(0.f, 0.f);
                 for (int a = 0; a < 3; a++) cfmac(acc, tg[3 * o + a], v[a]);
-                wave_partial(acc, part, stride, (d * NIN + o) * NH + ch);
+                const int f = 2 * (o * NH + ch);
+                if (f < 64) {
+                    va[f] = acc.x;
+                    va[f + 1] = acc.y;
+                } else {
+                    vb[f - 64] = acc.x;
+                    vb[f - 63] = acc.y;
+                }
             }
         }
+        wave_rs_store(va, part, stride, 2 * d * NIN * NH);
+        wave_rs_store(vb, part, stride, 2 * d * NIN * NH + 64);
     }
+    float vals0[2 * NIN * NIN];
     for (int o = 0; o < NIN; o++)
         for (int ch = 0; ch < NIN; ch++) {
             float2 acc = make_float2(0.f, 0.f);
@@ -274,8 +350,10 @@ __global__ __launch_bounds__(kBlock) void k_pt_grad2(Geom g, const float2 *__res
                     double2 x = r[(long)(3 * ch + a) * g.Vh + i];
                     cfmac(acc, gz[3 * o + a], make_float2((float)x.x * scale, (float)x.y * scale));
                 }
-            wave_partial(acc, part, stride, NW2 + o * NIN + ch);
+            vals0[2 * (o * NIN + ch)] = acc.x;
+            vals0[2 * (o * NIN + ch) + 1] = acc.y;
         }
+    wave_rs_store(vals0, part, stride, 2 * NW2);
 }
 
 // back to the hidden layer on odd y: Gg(y) = sum_d W2[opp d]^dag T_d(y) Gz(y + d), then
@@ -333,6 +411,8 @@ __global__ __launch_bounds__(kBlock) void k_pt_grad1(Geom g, const float2 *__res
     int c[4] = {0, 0, 0, 0};
     if (ok) eo_coords(g, 1, i, c);
     const long stride = 2L * NW1;
+    float2 gh[NH * 3];
+    for (int k = 0; k < NH * 3; k++) gh[k] = ok ? Gh[(long)k * g.Vh + i] : make_float2(0.f, 0.f);
     for (int d = 0; d < 8; d++) {
         int j = ok ? nbr_of(g, c, d) : 0;
         float2 t[NIN * 3], u[9];
@@ -347,25 +427,63 @@ __global__ __launch_bounds__(kBlock) void k_pt_grad1(Geom g, const float2 *__res
             if (ok) apply_T<0>(u, sgn, v, t + 3 * ch);
             else for (int a = 0; a < 3; a++) t[3 * ch + a] = make_float2(0.f, 0.f);
         }
-        for (int o = 0; o < NH; o++) {
-            float2 gh[3];
-            for (int a = 0; a < 3; a++) gh[a] = ok ? Gh[(long)(3 * o + a) * g.Vh + i] : make_float2(0.f, 0.f);
+        // the NH x NIN values of direction d in index order: hidden channels 0-7 in one
+        // reduce-scatter of 64 floats, 8-11 in one of 32
+        static_assert(2 * NIN * NH == 96, "split of the values of one direction");
+        float va[64];
+#pragma unroll
+        for (int o = 0; o < 8; o++)
+#pragma unroll
             for (int ch = 0; ch < NIN; ch++) {
                 float2 acc = make_float2(0.f, 0.f);
-                for (int a = 0; a < 3; a++) cfmac(acc, gh[a], t[3 * ch + a]);
-                wave_partial(acc, part, stride, (d * NH + o) * NIN + ch);
+                for (int a = 0; a < 3; a++) cfmac(acc, gh[3 * o + a], t[3 * ch + a]);
+                va[2 * (o * NIN + ch)] = acc.x;
+                va[2 * (o * NIN + ch) + 1] = acc.y;
             }
-        }
+        wave_rs_store(va, part, stride, 2 * d * NH * NIN);
+        float vb[32];
+#pragma unroll
+        for (int o = 8; o < NH; o++)
+#pragma unroll
+            for (int ch = 0; ch < NIN; ch++) {
+                float2 acc = make_float2(0.f, 0.f);
+                for (int a = 0; a < 3; a++) cfmac(acc, gh[3 * o + a], t[3 * ch + a]);
+                vb[2 * ((o - 8) * NIN + ch)] = acc.x;
+                vb[2 * ((o - 8) * NIN + ch) + 1] = acc.y;
+            }
+        wave_rs_store(vb, part, stride, 2 * d * NH * NIN + 64);
     }
 }
 
-// out[v] = sum_w part[w * nvals + v] in fixed order, one thread per value
-__global__ void k_pt_sum(const double *__restrict__ part, long nw, int nvals, double *__restrict__ out)
+// Column sums of the (nw x nvals) row-major partials in two fixed-order passes.
+// Pass 1: block (c, j) sums rows of chunk j for the 64 columns of group c, four row
+// phases per column folded through LDS; mid[j * nvals + v].
+constexpr int kSumChunks = 64;
+
+__global__ __launch_bounds__(256) void k_pt_sum_rows(const double *__restrict__ part, long nw, int nvals,
+                                                     double *__restrict__ mid)
+{
+    __shared__ double sh[256];
+    const int v = blockIdx.x * 64 + (threadIdx.x & 63), ph = threadIdx.x >> 6;
+    const long per = (nw + kSumChunks - 1) / kSumChunks;
+    const long w0 = blockIdx.y * per, w1 = w0 + per < nw ? w0 + per : nw;
+    double s = 0;
+    if (v < nvals)
+        for (long w = w0 + ph; w < w1; w += 4) s += part[w * nvals + v];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (ph == 0 && v < nvals)
+        mid[(long)blockIdx.y * nvals + v] = (sh[threadIdx.x] + sh[threadIdx.x + 64]) +
+                                            (sh[threadIdx.x + 128] + sh[threadIdx.x + 192]);
+}
+
+// pass 2: out[v] = sum_j mid[j * nvals + v], one thread per value
+__global__ void k_pt_sum(const double *__restrict__ mid, int nvals, double *__restrict__ out)
 {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nvals) return;
     double s = 0;
-    for (long w = 0; w < nw; w++) s += part[w * nvals + v];
+    for (int j = 0; j < kSumChunks; j++) s += mid[(long)j * nvals + v];
     out[v] = s;
 }
 
@@ -405,6 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_f_hop4(Geom g, const double2 *__rest
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         fs[F_PQ] = pq;
         fs[F_ALPHA] = alpha;
+        fs[F_RZOLD] = fs[F_RZ];
     }
     const int tt = xcd_site(2 * g.Vh);
     double nrm = 0;
@@ -539,6 +658,51 @@ __global__ void k_f_update_p(long n, const double2 *__restrict__ z, const double
     p[e] = make_double2(v.x + b * pv.x, v.y + b * pv.y);
 }
 
+// Polak-Ribiere step fused with p: <z, r> and <z, q> from the block partials of the
+// network's second layer (the same sums in every block), beta = -alpha <z, q> / rz_old
+// or the plain-CG fallback (z = r, beta = 0) where <z, r> <= 0; p = z + beta p.  Block 0
+// records rz and the fallback count.
+__global__ __launch_bounds__(kRedBlock) void k_f_update_p_fused(long n, const double2 *__restrict__ z,
+                                                                const double2 *__restrict__ r,
+                                                                double2 *__restrict__ p, double *__restrict__ fs,
+                                                                const double *__restrict__ dots, int nd)
+{
+    if (fs[F_DONE] != 0) return;
+    __shared__ double sh[2][kRedBlock / 64];
+    double a = 0, b = 0;
+    for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+        a += dots[2 * k];
+        b += dots[2 * k + 1];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_down(a, o, 64);
+        b += __shfl_down(b, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = a;
+        sh[1][threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    double zr = 0, zq = 0;
+    for (int k = 0; k < kRedBlock / 64; k++) {
+        zr += sh[0][k];
+        zq += sh[1][k];
+    }
+    const bool fb = !(zr > 0);
+    const double beta = fb ? 0.0 : -fs[F_ALPHA] * zq / fs[F_RZOLD];
+    const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (e < n) {
+        double2 v = fb ? r[e] : z[e], pv = p[e];
+        p[e] = make_double2(v.x + beta * pv.x, v.y + beta * pv.y);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        fs[F_BETA] = beta;
+        fs[F_FB] = fb ? 1 : 0;
+        if (fb) fs[F_NFB] += 1;
+        fs[F_RZ] = fb ? fs[F_RN2] : zr;
+    }
+}
+
 // start: x = 0, r = b, |r|^2 = |b|^2 and the thresholds
 __global__ __launch_bounds__(kRedBlock) void k_f_init(const double *__restrict__ part, int n, double tol2,
                                                       int maxiter, double *__restrict__ fs)
@@ -571,7 +735,7 @@ __global__ __launch_bounds__(kRedBlock) void k_f_init(const double *__restrict__
 
 struct PtWs {
     float2 *W, *H, *G, *Gz, *Gh, *z;
-    double *part, *sum;
+    double *part, *mid, *sum;
 };
 
 static int pt_ws(pfmp_ctx *ctx, const double *Wc, PtWs &w)
@@ -587,7 +751,8 @@ static int pt_ws(pfmp_ctx *ctx, const double *Wc, PtWs &w)
     w.Gh = (float2 *)ws_alloc(ctx, hb, 36);
     w.Gz = (float2 *)ws_alloc(ctx, zb, 37);
     w.z = (float2 *)ws_alloc(ctx, zb, 38);
-    w.part = (double *)ws_alloc(ctx, sizeof(double) * (nwaves * per_wave + 64), 33);
+    w.part = (double *)ws_alloc(ctx, sizeof(double) * ((nwaves + kSumChunks) * per_wave + 64), 33);
+    w.mid = w.part ? w.part + nwaves * per_wave : nullptr;
     w.sum = (double *)(ctx->scal + 6000);   // 2 * (NW2 + NW0) <= 800 doubles
     if (!w.W || !w.H || !w.G || !w.Gh || !w.Gz || !w.z || !w.part) return set_err(ctx, PFMP_ERR_OOM, "ptnet workspace");
     if (Wc) {
@@ -597,6 +762,14 @@ static int pt_ws(pfmp_ctx *ctx, const double *Wc, PtWs &w)
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     }
     return 0;
+}
+
+// w.sum[v] = column sums of the nwaves x nvals partials
+static void col_sums(pfmp_ctx *ctx, PtWs &w, long nwaves, int nvals)
+{
+    hipLaunchKernelGGL(k_pt_sum_rows, dim3((nvals + 63) / 64, kSumChunks), dim3(256), 0, ctx->stream, w.part, nwaves,
+                       nvals, w.mid);
+    hipLaunchKernelGGL(k_pt_sum, dim3(nblocks(nvals, 256)), dim3(256), 0, ctx->stream, w.mid, nvals, w.sum);
 }
 
 static double host_norm(pfmp_ctx *ctx, const double2 *v, int *rc)
@@ -617,7 +790,7 @@ static int pt_apply(pfmp_ctx *ctx, PtWs &w, const double2 *r, double nr, double2
     hipLaunchKernelGGL(k_pt_l1, grid4, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, (float2 *)nullptr, w.G,
                        (const double *)nullptr);
     hipLaunchKernelGGL(k_pt_l2, grid4, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W, w.G, nr, out,
-                       (float2 *)nullptr, (const double *)nullptr);
+                       (float2 *)nullptr, (const double *)nullptr, (const double2 *)nullptr, (double *)nullptr);
     LAUNCHCHK(ctx);
     return 0;
 }
@@ -667,7 +840,8 @@ extern "C" int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int op, int npair
         hipLaunchKernelGGL(k_pt_l1, dim3(nblocks(4L * g.Vh, kBlock)), block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W,
                            w.H, w.G, (const double *)nullptr);
         hipLaunchKernelGGL(k_pt_l2, dim3(nblocks(4L * g.Vh, kBlock)), block, 0, ctx->stream, g, ctx->Uf, r, sc, w.W,
-                           w.G, 1.0, (double2 *)nullptr, w.z, (const double *)nullptr);
+                           w.G, 1.0, (double2 *)nullptr, w.z, (const double *)nullptr, (const double2 *)nullptr,
+                           (double *)nullptr);
         LAUNCHCHK(ctx);
         if (op >= 0) {
             // y = Khat z, d = y - rhat, Gz = Khat d (Khat Hermitian)
@@ -689,8 +863,7 @@ extern "C" int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int op, int npair
         tot += lp;
         // A2 and A0
         hipLaunchKernelGGL(k_pt_grad2, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.G, w.Gz, w.part);
-        hipLaunchKernelGGL(k_pt_sum, dim3(nblocks(2 * (NW2 + NW0), 256)), dim3(256), 0, ctx->stream, w.part, nwaves,
-                           2 * (NW2 + NW0), w.sum);
+        col_sums(ctx, w, nwaves, 2 * (NW2 + NW0));
         LAUNCHCHK(ctx);
         HIPCHK(ctx, hipMemcpyAsync(tmp.data(), w.sum, sizeof(double) * 2 * (NW2 + NW0), hipMemcpyDeviceToHost,
                                    ctx->stream));
@@ -699,8 +872,7 @@ extern "C" int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int op, int npair
         // back through layer 2 and the gate, then A1
         hipLaunchKernelGGL(k_pt_back, grid, block, 0, ctx->stream, g, ctx->Uf, w.W, w.Gz, w.H, w.Gh);
         hipLaunchKernelGGL(k_pt_grad1, grid, block, 0, ctx->stream, g, ctx->Uf, r, sc, w.Gh, w.part);
-        hipLaunchKernelGGL(k_pt_sum, dim3(nblocks(2 * NW1, 256)), dim3(256), 0, ctx->stream, w.part, nwaves, 2 * NW1,
-                           w.sum);
+        col_sums(ctx, w, nwaves, 2 * NW1);
         LAUNCHCHK(ctx);
         HIPCHK(ctx, hipMemcpyAsync(tmp.data(), w.sum, sizeof(double) * 2 * NW1, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -760,10 +932,14 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
     double2 *r = pool_get(ctx, 2010), *T = pool_get(ctx, 2011), *z = pool_get(ctx, 2012), *p = pool_get(ctx, 2013),
             *q = pool_get(ctx, 2014), *t = pool_get(ctx, 2015);
     if (!r || !T || !z || !p || !q || !t) return set_err(ctx, PFMP_ERR_OOM, "fcg workspace");
-    const int nb = op_nparts(g), ndot = 256;
-    // part_b holds the |r|^2 block partials (nb) and the two dot products (2 ndot)
+    const int nb = op_nparts(g), ndot = 256, nl2 = nblocks(4L * g.Vh, kBlock);
+    // part_b holds the |r|^2 block partials (nb) and the two dot products (2 ndot, or
+    // 2 per block of the network's second layer)
+    long npb = nb;
+    if (2L * ndot > npb) npb = 2L * ndot;
+    if (2L * nl2 > npb) npb = 2L * nl2;
     double *part_a = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64), 9);
-    double *part_b = (double *)ws_alloc(ctx, sizeof(double) * ((nb > 2 * ndot ? nb : 2 * ndot) + 64), 10);
+    double *part_b = (double *)ws_alloc(ctx, sizeof(double) * (npb + 64), 10);
     if (!part_a || !part_b) return set_err(ctx, PFMP_ERR_OOM, "fcg workspace");
     const double2 *b = (const double2 *)b_;
     double2 *x = (double2 *)x_;
@@ -779,12 +955,13 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
                        prm->tol * prm->tol, prm->maxiter, fs);
     LAUNCHCHK(ctx);
     // z = N(r) (or r), rz = <z, r>, p = z (or the fallback p = r)
+    double *dots = nullptr;   // the second layer's <z, r>, <z, q> partials (in the iterations)
     auto precondition = [&]() -> int {
         if (W) {
             hipLaunchKernelGGL(k_pt_l1, pgrid, pblock, 0, ctx->stream, g, ctx->Uf, r, 0.f, w.W, (float2 *)nullptr,
                                w.G, (const double *)fs);
             hipLaunchKernelGGL(k_pt_l2, pgrid, pblock, 0, ctx->stream, g, ctx->Uf, r, 0.f, w.W, w.G, 0.0, z,
-                               (float2 *)nullptr, (const double *)fs);
+                               (float2 *)nullptr, (const double *)fs, (const double2 *)q, dots);
             LAUNCHCHK(ctx);
             return 0;
         }
@@ -817,11 +994,20 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
 #undef FHOP4
         hipLaunchKernelGGL(k_f_norm, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, fs);
         LAUNCHCHK(ctx);
-        // z = N(r); with the identity, z = r is read directly
-        if (W && (e = precondition())) return e;
-        hipLaunchKernelGGL(k_f_dots, dim3(ndot), dim3(kBlock), 0, ctx->stream, n, W ? z : r, r, q, fs, part_b);
-        hipLaunchKernelGGL(k_f_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, ndot, 0, fs);
-        hipLaunchKernelGGL(k_f_update_p, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, W ? z : r, r, p, fs);
+        if (W) {
+            // z = N(r) with the <z, r>, <z, q> partials, then beta and p in one launch
+            dots = part_b;
+            e = precondition();
+            dots = nullptr;
+            if (e) return e;
+            hipLaunchKernelGGL(k_f_update_p_fused, dim3(nblocks(n, kRedBlock)), dim3(kRedBlock), 0, ctx->stream, n, z,
+                               r, p, fs, part_b, nl2);
+        } else {
+            // identity: z = r is read directly
+            hipLaunchKernelGGL(k_f_dots, dim3(ndot), dim3(kBlock), 0, ctx->stream, n, r, r, q, fs, part_b);
+            hipLaunchKernelGGL(k_f_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, ndot, 0, fs);
+            hipLaunchKernelGGL(k_f_update_p, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, r, r, p, fs);
+        }
         LAUNCHCHK(ctx);
         return 0;
     };
