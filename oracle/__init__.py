@@ -73,6 +73,9 @@ def lib():
         L.or_update_momenta.argtypes = [ctypes.c_long, ctypes.c_double, dp, dp]
         L.or_kinetic.argtypes = [ctypes.c_long, dp]
         L.or_kinetic.restype = ctypes.c_double
+        L.or_sample_sites.argtypes = [ip, ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_int, dp, ctypes.c_long, ip, dp]
+        L.or_sample_sites.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -237,6 +240,23 @@ def _links(links):
     if len(_keep) > 8:
         del _keep[0]
     return len(arr), _p(arr)
+
+
+def sample_sites(dims, U, kappa, csw, psi, sites, mode, dagger=False, tbc=-1):
+    """The hop D_oe psi (mode "hop": odd output sites) or Mhat psi (mode "M": even
+    output sites, dagger for Mhat^dag) at the given even-odd output indices only,
+    from the definitions with the clover of the few sites involved built on the
+    spot (eq. 2.2; clover and Schur form as in the operator context).  psi: even
+    field [Vh][4][3].  Returns [n][4][3]."""
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    idx = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.zeros((len(idx), 4, 3), np.complex128)
+    rc = lib().or_sample_sites(_p(_dims(dims)), tbc, _p(U), kappa, csw, {"hop": 0, "M": 1}[mode], int(dagger),
+                               _p(psi), len(idx), _p(idx), _p(out))
+    if rc:
+        raise ValueError("or_sample_sites failed (%d)" % rc)
+    return out
 
 
 def gauge_action(dims, U, beta):

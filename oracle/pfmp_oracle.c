@@ -561,6 +561,64 @@ void or_apply_M(void *p, int dagger, const double *in, double *out)
     free(to); free(te); free(ae);
 }
 
+/* The hop D_oe psi (mode 0: output on odd sites) or Mhat psi (mode 1: output on even
+ * sites; dagger selects Mhat^dag) evaluated at n chosen output sites only, straight
+ * from the definitions and without an operator context: for an even site x the
+ * clover matrix A(x) and, for each of its eight odd neighbours y, A(y) and its
+ * inverse are built on the spot, and (D_oe psi)(y) is the hopping term at y.  This
+ * gives the oracle's value at sampled sites of lattices too large for the dense
+ * per-site clover storage of the operator context.  in: even-parity field
+ * [Vh][12] complex; sites: even-odd indices of the output parity; out: [n][12]. */
+int or_sample_sites(const int *L, int tbc, const double *U, double kappa, double csw, int mode, int dagger,
+                    const double *in_, long n, const long *sites, double *out_)
+{
+    for (int m = 0; m < 4; m++)
+        if (L[m] < 4 || (L[m] & 1)) return -1;
+    const long V = volume(L), Vh = V / 2;
+    const cplx *in = (const cplx *)in_;
+    cplx *out = (cplx *)out_;
+    linkview lv = {L, (const cplx *)U, -1, 0, NULL};
+    cplx *fi = calloc(12 * V, sizeof(cplx)), *fs = calloc(12 * V, sizeof(cplx));
+    if (!fi || !fs) { free(fi); free(fs); return -2; }
+    for (long i = 0; i < Vh; i++) memcpy(fi + 12 * lex_of_eo(L, 0, i), in + 12 * i, sizeof(cplx) * 12);
+    for (long k = 0; k < n; k++) {
+        if (sites[k] < 0 || sites[k] >= Vh) { free(fi); free(fs); return -1; }
+        if (mode == 0) {
+            hop_at(&lv, tbc, fi, lex_of_eo(L, 1, sites[k]), dagger, out + 12 * k);
+            continue;
+        }
+        const long x = lex_of_eo(L, 0, sites[k]);
+        long nb[8];
+        for (int mu = 0; mu < 4; mu++)
+            for (int st = 0; st < 2; st++) {
+                double sg;
+                long y = neighbour(L, tbc, x, mu, st ? -1 : +1, &sg);
+                nb[2 * mu + st] = y;
+                cplx t[12], A[144], Ai[144];
+                hop_at(&lv, tbc, fi, y, dagger, t);
+                clover_site(&lv, kappa, csw, y, 1, A);
+                if (gj_inverse(A, 12, Ai)) { free(fi); free(fs); return -3; }
+                for (int r = 0; r < 12; r++) {
+                    cplx acc = 0;
+                    for (int c = 0; c < 12; c++) acc += Ai[r * 12 + c] * t[c];
+                    fs[12 * y + r] = acc;
+                }
+            }
+        cplx te[12], A[144];
+        hop_at(&lv, tbc, fs, x, dagger, te);
+        clover_site(&lv, kappa, csw, x, 1, A);
+        for (int r = 0; r < 12; r++) {
+            cplx ae = 0;
+            for (int c = 0; c < 12; c++) ae += A[r * 12 + c] * fi[12 * x + c];
+            out[12 * k + r] = ae - kappa * kappa * te[r];
+        }
+        for (int j = 0; j < 8; j++) memset(fs + 12 * nb[j], 0, sizeof(cplx) * 12);
+    }
+    free(fi);
+    free(fs);
+    return 0;
+}
+
 /* K = Mhat^dag Mhat */
 void or_apply_K(void *p, const double *in, double *out)
 {
