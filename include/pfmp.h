@@ -159,8 +159,11 @@ int pfmp_apply_MdagM(pfmp_ctx *ctx, int op, const void *in, void *out, int prec)
 /* Product-form polynomial (paper App. A): out = norm * prod_k (Khat - z_k) in,
  * the factors applied in the order given (k = 0 first).  roots: n complex
  * numbers as 2n doubles (host); norm: complex (host).  chain: optional array of
- * n device buffers; chain[k] receives the partial product after k factors
- * (chain[0] = in, unscaled) -- the vectors the polynomial force needs.  FP64. */
+ * n device buffers; chain[k] receives norm times the partial product after k
+ * factors (chain[0] = norm * in) -- the vectors the polynomial force needs.
+ * prec PFMP_F64: in, out and chain are FP64 fields; PFMP_F32: FP32 fields, the
+ * operator applied with the FP32 copies of the links and clover (roots and norm
+ * rounded to FP32).  out must not alias a chain buffer (PFMP_ERR_ARG). */
 int pfmp_apply_poly(pfmp_ctx *ctx, int op, int n, const double *roots, const double norm[2],
                     const void *in, void *out, void *const *chain, int prec);
 
@@ -241,6 +244,10 @@ int pfmp_cg_harvest(pfmp_ctx *ctx, int op, const void *b, void *x, double tol, i
 int pfmp_dot(pfmp_ctx *ctx, const void *a, const void *b, double out[2]);
 /* y = alpha x + beta y (complex alpha, beta). */
 int pfmp_axpby(pfmp_ctx *ctx, const double alpha[2], const void *x, const double beta[2], void *y);
+/* out = in converted between the internal FP64 and FP32 spinor fields of one parity
+ * (prec_in, prec_out each PFMP_F64 or PFMP_F32; round to nearest into FP32).  in and
+ * out must not overlap unless prec_in == prec_out, which copies. */
+int pfmp_convert_spinor(pfmp_ctx *ctx, const void *in, int prec_in, void *out, int prec_out);
 
 /* ---- forces (paper App. C) and integrator updates (App. B) ------------------ */
 

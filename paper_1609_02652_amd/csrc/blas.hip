@@ -76,6 +76,13 @@ __global__ void k_axpby(long n, double2 al, const double2 *__restrict__ x, doubl
 
 }  // namespace
 
+template <typename A, typename B>
+__global__ void k_convert(long n, const A *__restrict__ x, B *__restrict__ y)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) y[t] = mk<B>((decltype(B::x))x[t].x, (decltype(B::x))x[t].y);
+}
+
 int launch_dot(pfmp_ctx *ctx, const double2 *a, const double2 *b, long n, double *partials)
 {
     hipLaunchKernelGGL(k_dot, dim3(ctx->nblk_red), dim3(kRedBlock), 0, ctx->stream, a, b, n, partials);
@@ -126,6 +133,24 @@ extern "C" int pfmp_axpby(pfmp_ctx *ctx, const double alpha[2], const void *x, c
     hipLaunchKernelGGL(k_axpby, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n,
                        make_double2(alpha[0], alpha[1]), (const double2 *)x, make_double2(beta[0], beta[1]),
                        (double2 *)y);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+extern "C" int pfmp_convert_spinor(pfmp_ctx *ctx, const void *in, int prec_in, void *out, int prec_out)
+{
+    if (!ctx || !in || !out) return ctx ? set_err(ctx, PFMP_ERR_ARG, "convert_spinor: null") : PFMP_ERR_ARG;
+    const bool ok_in = prec_in == PFMP_F64 || prec_in == PFMP_F32, ok_out = prec_out == PFMP_F64 || prec_out == PFMP_F32;
+    if (!ok_in || !ok_out) return set_err(ctx, PFMP_ERR_ARG, "convert_spinor: FP64 or FP32 fields only");
+    long n = 12L * ctx->g.Vh;
+    dim3 grid(nblocks(n, 256)), block(256);
+    if (prec_in == PFMP_F64 && prec_out == PFMP_F32)
+        hipLaunchKernelGGL((k_convert<double2, float2>), grid, block, 0, ctx->stream, n, (const double2 *)in, (float2 *)out);
+    else if (prec_in == PFMP_F32 && prec_out == PFMP_F64)
+        hipLaunchKernelGGL((k_convert<float2, double2>), grid, block, 0, ctx->stream, n, (const float2 *)in, (double2 *)out);
+    else
+        HIPCHK(ctx, hipMemcpyAsync(out, in, n * (prec_in == PFMP_F64 ? sizeof(double2) : sizeof(float2)),
+                                   hipMemcpyDeviceToDevice, ctx->stream));
     LAUNCHCHK(ctx);
     return 0;
 }

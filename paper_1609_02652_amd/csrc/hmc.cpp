@@ -137,13 +137,14 @@ int msolve(Ctx &X, int op, const std::vector<cd> &z, const void *b, std::vector<
     return rc;
 }
 
-int applyM(Ctx &X, int op, int dag, const void *in, void *out)
+int applyM(Ctx &X, int op, int dag, const void *in, void *out, int prec = PFMP_F64)
 {
     X.mhalf += 1;
-    return pfmp_apply_M(X.c, op, dag, in, out, PFMP_F64);
+    return pfmp_apply_M(X.c, op, dag, in, out, prec);
 }
 
-int poly(Ctx &X, int op, const std::vector<cd> &roots, cd norm, const void *in, void *out, void *const *chain)
+int poly(Ctx &X, int op, const std::vector<cd> &roots, cd norm, const void *in, void *out, void *const *chain,
+         int prec = PFMP_F64)
 {
     std::vector<double> r(2 * roots.size());
     for (size_t k = 0; k < roots.size(); k++) {
@@ -152,8 +153,11 @@ int poly(Ctx &X, int op, const std::vector<cd> &roots, cd norm, const void *in, 
     }
     double nm[2] = {norm.real(), norm.imag()};
     X.mhalf += 2 * (long long)roots.size();
-    return pfmp_apply_poly(X.c, op, (int)roots.size(), r.data(), nm, in, out, chain, PFMP_F64);
+    return pfmp_apply_poly(X.c, op, (int)roots.size(), r.data(), nm, in, out, chain, prec);
 }
+
+// the mixed-precision and learned modes (every solve to the same FP64 residual)
+bool low_precision_mode(const Ctx &X) { return X.sp->solver_prec != PFMP_F64 || X.sp->ptnet; }
 
 cd dot(Ctx &X, const void *a, const void *b, int &rc)
 {
@@ -294,6 +298,34 @@ int term_force(Ctx &X, const pfmp_term &t, const void *phi, double eps, double *
         for (int k = 0; k < n - 1; k++) {
             re[k] = std::conj(z[k]);
             rc_[k] = z[n - 1 - k];
+        }
+        if (low_precision_mode(X)) {
+            // the chains and their Mhat images in FP32 (FP32 links and clover), widened to
+            // FP64 for the force kernels; the filter action stays FP64
+            std::vector<void *> E32(n), C32(n);
+            for (int k = 0; k < n; k++) {
+                E32[k] = pool_get(ctx, kChain + 4 * n + k);
+                C32[k] = pool_get(ctx, kChain + 5 * n + k);
+                if (!E32[k] || !C32[k]) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+            }
+            void *phi32 = pool_get(ctx, kChain + 6 * n), *w32 = pool_get(ctx, kChain + 6 * n + 1);
+            if (!phi32 || !w32) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+            if ((rc = pfmp_convert_spinor(ctx, phi, PFMP_F64, phi32, PFMP_F32))) return rc;
+            if ((rc = poly(X, t.op, re, 1.0, phi32, E32[n - 1], E32.data(), PFMP_F32))) return rc;
+            if ((rc = poly(X, t.op, rc_, a, phi32, C32[n - 1], C32.data(), PFMP_F32))) return rc;
+            for (int k = 0; k < n; k++) {
+                if ((rc = pfmp_convert_spinor(ctx, E32[k], PFMP_F32, E[k], PFMP_F64))) return rc;
+                if ((rc = pfmp_convert_spinor(ctx, C32[k], PFMP_F32, C[k], PFMP_F64))) return rc;
+            }
+            for (int i = 1; i <= n; i++) {
+                if ((rc = applyM(X, t.op, 0, E32[i - 1], w32, PFMP_F32))) return rc;
+                if ((rc = pfmp_convert_spinor(ctx, w32, PFMP_F32, WE[i - 1], PFMP_F64))) return rc;
+                if ((rc = applyM(X, t.op, 0, C32[n - i], w32, PFMP_F32))) return rc;
+                if ((rc = pfmp_convert_spinor(ctx, w32, PFMP_F32, WC[i - 1], PFMP_F64))) return rc;
+                pair(WE[i - 1], C[n - i], eps);
+                pair(WC[i - 1], E[i - 1], eps);
+            }
+            return pfmp_fermion_force(ctx, t.op, (int)XX.size(), XX.data(), YY.data(), cc.data(), 0, F);
         }
         if ((rc = poly(X, t.op, re, 1.0, phi, E[n - 1], E.data()))) return rc;       // E[k] = eta_{k+1}
         if ((rc = poly(X, t.op, rc_, a, phi, C[n - 1], C.data()))) return rc;        // C[k] = chi_{n-k}

@@ -149,6 +149,7 @@ def load():
         "pfmp_cg_multishift": [vp, i, i, vp, vp, vp, vp, vp],
         "pfmp_dot": [vp, vp, vp, vp],
         "pfmp_axpby": [vp, vp, vp, vp, vp],
+        "pfmp_convert_spinor": [vp, vp, i, vp, i],
         "pfmp_logdet_action": [vp, i, vp],
         "pfmp_apply_poly": [vp, i, i, vp, vp, vp, vp, vp, i],
         "pfmp_fermion_force": [vp, i, i, vp, vp, vp, i, vp],
@@ -490,16 +491,21 @@ class Lattice:
         self._chk(self.lib.pfmp_axpby(self.h, a, _ptr(x), b, _ptr(y)), "axpby")
         return y
 
+    def convert_spinor(self, x, prec_in, prec_out, out=None):
+        out = self.field(FIELD_SPINOR, prec_out, zero=False) if out is None else out
+        self._chk(self.lib.pfmp_convert_spinor(self.h, _ptr(x), prec_in, _ptr(out), prec_out), "convert_spinor")
+        return out
+
     # ---------------------------------------------------------------- polynomial
-    def apply_poly(self, op, roots, norm, x, out=None, chain=None):
+    def apply_poly(self, op, roots, norm, x, out=None, chain=None, prec=F64):
         n = len(roots)
         r = _darr([v for z in roots for v in (complex(z).real, complex(z).imag)]) if n else None
         nm = _darr([complex(norm).real, complex(norm).imag])
-        out = self.field(zero=False) if out is None else out
+        out = self.field(FIELD_SPINOR, prec, zero=False) if out is None else out
         ch = None
         if chain is not None:
             ch = (ctypes.c_void_p * n)(*[c.data_ptr() for c in chain])
-        self._chk(self.lib.pfmp_apply_poly(self.h, op, n, r, nm, _ptr(x), _ptr(out), ch, F64), "apply_poly")
+        self._chk(self.lib.pfmp_apply_poly(self.h, op, n, r, nm, _ptr(x), _ptr(out), ch, prec), "apply_poly")
         return out
 
     # ---------------------------------------------------------------- forces and updates

@@ -54,6 +54,32 @@ def test_apply_poly_and_chain(setup):
     assert rel(lat.spinor_numpy(out2), ops[1].poly(zc, 1.0, psi)) < 1e-12
 
 
+def test_apply_poly_fp32_error(setup):
+    """FP32 filter with its chain: error against the FP64 oracle stated, at the FP32
+    rounding level of a degree-6 product."""
+    from paper_1609_02652_amd import pfmp
+    from paper_1609_02652_amd.pfmp import F32
+    dims, U, lat, ops = setup
+    z, a = pfmp.chebyshev(6, 1.2, 0.9)
+    psi = synth.gaussian_spinor(lat.Vh, 21)
+    f = lat.pack_spinor(psi, prec=F32)
+    chain = [lat.field(prec=F32) for _ in range(6)]
+    out = lat.apply_poly(0, z, a, f, chain=chain, prec=F32)
+    e = rel(lat.spinor_numpy(out, prec=F32), ops[0].poly(z, a, psi))
+    print("fp32 P(K) rel err", e)
+    assert e < 1e-5
+    v = a * psi
+    for k in range(6):
+        assert rel(lat.spinor_numpy(chain[k], prec=F32), v) < 1e-5
+        v = ops[0].K(v) - z[k] * v
+    # widening to FP64 is exact; narrowing rounds to nearest
+    from paper_1609_02652_amd.pfmp import F64
+    w = lat.convert_spinor(out, F32, F64)
+    assert np.array_equal(lat.spinor_numpy(w), lat.spinor_numpy(out, prec=F32))
+    n32 = lat.convert_spinor(lat.pack_spinor(psi), F64, F32)
+    assert np.array_equal(lat.spinor_numpy(n32, prec=F32), psi.astype(np.complex64).astype(np.complex128))
+
+
 @pytest.mark.parametrize("op", [0, 1])
 def test_fermion_force(setup, op):
     dims, U, lat, ops = setup

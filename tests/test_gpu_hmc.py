@@ -149,19 +149,25 @@ def _run(lat_U, sp_kw, P0, etas, u):
 
 
 def test_batched_and_mixed_solves_in_trajectory(U0):
-    """The ratio and heavy solves due at the same merged step as one multi-RHS solve,
-    and FP32 / FP16 inner solves with FP64 reliable updates, give the FP64
-    single-RHS trajectory up to the solver tolerance."""
+    """The ratio and heavy solves due at the same merged step as one multi-RHS solve
+    give the FP64 single-RHS trajectory up to the solver tolerance.  The FP32 / FP16
+    modes (inner solves with FP64 reliable updates to the same residual, filter-term
+    force chains in FP32) give it up to the FP32 rounding of that force; their
+    actions, dH and accept stay FP64."""
     from paper_1609_02652_amd.pfmp import F32, F16
     P0 = synth.gaussian_momenta(256, 103)
     etas = [synth.gaussian_spinor(128, 50 + j) for j in range(3)]
     ref, Uref = _run(U0, {}, P0, etas, 0.0)
-    for kw in (dict(batch=True), dict(solver_prec=F32), dict(solver_prec=F16)):
+    # FP32 filter forces (relative error ~1e-7) move the end point by ~1e-8 in the links
+    # and dH, a difference of Hamiltonians of size ~1e3 here, by a few 1e-6
+    for kw, tol_dh, tol_u in ((dict(batch=True), 1e-8, 1e-9), (dict(solver_prec=F32), 2e-5, 1e-6),
+                              (dict(solver_prec=F16), 2e-5, 1e-6)):
         st, Ug = _run(U0, kw, P0, etas, 0.0)
-        print(kw, "dH %.12f vs %.12f, iters %d vs %d" % (st["dH"], ref["dH"], st["solver_iters"],
-                                                          ref["solver_iters"]), flush=True)
-        assert abs(st["dH"] - ref["dH"]) < 1e-8
-        assert np.max(np.abs(Ug - Uref)) < 1e-9
+        du = np.max(np.abs(Ug - Uref))
+        print(kw, "dH %.12f vs %.12f, iters %d vs %d, max |dU| %.2e" % (st["dH"], ref["dH"], st["solver_iters"],
+                                                                      ref["solver_iters"], du), flush=True)
+        assert abs(st["dH"] - ref["dH"]) < tol_dh
+        assert du < tol_u
 
 
 def test_trajectory_det_on_own_scale_matches_oracle(U0):
