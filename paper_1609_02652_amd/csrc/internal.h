@@ -38,17 +38,20 @@ template <typename C> PFMP_HD C cscale(C a, decltype(C::x) s) { return mk<C>(a.x
 template <typename C> PFMP_HD C ctimesi(C a) { return mk<C>(-a.y, a.x); }     // i a
 template <typename C> PFMP_HD C ctimesmi(C a) { return mk<C>(a.y, -a.x); }    // -i a
 template <typename C> PFMP_HD C cneg(C a) { return mk<C>(-a.x, -a.y); }
-// acc += a * b
+// fused multiply-add a b + c (one rounding)
+PFMP_HD double fmadd(double a, double b, double c) { return fma(a, b, c); }
+PFMP_HD float fmadd(float a, float b, float c) { return fmaf(a, b, c); }
+// acc += a * b as four fused multiply-adds
 template <typename C> PFMP_HD void cfma(C &acc, C a, C b)
 {
-    acc.x += a.x * b.x - a.y * b.y;
-    acc.y += a.x * b.y + a.y * b.x;
+    acc.x = fmadd(-a.y, b.y, fmadd(a.x, b.x, acc.x));
+    acc.y = fmadd(a.y, b.x, fmadd(a.x, b.y, acc.y));
 }
 // acc += conj(a) * b
 template <typename C> PFMP_HD void cfmac(C &acc, C a, C b)
 {
-    acc.x += a.x * b.x + a.y * b.y;
-    acc.y += a.x * b.y - a.y * b.x;
+    acc.x = fmadd(a.y, b.y, fmadd(a.x, b.x, acc.x));
+    acc.y = fmadd(-a.y, b.x, fmadd(a.x, b.y, acc.y));
 }
 
 // ------------------------------------------------------------------ geometry

@@ -25,8 +25,9 @@ PFMP_HD M3 m3_mul(const M3 &a, const M3 &b)
     M3 r;
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) {
-            double2 s = make_double2(0, 0);
-            for (int k = 0; k < 3; k++) cfma(s, a.e[3 * i + k], b.e[3 * k + j]);
+            double2 s = cmul(a.e[3 * i], b.e[j]);
+            cfma(s, a.e[3 * i + 1], b.e[3 + j]);
+            cfma(s, a.e[3 * i + 2], b.e[6 + j]);
             r.e[3 * i + j] = s;
         }
     return r;
@@ -37,8 +38,9 @@ PFMP_HD M3 m3_mul_nd(const M3 &a, const M3 &b)
     M3 r;
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) {
-            double2 s = make_double2(0, 0);
-            for (int k = 0; k < 3; k++) cfma(s, a.e[3 * i + k], cconj(b.e[3 * j + k]));
+            double2 s = cmul(a.e[3 * i], cconj(b.e[3 * j]));
+            cfma(s, a.e[3 * i + 1], cconj(b.e[3 * j + 1]));
+            cfma(s, a.e[3 * i + 2], cconj(b.e[3 * j + 2]));
             r.e[3 * i + j] = s;
         }
     return r;
@@ -49,8 +51,9 @@ PFMP_HD M3 m3_mul_dn(const M3 &a, const M3 &b)
     M3 r;
     for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) {
-            double2 s = make_double2(0, 0);
-            for (int k = 0; k < 3; k++) cfmac(s, a.e[3 * k + i], b.e[3 * k + j]);
+            double2 s = cmulc(a.e[i], b.e[j]);
+            cfmac(s, a.e[3 + i], b.e[3 + j]);
+            cfmac(s, a.e[6 + i], b.e[6 + j]);
             r.e[3 * i + j] = s;
         }
     return r;
