@@ -229,8 +229,11 @@ int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int op, int n, const void *c
 int pfmp_ptnet_train(pfmp_ctx *ctx, double *W, int op, int n, const void *const *r, const void *const *e,
                      int steps, double lr, double *losses);
 /* Flexible CG on Khat (Notay 2000 with one direction kept, Polak-Ribiere beta) with N as
- * preconditioner; W = NULL uses the identity (then it is CG).  Stops on the FP64 true
- * residual |b - Khat x| <= tol |b|, like pfmp_cg_solve. */
+ * preconditioner; W = NULL uses the identity (then it is CG).  Plain CG is the fallback:
+ * a step whose <N(r), r> <= 0 takes z = r, and when |r| has not halved within 100
+ * iterations the rest of the solve is plain CG from the current iterate.  Stops on the
+ * FP64 true residual |b - Khat x| <= tol |b|, like pfmp_cg_solve; stats->reliable_updates
+ * counts the plain-CG steps. */
 int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void *b, void *x, const pfmp_solver_params *p,
                    pfmp_solver_stats *st);
 /* CG on Khat that copies (x_k, r_k) at the iterations snap_iters (ascending) into the

@@ -956,8 +956,9 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
     LAUNCHCHK(ctx);
     // z = N(r) (or r), rz = <z, r>, p = z (or the fallback p = r)
     double *dots = nullptr;   // the second layer's <z, r>, <z, q> partials (in the iterations)
+    bool use_net = W != nullptr;
     auto precondition = [&]() -> int {
-        if (W) {
+        if (use_net) {
             hipLaunchKernelGGL(k_pt_l1, pgrid, pblock, 0, ctx->stream, g, ctx->Uf, r, 0.f, w.W, (float2 *)nullptr,
                                w.G, (const double *)fs);
             hipLaunchKernelGGL(k_pt_l2, pgrid, pblock, 0, ctx->stream, g, ctx->Uf, r, 0.f, w.W, w.G, 0.0, z,
@@ -994,7 +995,7 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
 #undef FHOP4
         hipLaunchKernelGGL(k_f_norm, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, fs);
         LAUNCHCHK(ctx);
-        if (W) {
+        if (use_net) {
             // z = N(r) with the <z, r>, <z, q> partials, then beta and p in one launch
             dots = part_b;
             e = precondition();
@@ -1011,22 +1012,44 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
         LAUNCHCHK(ctx);
         return 0;
     };
-    std::vector<uint64_t> key;
-    key_add(key, 4);   // flexible-CG iteration
-    key_geom(key, g);
-    for (const void *ptr : {(const void *)p, (const void *)T, (const void *)t, (const void *)q, (const void *)x,
-                            (const void *)r, (const void *)z, (const void *)part_a, (const void *)part_b,
-                            (const void *)fs, (const void *)ctx->U, (const void *)ctx->Uf, (const void *)s.clov[0],
-                            (const void *)s.clov[1], (const void *)(W ? w.W : nullptr), (const void *)w.G})
-        key_add(key, ptr);
-    key_add(key, mk2);
-    key_add(key, (int)cl);
+    auto make_key = [&](bool net) {
+        std::vector<uint64_t> key;
+        key_add(key, 4);   // flexible-CG iteration
+        key_geom(key, g);
+        for (const void *ptr : {(const void *)p, (const void *)T, (const void *)t, (const void *)q, (const void *)x,
+                                (const void *)r, (const void *)z, (const void *)part_a, (const void *)part_b,
+                                (const void *)fs, (const void *)ctx->U, (const void *)ctx->Uf,
+                                (const void *)s.clov[0], (const void *)s.clov[1],
+                                (const void *)(net ? w.W : nullptr), (const void *)(net ? w.G : nullptr)})
+            key_add(key, ptr);
+        key_add(key, mk2);
+        key_add(key, (int)cl);
+        return key;
+    };
+    // Plain CG stays the fallback of the whole solve: when the network has not cut
+    // |r| by 2 within kFcgStall iterations, the solve goes on as plain CG from the
+    // current iterate (p = r), so a poor network costs at most kFcgStall iterations
+    // more than the plain method from there.
+    constexpr int kFcgStall = 100;
+    double rr_ref = -1, it_ref = 0, it_switch = -1;
     for (;;) {
-        if ((rc = graph_run(ctx, key, chunk, iteration))) return rc;
+        if ((rc = graph_run(ctx, make_key(use_net), chunk, iteration))) return rc;
         HIPCHK(ctx, hipMemcpyAsync(ctx->red_host, fs, sizeof(double) * F_NSLOT, hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
         for (int k = 0; k < F_NSLOT; k++) h[k] = ctx->red_host[k];
         if (h[F_DONE] != 0) break;
+        if (!use_net) continue;
+        if (rr_ref < 0 || h[F_RN2] < 0.25 * rr_ref) {
+            rr_ref = h[F_RN2];
+            it_ref = h[F_ITER];
+        } else if (h[F_ITER] - it_ref >= kFcgStall) {
+            use_net = false;
+            it_switch = h[F_ITER];
+            hipLaunchKernelGGL(k_f_dots, dim3(ndot), dim3(kBlock), 0, ctx->stream, n, r, r, r, fs, part_b);
+            hipLaunchKernelGGL(k_f_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, ndot, 1, fs);
+            hipLaunchKernelGGL(k_f_update_p, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, r, r, p, fs);
+            LAUNCHCHK(ctx);
+        }
     }
     // FP64 true residual
     if ((rc = op_apply_K(ctx, op, x, q, t, T, nullptr))) return rc;
@@ -1040,7 +1063,8 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
     auto t1 = std::chrono::steady_clock::now();
     if (st) {
         st->iters = (int)h[F_ITER];
-        st->reliable_updates = (int)h[F_NFB];   // plain-CG fallback steps of the flexible CG
+        // plain-CG steps: the per-step fallbacks and every step after a switch to plain CG
+        st->reliable_updates = (int)h[F_NFB] + (it_switch >= 0 ? (int)(h[F_ITER] - it_switch) : 0);
         st->true_res = bn > 0 ? tr / bn : 0;
         st->seconds = std::chrono::duration<double>(t1 - t0).count();
         st->kmults = (int)h[F_ITER] + 1;
