@@ -349,6 +349,9 @@ def main():
     ap.add_argument("--therm", type=int, default=20, help="quenched thermalisation trajectories")
     ap.add_argument("--roofline-only", action="store_true",
                     help="time only the hopping kernels and a plain copy (for counter runs)")
+    ap.add_argument("--trajectory-only", choices=["f64", "f32", "f16"],
+                    help="thermalise, then run --warmup and --steps trajectories in one solver precision and "
+                         "print their times (for kernel profiles of one trajectory)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -357,7 +360,20 @@ def main():
         roofline_only(max(args.steps, 10))
         return
     from paper_1609_02652_amd import synth
-    from paper_1609_02652_amd.pfmp import F64, Lattice
+    from paper_1609_02652_amd.pfmp import F64, F32, F16, Lattice
+    if args.trajectory_only:
+        lat = Lattice(DIMS)
+        lat.set_gauge(synth.random_gauge(DIMS, seed=0))
+        thermalise(lat, args.therm)
+        lat.set_operator(0, KAPPA, CSW)
+        lat.set_operator(1, KAPPA_H, CSW)
+        log("autotune: %s" % lat.autotune(0))
+        sp = pfmp_spec(lat, solver_prec={"f64": F64, "f32": F32, "f16": F16}[args.trajectory_only])
+        t, sts = run_trajectories(lat, sp, args.steps, args.warmup, 100)
+        lat.close()
+        print(json.dumps({"trajectory_only": args.trajectory_only, "s_per_traj": round(t, 4),
+                          "kmults": [s["kmults"] for s in sts], "dH": [round(s["dH"], 5) for s in sts]}), flush=True)
+        return
     log("bench: building inputs", DIMS)
     lat = Lattice(DIMS)
     lat.set_gauge(synth.random_gauge(DIMS, seed=0))
@@ -380,7 +396,6 @@ def main():
     chosen_prec = min(times, key=times.get)
 
     # ---- trajectories: plain FP64 form, then the chosen form (timed value)
-    from paper_1609_02652_amd.pfmp import F32, F16
     sp_plain = pfmp_spec(lat)
     if chosen_prec == "learned":
         sp_chosen = pfmp_spec(lat, ptnet=W_net)
