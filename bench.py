@@ -69,7 +69,21 @@ def time_kernel(lat, fn, reps):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def hop_roofline(dims, U, reps=200):
+def batch_apply(lat, reps=20):
+    """Khat for the Hasenbusch chain's three operators plus a second source of the first
+    (4 right-hand sides) as one multi-RHS launch per stage, against 4 single-RHS Khat:
+    the time per right-hand side relative to a single one."""
+    from paper_1609_02652_amd import synth
+    lat.set_operator(2, 0.1250, CSW)
+    xs = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 40 + k)) for k in range(4)]
+    outs = [lat.field() for _ in range(4)]
+    t1 = time_kernel(lat, lambda: lat.apply_MdagM(0, xs[0], out=outs[0]), reps)
+    t4 = time_kernel(lat, lambda: lat.apply_MdagM_batch([0, 1, 2, 0], xs, outs), reps)
+    return {"nrhs": 4, "single_K_us": round(t1 * 1e6, 1), "batch_K_us": round(t4 * 1e6, 1),
+            "per_rhs_vs_single": round(t4 / 4 / t1, 3)}
+
+
+def hop_roofline(dims, U, reps=200, extra=None):
     """The plain FP64 hop D_oe and Mhat after autotuning, timed with HIP events on the
     library stream.  bytes_hop counts the bytes the hop kernel must move per output
     site: 8 links (12 reals each when the third row is rebuilt, else 18) plus the
@@ -89,9 +103,10 @@ def hop_roofline(dims, U, reps=200):
     link_reals = 12 if lat.link_reconstruct() else 18
     bytes_plain = lat.Vh * (8 * link_reals + 24 + 24) * 8
     bytes_m = lat.Vh * (2 * (8 * link_reals + 24 + 24) + 72 * 2 + 24) * 8
+    more = extra(lat) if extra else None
     lat.close()
     return {"t_hop": t_plain, "bytes_hop": bytes_plain, "t_M": t_m, "bytes_M": bytes_m, "Vh": lat.Vh,
-            "link_reals": link_reals, "tune": tune}
+            "link_reals": link_reals, "tune": tune, "extra": more}
 
 
 def pmc_traffic(lattice):
@@ -426,7 +441,9 @@ def main():
     small = roof_entry(DIMS, hop_roofline(DIMS, U))
     big = (32, 32, 32, 64)
     try:
-        main_e = roof_entry(big, hop_roofline(big, synth.random_gauge(big, seed=5), reps=50))
+        rb = hop_roofline(big, synth.random_gauge(big, seed=5), reps=50, extra=batch_apply)
+        main_e = roof_entry(big, rb)
+        batched["apply_32x32x32x64"] = rb["extra"]
     except Exception as e:  # noqa: BLE001 -- report, do not hide
         main_e = dict(small, error_32x32x32x64=str(e))
     roof = {"kernel": "hop D_oe, FP64 (k_hop_clovinv, plain), %s" % main_e["lattice"], "bound": "hbm",

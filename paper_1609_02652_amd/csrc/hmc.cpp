@@ -478,7 +478,46 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
         for (int j = 0; j < nt; j++) st->nforce[j] = 0;
         st->nforce_det = 0;
     }
+    // A merged step whose only force is the gauge force (the finest scale between fermion
+    // force steps) is T then P -= eps F_G, with the gauge force added straight into P: the
+    // coefficients of -F_G are exactly the negated coefficients of F_G, so this equals the
+    // force buffer route bit for bit.  A run of such steps is replayed as one HIP graph
+    // (keyed by its step sizes); the links' derived fields are marked stale after it.
+    const bool det_on_gauge_row = sp->det_op >= 0 && !det_row;
+    auto gauge_only = [&](int k) {
+        if (So[k] == 0.0 || det_on_gauge_row) return false;
+        for (int j = 1; j < nrow; j++)
+            if (So[(size_t)j * cap + k] != 0.0) return false;
+        return true;
+    };
     for (int k = 0; k < nout; k++) {
+        if (gauge_only(k)) {
+            int k2 = k;
+            while (k2 + 1 < nout && gauge_only(k2 + 1)) k2++;
+            std::vector<uint64_t> key;
+            key_add(key, 6);   // run of gauge-only merged steps
+            key_geom(key, ctx->g);
+            key_add(key, (const void *)ctx->U);
+            key_add(key, (const void *)P);
+            key_add(key, sp->beta);
+            for (int q = k; q <= k2; q++) {
+                key_add(key, tick * (double)To[q]);
+                key_add(key, So[q]);
+            }
+            auto run = [&]() -> int {
+                int e;
+                for (int q = k; q <= k2; q++) {
+                    if (To[q] != 0 && (e = pfmp_update_gauge(ctx, tick * (double)To[q], P))) return e;
+                    if ((e = pfmp_gauge_force(ctx, -sp->beta * So[q], P))) return e;
+                }
+                return 0;
+            };
+            if ((rc = graph_run(ctx, key, 1, run))) return rc;
+            if ((rc = rebuild_gauge_derived(ctx))) return rc;
+            if (st) st->nforce[0] += k2 - k + 1;
+            k = k2;
+            continue;
+        }
         if (To[k] != 0 && (rc = pfmp_update_gauge(ctx, tick * (double)To[k], P))) return rc;
         bool any = false;
         for (int j = 0; j < nrow; j++) any = any || So[(size_t)j * cap + k] != 0.0;

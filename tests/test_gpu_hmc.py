@@ -187,3 +187,27 @@ def test_trajectory_det_on_own_scale_matches_oracle(U0):
     assert st["nforce"] + [st["nforce_det"]] == ref["nforce"]
     assert abs(st["dH"] - ref["dH"]) < 1e-7
     lat.close()
+
+
+def test_gauge_step_graphs_match_launches(U0):
+    """Runs of gauge-only merged steps replayed as HIP graphs (S_det on its own scale, so
+    the finest scale carries the gauge force alone) give the trajectory of the same
+    launches issued one by one, bit for bit, over two trajectories in a row."""
+    P0 = synth.gaussian_momenta(256, 105)
+    etas = [synth.gaussian_spinor(128, 70 + j) for j in range(2)]
+    terms = [dict(kind="poly", op=1, n=4, mu=1.2, nu=0.9, steps=10), dict(kind="ratio", op=1, op2=0, steps=5)]
+    res = []
+    for graphs in (True, False):
+        lat = make_lattice(U0)
+        lat.graphs(graphs)
+        sp = lat.spec(BETA, terms, 40, det_op=0, tol=1e-12, exact_start=True, det_steps=10)
+        out = []
+        for rep in range(2):
+            st = lat.trajectory(sp, lat.pack_momenta(P0), [lat.pack_spinor(e) for e in etas], 0.0)
+            out.append((st["dH"], st["nforce"], lat.get_gauge().cpu().numpy()))
+        lat.close()
+        res.append(out)
+    for (dh_g, nf_g, U_g), (dh_l, nf_l, U_l) in zip(*res):
+        print("graphs dH %.15f, launches dH %.15f, nforce %s" % (dh_g, dh_l, nf_g), flush=True)
+        assert dh_g == dh_l and nf_g == nf_l
+        assert np.array_equal(U_g, U_l)
