@@ -233,6 +233,10 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
     if ((rc = launch_norm2(ctx, b, n, ctx->red))) return rc;
     if ((rc = red_finish(ctx, ctx->red, ctx->nblk_red, 1, &bb))) return rc;
     const double tol2bb = prm->tol * prm->tol * bb;
+    if (bb == 0) {   // b = 0: x = 0 solves it exactly (and alpha would be 0 / 0)
+        if (st) *st = pfmp_solver_stats{};
+        return 0;
+    }
     // r = b, rs = (float) b, p = rs
     hipLaunchKernelGGL(k_m_residual, dim3(ctx->nblk_red), dim3(kRedBlock), 0, ctx->stream, n, b, Kx, rs, ctx->red);
     hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,

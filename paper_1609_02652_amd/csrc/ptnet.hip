@@ -949,6 +949,14 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
     const double mk2 = -s.kappa * s.kappa;
     dim3 pgrid(nblocks(4L * g.Vh, kBlock)), pblock(kBlock);
     HIPCHK(ctx, hipMemsetAsync(x, 0, vb, ctx->stream));
+    {
+        const double bn0 = host_norm(ctx, b, &rc);
+        if (rc) return rc;
+        if (bn0 == 0) {   // b = 0: x = 0 solves it exactly
+            if (st) *st = pfmp_solver_stats{};
+            return 0;
+        }
+    }
     HIPCHK(ctx, hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, ctx->stream));
     if ((rc = launch_norm2(ctx, b, n, ctx->red))) return rc;
     hipLaunchKernelGGL(k_f_init, dim3(1), dim3(kRedBlock), 0, ctx->stream, ctx->red, ctx->nblk_red,

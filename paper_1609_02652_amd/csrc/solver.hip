@@ -486,6 +486,14 @@ extern "C" int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const doubl
     HIPCHK(ctx, hipMemsetAsync(B.Kx, 0, vb, ctx->stream));
     ShiftRec *rec = (ShiftRec *)(ctx->scal + kShiftBase);
     if ((rc = launch_norm2(ctx, b, n, ctx->red))) return rc;
+    {
+        double bb0 = 0;
+        if ((rc = red_finish(ctx, ctx->red, ctx->nblk_red, 1, &bb0))) return rc;
+        if (bb0 == 0) {   // b = 0: every x_k = 0 solves it exactly
+            if (st) *st = pfmp_solver_stats{};
+            return 0;
+        }
+    }
     hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(kRedBlock), 0, ctx->stream, ctx->red, ctx->nblk_red,
                        prm->tol * prm->tol, prm->maxiter, ctx->scal);
     hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(PFMP_MAX_SHIFTS), 0, ctx->stream, nshift, zdev, rec);
