@@ -365,11 +365,11 @@ __global__ __launch_bounds__(kBlock) void k_gauge_force(Geom g, const double2 *_
             shifted(g, y, nu, sg, yn);
             shifted(g, ypm, nu, sg, ypmn);
             const int *a1 = side ? ypmn : ypm, *a3 = side ? yn : y;
-            M3 X1 = m3_dag_if(link_at(g, U, a1, nu), side);
-            M3 X3 = m3_dag_if(link_at(g, U, a3, nu), !side);
-            st = m3_add(st, m3_mul(X1, m3_mul_dn(link_at(g, U, yn, mu), X3)));
+            M3 X1 = m3_dag_if(link_at_su3(g, U, a1, nu), side);
+            M3 X3 = m3_dag_if(link_at_su3(g, U, a3, nu), !side);
+            st = m3_add(st, m3_mul(X1, m3_mul_dn(link_at_su3(g, U, yn, mu), X3)));
         }
-        lie_coeffs(m3_scale(m3_mul(link_at(g, U, y, mu), st), coef), f);
+        lie_coeffs(m3_scale(m3_mul(link_at_su3(g, U, y, mu), st), coef), f);
     }
 #pragma unroll
     for (int a = 0; a < 8; a++) f[a] += __shfl_xor(f[a], 1, 64);

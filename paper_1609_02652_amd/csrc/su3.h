@@ -160,6 +160,20 @@ __device__ __forceinline__ M3 link_at(const Geom &g, const double2 *__restrict__
     return r;
 }
 
+// As link_at, but when every link is in SU(3) (g.recon) only rows 1 and 2 are read and
+// row 3 is their conjugate cross product (for the kernels bound by their link gathers).
+__device__ __forceinline__ M3 link_at_su3(const Geom &g, const double2 *__restrict__ U, const int *c, int mu)
+{
+    if (!g.recon) return link_at(g, U, c, mu);
+    const double2 *b = U + ((long)(parity_of(c) * 4 + mu) * 9) * g.Vh + eo_index(g, c);
+    M3 r;
+    for (int k = 0; k < 6; k++) r.e[k] = b[(long)k * g.Vh];
+    r.e[6] = cconj(csub(cmul(r.e[1], r.e[5]), cmul(r.e[2], r.e[4])));
+    r.e[7] = cconj(csub(cmul(r.e[2], r.e[3]), cmul(r.e[0], r.e[5])));
+    r.e[8] = cconj(csub(cmul(r.e[0], r.e[4]), cmul(r.e[1], r.e[3])));
+    return r;
+}
+
 __device__ __forceinline__ void link_store(const Geom &g, double2 *__restrict__ U, int p, int i, int mu, const M3 &m)
 {
     double2 *b = U + ((long)(p * 4 + mu) * 9) * g.Vh + i;
