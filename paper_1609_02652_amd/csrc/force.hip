@@ -208,56 +208,52 @@ __global__ __launch_bounds__(kBlock) void k_logdet_insert(Geom g, const double *
     }
 }
 
-// Psi_mu_nu at the site with coordinates c, formed on load from the insertion field:
-// Psi = (Phi - Phi^dag) / 8 of the plane (min, max), with Psi_nu_mu = -Psi_mu_nu.
-// Returned as the base pointer of the 9 Phi elements and the scale +-1/8.
-__device__ __forceinline__ const double2 *psi_base(const Geom &g, const double2 *__restrict__ Phi, const int *c,
-                                                   int mu, int nu, double *sc)
-{
-    int p = parity_of(c), i = eo_index(g, c);
-    int a = mu < nu ? mu : nu, b = mu < nu ? nu : mu;
-    *sc = mu < nu ? 0.125 : -0.125;
-    return Phi + ((long)(p * 6 + plane_index(a, b)) * 9) * g.Vh + i;
-}
+// Psi = (Phi - Phi^dag) / 8 per parity, plane and site, packed as the 9 reals of an
+// anti-Hermitian 3x3 matrix: Im of the 3 diagonal entries, then Re, Im of entries
+// (0,1), (0,2), (1,2); layout ((p * 6 + plane) * 9 + k) * Vh + i.  Built once per
+// force evaluation, it halves (and packs) what the clover force reads per insertion.
+constexpr int kPsiReals = 9;
 
-__device__ __forceinline__ double2 psi_el(const double2 *__restrict__ b, long st, double sc, int r, int c)
+__global__ void k_psi_pack(Geom g, const double2 *__restrict__ Phi, double *__restrict__ Psi)
 {
-    return cscale(csub(b[(long)(3 * r + c) * st], cconj(b[(long)(3 * c + r) * st])), sc);
-}
-
-// Psi X, one row of Psi at a time
-__device__ __forceinline__ M3 psi_mul(const double2 *__restrict__ b, long st, double sc, const M3 &X)
-{
-    M3 r;
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 12L * g.Vh) return;
+    const long pp = t / g.Vh, i = t - pp * g.Vh;   // pp = parity * 6 + plane
+    const double2 *b = Phi + pp * 9 * g.Vh + i;
+    double *o = Psi + pp * kPsiReals * g.Vh + i;
+    const long st = g.Vh;
 #pragma unroll
-    for (int i = 0; i < 3; i++) {
-        double2 p0 = psi_el(b, st, sc, i, 0), p1 = psi_el(b, st, sc, i, 1), p2 = psi_el(b, st, sc, i, 2);
+    for (int d = 0; d < 3; d++) o[d * st] = 0.25 * b[(4 * d) * st].y;   // (Phi - Phi^*)_dd / 8 = i Im / 4
+    const int rc[3][2] = {{0, 1}, {0, 2}, {1, 2}};
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            double2 v = cmul(p0, X.e[k]);
-            cfma(v, p1, X.e[3 + k]);
-            cfma(v, p2, X.e[6 + k]);
-            r.e[3 * i + k] = v;
-        }
+    for (int q = 0; q < 3; q++) {
+        const double2 u = b[(3 * rc[q][0] + rc[q][1]) * st], l = b[(3 * rc[q][1] + rc[q][0]) * st];
+        o[(3 + 2 * q) * st] = 0.125 * (u.x - l.x);       // Re (Phi_rc - conj Phi_cr) / 8
+        o[(4 + 2 * q) * st] = 0.125 * (u.y + l.y);       // Im
     }
-    return r;
 }
 
-// X Psi, one column of Psi at a time
-__device__ __forceinline__ M3 mul_psi(const M3 &X, const double2 *__restrict__ b, long st, double sc)
+// Psi_mu_nu at the site with coordinates c as a 3x3 matrix, Psi_nu_mu = -Psi_mu_nu
+__device__ __forceinline__ M3 psi_at(const Geom &g, const double *__restrict__ Psi, const int *c, int mu, int nu)
 {
+    const int p = parity_of(c), i = eo_index(g, c);
+    const int a = mu < nu ? mu : nu, bb = mu < nu ? nu : mu;
+    const double sc = mu < nu ? 1.0 : -1.0;
+    const double *b = Psi + ((long)(p * 6 + plane_index(a, bb)) * kPsiReals) * g.Vh + i;
+    const long st = g.Vh;
+    double v[kPsiReals];
+#pragma unroll
+    for (int k = 0; k < kPsiReals; k++) v[k] = sc * b[k * st];
     M3 r;
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-        double2 p0 = psi_el(b, st, sc, 0, k), p1 = psi_el(b, st, sc, 1, k), p2 = psi_el(b, st, sc, 2, k);
-#pragma unroll
-        for (int i = 0; i < 3; i++) {
-            double2 v = cmul(X.e[3 * i], p0);
-            cfma(v, X.e[3 * i + 1], p1);
-            cfma(v, X.e[3 * i + 2], p2);
-            r.e[3 * i + k] = v;
-        }
-    }
+    r.e[0] = make_double2(0, v[0]);
+    r.e[4] = make_double2(0, v[1]);
+    r.e[8] = make_double2(0, v[2]);
+    r.e[1] = make_double2(v[3], v[4]);
+    r.e[3] = make_double2(-v[3], v[4]);   // Psi_10 = -conj(Psi_01)
+    r.e[2] = make_double2(v[5], v[6]);
+    r.e[6] = make_double2(-v[5], v[6]);
+    r.e[5] = make_double2(v[7], v[8]);
+    r.e[7] = make_double2(-v[7], v[8]);
     return r;
 }
 
@@ -272,13 +268,12 @@ __device__ __forceinline__ M3 mul_psi(const M3 &X, const double2 *__restrict__ b
 // Two lanes per link (the two sides s); the 8 coefficients of each leaf are
 // accumulated and the two lanes summed by a lane swap.
 __global__ __launch_bounds__(kBlock) void k_clover_force(Geom g, const double2 *__restrict__ U,
-                                                         const double2 *__restrict__ Phi, double *__restrict__ F)
+                                                         const double *__restrict__ Psi, double *__restrict__ F)
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const long l = t >> 1;
     const int side = (int)(t & 1);
     const bool ok = l < 8L * g.Vh;
-    const long st = g.Vh;
     double f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int mu = 0, p = 0, i = 0;
     if (ok) {
@@ -296,26 +291,20 @@ __global__ __launch_bounds__(kBlock) void k_clover_force(Geom g, const double2 *
             int yn[4], ypmn[4];
             shifted(g, y, nu, sg, yn);          // y + s nu
             shifted(g, ypm, nu, sg, ypmn);      // y + mu + s nu
-            double sc;
-            const double2 *b;
             // L1: y+mu -> y+mu+s nu
             M3 L1 = m3_dag_if(link_at(g, U, side ? ypmn : ypm, nu), side);
-            b = psi_base(g, Phi, ypm, mu, nu, &sc);
-            M3 Q = psi_mul(b, st, sc, L1);
-            b = psi_base(g, Phi, ypmn, mu, nu, &sc);
-            Q = m3_add(Q, mul_psi(L1, b, st, sc));
+            M3 Q = m3_mul(psi_at(g, Psi, ypm, mu, nu), L1);
+            Q = m3_add(Q, m3_mul(L1, psi_at(g, Psi, ypmn, mu, nu)));
             // L2: y+mu+s nu -> y+s nu
             M3 L2 = m3_dag(link_at(g, U, yn, mu));
             M3 R = m3_mul(L1, L2);
             Q = m3_mul(Q, L2);
-            b = psi_base(g, Phi, yn, mu, nu, &sc);
-            Q = m3_add(Q, mul_psi(R, b, st, sc));
+            Q = m3_add(Q, m3_mul(R, psi_at(g, Psi, yn, mu, nu)));
             // L3: y+s nu -> y
             M3 L3 = m3_dag_if(link_at(g, U, side ? yn : y, nu), !side);
             R = m3_mul(R, L3);
             Q = m3_mul(Q, L3);
-            b = psi_base(g, Phi, y, mu, nu, &sc);
-            Q = m3_add(Q, mul_psi(R, b, st, sc));
+            Q = m3_add(Q, m3_mul(R, psi_at(g, Psi, y, mu, nu)));
             // coefficients of s U_mu(y) Q
             double fl[8];
             lie_coeffs(m3_mul(link_at(g, U, y, mu), Q), fl);
@@ -483,8 +472,11 @@ __global__ __launch_bounds__(kBlock) void k_kinetic(long n, const double *__rest
 static int clover_force_add(pfmp_ctx *ctx, const double2 *Phi, double *F)
 {
     const Geom &g = ctx->g;
+    double *Psi = (double *)ws_alloc(ctx, sizeof(double) * 2L * 6 * kPsiReals * g.Vh, 17);
+    if (!Psi) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
+    hipLaunchKernelGGL(k_psi_pack, dim3(nblocks(12L * g.Vh, 256)), dim3(256), 0, ctx->stream, g, Phi, Psi);
     hipLaunchKernelGGL(k_clover_force, dim3(nblocks(16L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, ctx->U,
-                       Phi, F);
+                       Psi, F);
     LAUNCHCHK(ctx);
     return 0;
 }
