@@ -278,10 +278,50 @@ def batch_bench(lat, reps=3):
     return out
 
 
+def batched_force_bench():
+    """The Hasenbusch chain of the batched-force workload on 24^3 x 48 (kappa 0.1360,
+    0.1300, 0.1200, c_sw 1.6; heavy term on 0.1200 and ratio terms 0.1200/0.1300 and
+    0.1300/0.1360): one 2MN step of all three terms (three force evaluations, three CG
+    solves each to 1e-10, FP64), with the solves of each evaluation as one multi-RHS
+    batch against one after another.  Seeded start links (the timing does not need
+    thermalised ones)."""
+    import torch
+    from paper_1609_02652_amd import synth
+    from paper_1609_02652_amd.pfmp import Lattice
+    dims = (24, 24, 24, 48)
+    lat = Lattice(dims)
+    try:
+        lat.set_gauge(synth.random_gauge(dims, seed=0))
+        for k, kap in enumerate((0.1360, 0.1300, 0.1200)):
+            lat.set_operator(k, kap, CSW)
+        tune = lat.autotune(0)
+        terms = [dict(kind="heavy", op=2, steps=1), dict(kind="ratio", op=2, op2=1, steps=1),
+                 dict(kind="ratio", op=1, op2=0, steps=1)]
+        U0 = lat.get_gauge().clone()
+        phis = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 800 + j)) for j in range(3)]
+        out = {"lattice": "x".join(map(str, dims)), "nrhs": 3, "tuning": tune}
+        for batch in (False, True, False, True):
+            sp = lat.spec(5.8, terms, 1, det_op=-1, tau=0.02, batch=batch)
+            P = lat.pack_momenta(synth.gaussian_momenta(lat.V, 900))
+            lat.set_gauge(U0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = lat.md_evolve(sp, P, phis)
+            torch.cuda.synchronize()
+            key = "batched" if batch else "one_by_one"
+            out[key + "_s"] = round(time.perf_counter() - t0, 4)   # the second pass of each overwrites the first
+            out[key + "_solver_iters"] = st["solver_iters"]
+        out["speedup"] = round(out["one_by_one_s"] / out["batched_s"], 3)
+        lat.set_gauge(U0)
+        return out
+    finally:
+        lat.close()
+
+
 def learned_bench(lat, nsrc):
     """The learned preconditioner on Khat (kappa 0.1340): training vectors are
     residuals the solver itself produces (CG iterates 2, 6, 10, 14, 20, 30 of 4
-    solves) plus 8 Gaussian vectors; Adam (150 full-batch steps) on the
+    solves) plus 8 Gaussian vectors; Adam (300 full-batch steps) on the
     preconditioned-residual objective in the library's own forward / backward
     kernels; then flexible CG with the trained network on the benchmark sources to
     1e-10 (FP64 true residual), against plain FP64 CG on the same sources."""
@@ -403,6 +443,10 @@ def main():
     cg = cg_bench(lat, args.sources)
     lat.set_operator(2, 0.1250, CSW)
     batched = batch_bench(lat)
+    try:
+        batched["force_eval_24x24x24x48"] = batched_force_bench()
+    except Exception as e:  # noqa: BLE001 -- report, do not hide
+        batched["force_eval_24x24x24x48"] = {"error": str(e)}
     learned, W_net = learned_bench(lat, args.sources)
     cg["learned_fcg"] = learned
     cg["learned_gain_iters"] = round(1 - learned["fcg_iters"] / cg["f64"]["iters"], 3)
