@@ -1,10 +1,10 @@
 // hop.h -- device building blocks of the Wilson hopping term and the clover
 // apply, shared by the operator kernels and the fused solver kernels.
 //
-// One thread per output site.  For each of the 8 directions the neighbour spinor
-// is spin-projected to a half spinor (2 spins x 3 colours), multiplied by the link
-// (2 SU(3) mat-vecs instead of 4) and reconstructed into the 4-spinor accumulator.
-// Projectors in the chiral basis, g_mu = [[0, B],[C, 0]] with B = C^-1:
+// Two lanes per output site (see "two lanes per site" below).  For each of the 8
+// directions the neighbour spinor is spin-projected to a half spinor, multiplied by
+// the link and added back; projectors in the chiral basis, g_mu = [[0, B],[C, 0]]
+// with B = C^-1:
 //   (1 + s g_mu) psi = [h ; s C h],  h = psi_up + s B psi_low,   s = -1 (forward), +1 (backward)
 // with B = -i sigma_k, C = i sigma_k for k = x,y,z and B = C = 1 for t.
 // Neighbour indices come from the site coordinates (no index tables are read).
@@ -85,89 +85,6 @@ __device__ __forceinline__ void project(const C *p, C *h)
             h[3 + a] = S < 0 ? csub(p1, p3) : cadd(p1, p3);
         }
     }
-}
-
-// acc_up += w, acc_low += s C w
-template <int MU, int S, typename C>
-__device__ __forceinline__ void reconstruct(const C *w, C *acc)
-{
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        C w0 = w[a], w1 = w[3 + a];
-        acc[a] = cadd(acc[a], w0);
-        acc[3 + a] = cadd(acc[3 + a], w1);
-        if (MU == 0) {          // C w = (i w1, i w0)
-            acc[6 + a] = S < 0 ? csub(acc[6 + a], ctimesi(w1)) : cadd(acc[6 + a], ctimesi(w1));
-            acc[9 + a] = S < 0 ? csub(acc[9 + a], ctimesi(w0)) : cadd(acc[9 + a], ctimesi(w0));
-        } else if (MU == 1) {   // C w = (w1, -w0)
-            acc[6 + a] = S < 0 ? csub(acc[6 + a], w1) : cadd(acc[6 + a], w1);
-            acc[9 + a] = S < 0 ? cadd(acc[9 + a], w0) : csub(acc[9 + a], w0);
-        } else if (MU == 2) {   // C w = (i w0, -i w1)
-            acc[6 + a] = S < 0 ? csub(acc[6 + a], ctimesi(w0)) : cadd(acc[6 + a], ctimesi(w0));
-            acc[9 + a] = S < 0 ? cadd(acc[9 + a], ctimesi(w1)) : csub(acc[9 + a], ctimesi(w1));
-        } else {                // C w = w
-            acc[6 + a] = S < 0 ? csub(acc[6 + a], w0) : cadd(acc[6 + a], w0);
-            acc[9 + a] = S < 0 ? csub(acc[9 + a], w1) : cadd(acc[9 + a], w1);
-        }
-    }
-}
-
-// w = f * U h (DAG = 0) or f * U^dag h (DAG = 1) for the two spins of h
-template <int DAG, typename C>
-__device__ __forceinline__ void su3_half(const C *__restrict__ U, long stride, int site, const C *h,
-                                         decltype(C::x) f, C *w)
-{
-    C u[9];
-#pragma unroll
-    for (int k = 0; k < 9; k++) u[k] = U[k * stride + site];
-#pragma unroll
-    for (int s = 0; s < 2; s++)
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            C acc = mk<C>(0, 0);
-#pragma unroll
-            for (int b = 0; b < 3; b++) {
-                if (DAG) cfmac(acc, u[3 * b + a], h[3 * s + b]);
-                else cfma(acc, u[3 * a + b], h[3 * s + b]);
-            }
-            w[3 * s + a] = cscale(acc, f);
-        }
-}
-
-template <int MU, typename C, typename In>
-__device__ __forceinline__ void hop_dir(const Geom &g, int pout, int i, const int *c, const In in,
-                                        const C *__restrict__ U, decltype(C::x) gs, C *acc)
-{
-    using R = decltype(C::x);
-    const long Vh = g.Vh;
-    C p[12], h[6], w[6];
-    int sf, sb;
-    // forward: (1 - g_mu) U_mu(x) psi(x + mu)
-    int jf = eo_neighbour(g, c, MU, +1, &sf);
-    load_spinor(in, g.Vh, jf, gs, p);
-    project<MU, -1>(p, h);
-    su3_half<0>(U + ((long)(pout * 4 + MU) * 9) * Vh, Vh, i, h, (R)sf, w);
-    reconstruct<MU, -1>(w, acc);
-    // backward: (1 + g_mu) U_mu(x - mu)^dag psi(x - mu)
-    int jb = eo_neighbour(g, c, MU, -1, &sb);
-    load_spinor(in, g.Vh, jb, gs, p);
-    project<MU, +1>(p, h);
-    su3_half<1>(U + ((long)((1 - pout) * 4 + MU) * 9) * Vh, Vh, jb, h, (R)sb, w);
-    reconstruct<MU, +1>(w, acc);
-}
-
-template <typename C, typename In>
-__device__ __forceinline__ void hop_all(const Geom &g, int pout, int i, const In in,
-                                        const C *__restrict__ U, decltype(C::x) gs, C *acc)
-{
-    int c[4];
-    eo_coords(g, pout, i, c);
-#pragma unroll
-    for (int k = 0; k < 12; k++) acc[k] = mk<C>(0, 0);
-    hop_dir<0, C>(g, pout, i, c, in, U, gs, acc);
-    hop_dir<1, C>(g, pout, i, c, in, U, gs, acc);
-    hop_dir<2, C>(g, pout, i, c, in, U, gs, acc);
-    hop_dir<3, C>(g, pout, i, c, in, U, gs, acc);
 }
 
 // ------------------------------------------------------------------ two lanes per site
