@@ -282,9 +282,10 @@ def batched_force_bench():
     """The Hasenbusch chain of the batched-force workload on 24^3 x 48 (kappa 0.1360,
     0.1300, 0.1200, c_sw 1.6; heavy term on 0.1200 and ratio terms 0.1200/0.1300 and
     0.1300/0.1360): one 2MN step of all three terms (three force evaluations, three CG
-    solves each to 1e-10, FP64), with the solves of each evaluation as one multi-RHS
-    batch against one after another.  Seeded start links (the timing does not need
-    thermalised ones)."""
+    solves each to 1e-10), with the solves of each evaluation as one multi-RHS batch
+    against one after another, in FP64 and in the mixed-precision mode (single solves:
+    FP16-storage CG with FP64 reliable updates; batches: FP32 batched passes inside FP64
+    residuals).  Seeded start links (the timing does not need thermalised ones)."""
     import torch
     from paper_1609_02652_amd import synth
     from paper_1609_02652_amd.pfmp import Lattice
@@ -300,18 +301,20 @@ def batched_force_bench():
         U0 = lat.get_gauge().clone()
         phis = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 800 + j)) for j in range(3)]
         out = {"lattice": "x".join(map(str, dims)), "nrhs": 3, "tuning": tune}
-        for batch in (False, True, False, True):
-            sp = lat.spec(5.8, terms, 1, det_op=-1, tau=0.02, batch=batch)
+        from paper_1609_02652_amd.pfmp import F64, F16
+        modes = {"f64_one_by_one": (F64, False), "f64_batched": (F64, True),
+                 "mixed_one_by_one": (F16, False), "mixed_batched": (F16, True)}
+        for name, (prec, batch) in list(modes.items()) * 2:   # the second pass of each is kept
+            sp = lat.spec(5.8, terms, 1, det_op=-1, tau=0.02, batch=batch, solver_prec=prec)
             P = lat.pack_momenta(synth.gaussian_momenta(lat.V, 900))
             lat.set_gauge(U0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             st = lat.md_evolve(sp, P, phis)
             torch.cuda.synchronize()
-            key = "batched" if batch else "one_by_one"
-            out[key + "_s"] = round(time.perf_counter() - t0, 4)   # the second pass of each overwrites the first
-            out[key + "_solver_iters"] = st["solver_iters"]
-        out["speedup"] = round(out["one_by_one_s"] / out["batched_s"], 3)
+            out[name] = {"s": round(time.perf_counter() - t0, 4), "solver_iters": st["solver_iters"]}
+        out["batched_speedup_f64"] = round(out["f64_one_by_one"]["s"] / out["f64_batched"]["s"], 3)
+        out["mixed_batched_vs_f64_one_by_one"] = round(out["f64_one_by_one"]["s"] / out["mixed_batched"]["s"], 3)
         lat.set_gauge(U0)
         return out
     finally:

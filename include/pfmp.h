@@ -200,11 +200,17 @@ int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const double *z, const
 /* ---- multi-RHS batches (several pseudofermion solves at one gauge field) ------ */
 
 /* out_r = Khat_{ops[r]} in_r for nrhs <= 8 right-hand sides, each with its own
- * operator slot, in 4 launches: one thread per (site, rhs) so that the links
- * each site reads are shared by all right-hand sides.  FP64. */
+ * operator slot (all clover or all Wilson), in 4 launches: one workgroup per (site
+ * block, rhs), the workgroups of one site block adjacent so that they share the links
+ * through L2.  FP64 internal spinors. */
 int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *const *in, void *const *out);
 /* CG for Khat_{ops[r]} x_r = b_r, r < nrhs <= 8, all iterated in the same launches;
- * a converged right-hand side stops.  st: nrhs records.  FP64. */
+ * a converged right-hand side stops.  b, x: FP64 internal spinors; st: nrhs records.
+ * p->prec PFMP_F64: CG in FP64.  PFMP_F32 (and PFMP_F16, taken as FP32): defect
+ * correction, FP64 residuals and solution around batched FP32 CG passes (FP32 links and
+ * clover), each to a relative 2e-6 or what the remaining reduction needs;
+ * st->reliable_updates counts the passes, st->iters the FP32 iterations.  Every
+ * right-hand side stops on its FP64 true residual <= tol |b_r|. */
 int pfmp_cg_solve_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *const *b, void *const *x,
                         const pfmp_solver_params *p, pfmp_solver_stats *st);
 

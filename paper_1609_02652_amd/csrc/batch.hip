@@ -8,6 +8,12 @@
 // and every link is fetched once into its L2 for all n.  Per-rhs CG scalars and
 // convergence flags live on the device; a converged rhs stops touching memory.
 // Reductions: one FP64 partial per workgroup (indexed site block * n + rhs), fixed order.
+//
+// The kernels are written once for FP64 and FP32 fields.  The FP64 batched CG is plain
+// CG on every right-hand side; the mixed-precision one is defect correction: FP64
+// residuals r_r = b_r - Khat x_r, the batched FP32 CG (FP32 links and clover) on
+// r_r / |r_r| to a relative 2e-6 or what the remaining reduction needs, x_r += |r_r| e_r
+// in FP64, until every FP64 residual is at the tolerance.
 #include <chrono>
 #include <cmath>
 
@@ -19,23 +25,26 @@ constexpr int kMaxRhs = 8;
 enum { B_RR = 0, B_THR, B_PAP, B_ALPHA, B_BETA, B_ITER, B_DONE, B_MAXIT, B_NSLOT = 8 };
 constexpr int kBatchBase = 5120;   // per-rhs scalar records at ctx->scal + kBatchBase + 8 r
 
-struct Batch {
+template <typename R>
+struct BatchT {
     int k;                          // stride of the partials (= n)
     int n;                          // right-hand sides
     int nsb;                        // site blocks (two lanes per site, kBlock lanes per block)
-    const double *clo[kMaxRhs];     // A_oo^-1 of each rhs's operator
-    const double *cle[kMaxRhs];     // A_ee
-    double a[kMaxRhs];              // -kappa^2
+    const R *clo[kMaxRhs];          // A_oo^-1 of each rhs's operator
+    const R *cle[kMaxRhs];          // A_ee
+    R a[kMaxRhs];                   // -kappa^2
     int clov[kMaxRhs];
 };
 
-struct Vecs {
-    const double2 *in[kMaxRhs];
-    double2 *out[kMaxRhs];
+template <typename C>
+struct VecsT {
+    const C *in[kMaxRhs];
+    C *out[kMaxRhs];
 };
 
 // logical workgroup lb = site block * n + rhs (XCD-aware order); false past the end
-__device__ __forceinline__ bool item(const Geom &g, const Batch &b, int *lb, int *site, int *r, int *hb)
+template <typename R>
+__device__ __forceinline__ bool item(const Geom &g, const BatchT<R> &b, int *lb, int *site, int *r, int *hb)
 {
     const int nb = gridDim.x, bi = blockIdx.x;
     const int per = (nb + 7) >> 3;
@@ -64,18 +73,18 @@ __device__ __forceinline__ void batch_partial(double v, int lb, int nlb, double 
 }
 
 // out_r = [g5] A_oo^-1 D_oe [g5] in_r
-template <int CLOV, int LM>
-__global__ __launch_bounds__(kBlock) void k_b_clovinv(Geom g, Batch b, Vecs v, const double2 *__restrict__ U,
-                                                      double gin, double gout, const double *__restrict__ st)
+template <typename C, typename R, int CLOV, int LM>
+__global__ __launch_bounds__(kBlock) void k_b_clovinv(Geom g, BatchT<R> b, VecsT<C> v, const C *__restrict__ U,
+                                                      R gin, R gout, const double *__restrict__ st)
 {
     int lb, i, r, hb;
     if (!item(g, b, &lb, &i, &r, &hb)) return;
     if (st && st[8 * r + B_DONE] != 0) return;
-    double2 blk[6];
-    hop_pair<LM, double2>(g, 1, i, hb, v.in[r], U, gin, blk);
+    C blk[6];
+    hop_pair<LM, C>(g, 1, i, hb, v.in[r], U, gin, blk);
     if (CLOV) {
-        double2 t[6];
-        clover_block<double, double2>(b.clo[r], g.Vh, i, hb, blk, t);
+        C t[6];
+        clover_block<R, C>(b.clo[r], g.Vh, i, hb, blk, t);
         store_block(v.out[r], g.Vh, i, hb, gout, t);
     } else {
         store_block(v.out[r], g.Vh, i, hb, gout, blk);
@@ -83,9 +92,9 @@ __global__ __launch_bounds__(kBlock) void k_b_clovinv(Geom g, Batch b, Vecs v, c
 }
 
 // out_r = [g5] (A_ee [g5] x_r + a_r D_eo t_r), |out_r|^2 partials
-template <int CLOV, int LM>
-__global__ __launch_bounds__(kBlock) void k_b_xpay(Geom g, Batch b, Vecs x, Vecs t, const double2 *__restrict__ U,
-                                                   double gs, const double *__restrict__ st,
+template <typename C, typename R, int CLOV, int LM>
+__global__ __launch_bounds__(kBlock) void k_b_xpay(Geom g, BatchT<R> b, VecsT<C> x, VecsT<C> t,
+                                                   const C *__restrict__ U, R gs, const double *__restrict__ st,
                                                    double *__restrict__ partials)
 {
     int lb = 0, i = 0, r = 0, hb = 0;
@@ -93,16 +102,16 @@ __global__ __launch_bounds__(kBlock) void k_b_xpay(Geom g, Batch b, Vecs x, Vecs
     if (ok && st && st[8 * r + B_DONE] != 0) ok = false;
     double nrm = 0;
     if (ok) {
-        double2 acc[6], xv[6], ax[6];
-        hop_pair<LM, double2>(g, 0, i, hb, t.in[r], U, 1.0, acc);
+        C acc[6], xv[6], ax[6];
+        hop_pair<LM, C>(g, 0, i, hb, t.in[r], U, (R)1, acc);
         load_block(x.in[r], g.Vh, i, hb, gs, xv);
-        if (CLOV) clover_block<double, double2>(b.cle[r], g.Vh, i, hb, xv, ax);
-        const double a = b.a[r];
+        if (CLOV) clover_block<R, C>(b.cle[r], g.Vh, i, hb, xv, ax);
+        const R a = b.a[r];
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            double2 base = CLOV ? ax[k] : xv[k];
-            acc[k] = make_double2(base.x + a * acc[k].x, base.y + a * acc[k].y);
-            nrm += acc[k].x * acc[k].x + acc[k].y * acc[k].y;
+            C base = CLOV ? ax[k] : xv[k];
+            acc[k] = mk<C>(base.x + a * acc[k].x, base.y + a * acc[k].y);
+            nrm += (double)acc[k].x * acc[k].x + (double)acc[k].y * acc[k].y;
         }
         store_block(x.out[r], g.Vh, i, hb, gs, acc);
     }
@@ -110,36 +119,36 @@ __global__ __launch_bounds__(kBlock) void k_b_xpay(Geom g, Batch b, Vecs x, Vecs
 }
 
 // CG stage 4: Kp_r from t_r and T'_r; x_r += alpha_r p_r; r_r -= alpha_r Kp_r; |r_r|^2 partials
-template <int CLOV, int LM>
-__global__ __launch_bounds__(kBlock) void k_b_hop4(Geom g, Batch b, Vecs t, Vecs T, Vecs p, Vecs x, Vecs rr,
-                                                   const double2 *__restrict__ U, const double *__restrict__ st,
-                                                   double *__restrict__ partials)
+template <typename C, typename R, int CLOV, int LM>
+__global__ __launch_bounds__(kBlock) void k_b_hop4(Geom g, BatchT<R> b, VecsT<C> t, VecsT<C> T, VecsT<C> p,
+                                                   VecsT<C> x, VecsT<C> rr, const C *__restrict__ U,
+                                                   const double *__restrict__ st, double *__restrict__ partials)
 {
     int lb = 0, i = 0, r = 0, hb = 0;
     bool ok = item(g, b, &lb, &i, &r, &hb);
     if (ok && st[8 * r + B_DONE] != 0) ok = false;
     double nrm = 0;
     if (ok) {
-        double2 acc[6], tv[6], at[6];
-        hop_pair<LM, double2>(g, 0, i, hb, T.in[r], U, 1.0, acc);
-        load_block(t.in[r], g.Vh, i, hb, -1.0, tv);
-        if (CLOV) clover_block<double, double2>(b.cle[r], g.Vh, i, hb, tv, at);
-        const double alpha = st[8 * r + B_ALPHA], a = b.a[r];
+        C acc[6], tv[6], at[6];
+        hop_pair<LM, C>(g, 0, i, hb, T.in[r], U, (R)1, acc);
+        load_block(t.in[r], g.Vh, i, hb, (R)-1, tv);
+        if (CLOV) clover_block<R, C>(b.cle[r], g.Vh, i, hb, tv, at);
+        const R alpha = (R)st[8 * r + B_ALPHA], a = b.a[r];
         const long Vh = g.Vh;
-        const double2 *pp = p.in[r];
-        double2 *xx = x.out[r], *rv_ = rr.out[r];
+        const C *pp = p.in[r];
+        C *xx = x.out[r], *rv_ = rr.out[r];
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            double2 base = CLOV ? at[k] : tv[k];
-            double2 kp = make_double2(base.x + a * acc[k].x, base.y + a * acc[k].y);
+            C base = CLOV ? at[k] : tv[k];
+            C kp = mk<C>(base.x + a * acc[k].x, base.y + a * acc[k].y);
             if (hb) kp = cneg(kp);
             const long e = (long)(6 * hb + k) * Vh + i;
-            double2 pv = pp[e], xv = xx[e], rv = rv_[e];
+            C pv = pp[e], xv = xx[e], rv = rv_[e];
             xv.x += alpha * pv.x; xv.y += alpha * pv.y;
             rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
             xx[e] = xv;
             rv_[e] = rv;
-            nrm += rv.x * rv.x + rv.y * rv.y;
+            nrm += (double)rv.x * rv.x + (double)rv.y * rv.y;
         }
     }
     batch_partial(nrm, lb, b.nsb * b.n, partials);
@@ -191,42 +200,58 @@ __global__ __launch_bounds__(kRedBlock) void k_b_beta(const double *__restrict__
 }
 
 // p_r = r_r + beta_r p_r for the right-hand sides still running
-__global__ void k_b_update_p(Geom g, Batch b, Vecs rr, Vecs p, const double *__restrict__ st)
+template <typename C>
+__global__ void k_b_update_p(Geom g, int nrhs, VecsT<C> rr, VecsT<C> p, const double *__restrict__ st)
 {
+    using R = decltype(C::x);
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     long n = 12L * g.Vh;
     int r = (int)(t / n);
     long e = t - (long)r * n;
-    if (r >= b.n || st[8 * r + B_DONE] != 0) return;
-    double beta = st[8 * r + B_BETA];
-    double2 rv = rr.in[r][e], pv = p.out[r][e];
-    p.out[r][e] = make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y);
+    if (r >= nrhs || st[8 * r + B_DONE] != 0) return;
+    const R beta = (R)st[8 * r + B_BETA];
+    C rv = rr.in[r][e], pv = p.out[r][e];
+    p.out[r][e] = mk<C>(rv.x + beta * pv.x, rv.y + beta * pv.y);
+}
+
+// out = (FP32) (s * in); in FP64
+__global__ void k_b_narrow(long n, double s, const double2 *__restrict__ in, float2 *__restrict__ out)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) out[t] = make_float2((float)(s * in[t].x), (float)(s * in[t].y));
+}
+
+// x += s * e (e FP32, x FP64)
+__global__ void k_b_accum(long n, double s, const float2 *__restrict__ e, double2 *__restrict__ x)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) x[t] = make_double2(x[t].x + s * (double)e[t].x, x[t].y + s * (double)e[t].y);
 }
 
 }  // namespace
 
-// launch the (CLOV, link mode) instance of a batch stencil kernel.  Link loads are never
-// streaming here: the n workgroups of a site block read the same links, and the copy the
-// first one brings into L2 is what the others reuse (on 32^3 x 64, 4 right-hand sides:
-// 0.85 of the single-RHS time per rhs, against 1.0 with streaming loads).
-#define BLAUNCH(K, grid, block, shm, stream, ...)                                                        \
-    do {                                                                                              \
-        const int lm_ = link_mode(ctx->g) & 1;                                                        \
-        if (b.clov[0]) {                                                                              \
-            if (lm_ == 0) hipLaunchKernelGGL((K<1, 0>), grid, block, shm, stream, __VA_ARGS__);         \
-            else hipLaunchKernelGGL((K<1, 1>), grid, block, shm, stream, __VA_ARGS__);                  \
-        } else {                                                                                      \
-            if (lm_ == 0) hipLaunchKernelGGL((K<0, 0>), grid, block, shm, stream, __VA_ARGS__);         \
-            else hipLaunchKernelGGL((K<0, 1>), grid, block, shm, stream, __VA_ARGS__);                  \
-        }                                                                                             \
+// launch the (C, R, CLOV, link mode) instance of a batch stencil kernel.  Link loads are
+// never streaming here: the n workgroups of a site block read the same links, and the
+// copy the first one brings into L2 is what the others reuse (on 32^3 x 64, 4
+// right-hand sides: 0.85 of the single-RHS time per rhs, against 1.0 with streaming).
+#define BLAUNCH(K, C, R, b, grid, block, shm, stream, ...)                                                   \
+    do {                                                                                                  \
+        const int lm_ = link_mode(ctx->g) & 1;                                                            \
+        if ((b).clov[0]) {                                                                                \
+            if (lm_ == 0) hipLaunchKernelGGL((K<C, R, 1, 0>), grid, block, shm, stream, __VA_ARGS__);       \
+            else hipLaunchKernelGGL((K<C, R, 1, 1>), grid, block, shm, stream, __VA_ARGS__);                \
+        } else {                                                                                          \
+            if (lm_ == 0) hipLaunchKernelGGL((K<C, R, 0, 0>), grid, block, shm, stream, __VA_ARGS__);       \
+            else hipLaunchKernelGGL((K<C, R, 0, 1>), grid, block, shm, stream, __VA_ARGS__);                \
+        }                                                                                                 \
     } while (0)
 
-static int make_batch(pfmp_ctx *ctx, int nrhs, const int *ops, Batch &b)
+static int make_batch(pfmp_ctx *ctx, int nrhs, const int *ops, BatchT<double> &b, BatchT<float> &bf)
 {
     if (nrhs <= 0 || nrhs > kMaxRhs || !ops) return set_err(ctx, PFMP_ERR_ARG, "batch: 1..8 right-hand sides");
-    b.n = nrhs;
-    b.k = nrhs;
-    b.nsb = nblocks(2L * ctx->g.Vh, kBlock);
+    b.n = bf.n = nrhs;
+    b.k = bf.k = nrhs;
+    b.nsb = bf.nsb = nblocks(2L * ctx->g.Vh, kBlock);
     for (int r = 0; r < kMaxRhs; r++) {
         int op = r < nrhs ? ops[r] : ops[0];
         if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
@@ -236,7 +261,10 @@ static int make_batch(pfmp_ctx *ctx, int nrhs, const int *ops, Batch &b)
         b.clo[r] = s.clov[1];
         b.cle[r] = s.clov[0];
         b.a[r] = -s.kappa * s.kappa;
-        b.clov[r] = s.csw != 0;
+        bf.clo[r] = s.clovf[1];
+        bf.cle[r] = s.clovf[0];
+        bf.a[r] = (float)(-s.kappa * s.kappa);
+        b.clov[r] = bf.clov[r] = s.csw != 0;
     }
     for (int r = 1; r < nrhs; r++)
         if (b.clov[r] != b.clov[0])
@@ -244,12 +272,13 @@ static int make_batch(pfmp_ctx *ctx, int nrhs, const int *ops, Batch &b)
     return 0;
 }
 
-static Vecs vecs(int n, const void *const *in, void *const *out)
+template <typename C>
+static VecsT<C> vecs(int n, const void *const *in, void *const *out)
 {
-    Vecs v{};
+    VecsT<C> v{};
     for (int r = 0; r < n; r++) {
-        v.in[r] = in ? (const double2 *)in[r] : nullptr;
-        v.out[r] = out ? (double2 *)out[r] : nullptr;
+        v.in[r] = in ? (const C *)in[r] : nullptr;
+        v.out[r] = out ? (C *)out[r] : nullptr;
     }
     return v;
 }
@@ -259,8 +288,9 @@ extern "C" int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, c
                                       void *const *out)
 {
     if (!ctx) return PFMP_ERR_ARG;
-    Batch b;
-    int rc = make_batch(ctx, nrhs, ops, b);
+    BatchT<double> b;
+    BatchT<float> bf;
+    int rc = make_batch(ctx, nrhs, ops, b, bf);
     if (rc) return rc;
     if (!in || !out) return set_err(ctx, PFMP_ERR_ARG, "batch: null buffers");
     for (int r = 0; r < nrhs; r++)
@@ -273,44 +303,42 @@ extern "C" int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, c
         if (!te[r] || !to[r]) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
     }
     dim3 grid(((b.nsb * nrhs + 7) / 8) * 8), block(kBlock);
+    using C = double2;
+    using R = double;
     // Mhat in -> te (stage 1 to to, stage 2 to te), then Mhat^dag te -> out
-    BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b, vecs(nrhs, in, to.data()), ctx->U, 1.0, 1.0,
-                       nullptr);
-    BLAUNCH(k_b_xpay, grid, block, 0, ctx->stream, g, b, vecs(nrhs, in, te.data()),
-                       vecs(nrhs, (const void *const *)to.data(), nullptr), ctx->U, 1.0, nullptr, nullptr);
-    BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b,
-                       vecs(nrhs, (const void *const *)te.data(), to.data()), ctx->U, -1.0, 1.0, nullptr);
-    BLAUNCH(k_b_xpay, grid, block, 0, ctx->stream, g, b, vecs(nrhs, (const void *const *)te.data(), out),
-                       vecs(nrhs, (const void *const *)to.data(), nullptr), ctx->U, -1.0, nullptr, nullptr);
+    BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, vecs<C>(nrhs, in, to.data()), ctx->U, 1.0,
+            1.0, nullptr);
+    BLAUNCH(k_b_xpay, C, R, b, grid, block, 0, ctx->stream, g, b, vecs<C>(nrhs, in, te.data()),
+            vecs<C>(nrhs, (const void *const *)to.data(), nullptr), ctx->U, 1.0, nullptr, nullptr);
+    BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b,
+            vecs<C>(nrhs, (const void *const *)te.data(), to.data()), ctx->U, -1.0, 1.0, nullptr);
+    BLAUNCH(k_b_xpay, C, R, b, grid, block, 0, ctx->stream, g, b, vecs<C>(nrhs, (const void *const *)te.data(), out),
+            vecs<C>(nrhs, (const void *const *)to.data(), nullptr), ctx->U, -1.0, nullptr, nullptr);
     LAUNCHCHK(ctx);
     return 0;
 }
 
-extern "C" int pfmp_cg_solve_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *const *b_, void *const *x_,
-                                   const pfmp_solver_params *prm, pfmp_solver_stats *st)
+// Batched CG in the field type C from x_r = 0: rhs r runs until its recursive |r|^2 <=
+// thr[r] (or it is skipped: skip[r]), at most maxiter iterations; iters[r] filled.
+// rr0[r] = |b_r|^2.  Work buffers come from the pool at base (4 per rhs).
+template <typename C, typename R>
+static int batch_cg_core(pfmp_ctx *ctx, const BatchT<R> &b, const void *const *b_, void *const *x_,
+                         const double *rr0, const double *thr, const bool *skip, int maxiter, int check_every,
+                         int base, int *iters, double *done)
 {
-    if (!ctx) return PFMP_ERR_ARG;
-    Batch b;
-    int rc = make_batch(ctx, nrhs, ops, b);
-    if (rc) return rc;
-    if (!b_ || !x_ || !prm || !(prm->tol > 0) || prm->maxiter <= 0)
-        return set_err(ctx, PFMP_ERR_ARG, "cg_solve_batch: bad arguments");
-    if (prm->prec != PFMP_F64) return set_err(ctx, PFMP_ERR_ARG, "cg_solve_batch: FP64 only");
-    for (int r = 0; r < nrhs; r++)
-        if (!b_[r] || !x_[r]) return set_err(ctx, PFMP_ERR_ARG, "cg_solve_batch: null buffer");
-    auto t0 = std::chrono::steady_clock::now();
     const Geom &g = ctx->g;
-    const size_t vb = sizeof(double) * spinor_reals(g);
+    const int nrhs = b.n;
+    const size_t vb = sizeof(R) * spinor_reals(g);
     const long n = 12L * g.Vh;
-    std::vector<void *> R(nrhs), P(nrhs), T1(nrhs), T2(nrhs);
+    std::vector<void *> Rv(nrhs), P(nrhs), T1(nrhs), T2(nrhs);
     for (int r = 0; r < nrhs; r++) {
-        R[r] = pool_get(ctx, 1016 + r);
-        P[r] = pool_get(ctx, 1024 + r);
-        T1[r] = pool_get(ctx, 1000 + r);
-        T2[r] = pool_get(ctx, 1008 + r);
-        if (!R[r] || !P[r] || !T1[r] || !T2[r]) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
+        Rv[r] = pool_get(ctx, base + r);
+        P[r] = pool_get(ctx, base + 8 + r);
+        T1[r] = pool_get(ctx, base + 16 + r);
+        T2[r] = pool_get(ctx, base + 24 + r);
+        if (!Rv[r] || !P[r] || !T1[r] || !T2[r]) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
         HIPCHK(ctx, hipMemsetAsync(x_[r], 0, vb, ctx->stream));
-        HIPCHK(ctx, hipMemcpyAsync(R[r], b_[r], vb, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(Rv[r], b_[r], vb, hipMemcpyDeviceToDevice, ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(P[r], b_[r], vb, hipMemcpyDeviceToDevice, ctx->stream));
     }
     const int nb = b.nsb;   // partials per rhs
@@ -319,94 +347,196 @@ extern "C" int pfmp_cg_solve_batch(pfmp_ctx *ctx, int nrhs, const int *ops, cons
     double *part_b = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64) * b.k, 10);
     if (!part_a || !part_b) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
     double *sc = ctx->scal + kBatchBase;
-    std::vector<double> bb(nrhs);
-    for (int r = 0; r < nrhs; r++) {
-        if ((rc = launch_norm2(ctx, (const double2 *)b_[r], n, ctx->red))) return rc;
-        if ((rc = red_finish(ctx, ctx->red, ctx->nblk_red, 1, &bb[r]))) return rc;
-    }
     std::vector<double> init(8 * kMaxRhs, 0.0);
     for (int r = 0; r < nrhs; r++) {
-        init[8 * r + B_RR] = bb[r];
-        init[8 * r + B_THR] = prm->tol * prm->tol * bb[r];
-        init[8 * r + B_DONE] = bb[r] == 0 ? 1 : 0;
-        init[8 * r + B_MAXIT] = prm->maxiter;
+        init[8 * r + B_RR] = rr0[r];
+        init[8 * r + B_THR] = thr[r];
+        init[8 * r + B_DONE] = (rr0[r] == 0 || (skip && skip[r])) ? 1 : 0;
+        init[8 * r + B_MAXIT] = maxiter;
     }
     HIPCHK(ctx, hipMemcpyAsync(sc, init.data(), sizeof(double) * 8 * kMaxRhs, hipMemcpyHostToDevice, ctx->stream));
     dim3 grid(ngrid), block(kBlock);
-    const Vecs vP = vecs(nrhs, (const void *const *)P.data(), P.data());
-    const Vecs vT1 = vecs(nrhs, (const void *const *)T1.data(), T1.data());
-    const Vecs vT2 = vecs(nrhs, (const void *const *)T2.data(), T2.data());
-    const Vecs vR = vecs(nrhs, (const void *const *)R.data(), R.data());
-    const Vecs vX = vecs(nrhs, nullptr, x_);
+    const VecsT<C> vP = vecs<C>(nrhs, (const void *const *)P.data(), P.data());
+    const VecsT<C> vT1 = vecs<C>(nrhs, (const void *const *)T1.data(), T1.data());
+    const VecsT<C> vT2 = vecs<C>(nrhs, (const void *const *)T2.data(), T2.data());
+    const VecsT<C> vR = vecs<C>(nrhs, (const void *const *)Rv.data(), Rv.data());
+    const VecsT<C> vX = vecs<C>(nrhs, nullptr, x_);
     // stage buffers: T2 <- A^-1 D_oe p ; T1 <- Mhat p ; T2 <- A^-1 D_oe g5 T1
-    const Vecs p_to_T2 = vecs(nrhs, (const void *const *)P.data(), T2.data());
-    const Vecs p_to_T1 = vecs(nrhs, (const void *const *)P.data(), T1.data());
-    const Vecs T1_to_T2 = vecs(nrhs, (const void *const *)T1.data(), T2.data());
-    int chunk = prm->check_every > 0 ? prm->check_every : 25;
-    std::vector<double> h(8 * kMaxRhs);
+    const VecsT<C> p_to_T2 = vecs<C>(nrhs, (const void *const *)P.data(), T2.data());
+    const VecsT<C> p_to_T1 = vecs<C>(nrhs, (const void *const *)P.data(), T1.data());
+    const VecsT<C> T1_to_T2 = vecs<C>(nrhs, (const void *const *)T1.data(), T2.data());
+    const C *U = sizeof(R) == 8 ? (const C *)ctx->U : (const C *)ctx->Uf;
+    int chunk = check_every > 0 ? check_every : 25;
     // one iteration for all rhs: 7 launches with fixed arguments, replayed as a graph
     auto iteration = [&]() -> int {
-        BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b, p_to_T2, ctx->U, 1.0, 1.0, sc);
-        BLAUNCH(k_b_xpay, grid, block, 0, ctx->stream, g, b, p_to_T1, vT2, ctx->U, 1.0, sc, part_a);
+        BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, p_to_T2, U, (R)1, (R)1, sc);
+        BLAUNCH(k_b_xpay, C, R, b, grid, block, 0, ctx->stream, g, b, p_to_T1, vT2, U, (R)1, sc, part_a);
         hipLaunchKernelGGL(k_b_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_a, nb, b.k, nrhs, sc);
-        BLAUNCH(k_b_clovinv, grid, block, 0, ctx->stream, g, b, T1_to_T2, ctx->U, -1.0, 1.0, sc);
-        BLAUNCH(k_b_hop4, grid, block, 0, ctx->stream, g, b, vT1, vT2, vP, vX, vR, ctx->U, sc, part_b);
+        BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, T1_to_T2, U, (R)-1, (R)1, sc);
+        BLAUNCH(k_b_hop4, C, R, b, grid, block, 0, ctx->stream, g, b, vT1, vT2, vP, vX, vR, U, sc, part_b);
         hipLaunchKernelGGL(k_b_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, b.k, nrhs, sc);
-        hipLaunchKernelGGL(k_b_update_p, dim3(nblocks(n * nrhs, 256)), dim3(256), 0, ctx->stream, g, b, vR, vP, sc);
+        hipLaunchKernelGGL((k_b_update_p<C>), dim3(nblocks(n * nrhs, 256)), dim3(256), 0, ctx->stream, g, nrhs, vR,
+                           vP, sc);
         LAUNCHCHK(ctx);
         return 0;
     };
     std::vector<uint64_t> key;
     key_add(key, 5);   // batched CG iteration
+    key_add(key, (int)sizeof(R));
     key_geom(key, g);
     key_add(key, nrhs);
     for (int r = 0; r < nrhs; r++) {
-        for (const void *ptr : {(const void *)P[r], (const void *)T1[r], (const void *)T2[r], (const void *)R[r],
+        for (const void *ptr : {(const void *)P[r], (const void *)T1[r], (const void *)T2[r], (const void *)Rv[r],
                                 (const void *)x_[r], (const void *)b.clo[r], (const void *)b.cle[r]})
             key_add(key, ptr);
         key_add(key, b.a[r]);
     }
-    for (const void *ptr : {(const void *)part_a, (const void *)part_b, (const void *)sc, (const void *)ctx->U})
+    for (const void *ptr : {(const void *)part_a, (const void *)part_b, (const void *)sc, (const void *)U})
         key_add(key, ptr);
     key_add(key, b.clov[0]);
     for (;;) {
+        bool all = true;
+        for (int r = 0; r < nrhs; r++) all = all && init[8 * r + B_DONE] != 0;
+        if (all) break;
+        int rc;
         if ((rc = graph_run(ctx, key, chunk, iteration))) return rc;
         HIPCHK(ctx, hipMemcpyAsync(ctx->red_host, sc, sizeof(double) * 8 * kMaxRhs, hipMemcpyDeviceToHost,
                                    ctx->stream));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        bool all = true;
         for (int r = 0; r < nrhs; r++) {
-            h[8 * r + B_DONE] = ctx->red_host[8 * r + B_DONE];
-            h[8 * r + B_ITER] = ctx->red_host[8 * r + B_ITER];
-            all = all && h[8 * r + B_DONE] != 0;
+            init[8 * r + B_DONE] = ctx->red_host[8 * r + B_DONE];
+            init[8 * r + B_ITER] = ctx->red_host[8 * r + B_ITER];
         }
-        if (all) break;
     }
-    // FP64 true residuals, one rhs at a time
+    for (int r = 0; r < nrhs; r++) {
+        iters[r] = (int)init[8 * r + B_ITER];
+        done[r] = init[8 * r + B_DONE];
+    }
+    return 0;
+}
+
+// FP64 |b - Khat_op x|^2
+static int residual64(pfmp_ctx *ctx, int op, const double2 *b, const double2 *x, double2 *res, double *rr)
+{
+    const Geom &g = ctx->g;
+    const size_t vb = sizeof(double) * spinor_reals(g);
     double2 *Kx = (double2 *)ws_alloc(ctx, vb, 8), *te = (double2 *)ws_alloc(ctx, vb, 6),
             *to = (double2 *)ws_alloc(ctx, vb, 7);
     if (!Kx || !te || !to) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
-    int worst_rc = 0;
+    int rc;
+    if ((rc = op_apply_K(ctx, op, x, Kx, te, to, nullptr))) return rc;
+    double one[2] = {1, 0}, mone[2] = {-1, 0};
+    HIPCHK(ctx, hipMemcpyAsync(res, b, vb, hipMemcpyDeviceToDevice, ctx->stream));
+    if ((rc = pfmp_axpby(ctx, mone, Kx, one, res))) return rc;
+    if ((rc = launch_norm2(ctx, res, 12L * g.Vh, ctx->red))) return rc;
+    return red_finish(ctx, ctx->red, ctx->nblk_red, 1, rr);
+}
+
+extern "C" int pfmp_cg_solve_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *const *b_, void *const *x_,
+                                   const pfmp_solver_params *prm, pfmp_solver_stats *st)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    BatchT<double> b;
+    BatchT<float> bf;
+    int rc = make_batch(ctx, nrhs, ops, b, bf);
+    if (rc) return rc;
+    if (!b_ || !x_ || !prm || !(prm->tol > 0) || prm->maxiter <= 0)
+        return set_err(ctx, PFMP_ERR_ARG, "cg_solve_batch: bad arguments");
+    if (prm->prec != PFMP_F64 && prm->prec != PFMP_F32 && prm->prec != PFMP_F16)
+        return set_err(ctx, PFMP_ERR_ARG, "cg_solve_batch: precision");
+    for (int r = 0; r < nrhs; r++)
+        if (!b_[r] || !x_[r]) return set_err(ctx, PFMP_ERR_ARG, "cg_solve_batch: null buffer");
+    if (prm->prec != PFMP_F64 && (rc = gauge_f32_ready(ctx))) return rc;
+    auto t0 = std::chrono::steady_clock::now();
+    const Geom &g = ctx->g;
+    const size_t vb = sizeof(double) * spinor_reals(g);
+    const long n = 12L * g.Vh;
+    std::vector<double> bb(nrhs), thr(nrhs), res(nrhs, 0.0), done(nrhs, 0.0);
+    std::vector<int> its(nrhs, 0), total(nrhs, 0), outer(nrhs, 0);
     for (int r = 0; r < nrhs; r++) {
-        if ((rc = op_apply_K(ctx, ops[r], (const double2 *)x_[r], Kx, te, to, nullptr))) return rc;
-        double one[2] = {1, 0}, mone[2] = {-1, 0};
-        HIPCHK(ctx, hipMemcpyAsync(te, b_[r], vb, hipMemcpyDeviceToDevice, ctx->stream));
-        if ((rc = pfmp_axpby(ctx, mone, Kx, one, te))) return rc;
-        double rr;
-        if ((rc = launch_norm2(ctx, te, n, ctx->red))) return rc;
-        if ((rc = red_finish(ctx, ctx->red, ctx->nblk_red, 1, &rr))) return rc;
-        double res = bb[r] > 0 ? std::sqrt(rr / bb[r]) : 0;
-        if (st) {
-            st[r].iters = (int)h[8 * r + B_ITER];
-            st[r].reliable_updates = 0;
-            st[r].true_res = res;
-            st[r].kmults = st[r].iters + 1;
+        if ((rc = launch_norm2(ctx, (const double2 *)b_[r], n, ctx->red))) return rc;
+        if ((rc = red_finish(ctx, ctx->red, ctx->nblk_red, 1, &bb[r]))) return rc;
+        thr[r] = prm->tol * prm->tol * bb[r];
+    }
+    int worst_rc = 0;
+    std::vector<double2 *> rv(nrhs);
+    for (int r = 0; r < nrhs; r++)
+        if (!(rv[r] = pool_get(ctx, 1032 + r))) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
+    if (prm->prec == PFMP_F64) {
+        if ((rc = batch_cg_core<double2, double>(ctx, b, b_, x_, bb.data(), thr.data(), nullptr, prm->maxiter,
+                                                 prm->check_every, 1000, its.data(), done.data())))
+            return rc;
+        for (int r = 0; r < nrhs; r++) {
+            double rr;
+            if ((rc = residual64(ctx, ops[r], (const double2 *)b_[r], (const double2 *)x_[r], rv[r], &rr))) return rc;
+            res[r] = bb[r] > 0 ? std::sqrt(rr / bb[r]) : 0;
+            total[r] = its[r];
+            if (done[r] == 2 && !(res[r] <= prm->tol)) worst_rc = PFMP_ERR_NOCONV;
         }
-        if (h[8 * r + B_DONE] == 2 && !(res <= prm->tol)) worst_rc = PFMP_ERR_NOCONV;
+    } else {
+        // defect correction: FP64 residuals and solution, FP32 batched inner solves
+        std::vector<void *> r32(nrhs), e32(nrhs);
+        for (int r = 0; r < nrhs; r++) {
+            r32[r] = pool_get(ctx, 1040 + r);
+            e32[r] = pool_get(ctx, 1048 + r);
+            if (!r32[r] || !e32[r]) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
+            HIPCHK(ctx, hipMemsetAsync(x_[r], 0, vb, ctx->stream));
+            HIPCHK(ctx, hipMemcpyAsync(rv[r], b_[r], vb, hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        std::vector<double> rr(bb), one(nrhs, 1.0), ithr(nrhs);
+        std::vector<bool> conv(nrhs);
+        for (;;) {
+            bool all = true;
+            for (int r = 0; r < nrhs; r++) {
+                conv[r] = rr[r] <= thr[r];
+                all = all && conv[r];
+            }
+            if (all) break;
+            bool spent = false;
+            for (int r = 0; r < nrhs; r++) spent = spent || (!conv[r] && total[r] >= prm->maxiter);
+            if (spent) {
+                worst_rc = PFMP_ERR_NOCONV;
+                break;
+            }
+            bool skip[kMaxRhs] = {};
+            int budget = prm->maxiter;
+            for (int r = 0; r < nrhs; r++) {
+                skip[r] = conv[r];
+                // relative reduction asked of this pass, no tighter than FP32 reaches
+                const double need = 0.5 * prm->tol * std::sqrt(bb[r] / rr[r]);
+                ithr[r] = std::max(need, 2e-6) * std::max(need, 2e-6);
+                if (!conv[r]) budget = std::min(budget, prm->maxiter - total[r]);
+                hipLaunchKernelGGL(k_b_narrow, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n,
+                                   conv[r] ? 0.0 : 1.0 / std::sqrt(rr[r]), rv[r], (float2 *)r32[r]);
+            }
+            LAUNCHCHK(ctx);
+            if ((rc = batch_cg_core<float2, float>(ctx, bf, (const void *const *)r32.data(), e32.data(), one.data(),
+                                                   ithr.data(), skip, std::max(budget, 1), prm->check_every, 1056,
+                                                   its.data(), done.data())))
+                return rc;
+            for (int r = 0; r < nrhs; r++) {
+                if (conv[r]) continue;
+                total[r] += its[r];
+                outer[r]++;
+                hipLaunchKernelGGL(k_b_accum, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, std::sqrt(rr[r]),
+                                   (const float2 *)e32[r], (double2 *)x_[r]);
+                LAUNCHCHK(ctx);
+                if ((rc = residual64(ctx, ops[r], (const double2 *)b_[r], (const double2 *)x_[r], rv[r], &rr[r])))
+                    return rc;
+            }
+        }
+        for (int r = 0; r < nrhs; r++) res[r] = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : 0;
     }
     auto t1 = std::chrono::steady_clock::now();
     if (st)
-        for (int r = 0; r < nrhs; r++) st[r].seconds = std::chrono::duration<double>(t1 - t0).count();
+        for (int r = 0; r < nrhs; r++) {
+            st[r] = pfmp_solver_stats{};
+            st[r].iters = total[r];
+            st[r].reliable_updates = outer[r];
+            st[r].true_res = res[r];
+            st[r].kmults = total[r] + (prm->prec == PFMP_F64 ? 1 : outer[r]);
+            st[r].seconds = std::chrono::duration<double>(t1 - t0).count();
+        }
     if (worst_rc) return set_err(ctx, worst_rc, "cg_solve_batch: maxiter reached");
     return 0;
 }

@@ -525,7 +525,7 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
         HIPCHK(ctx, hipMemsetAsync(F, 0, sizeof(double) * mom_reals(ctx->g), ctx->stream));
         // the CG solves of the RATIO / HEAVY terms due at this step, as one multi-RHS solve
         std::vector<const void *> pre(nt, nullptr);
-        if (sp->batch && !sp->ptnet && sp->solver_prec == PFMP_F64) {
+        if (sp->batch && !sp->ptnet) {
             std::vector<int> js, sops;
             std::vector<const void *> rhs;
             std::vector<void *> sol;
@@ -564,7 +564,8 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
                     if (m == 1) {
                         if ((rc = solve(X, o[0], bb[0], xx[0]))) return rc;
                     } else {
-                        pfmp_solver_params p{sp->tol, sp->maxiter > 0 ? sp->maxiter : 100000, PFMP_F64, 0.0, 0};
+                        pfmp_solver_params p{sp->tol, sp->maxiter > 0 ? sp->maxiter : 100000, sp->solver_prec,
+                                             0.0, 0};
                         std::vector<pfmp_solver_stats> bst(m);
                         if ((rc = pfmp_cg_solve_batch(ctx, (int)m, o.data(), bb.data(), xx.data(), &p, bst.data())))
                             return rc;

@@ -380,14 +380,14 @@ class Lattice:
         self._chk(self.lib.pfmp_apply_MdagM_batch(self.h, n, o, ip, op_), "apply_MdagM_batch")
         return outs
 
-    def cg_solve_batch(self, ops, bs, xs=None, tol=1e-10, maxiter=10000, check_every=0):
+    def cg_solve_batch(self, ops, bs, xs=None, tol=1e-10, maxiter=10000, check_every=0, prec=F64):
         n = len(bs)
         xs = [self.field(zero=False) for _ in range(n)] if xs is None else xs
         o = (ctypes.c_int * n)(*ops)
         bp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in bs])
         xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
         st = (SolverStats * n)()
-        p = self.params(tol, maxiter, F64, 0.0, check_every)
+        p = self.params(tol, maxiter, prec, 0.0, check_every)
         self._chk(self.lib.pfmp_cg_solve_batch(self.h, n, o, bp, xp, ctypes.byref(p), st), "cg_solve_batch")
         return xs, [st[k].as_dict() for k in range(n)]
 

@@ -175,6 +175,21 @@ def test_batch_cg(setup):
         assert rel(xg, lat.spinor_numpy(xs1)) < 1e-9
 
 
+def test_batch_cg_mixed(setup):
+    """Batched defect correction (FP32 batched CG passes inside FP64 residuals) reaches
+    every right-hand side's FP64 true residual."""
+    from paper_1609_02652_amd.pfmp import F32
+    dims, U, lat, ops = setup
+    bs = [synth.gaussian_spinor(lat.Vh, 85 + k) for k in range(3)]
+    opl = [0, 2, 0]
+    xs, sts = lat.cg_solve_batch(opl, [lat.pack_spinor(b) for b in bs], tol=1e-10, prec=F32)
+    for op, b, x, st in zip(opl, bs, xs, sts):
+        print("batched mixed: op %d iters %d passes %d res %.2e" % (op, st["iters"], st["reliable_updates"],
+                                                                    st["true_res"]))
+        assert st["true_res"] <= 1e-10 and st["reliable_updates"] >= 2
+        assert rel(ops[op].K(lat.spinor_numpy(x)), b) <= 1.05e-10
+
+
 def test_cg_maxiter_reports(setup):
     from paper_1609_02652_amd.pfmp import PfmpError
     dims, U, lat, ops = setup
