@@ -426,7 +426,8 @@ def main():
         lat.set_operator(0, KAPPA, CSW)
         lat.set_operator(1, KAPPA_H, CSW)
         log("autotune: %s" % lat.autotune(0))
-        sp = pfmp_spec(lat, solver_prec={"f64": F64, "f32": F32, "f16": F16}[args.trajectory_only])
+        prec = {"f64": F64, "f32": F32, "f16": F16}[args.trajectory_only]
+        sp = pfmp_spec(lat, solver_prec=prec)
         t, sts = run_trajectories(lat, sp, args.steps, args.warmup, 100)
         lat.close()
         print(json.dumps({"trajectory_only": args.trajectory_only, "s_per_traj": round(t, 4),
@@ -526,8 +527,9 @@ def main():
                                "(ratio, correction, filter, S_det, gauge) = (20,20,120,120,480), every solve to 1e-10"
                                % args.therm,
                    "lattice": "16x16x16x32",
-                   "mode": "chosen (fastest measured solver): %s for the ratio-term solves; the correction "
-                           "poles by the FP64 multi-shift CG; all actions, dH and the accept in FP64" % {"f32": "FP32 inner CG with FP64 reliable updates",
+                   "mode": "chosen (fastest measured solver): %s for the ratio-term solves and the "
+                           "correction term's z = 0 pole, its complex poles by the FP64 multi-shift CG; "
+                           "filter-force chains in FP32; all actions, dH and the accept in FP64" % {"f32": "FP32 inner CG with FP64 reliable updates",
                                                "f16": "FP16-storage inner CG with FP64 reliable updates",
                                                "learned": "flexible CG with the trained PT-conv network"}[
                                chosen_prec]},

@@ -121,20 +121,41 @@ int solve(Ctx &X, int op, const void *b, void *x)
     return rc;
 }
 
-int msolve(Ctx &X, int op, const std::vector<cd> &z, const void *b, std::vector<double2 *> &xs)
+// the mixed-precision and learned modes (every solve to the same FP64 residual)
+bool low_precision_mode(const Ctx &X) { return X.sp->solver_prec != PFMP_F64 || X.sp->ptnet; }
+
+// x_k = (J - z_k)^-1 b for every pole.  The plain FP64 form runs all poles in one
+// multi-shift solve.  In the mixed-precision and learned modes the pole z = 0, which
+// needs the most iterations, is solved by that mode's CG (or taken from x0, solved
+// beforehand with the other CG solves of the step), and the FP64 multi-shift solver
+// stops as soon as the complex poles, well away from the spectrum, have converged.
+int msolve(Ctx &X, int op, const std::vector<cd> &z, const void *b, std::vector<double2 *> &xs,
+           const void *x0 = nullptr)
 {
-    std::vector<double> zz(2 * z.size());
+    int k0 = -1;
+    if (low_precision_mode(X) && z.size() > 1)
+        for (size_t k = 0; k < z.size(); k++)
+            if (z[k] == cd(0.0)) k0 = (int)k;
+    std::vector<double> zz;
+    std::vector<void *> xv;
     for (size_t k = 0; k < z.size(); k++) {
-        zz[2 * k] = z[k].real();
-        zz[2 * k + 1] = z[k].imag();
+        if ((int)k == k0) continue;
+        zz.push_back(z[k].real());
+        zz.push_back(z[k].imag());
+        xv.push_back(xs[k]);
     }
     pfmp_solver_params p{X.sp->tol, X.sp->maxiter > 0 ? X.sp->maxiter : 100000, PFMP_F64, 0.0, 0};
     pfmp_solver_stats st{};
-    std::vector<void *> xv(xs.begin(), xs.end());
-    int rc = pfmp_cg_multishift(X.c, op, (int)z.size(), zz.data(), b, xv.data(), &p, &st);
+    int rc = pfmp_cg_multishift(X.c, op, (int)xv.size(), zz.data(), b, xv.data(), &p, &st);
     X.iters += st.iters;
     X.mhalf += 2 * st.kmults;
-    return rc;
+    if (rc || k0 < 0) return rc;
+    if (x0) {
+        HIPCHK(X.c, hipMemcpyAsync(xs[k0], x0, sizeof(double) * spinor_reals(X.c->g), hipMemcpyDeviceToDevice,
+                                   X.c->stream));
+        return 0;
+    }
+    return solve(X, op, b, xs[k0]);
 }
 
 int applyM(Ctx &X, int op, int dag, const void *in, void *out, int prec = PFMP_F64)
@@ -155,9 +176,6 @@ int poly(Ctx &X, int op, const std::vector<cd> &roots, cd norm, const void *in, 
     X.mhalf += 2 * (long long)roots.size();
     return pfmp_apply_poly(X.c, op, (int)roots.size(), r.data(), nm, in, out, chain, prec);
 }
-
-// the mixed-precision and learned modes (every solve to the same FP64 residual)
-bool low_precision_mode(const Ctx &X) { return X.sp->solver_prec != PFMP_F64 || X.sp->ptnet; }
 
 cd dot(Ctx &X, const void *a, const void *b, int &rc)
 {
@@ -351,7 +369,7 @@ int term_force(Ctx &X, const pfmp_term &t, const void *phi, double eps, double *
             wx[k] = pool_get(ctx, kChain + m + k);
             if (!xs[k] || !wx[k]) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
         }
-        if ((rc = msolve(X, t.op, z, phi, xs))) return rc;
+        if ((rc = msolve(X, t.op, z, phi, xs, presolved))) return rc;
         for (int k = 0; k < m; k++)
             if ((rc = applyM(X, t.op, 0, xs[k], wx[k]))) return rc;
         for (int i = 0; i < m; i++) {
@@ -531,7 +549,10 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
             std::vector<void *> sol;
             for (int j = 1; j < nt; j++) {
                 const pfmp_term &t = sp->terms[j - 1];
-                if (So[(size_t)j * cap + k] == 0.0 || (t.kind != PFMP_TERM_RATIO && t.kind != PFMP_TERM_HEAVY))
+                // the correction term's z = 0 pole is a CG solve on J in the low-precision modes
+                const bool pole0 = t.kind == PFMP_TERM_POLYCORR && low_precision_mode(X);
+                if (So[(size_t)j * cap + k] == 0.0 ||
+                    (t.kind != PFMP_TERM_RATIO && t.kind != PFMP_TERM_HEAVY && !pole0))
                     continue;
                 double2 *b = pool_get(ctx, 2200 + j), *x = pool_get(ctx, 2100 + j);
                 if (!b || !x) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");

@@ -161,7 +161,7 @@ def test_batched_and_mixed_solves_in_trajectory(U0):
     # FP32 filter forces (relative error ~1e-7) move the end point by ~1e-8 in the links
     # and dH, a difference of Hamiltonians of size ~1e3 here, by a few 1e-6
     for kw, tol_dh, tol_u in ((dict(batch=True), 1e-8, 1e-9), (dict(solver_prec=F32), 2e-5, 1e-6),
-                              (dict(solver_prec=F16), 2e-5, 1e-6)):
+                              (dict(solver_prec=F16), 2e-5, 1e-6), (dict(solver_prec=F16, batch=True), 2e-5, 1e-6)):
         st, Ug = _run(U0, kw, P0, etas, 0.0)
         du = np.max(np.abs(Ug - Uref))
         print(kw, "dH %.12f vs %.12f, iters %d vs %d, max |dU| %.2e" % (st["dH"], ref["dH"], st["solver_iters"],
