@@ -9,6 +9,8 @@
 //   Gx = s F_03 - F_12,  Gy = s F_13 + F_02,  Gz = s F_23 - F_01.
 // Even sites store A (diagonal + upper triangle of each 6x6 block); odd sites store
 // A^-1 from a Cholesky factorisation, whose pivots also give ln det A.
+#include <hip/hip_fp16.h>
+
 #include "su3.h"
 
 namespace {
@@ -63,6 +65,13 @@ __global__ __launch_bounds__(kBlock) void k_fhat(Geom g, const double2 *__restri
 }
 
 __device__ __forceinline__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c; }   // c <= r
+
+// FP16 copy of a clover field (round to nearest), for the FP16-storage inner solver
+__global__ void k_clover_half(long n, const float *__restrict__ a, __half *__restrict__ h)
+{
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < n) h[t] = __float2half_rn(a[t]);
+}
 
 // Chiral block b of A at parity p from F-hat: thread (b, i).  INV = 0 stores A
 // (even sites); INV = 1 stores A^-1 from a packed Cholesky factorisation and sums
@@ -235,6 +244,11 @@ int clover_build(pfmp_ctx *ctx, int op)
     LAUNCHCHK(ctx);
     hipLaunchKernelGGL(k_clover_blocks<1>, dim3(nb), dim3(kBlock), 0, ctx->stream, g, 1, ctx->Fhat, kc, s.clov[1],
                        s.clovf[1], s.ldpart, bad);
+    LAUNCHCHK(ctx);
+    const long nr = clover_reals(g);
+    for (int p = 0; p < 2; p++)
+        hipLaunchKernelGGL(k_clover_half, dim3(nblocks(nr, 256)), dim3(256), 0, ctx->stream, nr, s.clovf[p],
+                           (__half *)s.clovh[p]);
     LAUNCHCHK(ctx);
     s.ld_dirty = true;
     return 0;

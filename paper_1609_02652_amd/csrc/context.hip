@@ -2,6 +2,8 @@
 #include <cstring>
 #include <vector>
 
+#include <hip/hip_fp16.h>
+
 #include "internal.h"
 
 // Scratch buffers of the context, one per slot:
@@ -120,10 +122,14 @@ __global__ void k_pack_gauge(Geom g, const double2 *__restrict__ in, double2 *__
         }
 }
 
-__global__ void k_gauge_f32(long n, const double2 *__restrict__ a, float2 *__restrict__ b)
+// FP32 and FP16 copies of the links (round to nearest)
+__global__ void k_gauge_f32(long n, const double2 *__restrict__ a, float2 *__restrict__ b, __half2 *__restrict__ h)
 {
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t < n) b[t] = make_float2((float)a[t].x, (float)a[t].y);
+    if (t < n) {
+        b[t] = make_float2((float)a[t].x, (float)a[t].y);
+        h[t] = __floats2half2_rn((float)a[t].x, (float)a[t].y);
+    }
 }
 
 // canonical spinor [Vh][12] complex128 <-> internal [12][Vh]
@@ -210,6 +216,7 @@ extern "C" int pfmp_create(const int dims[4], int t_bc, void *stream, pfmp_ctx *
     ctx->nblk_red = 1024;
     size_t gb = sizeof(double) * gauge_reals(ctx->g);
     if (hipMalloc(&ctx->U, gb) != hipSuccess || hipMalloc(&ctx->Uf, gb / 2) != hipSuccess ||
+        hipMalloc(&ctx->Uh, gb / 4) != hipSuccess ||
         hipMalloc(&ctx->red, sizeof(double) * 64 * 4096) != hipSuccess ||
         hipMalloc(&ctx->scal, sizeof(double) * 8192) != hipSuccess ||
         hipHostMalloc(&ctx->red_host, sizeof(double) * 4096, hipHostMallocDefault) != hipSuccess) {
@@ -226,6 +233,7 @@ extern "C" int pfmp_destroy(pfmp_ctx *ctx)
     hipStreamSynchronize(ctx->stream);
     hipFree(ctx->U);
     hipFree(ctx->Uf);
+    hipFree(ctx->Uh);
     hipFree(ctx->Fhat);
     for (auto &gr : ctx->graphs) hipGraphExecDestroy(gr.exec);
     if (ctx->cap) hipStreamDestroy(ctx->cap);
@@ -235,6 +243,7 @@ extern "C" int pfmp_destroy(pfmp_ctx *ctx)
     for (auto &s : ctx->ops) {
         hipFree(s.clov[0]); hipFree(s.clov[1]);
         hipFree(s.clovf[0]); hipFree(s.clovf[1]);
+        hipFree(s.clovh[0]); hipFree(s.clovh[1]);
         hipFree(s.ldpart);
     }
     for (double2 *p : ctx->pool) hipFree(p);
@@ -286,7 +295,8 @@ int gauge_f32_ready(pfmp_ctx *ctx)
 {
     if (!ctx->uf_stale) return 0;
     long n = gauge_reals(ctx->g) / 2;
-    hipLaunchKernelGGL(k_gauge_f32, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, ctx->U, ctx->Uf);
+    hipLaunchKernelGGL(k_gauge_f32, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, ctx->U, ctx->Uf,
+                       (__half2 *)ctx->Uh);
     LAUNCHCHK(ctx);
     ctx->uf_stale = false;
     return 0;
@@ -453,7 +463,8 @@ extern "C" int pfmp_set_operator(pfmp_ctx *ctx, int op, double kappa, double csw
     if (!s.clov[0]) {
         size_t b = sizeof(double) * clover_reals(ctx->g);
         if (hipMalloc(&s.clov[0], b) != hipSuccess || hipMalloc(&s.clov[1], b) != hipSuccess ||
-            hipMalloc(&s.clovf[0], b / 2) != hipSuccess || hipMalloc(&s.clovf[1], b / 2) != hipSuccess)
+            hipMalloc(&s.clovf[0], b / 2) != hipSuccess || hipMalloc(&s.clovf[1], b / 2) != hipSuccess ||
+            hipMalloc(&s.clovh[0], b / 4) != hipSuccess || hipMalloc(&s.clovh[1], b / 4) != hipSuccess)
             return set_err(ctx, PFMP_ERR_OOM, "clover fields");
     }
     s.valid = true;

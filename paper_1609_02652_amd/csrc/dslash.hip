@@ -12,10 +12,9 @@ namespace {
 // out = [g5] A^-1 D in [g5], output parity pout (CLOV = 0: no clover); In / Out are
 // spinor pointers of the register type C or FP16 storage (HalfField).  Two lanes per
 // site, lane hb writing chiral block hb.
-template <typename C, typename R, int CLOV, int LM, typename In, typename Out>
-__global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const In in, const C *__restrict__ U,
-                                                        const R *__restrict__ cl, Out out, R gin, R gout,
-                                                        const double *__restrict__ stop)
+template <typename C, typename R, int CLOV, int LM, typename In, typename Out, typename UL, typename CL>
+__global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const In in, UL U, CL cl, Out out, R gin,
+                                                        R gout, const double *__restrict__ stop)
 {
     if (stop && stop[0] != 0) return;
     const int tt = xcd_site(2 * g.Vh);
@@ -33,10 +32,10 @@ __global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const 
 }
 
 // out = [g5] (A [g5] x + a D t), output parity pout; NORM: |out|^2 block partials
-template <typename C, typename R, int CLOV, int NORM, int LM, typename X, typename T, typename Out>
-__global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const X x, const T t,
-                                                     const C *__restrict__ U, const R *__restrict__ cl, R a, Out out,
-                                                     R gs, double *partials, const double *__restrict__ stop)
+template <typename C, typename R, int CLOV, int NORM, int LM, typename X, typename T, typename Out, typename UL,
+          typename CL>
+__global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const X x, const T t, UL U, CL cl, R a,
+                                                     Out out, R gs, double *partials, const double *__restrict__ stop)
 {
     if (stop && stop[0] != 0) return;
     const int tt = xcd_site(2 * g.Vh);
@@ -60,14 +59,14 @@ __global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const X x
 
 }  // namespace
 
-template <typename C, typename R, typename In, typename Out>
-int launch_clovinv(pfmp_ctx *ctx, int pout, In in, const C *U, const R *cl, Out out, R gin, R gout, bool clov,
+template <typename C, typename R, typename In, typename Out, typename UL, typename CL>
+int launch_clovinv(pfmp_ctx *ctx, int pout, In in, UL U, CL cl, Out out, R gin, R gout, bool clov,
                    const double *stop)
 {
     dim3 grid(op_nparts(ctx->g)), block(kBlock);
-#define CLOVINV(CL, LM)                                                                                           \
-    hipLaunchKernelGGL((k_hop_clovinv<C, R, CL, LM, In, Out>), grid, block, 0, ctx->stream, ctx->g, pout, in, U, cl, \
-                       out, gin, gout, stop)
+#define CLOVINV(CV, LM)                                                                                           \
+    hipLaunchKernelGGL((k_hop_clovinv<C, R, CV, LM, In, Out, UL, CL>), grid, block, 0, ctx->stream, ctx->g, pout, in, \
+                       U, cl, out, gin, gout, stop)
 #define CLOVINV1(LM) CLOVINV(1, LM)
 #define CLOVINV0(LM) CLOVINV(0, LM)
     const int lm = link_mode(ctx->g);
@@ -80,14 +79,14 @@ int launch_clovinv(pfmp_ctx *ctx, int pout, In in, const C *U, const R *cl, Out 
     return 0;
 }
 
-template <typename C, typename R, typename X, typename T, typename Out>
-int launch_xpay(pfmp_ctx *ctx, int pout, X x, T t, const C *U, const R *cl, R a, Out out, R gs, bool clov,
-                double *partials, const double *stop)
+template <typename C, typename R, typename X, typename T, typename Out, typename UL, typename CL>
+int launch_xpay(pfmp_ctx *ctx, int pout, X x, T t, UL U, CL cl, R a, Out out, R gs, bool clov, double *partials,
+                const double *stop)
 {
     dim3 grid(op_nparts(ctx->g)), block(kBlock);
-#define XPAY(CL, NM, LM)                                                                                           \
-    hipLaunchKernelGGL((k_hop_xpay<C, R, CL, NM, LM, X, T, Out>), grid, block, 0, ctx->stream, ctx->g, pout, x, t, U, \
-                       cl, a, out, gs, partials, stop)
+#define XPAY(CV, NM, LM)                                                                                           \
+    hipLaunchKernelGGL((k_hop_xpay<C, R, CV, NM, LM, X, T, Out, UL, CL>), grid, block, 0, ctx->stream, ctx->g, pout, \
+                       x, t, U, cl, a, out, gs, partials, stop)
 #define XPAY11(LM) XPAY(1, 1, LM)
 #define XPAY10(LM) XPAY(1, 0, LM)
 #define XPAY01(LM) XPAY(0, 1, LM)
@@ -106,25 +105,24 @@ int launch_xpay(pfmp_ctx *ctx, int pout, X x, T t, const C *U, const R *cl, R a,
     return 0;
 }
 
-template int launch_clovinv<double2, double, const double2 *, double2 *>(pfmp_ctx *, int, const double2 *,
-                                                                        const double2 *, const double *, double2 *,
-                                                                        double, double, bool, const double *);
-template int launch_clovinv<float2, float, const float2 *, float2 *>(pfmp_ctx *, int, const float2 *, const float2 *,
-                                                                    const float *, float2 *, float, float, bool,
-                                                                    const double *);
-template int launch_clovinv<float2, float, HalfField, HalfField>(pfmp_ctx *, int, HalfField, const float2 *,
-                                                                const float *, HalfField, float, float, bool,
-                                                                const double *);
-template int launch_xpay<double2, double, const double2 *, const double2 *, double2 *>(
-    pfmp_ctx *, int, const double2 *, const double2 *, const double2 *, const double *, double, double2 *, double,
-    bool, double *, const double *);
-template int launch_xpay<float2, float, const float2 *, const float2 *, float2 *>(
+template int launch_clovinv<double2, double, const double2 *, double2 *, const double2 *, const double *>(
+    pfmp_ctx *, int, const double2 *, const double2 *, const double *, double2 *, double, double, bool,
+    const double *);
+template int launch_clovinv<float2, float, const float2 *, float2 *, const float2 *, const float *>(
+    pfmp_ctx *, int, const float2 *, const float2 *, const float *, float2 *, float, float, bool, const double *);
+template int launch_clovinv<float2, float, HalfField, HalfField, HalfLinks, HalfClover>(pfmp_ctx *, int, HalfField,
+                                                                                       HalfLinks, HalfClover,
+                                                                                       HalfField, float, float, bool,
+                                                                                       const double *);
+template int launch_xpay<double2, double, const double2 *, const double2 *, double2 *, const double2 *,
+                         const double *>(pfmp_ctx *, int, const double2 *, const double2 *, const double2 *,
+                                         const double *, double, double2 *, double, bool, double *, const double *);
+template int launch_xpay<float2, float, const float2 *, const float2 *, float2 *, const float2 *, const float *>(
     pfmp_ctx *, int, const float2 *, const float2 *, const float2 *, const float *, float, float2 *, float, bool,
     double *, const double *);
-template int launch_xpay<float2, float, HalfField, HalfField, HalfField>(pfmp_ctx *, int, HalfField, HalfField,
-                                                                       const float2 *, const float *, float,
-                                                                       HalfField, float, bool, double *,
-                                                                       const double *);
+template int launch_xpay<float2, float, HalfField, HalfField, HalfField, HalfLinks, HalfClover>(
+    pfmp_ctx *, int, HalfField, HalfField, HalfLinks, HalfClover, float, HalfField, float, bool, double *,
+    const double *);
 
 namespace {
 
@@ -153,9 +151,9 @@ int op_apply_M(pfmp_ctx *ctx, int op, int dagger, const double2 *in, double2 *ou
     OpSlot &s = ctx->ops[op];
     double gs = dagger ? -1.0 : 1.0;
     bool cl = op_has_clover(s);
-    int rc = launch_clovinv<double2, double, const double2 *, double2 *>(ctx, 1, in, ctx->U, s.clov[1], tmp_odd, gs, 1.0, cl, nullptr);
+    int rc = launch_clovinv<double2, double, const double2 *, double2 *, const double2 *, const double *>(ctx, 1, in, ctx->U, s.clov[1], tmp_odd, gs, 1.0, cl, nullptr);
     if (rc) return rc;
-    return launch_xpay<double2, double, const double2 *, const double2 *, double2 *>(ctx, 0, in, tmp_odd, ctx->U, s.clov[0], -s.kappa * s.kappa, out, gs, cl,
+    return launch_xpay<double2, double, const double2 *, const double2 *, double2 *, const double2 *, const double *>(ctx, 0, in, tmp_odd, ctx->U, s.clov[0], -s.kappa * s.kappa, out, gs, cl,
                                         norm_partials, nullptr);
 }
 
@@ -173,9 +171,9 @@ int op_apply_M_f32(pfmp_ctx *ctx, int op, int dagger, const float2 *in, float2 *
     OpSlot &s = ctx->ops[op];
     float gs = dagger ? -1.f : 1.f;
     bool cl = op_has_clover(s);
-    int rc = launch_clovinv<float2, float, const float2 *, float2 *>(ctx, 1, in, ctx->Uf, s.clovf[1], tmp_odd, gs, 1.f, cl, nullptr);
+    int rc = launch_clovinv<float2, float, const float2 *, float2 *, const float2 *, const float *>(ctx, 1, in, ctx->Uf, s.clovf[1], tmp_odd, gs, 1.f, cl, nullptr);
     if (rc) return rc;
-    return launch_xpay<float2, float, const float2 *, const float2 *, float2 *>(ctx, 0, in, tmp_odd, ctx->Uf, s.clovf[0], (float)(-s.kappa * s.kappa), out,
+    return launch_xpay<float2, float, const float2 *, const float2 *, float2 *, const float2 *, const float *>(ctx, 0, in, tmp_odd, ctx->Uf, s.clovf[0], (float)(-s.kappa * s.kappa), out,
                                       gs, cl, norm_partials, nullptr);
 }
 
@@ -204,7 +202,7 @@ extern "C" int pfmp_apply_hop(pfmp_ctx *ctx, int out_parity, int dagger, const v
     if (!ctx || !in || !out || (out_parity != 0 && out_parity != 1)) return ctx ? set_err(ctx, PFMP_ERR_ARG, "apply_hop: bad argument") : PFMP_ERR_ARG;
     if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
     double gs = dagger ? -1.0 : 1.0;
-    return launch_clovinv<double2, double, const double2 *, double2 *>(ctx, out_parity, (const double2 *)in, ctx->U, nullptr, (double2 *)out, gs,
+    return launch_clovinv<double2, double, const double2 *, double2 *, const double2 *, const double *>(ctx, out_parity, (const double2 *)in, ctx->U, nullptr, (double2 *)out, gs,
                                            gs, false, nullptr);
 }
 

@@ -137,21 +137,41 @@ __device__ __forceinline__ float2 ld_stream(const float2 *p)
     return make_float2(v.x, v.y);
 }
 
+// Link storage: a pointer to complex planes of the arithmetic type, or the FP16 copy
+// (HalfLinks; SU(3) entries have |u| <= 1, so binary16 needs no scale) read into FP32.
+// lload / lstream fetch element idx (lstream non-temporally where the type allows);
+// lshift offsets the base.
+struct HalfLinks {
+    const __half2 *p;
+};
+template <typename C> __device__ __forceinline__ C lload(const C *__restrict__ U, long idx) { return U[idx]; }
+template <typename C> __device__ __forceinline__ C lstream(const C *__restrict__ U, long idx) { return ld_stream(U + idx); }
+template <typename C> __device__ __forceinline__ C lload(const HalfLinks &U, long idx)
+{
+    return __half22float2(U.p[idx]);
+}
+template <typename C> __device__ __forceinline__ C lstream(const HalfLinks &U, long idx)
+{
+    return __half22float2(U.p[idx]);
+}
+template <typename C> __device__ __forceinline__ const C *lshift(const C *U, long off) { return U + off; }
+__device__ __forceinline__ HalfLinks lshift(const HalfLinks &U, long off) { return HalfLinks{U.p + off}; }
+
 // LM (link mode): bit 0 rebuild the third row, bit 1 streaming loads
-template <int DAG, int LM, typename C>
-__device__ __forceinline__ void su3_vec(const C *__restrict__ U, long stride, int site, const C *h,
-                                        decltype(C::x) f, C *w)
+template <int DAG, int LM, typename C, typename UL>
+__device__ __forceinline__ void su3_vec(UL U, long stride, int site, const C *h, decltype(C::x) f, C *w)
 {
     C u[9];
 #pragma unroll
-    for (int k = 0; k < 6; k++) u[k] = (LM & 2) ? ld_stream(U + k * stride + site) : U[k * stride + site];
+    for (int k = 0; k < 6; k++) u[k] = (LM & 2) ? lstream<C>(U, k * stride + site) : lload<C>(U, k * stride + site);
     if (LM & 1) {
         u[6] = cconj(csub(cmul(u[1], u[5]), cmul(u[2], u[4])));
         u[7] = cconj(csub(cmul(u[2], u[3]), cmul(u[0], u[5])));
         u[8] = cconj(csub(cmul(u[0], u[4]), cmul(u[1], u[3])));
     } else {
 #pragma unroll
-        for (int k = 6; k < 9; k++) u[k] = (LM & 2) ? ld_stream(U + k * stride + site) : U[k * stride + site];
+        for (int k = 6; k < 9; k++)
+            u[k] = (LM & 2) ? lstream<C>(U, k * stride + site) : lload<C>(U, k * stride + site);
     }
 #pragma unroll
     for (int a = 0; a < 3; a++) {
@@ -165,9 +185,9 @@ __device__ __forceinline__ void su3_vec(const C *__restrict__ U, long stride, in
     }
 }
 
-template <int MU, int LM, typename C, typename In>
+template <int MU, int LM, typename C, typename In, typename UL>
 __device__ __forceinline__ void hop_dir_pair(const Geom &g, int pout, int i, const int *c, int hb, const In in,
-                                             const C *__restrict__ U, decltype(C::x) gs, C *up, C *loA, C *loB)
+                                             UL U, decltype(C::x) gs, C *up, C *loA, C *loB)
 {
     using R = decltype(C::x);
     constexpr int IM = (MU == 0 || MU == 2) ? 1 : 0;
@@ -186,7 +206,7 @@ __device__ __forceinline__ void hop_dir_pair(const Geom &g, int pout, int i, con
         C pq = cscale(load_comp(in, g.Vh, jf, 3 * q + a), gs);
         h[a] = csub(pt, unit_mul<IM>(pq, sgp));
     }
-    su3_vec<0, LM>(U + ((long)(pout * 4 + MU) * 9) * Vh, Vh, i, h, (R)sf, w);
+    su3_vec<0, LM>(lshift(U, ((long)(pout * 4 + MU) * 9) * Vh), Vh, i, h, (R)sf, w);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         up[a] = cadd(up[a], w[a]);
@@ -200,7 +220,7 @@ __device__ __forceinline__ void hop_dir_pair(const Geom &g, int pout, int i, con
         C pq = cscale(load_comp(in, g.Vh, jb, 3 * q + a), gs);
         h[a] = cadd(pt, unit_mul<IM>(pq, sgp));
     }
-    su3_vec<1, LM>(U + ((long)((1 - pout) * 4 + MU) * 9) * Vh, Vh, jb, h, (R)sb, w);
+    su3_vec<1, LM>(lshift(U, ((long)((1 - pout) * 4 + MU) * 9) * Vh), Vh, jb, h, (R)sb, w);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         up[a] = cadd(up[a], w[a]);
@@ -213,8 +233,8 @@ __device__ __forceinline__ float pair_swap(float v) { return __shfl_xor(v, 1, 64
 
 // D_hop in (gs = -1 flips the lower spins of the input), chiral block hb of the
 // result at output site i of parity pout; LM: link mode (see su3_vec)
-template <int LM, typename C, typename In>
-__device__ __forceinline__ void hop_pair(const Geom &g, int pout, int i, int hb, const In in, const C *__restrict__ U,
+template <int LM, typename C, typename In, typename UL>
+__device__ __forceinline__ void hop_pair(const Geom &g, int pout, int i, int hb, const In in, UL U,
                                          decltype(C::x) gs, C *blk)
 {
     int c[4];
@@ -283,16 +303,35 @@ __device__ __forceinline__ void store_block(const HalfField &f, int Vh, int i, i
 }
 
 // out[6] = (6x6 Hermitian block b of the clover field at site i) v[6]
-template <typename R, typename C>
-__device__ __forceinline__ void clover_block(const R *__restrict__ cl, int Vh, int i, int b, const C *v, C *out)
+// Clover storage: real planes of the arithmetic type, or the FP16 copy (HalfClover,
+// entries of A and A^-1 are O(1)) read into FP32.  Same layout: 12 diagonal planes, then
+// 30 complex upper-triangle planes.
+struct HalfClover {
+    const __half *p;
+};
+template <typename R> __device__ __forceinline__ R cl_diag(const R *__restrict__ cl, long idx) { return cl[idx]; }
+template <typename C, typename R> __device__ __forceinline__ C cl_off(const R *__restrict__ cl, long Vh, long idx)
 {
-    const C *off = reinterpret_cast<const C *>(cl + 12L * Vh);
+    return reinterpret_cast<const C *>(cl + 12L * Vh)[idx];
+}
+template <typename R> __device__ __forceinline__ R cl_diag(const HalfClover &cl, long idx)
+{
+    return __half2float(cl.p[idx]);
+}
+template <typename C> __device__ __forceinline__ C cl_off(const HalfClover &cl, long Vh, long idx)
+{
+    return __half22float2(reinterpret_cast<const __half2 *>(cl.p + 12L * Vh)[idx]);
+}
+
+template <typename R, typename C, typename CL>
+__device__ __forceinline__ void clover_block(CL cl, int Vh, int i, int b, const C *v, C *out)
+{
     R d[6];
     C o[15];
 #pragma unroll
-    for (int k = 0; k < 6; k++) d[k] = cl[(long)(b * 6 + k) * Vh + i];
+    for (int k = 0; k < 6; k++) d[k] = cl_diag<R>(cl, (long)(b * 6 + k) * Vh + i);
 #pragma unroll
-    for (int m = 0; m < 15; m++) o[m] = off[(long)(b * 15 + m) * Vh + i];
+    for (int m = 0; m < 15; m++) o[m] = cl_off<C>(cl, Vh, (long)(b * 15 + m) * Vh + i);
 #pragma unroll
     for (int r = 0; r < 6; r++) out[r] = cscale(v[r], d[r]);
     int m = 0;
@@ -305,8 +344,8 @@ __device__ __forceinline__ void clover_block(const R *__restrict__ cl, int Vh, i
         }
 }
 
-template <typename R, typename C>
-__device__ __forceinline__ void clover_apply(const R *__restrict__ cl, int Vh, int i, const C *v, C *out)
+template <typename R, typename C, typename CL>
+__device__ __forceinline__ void clover_apply(CL cl, int Vh, int i, const C *v, C *out)
 {
     clover_block<R, C>(cl, Vh, i, 0, v, out);
     clover_block<R, C>(cl, Vh, i, 1, v + 6, out + 6);
@@ -329,35 +368,36 @@ __device__ __forceinline__ void block_sum_store(double v, double *partials)
 }
 
 
-// operator stages (dslash.hip); In / X / T / Out: const C* / C* or HalfField
-template <typename C, typename R, typename In, typename Out>
-int launch_clovinv(pfmp_ctx *ctx, int pout, In in, const C *U, const R *cl, Out out, R gin, R gout, bool clov,
+// operator stages (dslash.hip); In / X / T / Out: const C* / C* or HalfField; UL: const C*
+// or HalfLinks; CL: const R* or HalfClover
+template <typename C, typename R, typename In, typename Out, typename UL, typename CL>
+int launch_clovinv(pfmp_ctx *ctx, int pout, In in, UL U, CL cl, Out out, R gin, R gout, bool clov,
                    const double *stop);
-template <typename C, typename R, typename X, typename T, typename Out>
-int launch_xpay(pfmp_ctx *ctx, int pout, X x, T t, const C *U, const R *cl, R a, Out out, R gs, bool clov,
-                double *partials, const double *stop);
+template <typename C, typename R, typename X, typename T, typename Out, typename UL, typename CL>
+int launch_xpay(pfmp_ctx *ctx, int pout, X x, T t, UL U, CL cl, R a, Out out, R gs, bool clov, double *partials,
+                const double *stop);
 
 inline int clovinv64(pfmp_ctx *ctx, int pout, const double2 *in, const double *cl, double2 *out, double gin,
                      double gout, bool clov, const double *stop)
 {
-    return launch_clovinv<double2, double, const double2 *, double2 *>(ctx, pout, in, ctx->U, cl, out, gin, gout,
+    return launch_clovinv<double2, double, const double2 *, double2 *, const double2 *, const double *>(ctx, pout, in, ctx->U, cl, out, gin, gout,
                                                                        clov, stop);
 }
 inline int xpay64(pfmp_ctx *ctx, int pout, const double2 *x, const double2 *t, const double *cl, double a,
                   double2 *out, double gs, bool clov, double *partials, const double *stop)
 {
-    return launch_xpay<double2, double, const double2 *, const double2 *, double2 *>(ctx, pout, x, t, ctx->U, cl, a,
+    return launch_xpay<double2, double, const double2 *, const double2 *, double2 *, const double2 *, const double *>(ctx, pout, x, t, ctx->U, cl, a,
                                                                                      out, gs, clov, partials, stop);
 }
 inline int clovinv32(pfmp_ctx *ctx, int pout, const float2 *in, const float *cl, float2 *out, float gin, float gout,
                      bool clov, const double *stop)
 {
-    return launch_clovinv<float2, float, const float2 *, float2 *>(ctx, pout, in, ctx->Uf, cl, out, gin, gout, clov,
+    return launch_clovinv<float2, float, const float2 *, float2 *, const float2 *, const float *>(ctx, pout, in, ctx->Uf, cl, out, gin, gout, clov,
                                                                    stop);
 }
 inline int xpay32(pfmp_ctx *ctx, int pout, const float2 *x, const float2 *t, const float *cl, float a, float2 *out,
                   float gs, bool clov, double *partials, const double *stop)
 {
-    return launch_xpay<float2, float, const float2 *, const float2 *, float2 *>(ctx, pout, x, t, ctx->Uf, cl, a, out,
+    return launch_xpay<float2, float, const float2 *, const float2 *, float2 *, const float2 *, const float *>(ctx, pout, x, t, ctx->Uf, cl, a, out,
                                                                                 gs, clov, partials, stop);
 }

@@ -150,6 +150,7 @@ struct OpSlot {
     double kappa = 0, csw = 0;
     double *clov[2] = {nullptr, nullptr};   // FP64: A_ee on [0] (even), A_oo^-1 on [1] (odd)
     float *clovf[2] = {nullptr, nullptr};   // FP32 copies
+    void *clovh[2] = {nullptr, nullptr};    // FP16 copies (binary16 reals, same layout)
     double logdet_odd = 0;                  // sum_{x odd} ln det A(x)
     double *ldpart = nullptr;               // per-block ln det A_oo partials (device)
     bool ld_dirty = false;                  // ldpart newer than logdet_odd
@@ -164,6 +165,7 @@ struct pfmp_ctx {
     int nblk_red = 0;            // blocks of the reduction kernels
     double2 *U = nullptr;        // internal FP64 gauge field
     float2 *Uf = nullptr;        // FP32 copy
+    void *Uh = nullptr;          // FP16 copy (binary16 complex planes), for the FP16-storage inner solver
     bool have_gauge = false;
     bool uf_stale = true;        // Uf older than U
     double2 *Fhat = nullptr;     // clover field strength [2 parities][6 planes][9][Vh], shared by all slots

@@ -69,9 +69,8 @@ __global__ __launch_bounds__(kRedBlock) void k_m_restart(const double *__restric
 // FP32 Khat p from t = Mhat p and T' (as in the FP64 solver), fused with
 // x += alpha p, r -= alpha Khat p and FP64 |r|^2 partials.  alpha = |r|^2 / <p, Khat p>
 // is formed in every block from the stage-2 partials; block 0 keeps |r|^2 for beta.
-template <int CLOV, int LM, typename S>
-__global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T, const float2 *__restrict__ U,
-                                                   const float *__restrict__ cl, float a, const S p,
+template <int CLOV, int LM, typename S, typename UL, typename CL>
+__global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T, UL U, CL cl, float a, const S p,
                                                    float2 *__restrict__ x, float2 *__restrict__ r,
                                                    double *__restrict__ st, double *__restrict__ partials,
                                                    const double *__restrict__ part_pap, int npap)
@@ -186,16 +185,26 @@ __global__ __launch_bounds__(kRedBlock) void k_m_residual(long n, const double2 
 
 }  // namespace
 
+// Inner-solver storage: FP32 spinors with the FP32 links and clover, or FP16 spinors
+// (per-site scale) with the FP16 links and clover; arithmetic in FP32 either way.
 template <typename S> struct Store;
 template <> struct Store<float2 *> {
     using In = const float2 *;
+    using UL = const float2 *;
+    using CL = const float *;
     static size_t bytes(long Vh) { return 8L * 12 * Vh; }
     static float2 *make(void *p, long) { return (float2 *)p; }
+    static UL links(const pfmp_ctx *ctx) { return ctx->Uf; }
+    static CL clover(const OpSlot &s, int p) { return s.clovf[p]; }
 };
 template <> struct Store<HalfField> {
     using In = HalfField;
+    using UL = HalfLinks;
+    using CL = HalfClover;
     static size_t bytes(long Vh) { return 4L * 12 * Vh + 4L * Vh; }
     static HalfField make(void *p, long Vh) { return HalfField{(__half2 *)p, (float *)((char *)p + 4L * 12 * Vh)}; }
+    static UL links(const pfmp_ctx *ctx) { return HalfLinks{(const __half2 *)ctx->Uh}; }
+    static CL clover(const OpSlot &s, int p) { return HalfClover{(const __half *)s.clovh[p]}; }
 };
 
 template <typename S>
@@ -203,9 +212,13 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
                       pfmp_solver_stats *st)
 {
     using In = typename Store<S>::In;
+    using UL = typename Store<S>::UL;
+    using CL = typename Store<S>::CL;
     auto t0 = std::chrono::steady_clock::now();
     const Geom &g = ctx->g;
     OpSlot &s = ctx->ops[op];
+    const UL links = Store<S>::links(ctx);
+    const CL clo0 = Store<S>::clover(s, 0), clo1 = Store<S>::clover(s, 1);
     const long n = 12L * g.Vh;
     const size_t vb = sizeof(double) * spinor_reals(g), fb = vb / 2;
     const int nb = op_nparts(g);
@@ -250,17 +263,17 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
     // one inner iteration: 5 launches with fixed arguments, replayed as a graph
     auto iteration = [&]() -> int {
         int e;
-        if ((e = launch_clovinv<float2, float, In, S>(ctx, 1, ps, ctx->Uf, s.clovf[1], Ts, 1.f, 1.f, cl, sc + M_DONE)))
+        if ((e = launch_clovinv<float2, float, In, S, UL, CL>(ctx, 1, ps, links, clo1, Ts, 1.f, 1.f, cl, sc + M_DONE)))
             return e;
-        if ((e = launch_xpay<float2, float, In, In, S>(ctx, 0, ps, Ts, ctx->Uf, s.clovf[0], mk2, ts, 1.f, cl, part_a,
-                                                        sc + M_DONE)))
+        if ((e = launch_xpay<float2, float, In, In, S, UL, CL>(ctx, 0, ps, Ts, links, clo0, mk2, ts, 1.f, cl, part_a,
+                                                                sc + M_DONE)))
             return e;
-        if ((e = launch_clovinv<float2, float, In, S>(ctx, 1, ts, ctx->Uf, s.clovf[1], Ts, -1.f, 1.f, cl,
-                                                       sc + M_DONE)))
+        if ((e = launch_clovinv<float2, float, In, S, UL, CL>(ctx, 1, ts, links, clo1, Ts, -1.f, 1.f, cl,
+                                                               sc + M_DONE)))
             return e;
-#define MHOP4(CL, LM)                                                                                       \
-    hipLaunchKernelGGL((k_m_hop4<CL, LM, In>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, ctx->Uf,     \
-                       s.clovf[0], mk2, ps, xs, rs, sc, part_b, part_a, nb)
+#define MHOP4(CV, LM)                                                                                       \
+    hipLaunchKernelGGL((k_m_hop4<CV, LM, In, UL, CL>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, links, \
+                       clo0, mk2, ps, xs, rs, sc, part_b, part_a, nb)
 #define MHOP4_1(LM) MHOP4(1, LM)
 #define MHOP4_0(LM) MHOP4(0, LM)
         if (cl) { PFMP_LM_SWITCH(link_mode(g), MHOP4_1) }
@@ -277,8 +290,9 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
     key_add(key, 2 + (int)sizeof(S));   // mixed-precision iteration, storage type
     key_geom(key, g);
     for (const void *ptr : {(const void *)pb, (const void *)tb, (const void *)Tb, (const void *)xs, (const void *)rs, (const void *)part_a,
-                            (const void *)part_b, (const void *)sc, (const void *)ctx->Uf, (const void *)s.clovf[0],
-                            (const void *)s.clovf[1]})
+                            (const void *)part_b, (const void *)sc, (const void *)ctx->Uf, (const void *)ctx->Uh,
+                            (const void *)s.clovf[0], (const void *)s.clovf[1], (const void *)s.clovh[0],
+                            (const void *)s.clovh[1]})
         key_add(key, ptr);
     key_add(key, mk2);
     key_add(key, (int)cl);
