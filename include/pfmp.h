@@ -173,7 +173,7 @@ typedef struct {
     double tol;          /* stop at |b - A x| <= tol |b| (relative 2-norm, recomputed in FP64 at exit) */
     int maxiter;
     int prec;            /* pfmp_prec of the inner operator; FP32/F16 use FP64 reliable updates */
-    double delta;        /* reliable-update trigger: residual drop factor (mixed precision); 0 = 0.1 */
+    double delta;        /* reliable-update trigger: residual drop factor (mixed precision); 0 = 0.01 FP32, 0.1 FP16 */
     int check_every;     /* iterations between host convergence checks (0 = automatic) */
 } pfmp_solver_params;
 

@@ -99,19 +99,7 @@ __device__ __forceinline__ void project(const C *p, C *h)
 //   mu = z: f = (hb ? i : -i), r = -f
 //   mu = t: f = r = 1
 // (the chiral-basis projectors written per half-spin).  The two partial lower spins
-// are combined by one lane swap at the end (pair_block).
-
-template <typename C>
-__device__ __forceinline__ C load_comp(const C *__restrict__ f, int Vh, int j, int k)
-{
-    return f[(long)k * Vh + j];
-}
-__device__ __forceinline__ float2 load_comp(const HalfField &f, int Vh, int j, int k)
-{
-    float2 a = __half22float2(f.h[(long)k * Vh + j]);
-    const float sc = f.s[j];
-    return make_float2(a.x * sc, a.y * sc);
-}
+// are combined by one lane swap at the end (hop_pair).
 
 template <int IM, typename C>
 __device__ __forceinline__ C unit_mul(C v, decltype(C::x) sg)
@@ -119,9 +107,6 @@ __device__ __forceinline__ C unit_mul(C v, decltype(C::x) sg)
     return IM ? mk<C>(-sg * v.y, sg * v.x) : mk<C>(sg * v.x, sg * v.y);
 }
 
-// w = f U h (DAG = 0) or f U^dag h (DAG = 1) for one half-spin (3 colours).  With
-// recon the link is in SU(3) and its third row is rebuilt as the conjugate cross
-// product of the first two (6 of the 9 planes read).
 // Streaming (non-temporal) load: every link is read once per hop launch, so it should
 // not displace the neighbour spinors, which are read eight times, from the caches.
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
@@ -157,74 +142,188 @@ template <typename C> __device__ __forceinline__ C lstream(const HalfLinks &U, l
 template <typename C> __device__ __forceinline__ const C *lshift(const C *U, long off) { return U + off; }
 __device__ __forceinline__ HalfLinks lshift(const HalfLinks &U, long off) { return HalfLinks{U.p + off}; }
 
+// ------------------------------------------------------------------ leg pipeline
+//
+// One leg is one of the 8 hops (direction mu, forward or backward): the neighbour's
+// half-spin hb and partner lower spin q, and the link.  Its operands are first loaded
+// raw (FP16 stays packed) into a Leg, and only later decoded and applied, so that the
+// loads of PD legs are in flight while one is computed.  With a single leg in flight
+// every hop waits for 8 memory round trips in a row, which bounds the kernel whenever the
+// lattice gives each SIMD only a few waves (16^3 x 32: two per SIMD).  The arithmetic and
+// its order are the same for every PD.
+
+template <typename C, typename In>
+struct SpinLeg {
+    C v[6];
+    __device__ __forceinline__ void load(const In f, long Vh, int j, int k0, int k1)
+    {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            v[a] = f[(long)(k0 + a) * Vh + j];
+            v[3 + a] = f[(long)(k1 + a) * Vh + j];
+        }
+    }
+    __device__ __forceinline__ C raw(int k) const { return v[k]; }
+    __device__ __forceinline__ decltype(C::x) scale() const { return 1; }
+};
+// FP16: raw() gives the stored values, scale() the site's factor
+template <>
+struct SpinLeg<float2, HalfField> {
+    __half2 v[6];
+    float s;
+    __device__ __forceinline__ void load(const HalfField &f, long Vh, int j, int k0, int k1)
+    {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            v[a] = f.h[(long)(k0 + a) * Vh + j];
+            v[3 + a] = f.h[(long)(k1 + a) * Vh + j];
+        }
+        s = f.s[j];
+    }
+    __device__ __forceinline__ float2 raw(int k) const { return __half22float2(v[k]); }
+    __device__ __forceinline__ float scale() const { return s; }
+};
+
+// N link planes (6 with the third row rebuilt, else 9); ST: streaming loads
+template <typename C, typename UL, int N>
+struct LinkLeg {
+    C u[N];
+    template <int ST>
+    __device__ __forceinline__ void load(UL U, long stride, long site)
+    {
+#pragma unroll
+        for (int k = 0; k < N; k++) u[k] = ST ? lstream<C>(U, k * stride + site) : lload<C>(U, k * stride + site);
+    }
+    __device__ __forceinline__ C get(int k) const { return u[k]; }
+};
+template <int N>
+struct LinkLeg<float2, HalfLinks, N> {
+    __half2 u[N];
+    template <int ST>
+    __device__ __forceinline__ void load(const HalfLinks &U, long stride, long site)
+    {
+#pragma unroll
+        for (int k = 0; k < N; k++) u[k] = U.p[k * stride + site];
+    }
+    __device__ __forceinline__ float2 get(int k) const { return __half22float2(u[k]); }
+};
+
 // LM (link mode): bit 0 rebuild the third row, bit 1 streaming loads
-template <int DAG, int LM, typename C, typename UL>
-__device__ __forceinline__ void su3_vec(UL U, long stride, int site, const C *h, decltype(C::x) f, C *w)
+template <typename C, typename In, typename UL, int LM>
+struct Leg {
+    SpinLeg<C, In> sp;
+    LinkLeg<C, UL, (LM & 1) ? 6 : 9> lk;
+    decltype(C::x) sg;   // boundary sign of the hop
+};
+
+// legs in flight per lane: all 8 for FP16 storage (13 registers per leg); for FP32 and
+// FP64 fewer, as their legs take 2x and 4x the registers
+#ifndef PFMP_LEGS_F16
+#define PFMP_LEGS_F16 8
+#endif
+#ifndef PFMP_LEGS_F32
+#define PFMP_LEGS_F32 4
+#endif
+#ifndef PFMP_LEGS_F64
+#define PFMP_LEGS_F64 2
+#endif
+template <typename In> struct LegDepth { static constexpr int value = PFMP_LEGS_F64; };
+template <> struct LegDepth<HalfField> { static constexpr int value = PFMP_LEGS_F16; };
+template <> struct LegDepth<const float2 *> { static constexpr int value = PFMP_LEGS_F32; };
+template <> struct LegDepth<float2 *> { static constexpr int value = PFMP_LEGS_F32; };
+
+template <int MU, int DIR, int LM, typename C, typename In, typename UL>
+__device__ __forceinline__ void leg_load(const Geom &g, int pout, int i, const int *c, int hb, const In in, UL U,
+                                         Leg<C, In, UL, LM> &l)
+{
+    int s;
+    const int j = eo_neighbour(g, c, MU, DIR ? -1 : +1, &s);
+    const int q = MU < 2 ? 3 - hb : 2 + hb;
+    l.sp.load(in, g.Vh, j, 3 * hb, 3 * q);
+    // forward: U_mu(x) on the output parity; backward: U_mu(x - mu) on the other one
+    const int lp = DIR ? 1 - pout : pout;
+    l.lk.template load<(LM >> 1) & 1>(lshift(U, ((long)(lp * 4 + MU) * 9) * g.Vh), g.Vh, DIR ? j : i);
+    l.sg = (decltype(C::x))s;
+}
+
+// w = U h (DIR = 0) or U^dag h (DIR = 1) for one half-spin (3 colours).  With recon the
+// link is in SU(3) and its third row is the conjugate cross product of the first two.
+template <int DIR, int LM, typename C, typename LL>
+__device__ __forceinline__ void leg_su3(const LL &L, const C *h, C *w)
 {
     C u[9];
 #pragma unroll
-    for (int k = 0; k < 6; k++) u[k] = (LM & 2) ? lstream<C>(U, k * stride + site) : lload<C>(U, k * stride + site);
-    if (LM & 1) {
+    for (int k = 0; k < 6; k++) u[k] = L.get(k);
+    if constexpr ((LM & 1) != 0) {
         u[6] = cconj(csub(cmul(u[1], u[5]), cmul(u[2], u[4])));
         u[7] = cconj(csub(cmul(u[2], u[3]), cmul(u[0], u[5])));
         u[8] = cconj(csub(cmul(u[0], u[4]), cmul(u[1], u[3])));
     } else {
 #pragma unroll
-        for (int k = 6; k < 9; k++)
-            u[k] = (LM & 2) ? lstream<C>(U, k * stride + site) : lload<C>(U, k * stride + site);
+        for (int k = 6; k < 9; k++) u[k] = L.get(k);
     }
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         C acc = mk<C>(0, 0);
 #pragma unroll
         for (int b = 0; b < 3; b++) {
-            if (DAG) cfmac(acc, u[3 * b + a], h[b]);
+            if (DIR) cfmac(acc, u[3 * b + a], h[b]);
             else cfma(acc, u[3 * a + b], h[b]);
         }
-        w[a] = cscale(acc, f);
+        w[a] = acc;
     }
 }
 
-template <int MU, int LM, typename C, typename In, typename UL>
-__device__ __forceinline__ void hop_dir_pair(const Geom &g, int pout, int i, const int *c, int hb, const In in,
-                                             UL U, decltype(C::x) gs, C *up, C *loA, C *loB)
+// forward leg: (1 - g_mu) U_mu(x) psi(x + mu); backward: (1 + g_mu) U_mu(x - mu)^dag psi(x - mu)
+template <int MU, int DIR, int LM, typename C, typename LegT>
+__device__ __forceinline__ void leg_apply(const LegT &l, int hb, decltype(C::x) gs, C *up, C *loA, C *loB)
 {
     using R = decltype(C::x);
     constexpr int IM = (MU == 0 || MU == 2) ? 1 : 0;
-    const long Vh = g.Vh;
     const R sgp = MU == 0 ? (R)-1 : (MU == 3 ? (R)1 : (hb ? (R)1 : (R)-1));
     const R sgr = MU == 0 ? (R)1 : (MU == 2 ? -sgp : sgp);
-    const int q = MU < 2 ? 3 - hb : 2 + hb;
     C *lo = MU < 2 ? loA : loB;
+    // The signs (all +-1) are combined before they meet the data, so each costs nothing per
+    // component; the neighbour's FP16 scale and the boundary sign multiply U h once.
+    const R fq = sgp * gs;
+    const R fu = l.sg * l.sp.scale(), fl = fu * sgr;
     C h[3], w[3];
-    int sf, sb;
-    // forward: (1 - g_mu) U_mu(x) psi(x + mu)
-    const int jf = eo_neighbour(g, c, MU, +1, &sf);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        C pt = load_comp(in, g.Vh, jf, 3 * hb + a);
-        C pq = cscale(load_comp(in, g.Vh, jf, 3 * q + a), gs);
-        h[a] = csub(pt, unit_mul<IM>(pq, sgp));
+        const C pt = l.sp.raw(a), pq = l.sp.raw(3 + a);
+        h[a] = DIR ? cadd(pt, unit_mul<IM>(pq, fq)) : csub(pt, unit_mul<IM>(pq, fq));
     }
-    su3_vec<0, LM>(lshift(U, ((long)(pout * 4 + MU) * 9) * Vh), Vh, i, h, (R)sf, w);
+    leg_su3<DIR, LM>(l.lk, h, w);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        up[a] = cadd(up[a], w[a]);
-        lo[a] = csub(lo[a], unit_mul<IM>(w[a], sgr));
+        up[a] = cadd(up[a], cscale(w[a], fu));
+        lo[a] = DIR ? cadd(lo[a], unit_mul<IM>(w[a], fl)) : csub(lo[a], unit_mul<IM>(w[a], fl));
     }
-    // backward: (1 + g_mu) U_mu(x - mu)^dag psi(x - mu)
-    const int jb = eo_neighbour(g, c, MU, -1, &sb);
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        C pt = load_comp(in, g.Vh, jb, 3 * hb + a);
-        C pq = cscale(load_comp(in, g.Vh, jb, 3 * q + a), gs);
-        h[a] = cadd(pt, unit_mul<IM>(pq, sgp));
+}
+
+// apply leg L from slot L % PD, then refill that slot with leg L + PD
+template <int L, int PD, int LM, typename C, typename In, typename UL>
+__device__ __forceinline__ void hop_legs(const Geom &g, int pout, int i, const int *c, int hb, const In in, UL U,
+                                         decltype(C::x) gs, Leg<C, In, UL, LM> *buf, C *up, C *loA, C *loB)
+{
+    if constexpr (L < 8) {
+        leg_apply<(L >> 1), (L & 1), LM, C>(buf[L % PD], hb, gs, up, loA, loB);
+        if constexpr (L + PD < 8) {
+            leg_load<((L + PD) >> 1), ((L + PD) & 1), LM, C>(g, pout, i, c, hb, in, U, buf[L % PD]);
+            // keep the scheduler from sinking the loads to their first use
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        hop_legs<L + 1, PD, LM, C>(g, pout, i, c, hb, in, U, gs, buf, up, loA, loB);
     }
-    su3_vec<1, LM>(lshift(U, ((long)((1 - pout) * 4 + MU) * 9) * Vh), Vh, jb, h, (R)sb, w);
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        up[a] = cadd(up[a], w[a]);
-        lo[a] = cadd(lo[a], unit_mul<IM>(w[a], sgr));
+}
+
+template <int L, int PD, int LM, typename C, typename In, typename UL>
+__device__ __forceinline__ void hop_prime(const Geom &g, int pout, int i, const int *c, int hb, const In in, UL U,
+                                          Leg<C, In, UL, LM> *buf)
+{
+    if constexpr (L < PD) {
+        leg_load<(L >> 1), (L & 1), LM, C>(g, pout, i, c, hb, in, U, buf[L]);
+        hop_prime<L + 1, PD, LM, C>(g, pout, i, c, hb, in, U, buf);
     }
 }
 
@@ -232,8 +331,8 @@ __device__ __forceinline__ double pair_swap(double v) { return __shfl_xor(v, 1, 
 __device__ __forceinline__ float pair_swap(float v) { return __shfl_xor(v, 1, 64); }
 
 // D_hop in (gs = -1 flips the lower spins of the input), chiral block hb of the
-// result at output site i of parity pout; LM: link mode (see su3_vec)
-template <int LM, typename C, typename In, typename UL>
+// result at output site i of parity pout; LM: link mode (see Leg)
+template <int LM, typename C, typename In, typename UL, int PD = LegDepth<In>::value>
 __device__ __forceinline__ void hop_pair(const Geom &g, int pout, int i, int hb, const In in, UL U,
                                          decltype(C::x) gs, C *blk)
 {
@@ -242,10 +341,10 @@ __device__ __forceinline__ void hop_pair(const Geom &g, int pout, int i, int hb,
     C up[3], loA[3], loB[3];   // upper spin hb; lower spins 3 - hb and 2 + hb
 #pragma unroll
     for (int a = 0; a < 3; a++) up[a] = loA[a] = loB[a] = mk<C>(0, 0);
-    hop_dir_pair<0, LM, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
-    hop_dir_pair<1, LM, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
-    hop_dir_pair<2, LM, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
-    hop_dir_pair<3, LM, C>(g, pout, i, c, hb, in, U, gs, up, loA, loB);
+    Leg<C, In, UL, LM> buf[PD];
+    hop_prime<0, PD, LM, C>(g, pout, i, c, hb, in, U, buf);
+    __builtin_amdgcn_sched_barrier(0);
+    hop_legs<0, PD, LM, C>(g, pout, i, c, hb, in, U, gs, buf, up, loA, loB);
     // lane 0 keeps spin 0 and takes spin 1 from lane 1; lane 1 sums the lower spins
     C x[6];
 #pragma unroll

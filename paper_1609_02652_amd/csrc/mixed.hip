@@ -10,6 +10,7 @@
 // direction ps.  The solve ends only when the FP64 true residual meets tol.
 #include <chrono>
 #include <cmath>
+#include <type_traits>
 
 #include "hop.h"
 
@@ -235,7 +236,9 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
     const double2 *b = (const double2 *)b_;
     double2 *x = (double2 *)x_;
     double *sc = ctx->scal + kMixBase;
-    const double delta = prm->delta > 0 ? prm->delta : 0.1;
+    // default trigger: FP32 storage keeps the recurrence close to the true residual, so rare updates
+    // (a 100x drop) cost nothing in iterations; FP16 storage drifts sooner and wants one per 10x drop
+    const double delta = prm->delta > 0 ? prm->delta : (std::is_same<S, float2 *>::value ? 0.01 : 0.1);
     const bool cl = s.csw != 0;
     const float mk2 = (float)(-s.kappa * s.kappa);
     int rc;
