@@ -42,13 +42,17 @@ void *ws_alloc(pfmp_ctx *ctx, size_t bytes, int slot)
     return w->buf[slot];
 }
 
-int graph_run(pfmp_ctx *ctx, const std::vector<uint64_t> &key, int reps, const std::function<int()> &issue)
+#ifndef PFMP_UNROLL
+#define PFMP_UNROLL 4
+#endif
+
+namespace {
+// the executable graph of `copies` back-to-back issues of the launches (captured on first use)
+int graph_get(pfmp_ctx *ctx, const std::vector<uint64_t> &key0, int copies, const std::function<int()> &issue,
+              hipGraphExec_t *out)
 {
-    if (!ctx->use_graphs) {
-        for (int r = 0; r < reps; r++)
-            if (int rc = issue()) return rc;
-        return 0;
-    }
+    std::vector<uint64_t> key = key0;
+    key.push_back(0x5eed0000u + (uint64_t)copies);
     hipGraphExec_t exec = nullptr;
     for (size_t k = 0; k < ctx->graphs.size(); k++)
         if (ctx->graphs[k].key == key) {
@@ -60,7 +64,8 @@ int graph_run(pfmp_ctx *ctx, const std::vector<uint64_t> &key, int reps, const s
         hipStream_t orig = ctx->stream;
         HIPCHK(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
         ctx->stream = ctx->cap;
-        int rc = issue();
+        int rc = 0;
+        for (int c = 0; c < copies && !rc; c++) rc = issue();
         ctx->stream = orig;
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
@@ -71,13 +76,38 @@ int graph_run(pfmp_ctx *ctx, const std::vector<uint64_t> &key, int reps, const s
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         hipGraphDestroy(graph);
         if (e != hipSuccess) return set_err(ctx, PFMP_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
-        if (ctx->graphs.size() >= 32) {
+        if (ctx->graphs.size() >= 64) {
             hipGraphExecDestroy(ctx->graphs.front().exec);
             ctx->graphs.erase(ctx->graphs.begin());
         }
         ctx->graphs.push_back({key, exec});
     }
-    for (int r = 0; r < reps; r++) HIPCHK(ctx, hipGraphLaunch(exec, ctx->stream));
+    *out = exec;
+    return 0;
+}
+}  // namespace
+
+// reps issues of one iteration's launches: graphs of PFMP_UNROLL iterations, then single
+// iterations for the rest (one graph launch per iteration would leave the GPU idle between them)
+int graph_run(pfmp_ctx *ctx, const std::vector<uint64_t> &key, int reps, const std::function<int()> &issue)
+{
+    if (!ctx->use_graphs) {
+        for (int r = 0; r < reps; r++)
+            if (int rc = issue()) return rc;
+        return 0;
+    }
+    hipGraphExec_t exec = nullptr;
+    int rc;
+    const int nu = PFMP_UNROLL > 1 ? reps / PFMP_UNROLL : 0;
+    if (nu > 0) {
+        if ((rc = graph_get(ctx, key, PFMP_UNROLL, issue, &exec))) return rc;
+        for (int r = 0; r < nu; r++) HIPCHK(ctx, hipGraphLaunch(exec, ctx->stream));
+    }
+    const int rest = reps - nu * PFMP_UNROLL;
+    if (rest > 0) {
+        if ((rc = graph_get(ctx, key, 1, issue, &exec))) return rc;
+        for (int r = 0; r < rest; r++) HIPCHK(ctx, hipGraphLaunch(exec, ctx->stream));
+    }
     return 0;
 }
 
