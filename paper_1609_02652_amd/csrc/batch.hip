@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_b_xpay(Geom g, BatchT<R> b, VecsT<C>
         for (int k = 0; k < 6; k++) {
             C base = CLOV ? ax[k] : xv[k];
             acc[k] = mk<C>(base.x + a * acc[k].x, base.y + a * acc[k].y);
-            nrm += (double)acc[k].x * acc[k].x + (double)acc[k].y * acc[k].y;
+            cnorm_acc(nrm, acc[k]);
         }
         store_block(x.out[r], g.Vh, i, hb, gs, acc);
     }
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_b_hop4(Geom g, BatchT<R> b, VecsT<C>
             rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
             xx[e] = xv;
             rv_[e] = rv;
-            nrm += (double)rv.x * rv.x + (double)rv.y * rv.y;
+            cnorm_acc(nrm, rv);
         }
     }
     batch_partial(nrm, lb, b.nsb * b.n, partials);

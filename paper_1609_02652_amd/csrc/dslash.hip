@@ -49,8 +49,8 @@ __global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const X x
 #pragma unroll
         for (int k = 0; k < 6; k++) {
             C base = CLOV ? ax[k] : xv[k];
-            acc[k] = mk<C>(base.x + a * acc[k].x, base.y + a * acc[k].y);
-            if (NORM) nrm += (double)acc[k].x * acc[k].x + (double)acc[k].y * acc[k].y;
+            acc[k] = mk<C>(fmadd(a, acc[k].x, base.x), fmadd(a, acc[k].y, base.y));
+            if (NORM) cnorm_acc(nrm, acc[k]);
         }
         store_block(out, g.Vh, i, hb, gs, acc);
     }

@@ -30,9 +30,6 @@ template <> struct cplx_t<float> { using type = float2; };
 template <typename C> PFMP_HD C mk(decltype(C::x) a, decltype(C::x) b) { C c; c.x = a; c.y = b; return c; }
 template <typename C> PFMP_HD C cadd(C a, C b) { return mk<C>(a.x + b.x, a.y + b.y); }
 template <typename C> PFMP_HD C csub(C a, C b) { return mk<C>(a.x - b.x, a.y - b.y); }
-template <typename C> PFMP_HD C cmul(C a, C b) { return mk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
-// conj(a) * b
-template <typename C> PFMP_HD C cmulc(C a, C b) { return mk<C>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
 template <typename C> PFMP_HD C cconj(C a) { return mk<C>(a.x, -a.y); }
 template <typename C> PFMP_HD C cscale(C a, decltype(C::x) s) { return mk<C>(a.x * s, a.y * s); }
 template <typename C> PFMP_HD C ctimesi(C a) { return mk<C>(-a.y, a.x); }     // i a
@@ -41,6 +38,22 @@ template <typename C> PFMP_HD C cneg(C a) { return mk<C>(-a.x, -a.y); }
 // fused multiply-add a b + c (one rounding)
 PFMP_HD double fmadd(double a, double b, double c) { return fma(a, b, c); }
 PFMP_HD float fmadd(float a, float b, float c) { return fmaf(a, b, c); }
+// a b and conj(a) b, each part one product and one fused multiply-add in a fixed order
+// (left free, the compiler may fuse either product, and not always the same one in two
+// instantiations of a kernel)
+template <typename C> PFMP_HD C cmul(C a, C b)
+{
+    return mk<C>(fmadd(a.x, b.x, -(a.y * b.y)), fmadd(a.x, b.y, a.y * b.x));
+}
+template <typename C> PFMP_HD C cmulc(C a, C b)
+{
+    return mk<C>(fmadd(a.x, b.x, a.y * b.y), fmadd(a.x, b.y, -(a.y * b.x)));
+}
+// s += |v|^2 in FP64, in a fixed order
+template <typename C> PFMP_HD void cnorm_acc(double &s, C v)
+{
+    s = fmadd((double)v.y, (double)v.y, fmadd((double)v.x, (double)v.x, s));
+}
 // acc += a * b as four fused multiply-adds
 template <typename C> PFMP_HD void cfma(C &acc, C a, C b)
 {

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T,
             rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
             x[e] = xv;
             r[e] = rv;
-            nrm += (double)rv.x * rv.x + (double)rv.y * rv.y;
+            cnorm_acc(nrm, rv);
         }
     }
     block_sum_store<float2>(nrm, partials);

@@ -545,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_f_hop4(Geom g, const double2 *__rest
             x[e] = xv;
             r[e] = rv;
             q[e] = kp;
-            nrm += rv.x * rv.x + rv.y * rv.y;
+            cnorm_acc(nrm, rv);
         }
     }
     block_sum_store<double2>(nrm, part_rr);

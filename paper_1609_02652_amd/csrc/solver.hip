@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
             rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
             x[e] = xv;
             r[e] = rv;
-            nrm += rv.x * rv.x + rv.y * rv.y;
+            cnorm_acc(nrm, rv);
         }
     }
     block_sum_store<double2>(nrm, partials);

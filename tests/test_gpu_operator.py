@@ -268,6 +268,25 @@ def test_visit_order_and_link_streaming(setup, zt, stream):
     assert rel(lat.spinor_numpy(lat.apply_MdagM(0, f)), ops[0].K(psi)) < 1e-12
 
 
+def test_link_streaming_bitwise(setup):
+    """Streaming and cached link loads differ only in the load instruction: the hop, Mhat
+    (FP64 and FP32) and a CG solve agree bit for bit (every product that is rounded is
+    fused in a fixed order, so the two instantiations of a kernel compute the same)."""
+    dims, U, lat, ops = setup
+    from paper_1609_02652_amd.pfmp import F64, F32
+    f = lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 29))
+    f32 = lat.convert_spinor(f, F64, F32)
+    out = []
+    for stream in (0, 1):
+        lat.link_streaming(stream)
+        x, st = lat.cg_solve(0, f, tol=1e-10)
+        out.append([lat.apply_hop(1, f).cpu().numpy(), lat.apply_M(0, f).cpu().numpy(),
+                    lat.apply_M(0, f32, prec=F32).cpu().numpy(), x.cpu().numpy(), st["iters"]])
+    lat.link_streaming(0)
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
 def test_graph_replay_matches_eager(setup):
     """Solver iterations replayed as HIP graphs give the eager launches' results bit for
     bit, for several solves in a row (each replaying graphs captured earlier), with
