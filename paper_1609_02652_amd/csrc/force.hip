@@ -468,9 +468,13 @@ __global__ __launch_bounds__(kBlock) void k_kinetic(long n, const double *__rest
 
 // ---------------------------------------------------------------- host side
 
-// F += clover force of the insertion field Phi
+// F += clover force of the insertion field Phi (deferred: kept for clover_force_flush)
 static int clover_force_add(pfmp_ctx *ctx, const double2 *Phi, double *F)
 {
+    if (ctx->clover_defer) {
+        ctx->phi_pending = true;
+        return 0;
+    }
     const Geom &g = ctx->g;
     double *Psi = (double *)ws_alloc(ctx, sizeof(double) * 2L * 6 * kPsiReals * g.Vh, 17);
     if (!Psi) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
@@ -479,6 +483,23 @@ static int clover_force_add(pfmp_ctx *ctx, const double2 *Phi, double *F)
                        Psi, F);
     LAUNCHCHK(ctx);
     return 0;
+}
+
+void clover_force_defer(pfmp_ctx *ctx)
+{
+    ctx->clover_defer = true;
+    ctx->phi_pending = false;
+}
+
+int clover_force_flush(pfmp_ctx *ctx, double *F)
+{
+    const bool pending = ctx->phi_pending;
+    ctx->clover_defer = false;
+    ctx->phi_pending = false;
+    if (!pending) return 0;
+    const double2 *Phi = (const double2 *)ws_alloc(ctx, sizeof(double2) * 2L * 6 * 9 * ctx->g.Vh, 16);
+    if (!Phi) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
+    return clover_force_add(ctx, Phi, F);
 }
 
 extern "C" int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void *const *X, const void *const *Y,
@@ -502,6 +523,8 @@ extern "C" int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void 
     if (!Phi) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
     const double k2 = s.kappa * s.kappa, kc = s.kappa * s.csw;
     const double2 fe = make_double2(0, kc), fo = make_double2(0, kc * k2);   // i kappa c_sw w: w = 1 even, kappa^2 odd
+    // the first insertion overwrites Phi unless earlier terms of a deferred sum are in it
+    const int acc0 = ctx->clover_defer && ctx->phi_pending ? 1 : 0;
     int rc = 0;
     for (int q0 = 0; q0 < npairs; q0 += kForcePairs) {
         PairSet ps{};
@@ -524,7 +547,7 @@ extern "C" int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void 
                                ps, ctx->U, -k2, F);
         if (do_clov)
             hipLaunchKernelGGL(k_clover_insert_multi, dim3(nblocks(12L * g.Vh, kBlock)), dim3(kBlock), 0,
-                               ctx->stream, g, ps, fe, fo, q0 > 0 ? 1 : 0, Phi);
+                               ctx->stream, g, ps, fe, fo, q0 > 0 ? 1 : acc0, Phi);
         LAUNCHCHK(ctx);
     }
     if (do_clov && npairs > 0 && (rc = clover_force_add(ctx, Phi, F))) return rc;
@@ -543,7 +566,8 @@ extern "C" int pfmp_logdet_force(pfmp_ctx *ctx, int op, double coef, double *F)
     const Geom &g = ctx->g;
     double2 *Phi = (double2 *)ws_alloc(ctx, sizeof(double2) * 2L * 6 * 9 * g.Vh, 16);
     if (!Phi) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
-    HIPCHK(ctx, hipMemsetAsync(Phi, 0, sizeof(double2) * 2L * 6 * 9 * g.Vh, ctx->stream));
+    if (!(ctx->clover_defer && ctx->phi_pending))
+        HIPCHK(ctx, hipMemsetAsync(Phi, 0, sizeof(double2) * 2L * 6 * 9 * g.Vh, ctx->stream));
     double2 fac = ctimesi(make_double2(-2.0 * coef * s.kappa * s.csw, 0));
     hipLaunchKernelGGL(k_logdet_insert, dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, s.clov[1], fac,
                        Phi);

@@ -599,6 +599,17 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
                 }
             }
         }
+        // the clover-force insertions of all terms due at this step go into one field,
+        // applied by one clover-force pass before the momentum update
+        struct DeferGuard {
+            pfmp_ctx *c;
+            ~DeferGuard()
+            {
+                c->clover_defer = false;
+                c->phi_pending = false;
+            }
+        } guard{ctx};
+        clover_force_defer(ctx);
         for (int j = 0; j < nt; j++) {
             double eps = So[(size_t)j * cap + k];
             if (eps == 0.0) continue;
@@ -617,6 +628,7 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
                 if ((rc = pfmp_logdet_force(ctx, sp->det_op, eps, F))) return rc;
             }
         }
+        if ((rc = clover_force_flush(ctx, F))) return rc;
         if ((rc = pfmp_update_momenta(ctx, 1.0, F, P))) return rc;
     }
     return 0;

@@ -192,6 +192,10 @@ struct pfmp_ctx {
     SolverWS *ws = nullptr;
     std::vector<double2 *> pool;   // FP64 spinor buffers for the HMC driver, grown on demand
     bool use_graphs = true;        // solver iterations replayed as HIP graphs
+    // clover-force insertions of several force terms summed into one field before a single
+    // clover-force pass (set by the integrator for the terms due at one merged step)
+    bool clover_defer = false;
+    bool phi_pending = false;      // the insertion field holds terms not yet applied
     hipStream_t cap = nullptr;     // private stream the graphs are captured on
     struct Graph {
         std::vector<uint64_t> key;
@@ -276,6 +280,9 @@ inline void key_geom(std::vector<uint64_t> &k, const Geom &g)
     key_add(k, g.stream);
 }
 int clover_logdet(pfmp_ctx *ctx, int op);
+// force.hip: start collecting clover insertions; apply what was collected (F += its force)
+void clover_force_defer(pfmp_ctx *ctx);
+int clover_force_flush(pfmp_ctx *ctx, double *F);
 // reductions (blas.hip)
 int red_finish(pfmp_ctx *ctx, const double *partials, int nparts, int nvals, double *host_out);
 int launch_dot(pfmp_ctx *ctx, const double2 *a, const double2 *b, long n, double *partials);
