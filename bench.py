@@ -467,6 +467,23 @@ def main():
     t_plain, st_plain = run_trajectories(lat, sp_plain, args.steps, args.warmup, 100)
     t_chosen, st_chosen = run_trajectories(lat, sp_chosen, args.steps, args.warmup, 100)
     kmults = int(np.mean([s["kmults"] for s in st_plain]))
+
+    def traj_summary(t, sts):
+        return {"s_per_traj": round(t, 4), "accept_rate": float(np.mean([s["accept"] for s in sts])),
+                "dH": [round(s["dH"], 5) for s in sts], "kmults": int(np.mean([s["kmults"] for s in sts])),
+                "solver_iters": int(np.mean([s["solver_iters"] for s in sts]))}
+
+    # ---- the other uses of the three changes, one timed trajectory each on the same inputs
+    # (context for the chosen mode): the ratio solve and the correction term's z = 0 pole
+    # of each merged step as one multi-RHS solve in mixed precision, and every CG solve
+    # as the flexible CG with the trained network
+    variants = {}
+    for name, kw in (("mixed_batched", {"solver_prec": F16, "batch": True}), ("learned_fcg", {"ptnet": W_net})):
+        try:
+            t_v, st_v = run_trajectories(lat, pfmp_spec(lat, **kw), 1, args.warmup, 100)
+            variants[name] = traj_summary(t_v, st_v)
+        except Exception as e:  # noqa: BLE001 -- report, do not hide
+            variants[name] = {"error": str(e)}
     lat.close()
 
     # ---- dominant-kernel roofline (HIP events on the library stream).  The hop is
@@ -503,11 +520,6 @@ def main():
     roof["copy"] = copy_bandwidth()
     roof["workload_lattice"] = dict(small, note="16^3x32 working set fits the 256 MB Infinity Cache")
 
-    def traj_summary(t, sts):
-        return {"s_per_traj": round(t, 4), "accept_rate": float(np.mean([s["accept"] for s in sts])),
-                "dH": [round(s["dH"], 5) for s in sts], "kmults": int(np.mean([s["kmults"] for s in sts])),
-                "solver_iters": int(np.mean([s["solver_iters"] for s in sts]))}
-
     out = {
         "metric": "PF-MP trajectory s & CG solve s at 1e-10 resid, plain FP64 vs chosen; Dslash GB/s",
         "value": round(t_chosen, 4),
@@ -534,7 +546,8 @@ def main():
                                                "learned": "flexible CG with the trained PT-conv network"}[
                                chosen_prec]},
         "trajectory": {"chosen": traj_summary(t_chosen, st_chosen), "plain_f64": traj_summary(t_plain, st_plain),
-                       "speedup_vs_plain": round(t_plain / t_chosen, 3)},
+                       "speedup_vs_plain": round(t_plain / t_chosen, 3),
+                       "other_modes_one_trajectory": variants},
         "cg_solve": dict(cg, tol=TOL, sources=args.sources),
         "batched_solves": batched,
         "thermalisation": therm,
