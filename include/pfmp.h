@@ -263,10 +263,13 @@ int pfmp_convert_spinor(pfmp_ctx *ctx, const void *in, int prec_in, void *out, i
 /* F += sum_p d/dw Re[ c_p X_p^dag Mhat_op Y_p ] along U_mu(x) -> exp(i w T_a) U_mu(x),
  * for npairs pairs of FP64 internal spinors X_p, Y_p (device) with complex
  * coefficients c_p (2*npairs doubles, host).  flags: PFMP_FORCE_HOP and/or
- * PFMP_FORCE_CLOVER select the parts of dMhat (both = the full derivative).
+ * PFMP_FORCE_CLOVER select the parts of dMhat (neither = the full derivative);
+ * PFMP_FORCE_F32: X_p, Y_p are FP32 internal spinors, their odd-site
+ * intermediates are formed by the FP32 operator and the force is summed in FP64.
  * F: internal momenta layout, accumulated. */
 #define PFMP_FORCE_HOP 1
 #define PFMP_FORCE_CLOVER 2
+#define PFMP_FORCE_F32 4
 int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void *const *X, const void *const *Y,
                        const double *coeff, int flags, double *F);
 /* F += coef * d/dw S_det, S_det = -2 sum_{x odd} ln det A(x) of slot op. */

@@ -18,6 +18,7 @@
 // the contribution is Re tr[dFhat_p Phi_p] = Re tr[dQ_p Psi_p], Psi_p = (Phi_p - Phi_p^dag)/8;
 // each link then collects, over the 2 plaquettes x 4 corners of every plane holding
 // it, the leaf products with Psi inserted at the corner.
+#include <type_traits>
 #include <vector>
 
 #include "hop.h"
@@ -47,30 +48,44 @@ __device__ __forceinline__ M3 pauli_contract(int type, const M3 *O)
 
 // Up to kForcePairs bilinears (X_q, Y_q) with coefficients c_q in one launch; Xo_q and
 // Zo_q are their odd-site intermediates (see the header).
+// The spinors are FP64 (C = double2) or FP32 (float2, widened on load); the force is
+// accumulated in FP64 either way.
 constexpr int kForcePairs = 8;
+template <typename C>
 struct PairSet {
     int n;
-    const double2 *X[kForcePairs], *Xo[kForcePairs], *Y[kForcePairs], *Zo[kForcePairs];
+    const C *X[kForcePairs], *Xo[kForcePairs], *Y[kForcePairs], *Zo[kForcePairs];
     double2 c[kForcePairs];
 };
 
+// the 12 components of a spinor at site i, in FP64
+template <typename C>
+__device__ __forceinline__ void load_wide(const C *__restrict__ f, int Vh, int i, double2 *v)
+{
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const C a = f[(long)k * Vh + i];
+        v[k] = make_double2((double)a.x, (double)a.y);
+    }
+}
+
 // c (U G_A) + conj(c) (U G_B^dag): the coefficient map is odd under Z -> Z^dag, so
 // this gives the force of c (U G_A - G_B U^dag)
-template <int MU>
-__device__ __forceinline__ void hop_force_link(const Geom &g, int p, int i, const int *c, const PairSet &ps,
+template <int MU, typename C>
+__device__ __forceinline__ void hop_force_link(const Geom &g, int p, int i, const int *c, const PairSet<C> &ps,
                                                const double2 *__restrict__ U, double scale, double *__restrict__ F)
 {
     int s;
     const int j = eo_neighbour(g, c, MU, +1, &s);
     M3 M = m3_zero();
     for (int q = 0; q < ps.n; q++) {
-        const double2 *Lx = p == 0 ? ps.X[q] : ps.Xo[q], *Rx = p == 0 ? ps.Y[q] : ps.Zo[q];
-        const double2 *Ly = p == 0 ? ps.Xo[q] : ps.X[q], *Ry = p == 0 ? ps.Zo[q] : ps.Y[q];
+        const C *Lx = p == 0 ? ps.X[q] : ps.Xo[q], *Rx = p == 0 ? ps.Y[q] : ps.Zo[q];
+        const C *Ly = p == 0 ? ps.Xo[q] : ps.X[q], *Ry = p == 0 ? ps.Zo[q] : ps.Y[q];
         double2 v[12], hL[6], hR[6];
         // G_A: (1 - g) projections of R(x+mu) and L(x)
-        load_spinor(Ry, g.Vh, j, 1.0, v);
+        load_wide(Ry, g.Vh, j, v);
         project<MU, -1>(v, hR);
-        load_spinor(Lx, g.Vh, i, 1.0, v);
+        load_wide(Lx, g.Vh, i, v);
         project<MU, -1>(v, hL);
         const double2 cq = ps.c[q], cc = cconj(cq);
 #pragma unroll
@@ -81,9 +96,9 @@ __device__ __forceinline__ void hop_force_link(const Geom &g, int p, int i, cons
                 cfma(M.e[3 * a + b], cq, o);
             }
         // G_B: (1 + g) projections of R(x) and L(x+mu); add conj(c) G_B^dag
-        load_spinor(Rx, g.Vh, i, 1.0, v);
+        load_wide(Rx, g.Vh, i, v);
         project<MU, +1>(v, hR);
-        load_spinor(Ly, g.Vh, j, 1.0, v);
+        load_wide(Ly, g.Vh, j, v);
         project<MU, +1>(v, hL);
 #pragma unroll
         for (int a = 0; a < 3; a++)
@@ -106,7 +121,8 @@ __device__ __forceinline__ void hop_force_link(const Geom &g, int p, int i, cons
 }
 
 // F[link] += scale * (hopping-term force of all pairs); one thread per link
-__global__ __launch_bounds__(kBlock) void k_hop_force_multi(Geom g, PairSet ps, const double2 *__restrict__ U,
+template <typename C>
+__global__ __launch_bounds__(kBlock) void k_hop_force_multi(Geom g, PairSet<C> ps, const double2 *__restrict__ U,
                                                             double scale, double *__restrict__ F)
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -126,7 +142,8 @@ __global__ __launch_bounds__(kBlock) void k_hop_force_multi(Geom g, PairSet ps, 
 
 // Phi_pl(x) (+)= sum_q fac(x) c_q sum_{s,t} sigma_pl[s][t] R_t L_s^dag, fac = fe (even) / fo
 // (odd), L = (X | Xo), R = (Y | Zo); one thread per (parity, plane, site)
-__global__ __launch_bounds__(kBlock) void k_clover_insert_multi(Geom g, PairSet ps, double2 fe, double2 fo,
+template <typename C>
+__global__ __launch_bounds__(kBlock) void k_clover_insert_multi(Geom g, PairSet<C> ps, double2 fe, double2 fo,
                                                                 int accumulate, double2 *__restrict__ Phi)
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -137,17 +154,19 @@ __global__ __launch_bounds__(kBlock) void k_clover_insert_multi(Geom g, PairSet 
     const double su = kSigUp[pl], sl = kSigLo[pl];
     M3 acc = m3_zero();
     for (int q = 0; q < ps.n; q++) {
-        const double2 *L = p == 0 ? ps.X[q] : ps.Xo[q], *R = p == 0 ? ps.Y[q] : ps.Zo[q];
+        const C *L = p == 0 ? ps.X[q] : ps.Xo[q], *R = p == 0 ? ps.Y[q] : ps.Zo[q];
         const double2 cq = cmul(ps.c[q], p == 0 ? fe : fo);
 #pragma unroll
         for (int blk = 0; blk < 2; blk++) {
             double2 r0[3], r1[3], l0[3], l1[3];
 #pragma unroll
             for (int a = 0; a < 3; a++) {
-                r0[a] = R[(long)(6 * blk + a) * g.Vh + i];
-                r1[a] = R[(long)(6 * blk + 3 + a) * g.Vh + i];
-                l0[a] = L[(long)(6 * blk + a) * g.Vh + i];
-                l1[a] = L[(long)(6 * blk + 3 + a) * g.Vh + i];
+                const C ra = R[(long)(6 * blk + a) * g.Vh + i], rb = R[(long)(6 * blk + 3 + a) * g.Vh + i];
+                const C la = L[(long)(6 * blk + a) * g.Vh + i], lb = L[(long)(6 * blk + 3 + a) * g.Vh + i];
+                r0[a] = make_double2((double)ra.x, (double)ra.y);
+                r1[a] = make_double2((double)rb.x, (double)rb.y);
+                l0[a] = make_double2((double)la.x, (double)la.y);
+                l1[a] = make_double2((double)lb.x, (double)lb.y);
             }
             const double2 w = cscale(cq, blk ? sl : su);
 #pragma unroll
@@ -502,13 +521,30 @@ int clover_force_flush(pfmp_ctx *ctx, double *F)
     return clover_force_add(ctx, Phi, F);
 }
 
-extern "C" int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void *const *X, const void *const *Y,
-                                  const double *coeff, int flags, double *F)
+// Xo = A_oo^-1 (D_eo)^dag X, Zo = A_oo^-1 D_oe Y in the spinors' precision
+static int force_odd(pfmp_ctx *ctx, OpSlot &s, bool cl, const double2 *x, const double2 *y, double2 *xo, double2 *zo)
+{
+    int rc;
+    if ((rc = clovinv64(ctx, 1, y, s.clov[1], zo, 1.0, 1.0, cl, nullptr))) return rc;
+    return clovinv64(ctx, 1, x, s.clov[1], xo, -1.0, -1.0, cl, nullptr);
+}
+static int force_odd(pfmp_ctx *ctx, OpSlot &s, bool cl, const float2 *x, const float2 *y, float2 *xo, float2 *zo)
+{
+    int rc;
+    if ((rc = clovinv32(ctx, 1, y, s.clovf[1], zo, 1.f, 1.f, cl, nullptr))) return rc;
+    return clovinv32(ctx, 1, x, s.clovf[1], xo, -1.f, -1.f, cl, nullptr);
+}
+
+template <typename C>
+static int fermion_force_t(pfmp_ctx *ctx, int op, int npairs, const void *const *X, const void *const *Y,
+                           const double *coeff, int flags, double *F)
 {
     if (!ctx) return PFMP_ERR_ARG;
     if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
         return set_err(ctx, PFMP_ERR_STATE, "fermion_force: operator not configured");
     if (int rc0 = op_ready(ctx, op)) return rc0;
+    if (std::is_same<C, float2>::value)
+        if (int rc0 = gauge_f32_ready(ctx)) return rc0;
     if (npairs < 0 || (npairs > 0 && (!X || !Y || !coeff)) || !F)
         return set_err(ctx, PFMP_ERR_ARG, "fermion_force: bad arguments");
     for (int q = 0; q < npairs; q++)
@@ -527,15 +563,14 @@ extern "C" int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void 
     const int acc0 = ctx->clover_defer && ctx->phi_pending ? 1 : 0;
     int rc = 0;
     for (int q0 = 0; q0 < npairs; q0 += kForcePairs) {
-        PairSet ps{};
+        PairSet<C> ps{};
         ps.n = npairs - q0 < kForcePairs ? npairs - q0 : kForcePairs;
         for (int k = 0; k < ps.n; k++) {
-            const double2 *x = (const double2 *)X[q0 + k], *y = (const double2 *)Y[q0 + k];
-            double2 *xo = pool_get(ctx, 2300 + k), *zo = pool_get(ctx, 2300 + kForcePairs + k);
+            const C *x = (const C *)X[q0 + k], *y = (const C *)Y[q0 + k];
+            // pool buffers hold an FP64 spinor, so an FP32 one fits
+            C *xo = (C *)pool_get(ctx, 2300 + k), *zo = (C *)pool_get(ctx, 2300 + kForcePairs + k);
             if (!xo || !zo) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
-            // Zo = A_oo^-1 D_oe Y,  Xo = A_oo^-1 g5 D_oe g5 X = A_oo^-1 (D_eo)^dag X
-            if ((rc = clovinv64(ctx, 1, y, s.clov[1], zo, 1.0, 1.0, cl, nullptr))) return rc;
-            if ((rc = clovinv64(ctx, 1, x, s.clov[1], xo, -1.0, -1.0, cl, nullptr))) return rc;
+            if ((rc = force_odd(ctx, s, cl, x, y, xo, zo))) return rc;
             ps.X[k] = x;
             ps.Y[k] = y;
             ps.Xo[k] = xo;
@@ -543,15 +578,29 @@ extern "C" int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void 
             ps.c[k] = make_double2(coeff[2 * (q0 + k)], coeff[2 * (q0 + k) + 1]);
         }
         if (do_hop)
-            hipLaunchKernelGGL(k_hop_force_multi, dim3(nblocks(8L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g,
-                               ps, ctx->U, -k2, F);
+            hipLaunchKernelGGL(k_hop_force_multi<C>, dim3(nblocks(8L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream,
+                               g, ps, ctx->U, -k2, F);
         if (do_clov)
-            hipLaunchKernelGGL(k_clover_insert_multi, dim3(nblocks(12L * g.Vh, kBlock)), dim3(kBlock), 0,
+            hipLaunchKernelGGL(k_clover_insert_multi<C>, dim3(nblocks(12L * g.Vh, kBlock)), dim3(kBlock), 0,
                                ctx->stream, g, ps, fe, fo, q0 > 0 ? 1 : acc0, Phi);
         LAUNCHCHK(ctx);
     }
     if (do_clov && npairs > 0 && (rc = clover_force_add(ctx, Phi, F))) return rc;
     return 0;
+}
+
+extern "C" int pfmp_fermion_force(pfmp_ctx *ctx, int op, int npairs, const void *const *X, const void *const *Y,
+                                  const double *coeff, int flags, double *F)
+{
+    if (flags & PFMP_FORCE_F32)
+        return fermion_force_t<float2>(ctx, op, npairs, X, Y, coeff, flags & ~PFMP_FORCE_F32, F);
+    return fermion_force_t<double2>(ctx, op, npairs, X, Y, coeff, flags, F);
+}
+
+int fermion_force_f32(pfmp_ctx *ctx, int op, int npairs, const void *const *X, const void *const *Y,
+                      const double *coeff, double *F)
+{
+    return fermion_force_t<float2>(ctx, op, npairs, X, Y, coeff, 0, F);
 }
 
 extern "C" int pfmp_logdet_force(pfmp_ctx *ctx, int op, double coef, double *F)

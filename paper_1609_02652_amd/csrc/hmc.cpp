@@ -318,32 +318,28 @@ int term_force(Ctx &X, const pfmp_term &t, const void *phi, double eps, double *
             rc_[k] = z[n - 1 - k];
         }
         if (low_precision_mode(X)) {
-            // the chains and their Mhat images in FP32 (FP32 links and clover), widened to
-            // FP64 for the force kernels; the filter action stays FP64
-            std::vector<void *> E32(n), C32(n);
+            // the chains, their Mhat images and the force's odd-site intermediates in FP32
+            // (FP32 links and clover); the force sums in FP64 and the filter action stays FP64
+            std::vector<void *> E32(n), C32(n), WE32(n), WC32(n);
             for (int k = 0; k < n; k++) {
                 E32[k] = pool_get(ctx, kChain + 4 * n + k);
                 C32[k] = pool_get(ctx, kChain + 5 * n + k);
-                if (!E32[k] || !C32[k]) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+                WE32[k] = pool_get(ctx, kChain + 2 * n + k);   // FP32 in the FP64 mode's WE / WC
+                WC32[k] = pool_get(ctx, kChain + 3 * n + k);
+                if (!E32[k] || !C32[k] || !WE32[k] || !WC32[k]) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
             }
-            void *phi32 = pool_get(ctx, kChain + 6 * n), *w32 = pool_get(ctx, kChain + 6 * n + 1);
-            if (!phi32 || !w32) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+            void *phi32 = pool_get(ctx, kChain + 6 * n);
+            if (!phi32) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
             if ((rc = pfmp_convert_spinor(ctx, phi, PFMP_F64, phi32, PFMP_F32))) return rc;
             if ((rc = poly(X, t.op, re, 1.0, phi32, E32[n - 1], E32.data(), PFMP_F32))) return rc;
             if ((rc = poly(X, t.op, rc_, a, phi32, C32[n - 1], C32.data(), PFMP_F32))) return rc;
-            for (int k = 0; k < n; k++) {
-                if ((rc = pfmp_convert_spinor(ctx, E32[k], PFMP_F32, E[k], PFMP_F64))) return rc;
-                if ((rc = pfmp_convert_spinor(ctx, C32[k], PFMP_F32, C[k], PFMP_F64))) return rc;
-            }
             for (int i = 1; i <= n; i++) {
-                if ((rc = applyM(X, t.op, 0, E32[i - 1], w32, PFMP_F32))) return rc;
-                if ((rc = pfmp_convert_spinor(ctx, w32, PFMP_F32, WE[i - 1], PFMP_F64))) return rc;
-                if ((rc = applyM(X, t.op, 0, C32[n - i], w32, PFMP_F32))) return rc;
-                if ((rc = pfmp_convert_spinor(ctx, w32, PFMP_F32, WC[i - 1], PFMP_F64))) return rc;
-                pair(WE[i - 1], C[n - i], eps);
-                pair(WC[i - 1], E[i - 1], eps);
+                if ((rc = applyM(X, t.op, 0, E32[i - 1], WE32[i - 1], PFMP_F32))) return rc;
+                if ((rc = applyM(X, t.op, 0, C32[n - i], WC32[i - 1], PFMP_F32))) return rc;
+                pair(WE32[i - 1], C32[n - i], eps);
+                pair(WC32[i - 1], E32[i - 1], eps);
             }
-            return pfmp_fermion_force(ctx, t.op, (int)XX.size(), XX.data(), YY.data(), cc.data(), 0, F);
+            return fermion_force_f32(ctx, t.op, (int)XX.size(), XX.data(), YY.data(), cc.data(), F);
         }
         if ((rc = poly(X, t.op, re, 1.0, phi, E[n - 1], E.data()))) return rc;       // E[k] = eta_{k+1}
         if ((rc = poly(X, t.op, rc_, a, phi, C[n - 1], C.data()))) return rc;        // C[k] = chi_{n-k}

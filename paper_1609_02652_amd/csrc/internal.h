@@ -283,6 +283,9 @@ int clover_logdet(pfmp_ctx *ctx, int op);
 // force.hip: start collecting clover insertions; apply what was collected (F += its force)
 void clover_force_defer(pfmp_ctx *ctx);
 int clover_force_flush(pfmp_ctx *ctx, double *F);
+// pfmp_fermion_force with FP32 spinors (intermediates by the FP32 operator, force in FP64)
+int fermion_force_f32(pfmp_ctx *ctx, int op, int npairs, const void *const *X, const void *const *Y,
+                      const double *coeff, double *F);
 // reductions (blas.hip)
 int red_finish(pfmp_ctx *ctx, const double *partials, int nparts, int nvals, double *host_out);
 int launch_dot(pfmp_ctx *ctx, const double2 *a, const double2 *b, long n, double *partials);

@@ -18,7 +18,7 @@ LIBPATH = os.path.join(HERE, "libpfmp.so")
 
 F64, F32, F16 = 0, 1, 2
 FIELD_SPINOR, FIELD_GAUGE, FIELD_MOMENTA = 0, 1, 2
-FORCE_HOP, FORCE_CLOVER = 1, 2
+FORCE_HOP, FORCE_CLOVER, FORCE_F32 = 1, 2, 4
 MAX_SHIFTS = 128
 
 ERRORS = {-1: "PFMP_ERR_ARG", -2: "PFMP_ERR_HIP", -3: "PFMP_ERR_NOCONV", -4: "PFMP_ERR_OOM", -5: "PFMP_ERR_STATE"}

@@ -92,6 +92,28 @@ def test_fermion_force(setup, op):
     assert rel(got, want) < 1e-12
 
 
+@pytest.mark.parametrize("op", [0, 1])
+def test_fermion_force_fp32(setup, op):
+    """FP32 spinor pairs (FORCE_F32: odd-site intermediates by the FP32 operator, the
+    force summed in FP64) against the FP64 oracle on the same FP32-rounded vectors; nine
+    pairs, so two launches of at most eight.  Error stated, at the FP32 rounding level."""
+    from paper_1609_02652_amd.pfmp import F32, FORCE_F32
+    dims, U, lat, ops = setup
+    pairs_np = []
+    for k in range(9):
+        x = synth.gaussian_spinor(lat.Vh, 60 + k).astype(np.complex64).astype(np.complex128)
+        y = synth.gaussian_spinor(lat.Vh, 70 + k).astype(np.complex64).astype(np.complex128)
+        pairs_np.append((x, y, complex(np.cos(k), np.sin(0.7 * k))))
+    F = lat.pack_momenta(np.zeros((lat.V, 4, 8)))
+    lat.fermion_force(op, [(lat.pack_spinor(x, prec=F32), lat.pack_spinor(y, prec=F32), c)
+                           for x, y, c in pairs_np], F, flags=FORCE_F32)
+    got = lat.unpack_momenta(F).cpu().numpy()
+    want = ops[op].force_bilinear(pairs_np)
+    e = rel(got, want)
+    print("fp32 fermion force rel err", e)
+    assert e < 1e-5
+
+
 def test_fermion_force_parts(setup):
     """Hop-only plus clover-only equals the full derivative."""
     from paper_1609_02652_amd.pfmp import FORCE_HOP, FORCE_CLOVER
