@@ -29,6 +29,20 @@ def norm(n, mu, nu):
     return 1.0 / p
 
 
+def quotient(n, n1, mu, nu):
+    """Q = P_n / P_n1 for two filters on the same ellipse with (n1 + 1) dividing (n + 1)
+    (App. A): the roots of P_n that are not roots of P_n1, found by comparing values,
+    in the paper's order, and the norm a_n / a_n1.  Q has degree n - n1 (eq. 2poly)."""
+    if n1 <= 0 or n1 >= n or (n + 1) % (n1 + 1):
+        raise ValueError("P_n1 divides P_n only when (n1 + 1) divides (n + 1)")
+    inner = roots(n1, mu, nu)
+    scale = max(mu, 1.0)
+    keep = [z for z in roots(n, mu, nu) if min(abs(z - w) for w in inner) > 1e-9 * scale]
+    if len(keep) != n - n1:
+        raise ValueError("root sets do not nest")
+    return keep, norm(n, mu, nu) / norm(n1, mu, nu)
+
+
 def evaluate(z, n, mu, nu):
     """P_n(z) by its product form."""
     v = norm(n, mu, nu)

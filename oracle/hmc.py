@@ -7,6 +7,8 @@ Action (paper eq. pfmp_action, with the even-odd reduction of the clover operato
   S_G   = beta sum_P (1 - Re tr U_P / 3)                        (Wilson gauge action)
   S_det = -2 sum_{x odd} ln det A(x)                             (det M = det A_oo det Mhat)
   'poly'     phi^dag P(J) phi,          P = a_n prod (J - z_k)     (App. A)
+  'polyq'    phi^dag Q(J) phi,          Q = P_n / P_n1, the intermediate filter of the
+                                       2-filter actions (eq. 2poly; App. A factorisation)
   'polycorr' phi^dag [J P(J)]^-1 phi                              (eq. 1poly, 2nd term)
   'ratio'    phi^dag W_a^dag J_b^-1 W_a phi                        (Hasenbusch ratio J_a J_b^-1,
                                                                    read as W_a^dag J_b^-1 W_a)
@@ -71,23 +73,26 @@ def _dJ_pairs(op, X, Y, c=1.0):
 
 
 def term_roots(term):
+    if term["kind"] == "polyq":
+        z, a = chebyshev.quotient(term["n"], term["n1"], term["mu"], term["nu"])
+        return z, a.real
     return chebyshev.roots(term["n"], term["mu"], term["nu"]), chebyshev.norm(term["n"], term["mu"], term["nu"]).real
 
 
 def heatbath(ops, term, eta):
     """phi with density exp(-S_term) from Gaussian eta (exp(-eta^dag eta))."""
     kind = term["kind"]
-    if kind == "poly":
-        # P = R^dag R with R = sqrt(a_n) prod_{k <= n/2} (J - z_k) (one root of each
-        # conjugate pair); phi = R^-1 eta.
+    if kind in ("poly", "polyq"):
+        # P = R^dag R with R = sqrt(a) prod (J - z_k) over the roots below the real axis
+        # (one of each conjugate pair); phi = R^-1 eta.
         op = ops(term["kappa"])
         z, a = term_roots(term)
-        n = len(z)
-        if n % 2:
-            raise ValueError("heatbath for the polynomial term needs an even degree")
+        half = [r for r in z if r.imag < 0]
+        if 2 * len(half) != len(z):
+            raise ValueError("heatbath for a polynomial term needs conjugate root pairs (even degree)")
         v = eta / math.sqrt(a)
-        for k in range(n // 2):
-            v, st = op.cg_shift(z[k], v, tol=term.get("tol_hb", 1e-13))
+        for r in half:
+            v, st = op.cg_shift(r, v, tol=term.get("tol_hb", 1e-13))
         return v
     if kind == "polycorr":
         # phi = R^dag W^dag eta, R^dag = sqrt(a_n) prod_{k <= n/2} (J - z_k^*)
@@ -111,7 +116,7 @@ def heatbath(ops, term, eta):
 
 def action(ops, term, phi, tol):
     kind = term["kind"]
-    if kind == "poly":
+    if kind in ("poly", "polyq"):
         op = ops(term["kappa"])
         z, a = term_roots(term)
         return _vdot(phi, op.poly(z, a, phi)).real
@@ -138,7 +143,7 @@ def force(ops, term, phi, tol, F=None, links=None):
     if F is None:
         F = np.zeros((V, 4, 8))
     kind = term["kind"]
-    if kind == "poly":
+    if kind in ("poly", "polyq"):
         op = ops(term["kappa"])
         z, a = term_roots(term)
         chi, eta = _prod_vectors(op, z, a, phi)

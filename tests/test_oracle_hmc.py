@@ -80,6 +80,7 @@ TERMS = [
     dict(kind="polycorr", kappa=0.110, n=4, mu=1.2, nu=0.9),
     dict(kind="ratio", kappa_num=0.110, kappa_den=0.120),
     dict(kind="heavy", kappa=0.110),
+    dict(kind="polyq", kappa=0.110, n=8, n1=2, mu=1.2, nu=0.9),
 ]
 
 

@@ -117,6 +117,32 @@ def test_factorisation_rule():
         assert not chebyshev.divides(p1, p2, mu, nu)
 
 
+def test_quotient_filter():
+    """Q = P_p2 / P_p1 (eq. 2poly): Q(z) P_p1(z) = P_p2(z) at points off the roots, p2 - p1
+    roots closed under conjugation, a positive norm; the pairs the paper's schemes use
+    (p1 = 4 inside p2 = 24 for 2PF-1MP) and the golden factorising pairs."""
+    g = json.load(open(os.path.join(GOLD, "chebyshev_params.json")))
+    mu, nu = g["mu"], g["nu"]
+    rng = np.random.default_rng(7)
+    pairs = [(4, 24), (2, 8)] + [tuple(p) for p in g["nested_pairs_factorising"]]
+    for p1, p2 in pairs:
+        zq, aq = chebyshev.quotient(p2, p1, mu, nu)
+        assert len(zq) == p2 - p1
+        chebyshev.conjugate_partner(zq)
+        assert abs(aq.imag) < 1e-12 * abs(aq) and aq.real > 0
+        assert sum(1 for z in zq if z.imag < 0) == (p2 - p1) // 2
+        for w in rng.normal(size=6) * 1.5 + 1j * rng.normal(size=6) + 1.0:
+            q = aq
+            for z in zq:
+                q *= (w - z)
+            lhs = q * chebyshev.evaluate(w, p1, mu, nu)
+            rhs = chebyshev.evaluate(w, p2, mu, nu)
+            assert abs(lhs - rhs) < 1e-11 * abs(rhs), (p1, p2, w)
+    for p1, p2 in g["pairs_not_factorising"]:
+        with pytest.raises(ValueError):
+            chebyshev.quotient(p2, p1, mu, nu)
+
+
 @pytest.mark.parametrize("n", [4, 16, 64])
 def test_partial_fractions(n):
     """prod_i 1/(z - z_i) = sum_i r_i / (z - z_i) over the n roots plus z_{n+1} = 0."""
