@@ -298,7 +298,11 @@ typedef enum {
     PFMP_TERM_POLY = 0,      /* phi^dag P(J) phi, P the degree-n Chebyshev filter of App. A        */
     PFMP_TERM_POLYCORR = 1,  /* phi^dag [J P(J)]^-1 phi (pole sum + multi-shift CG, App. C)         */
     PFMP_TERM_RATIO = 2,     /* phi^dag W^dag K_b^-1 W phi: the Hasenbusch ratio J K_b^-1            */
-    PFMP_TERM_HEAVY = 3      /* phi^dag J^-1 phi                                                  */
+    PFMP_TERM_HEAVY = 3,     /* phi^dag J^-1 phi                                                  */
+    PFMP_TERM_POLYQ = 4      /* phi^dag Q(J) phi, Q = P_n / P_n1: the intermediate filter of the
+                                2-filter actions (eq. 2poly); P_n1 divides P_n when (n1 + 1)
+                                divides (n + 1) (App. A), and Q has the n - n1 roots of P_n that
+                                are not roots of P_n1, norm a_n / a_n1                            */
 } pfmp_term_kind;
 
 #define PFMP_MAX_TERMS 16
@@ -310,6 +314,7 @@ typedef struct {
     int n;           /* POLY / POLYCORR: polynomial degree (even) */
     double mu, nu;   /* Chebyshev ellipse (mu >= nu > 0) */
     int steps;       /* 2MN steps of this term over the trajectory */
+    int n1;          /* POLYQ: degree of the inner filter P_n1 (even, (n1 + 1) | (n + 1)) */
 } pfmp_term;
 
 typedef struct {
@@ -327,7 +332,9 @@ typedef struct {
     const double *ptnet;  /* optional learned-preconditioner weights (1568 doubles): the CG solves become
                              flexible CG with that network; NULL: plain CG */
     int batch;            /* 1: the CG solves of all RATIO / HEAVY terms due at the same merged step run
-                             as one multi-RHS solve (the S_j commute, App. B); FP64 plain CG only */
+                             as one multi-RHS solve (the S_j commute, App. B), with the correction
+                             term's z = 0 pole in the FP32 / F16 modes; FP64, or FP32 passes inside
+                             FP64 defect correction in those modes; not with ptnet */
     int det_steps;        /* > 0: S_det on its own 2MN scale with this many steps (one more row of the
                              merged schedule); 0: S_det moves with the gauge action */
 } pfmp_hmc_spec;

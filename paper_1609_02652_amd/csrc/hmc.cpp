@@ -74,20 +74,36 @@ int chk_spec(pfmp_ctx *ctx, const pfmp_hmc_spec *sp)
             return set_err(ctx, PFMP_ERR_ARG, "hmc: term operator or steps");
         if (t.kind == PFMP_TERM_RATIO && (t.op2 < 0 || t.op2 >= PFMP_MAX_OPS || !ctx->ops[t.op2].valid))
             return set_err(ctx, PFMP_ERR_ARG, "hmc: ratio denominator");
-        if ((t.kind == PFMP_TERM_POLY || t.kind == PFMP_TERM_POLYCORR) && (t.n < 2 || (t.n & 1) || t.n + 1 > PFMP_MAX_SHIFTS))
+        if ((t.kind == PFMP_TERM_POLY || t.kind == PFMP_TERM_POLYCORR || t.kind == PFMP_TERM_POLYQ) &&
+            (t.n < 2 || (t.n & 1) || t.n + 1 > PFMP_MAX_SHIFTS))
             return set_err(ctx, PFMP_ERR_ARG, "hmc: polynomial degree must be even, 2..126");
+        if (t.kind == PFMP_TERM_POLYQ && (t.n1 < 2 || (t.n1 & 1) || t.n1 >= t.n || (t.n + 1) % (t.n1 + 1)))
+            return set_err(ctx, PFMP_ERR_ARG, "hmc: polyq needs an even n1 < n with (n1 + 1) dividing (n + 1)");
+        if (t.kind < PFMP_TERM_POLY || t.kind > PFMP_TERM_POLYQ) return set_err(ctx, PFMP_ERR_ARG, "hmc: term kind");
     }
     return 0;
 }
 
+// The roots (in the order k = 1..n) and norm of a term's polynomial.  POLYQ: Q = P_n / P_n1
+// has the roots of P_n whose angle 2 pi k / (n + 1) is not an angle 2 pi k' / (n1 + 1) of P_n1,
+// i.e. k not a multiple of (n + 1) / (n1 + 1), and norm a_n / a_n1 (App. A).  In either case
+// the first half of the list holds one root of each conjugate pair (k <= n / 2).
 void roots_of(const pfmp_term &t, std::vector<cd> &z, double &a)
 {
     std::vector<double> r(2 * t.n);
     double nm[2];
     pfmp_chebyshev(t.n, t.mu, t.nu, r.data(), nm);
-    z.resize(t.n);
-    for (int k = 0; k < t.n; k++) z[k] = cd(r[2 * k], r[2 * k + 1]);
+    z.clear();
+    const int m = t.kind == PFMP_TERM_POLYQ ? (t.n + 1) / (t.n1 + 1) : 0;
+    for (int k = 1; k <= t.n; k++)
+        if (m == 0 || k % m != 0) z.push_back(cd(r[2 * (k - 1)], r[2 * (k - 1) + 1]));
     a = nm[0];
+    if (m) {
+        std::vector<double> r1(2 * t.n1);
+        double nm1[2];
+        pfmp_chebyshev(t.n1, t.mu, t.nu, r1.data(), nm1);
+        a /= nm1[0];
+    }
 }
 
 // partial fractions: 1 / prod_k (x - z_k) = sum_i r_i / (x - z_i), r_i = prod_{j != i} 1 / (z_i - z_j)
@@ -195,7 +211,8 @@ int term_action(Ctx &X, const pfmp_term &t, const void *phi, double *S)
     double2 *t0 = pool_get(ctx, kTmp), *t1 = pool_get(ctx, kTmp + 1);
     if (!t0 || !t1) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
     switch (t.kind) {
-    case PFMP_TERM_POLY: {
+    case PFMP_TERM_POLY:
+    case PFMP_TERM_POLYQ: {
         std::vector<cd> z;
         double a;
         roots_of(t, z, a);
@@ -241,13 +258,15 @@ int term_heatbath(Ctx &X, const pfmp_term &t, const void *eta, void *phi)
     double2 *t0 = pool_get(ctx, kTmp), *t1 = pool_get(ctx, kTmp + 1);
     if (!t0 || !t1) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
     switch (t.kind) {
-    case PFMP_TERM_POLY: {
-        // P = R^dag R, R = sqrt(a) prod_{k<=n/2} (J - z_k); phi = R^-1 eta by partial
-        // fractions over the n/2 poles and one multi-shift solve
+    case PFMP_TERM_POLY:
+    case PFMP_TERM_POLYQ: {
+        // P = R^dag R, R = sqrt(a) prod (J - z_k) over the first half of the roots (one of
+        // each conjugate pair); phi = R^-1 eta by partial fractions over those poles and
+        // one multi-shift solve
         std::vector<cd> z;
         double a;
         roots_of(t, z, a);
-        z.resize(t.n / 2);
+        z.resize(z.size() / 2);
         std::vector<cd> r = residues(z);
         std::vector<double2 *> xs(z.size());
         for (size_t k = 0; k < z.size(); k++)
@@ -298,11 +317,12 @@ int term_force(Ctx &X, const pfmp_term &t, const void *phi, double eps, double *
         cc.push_back(c.imag());
     };
     switch (t.kind) {
-    case PFMP_TERM_POLY: {
+    case PFMP_TERM_POLY:
+    case PFMP_TERM_POLYQ: {
         std::vector<cd> z;
         double a;
         roots_of(t, z, a);
-        const int n = t.n;
+        const int n = (int)z.size();
         // eta_1..eta_n from roots z_1^*..z_{n-1}^*; chi_n..chi_1 from z_n..z_2 with norm a
         std::vector<void *> E(n), C(n), WE(n), WC(n);
         for (int k = 0; k < n; k++) {

@@ -49,8 +49,9 @@ class SolverStats(ctypes.Structure):
 
 
 MAX_TERMS = 16
-TERM_POLY, TERM_POLYCORR, TERM_RATIO, TERM_HEAVY = 0, 1, 2, 3
-TERM_KINDS = {"poly": TERM_POLY, "polycorr": TERM_POLYCORR, "ratio": TERM_RATIO, "heavy": TERM_HEAVY}
+TERM_POLY, TERM_POLYCORR, TERM_RATIO, TERM_HEAVY, TERM_POLYQ = 0, 1, 2, 3, 4
+TERM_KINDS = {"poly": TERM_POLY, "polycorr": TERM_POLYCORR, "ratio": TERM_RATIO, "heavy": TERM_HEAVY,
+              "polyq": TERM_POLYQ}
 
 
 class Tuning(ctypes.Structure):
@@ -59,7 +60,7 @@ class Tuning(ctypes.Structure):
 
 class Term(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("op", ctypes.c_int), ("op2", ctypes.c_int), ("n", ctypes.c_int),
-                ("mu", ctypes.c_double), ("nu", ctypes.c_double), ("steps", ctypes.c_int)]
+                ("mu", ctypes.c_double), ("nu", ctypes.c_double), ("steps", ctypes.c_int), ("n1", ctypes.c_int)]
 
 
 class HmcSpec(ctypes.Structure):
@@ -547,14 +548,14 @@ class Lattice:
     @staticmethod
     def spec(beta, terms, gauge_steps, det_op=-1, tau=1.0, lam=0.0, tol=1e-10, maxiter=100000,
              exact_start=False, solver_prec=F64, ptnet=None, batch=False, det_steps=0):
-        """terms: list of dicts {kind, op, op2, n, mu, nu, steps}; ptnet: (W1, W2, W0) or None;
-        batch: the solves of all ratio / heavy terms due at one merged step run as one
-        multi-RHS solve (FP64 plain CG); det_steps: S_det on its own 2MN scale (0: with the
-        gauge action)."""
+        """terms: list of dicts {kind, op, op2, n, n1, mu, nu, steps} (kind poly, polycorr, ratio,
+        heavy or polyq; n1: the inner degree of polyq); ptnet: (W1, W2, W0) or None; batch: the
+        solves of all ratio / heavy terms due at one merged step run as one multi-RHS solve;
+        det_steps: S_det on its own 2MN scale (0: with the gauge action)."""
         arr = (Term * max(1, len(terms)))()
         for k, t in enumerate(terms):
             arr[k] = Term(TERM_KINDS[t["kind"]], t["op"], t.get("op2", -1), t.get("n", 0), t.get("mu", 0.0),
-                          t.get("nu", 0.0), t["steps"])
+                          t.get("nu", 0.0), t["steps"], t.get("n1", 0))
         wp, keep_w = None, None
         if ptnet is not None:
             keep_w = Lattice._weights(ptnet).copy()

@@ -211,3 +211,68 @@ def test_gauge_step_graphs_match_launches(U0):
         print("graphs dH %.15f, launches dH %.15f, nforce %s" % (dh_g, dh_l, nf_g), flush=True)
         assert dh_g == dh_l and nf_g == nf_l
         assert np.array_equal(U_g, U_l)
+
+
+# The paper's other actions over the same terms (Sec. 2.2 eq. hasenbusch, 1poly, 2poly;
+# Sec. 3 2MP, 1PF-2MP, 2PF-1MP), one trajectory each against the oracle.  Slots: 0 = K
+# (kappa 0.120), 1 = J / J_2 (0.110), 2 = J_1 (0.100).  2-filter actions factor P_8 by
+# P_2 ((2 + 1) divides (8 + 1)); few 2MN steps keep the oracle's trajectory short.
+KAPPA_1 = 0.100
+KAPPAS = {0: KAPPA, 1: KAPPA_H, 2: KAPPA_1}
+
+
+def _poly(kind, op, n, steps, n1=0):
+    return dict(kind=kind, op=op, n=n, n1=n1, mu=1.2, nu=0.9, steps=steps)
+
+
+ZOO = {
+    "1MP": [dict(kind="heavy", op=1, steps=4), dict(kind="ratio", op=1, op2=0, steps=3)],
+    "2MP": [dict(kind="heavy", op=2, steps=4), dict(kind="ratio", op=2, op2=1, steps=3),
+            dict(kind="ratio", op=1, op2=0, steps=3)],
+    "1PF": [_poly("poly", 0, 4, 6), _poly("polycorr", 0, 4, 3)],
+    "2PF": [_poly("poly", 0, 2, 8), _poly("polyq", 0, 8, 4, n1=2), _poly("polycorr", 0, 8, 3)],
+    "2PF-1MP": [_poly("poly", 1, 2, 8), _poly("polyq", 1, 8, 4, n1=2), _poly("polycorr", 1, 8, 4),
+                dict(kind="ratio", op=1, op2=0, steps=3)],
+    "1PF-2MP": [_poly("poly", 2, 4, 6), _poly("polycorr", 2, 4, 4), dict(kind="ratio", op=2, op2=1, steps=3),
+                dict(kind="ratio", op=1, op2=0, steps=3)],
+}
+
+
+def _oracle_term(t):
+    o = {k: v for k, v in t.items() if k not in ("op", "op2")}
+    if t["kind"] == "ratio":
+        o["kappa_num"], o["kappa_den"] = KAPPAS[t["op"]], KAPPAS[t["op2"]]
+    else:
+        o["kappa"] = KAPPAS[t["op"]]
+    return o
+
+
+@pytest.mark.parametrize("name", list(ZOO))
+def test_action_variants_match_oracle(U0, name):
+    """One trajectory of each action (heatbath, H, 2MN MD with the generalized merge, the
+    accept) on 4^4 against the oracle, CG 1e-12: H0, dH, accept, links and momenta."""
+    print("action variant", name, flush=True)
+    terms = ZOO[name]
+    P0 = synth.gaussian_momenta(256, 300)
+    etas = [synth.gaussian_spinor(128, 310 + j) for j in range(len(terms))]
+    u = synth.uniform(326)[0]   # 0.048: accepted, so the final links are compared too
+    ospec = dict(dims=DIMS, beta=BETA, csw=CSW, kappa=KAPPA, gauge_steps=16,
+                 terms=[_oracle_term(t) for t in terms])
+    ref = hmc.trajectory(ospec, U0, P0, etas, u=u, tol=1e-12)
+    lat = make_lattice(U0)
+    lat.set_operator(2, KAPPA_1, CSW)
+    sp = lat.spec(BETA, terms, 16, det_op=0, tol=1e-12, exact_start=True)
+    Pend = lat.pack_momenta(np.zeros((256, 4, 8)))
+    st = lat.trajectory(sp, lat.pack_momenta(P0), [lat.pack_spinor(e) for e in etas], u, P_end=Pend)
+    print("dH gpu %.12f oracle %.12f" % (st["dH"], ref["dH"]), st["nforce"], ref["nforce"], flush=True)
+    assert list(st["nforce"][:len(terms) + 1]) == list(ref["nforce"])
+    assert abs(st["H0"] - ref["H0"]) < 1e-8 * abs(ref["H0"])
+    assert abs(st["dH"] - ref["dH"]) < 1e-7
+    assert st["accept"] == ref["accept"]
+    Ug = lat.get_gauge().cpu().numpy()
+    if st["accept"]:
+        assert np.max(np.abs(Ug - ref["U"])) < 1e-9
+    else:
+        assert np.array_equal(Ug, U0)
+    assert np.max(np.abs(lat.unpack_momenta(Pend).cpu().numpy() - ref["P"])) < 1e-8
+    lat.close()
