@@ -361,6 +361,58 @@ def learned_bench(lat, nsrc):
     return out, W
 
 
+KAPPA_1 = 0.1250
+
+
+def zoo_specs(lat, prec):
+    """The paper's actions over the same terms (Sec. 2.2 eq. hasenbusch, 1poly, 2poly; Sec. 3
+    PF-MP, 2MP, 1PF-2MP, 2PF-1MP) on the benchmark field: slots 0 = K (kappa 0.1340),
+    1 = J (0.1300), 2 = J_1 (0.1250); degree-4 filters, the 2-filter actions with P_4
+    inside P_24 (the paper's 2PF-1MP choice), gauge 480 and S_det 120 2MN steps, every
+    solve to 1e-10.  Step counts are fixed, not tuned per action."""
+    def p(kind, op, n, steps, n1=0):
+        return dict(kind=kind, op=op, n=n, n1=n1, mu=1.2, nu=0.9, steps=steps)
+
+    def r(op, op2, steps):
+        return dict(kind="ratio", op=op, op2=op2, steps=steps)
+    zoo = {
+        "PF-MP": [p("poly", 1, 4, 120), p("polycorr", 1, 4, 20), r(1, 0, 20)],
+        "1MP": [dict(kind="heavy", op=1, steps=120), r(1, 0, 20)],
+        "2MP": [dict(kind="heavy", op=2, steps=120), r(2, 1, 40), r(1, 0, 20)],
+        "1PF": [p("poly", 0, 4, 120), p("polycorr", 0, 4, 20)],
+        "2PF": [p("poly", 0, 4, 120), p("polyq", 0, 24, 40, n1=4), p("polycorr", 0, 24, 20)],
+        "2PF-1MP": [p("poly", 1, 4, 120), p("polyq", 1, 24, 40, n1=4), p("polycorr", 1, 24, 20), r(1, 0, 20)],
+        "1PF-2MP": [p("poly", 2, 4, 120), p("polycorr", 2, 4, 20), r(2, 1, 20), r(1, 0, 20)],
+    }
+    return {k: lat.spec(BETA, v, STEPS["gauge"], det_op=0, tol=TOL, det_steps=STEPS["det"], solver_prec=prec)
+            for k, v in zoo.items()}
+
+
+def zoo_bench(args):
+    """One timed trajectory (after one warm-up) of each action of zoo_specs, in plain FP64 and
+    in the chosen mixed precision (FP16-storage CG), on the same inputs."""
+    from paper_1609_02652_amd import synth
+    from paper_1609_02652_amd.pfmp import F64, F16, Lattice
+    lat = Lattice(DIMS)
+    lat.set_gauge(synth.random_gauge(DIMS, seed=0))
+    thermalise(lat, args.therm)
+    for op, k in ((0, KAPPA), (1, KAPPA_H), (2, KAPPA_1)):
+        lat.set_operator(op, k, CSW)
+    log("autotune: %s" % lat.autotune(0))
+    out = {}
+    for mode, prec in (("f16", F16), ("f64", F64)):
+        for name, sp in zoo_specs(lat, prec).items():
+            t, sts = run_trajectories(lat, sp, 1, 1, 100)
+            s = sts[0]
+            out.setdefault(name, {})[mode] = {"s_per_traj": round(t, 4), "dH": round(s["dH"], 5),
+                                              "kmults": s["kmults"], "solver_iters": s["solver_iters"],
+                                              "nforce": s["nforce"]}
+            log("zoo %s %s: %s" % (name, mode, out[name][mode]))
+    lat.close()
+    print(json.dumps({"zoo": out, "lattice": "x".join(map(str, DIMS)),
+                      "kappas": {"K": KAPPA, "J": KAPPA_H, "J_1": KAPPA_1}}), flush=True)
+
+
 def run_trajectories(lat, sp, steps, warmup, seed):
     """warmup untimed, then exactly `steps` timed trajectories on fresh momenta and
     pseudofermion sources; the links are restored after each so every mode sees
@@ -372,7 +424,7 @@ def run_trajectories(lat, sp, steps, warmup, seed):
 
     def inputs(k):
         P = lat.pack_momenta(synth.gaussian_momenta(V, seed + k))
-        etas = [lat.pack_spinor(synth.gaussian_spinor(Vh, seed + 10000 + 3 * k + j)) for j in range(3)]
+        etas = [lat.pack_spinor(synth.gaussian_spinor(Vh, seed + 10000 + 3 * k + j)) for j in range(sp.nterms)]
         return P, etas
 
     for k in range(warmup):
@@ -407,6 +459,9 @@ def main():
     ap.add_argument("--therm", type=int, default=20, help="quenched thermalisation trajectories")
     ap.add_argument("--roofline-only", action="store_true",
                     help="time only the hopping kernels and a plain copy (for counter runs)")
+    ap.add_argument("--zoo", action="store_true",
+                    help="one trajectory of each of the paper's actions (PF-MP, 1MP, 2MP, 1PF, 2PF, 2PF-1MP, "
+                         "1PF-2MP) in FP64 and in the chosen mixed precision")
     ap.add_argument("--trajectory-only", choices=["f64", "f32", "f16"],
                     help="thermalise, then run --warmup and --steps trajectories in one solver precision and "
                          "print their times (for kernel profiles of one trajectory)")
@@ -416,6 +471,9 @@ def main():
         sys.exit(2)
     if args.roofline_only:
         roofline_only(max(args.steps, 10))
+        return
+    if args.zoo:
+        zoo_bench(args)
         return
     from paper_1609_02652_amd import synth
     from paper_1609_02652_amd.pfmp import F64, F32, F16, Lattice
