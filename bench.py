@@ -413,6 +413,60 @@ def zoo_bench(args):
                       "kappas": {"K": KAPPA, "J": KAPPA_H, "J_1": KAPPA_1}}), flush=True)
 
 
+def tune_bench(args):
+    """The paper's tuning procedure (Sec. 2.4) for the PF-MP action on the benchmark field:
+    maximal forces per row over 3 trajectories, steps with F_i h_i = const, the scale tuned
+    to P_acc in [0.65, 0.75] (rounds of 8 trajectories), then the cost C = N_mat / P_acc with
+    the tau_int-corrected error over a further 12 trajectories, in the chosen mixed
+    precision."""
+    from paper_1609_02652_amd import synth, tuner
+    from paper_1609_02652_amd.pfmp import F16, Lattice
+    lat = Lattice(DIMS)
+    lat.set_gauge(synth.random_gauge(DIMS, seed=0))
+    thermalise(lat, args.therm)
+    lat.set_operator(0, KAPPA, CSW)
+    lat.set_operator(1, KAPPA_H, CSW)
+    log("autotune: %s" % lat.autotune(0))
+
+    # S_det rides on the gauge scale here (its default): with a step count from its small
+    # maximal force it becomes unstable at 2-3 steps, a stiffness the force size misses
+    def build(steps):
+        n_g, n_p, n_c, n_r = steps[:4]
+        st = dict(poly=n_p, corr=n_c, ratio=n_r, gauge=n_g, det=0)
+        return pfmp_spec(lat, steps=st, solver_prec=F16)
+    start = [STEPS["gauge"], STEPS["poly"], STEPS["corr"], STEPS["ratio"]]
+    T = tuner.StepTuner(lat, build, 3, seed=7000)
+    t0 = time.perf_counter()
+    F = T.measure_forces(start, 3)
+    fmax = list(F[:4, 0])
+    log("maximal forces (gauge, poly, corr, ratio, det): %s" % [round(f, 4) for f in fmax])
+    c0 = fmax[3] / STEPS["ratio"]   # keep the ratio term's step at first
+    hist, best = T.tune(fmax, c0)
+    for c, steps, traj in hist:
+        log("c %.5f steps %s dH %s" % (c, steps, [round(t[0], 4) for t in traj]))
+    c, steps, _ = hist[best]
+    chain = T.run(steps, 12)
+    lat.close()
+    dH = [t[0] for t in chain]
+    acc = [t[1] for t in chain]
+    nmat = [t[2] for t in chain]
+    C, dC = tuner.cost(nmat, acc)
+    print(json.dumps({"tune": {"action": "PF-MP (poly, corr, ratio) + gauge, S_det on the gauge scale",
+                               "rows": ["gauge", "poly", "corr", "ratio"],
+                               "max_force": [round(f, 5) for f in fmax], "mean_force": [round(f, 5) for f in F[:4, 1]],
+                               "det_max_force": round(float(F[4, 0]), 5),
+                               "rounds": [{"c": round(cc, 6), "steps": st,
+                                           "dH2_over_2": round(tuner.mean_dH_estimate([t[0] for t in tr]), 4)}
+                                          for cc, st, tr in hist],
+                               "tuned_round": best, "steps": steps, "chain": {"n": len(chain), "mean_dH": round(float(np.mean(dH)), 4),
+                                                         "acc": float(np.mean(acc)),
+                                                         "acc_from_dH2": round(tuner.acceptance_from_dH(tuner.mean_dH_estimate(dH)), 3),
+                                                         "nmat": float(np.mean(nmat)),
+                                                         "exp_minus_dH": round(float(np.mean(np.exp(-np.array(dH)))), 3)},
+                               "cost": round(C, 1), "cost_err": round(dC, 1), "tau_int": tuner.TAU_INT,
+                               "seconds": round(time.perf_counter() - t0, 1)}}), flush=True)
+
+
 def run_trajectories(lat, sp, steps, warmup, seed):
     """warmup untimed, then exactly `steps` timed trajectories on fresh momenta and
     pseudofermion sources; the links are restored after each so every mode sees
@@ -459,6 +513,9 @@ def main():
     ap.add_argument("--therm", type=int, default=20, help="quenched thermalisation trajectories")
     ap.add_argument("--roofline-only", action="store_true",
                     help="time only the hopping kernels and a plain copy (for counter runs)")
+    ap.add_argument("--tune", action="store_true",
+                    help="the paper's step-size tuning (F_i h_i = const, P_acc in [0.65, 0.75]) and cost "
+                         "C = N_mat / P_acc for the PF-MP action")
     ap.add_argument("--zoo", action="store_true",
                     help="one trajectory of each of the paper's actions (PF-MP, 1MP, 2MP, 1PF, 2PF, 2PF-1MP, "
                          "1PF-2MP) in FP64 and in the chosen mixed precision")
@@ -474,6 +531,9 @@ def main():
         return
     if args.zoo:
         zoo_bench(args)
+        return
+    if args.tune:
+        tune_bench(args)
         return
     from paper_1609_02652_amd import synth
     from paper_1609_02652_amd.pfmp import F64, F32, F16, Lattice

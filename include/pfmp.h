@@ -358,6 +358,12 @@ int pfmp_heatbath(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const void *const *e
 /* H = sum tr P^2 + S_G + S_det + sum_j S_j(phi_j); parts (nterms + 3 doubles) optional. */
 int pfmp_hamiltonian(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const double *P, const void *const *phi,
                      double *H, double *parts);
+/* Force sizes for step-size tuning (Sec. 2.4: F_i h_i = const with the maximal force):
+ * each row's force at the context's gauge field with pseudofermions phi, as the norm
+ * (sum_a F_a^2)^(1/2) of its 8 coefficients per link; out (2 (nterms + 2) doubles, host)
+ * holds (maximum over links, mean over links) for the gauge action, each term in order,
+ * then S_det (zeros when det_op < 0).  Terms use the spec's solver precision.  Synchronises. */
+int pfmp_force_norms(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const void *const *phi, double *out);
 /* Molecular dynamics over tau: the per-term 2MN schemes merged by the generalized
  * multi-scale scheme (App. B); T[eps] then the S_j of the merged step.  P
  * (internal momenta) and the context's gauge field are updated in place. */

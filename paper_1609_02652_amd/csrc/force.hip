@@ -483,9 +483,67 @@ __global__ __launch_bounds__(kBlock) void k_kinetic(long n, const double *__rest
     block_partial(s, part);
 }
 
+// per-block maximum and sum of the link force norms |F| = (sum_a F_a^2)^(1/2) over the nl
+// links (p, mu, i) of the internal momenta layout; part[2 b] = max, part[2 b + 1] = sum
+__global__ __launch_bounds__(256) void k_force_norm(long nl, long Vh, const double *__restrict__ F,
+                                                    double *__restrict__ part)
+{
+    double mx = 0, sm = 0;
+    for (long l = blockIdx.x * (long)blockDim.x + threadIdx.x; l < nl; l += (long)gridDim.x * blockDim.x) {
+        const long pm = l / Vh, i = l - pm * Vh;
+        const double *b = F + pm * 8 * Vh + i;
+        double s = 0;
+#pragma unroll
+        for (int a = 0; a < 8; a++) s = fma(b[(long)a * Vh], b[(long)a * Vh], s);
+        const double v = sqrt(s);
+        mx = fmax(mx, v);
+        sm += v;
+    }
+    __shared__ double smx[4], ssm[4];
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+        sm += __shfl_xor(sm, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        smx[threadIdx.x >> 6] = mx;
+        ssm[threadIdx.x >> 6] = sm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; w++) {
+            mx = fmax(mx, smx[w]);
+            sm += ssm[w];
+        }
+        part[2 * blockIdx.x] = mx;
+        part[2 * blockIdx.x + 1] = sm;
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host side
+
+// maximum and mean over all links of the force norm; synchronises
+int force_norms(pfmp_ctx *ctx, const double *F, double *mx, double *mean)
+{
+    constexpr int nb = 256;
+    const long nl = 8L * ctx->g.Vh;
+    double *part = (double *)ws_alloc(ctx, sizeof(double) * 2 * nb, 18);
+    if (!part) return set_err(ctx, PFMP_ERR_OOM, "force norm workspace");
+    hipLaunchKernelGGL(k_force_norm, dim3(nb), dim3(256), 0, ctx->stream, nl, (long)ctx->g.Vh, F, part);
+    LAUNCHCHK(ctx);
+    double h[2 * nb];
+    HIPCHK(ctx, hipMemcpyAsync(h, part, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    double m = 0, s = 0;
+    for (int b = 0; b < nb; b++) {
+        m = h[2 * b] > m ? h[2 * b] : m;
+        s += h[2 * b + 1];
+    }
+    *mx = m;
+    *mean = s / (double)nl;
+    return 0;
+}
 
 // F += clover force of the insertion field Phi (deferred: kept for clover_force_flush)
 static int clover_force_add(pfmp_ctx *ctx, const double2 *Phi, double *F)

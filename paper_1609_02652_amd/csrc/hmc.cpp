@@ -473,6 +473,28 @@ extern "C" int pfmp_hamiltonian(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const 
     return 0;
 }
 
+extern "C" int pfmp_force_norms(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const void *const *phi, double *out)
+{
+    if (!ctx || !out || (spec && spec->nterms > 0 && !phi))
+        return ctx ? set_err(ctx, PFMP_ERR_ARG, "force_norms: null") : PFMP_ERR_ARG;
+    int rc = chk_spec(ctx, spec);
+    if (rc) return rc;
+    Ctx X{ctx, spec};
+    double *F = (double *)ws_alloc(ctx, sizeof(double) * mom_reals(ctx->g), 24);
+    if (!F) return set_err(ctx, PFMP_ERR_OOM, "force buffer");
+    const int nrow = spec->nterms + 2;
+    for (int r = 0; r < nrow; r++) {
+        out[2 * r] = out[2 * r + 1] = 0;
+        if (r == nrow - 1 && spec->det_op < 0) continue;
+        HIPCHK(ctx, hipMemsetAsync(F, 0, sizeof(double) * mom_reals(ctx->g), ctx->stream));
+        if (r == 0) rc = pfmp_gauge_force(ctx, spec->beta, F);
+        else if (r < nrow - 1) rc = term_force(X, spec->terms[r - 1], phi[r - 1], 1.0, F);
+        else rc = pfmp_logdet_force(ctx, spec->det_op, 1.0, F);
+        if (rc || (rc = force_norms(ctx, F, &out[2 * r], &out[2 * r + 1]))) return rc;
+    }
+    return 0;
+}
+
 static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats *st)
 {
     pfmp_ctx *ctx = X.c;

@@ -283,6 +283,8 @@ int clover_logdet(pfmp_ctx *ctx, int op);
 // force.hip: start collecting clover insertions; apply what was collected (F += its force)
 void clover_force_defer(pfmp_ctx *ctx);
 int clover_force_flush(pfmp_ctx *ctx, double *F);
+// maximum and mean over links of the force norm (sum_a F_a^2)^(1/2); synchronises
+int force_norms(pfmp_ctx *ctx, const double *F, double *mx, double *mean);
 // pfmp_fermion_force with FP32 spinors (intermediates by the FP32 operator, force in FP64)
 int fermion_force_f32(pfmp_ctx *ctx, int op, int npairs, const void *const *X, const void *const *Y,
                       const double *coeff, double *F);

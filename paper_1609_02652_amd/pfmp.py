@@ -164,6 +164,7 @@ def load():
         "pfmp_schedule_build": [i, vp, vp, vp, i, vp, vp, vp],
         "pfmp_heatbath": [vp, vp, vp, vp],
         "pfmp_hamiltonian": [vp, vp, vp, vp, vp, vp],
+        "pfmp_force_norms": [vp, vp, vp, vp],
         "pfmp_md_evolve": [vp, vp, vp, vp, vp],
         "pfmp_trajectory": [vp, vp, vp, vp, d, vp, vp],
         "pfmp_set_link_reconstruct": [vp, i],
@@ -581,6 +582,14 @@ class Lattice:
         self._chk(self.lib.pfmp_hamiltonian(self.h, ctypes.byref(spec), _ptr(P), p, ctypes.byref(H), parts),
                   "hamiltonian")
         return H.value, list(parts)
+
+    def force_norms(self, spec, phis):
+        """Rows (gauge, each term, S_det) of (max, mean) over links of |F| at the current links."""
+        n = spec.nterms
+        p = (ctypes.c_void_p * max(1, n))(*[x.data_ptr() for x in phis])
+        out = (ctypes.c_double * (2 * (n + 2)))()
+        self._chk(self.lib.pfmp_force_norms(self.h, ctypes.byref(spec), p, out), "force_norms")
+        return np.array(list(out)).reshape(n + 2, 2)
 
     def md_evolve(self, spec, P, phis):
         n = spec.nterms

@@ -63,6 +63,31 @@ def test_heatbath_matches_oracle(U0):
     lat.close()
 
 
+def test_force_norms_match_oracle(U0):
+    """Force sizes for step tuning (Sec. 2.4): max and mean over links of the coefficient norm
+    of the gauge force, each PF-MP term's force and the S_det force, against the oracle's
+    forces for the same eta (its own heatbath)."""
+    lat = make_lattice(U0)
+    sp = gpu_spec(lat)
+    etas = [synth.gaussian_spinor(lat.Vh, 20 + j) for j in range(3)]
+    phis = lat.heatbath(sp, [lat.pack_spinor(e) for e in etas])
+    got = lat.force_norms(sp, phis)
+    ops = hmc.Ops(DIMS, U0, CSW)
+    Fs = [oracle.force_gauge(DIMS, U0, BETA)]
+    for j, t in enumerate(oracle_spec()["terms"]):
+        Fs.append(hmc.force(ops, t, hmc.heatbath(ops, t, etas[j]), 1e-13))
+    Fd = np.zeros_like(Fs[0])
+    ops(KAPPA).force_logdet(Fd)
+    Fs.append(Fd)
+    assert got.shape == (len(Fs), 2)
+    for row, F in enumerate(Fs):
+        nrm = np.sqrt((F ** 2).sum(axis=2))
+        print("row", row, got[row], nrm.max(), nrm.mean(), flush=True)
+        assert abs(got[row, 0] - nrm.max()) < 1e-8 * nrm.max()
+        assert abs(got[row, 1] - nrm.mean()) < 1e-8 * nrm.mean()
+    lat.close()
+
+
 def test_trajectory_matches_oracle(U0):
     """4^4, kappa 0.120 / 0.110, c_sw 1.0, degree-4 filter, 2MN steps (10, 20, 40, 80), CG 1e-12."""
     print("trajectory 4^4 config", flush=True)
@@ -275,4 +300,29 @@ def test_action_variants_match_oracle(U0, name):
     else:
         assert np.array_equal(Ug, U0)
     assert np.max(np.abs(lat.unpack_momenta(Pend).cpu().numpy() - ref["P"])) < 1e-8
+    lat.close()
+
+
+def test_step_tuner_on_gpu(U0):
+    """The tuner's loop over the library (Sec. 2.4): measured maximal forces per row, steps
+    with F_i h_i = c, rounds of trajectories rescaling c; the gauge force is the largest, and
+    each round's steps keep every row at or below c."""
+    from paper_1609_02652_amd import tuner
+    lat = make_lattice(U0)
+
+    def build(steps):
+        n_g, n_p, n_c, n_r = steps[:4]
+        return gpu_spec(lat, steps=(n_r, n_c, n_p, n_g), tol=1e-10, exact_start=False)
+    T = tuner.StepTuner(lat, build, 3)
+    F = T.measure_forces([80, 40, 20, 10, 1], 2)
+    print("forces", F.tolist(), flush=True)
+    assert F.shape == (5, 2) and np.all(F[:, 0] > 0) and np.all(F[:, 0] >= F[:, 1])
+    assert F[0, 0] == F[:, 0].max()
+    fmax = list(F[:4, 0])
+    hist, best = T.tune(fmax, c0=fmax[3] / 10, ntraj=2, rounds=2)
+    assert 0 <= best < len(hist)
+    for c, steps, traj in hist:
+        assert all(f / n <= c * (1 + 1e-12) for f, n in zip(fmax, steps))
+        assert all(math.isfinite(t[0]) and t[2] > 0 for t in traj)
+        print("c %.4f steps %s dH %s" % (c, steps, [round(t[0], 4) for t in traj]), flush=True)
     lat.close()
