@@ -467,6 +467,47 @@ def tune_bench(args):
                                "seconds": round(time.perf_counter() - t0, 1)}}), flush=True)
 
 
+def integrator_bench(args):
+    """Integrator error against step size for a non-nested and a nested schedule (App. B:
+    arbitrary step sizes per term): the PF-MP action in the chosen mixed precision with
+    S_det on the gauge scale, step counts (gauge, filter, correction, ratio) scaled by s,
+    <dH^2> / 2 over the same 6 inputs at every s, and its exponent in h = 1 / s (4 for a
+    second-order integrator, <dH> ~ h^4).  The non-nested base is the tuned schedule of
+    --tune; the nested one has step counts dividing each other at similar cost."""
+    from paper_1609_02652_amd import synth, tuner
+    from paper_1609_02652_amd.pfmp import F16, Lattice
+    lat = Lattice(DIMS)
+    lat.set_gauge(synth.random_gauge(DIMS, seed=0))
+    thermalise(lat, args.therm)
+    lat.set_operator(0, KAPPA, CSW)
+    lat.set_operator(1, KAPPA_H, CSW)
+    log("autotune: %s" % lat.autotune(0))
+    bases = {"non_nested": (26, 14, 8, 11), "nested": (28, 14, 7, 14)}
+    scales = (1.0, 1.5, 2.0, 3.0)
+    out = {}
+    for name, base in bases.items():
+        rows = []
+        for sc in scales:
+            n_g, n_p, n_c, n_r = [int(round(b * sc)) for b in base]
+            sp = pfmp_spec(lat, steps=dict(poly=n_p, corr=n_c, ratio=n_r, gauge=n_g, det=0), solver_prec=F16)
+            U0 = lat.get_gauge().clone()
+            dH = []
+            for k in range(6):
+                P = lat.pack_momenta(synth.gaussian_momenta(lat.V, 9000 + k))
+                etas = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 9100 + 3 * k + j)) for j in range(3)]
+                dH.append(lat.trajectory(sp, P, etas, 0.0)["dH"])
+                lat.set_gauge(U0)
+            m = tuner.mean_dH_estimate(dH)
+            rows.append({"scale": sc, "steps": [n_g, n_p, n_c, n_r], "dH2_over_2": round(m, 6),
+                         "acc_from_dH2": round(tuner.acceptance_from_dH(m), 3)})
+            log("integrator %s %s" % (name, rows[-1]))
+        x = np.log([1.0 / r["scale"] for r in rows])
+        y = np.log([max(r["dH2_over_2"], 1e-300) for r in rows])
+        out[name] = {"rows": rows, "exponent": round(float(np.polyfit(x, y, 1)[0]), 2)}
+    lat.close()
+    print(json.dumps({"integrator": out, "rows": ["gauge", "poly", "corr", "ratio"]}), flush=True)
+
+
 def run_trajectories(lat, sp, steps, warmup, seed):
     """warmup untimed, then exactly `steps` timed trajectories on fresh momenta and
     pseudofermion sources; the links are restored after each so every mode sees
@@ -516,6 +557,8 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="the paper's step-size tuning (F_i h_i = const, P_acc in [0.65, 0.75]) and cost "
                          "C = N_mat / P_acc for the PF-MP action")
+    ap.add_argument("--integrator", action="store_true",
+                    help="<dH^2>/2 against the step scale for a non-nested and a nested PF-MP schedule")
     ap.add_argument("--zoo", action="store_true",
                     help="one trajectory of each of the paper's actions (PF-MP, 1MP, 2MP, 1PF, 2PF, 2PF-1MP, "
                          "1PF-2MP) in FP64 and in the chosen mixed precision")
@@ -534,6 +577,9 @@ def main():
         return
     if args.tune:
         tune_bench(args)
+        return
+    if args.integrator:
+        integrator_bench(args)
         return
     from paper_1609_02652_amd import synth
     from paper_1609_02652_amd.pfmp import F64, F32, F16, Lattice

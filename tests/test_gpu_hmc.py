@@ -145,6 +145,24 @@ def test_dH_scaling_gpu(U0):
     assert abs(slope - 2) < 0.15
 
 
+def test_dH_scaling_non_nested_gpu(U0):
+    """dH ~ h^2 also when no step size divides another: base steps (ratio, correction,
+    filter, gauge) = (3, 5, 7, 11) scaled by m (the generalized merge of App. B)."""
+    P0 = synth.gaussian_momenta(256, 103)
+    etas = [synth.gaussian_spinor(128, 50 + j) for j in range(3)]
+    dH = []
+    mults = [2, 4, 8]
+    for m in mults:
+        lat = make_lattice(U0)
+        sp = gpu_spec(lat, steps=(3 * m, 5 * m, 7 * m, 11 * m), tol=1e-13, exact_start=True)
+        st = lat.trajectory(sp, lat.pack_momenta(P0), [lat.pack_spinor(e) for e in etas], 0.0)
+        dH.append(abs(st["dH"]))
+        lat.close()
+    slope = np.polyfit(np.log([1.0 / m for m in mults]), np.log(dH), 1)[0]
+    print("non-nested dH", dH, "slope", slope)
+    assert abs(slope - 2) < 0.15
+
+
 def test_exp_minus_dH_average_gpu(U0):
     """<exp(-dH)> = 1 within 3 sigma over a Markov chain of 120 trajectories."""
     lat = make_lattice(U0)
