@@ -26,6 +26,31 @@ struct ShiftRec {                // 16 doubles
     double active, upd, res2, pad;
 };
 
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b)
+{
+    double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// zeta_{k+1} and alpha_s of every active shift from the base alpha (Jegerlehner's
+// recurrences), one thread per shift; called by one block only
+__device__ __forceinline__ void ms_shift_alphas(double alpha, const double *__restrict__ st, int ns,
+                                                ShiftRec *__restrict__ rec)
+{
+    const double ap = st[S_APREV], bp = st[S_BPREV];
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+        ShiftRec q = rec[s];
+        if (q.active == 0) continue;
+        // zn = z zp ap / (alpha bp (zp - z) + zp ap (1 + sigma alpha))
+        double2 num = cscale(cmul(q.z, q.zp), ap);
+        double2 one_sa = make_double2(1 + q.sigma.x * alpha, q.sigma.y * alpha);
+        double2 den = cadd(cscale(csub(q.zp, q.z), alpha * bp), cscale(cmul(q.zp, one_sa), ap));
+        q.zn = cdiv(num, den);
+        q.as = cscale(cdiv(q.zn, q.z), alpha);
+        rec[s] = q;
+    }
+}
+
 __global__ void k_cg_init(const double *__restrict__ partials, int nparts, double tol2, int maxiter,
                           double *__restrict__ st)
 {
@@ -83,14 +108,17 @@ __device__ __forceinline__ double block_total(const double *__restrict__ partial
 // then x += alpha p, r -= alpha Kp, |r|^2 partials.
 // SELF = 1: alpha = |r|^2 / <p, Khat p> formed in every block from the stage-2 partials
 // (part_pap, npap); block 0 keeps |r|^2 in S_RROLD for beta.  SELF = 0: alpha from st.
-template <int CLOV, int LM, int SELF>
+// SELF: alpha formed from the <p, Khat p> partials in every block; MS (multi-shift, with
+// SELF): block 0 also steps the shifts' zeta and alpha_s
+template <int CLOV, int LM, int SELF, int MS = 0>
 __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__restrict__ t,
                                                     const double2 *__restrict__ T, const double2 *__restrict__ U,
                                                     const double *__restrict__ cl, double a,
                                                     const double2 *__restrict__ p, double2 *__restrict__ x,
                                                     double2 *__restrict__ r, double *__restrict__ st,
                                                     double *__restrict__ partials,
-                                                    const double *__restrict__ part_pap, int npap)
+                                                    const double *__restrict__ part_pap, int npap,
+                                                    ShiftRec *__restrict__ rec = nullptr, int ns = 0)
 {
     if (st[S_DONE] != 0) return;
     double alpha_self = 0;
@@ -102,6 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
             st[S_ALPHA] = alpha_self;
             st[S_RROLD] = st[S_RR];
         }
+        if (MS && blockIdx.x == 0) ms_shift_alphas(alpha_self, st, ns, rec);
     }
     const int tt = xcd_site(2 * g.Vh);
     double nrm = 0;
@@ -130,21 +159,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
     block_sum_store<double2>(nrm, partials);
 }
 
-// stage 4; part_pap != nullptr: alpha formed in the kernel (fused CG), else from st
-void launch_cg_hop4(pfmp_ctx *ctx, bool cl, int nb, const double2 *t, const double2 *T, const double *clov,
-                    double mk2, const double2 *p, double2 *x, double2 *r, double *part, const double *part_pap)
+// stage 4 with alpha formed in the kernel from the <p, Khat p> partials (fused CG); with
+// rec, block 0 also steps the ns shifts' coefficients (multi-shift CG)
+static void launch_cg_hop4(pfmp_ctx *ctx, bool cl, int nb, const double2 *t, const double2 *T, const double *clov,
+                           double mk2, const double2 *p, double2 *x, double2 *r, double *part,
+                           const double *part_pap, ShiftRec *rec = nullptr, int ns = 0)
 {
-#define HOP4(CL, LM, SF)                                                                                            \
-    hipLaunchKernelGGL((k_cg_hop4<CL, LM, SF>), dim3(nb), dim3(kBlock), 0, ctx->stream, ctx->g, t, T, ctx->U, clov, \
-                       mk2, p, x, r, ctx->scal, part, part_pap, nb)
+#define HOP4(CL, LM, MS)                                                                                       \
+    hipLaunchKernelGGL((k_cg_hop4<CL, LM, 1, MS>), dim3(nb), dim3(kBlock), 0, ctx->stream, ctx->g, t, T, ctx->U, \
+                       clov, mk2, p, x, r, ctx->scal, part, part_pap, nb, rec, ns)
 #define HOP4_11(LM) HOP4(1, LM, 1)
 #define HOP4_10(LM) HOP4(1, LM, 0)
 #define HOP4_01(LM) HOP4(0, LM, 1)
 #define HOP4_00(LM) HOP4(0, LM, 0)
     const int lm = link_mode(ctx->g);
-    if (cl && part_pap) { PFMP_LM_SWITCH(lm, HOP4_11) }
+    if (cl && rec) { PFMP_LM_SWITCH(lm, HOP4_11) }
     else if (cl) { PFMP_LM_SWITCH(lm, HOP4_10) }
-    else if (part_pap) { PFMP_LM_SWITCH(lm, HOP4_01) }
+    else if (rec) { PFMP_LM_SWITCH(lm, HOP4_01) }
     else { PFMP_LM_SWITCH(lm, HOP4_00) }
 #undef HOP4_11
 #undef HOP4_10
@@ -188,11 +219,7 @@ __global__ void k_residual(long n, const double2 *__restrict__ b, const double2 
 
 // ---------------------------------------------------------------- multi-shift
 
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b)
-{
-    double d = b.x * b.x + b.y * b.y;
-    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
-}
+
 
 __global__ void k_ms_init(int ns, const double *__restrict__ zs, ShiftRec *__restrict__ rec)
 {
@@ -207,32 +234,6 @@ __global__ void k_ms_init(int ns, const double *__restrict__ zs, ShiftRec *__res
     q.res2 = 0;
     q.pad = 0;
     rec[s] = q;
-}
-
-// alpha and the shifted zeta_{k+1}, alpha_s (Jegerlehner's recurrences)
-__global__ __launch_bounds__(kRedBlock) void k_ms_alpha(const double *__restrict__ partials, int nparts, int ns,
-                                                        double *__restrict__ st, ShiftRec *__restrict__ rec)
-{
-    if (st[S_DONE] != 0) return;
-    double pap = block_total(partials, nparts);
-    double alpha = st[S_RR] / pap;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        st[S_PAP] = pap;
-        st[S_ALPHA] = alpha;
-    }
-    double ap = st[S_APREV], bp = st[S_BPREV];
-    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
-        ShiftRec q = rec[s];
-        if (q.active == 0) continue;
-        // zn = z zp ap / (alpha bp (zp - z) + zp ap (1 + sigma alpha))
-        double2 num = cscale(cmul(q.z, q.zp), ap);
-        double2 one_sa = make_double2(1 + q.sigma.x * alpha, q.sigma.y * alpha);
-        double2 den = cadd(cscale(csub(q.zp, q.z), alpha * bp), cscale(cmul(q.zp, one_sa), ap));
-        q.zn = cdiv(num, den);
-        q.as = cscale(cdiv(q.zn, q.z), alpha);
-        rec[s] = q;
-    }
 }
 
 __global__ __launch_bounds__(kRedBlock) void k_ms_beta(const double *__restrict__ partials, int nparts, int ns,
@@ -502,16 +503,14 @@ extern "C" int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const doubl
     const double mk2 = -s.kappa * s.kappa;
     int chunk = prm->check_every > 0 ? prm->check_every : 25;
     double h[16], rr_prev = 0, it_prev = 0;
-    // one iteration: 7 launches with fixed arguments, replayed as a graph
+    // one iteration: 6 launches with fixed arguments, replayed as a graph
     auto iteration = [&]() -> int {
         int e;
         if ((e = clovinv64(ctx, 1, B.p, s.clov[1], B.T, 1.0, 1.0, cl, ctx->scal + S_DONE))) return e;
         if ((e = xpay64(ctx, 0, B.p, B.T, s.clov[0], mk2, B.t, 1.0, cl, B.part_a, ctx->scal + S_DONE))) return e;
-        hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_a, nb, nshift, ctx->scal,
-                           rec);
         if ((e = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE))) return e;
         // r -= alpha Khat p (the base x is not needed; it goes to scratch)
-        launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, B.Kx, B.r, B.part_b, nullptr);
+        launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, B.Kx, B.r, B.part_b, B.part_a, rec, nshift);
         hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_b, nb, nshift, ctx->scal,
                            rec);
         hipLaunchKernelGGL(k_ms_update, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, nshift, B.r, B.p, ptrs,
