@@ -246,6 +246,33 @@ def cg_bench(lat, nsrc):
     return res
 
 
+# Algorithmic bytes of one CG iteration per even site, from the I/O of its five kernels (each
+# input field counted once per site): stage 1 (hop + A_oo^-1): links 8 x 18, in 24, clover 72,
+# out 24 reals; stage 2 (hop + A_ee + axpy, |t|^2): links, T 24, p 24, clover, out 24; stage 3
+# as stage 1; stage 4 (hop + A_ee, x and r updates, |r|^2): links, T' 24, t 24, clover, p 24,
+# x and r read and written 4 x 24; p update: r 24, p read and written 48.  FP64: 1296 reals
+# x 8 B; FP32: x 4 B; FP16 storage: links and clover in binary16, the p / t / T fields as
+# binary16 with a 4 B site scale, x and r in FP32.
+CG_ITER_BYTES = {
+    "f64": 8 * (264 + 288 + 264 + 384 + 96),
+    "f32": 4 * (264 + 288 + 264 + 384 + 96),
+    "f16": (144 * 2 + 52 + 72 * 2 + 52) * 2 + (144 * 2 + 52 + 52 + 72 * 2 + 52)
+           + (144 * 2 + 52 + 52 + 72 * 2 + 52 + 4 * 96) + (96 + 2 * 52),
+}
+
+
+def cg_roofline(cg, Vh):
+    """Achieved algorithmic bandwidth of each solve (iterations x CG_ITER_BYTES x Vh / time)
+    as a fraction of the 8 TB/s HBM peak; at 16^3 x 32 the working set sits in the 256 MB
+    last-level cache, so the fraction is against HBM, not the cache."""
+    out = {}
+    for k in ("f64", "f32", "f16"):
+        b = cg[k]["iters"] * CG_ITER_BYTES[k] * Vh
+        out[k] = {"bytes_per_iter_site": CG_ITER_BYTES[k], "GBps": round(b / cg[k]["median_s"] / 1e9, 1),
+                  "frac": round(b / cg[k]["median_s"] / 1e9 / HBM_PEAK_GBS, 3)}
+    return out
+
+
 def batch_bench(lat, reps=3):
     """Multi-RHS CG: the three solves of a Hasenbusch chain at one gauge field
     (kappa 0.1340, 0.1300, 0.1250 on slots 0, 1, 2) in one batched solve against the
@@ -609,6 +636,8 @@ def main():
 
     # ---- CG solves at 1e-10 in the three precisions
     cg = cg_bench(lat, args.sources)
+    cg["roofline"] = cg_roofline(cg, lat.Vh)
+    log("cg roofline: %s" % cg["roofline"])
     lat.set_operator(2, 0.1250, CSW)
     batched = batch_bench(lat)
     try:
