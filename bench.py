@@ -742,6 +742,16 @@ def main():
                        "speedup_vs_plain": round(t_plain / t_chosen, 3),
                        "other_modes_one_trajectory": variants},
         "cg_solve": dict(cg, tol=TOL, sources=args.sources),
+        "paper_context": {
+            "note": "the paper publishes work counts only (K multiplications per trajectory over acceptance), on "
+                    "its own 16^3x32 Wilson ensemble at kappa 0.15825 with a modified BQCD; hardware, precision "
+                    "and times are not stated; context, not a target (bench.py --tune measures C here)",
+            "cost_C_PF-MP": "29000 +- 1800 (Table 3.6, p = 4, kappa' = 0.155, steps (6, 20, 120, 480))",
+            "cost_C_2MP": "31000 +- 2200 (Table 3.5)",
+            "cost_C_1MP": "43800 +- 3500 (Table 3.3)",
+            "cost_C_2PF": "47700 +- 3700 (Table 3.4)",
+            "cost_C_1PF": "87500 +- 7400 (Table 3.2)",
+            "kmults_per_filter_force": "2p - 2 (Table 3.2)"},
         "batched_solves": batched,
         "thermalisation": therm,
         "autotune": tune,
