@@ -88,3 +88,25 @@ def test_argument_errors(setup):
     with pytest.raises(PfmpError) as e:
         lat.cg_solve_batch([0] * 9, [x] * 9)    # more than 8 right-hand sides
     assert e.value.code == -1
+
+
+def test_spec_errors_and_force_norms_without_det(setup):
+    """An intermediate filter whose inner degree does not divide the outer one ((4 + 1) does
+    not divide (8 + 1)), an inner degree equal to the outer one and an odd degree are rejected
+    before any work;
+    with det_op < 0 the S_det row of the force sizes is zero and the gauge row is positive."""
+    from paper_1609_02652_amd.pfmp import PfmpError
+    U, lat = setup
+    bad = [[dict(kind="polyq", op=0, n=8, n1=4, mu=1.2, nu=0.9, steps=2)],
+           [dict(kind="polyq", op=0, n=8, n1=8, mu=1.2, nu=0.9, steps=2)],
+           [dict(kind="poly", op=0, n=5, mu=1.2, nu=0.9, steps=2)]]
+    phi = [lat.field()]
+    for terms in bad:
+        with pytest.raises(PfmpError) as e:
+            lat.force_norms(lat.spec(5.6, terms, 4), phi)
+        assert e.value.code == -1
+    sp = lat.spec(5.6, [dict(kind="polyq", op=0, n=8, n1=2, mu=1.2, nu=0.9, steps=2)], 4, det_op=-1)
+    phi = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 5))]
+    F = lat.force_norms(sp, phi)
+    assert F.shape == (3, 2)
+    assert np.all(F[:2] > 0) and np.all(F[2] == 0)
