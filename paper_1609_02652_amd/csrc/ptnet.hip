@@ -89,7 +89,10 @@ __global__ __launch_bounds__(kBlock) void k_pt_l1(Geom g, const float2 *__restri
     __shared__ float2 sw[NW1];
     for (int k = threadIdx.x; k < NW1; k += blockDim.x) sw[k] = W[k];
     __syncthreads();
-    // four lanes per site: lane q computes the hidden channels 3q .. 3q + 2
+    // four lanes per site (one quad of a wave): lane q transports input channel q along each
+    // direction, the quad shares the four transported vectors by xor shuffles, and lane q
+    // mixes them into the hidden channels 3q .. 3q + 2.  The lanes of a site are valid or
+    // not together, so a whole quad returns at once.
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const int i = (int)(t >> 2), q = (int)(t & 3);
     if (i >= g.Vh) return;
@@ -97,26 +100,34 @@ __global__ __launch_bounds__(kBlock) void k_pt_l1(Geom g, const float2 *__restri
     eo_coords(g, 1, i, c);
     constexpr int NO = NH / 4;
     float2 h[NO * 3];
+#pragma unroll
     for (int k = 0; k < NO * 3; k++) h[k] = make_float2(0.f, 0.f);
     for (int d = 0; d < 8; d++) {
-        int j = nbr_of(g, c, d);
-        float2 u[9], tv[NIN * 3];
+        const int j = nbr_of(g, c, d);
+        float2 u[9], v[3], tv[3];
         float sgn;
         load_T(g, U, 1, i, c, d, u, &sgn);
-        for (int ch = 0; ch < NIN; ch++) {
-            float2 v[3];
-            for (int a = 0; a < 3; a++) {
-                double2 x = r[(long)(3 * ch + a) * g.Vh + j];
-                v[a] = make_float2((float)x.x * scale, (float)x.y * scale);
-            }
-            apply_T<0>(u, sgn, v, tv + 3 * ch);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const double2 x = r[(long)(3 * q + a) * g.Vh + j];
+            v[a] = make_float2((float)x.x * scale, (float)x.y * scale);
         }
+        apply_T<0>(u, sgn, v, tv);
         const float2 *w = sw + d * NH * NIN + (NO * q) * NIN;
-        for (int o = 0; o < NO; o++)
-            for (int ch = 0; ch < NIN; ch++) {
-                float2 wc = w[o * NIN + ch];
-                for (int a = 0; a < 3; a++) cfma(h[3 * o + a], wc, tv[3 * ch + a]);
+#pragma unroll
+        for (int m = 0; m < NIN; m++) {
+            const int ch = q ^ m;   // channel held by the lane m away in the quad
+            float2 pv[3];
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+                pv[a] = m == 0 ? tv[a] : make_float2(__shfl_xor(tv[a].x, m, 64), __shfl_xor(tv[a].y, m, 64));
+#pragma unroll
+            for (int o = 0; o < NO; o++) {
+                const float2 wc = w[o * NIN + ch];
+#pragma unroll
+                for (int a = 0; a < 3; a++) cfma(h[3 * o + a], wc, pv[a]);
             }
+        }
     }
     for (int o = 0; o < NO; o++) {
         const int oc = NO * q + o;
@@ -166,17 +177,50 @@ __global__ __launch_bounds__(kBlock) void k_pt_l2(Geom g, const float2 *__restri
             z[a] = acc;
         }
         for (int d = 0; d < 8; d++) {
-            int j = nbr_of(g, c, d);
-            const float2 *w = W2 + d * NIN * NH + o * NH;
-            float2 m[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-            for (int ch = 0; ch < NH; ch++) {
-                const float2 wc = w[ch];
-                for (int a = 0; a < 3; a++) cfma(m[a], wc, G[(long)(3 * ch + a) * g.Vh + j]);
+            const int j = nbr_of(g, c, d);
+            // lane o reads the hidden channels 3o .. 3o + 2 and mixes them into all four
+            // outputs; a reduce-scatter over the quad (xor 2, then xor 1) leaves output o's
+            // sum on lane o
+            const float2 *w = W2 + d * NIN * NH;
+            float2 mp[NIN][3];
+#pragma unroll
+            for (int oo = 0; oo < NIN; oo++)
+#pragma unroll
+                for (int a = 0; a < 3; a++) mp[oo][a] = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const int ch = 3 * o + k;
+                float2 gv[3];
+#pragma unroll
+                for (int a = 0; a < 3; a++) gv[a] = G[(long)(3 * ch + a) * g.Vh + j];
+#pragma unroll
+                for (int oo = 0; oo < NIN; oo++) {
+                    const float2 wc = w[oo * NH + ch];
+#pragma unroll
+                    for (int a = 0; a < 3; a++) cfma(mp[oo][a], wc, gv[a]);
+                }
+            }
+            const bool hi2 = (o & 2) != 0, hi1 = (o & 1) != 0;
+            float2 kp[2][3], m[3];
+#pragma unroll
+            for (int k = 0; k < 2; k++)
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    const float2 keep = hi2 ? mp[2 + k][a] : mp[k][a];
+                    const float2 send = hi2 ? mp[k][a] : mp[2 + k][a];
+                    kp[k][a] = make_float2(keep.x + __shfl_xor(send.x, 2, 64), keep.y + __shfl_xor(send.y, 2, 64));
+                }
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                const float2 keep = hi1 ? kp[1][a] : kp[0][a];
+                const float2 send = hi1 ? kp[0][a] : kp[1][a];
+                m[a] = make_float2(keep.x + __shfl_xor(send.x, 1, 64), keep.y + __shfl_xor(send.y, 1, 64));
             }
             float2 u[9], tv[3];
             float sgn;
             load_T(g, U, 0, i, c, d, u, &sgn);
             apply_T<0>(u, sgn, m, tv);
+#pragma unroll
             for (int a = 0; a < 3; a++) z[a] = cadd(z[a], tv[a]);
         }
         for (int a = 0; a < 3; a++) {
