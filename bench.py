@@ -203,17 +203,17 @@ def cpu_baseline(kmults_per_traj, budget_s=15.0):
                       % (n, per_k, t_setup, kmults_per_traj)}
 
 
-def thermalise(lat, ntraj, gauge_steps=128):
-    """Quenched HMC (Wilson gauge action at BETA, 2MN, tau = 1) from the seeded start:
+def thermalise(lat, ntraj, gauge_steps=128, beta=BETA):
+    """Quenched HMC (Wilson gauge action at beta, 2MN, tau = 1) from the seeded start:
     the links the solver and trajectory benchmarks run on."""
     from paper_1609_02652_amd import synth
-    sp = lat.spec(BETA, [], gauge_steps, det_op=-1)
+    sp = lat.spec(beta, [], gauge_steps, det_op=-1)
     acc = 0
     for k in range(ntraj):
         st = lat.trajectory(sp, lat.pack_momenta(synth.gaussian_momenta(lat.V, 7000 + k)), [],
                             synth.uniform(8000 + k)[0])
         acc += st["accept"]
-    plaq = 1.0 - lat.gauge_action(BETA) / (BETA * 6 * lat.V)
+    plaq = 1.0 - lat.gauge_action(beta) / (beta * 6 * lat.V)
     log("quenched thermalisation: %d trajectories, acceptance %.2f, plaquette %.5f" % (ntraj, acc / max(ntraj, 1),
                                                                                       plaq))
     return {"trajectories": ntraj, "accept_rate": acc / max(ntraj, 1), "plaquette": round(plaq, 6)}
@@ -386,6 +386,59 @@ def learned_bench(lat, nsrc):
            "max_true_res": float(max(r[2] for r in rows))}
     log("learned preconditioner: %s" % out)
     return out, W
+
+
+def learned32_bench(args):
+    """The learned preconditioner at the learning workload's size: 32^3 x 64, links from 10
+    quenched HMC trajectories at beta = 5.9 (1024 2MN steps), clover kappa = 0.1365, c_sw = 1.6; training
+    vectors from 4 CG solves (iterates 2, 6, 10, 14, 20, 30) and 8 Gaussian vectors, 150 Adam
+    steps; then flexible CG with the trained network against plain FP64 CG and the
+    FP32 and FP16-storage mixed CG on 3 sources, all to 1e-10."""
+    import torch
+    from paper_1609_02652_amd import synth
+    from paper_1609_02652_amd.pfmp import F16, F32, Lattice
+    dims = (32, 32, 32, 64)
+    lat = Lattice(dims)
+    lat.set_gauge(synth.random_gauge(dims, seed=0))
+    therm = thermalise(lat, 10, gauge_steps=1024, beta=5.9)   # dH grows with the volume: finer steps than 16^3 x 32
+    lat.set_operator(0, 0.1365, 1.6)
+    log("autotune: %s" % lat.autotune(0))
+    rs = []
+    for s in range(4):
+        b = lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 500 + s))
+        _, pr = lat.cg_harvest(0, b, [2, 6, 10, 14, 20, 30], tol=1e-10)
+        rs += [r for r, _ in pr]
+    rs += [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 600 + k)) for k in range(8)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W, losses = lat.ptnet_train(synth.network_weights(4, scale=0.05), rs, steps=150, lr=1e-2, op=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    srcs = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 1 + s)) for s in range(3)]
+    x = lat.field()
+    res = {}
+    for name, fn in (("cg_f64", lambda b: lat.cg_solve(0, b, x=x, tol=TOL)),
+                     ("cg_f32", lambda b: lat.cg_solve(0, b, x=x, tol=TOL, prec=F32)),
+                     ("cg_f16", lambda b: lat.cg_solve(0, b, x=x, tol=TOL, prec=F16)),
+                     ("fcg_learned", lambda b: lat.fcg_solve(0, W, b, x=x, tol=TOL))):
+        fn(srcs[0])
+        rows = []
+        for b in srcs:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = fn(b)
+            torch.cuda.synchronize()
+            rows.append((time.perf_counter() - t0, st["iters"], st["true_res"]))
+        res[name] = {"median_s": round(float(np.median([r[0] for r in rows])), 4),
+                     "iters": [r[1] for r in rows], "max_true_res": float(max(r[2] for r in rows))}
+        log("learned32 %s: %s" % (name, res[name]))
+    lat.close()
+    print(json.dumps({"learned_32x32x32x64": dict(res, train_s=round(t_train, 2), train_vectors=len(rs),
+                                                  loss=[round(float(losses[0]), 4), round(float(losses[-1]), 4)],
+                                                  thermalisation=therm,
+                                                  fcg_vs_cg_f64=round(res["cg_f64"]["median_s"] /
+                                                                      res["fcg_learned"]["median_s"], 3))}),
+          flush=True)
 
 
 KAPPA_1 = 0.1250
@@ -584,6 +637,8 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="the paper's step-size tuning (F_i h_i = const, P_acc in [0.65, 0.75]) and cost "
                          "C = N_mat / P_acc for the PF-MP action")
+    ap.add_argument("--learned32", action="store_true",
+                    help="the learned preconditioner trained and used at 32^3 x 64 against plain and mixed CG")
     ap.add_argument("--integrator", action="store_true",
                     help="<dH^2>/2 against the step scale for a non-nested and a nested PF-MP schedule")
     ap.add_argument("--zoo", action="store_true",
@@ -607,6 +662,9 @@ def main():
         return
     if args.integrator:
         integrator_bench(args)
+        return
+    if args.learned32:
+        learned32_bench(args)
         return
     from paper_1609_02652_amd import synth
     from paper_1609_02652_amd.pfmp import F64, F32, F16, Lattice
