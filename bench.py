@@ -393,7 +393,8 @@ def learned32_bench(args):
     quenched HMC trajectories at beta = 5.9 (1024 2MN steps), clover kappa = 0.1365, c_sw = 1.6; training
     vectors from 4 CG solves (iterates 2, 6, 10, 14, 20, 30) and 8 Gaussian vectors, 150 Adam
     steps; then flexible CG with the trained network against plain FP64 CG and the
-    FP32 and FP16-storage mixed CG on 3 sources, all to 1e-10."""
+    FP32 and FP16-storage mixed CG (FP16 storage with the FP16 and with the FP32 copies of
+    links and clover) on 3 sources, all to 1e-10."""
     import torch
     from paper_1609_02652_amd import synth
     from paper_1609_02652_amd.pfmp import F16, F32, Lattice
@@ -420,6 +421,8 @@ def learned32_bench(args):
     for name, fn in (("cg_f64", lambda b: lat.cg_solve(0, b, x=x, tol=TOL)),
                      ("cg_f32", lambda b: lat.cg_solve(0, b, x=x, tol=TOL, prec=F32)),
                      ("cg_f16", lambda b: lat.cg_solve(0, b, x=x, tol=TOL, prec=F16)),
+                     ("cg_f16_fp32_links", lambda b: (lat.half_links(False),
+                                                      lat.cg_solve(0, b, x=x, tol=TOL, prec=F16), lat.half_links(True))[1]),
                      ("fcg_learned", lambda b: lat.fcg_solve(0, W, b, x=x, tol=TOL))):
         fn(srcs[0])
         rows = []

@@ -131,6 +131,11 @@ int pfmp_autotune(pfmp_ctx *ctx, int op, pfmp_tuning *out);
  * the per-launch host overhead out of the iteration.  on = 0 launches them one by one;
  * the results are the same bit for bit. */
 int pfmp_set_graphs(pfmp_ctx *ctx, int on);
+/* Links and clover blocks of the FP16-storage solver (prec F16): on = 1 (the default) reads
+ * their FP16 copies, on = 0 the FP32 ones.  The FP16 copies move fewer bytes; on a system
+ * with a harder spectrum their rounding can cost iterations (both converge to the same
+ * tolerance with FP64 reliable updates).  Applies to later solves. */
+int pfmp_set_half_links(pfmp_ctx *ctx, int on);
 int pfmp_get_link_reconstruct(pfmp_ctx *ctx, int *active);
 /* Configure slot op with (kappa, c_sw): builds A_ee, A_oo^-1 (per-site Cholesky
  * of the two 6x6 chiral blocks) and ln det A_oo.  Needs a gauge field.  Errors:

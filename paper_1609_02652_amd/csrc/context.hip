@@ -111,6 +111,13 @@ int graph_run(pfmp_ctx *ctx, const std::vector<uint64_t> &key, int reps, const s
     return 0;
 }
 
+extern "C" int pfmp_set_half_links(pfmp_ctx *ctx, int on)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    ctx->half_links = on != 0;
+    return 0;
+}
+
 extern "C" int pfmp_set_graphs(pfmp_ctx *ctx, int on)
 {
     if (!ctx) return PFMP_ERR_ARG;

@@ -123,6 +123,11 @@ template int launch_xpay<float2, float, const float2 *, const float2 *, float2 *
 template int launch_xpay<float2, float, HalfField, HalfField, HalfField, HalfLinks, HalfClover>(
     pfmp_ctx *, int, HalfField, HalfField, HalfLinks, HalfClover, float, HalfField, float, bool, double *,
     const double *);
+template int launch_clovinv<float2, float, HalfField, HalfField, const float2 *, const float *>(
+    pfmp_ctx *, int, HalfField, const float2 *, const float *, HalfField, float, float, bool, const double *);
+template int launch_xpay<float2, float, HalfField, HalfField, HalfField, const float2 *, const float *>(
+    pfmp_ctx *, int, HalfField, HalfField, const float2 *, const float *, float, HalfField, float, bool, double *,
+    const double *);
 
 namespace {
 

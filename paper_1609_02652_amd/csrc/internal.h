@@ -192,6 +192,7 @@ struct pfmp_ctx {
     SolverWS *ws = nullptr;
     std::vector<double2 *> pool;   // FP64 spinor buffers for the HMC driver, grown on demand
     bool use_graphs = true;        // solver iterations replayed as HIP graphs
+    bool half_links = true;        // FP16-storage solver reads the FP16 copies of links and clover
     // clover-force insertions of several force terms summed into one field before a single
     // clover-force pass (set by the integrator for the terms due at one merged step)
     bool clover_defer = false;

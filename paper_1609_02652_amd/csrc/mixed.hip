@@ -188,8 +188,8 @@ __global__ __launch_bounds__(kRedBlock) void k_m_residual(long n, const double2 
 
 // Inner-solver storage: FP32 spinors with the FP32 links and clover, or FP16 spinors
 // (per-site scale) with the FP16 links and clover; arithmetic in FP32 either way.
-template <typename S> struct Store;
-template <> struct Store<float2 *> {
+template <typename S, bool HL = true> struct Store;
+template <> struct Store<float2 *, true> {
     using In = const float2 *;
     using UL = const float2 *;
     using CL = const float *;
@@ -198,7 +198,8 @@ template <> struct Store<float2 *> {
     static UL links(const pfmp_ctx *ctx) { return ctx->Uf; }
     static CL clover(const OpSlot &s, int p) { return s.clovf[p]; }
 };
-template <> struct Store<HalfField> {
+// FP16 spinor storage with the FP16 copies of the links and clover (HL) or the FP32 ones
+template <> struct Store<HalfField, true> {
     using In = HalfField;
     using UL = HalfLinks;
     using CL = HalfClover;
@@ -207,32 +208,42 @@ template <> struct Store<HalfField> {
     static UL links(const pfmp_ctx *ctx) { return HalfLinks{(const __half2 *)ctx->Uh}; }
     static CL clover(const OpSlot &s, int p) { return HalfClover{(const __half *)s.clovh[p]}; }
 };
+template <> struct Store<HalfField, false> {
+    using In = HalfField;
+    using UL = const float2 *;
+    using CL = const float *;
+    static size_t bytes(long Vh) { return Store<HalfField, true>::bytes(Vh); }
+    static HalfField make(void *p, long Vh) { return Store<HalfField, true>::make(p, Vh); }
+    static UL links(const pfmp_ctx *ctx) { return ctx->Uf; }
+    static CL clover(const OpSlot &s, int p) { return s.clovf[p]; }
+};
 
-template <typename S>
+template <typename S, bool HL = true>
 static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfmp_solver_params *prm,
                       pfmp_solver_stats *st)
 {
-    using In = typename Store<S>::In;
-    using UL = typename Store<S>::UL;
-    using CL = typename Store<S>::CL;
+    using St = Store<S, HL>;
+    using In = typename St::In;
+    using UL = typename St::UL;
+    using CL = typename St::CL;
     auto t0 = std::chrono::steady_clock::now();
     const Geom &g = ctx->g;
     OpSlot &s = ctx->ops[op];
-    const UL links = Store<S>::links(ctx);
-    const CL clo0 = Store<S>::clover(s, 0), clo1 = Store<S>::clover(s, 1);
+    const UL links = St::links(ctx);
+    const CL clo0 = St::clover(s, 0), clo1 = St::clover(s, 1);
     const long n = 12L * g.Vh;
     const size_t vb = sizeof(double) * spinor_reals(g), fb = vb / 2;
     const int nb = op_nparts(g);
     double2 *Kx = (double2 *)ws_alloc(ctx, vb, 8), *te = (double2 *)ws_alloc(ctx, vb, 6),
             *to = (double2 *)ws_alloc(ctx, vb, 7);
-    const size_t sb = Store<S>::bytes(g.Vh);
+    const size_t sb = St::bytes(g.Vh);
     float2 *rs = (float2 *)ws_alloc(ctx, fb, 27), *xs = (float2 *)ws_alloc(ctx, fb, 29);
     void *pb = ws_alloc(ctx, sb, 28), *tb = ws_alloc(ctx, sb, 30), *Tb = ws_alloc(ctx, sb, 31);
     double *part_a = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64), 9);
     double *part_b = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64), 10);
     if (!Kx || !te || !to || !rs || !xs || !pb || !tb || !Tb || !part_a || !part_b)
         return set_err(ctx, PFMP_ERR_OOM, "mixed solver workspace");
-    S ps = Store<S>::make(pb, g.Vh), ts = Store<S>::make(tb, g.Vh), Ts = Store<S>::make(Tb, g.Vh);
+    S ps = St::make(pb, g.Vh), ts = St::make(tb, g.Vh), Ts = St::make(Tb, g.Vh);
     const double2 *b = (const double2 *)b_;
     double2 *x = (double2 *)x_;
     double *sc = ctx->scal + kMixBase;
@@ -291,6 +302,7 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
     };
     std::vector<uint64_t> key;
     key_add(key, 2 + (int)sizeof(S));   // mixed-precision iteration, storage type
+    key_add(key, (int)HL);
     key_geom(key, g);
     for (const void *ptr : {(const void *)pb, (const void *)tb, (const void *)Tb, (const void *)xs, (const void *)rs, (const void *)part_a,
                             (const void *)part_b, (const void *)sc, (const void *)ctx->Uf, (const void *)ctx->Uh,
@@ -346,6 +358,8 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
 int cg_solve_mixed(pfmp_ctx *ctx, int op, const void *b, void *x, const pfmp_solver_params *p, pfmp_solver_stats *st)
 {
     if (p->prec == PFMP_F32) return mixed_impl<float2 *>(ctx, op, b, x, p, st);
-    if (p->prec == PFMP_F16) return mixed_impl<HalfField>(ctx, op, b, x, p, st);
+    if (p->prec == PFMP_F16)
+        return ctx->half_links ? mixed_impl<HalfField, true>(ctx, op, b, x, p, st)
+                               : mixed_impl<HalfField, false>(ctx, op, b, x, p, st);
     return set_err(ctx, PFMP_ERR_ARG, "cg_solve: unsupported precision");
 }

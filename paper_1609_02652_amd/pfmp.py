@@ -165,6 +165,7 @@ def load():
         "pfmp_heatbath": [vp, vp, vp, vp],
         "pfmp_hamiltonian": [vp, vp, vp, vp, vp, vp],
         "pfmp_force_norms": [vp, vp, vp, vp],
+        "pfmp_set_half_links": [vp, i],
         "pfmp_md_evolve": [vp, vp, vp, vp, vp],
         "pfmp_trajectory": [vp, vp, vp, vp, d, vp, vp],
         "pfmp_set_link_reconstruct": [vp, i],
@@ -278,6 +279,10 @@ class Lattice:
     def site_order(self, zt):
         """Visit order of the operator kernels: 0 memory order, zt > 0 groups of zt z-planes."""
         self._chk(self.lib.pfmp_set_site_order(self.h, int(zt)), "set_site_order")
+
+    def half_links(self, on):
+        """FP16-storage solver: FP16 copies of links and clover (True, default) or FP32 ones."""
+        self._chk(self.lib.pfmp_set_half_links(self.h, int(bool(on))), "set_half_links")
 
     def link_streaming(self, on):
         self._chk(self.lib.pfmp_set_link_streaming(self.h, int(bool(on))), "set_link_streaming")

@@ -134,16 +134,22 @@ def test_cg_mixed_fp32(setup):
     print("mixed: iters %d, updates %d, |x - x64|/|x| = %.2e" % (st["iters"], st["reliable_updates"], rel(xg, xo)))
 
 
-def test_cg_mixed_fp16_storage(setup):
+@pytest.mark.parametrize("half_links", [True, False], ids=["fp16-links", "fp32-links"])
+def test_cg_mixed_fp16_storage(setup, half_links):
     """FP16 half-spinor storage (per-site FP32 scale) in the inner operator, FP32
-    arithmetic, FP64 reliable updates: same FP64 true residual."""
+    arithmetic, FP64 reliable updates, with the FP16 or the FP32 copies of the links and
+    clover: same FP64 true residual."""
     from paper_1609_02652_amd.pfmp import F16
     dims, U, lat, ops = setup
     b = synth.gaussian_spinor(lat.Vh, 17)
-    x, st = lat.cg_solve(0, lat.pack_spinor(b), tol=1e-10, prec=F16, check_every=5)
+    lat.half_links(half_links)
+    try:
+        x, st = lat.cg_solve(0, lat.pack_spinor(b), tol=1e-10, prec=F16, check_every=5)
+    finally:
+        lat.half_links(True)
     assert st["true_res"] <= 1e-10
     assert rel(ops[0].K(lat.spinor_numpy(x)), b) <= 1.05e-10
-    print("fp16 storage: iters %d, updates %d" % (st["iters"], st["reliable_updates"]))
+    print("fp16 storage (half links %s): iters %d, updates %d" % (half_links, st["iters"], st["reliable_updates"]))
 
 
 def test_batch_apply_matches_single(setup):
