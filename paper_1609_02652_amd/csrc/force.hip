@@ -372,7 +372,13 @@ __global__ __launch_bounds__(kBlock) void k_gauge_force(Geom g, const double2 *_
             int yn[4], ypmn[4];
             shifted(g, y, nu, sg, yn);
             shifted(g, ypm, nu, sg, ypmn);
-            const int *a1 = side ? ypmn : ypm, *a3 = side ? yn : y;
+            // the two nu links' sites, chosen element-wise so that the arrays stay in registers
+            int a1[4], a3[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                a1[k] = side ? ypmn[k] : ypm[k];
+                a3[k] = side ? yn[k] : y[k];
+            }
             M3 X1 = m3_dag_if(link_at_su3(g, U, a1, nu), side);
             M3 X3 = m3_dag_if(link_at_su3(g, U, a3, nu), !side);
             st = m3_add(st, m3_mul(X1, m3_mul_dn(link_at_su3(g, U, yn, mu), X3)));
