@@ -80,7 +80,8 @@ typedef enum {
 /* ---- context ---------------------------------------------------------------- */
 
 /* Create a context for a lattice.  stream: hipStream_t to enqueue on (NULL = the
- * null stream).  Errors: PFMP_ERR_ARG (odd or < 4 extent), PFMP_ERR_OOM. */
+ * null stream).  Errors: PFMP_ERR_ARG (odd or < 4 extent, or a volume above 2^31 - 1
+ * sites), PFMP_ERR_OOM. */
 int pfmp_create(const int dims[4], int t_bc, void *stream, pfmp_ctx **out);
 int pfmp_destroy(pfmp_ctx *ctx);
 const char *pfmp_last_error(pfmp_ctx *ctx);

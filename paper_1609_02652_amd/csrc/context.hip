@@ -235,7 +235,7 @@ extern "C" int pfmp_create(const int dims[4], int t_bc, void *stream, pfmp_ctx *
         if (dims[m] < 4 || (dims[m] & 1)) return PFMP_ERR_ARG;
         V *= dims[m];
     }
-    if (V / 2 > (1L << 30)) return PFMP_ERR_ARG;
+    if (V > 2147483647L) return PFMP_ERR_ARG;   // site indices are int
     if (t_bc != 1 && t_bc != -1) return PFMP_ERR_ARG;
     pfmp_ctx *ctx = new pfmp_ctx();
     for (int m = 0; m < 4; m++) ctx->g.L[m] = dims[m];

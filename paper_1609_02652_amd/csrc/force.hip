@@ -347,10 +347,15 @@ __global__ __launch_bounds__(kBlock) void k_clover_force(Geom g, const double2 *
 __global__ __launch_bounds__(kBlock) void k_gauge_force(Geom g, const double2 *__restrict__ U, double coef,
                                                         double *__restrict__ F)
 {
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    // XCD-aware order: each XCD takes a contiguous eighth of the links (one direction and
+    // parity), so the staples' neighbour links are gathered through its own L2
+    // (the grid is a multiple of 8 blocks; 16 Vh lanes may exceed the int range)
+    const int nb = gridDim.x, per = (nb + 7) >> 3;
+    const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const long t = (long)lb * blockDim.x + threadIdx.x;
     const long l = t >> 1;
     const int side = (int)(t & 1);
-    const bool ok = l < 8L * g.Vh;
+    const bool ok = lb < nb && l < 8L * g.Vh;
     double f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int mu = 0, p = 0, i = 0;
     if (ok) {
@@ -699,7 +704,7 @@ extern "C" int pfmp_gauge_force(pfmp_ctx *ctx, double beta, double *F)
     if (!ctx || !F) return ctx ? set_err(ctx, PFMP_ERR_ARG, "gauge_force: null") : PFMP_ERR_ARG;
     if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
     const Geom &g = ctx->g;
-    hipLaunchKernelGGL(k_gauge_force, dim3(nblocks(16L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, ctx->U,
+    hipLaunchKernelGGL(k_gauge_force, dim3(nblocks_site(16L * g.Vh)), dim3(kBlock), 0, ctx->stream, g, ctx->U,
                        -beta / 3.0, F);
     LAUNCHCHK(ctx);
     return 0;
