@@ -51,7 +51,7 @@ __device__ M3 fhat(const Geom &g, const double2 *__restrict__ U, const int *c, i
 // F-hat of one plane at one site, for both parities: thread (p, plane, i), sites fastest.
 __global__ __launch_bounds__(kBlock) void k_fhat(Geom g, const double2 *__restrict__ U, double2 *__restrict__ Fh)
 {
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    long t = xcd_lane(12L * g.Vh);   // XCD-aware order: the leaves' link gathers through one L2
     if (t >= 12L * g.Vh) return;
     const int pp = (int)(t / g.Vh), i = (int)(t - (long)pp * g.Vh);
     const int p = pp / 6, pl = pp - 6 * p;
@@ -212,7 +212,7 @@ static int fhat_ready(pfmp_ctx *ctx)
         ctx->Fhat = nullptr;
         return set_err(ctx, PFMP_ERR_OOM, "clover field strength");
     }
-    hipLaunchKernelGGL(k_fhat, dim3(nblocks(12L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, ctx->U, ctx->Fhat);
+    hipLaunchKernelGGL(k_fhat, dim3(nblocks_site(12L * g.Vh)), dim3(kBlock), 0, ctx->stream, g, ctx->U, ctx->Fhat);
     LAUNCHCHK(ctx);
     ctx->fhat_stale = false;
     return 0;

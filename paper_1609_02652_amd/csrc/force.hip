@@ -289,7 +289,7 @@ __device__ __forceinline__ M3 psi_at(const Geom &g, const double *__restrict__ P
 __global__ __launch_bounds__(kBlock) void k_clover_force(Geom g, const double2 *__restrict__ U,
                                                          const double *__restrict__ Psi, double *__restrict__ F)
 {
-    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long t = xcd_lane(16L * g.Vh);   // XCD-aware order, as the gauge force
     const long l = t >> 1;
     const int side = (int)(t & 1);
     const bool ok = l < 8L * g.Vh;
@@ -349,13 +349,10 @@ __global__ __launch_bounds__(kBlock) void k_gauge_force(Geom g, const double2 *_
 {
     // XCD-aware order: each XCD takes a contiguous eighth of the links (one direction and
     // parity), so the staples' neighbour links are gathered through its own L2
-    // (the grid is a multiple of 8 blocks; 16 Vh lanes may exceed the int range)
-    const int nb = gridDim.x, per = (nb + 7) >> 3;
-    const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const long t = (long)lb * blockDim.x + threadIdx.x;
+    const long t = xcd_lane(16L * g.Vh);
     const long l = t >> 1;
     const int side = (int)(t & 1);
-    const bool ok = lb < nb && l < 8L * g.Vh;
+    const bool ok = l < 8L * g.Vh;
     double f[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int mu = 0, p = 0, i = 0;
     if (ok) {
@@ -573,7 +570,7 @@ static int clover_force_add(pfmp_ctx *ctx, const double2 *Phi, double *F)
     double *Psi = (double *)ws_alloc(ctx, sizeof(double) * 2L * 6 * kPsiReals * g.Vh, 17);
     if (!Psi) return set_err(ctx, PFMP_ERR_OOM, "force workspace");
     hipLaunchKernelGGL(k_psi_pack, dim3(nblocks(12L * g.Vh, 256)), dim3(256), 0, ctx->stream, g, Phi, Psi);
-    hipLaunchKernelGGL(k_clover_force, dim3(nblocks(16L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, ctx->U,
+    hipLaunchKernelGGL(k_clover_force, dim3(nblocks_site(16L * g.Vh)), dim3(kBlock), 0, ctx->stream, g, ctx->U,
                        Psi, F);
     LAUNCHCHK(ctx);
     return 0;

@@ -156,6 +156,17 @@ __device__ __forceinline__ int xcd_site(int n)
     return i < n ? i : -1;
 }
 
+// The same block order for kernels with more lanes than the int range may hold
+// (several lanes per link or plane): the lane index, or n for every lane of the
+// blocks past the end, so that the kernel's own bound check (lane < n) drops them.
+__device__ __forceinline__ long xcd_lane(long n)
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int per = (nb + 7) >> 3;
+    const int lb = (b & 7) * per + (b >> 3);
+    return lb < nb ? (long)lb * blockDim.x + threadIdx.x : n;
+}
+
 // ------------------------------------------------------------------ context
 
 struct OpSlot {
