@@ -229,19 +229,28 @@ def cg_bench(lat, nsrc):
     res = {}
     srcs = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 1 + s)) for s in range(nsrc)]
     x = lat.field()
+    x64 = []
     for name, prec in (("f64", F64), ("f32", F32), ("f16", F16)):
         lat.cg_solve(0, srcs[0], x=x, tol=TOL, prec=prec)   # warm-up
         rows = []
-        for b in srcs:
+        for k, b in enumerate(srcs):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             _, st = lat.cg_solve(0, b, x=x, tol=TOL, prec=prec)
             torch.cuda.synchronize()
-            rows.append((time.perf_counter() - t0, st["iters"], st["true_res"], st["reliable_updates"]))
+            dt = time.perf_counter() - t0
+            # error of the solution against the FP64 solve of the same source (outside the timing)
+            if prec == F64:
+                x64.append(x.clone())
+                err = 0.0
+            else:
+                err = float(torch.linalg.vector_norm(x - x64[k]) / torch.linalg.vector_norm(x64[k]))
+            rows.append((dt, st["iters"], st["true_res"], st["reliable_updates"], err))
         res[name] = {"median_s": round(float(np.median([r[0] for r in rows])), 5),
                      "iters": int(np.median([r[1] for r in rows])),
                      "reliable_updates": int(np.median([r[3] for r in rows])),
-                     "max_true_res": float(max(r[2] for r in rows))}
+                     "max_true_res": float(max(r[2] for r in rows)),
+                     "max_rel_err_vs_f64": float(max(r[4] for r in rows))}
         log("cg %s: %s" % (name, res[name]))
     return res
 

@@ -157,9 +157,15 @@ int pfmp_unpack_momenta(pfmp_ctx *ctx, const double *internal, double *canonical
 int pfmp_apply_hop(pfmp_ctx *ctx, int out_parity, int dagger, const void *in, void *out);
 /* out = A in, or A^-1 in (inverse = 1, odd parity only), on one parity of slot op. */
 int pfmp_apply_clover(pfmp_ctx *ctx, int op, int parity, int inverse, const void *in, void *out);
-/* out = Mhat in (dagger 0) or Mhat^dag in = g5 Mhat g5 in (dagger 1). */
+/* out = Mhat in (dagger 0) or Mhat^dag in = g5 Mhat g5 in (dagger 1).
+ * prec PFMP_F64: FP64 fields and arithmetic; PFMP_F32: FP32 fields, links and clover.
+ * PFMP_F16: in and out are FP32 fields; the input is rounded into FP16 spinor storage,
+ * each stage stores its result in FP16 storage with FP32 arithmetic and the FP16 (or,
+ * after pfmp_set_half_links(ctx, 0), FP32) copies of the links and clover, as the
+ * FP16-storage inner solver does, and the result is widened to FP32. */
 int pfmp_apply_M(pfmp_ctx *ctx, int op, int dagger, const void *in, void *out, int prec);
-/* out = Khat in = Mhat^dag Mhat in. */
+/* out = Khat in = Mhat^dag Mhat in; prec as for pfmp_apply_M (PFMP_F16: the intermediate
+ * Mhat in is stored in FP16 as well). */
 int pfmp_apply_MdagM(pfmp_ctx *ctx, int op, const void *in, void *out, int prec);
 
 /* Product-form polynomial (paper App. A): out = norm * prod_k (Khat - z_k) in,
@@ -377,7 +383,11 @@ int pfmp_md_evolve(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, double *P, const vo
                    pfmp_traj_stats *st);
 /* One trajectory from the context's gauge field: heatbath, H0, MD, H1, Metropolis
  * with the uniform u (accept iff u < exp(-dH)); on reject the start field is
- * restored.  P0 is not modified; P_end (optional) receives the final momenta. */
+ * restored.  P0 is not modified; P_end (optional) receives the final momenta.
+ * Errors: when any step fails (PFMP_ERR_NOCONV from a solve that reached maxiter,
+ * PFMP_ERR_OOM, PFMP_ERR_HIP) the context's gauge field is also restored to the start
+ * field (derived clover fields are rebuilt on next use) and the code of the failure is
+ * returned, with its text in pfmp_last_error; P_end and st are then undefined. */
 int pfmp_trajectory(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const double *P0, const void *const *eta, double u,
                     double *P_end, pfmp_traj_stats *st);
 

@@ -7,7 +7,10 @@
 // sides are consecutive in the XCD-aware block order, so they run together on one XCD
 // and every link is fetched once into its L2 for all n.  Per-rhs CG scalars and
 // convergence flags live on the device; a converged rhs stops touching memory.
-// Reductions: one FP64 partial per workgroup (indexed site block * n + rhs), fixed order.
+// Reductions: one FP64 partial per workgroup and rhs, indexed by its site block, totalled
+// per rhs by one-workgroup kernels in the fixed order of the single-RHS solver
+// (partials_total), so an FP64 batched solve gives each right-hand side the bits of its
+// single-RHS solve.
 //
 // The kernels are written once for FP64 and FP32 fields.  The FP64 batched CG is plain
 // CG on every right-hand side; the mixed-precision one is defect correction: FP64
@@ -30,6 +33,7 @@ struct BatchT {
     int k;                          // stride of the partials (= n)
     int n;                          // right-hand sides
     int nsb;                        // site blocks (two lanes per site, kBlock lanes per block)
+    int pstride;                    // partials per right-hand side (>= nsb)
     const R *clo[kMaxRhs];          // A_oo^-1 of each rhs's operator
     const R *cle[kMaxRhs];          // A_ee
     R a[kMaxRhs];                   // -kappa^2
@@ -42,34 +46,16 @@ struct VecsT {
     C *out[kMaxRhs];
 };
 
-// logical workgroup lb = site block * n + rhs (XCD-aware order); false past the end
+// Workgroup of this launch: logical workgroup lb = site block * n + rhs (XCD-aware
+// order).  False for the padding workgroups past the end (a whole workgroup).
 template <typename R>
-__device__ __forceinline__ bool item(const Geom &g, const BatchT<R> &b, int *lb, int *site, int *r, int *hb)
+__device__ __forceinline__ bool wg_item(const BatchT<R> &b, int *sb, int *r)
 {
-    const int nb = gridDim.x, bi = blockIdx.x;
-    const int per = (nb + 7) >> 3;
-    *lb = (bi & 7) * per + (bi >> 3);
-    if (*lb >= b.nsb * b.n) return false;
-    *r = *lb % b.n;
-    const int t = (*lb / b.n) * blockDim.x + threadIdx.x;
-    if (t >= 2 * g.Vh) return false;
-    *site = tile_site(g, t >> 1);
-    *hb = t & 1;
+    const int lb = xcd_block();
+    if (lb >= b.nsb * b.n) return false;
+    *r = lb % b.n;
+    *sb = lb / b.n;
     return true;
-}
-
-// one FP64 partial per logical workgroup (every thread of the block calls this)
-__device__ __forceinline__ void batch_partial(double v, int lb, int nlb, double *partials)
-{
-    __shared__ double sh[kBlock / 64];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0 && lb < nlb) {
-        double s = 0;
-        for (int q = 0; q < kBlock / 64; q++) s += sh[q];
-        partials[lb] = s;
-    }
 }
 
 // out_r = [g5] A_oo^-1 D_oe [g5] in_r
@@ -77,31 +63,37 @@ template <typename C, typename R, int CLOV, int LM>
 __global__ __launch_bounds__(kBlock) void k_b_clovinv(Geom g, BatchT<R> b, VecsT<C> v, const C *__restrict__ U,
                                                       R gin, R gout, const double *__restrict__ st)
 {
-    int lb, i, r, hb;
-    if (!item(g, b, &lb, &i, &r, &hb)) return;
+    int sb, r;
+    if (!wg_item(b, &sb, &r)) return;
     if (st && st[8 * r + B_DONE] != 0) return;
+    const int t = sb * kBlock + threadIdx.x;
+    if (t >= 2 * g.Vh) return;
+    const int i = tile_site(g, t >> 1), hb = t & 1;
     C blk[6];
     hop_pair<LM, C>(g, 1, i, hb, v.in[r], U, gin, blk);
     if (CLOV) {
-        C t[6];
-        clover_block<R, C>(b.clo[r], g.Vh, i, hb, blk, t);
-        store_block(v.out[r], g.Vh, i, hb, gout, t);
+        C tq[6];
+        clover_block<R, C>(b.clo[r], g.Vh, i, hb, blk, tq);
+        store_block(v.out[r], g.Vh, i, hb, gout, tq);
     } else {
         store_block(v.out[r], g.Vh, i, hb, gout, blk);
     }
 }
 
-// out_r = [g5] (A_ee [g5] x_r + a_r D_eo t_r), |out_r|^2 partials
+// out_r = [g5] (A_ee [g5] x_r + a_r D_eo t_r) in the single-RHS stage's arithmetic; with
+// partials, the |out_r|^2 partials of each rhs, indexed by site block
 template <typename C, typename R, int CLOV, int LM>
 __global__ __launch_bounds__(kBlock) void k_b_xpay(Geom g, BatchT<R> b, VecsT<C> x, VecsT<C> t,
                                                    const C *__restrict__ U, R gs, const double *__restrict__ st,
                                                    double *__restrict__ partials)
 {
-    int lb = 0, i = 0, r = 0, hb = 0;
-    bool ok = item(g, b, &lb, &i, &r, &hb);
-    if (ok && st && st[8 * r + B_DONE] != 0) ok = false;
+    int sb, r;
+    if (!wg_item(b, &sb, &r)) return;
+    if (st && st[8 * r + B_DONE] != 0) return;
+    const int tt = sb * kBlock + threadIdx.x;
     double nrm = 0;
-    if (ok) {
+    if (tt < 2 * g.Vh) {
+        const int i = tile_site(g, tt >> 1), hb = tt & 1;
         C acc[6], xv[6], ax[6];
         hop_pair<LM, C>(g, 0, i, hb, t.in[r], U, (R)1, acc);
         load_block(x.in[r], g.Vh, i, hb, gs, xv);
@@ -110,90 +102,86 @@ __global__ __launch_bounds__(kBlock) void k_b_xpay(Geom g, BatchT<R> b, VecsT<C>
 #pragma unroll
         for (int k = 0; k < 6; k++) {
             C base = CLOV ? ax[k] : xv[k];
-            acc[k] = mk<C>(base.x + a * acc[k].x, base.y + a * acc[k].y);
+            acc[k] = mk<C>(fmadd(a, acc[k].x, base.x), fmadd(a, acc[k].y, base.y));
             cnorm_acc(nrm, acc[k]);
         }
         store_block(x.out[r], g.Vh, i, hb, gs, acc);
     }
-    if (partials) batch_partial(nrm, lb, b.nsb * b.n, partials);
+    if (partials) {
+        const double v[1] = {nrm};
+        partials_store_at<kBlock, 1>(v, partials + (long)r * b.pstride, sb);
+    }
 }
 
-// CG stage 4: Kp_r from t_r and T'_r; x_r += alpha_r p_r; r_r -= alpha_r Kp_r; |r_r|^2 partials
+// CG stage 4 in the single-RHS arithmetic: Kp_r from t_r and T'_r; x_r += alpha_r p_r;
+// r_r -= alpha_r Kp_r; the |r_r|^2 partials of each rhs, indexed by site block
 template <typename C, typename R, int CLOV, int LM>
 __global__ __launch_bounds__(kBlock) void k_b_hop4(Geom g, BatchT<R> b, VecsT<C> t, VecsT<C> T, VecsT<C> p,
                                                    VecsT<C> x, VecsT<C> rr, const C *__restrict__ U,
                                                    const double *__restrict__ st, double *__restrict__ partials)
 {
-    int lb = 0, i = 0, r = 0, hb = 0;
-    bool ok = item(g, b, &lb, &i, &r, &hb);
-    if (ok && st[8 * r + B_DONE] != 0) ok = false;
+    int sb, r;
+    if (!wg_item(b, &sb, &r)) return;
+    const double *s = st + 8 * r;
+    if (s[B_DONE] != 0) return;
+    const double alpha_d = s[B_RR] / s[B_PAP];
+    const int tt = sb * kBlock + threadIdx.x;
     double nrm = 0;
-    if (ok) {
+    if (tt < 2 * g.Vh) {
+        const int i = tile_site(g, tt >> 1), hb = tt & 1;
         C acc[6], tv[6], at[6];
         hop_pair<LM, C>(g, 0, i, hb, T.in[r], U, (R)1, acc);
         load_block(t.in[r], g.Vh, i, hb, (R)-1, tv);
         if (CLOV) clover_block<R, C>(b.cle[r], g.Vh, i, hb, tv, at);
-        const R alpha = (R)st[8 * r + B_ALPHA], a = b.a[r];
+        const R alpha = (R)alpha_d, a = b.a[r];
         const long Vh = g.Vh;
         const C *pp = p.in[r];
         C *xx = x.out[r], *rv_ = rr.out[r];
 #pragma unroll
         for (int k = 0; k < 6; k++) {
             C base = CLOV ? at[k] : tv[k];
-            C kp = mk<C>(base.x + a * acc[k].x, base.y + a * acc[k].y);
+            C kp = mk<C>(fmadd(a, acc[k].x, base.x), fmadd(a, acc[k].y, base.y));
             if (hb) kp = cneg(kp);
             const long e = (long)(6 * hb + k) * Vh + i;
             C pv = pp[e], xv = xx[e], rv = rv_[e];
-            xv.x += alpha * pv.x; xv.y += alpha * pv.y;
-            rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
+            xv.x = fmadd(alpha, pv.x, xv.x); xv.y = fmadd(alpha, pv.y, xv.y);
+            rv.x = fmadd(-alpha, kp.x, rv.x); rv.y = fmadd(-alpha, kp.y, rv.y);
             xx[e] = xv;
             rv_[e] = rv;
             cnorm_acc(nrm, rv);
         }
     }
-    batch_partial(nrm, lb, b.nsb * b.n, partials);
+    const double v[1] = {nrm};
+    partials_store_at<kBlock, 1>(v, partials + (long)r * b.pstride, sb);
 }
 
-__device__ __forceinline__ double rhs_total(const double *__restrict__ partials, int nparts, int k, int r)
-{
-    __shared__ double sh[kRedBlock / 64];
-    double s = 0;
-    for (int q = threadIdx.x; q < nparts; q += blockDim.x) s += partials[q * k + r];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double tot = 0;
-    for (int q = 0; q < kRedBlock / 64; q++) tot += sh[q];
-    __syncthreads();
-    return tot;
-}
-
-__global__ __launch_bounds__(kRedBlock) void k_b_alpha(const double *__restrict__ partials, int nparts, int k, int n,
-                                                       double *__restrict__ st)
+// <p, Khat p> of each running rhs from its partials (the single-RHS solver's order)
+__global__ __launch_bounds__(kFinishThreads) void k_b_pap(const double *__restrict__ partials, int nparts,
+                                                         int pstride, int n, double *__restrict__ st)
 {
     for (int r = 0; r < n; r++) {
         if (st[8 * r + B_DONE] != 0) continue;
-        double pap = rhs_total(partials, nparts, k, r);
-        if (threadIdx.x == 0) {
-            st[8 * r + B_PAP] = pap;
-            st[8 * r + B_ALPHA] = st[8 * r + B_RR] / pap;
-        }
-        __syncthreads();
+        double t[1];
+        partials_total<kFinishThreads, 1, kMaxChunks>(partials + (long)r * pstride, nparts, t);
+        if (threadIdx.x == 0) st[8 * r + B_PAP] = t[0];
     }
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_b_beta(const double *__restrict__ partials, int nparts, int k, int n,
-                                                      double *__restrict__ st)
+// |r+|^2, beta and the stop decision of each running rhs (the single-RHS solver's order)
+__global__ __launch_bounds__(kFinishThreads) void k_b_beta(const double *__restrict__ partials, int nparts,
+                                                          int pstride, int n, double *__restrict__ st)
 {
     for (int r = 0; r < n; r++) {
         double *s = st + 8 * r;
         if (s[B_DONE] != 0) continue;
-        double rr = rhs_total(partials, nparts, k, r);
+        double t[1];
+        partials_total<kFinishThreads, 1, kMaxChunks>(partials + (long)r * pstride, nparts, t);
         if (threadIdx.x == 0) {
+            const double rr = t[0], it = s[B_ITER] + 1;
             s[B_BETA] = rr / s[B_RR];
             s[B_RR] = rr;
-            s[B_ITER] += 1;
-            s[B_DONE] = rr <= s[B_THR] ? 1 : (s[B_ITER] >= s[B_MAXIT] ? 2 : 0);
+            s[B_ITER] = it;
+            s[B_DONE] = rr <= s[B_THR] ? 1 : (it >= s[B_MAXIT] ? 2 : 0);
         }
         __syncthreads();
     }
@@ -211,7 +199,7 @@ __global__ void k_b_update_p(Geom g, int nrhs, VecsT<C> rr, VecsT<C> p, const do
     if (r >= nrhs || st[8 * r + B_DONE] != 0) return;
     const R beta = (R)st[8 * r + B_BETA];
     C rv = rr.in[r][e], pv = p.out[r][e];
-    p.out[r][e] = mk<C>(rv.x + beta * pv.x, rv.y + beta * pv.y);
+    p.out[r][e] = mk<C>(fmadd(beta, pv.x, rv.x), fmadd(beta, pv.y, rv.y));
 }
 
 // out = (FP32) (s * in); in FP64
@@ -252,6 +240,7 @@ static int make_batch(pfmp_ctx *ctx, int nrhs, const int *ops, BatchT<double> &b
     b.n = bf.n = nrhs;
     b.k = bf.k = nrhs;
     b.nsb = bf.nsb = nblocks(2L * ctx->g.Vh, kBlock);
+    b.pstride = bf.pstride = ((b.nsb + 63) / 64) * 64;
     for (int r = 0; r < kMaxRhs; r++) {
         int op = r < nrhs ? ops[r] : ops[0];
         if (op < 0 || op >= PFMP_MAX_OPS || !ctx->ops[op].valid || !ctx->have_gauge)
@@ -341,10 +330,9 @@ static int batch_cg_core(pfmp_ctx *ctx, const BatchT<R> &b, const void *const *b
         HIPCHK(ctx, hipMemcpyAsync(Rv[r], b_[r], vb, hipMemcpyDeviceToDevice, ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(P[r], b_[r], vb, hipMemcpyDeviceToDevice, ctx->stream));
     }
-    const int nb = b.nsb;   // partials per rhs
     const int ngrid = ((b.nsb * nrhs + 7) / 8) * 8;
-    double *part_a = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64) * b.k, 9);
-    double *part_b = (double *)ws_alloc(ctx, sizeof(double) * (nb + 64) * b.k, 10);
+    double *part_a = (double *)ws_alloc(ctx, sizeof(double) * b.pstride * b.k, 9);
+    double *part_b = (double *)ws_alloc(ctx, sizeof(double) * b.pstride * b.k, 10);
     if (!part_a || !part_b) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
     double *sc = ctx->scal + kBatchBase;
     std::vector<double> init(8 * kMaxRhs, 0.0);
@@ -367,14 +355,17 @@ static int batch_cg_core(pfmp_ctx *ctx, const BatchT<R> &b, const void *const *b
     const VecsT<C> T1_to_T2 = vecs<C>(nrhs, (const void *const *)T1.data(), T2.data());
     const C *U = sizeof(R) == 8 ? (const C *)ctx->U : (const C *)ctx->Uf;
     int chunk = check_every > 0 ? check_every : 25;
-    // one iteration for all rhs: 7 launches with fixed arguments, replayed as a graph
+    // one iteration for all rhs: 7 launches with fixed arguments, replayed as a graph; each
+    // rhs takes the single-RHS CG's steps in its arithmetic and summation order
     auto iteration = [&]() -> int {
         BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, p_to_T2, U, (R)1, (R)1, sc);
         BLAUNCH(k_b_xpay, C, R, b, grid, block, 0, ctx->stream, g, b, p_to_T1, vT2, U, (R)1, sc, part_a);
-        hipLaunchKernelGGL(k_b_alpha, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_a, nb, b.k, nrhs, sc);
+        hipLaunchKernelGGL(k_b_pap, dim3(1), dim3(kFinishThreads), 0, ctx->stream, part_a, b.nsb, b.pstride, nrhs,
+                           sc);
         BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, T1_to_T2, U, (R)-1, (R)1, sc);
         BLAUNCH(k_b_hop4, C, R, b, grid, block, 0, ctx->stream, g, b, vT1, vT2, vP, vX, vR, U, sc, part_b);
-        hipLaunchKernelGGL(k_b_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, b.k, nrhs, sc);
+        hipLaunchKernelGGL(k_b_beta, dim3(1), dim3(kFinishThreads), 0, ctx->stream, part_b, b.nsb, b.pstride, nrhs,
+                           sc);
         hipLaunchKernelGGL((k_b_update_p<C>), dim3(nblocks(n * nrhs, 256)), dim3(256), 0, ctx->stream, g, nrhs, vR,
                            vP, sc);
         LAUNCHCHK(ctx);

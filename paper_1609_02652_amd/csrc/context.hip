@@ -9,7 +9,7 @@
 // Scratch buffers of the context, one per slot:
 //   0-3 operator temporaries, 4-10 CG, 11-13 multi-shift, 14 link accumulator,
 //   15 reduction partials, 16-19 forces, 20-23 polynomial, 24-26 trajectory,
-//   27-31 mixed precision, 32-38 learned preconditioner.
+//   27-31 mixed precision, 32-38 learned preconditioner, 40-42 FP16-storage operator.
 constexpr int kWsSlots = 48;
 struct SolverWS {
     void *buf[kWsSlots] = {};
@@ -256,6 +256,7 @@ extern "C" int pfmp_create(const int dims[4], int t_bc, void *stream, pfmp_ctx *
         hipMalloc(&ctx->Uh, gb / 4) != hipSuccess ||
         hipMalloc(&ctx->red, sizeof(double) * 64 * 4096) != hipSuccess ||
         hipMalloc(&ctx->scal, sizeof(double) * 8192) != hipSuccess ||
+
         hipHostMalloc(&ctx->red_host, sizeof(double) * 4096, hipHostMallocDefault) != hipSuccess) {
         pfmp_destroy(ctx);
         return PFMP_ERR_OOM;

@@ -54,7 +54,10 @@ __global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const X x
         }
         store_block(out, g.Vh, i, hb, gs, acc);
     }
-    if (NORM) block_sum_store<C>(nrm, partials);
+    if (NORM) {
+        const double v[1] = {nrm};
+        op_partials_store<kBlock, 1>(v, partials);
+    }
 }
 
 }  // namespace
@@ -144,6 +147,25 @@ __global__ __launch_bounds__(kBlock) void k_clover(Geom g, const C *__restrict__
     store_spinor(out, g.Vh, i, (R)1, w);
 }
 
+// FP32 spinor (one parity) into FP16 storage (per-site scale) and back
+__global__ __launch_bounds__(kBlock) void k_to_half(int Vh, const float2 *__restrict__ in, HalfField out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Vh) return;
+    float2 v[12];
+    load_spinor(in, Vh, i, 1.f, v);
+    store_spinor(out, Vh, i, 1.f, v);
+}
+
+__global__ __launch_bounds__(kBlock) void k_from_half(int Vh, HalfField in, float2 *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Vh) return;
+    float2 v[12];
+    load_spinor(in, Vh, i, 1.f, v);
+    store_spinor(out, Vh, i, 1.f, v);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ internal API
@@ -188,6 +210,53 @@ int op_apply_K_f32(pfmp_ctx *ctx, int op, const float2 *in, float2 *out, float2 
     int rc = op_apply_M_f32(ctx, op, 0, in, tmp_even, tmp_odd, norm_partials);
     if (rc) return rc;
     return op_apply_M_f32(ctx, op, 1, tmp_even, out, tmp_odd, nullptr);
+}
+
+// Mhat (dagger) or Khat (K = 1) with FP16 spinor storage: in and out are FP32 spinors; the
+// input is rounded into FP16 storage, each stage stores its result in FP16 storage (FP32
+// arithmetic), as the FP16-storage inner solver does, and the result is widened to FP32.
+// Links and clover: the FP16 copies, or the FP32 ones when half links are off.
+template <typename UL, typename CL>
+static int apply_half(pfmp_ctx *ctx, int op, int dagger, int K, const float2 *in, float2 *out, UL U, CL c0, CL c1)
+{
+    const Geom &g = ctx->g;
+    const OpSlot &s = ctx->ops[op];
+    const size_t hb = 4L * 12 * g.Vh + 4L * g.Vh;
+    void *b0 = ws_alloc(ctx, hb, 40), *b1 = ws_alloc(ctx, hb, 41), *b2 = ws_alloc(ctx, hb, 42);
+    if (!b0 || !b1 || !b2) return set_err(ctx, PFMP_ERR_OOM, "workspace");
+    auto half = [&](void *p) { return HalfField{(__half2 *)p, (float *)((char *)p + 4L * 12 * g.Vh)}; };
+    HalfField hin = half(b0), htmp = half(b1), hout = half(b2);
+    const bool cl = op_has_clover(s);
+    const float mk2 = (float)(-s.kappa * s.kappa);
+    hipLaunchKernelGGL(k_to_half, dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g.Vh, in, hin);
+    LAUNCHCHK(ctx);
+    int rc;
+    for (int pass = 0; pass < (K ? 2 : 1); pass++) {
+        const float gs = (K ? pass == 1 : dagger != 0) ? -1.f : 1.f;
+        HalfField src = pass == 0 ? hin : hout, dst = pass == 0 ? hout : hin;
+        if ((rc = launch_clovinv<float2, float, HalfField, HalfField, UL, CL>(ctx, 1, src, U, c1, htmp, gs, 1.f, cl,
+                                                                               nullptr)))
+            return rc;
+        if ((rc = launch_xpay<float2, float, HalfField, HalfField, HalfField, UL, CL>(ctx, 0, src, htmp, U, c0, mk2, dst,
+                                                                                       gs, cl, nullptr, nullptr)))
+            return rc;
+    }
+    hipLaunchKernelGGL(k_from_half, dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g.Vh,
+                       K ? hin : hout, out);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
+static int apply_f16(pfmp_ctx *ctx, int op, int dagger, int K, const void *in, void *out)
+{
+    const OpSlot &s = ctx->ops[op];
+    if (ctx->half_links)
+        return apply_half<HalfLinks, HalfClover>(ctx, op, dagger, K, (const float2 *)in, (float2 *)out,
+                                                 HalfLinks{(const __half2 *)ctx->Uh},
+                                                 HalfClover{(const __half *)s.clovh[0]},
+                                                 HalfClover{(const __half *)s.clovh[1]});
+    return apply_half<const float2 *, const float *>(ctx, op, dagger, K, (const float2 *)in, (float2 *)out, ctx->Uf,
+                                                     s.clovf[0], s.clovf[1]);
 }
 
 // ------------------------------------------------------------------ C-ABI
@@ -243,6 +312,7 @@ extern "C" int pfmp_apply_M(pfmp_ctx *ctx, int op, int dagger, const void *in, v
         if (!tmp) return set_err(ctx, PFMP_ERR_OOM, "workspace");
         return op_apply_M_f32(ctx, op, dagger, (const float2 *)in, (float2 *)out, tmp, nullptr);
     }
+    if (prec == PFMP_F16) return apply_f16(ctx, op, dagger, 0, in, out);
     return set_err(ctx, PFMP_ERR_ARG, "apply_M: unsupported precision");
 }
 
@@ -263,5 +333,6 @@ extern "C" int pfmp_apply_MdagM(pfmp_ctx *ctx, int op, const void *in, void *out
         if (!te || !to) return set_err(ctx, PFMP_ERR_OOM, "workspace");
         return op_apply_K_f32(ctx, op, (const float2 *)in, (float2 *)out, te, to, nullptr);
     }
+    if (prec == PFMP_F16) return apply_f16(ctx, op, 0, 1, in, out);
     return set_err(ctx, PFMP_ERR_ARG, "apply_MdagM: unsupported precision");
 }

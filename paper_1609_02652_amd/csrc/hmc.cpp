@@ -703,6 +703,27 @@ extern "C" int pfmp_trajectory(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const d
     if (!P || !U0) return set_err(ctx, PFMP_ERR_OOM, "trajectory buffers");
     HIPCHK(ctx, hipMemcpyAsync(P, P0, mb, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(U0, ctx->U, gb, hipMemcpyDeviceToDevice, ctx->stream));
+    // Any failure from here on (a solve that hits maxiter, an allocation, a launch) puts the
+    // start field back and marks everything derived from the links stale, so a caller that
+    // catches the error goes on from the configuration it passed in.  The error text of the
+    // failure is kept.
+    struct Restore {
+        pfmp_ctx *c;
+        const double2 *U0;
+        size_t gb;
+        bool armed = true;
+        void now()
+        {
+            armed = false;
+            hipMemcpyAsync(c->U, U0, gb, hipMemcpyDeviceToDevice, c->stream);
+            hipStreamSynchronize(c->stream);
+            rebuild_gauge_derived(c);
+        }
+        ~Restore()
+        {
+            if (armed) now();
+        }
+    } restore{ctx, U0, gb};
     std::vector<void *> phi(spec->nterms);
     for (int j = 0; j < spec->nterms; j++)
         if (!(phi[j] = pool_get(ctx, j))) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
@@ -726,11 +747,10 @@ extern "C" int pfmp_trajectory(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const d
     double dH = H1 - H0;
     int acc = (dH <= 0 || u < std::exp(-dH)) ? 1 : 0;
     if (P_end) HIPCHK(ctx, hipMemcpyAsync(P_end, P, mb, hipMemcpyDeviceToDevice, ctx->stream));
-    if (!acc) {
-        HIPCHK(ctx, hipMemcpyAsync(ctx->U, U0, gb, hipMemcpyDeviceToDevice, ctx->stream));
-        if ((rc = rebuild_gauge_derived(ctx))) return rc;
-    }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    // accepted: keep the evolved links; rejected: back to the start field
+    if (acc) restore.armed = false;
+    else restore.now();
     auto t1 = std::chrono::steady_clock::now();
     if (st) {
         *st = loc;

@@ -466,6 +466,119 @@ __device__ __forceinline__ void block_sum_store(double v, double *partials)
     }
 }
 
+// ------------------------------------------------------------------ deterministic totals
+//
+// A grid-wide sum is written as block partials by the kernel that produces it and
+// totalled by one fixed order, the same wherever the total is formed: chunk c of 64
+// consecutive partials is reduced by one wave (shuffle tree), and the chunk sums are added
+// by 128 lanes (lane k takes chunks k, k + 128, ... in turn, then a shuffle tree per wave
+// and the two waves in order).  Trailing zero partials (padding workgroups) leave it
+// unchanged.  With few partials every workgroup of the consuming kernel forms the total
+// itself (no launch in between); with many, one single-workgroup kernel forms it once into
+// a device scalar, and the consumers read that: the bits are the same either way.  No
+// atomics: results are reproducible run to run and between the batched and single-RHS
+// solvers, whose partials are indexed by the block of sites they cover.
+constexpr int kInlineChunks = 32;      // consuming workgroups total up to 32 chunks (2048 partials)
+constexpr int kFinishThreads = 1024;   // the single-workgroup total kernels
+constexpr int kMaxChunks = 4096;       // their limit: 262144 partials
+inline bool totals_inline(int nparts) { return nparts <= 64 * kInlineChunks; }
+
+// this workgroup's NV sums (wave trees, then the waves in order) to part[NV * idx + j]
+template <int NT, int NV>
+__device__ __forceinline__ void partials_store_at(const double (&v)[NV], double *part, int idx)
+{
+    __shared__ double sh[NV][NT / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; j++) {
+        double s = v[j];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+        if (lane == 0) sh[j][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < NV; j++) {
+            double b = 0;
+            for (int k = 0; k < NT / 64; k++) b += sh[j][k];
+            part[NV * idx + j] = b;
+        }
+}
+
+// partials of an operator launch, indexed by the logical block (the sites it covers)
+template <int NT, int NV>
+__device__ __forceinline__ void op_partials_store(const double (&v)[NV], double *part)
+{
+    partials_store_at<NT, NV>(v, part, xcd_block());
+}
+
+// the total of n partials (NV interleaved values) in the fixed order above, in every thread
+// of the workgroup (NT >= 128 threads, all of which must call this); at most 64 * MAXC
+// partials
+template <int NT, int NV, int MAXC>
+__device__ __forceinline__ void partials_total(const double *__restrict__ part, int n, double (&tot)[NV])
+{
+    static_assert(NT >= 128 && NT % 64 == 0, "at least two waves");
+    __shared__ double shc[MAXC];
+    __shared__ double sh2[2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nch = (n + 63) >> 6;
+    constexpr int NW = NT / 64, B = 8;   // chunks per wave and batch: their loads are issued together
+#pragma unroll
+    for (int j = 0; j < NV; j++) {
+        for (int c0 = w; c0 < nch; c0 += NW * B) {
+            double s[B];
+#pragma unroll
+            for (int b = 0; b < B; b++) {
+                const int k = 64 * (c0 + b * NW) + lane;
+                s[b] = k < n ? part[NV * k + j] : 0.0;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+                for (int b = 0; b < B; b++) s[b] += __shfl_down(s[b], o, 64);
+            if (lane == 0)
+#pragma unroll
+                for (int b = 0; b < B; b++)
+                    if (c0 + b * NW < nch) shc[c0 + b * NW] = s[b];
+        }
+        __syncthreads();
+        if (threadIdx.x < 128) {
+            double s = 0;
+            for (int c = threadIdx.x; c < nch; c += 128) s += shc[c];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+            if (lane == 0) sh2[w] = s;
+        }
+        __syncthreads();
+        tot[j] = sh2[0] + sh2[1];
+        __syncthreads();
+    }
+}
+
+// out[j] = total of n partials (one workgroup of kFinishThreads); skipped while *stop != 0
+template <int NV>
+__global__ __launch_bounds__(kFinishThreads) void k_total(const double *__restrict__ part, int n,
+                                                         double *__restrict__ out, const double *__restrict__ stop)
+{
+    if (stop && stop[0] != 0) return;
+    double t[NV];
+    partials_total<kFinishThreads, NV, kMaxChunks>(part, n, t);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < NV; j++) out[j] = t[j];
+}
+
+// launch k_total: the NV totals of n partials into the device scalars out (stream order)
+template <int NV>
+inline int launch_total(pfmp_ctx *ctx, const double *part, int n, double *out, const double *stop)
+{
+    if ((n + 63) / 64 > kMaxChunks) return set_err(ctx, PFMP_ERR_ARG, "totals: too many partials");
+    hipLaunchKernelGGL(k_total<NV>, dim3(1), dim3(kFinishThreads), 0, ctx->stream, part, n, out, stop);
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
 
 // operator stages (dslash.hip); In / X / T / Out: const C* / C* or HalfField; UL: const C*
 // or HalfLinks; CL: const R* or HalfClover

@@ -156,6 +156,15 @@ __device__ __forceinline__ int xcd_site(int n)
     return i < n ? i : -1;
 }
 
+// Logical block of this workgroup in the order above (a bijection onto [0, nb) when the
+// grid is a multiple of 8 workgroups, as for every operator launch)
+__device__ __forceinline__ int xcd_block()
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int per = (nb + 7) >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
 // The same block order for kernels with more lanes than the int range may hold
 // (several lanes per link or plane): the lane index, or n for every lane of the
 // blocks past the end, so that the kernel's own bound check (lane < n) drops them.

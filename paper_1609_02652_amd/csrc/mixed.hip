@@ -16,24 +16,8 @@
 
 namespace {
 
-enum { M_RR = 0, M_THR, M_DTHR, M_PAP, M_ALPHA, M_BETA, M_ITER, M_DONE, M_MAXIT, M_RROLD };
+enum { M_RR = 0, M_THR, M_DTHR, M_PAP, M_ALPHA, M_BETA, M_ITER, M_DONE, M_MAXIT, M_RROLD, M_ITNEXT };
 constexpr int kMixBase = 4096;    // device scalar slots of this solver (ctx->scal + kMixBase)
-
-// sum of n partials, the same in every block (fixed order); NT threads per block
-template <int NT>
-__device__ __forceinline__ double block_total_t(const double *__restrict__ part, int n)
-{
-    __shared__ double sh[NT / 64];
-    double s = 0;
-    for (int k = threadIdx.x; k < n; k += NT) s += part[k];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double t = 0;
-    for (int k = 0; k < NT / 64; k++) t += sh[k];
-    __syncthreads();
-    return t;
-}
 
 __device__ __forceinline__ double block_total_m(const double *__restrict__ partials, int nparts)
 {
@@ -68,21 +52,33 @@ __global__ __launch_bounds__(kRedBlock) void k_m_restart(const double *__restric
 }
 
 // FP32 Khat p from t = Mhat p and T' (as in the FP64 solver), fused with
-// x += alpha p, r -= alpha Khat p and FP64 |r|^2 partials.  alpha = |r|^2 / <p, Khat p>
-// is formed in every block from the stage-2 partials; block 0 keeps |r|^2 for beta.
-template <int CLOV, int LM, typename S, typename UL, typename CL>
+// x += alpha p, r -= alpha Khat p and the FP64 |r+|^2 partials.  alpha = |r|^2 / <p, Khat p>
+// with <p, Khat p> formed from the stage-2 partials by every block (INL) or read from M_PAP
+// (totalled by a one-block kernel); block 0 records alpha and, with INL, <p, Khat p>, |r|^2
+// (M_RROLD) and the next iteration count (M_ITNEXT) for the p update.
+template <int CLOV, int LM, int INL, typename S, typename UL, typename CL>
 __global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T, UL U, CL cl, float a, const S p,
                                                    float2 *__restrict__ x, float2 *__restrict__ r,
                                                    double *__restrict__ st, double *__restrict__ partials,
                                                    const double *__restrict__ part_pap, int npap)
 {
     if (st[M_DONE] != 0) return;
-    const double pap = block_total_t<kBlock>(part_pap, npap);
+    double pap;
+    if (INL) {
+        double tp[1];
+        partials_total<kBlock, 1, kInlineChunks>(part_pap, npap, tp);
+        pap = tp[0];
+    } else {
+        pap = st[M_PAP];
+    }
     const double alpha_d = st[M_RR] / pap;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st[M_PAP] = pap;
         st[M_ALPHA] = alpha_d;
-        st[M_RROLD] = st[M_RR];
+        if (INL) {
+            st[M_PAP] = pap;
+            st[M_RROLD] = st[M_RR];
+            st[M_ITNEXT] = st[M_ITER] + 1;
+        }
     }
     const int tt = xcd_site(2 * g.Vh);
     double nrm = 0;
@@ -98,26 +94,50 @@ __global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T,
 #pragma unroll
         for (int k = 0; k < 6; k++) {
             float2 base = CLOV ? at[k] : tv[k];
-            float2 kp = make_float2(base.x + a * acc[k].x, base.y + a * acc[k].y);
+            float2 kp = make_float2(fmadd(a, acc[k].x, base.x), fmadd(a, acc[k].y, base.y));
             if (hb) kp = cneg(kp);
             const long e = (long)(6 * hb + k) * Vh + i;
             float2 pv = pp[k], xv = x[e], rv = r[e];
-            xv.x += alpha * pv.x; xv.y += alpha * pv.y;
-            rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
+            xv.x = fmadd(alpha, pv.x, xv.x); xv.y = fmadd(alpha, pv.y, xv.y);
+            rv.x = fmadd(-alpha, kp.x, rv.x); rv.y = fmadd(-alpha, kp.y, rv.y);
             x[e] = xv;
             r[e] = rv;
             cnorm_acc(nrm, rv);
         }
     }
-    block_sum_store<float2>(nrm, partials);
+    const double v[1] = {nrm};
+    op_partials_store<kBlock, 1>(v, partials);
 }
 
-// p = r + beta p (per site: FP16 storage needs the site's 24 reals for its scale);
-// with st == nullptr: p = r.  With part_rr: beta = |r+|^2 / |r|^2 formed in every block
-// from the stage-4 partials; every block takes the same stop decision from it (1: inner
-// residual at the target, 3: dropped by delta -> reliable update, 2: iteration limit)
-// and skips the update then, which the restart after a reliable update relies on;
-// block 0 records the state.  Without part_rr: beta from st (restart).
+// The stop decision from |r+|^2 (1: inner residual at the target, 3: dropped by delta ->
+// reliable update, 2: iteration limit) and beta = |r+|^2 / |r|^2
+__device__ __forceinline__ int m_decide(double rr, double it, const double *st)
+{
+    return rr <= st[M_THR] ? 1 : (rr <= st[M_DTHR] ? 3 : (it >= st[M_MAXIT] ? 2 : 0));
+}
+
+// |r+|^2 from the stage-4 partials, the decision and beta; one workgroup (many partials)
+__global__ __launch_bounds__(kFinishThreads) void k_m_finish_rr(const double *__restrict__ part, int n,
+                                                               double *__restrict__ st)
+{
+    if (st[M_DONE] != 0) return;
+    double t[1];
+    partials_total<kFinishThreads, 1, kMaxChunks>(part, n, t);
+    if (threadIdx.x == 0) {
+        const double rr = t[0], it = st[M_ITER] + 1;
+        st[M_BETA] = rr / st[M_RR];
+        st[M_RR] = rr;
+        st[M_ITER] = it;
+        st[M_DONE] = m_decide(rr, it, st);
+    }
+}
+
+// p = r + beta p (per site: FP16 storage needs the site's 24 reals for its scale).  With
+// part_rr (INL): every block forms |r+|^2 from the stage-4 partials and takes the stop
+// decision from it and the iteration count M_ITNEXT (written by stage 4), the same in every
+// block, and skips the update on a stop, which the restart after a reliable update relies
+// on; block 0 records the state.  Without part_rr: beta and the decision from st (one-block
+// total, or the restart).  st == nullptr: p = r.
 template <typename S>
 __global__ __launch_bounds__(kBlock) void k_m_update_p(Geom g, const float2 *__restrict__ r, S p,
                                                        double *__restrict__ st, const double *__restrict__ part_rr,
@@ -126,9 +146,10 @@ __global__ __launch_bounds__(kBlock) void k_m_update_p(Geom g, const float2 *__r
     if (st && st[M_DONE] != 0) return;
     double bd = st ? st[M_BETA] : 0.0;
     if (part_rr) {
-        const double rr = block_total_t<kBlock>(part_rr, nrr);
-        const double it = st[M_ITER] + 1;
-        const int done = rr <= st[M_THR] ? 1 : (rr <= st[M_DTHR] ? 3 : (it >= st[M_MAXIT] ? 2 : 0));
+        double tr[1];
+        partials_total<kBlock, 1, kInlineChunks>(part_rr, nrr, tr);
+        const double rr = tr[0], it = st[M_ITNEXT];
+        const int done = m_decide(rr, it, st);
         bd = rr / st[M_RROLD];
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st[M_BETA] = bd;
@@ -146,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_m_update_p(Geom g, const float2 *__r
         const float b = (float)bd;
         load_spinor(p, g.Vh, i, 1.f, pv);
 #pragma unroll
-        for (int k = 0; k < 12; k++) rv[k] = make_float2(rv[k].x + b * pv[k].x, rv[k].y + b * pv[k].y);
+        for (int k = 0; k < 12; k++) rv[k] = make_float2(fmadd(b, pv[k].x, rv[k].x), fmadd(b, pv[k].y, rv[k].y));
     }
     store_spinor(p, g.Vh, i, 1.f, rv);
 }
@@ -252,6 +273,7 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
     const double delta = prm->delta > 0 ? prm->delta : (std::is_same<S, float2 *>::value ? 0.01 : 0.1);
     const bool cl = s.csw != 0;
     const float mk2 = (float)(-s.kappa * s.kappa);
+    const bool inl = totals_inline(nb);
     int rc;
     HIPCHK(ctx, hipMemsetAsync(x, 0, vb, ctx->stream));
     HIPCHK(ctx, hipMemsetAsync(xs, 0, fb, ctx->stream));
@@ -267,7 +289,7 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
     // r = b, rs = (float) b, p = rs
     hipLaunchKernelGGL(k_m_residual, dim3(ctx->nblk_red), dim3(kRedBlock), 0, ctx->stream, n, b, Kx, rs, ctx->red);
     hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
-                       nullptr, nullptr, 0);
+                       (double *)nullptr, (const double *)nullptr, 0);
     hipLaunchKernelGGL(k_m_restart, dim3(1), dim3(kRedBlock), 0, ctx->stream, ctx->red, ctx->nblk_red, tol2bb,
                        delta * delta, prm->maxiter, 1, sc);
     LAUNCHCHK(ctx);
@@ -282,21 +304,24 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
         if ((e = launch_xpay<float2, float, In, In, S, UL, CL>(ctx, 0, ps, Ts, links, clo0, mk2, ts, 1.f, cl, part_a,
                                                                 sc + M_DONE)))
             return e;
+        if (!inl && (e = launch_total<1>(ctx, part_a, nb, sc + M_PAP, sc + M_DONE))) return e;
         if ((e = launch_clovinv<float2, float, In, S, UL, CL>(ctx, 1, ts, links, clo1, Ts, -1.f, 1.f, cl,
                                                                sc + M_DONE)))
             return e;
-#define MHOP4(CV, LM)                                                                                       \
-    hipLaunchKernelGGL((k_m_hop4<CV, LM, In, UL, CL>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, links, \
+#define MHOP4(CV, LM, IN)                                                                                       \
+    hipLaunchKernelGGL((k_m_hop4<CV, LM, IN, In, UL, CL>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, ts, Ts, links, \
                        clo0, mk2, ps, xs, rs, sc, part_b, part_a, nb)
-#define MHOP4_1(LM) MHOP4(1, LM)
-#define MHOP4_0(LM) MHOP4(0, LM)
+#define MHOP4_1(LM) if (inl) MHOP4(1, LM, 1); else MHOP4(1, LM, 0)
+#define MHOP4_0(LM) if (inl) MHOP4(0, LM, 1); else MHOP4(0, LM, 0)
         if (cl) { PFMP_LM_SWITCH(link_mode(g), MHOP4_1) }
         else { PFMP_LM_SWITCH(link_mode(g), MHOP4_0) }
 #undef MHOP4_1
 #undef MHOP4_0
 #undef MHOP4
+        if (!inl)
+            hipLaunchKernelGGL(k_m_finish_rr, dim3(1), dim3(kFinishThreads), 0, ctx->stream, part_b, nb, sc);
         hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
-                           sc, part_b, nb);
+                           sc, inl ? (const double *)part_b : (const double *)nullptr, nb);
         LAUNCHCHK(ctx);
         return 0;
     };
@@ -334,7 +359,7 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
         hipLaunchKernelGGL(k_m_restart, dim3(1), dim3(kRedBlock), 0, ctx->stream, ctx->red, ctx->nblk_red, tol2bb,
                            delta * delta, prm->maxiter, 0, sc);
         hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
-                           sc, nullptr, 0);
+                           sc, (const double *)nullptr, 0);
         LAUNCHCHK(ctx);
         // the next chunk: about as long as the last stretch between reliable updates
         if (prm->check_every <= 0) {

@@ -31,7 +31,7 @@ __device__ __forceinline__ float2 fconj(float2 a) { return make_float2(a.x, -a.y
 // device scalars of the flexible CG (ctx->scal + kFcgBase)
 constexpr int kFcgBase = 7600;
 enum { F_RZ = 0, F_PQ, F_ALPHA, F_RN2, F_THR, F_ITER, F_DONE, F_MAXIT, F_INVR, F_NR, F_BETA, F_FB, F_NFB, F_RZOLD,
-       F_NSLOT };
+       F_ZR, F_ZQ, F_NSLOT };
 
 // The transporter T_d(y) of the site y with coordinates c, loaded once per direction:
 // U_mu(y) for d = 2 mu, U_mu(y - mu)^dag for d = 2 mu + 1, and its fermion boundary factor.
@@ -236,25 +236,8 @@ __global__ __launch_bounds__(kBlock) void k_pt_l2(Geom g, const float2 *__restri
         }
     }
     if (dots) {
-        __shared__ double sh[2][kBlock / 64];
-        for (int off = 32; off > 0; off >>= 1) {
-            dzr += __shfl_down(dzr, off, 64);
-            dzq += __shfl_down(dzq, off, 64);
-        }
-        if ((threadIdx.x & 63) == 0) {
-            sh[0][threadIdx.x >> 6] = dzr;
-            sh[1][threadIdx.x >> 6] = dzq;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double a = 0, b = 0;
-            for (int k = 0; k < kBlock / 64; k++) {
-                a += sh[0][k];
-                b += sh[1][k];
-            }
-            dots[2 * blockIdx.x] = a;
-            dots[2 * blockIdx.x + 1] = b;
-        }
+        const double v[2] = {dzr, dzq};
+        partials_store_at<kBlock, 2>(v, dots, blockIdx.x);
     }
 }
 
@@ -535,37 +518,20 @@ __global__ void k_pt_sum(const double *__restrict__ mid, int nvals, double *__re
 //
 // Every scalar lives in fs (device); a chunk of iterations runs without the host.
 
-// sum of n block partials, identical in every block (fixed order)
-__device__ __forceinline__ double block_total_f(const double *__restrict__ part, int n)
-{
-    __shared__ double sh[kBlock / 64];
-    double s = 0;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) s += part[k];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double t = 0;
-    for (int k = 0; k < kBlock / 64; k++) t += sh[k];
-    __syncthreads();
-    return t;
-}
-
-// q = Khat p (from t = Mhat p, T' = A_oo^-1 D_oe g5 t), alpha = rz / <p, q> (the <p, q>
-// partials come from stage 2), x += alpha p, r -= alpha q; |r|^2 partials
+// q = Khat p (from t = Mhat p, T' = A_oo^-1 D_oe g5 t), alpha = rz / <p, q> (<p, q>
+// totalled from the stage-2 partials by a one-block kernel), x += alpha p, r -= alpha q;
+// |r|^2 partials
 template <int CLOV, int LM>
 __global__ __launch_bounds__(kBlock) void k_f_hop4(Geom g, const double2 *__restrict__ t,
                                                    const double2 *__restrict__ T, const double2 *__restrict__ U,
                                                    const double *__restrict__ cl, double a,
                                                    const double2 *__restrict__ p, double2 *__restrict__ q,
                                                    double2 *__restrict__ x, double2 *__restrict__ r,
-                                                   const double *__restrict__ part_pq, int npart,
                                                    double *__restrict__ fs, double *__restrict__ part_rr)
 {
     if (fs[F_DONE] != 0) return;
-    const double pq = block_total_f(part_pq, npart);
-    const double alpha = fs[F_RZ] / pq;
+    const double alpha = fs[F_RZ] / fs[F_PQ];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        fs[F_PQ] = pq;
         fs[F_ALPHA] = alpha;
         fs[F_RZOLD] = fs[F_RZ];
     }
@@ -592,23 +558,19 @@ __global__ __launch_bounds__(kBlock) void k_f_hop4(Geom g, const double2 *__rest
             cnorm_acc(nrm, rv);
         }
     }
-    block_sum_store<double2>(nrm, part_rr);
+    const double v[1] = {nrm};
+    op_partials_store<kBlock, 1>(v, part_rr);
 }
 
-// |r|^2, convergence, 1/|r| for the network
-__global__ __launch_bounds__(kRedBlock) void k_f_norm(const double *__restrict__ part, int n,
-                                                      double *__restrict__ fs)
+// |r|^2 from the stage-4 partials, convergence, |r| and 1/|r| for the network (one workgroup)
+__global__ __launch_bounds__(kFinishThreads) void k_f_norm(const double *__restrict__ part, int n,
+                                                          double *__restrict__ fs)
 {
     if (fs[F_DONE] != 0) return;
-    __shared__ double sh[kRedBlock / 64];
-    double s = 0;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) s += part[k];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
+    double t[1];
+    partials_total<kFinishThreads, 1, kMaxChunks>(part, n, t);
     if (threadIdx.x == 0) {
-        double rr = 0;
-        for (int k = 0; k < kRedBlock / 64; k++) rr += sh[k];
+        const double rr = t[0];
         fs[F_RN2] = rr;
         fs[F_NR] = sqrt(rr);
         fs[F_INVR] = rr > 0 ? 1.0 / sqrt(rr) : 0.0;
@@ -702,36 +664,16 @@ __global__ void k_f_update_p(long n, const double2 *__restrict__ z, const double
     p[e] = make_double2(v.x + b * pv.x, v.y + b * pv.y);
 }
 
-// Polak-Ribiere step fused with p: <z, r> and <z, q> from the block partials of the
-// network's second layer (the same sums in every block), beta = -alpha <z, q> / rz_old
-// or the plain-CG fallback (z = r, beta = 0) where <z, r> <= 0; p = z + beta p.  Block 0
-// records rz and the fallback count.
+// Polak-Ribiere step fused with p: <z, r> and <z, q> totalled from the network's second
+// layer's partials by a one-block kernel, beta = -alpha <z, q> / rz_old or the plain-CG fallback (z = r, beta = 0) where
+// <z, r> <= 0; p = z + beta p.  Block 0 records rz and the fallback count (no block reads
+// them in this launch).
 __global__ __launch_bounds__(kRedBlock) void k_f_update_p_fused(long n, const double2 *__restrict__ z,
                                                                 const double2 *__restrict__ r,
-                                                                double2 *__restrict__ p, double *__restrict__ fs,
-                                                                const double *__restrict__ dots, int nd)
+                                                                double2 *__restrict__ p, double *__restrict__ fs)
 {
     if (fs[F_DONE] != 0) return;
-    __shared__ double sh[2][kRedBlock / 64];
-    double a = 0, b = 0;
-    for (int k = threadIdx.x; k < nd; k += blockDim.x) {
-        a += dots[2 * k];
-        b += dots[2 * k + 1];
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_down(a, o, 64);
-        b += __shfl_down(b, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        sh[0][threadIdx.x >> 6] = a;
-        sh[1][threadIdx.x >> 6] = b;
-    }
-    __syncthreads();
-    double zr = 0, zq = 0;
-    for (int k = 0; k < kRedBlock / 64; k++) {
-        zr += sh[0][k];
-        zq += sh[1][k];
-    }
+    const double zr = fs[F_ZR], zq = fs[F_ZQ];
     const bool fb = !(zr > 0);
     const double beta = fb ? 0.0 : -fs[F_ALPHA] * zq / fs[F_RZOLD];
     const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -1016,6 +958,7 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
             hipLaunchKernelGGL(k_pt_l2, pgrid, pblock, 0, ctx->stream, g, ctx->Uf, r, 0.f, w.W, w.G, 0.0, z,
                                (float2 *)nullptr, (const double *)fs, (const double2 *)q, dots);
             LAUNCHCHK(ctx);
+            if (dots) return launch_total<2>(ctx, dots, nl2, fs + F_ZR, fs + F_DONE);
             return 0;
         }
         HIPCHK(ctx, hipMemcpyAsync(z, r, vb, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1034,10 +977,11 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
         // <p, Khat p> = |Mhat p|^2 partials, then q = Khat p fused with the x, r updates
         if ((e = clovinv64(ctx, 1, p, s.clov[1], T, 1.0, 1.0, cl, fs + F_DONE))) return e;
         if ((e = xpay64(ctx, 0, p, T, s.clov[0], mk2, t, 1.0, cl, part_a, fs + F_DONE))) return e;
+        if ((e = launch_total<1>(ctx, part_a, nb, fs + F_PQ, fs + F_DONE))) return e;
         if ((e = clovinv64(ctx, 1, t, s.clov[1], T, -1.0, 1.0, cl, fs + F_DONE))) return e;
 #define FHOP4(CL, LM)                                                                                        \
     hipLaunchKernelGGL((k_f_hop4<CL, LM>), dim3(nb), dim3(kBlock), 0, ctx->stream, g, t, T, ctx->U, s.clov[0], mk2, \
-                       p, q, x, r, part_a, nb, fs, part_b)
+                       p, q, x, r, fs, part_b)
 #define FHOP4_1(LM) FHOP4(1, LM)
 #define FHOP4_0(LM) FHOP4(0, LM)
         if (cl) { PFMP_LM_SWITCH(link_mode(g), FHOP4_1) }
@@ -1045,16 +989,16 @@ extern "C" int pfmp_fcg_solve(pfmp_ctx *ctx, int op, const double *W, const void
 #undef FHOP4_1
 #undef FHOP4_0
 #undef FHOP4
-        hipLaunchKernelGGL(k_f_norm, dim3(1), dim3(kRedBlock), 0, ctx->stream, part_b, nb, fs);
+        hipLaunchKernelGGL(k_f_norm, dim3(1), dim3(kFinishThreads), 0, ctx->stream, part_b, nb, fs);
         LAUNCHCHK(ctx);
         if (use_net) {
-            // z = N(r) with the <z, r>, <z, q> partials, then beta and p in one launch
+            // z = N(r) with <z, r> and <z, q>, then beta and p in one launch
             dots = part_b;
             e = precondition();
             dots = nullptr;
             if (e) return e;
             hipLaunchKernelGGL(k_f_update_p_fused, dim3(nblocks(n, kRedBlock)), dim3(kRedBlock), 0, ctx->stream, n, z,
-                               r, p, fs, part_b, nl2);
+                               r, p, fs);
         } else {
             // identity: z = r is read directly
             hipLaunchKernelGGL(k_f_dots, dim3(ndot), dim3(kBlock), 0, ctx->stream, n, r, r, q, fs, part_b);

@@ -1,14 +1,15 @@
 // solver.hip -- CG on Khat and multi-shift CG (paper Sec. 2.1; App. C), FP64.
 //
 // The iteration never waits for the host: every scalar (alpha, beta, |r|^2, the
-// shift recurrences) lives in device memory, is formed by single-block kernels
-// from deterministic block partials, and a "done" flag written on the device
-// turns the remaining launches of a chunk into early exits.  The host only looks
-// at the flag once per chunk of iterations.
+// shift recurrences) lives in device memory and is formed from block partials in one
+// fixed order (partials_total): by every block of the kernel that needs it while the
+// lattice gives few partials, else once by a one-block kernel.  A "done" flag written
+// on the device turns the remaining launches of a chunk into early exits; the host only
+// looks at it once per chunk of iterations.
 //
-// CG iteration (5 launches): hop1, hop2 (|Mhat p|^2 = <p, Khat p> partials), hop3,
-// hop4 fused with alpha, x += alpha p, r -= alpha Khat p and |r|^2 partials, and
-// p = r + beta p fused with beta and the convergence test.
+// CG iteration (5 launches, 7 on large lattices): hop1, hop2 (|Mhat p|^2 = <p, Khat p>
+// partials), [its total], hop3, hop4 fused with alpha, x += alpha p, r -= alpha Khat p and
+// the |r+|^2 partials, [|r+|^2, beta and the stop test], p = r + beta p.
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -19,7 +20,8 @@ namespace {
 
 // device scalar slots in ctx->scal
 enum { S_RR = 0, S_THR, S_PAP, S_ALPHA, S_BETA, S_ITER, S_DONE, S_MAXIT, S_BB, S_APREV, S_BPREV, S_CACT, S_NACT,
-       S_RROLD };   // |r|^2 at the start of the iteration (fused CG kernels)
+       S_RROLD,     // |r|^2 at the start of the iteration (stage 4, for beta)
+       S_ITNEXT };  // iteration count after this iteration (stage 4, for the stop decision)
 constexpr int kShiftBase = 64;   // per-shift records start here
 struct ShiftRec {                // 16 doubles
     double2 sigma, zp, z, zn, as, bs;
@@ -75,62 +77,41 @@ __global__ void k_cg_init(const double *__restrict__ partials, int nparts, doubl
     }
 }
 
-// sum of n partials, the same in every block and thread (fixed order); NT threads
-template <int NT>
-__device__ __forceinline__ double block_total_n(const double *__restrict__ part, int n)
-{
-    __shared__ double sh[NT / 64];
-    double s = 0;
-    for (int k = threadIdx.x; k < n; k += NT) s += part[k];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double t = 0;
-    for (int k = 0; k < NT / 64; k++) t += sh[k];
-    __syncthreads();
-    return t;
-}
-
-__device__ __forceinline__ double block_total(const double *__restrict__ partials, int nparts)
-{
-    __shared__ double sh[kRedBlock / 64];
-    double s = 0;
-    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += partials[k];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double t = 0;
-    for (int k = 0; k < kRedBlock / 64; k++) t += sh[k];
-    return t;
-}
-
 // Khat p from t = Mhat p and T' = A_oo^-1 D_oe g5 t:  Kp = g5 (A_ee g5 t - kappa^2 D_eo T');
-// then x += alpha p, r -= alpha Kp, |r|^2 partials.
-// SELF = 1: alpha = |r|^2 / <p, Khat p> formed in every block from the stage-2 partials
-// (part_pap, npap); block 0 keeps |r|^2 in S_RROLD for beta.  SELF = 0: alpha from st.
-// SELF: alpha formed from the <p, Khat p> partials in every block; MS (multi-shift, with
-// SELF): block 0 also steps the shifts' zeta and alpha_s
-template <int CLOV, int LM, int SELF, int MS = 0>
+// then x += alpha p, r -= alpha Kp and the |r+|^2 partials.  alpha = |r|^2 / <p, Khat p>:
+// INL = 1, every block forms <p, Khat p> from the stage-2 partials (part_pap, npap), and
+// block 0 records it with alpha, |r|^2 (S_RROLD) and the next iteration count (S_ITNEXT)
+// for the p update; INL = 0, <p, Khat p> was totalled into S_PAP by a one-block kernel.
+// MS (multi-shift): block 0 also steps the shifts' zeta and alpha_s.
+template <int CLOV, int LM, int MS, int INL>
 __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__restrict__ t,
                                                     const double2 *__restrict__ T, const double2 *__restrict__ U,
                                                     const double *__restrict__ cl, double a,
                                                     const double2 *__restrict__ p, double2 *__restrict__ x,
                                                     double2 *__restrict__ r, double *__restrict__ st,
-                                                    double *__restrict__ partials,
-                                                    const double *__restrict__ part_pap, int npap,
-                                                    ShiftRec *__restrict__ rec = nullptr, int ns = 0)
+                                                    double *__restrict__ partials, const double *__restrict__ part_pap,
+                                                    int npap, ShiftRec *__restrict__ rec = nullptr, int ns = 0)
 {
     if (st[S_DONE] != 0) return;
-    double alpha_self = 0;
-    if (SELF) {
-        const double pap = block_total_n<kBlock>(part_pap, npap);
-        alpha_self = st[S_RR] / pap;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            st[S_PAP] = pap;
-            st[S_ALPHA] = alpha_self;
-            st[S_RROLD] = st[S_RR];
+    double pap;
+    if (INL) {
+        double tp[1];
+        partials_total<kBlock, 1, kInlineChunks>(part_pap, npap, tp);
+        pap = tp[0];
+    } else {
+        pap = st[S_PAP];
+    }
+    const double alpha = st[S_RR] / pap;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            st[S_ALPHA] = alpha;
+            if (INL) {
+                st[S_PAP] = pap;
+                st[S_RROLD] = st[S_RR];
+                st[S_ITNEXT] = st[S_ITER] + 1;
+            }
         }
-        if (MS && blockIdx.x == 0) ms_shift_alphas(alpha_self, st, ns, rec);
+        if (MS) ms_shift_alphas(alpha, st, ns, rec);
     }
     const int tt = xcd_site(2 * g.Vh);
     double nrm = 0;
@@ -140,38 +121,37 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
         hop_pair<LM, double2>(g, 0, i, hb, T, U, 1.0, acc);
         load_block(t, g.Vh, i, hb, -1.0, tv);
         if (CLOV) clover_block<double, double2>(cl, g.Vh, i, hb, tv, at);
-        const double alpha = SELF ? alpha_self : st[S_ALPHA];
         const long Vh = g.Vh;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
             double2 base = CLOV ? at[k] : tv[k];
-            double2 kp = make_double2(base.x + a * acc[k].x, base.y + a * acc[k].y);
+            double2 kp = make_double2(fmadd(a, acc[k].x, base.x), fmadd(a, acc[k].y, base.y));
             if (hb) kp = cneg(kp);
             const long e = (long)(6 * hb + k) * Vh + i;
             double2 pv = p[e], xv = x[e], rv = r[e];
-            xv.x += alpha * pv.x; xv.y += alpha * pv.y;
-            rv.x -= alpha * kp.x; rv.y -= alpha * kp.y;
+            xv.x = fmadd(alpha, pv.x, xv.x); xv.y = fmadd(alpha, pv.y, xv.y);
+            rv.x = fmadd(-alpha, kp.x, rv.x); rv.y = fmadd(-alpha, kp.y, rv.y);
             x[e] = xv;
             r[e] = rv;
             cnorm_acc(nrm, rv);
         }
     }
-    block_sum_store<double2>(nrm, partials);
+    const double v[1] = {nrm};
+    op_partials_store<kBlock, 1>(v, partials);
 }
 
-// stage 4 with alpha formed in the kernel from the <p, Khat p> partials (fused CG); with
-// rec, block 0 also steps the ns shifts' coefficients (multi-shift CG)
-static void launch_cg_hop4(pfmp_ctx *ctx, bool cl, int nb, const double2 *t, const double2 *T, const double *clov,
-                           double mk2, const double2 *p, double2 *x, double2 *r, double *part,
+// stage 4 of the fused CG (with rec: of the multi-shift CG)
+static void launch_cg_hop4(pfmp_ctx *ctx, bool cl, bool inl, int nb, const double2 *t, const double2 *T,
+                           const double *clov, double mk2, const double2 *p, double2 *x, double2 *r, double *part,
                            const double *part_pap, ShiftRec *rec = nullptr, int ns = 0)
 {
-#define HOP4(CL, LM, MS)                                                                                       \
-    hipLaunchKernelGGL((k_cg_hop4<CL, LM, 1, MS>), dim3(nb), dim3(kBlock), 0, ctx->stream, ctx->g, t, T, ctx->U, \
+#define HOP4(CL, LM, MS, IN)                                                                                     \
+    hipLaunchKernelGGL((k_cg_hop4<CL, LM, MS, IN>), dim3(nb), dim3(kBlock), 0, ctx->stream, ctx->g, t, T, ctx->U, \
                        clov, mk2, p, x, r, ctx->scal, part, part_pap, nb, rec, ns)
-#define HOP4_11(LM) HOP4(1, LM, 1)
-#define HOP4_10(LM) HOP4(1, LM, 0)
-#define HOP4_01(LM) HOP4(0, LM, 1)
-#define HOP4_00(LM) HOP4(0, LM, 0)
+#define HOP4_11(LM) if (inl) HOP4(1, LM, 1, 1); else HOP4(1, LM, 1, 0)
+#define HOP4_10(LM) if (inl) HOP4(1, LM, 0, 1); else HOP4(1, LM, 0, 0)
+#define HOP4_01(LM) if (inl) HOP4(0, LM, 1, 1); else HOP4(0, LM, 1, 0)
+#define HOP4_00(LM) if (inl) HOP4(0, LM, 0, 1); else HOP4(0, LM, 0, 0)
     const int lm = link_mode(ctx->g);
     if (cl && rec) { PFMP_LM_SWITCH(lm, HOP4_11) }
     else if (cl) { PFMP_LM_SWITCH(lm, HOP4_10) }
@@ -184,25 +164,55 @@ static void launch_cg_hop4(pfmp_ctx *ctx, bool cl, int nb, const double2 *t, con
 #undef HOP4
 }
 
-// beta = |r+|^2 / |r|^2 formed in every block from the stage-4 partials, p = r + beta p;
-// block 0 records |r+|^2, the iteration count and the stop flag
-__global__ __launch_bounds__(kRedBlock) void k_cg_update_p_fused(long n, const double2 *__restrict__ r,
-                                                                 double2 *__restrict__ p, double *__restrict__ st,
-                                                                 const double *__restrict__ part_rr, int nrr)
+// |r+|^2 from the stage-4 partials, beta = |r+|^2 / |r|^2 and the stop decision; one
+// workgroup (many partials)
+__global__ __launch_bounds__(kFinishThreads) void k_cg_finish_rr(const double *__restrict__ part, int n,
+                                                                double *__restrict__ st)
 {
     if (st[S_DONE] != 0) return;
-    const double rr = block_total_n<kRedBlock>(part_rr, nrr);
-    const double b = rr / st[S_RROLD];
+    double t[1];
+    partials_total<kFinishThreads, 1, kMaxChunks>(part, n, t);
+    if (threadIdx.x == 0) {
+        const double rr = t[0], it = st[S_ITER] + 1;
+        st[S_BETA] = rr / st[S_RR];
+        st[S_RR] = rr;
+        st[S_ITER] = it;
+        st[S_DONE] = rr <= st[S_THR] ? 1 : (it >= st[S_MAXIT] ? 2 : 0);
+    }
+}
+
+// p = r + beta p.  INL = 1: every block forms |r+|^2 from the stage-4 partials and with it
+// beta = |r+|^2 / S_RROLD and the stop decision (iteration count S_ITNEXT, written by stage
+// 4), all the same in every block; block 0 records them.  (A block that starts after block 0
+// has written S_DONE returns at once, as it would have after taking the same decision.)
+// INL = 0: beta and the decision were recorded by k_cg_finish_rr.
+template <int INL>
+__global__ __launch_bounds__(kRedBlock) void k_cg_update_p(long n, const double2 *__restrict__ r,
+                                                           double2 *__restrict__ p, double *__restrict__ st,
+                                                           const double *__restrict__ part_rr, int nrr)
+{
+    if (st[S_DONE] != 0) return;
+    double b;
+    if (INL) {
+        double tr[1];
+        partials_total<kRedBlock, 1, kInlineChunks>(part_rr, nrr, tr);
+        const double rr = tr[0], it = st[S_ITNEXT];
+        const int done = rr <= st[S_THR] ? 1 : (it >= st[S_MAXIT] ? 2 : 0);
+        b = rr / st[S_RROLD];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st[S_BETA] = b;
+            st[S_RR] = rr;
+            st[S_ITER] = it;
+            st[S_DONE] = done;
+        }
+        if (done) return;
+    } else {
+        b = st[S_BETA];
+    }
     const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (e < n) {
         double2 rv = r[e], pv = p[e];
-        p[e] = make_double2(rv.x + b * pv.x, rv.y + b * pv.y);
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st[S_BETA] = b;
-        st[S_RR] = rr;
-        st[S_ITER] += 1;
-        st[S_DONE] = rr <= st[S_THR] ? 1 : (st[S_ITER] >= st[S_MAXIT] ? 2 : 0);
+        p[e] = make_double2(fmadd(b, pv.x, rv.x), fmadd(b, pv.y, rv.y));
     }
 }
 
@@ -236,14 +246,17 @@ __global__ void k_ms_init(int ns, const double *__restrict__ zs, ShiftRec *__res
     rec[s] = q;
 }
 
-__global__ __launch_bounds__(kRedBlock) void k_ms_beta(const double *__restrict__ partials, int nparts, int ns,
-                                                       double *__restrict__ st, ShiftRec *__restrict__ rec)
+__global__ __launch_bounds__(kFinishThreads) void k_ms_beta(const double *__restrict__ partials, int nparts,
+                                                            int ns, double *__restrict__ st,
+                                                            ShiftRec *__restrict__ rec)
 {
     if (st[S_DONE] != 0) {
         if (threadIdx.x == 0) st[S_CACT] = 0;
         return;
     }
-    double rr = block_total(partials, nparts);
+    double tr[1];
+    partials_total<kFinishThreads, 1, kMaxChunks>(partials, nparts, tr);
+    const double rr = tr[0];
     double beta = rr / st[S_RR];
     __shared__ int nact;
     if (threadIdx.x == 0) nact = 0;
@@ -399,20 +412,30 @@ extern "C" int pfmp_cg_solve(pfmp_ctx *ctx, int op, const void *b_, void *x_, co
     LAUNCHCHK(ctx);
     const bool cl = s.csw != 0;
     const double mk2 = -s.kappa * s.kappa;
+    const bool inl = totals_inline(nb);
     int chunk = prm->check_every > 0 ? prm->check_every : 25;
     double h[16], rr_prev = 0, it_prev = 0;
-    // one iteration: 5 launches with fixed arguments, replayed as a graph
+    // one iteration: 5 launches with fixed arguments (7 with the two one-block totals of a
+    // large lattice), replayed as a graph
     auto iteration = [&]() -> int {
         int e;
         // t = Mhat p, with <p, Khat p> = |t|^2 partials
         if ((e = clovinv64(ctx, 1, B.p, s.clov[1], B.T, 1.0, 1.0, cl, ctx->scal + S_DONE))) return e;
         if ((e = xpay64(ctx, 0, B.p, B.T, s.clov[0], mk2, B.t, 1.0, cl, B.part_a, ctx->scal + S_DONE))) return e;
+        if (!inl && (e = launch_total<1>(ctx, B.part_a, nb, ctx->scal + S_PAP, ctx->scal + S_DONE))) return e;
         // T' = A_oo^-1 D_oe g5 t
         if ((e = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE))) return e;
-        // alpha, x and r updates; then beta and p, each formed where it is used
-        launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, x, B.r, B.part_b, B.part_a);
-        hipLaunchKernelGGL(k_cg_update_p_fused, dim3(nblocks(n, kRedBlock)), dim3(kRedBlock), 0, ctx->stream, n,
-                           B.r, B.p, ctx->scal, B.part_b, nb);
+        // alpha, x and r updates and the |r+|^2 partials; then beta, the stop test and p
+        launch_cg_hop4(ctx, cl, inl, nb, B.t, B.T, s.clov[0], mk2, B.p, x, B.r, B.part_b, B.part_a);
+        if (!inl)
+            hipLaunchKernelGGL(k_cg_finish_rr, dim3(1), dim3(kFinishThreads), 0, ctx->stream, B.part_b, nb,
+                               ctx->scal);
+        if (inl)
+            hipLaunchKernelGGL(k_cg_update_p<1>, dim3(nblocks(n, kRedBlock)), dim3(kRedBlock), 0, ctx->stream, n,
+                               B.r, B.p, ctx->scal, B.part_b, nb);
+        else
+            hipLaunchKernelGGL(k_cg_update_p<0>, dim3(nblocks(n, kRedBlock)), dim3(kRedBlock), 0, ctx->stream, n,
+                               B.r, B.p, ctx->scal, B.part_b, nb);
         LAUNCHCHK(ctx);
         return 0;
     };
@@ -501,17 +524,20 @@ extern "C" int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const doubl
     LAUNCHCHK(ctx);
     const bool cl = s.csw != 0;
     const double mk2 = -s.kappa * s.kappa;
+    const bool inl = totals_inline(nb);
     int chunk = prm->check_every > 0 ? prm->check_every : 25;
     double h[16], rr_prev = 0, it_prev = 0;
-    // one iteration: 6 launches with fixed arguments, replayed as a graph
+    // one iteration: 6 launches with fixed arguments (7 with the one-block total of a large
+    // lattice), replayed as a graph
     auto iteration = [&]() -> int {
         int e;
         if ((e = clovinv64(ctx, 1, B.p, s.clov[1], B.T, 1.0, 1.0, cl, ctx->scal + S_DONE))) return e;
         if ((e = xpay64(ctx, 0, B.p, B.T, s.clov[0], mk2, B.t, 1.0, cl, B.part_a, ctx->scal + S_DONE))) return e;
+        if (!inl && (e = launch_total<1>(ctx, B.part_a, nb, ctx->scal + S_PAP, ctx->scal + S_DONE))) return e;
         if ((e = clovinv64(ctx, 1, B.t, s.clov[1], B.T, -1.0, 1.0, cl, ctx->scal + S_DONE))) return e;
         // r -= alpha Khat p (the base x is not needed; it goes to scratch)
-        launch_cg_hop4(ctx, cl, nb, B.t, B.T, s.clov[0], mk2, B.p, B.Kx, B.r, B.part_b, B.part_a, rec, nshift);
-        hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(kRedBlock), 0, ctx->stream, B.part_b, nb, nshift, ctx->scal,
+        launch_cg_hop4(ctx, cl, inl, nb, B.t, B.T, s.clov[0], mk2, B.p, B.Kx, B.r, B.part_b, B.part_a, rec, nshift);
+        hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(kFinishThreads), 0, ctx->stream, B.part_b, nb, nshift, ctx->scal,
                            rec);
         hipLaunchKernelGGL(k_ms_update, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, nshift, B.r, B.p, ptrs,
                            ptrs + nshift, rec, ctx->scal);

@@ -344,12 +344,13 @@ class Lattice:
         return out
 
     def apply_M(self, op, x, dagger=False, prec=F64, out=None):
-        out = self.field(FIELD_SPINOR, prec, zero=False) if out is None else out
+        # F16: FP32 fields in and out (FP16 storage inside the library)
+        out = self.field(FIELD_SPINOR, F32 if prec == F16 else prec, zero=False) if out is None else out
         self._chk(self.lib.pfmp_apply_M(self.h, op, int(dagger), _ptr(x), _ptr(out), prec), "apply_M")
         return out
 
     def apply_MdagM(self, op, x, prec=F64, out=None):
-        out = self.field(FIELD_SPINOR, prec, zero=False) if out is None else out
+        out = self.field(FIELD_SPINOR, F32 if prec == F16 else prec, zero=False) if out is None else out
         self._chk(self.lib.pfmp_apply_MdagM(self.h, op, _ptr(x), _ptr(out), prec), "apply_MdagM")
         return out
 

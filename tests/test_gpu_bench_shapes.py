@@ -2,8 +2,8 @@
 trajectory lattice) and 32^3 x 64 (the bandwidth lattice), in the launch
 configuration the benchmark times: the visit order and link-load mode chosen by
 the autotuner.  The FP64 hop D_oe, Mhat and Mhat^dag are compared on sampled
-output sites with the oracle evaluated site by site; the FP32 Mhat error against
-the same samples is stated."""
+output sites with the oracle evaluated site by site; the FP32 and FP16-storage Mhat
+errors against the same samples are stated."""
 import numpy as np
 import pytest
 
@@ -21,7 +21,7 @@ def rel(a, b):
 
 @pytest.mark.parametrize("dims", [(16, 16, 16, 32), (32, 32, 32, 64)], ids=lambda d: "x".join(map(str, d)))
 def test_operator_sampled_at_bench_shape(dims):
-    from paper_1609_02652_amd.pfmp import Lattice, F32
+    from paper_1609_02652_amd.pfmp import Lattice, F32, F16
     print("case", dims, flush=True)
     U = synth.random_gauge(dims, seed=5)
     lat = Lattice(dims)
@@ -45,5 +45,13 @@ def test_operator_sampled_at_bench_shape(dims):
         e32 = rel(lat.spinor_numpy(lat.apply_M(0, x32, prec=F32), prec=F32)[sites], want[False])
         print("fp32 Mhat rel err on the samples", e32, flush=True)
         assert e32 < 2e-6
+        # FP16 spinor storage (input rounded, the odd intermediate and the result stored in
+        # FP16 with a per-site scale) with the FP16 and with the FP32 copies of links and clover
+        for half_links in (1, 0):
+            lat.half_links(half_links)
+            e16 = rel(lat.spinor_numpy(lat.apply_M(0, x32, prec=F16), prec=F32)[sites], want[False])
+            print("fp16-storage Mhat rel err on the samples (half links %d): %.3e" % (half_links, e16), flush=True)
+            assert e16 < 3e-3
+        lat.half_links(1)
     finally:
         lat.close()

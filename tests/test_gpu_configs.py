@@ -16,6 +16,7 @@ hold at any size or on outputs the oracle computes site by site:
 import math
 
 import numpy as np
+import torch
 import pytest
 
 import oracle
@@ -45,8 +46,7 @@ def test_batched_chain_24x24x24x48():
         xs = [lat.pack_spinor(p) for p in psis]
         outs = lat.apply_MdagM_batch(ops, xs)
         for q, o in enumerate(ops):
-            single = lat.spinor_numpy(lat.apply_MdagM(o, xs[q]))
-            assert rel(lat.spinor_numpy(outs[q]), single) < 1e-14
+            assert torch.equal(outs[q], lat.apply_MdagM(o, xs[q]))
         # the oracle's Mhat on sampled sites of the first operator
         rng = np.random.default_rng(3)
         sites = np.unique(rng.choice(lat.Vh, 96, replace=False))
@@ -58,8 +58,9 @@ def test_batched_chain_24x24x24x48():
             xq, sq = lat.cg_solve(o, xs[q], tol=1e-10, maxiter=20000)
             print("rhs", q, "op", o, "iters", stats[q]["iters"], sq["iters"], "res", stats[q]["true_res"], flush=True)
             assert stats[q]["true_res"] <= 1e-10
-            assert abs(stats[q]["iters"] - sq["iters"]) <= 1
-            assert rel(lat.spinor_numpy(sols[q]), lat.spinor_numpy(xq)) < 1e-8
+            # the batch gives each right-hand side the bits of its single-RHS solve
+            assert stats[q]["iters"] == sq["iters"]
+            assert torch.equal(sols[q], xq)
     finally:
         lat.close()
 

@@ -102,11 +102,14 @@ def test_trajectory_matches_oracle(U0):
     print("dH gpu %.12f oracle %.12f" % (st["dH"], ref["dH"]), st["nforce"], ref["nforce"], flush=True)
     assert st["nforce"] == ref["nforce"]
     assert abs(st["H0"] - ref["H0"]) < 1e-8 * abs(ref["H0"])
-    assert abs(st["dH"] - ref["dH"]) < 1e-7
-    assert st["accept"] == ref["accept"]
     Ug = lat.get_gauge().cpu().numpy()
+    Pg = lat.unpack_momenta(Pend).cpu().numpy()
+    print("|dH - dH_oracle| %.2e, max |U - U_oracle| %.2e, max |P - P_oracle| %.2e"
+          % (abs(st["dH"] - ref["dH"]), np.max(np.abs(Ug - ref["U"])), np.max(np.abs(Pg - ref["P"]))), flush=True)
+    assert abs(st["dH"] - ref["dH"]) < 1e-10
+    assert st["accept"] == ref["accept"]
     if st["accept"]:
-        assert np.max(np.abs(Ug - ref["U"])) < 1e-9
+        assert np.max(np.abs(Ug - ref["U"])) < 1e-10
     else:
         assert np.array_equal(Ug, U0)
     assert np.max(np.abs(lat.unpack_momenta(Pend).cpu().numpy() - ref["P"])) < 1e-8
@@ -203,14 +206,15 @@ def test_batched_and_mixed_solves_in_trajectory(U0):
     ref, Uref = _run(U0, {}, P0, etas, 0.0)
     # FP32 filter forces (relative error ~1e-7) move the end point by ~1e-8 in the links
     # and dH, a difference of Hamiltonians of size ~1e3 here, by a few 1e-6
-    for kw, tol_dh, tol_u in ((dict(batch=True), 1e-8, 1e-9), (dict(solver_prec=F32), 2e-5, 1e-6),
+    for kw, tol_dh, tol_u in ((dict(batch=True), 0.0, 0.0), (dict(solver_prec=F32), 2e-5, 1e-6),
                               (dict(solver_prec=F16), 2e-5, 1e-6), (dict(solver_prec=F16, batch=True), 2e-5, 1e-6)):
         st, Ug = _run(U0, kw, P0, etas, 0.0)
         du = np.max(np.abs(Ug - Uref))
         print(kw, "dH %.12f vs %.12f, iters %d vs %d, max |dU| %.2e" % (st["dH"], ref["dH"], st["solver_iters"],
                                                                       ref["solver_iters"], du), flush=True)
-        assert abs(st["dH"] - ref["dH"]) < tol_dh
-        assert du < tol_u
+        # batched FP64 solves give each right-hand side the single-RHS bits: the same trajectory
+        assert abs(st["dH"] - ref["dH"]) <= tol_dh
+        assert du <= tol_u
 
 
 def test_trajectory_det_on_own_scale_matches_oracle(U0):
@@ -228,7 +232,7 @@ def test_trajectory_det_on_own_scale_matches_oracle(U0):
     print("det scale: dH gpu %.12f oracle %.12f" % (st["dH"], ref["dH"]), st["nforce"], st["nforce_det"],
           ref["nforce"], flush=True)
     assert st["nforce"] + [st["nforce_det"]] == ref["nforce"]
-    assert abs(st["dH"] - ref["dH"]) < 1e-7
+    assert abs(st["dH"] - ref["dH"]) < 1e-10
     lat.close()
 
 
@@ -310,11 +314,14 @@ def test_action_variants_match_oracle(U0, name):
     print("dH gpu %.12f oracle %.12f" % (st["dH"], ref["dH"]), st["nforce"], ref["nforce"], flush=True)
     assert list(st["nforce"][:len(terms) + 1]) == list(ref["nforce"])
     assert abs(st["H0"] - ref["H0"]) < 1e-8 * abs(ref["H0"])
-    assert abs(st["dH"] - ref["dH"]) < 1e-7
-    assert st["accept"] == ref["accept"]
     Ug = lat.get_gauge().cpu().numpy()
+    Pg = lat.unpack_momenta(Pend).cpu().numpy()
+    print("|dH - dH_oracle| %.2e, max |U - U_oracle| %.2e, max |P - P_oracle| %.2e"
+          % (abs(st["dH"] - ref["dH"]), np.max(np.abs(Ug - ref["U"])), np.max(np.abs(Pg - ref["P"]))), flush=True)
+    assert abs(st["dH"] - ref["dH"]) < 1e-10
+    assert st["accept"] == ref["accept"]
     if st["accept"]:
-        assert np.max(np.abs(Ug - ref["U"])) < 1e-9
+        assert np.max(np.abs(Ug - ref["U"])) < 1e-10
     else:
         assert np.array_equal(Ug, U0)
     assert np.max(np.abs(lat.unpack_momenta(Pend).cpu().numpy() - ref["P"])) < 1e-8
@@ -344,3 +351,57 @@ def test_step_tuner_on_gpu(U0):
         assert all(math.isfinite(t[0]) and t[2] > 0 for t in traj)
         print("c %.4f steps %s dH %s" % (c, steps, [round(t[0], 4) for t in traj]), flush=True)
     lat.close()
+
+
+def test_trajectory_failure_restores_start_field():
+    """A trajectory whose solve hits maxiter after the links have moved returns NOCONV
+    and leaves the context on its start field: free field U = 1 (Wilson, kappa 0.12), one
+    heavy term with phi = W^dag eta for a plane wave eta chosen as an eigenvector of Khat,
+    so the solve of the first force step converges in one CG iteration (maxiter = 1);
+    after the first link update the field is no longer free, the next solve stops at
+    maxiter, and the links must come back bit for bit.  A trajectory run afterwards on the
+    same context must give the bits of one on a fresh context."""
+    from paper_1609_02652_amd.pfmp import Lattice, PfmpError
+    U1 = synth.unit_gauge(DIMS)
+    n = (1, 0, 0, 0)
+    p = [2 * math.pi * n[m] / DIMS[m] for m in range(3)] + [2 * math.pi * (n[3] + 0.5) / DIMS[3]]
+    b = [2 * math.sin(q) for q in p]
+    bg = sum(b[m] * oracle.gamma(m) for m in range(4))
+    w, v = np.linalg.eigh(bg)
+    u = np.outer(v[:, 0], [1.0, 0.3j, -0.2])
+    lexeo, _, _ = oracle.index_maps(DIMS)
+    eta = np.zeros((len(lexeo[0]), 4, 3), np.complex128)
+    for i, x in enumerate(lexeo[0]):
+        c, r = [], int(x)
+        for L in DIMS:
+            c.append(r % L)
+            r //= L
+        eta[i] = np.exp(1j * sum(p[m] * c[m] for m in range(4))) * u
+    P0 = synth.gaussian_momenta(256, 107)
+
+    def lattice():
+        lat = Lattice(DIMS)
+        lat.set_gauge(U1)
+        lat.set_operator(0, 0.12, 0.0)
+        return lat
+
+    terms = [dict(kind="heavy", op=0, steps=1)]
+    lat = lattice()
+    sp = lat.spec(BETA, terms, 2, det_op=-1, tol=1e-12, maxiter=1, exact_start=False)
+    with pytest.raises(PfmpError) as e:
+        lat.trajectory(sp, lat.pack_momenta(P0), [lat.pack_spinor(eta)], 0.5)
+    assert e.value.code == -3
+    assert np.array_equal(lat.get_gauge().cpu().numpy(), U1)
+    # the same trajectory with room to converge, here and on a fresh context
+    sp2 = lat.spec(BETA, terms, 2, det_op=-1, tol=1e-12, maxiter=10000, exact_start=False)
+    st = lat.trajectory(sp2, lat.pack_momenta(P0), [lat.pack_spinor(eta)], 0.0)
+    U_here = lat.get_gauge().cpu().numpy()
+    lat.close()
+    fresh = lattice()
+    st2 = fresh.trajectory(fresh.spec(BETA, terms, 2, det_op=-1, tol=1e-12, maxiter=10000, exact_start=False),
+                           fresh.pack_momenta(P0), [fresh.pack_spinor(eta)], 0.0)
+    print("after the failure: dH %.12f, fresh context %.12f" % (st["dH"], st2["dH"]), flush=True)
+    assert st["dH"] == st2["dH"] and st["accept"] == 1
+    assert np.array_equal(U_here, fresh.get_gauge().cpu().numpy())
+    assert not np.array_equal(U_here, U1)
+    fresh.close()

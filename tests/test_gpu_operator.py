@@ -5,6 +5,7 @@ Index maps must match bit for bit; FP64 operator applications to 1e-12 relative
 128-site blocks and a ragged last block.
 """
 import numpy as np
+import torch
 import pytest
 
 import oracle
@@ -96,6 +97,24 @@ def test_apply_M_fp32_error(setup):
     assert e < 2e-6
 
 
+def test_apply_M_fp16_storage_error(setup):
+    """FP16 spinor storage (FP32 arithmetic): Mhat, Mhat^dag and Khat against the oracle,
+    with the FP16 and with the FP32 copies of links and clover; the error is stated and
+    must stay at the binary16 rounding level."""
+    from paper_1609_02652_amd.pfmp import F32, F16
+    dims, U, lat, ops = setup
+    psi = synth.gaussian_spinor(lat.Vh, 10)
+    f = lat.pack_spinor(psi, prec=F32)
+    for half_links in (1, 0):
+        lat.half_links(half_links)
+        eM = rel(lat.spinor_numpy(lat.apply_M(0, f, prec=F16), prec=F32), ops[0].M(psi))
+        eD = rel(lat.spinor_numpy(lat.apply_M(0, f, dagger=True, prec=F16), prec=F32), ops[0].M(psi, dagger=True))
+        eK = rel(lat.spinor_numpy(lat.apply_MdagM(0, f, prec=F16), prec=F32), ops[0].K(psi))
+        print("fp16 storage (half links %d): Mhat %.3e, Mhat^dag %.3e, Khat %.3e" % (half_links, eM, eD, eK))
+        assert max(eM, eD) < 3e-3 and eK < 5e-3
+    lat.half_links(1)
+
+
 def test_blas(setup):
     dims, U, lat, ops = setup
     a = synth.gaussian_spinor(lat.Vh, 11)
@@ -153,18 +172,15 @@ def test_cg_mixed_fp16_storage(setup, half_links):
 
 
 def test_batch_apply_matches_single(setup):
-    """k right-hand sides with their own operators in one launch per stage agree
-    with k single-RHS applications to the last few bits (the batched kernels are
-    separate code, so the compiler may contract multiply-adds differently)."""
+    """k right-hand sides with their own operators in one launch per stage give the
+    bits of k single-RHS applications (same per-RHS arithmetic order)."""
     dims, U, lat, ops = setup
     psis = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 70 + k)) for k in range(3)]
     opl = [0, 2, 0]
     outs = lat.apply_MdagM_batch(opl, psis)
     for op, x, o in zip(opl, psis, outs):
         single = lat.apply_MdagM(op, x)
-        d = (o - single).abs().max().item() / single.abs().max().item()
-        print("batch vs single: max rel diff %.3e" % d)
-        assert d <= 1e-14
+        assert torch.equal(o, single)
 
 
 def test_batch_cg(setup):
@@ -176,9 +192,10 @@ def test_batch_cg(setup):
         assert st["true_res"] <= 1.1e-11
         xg = lat.spinor_numpy(x)
         assert rel(ops[op].K(xg), b) <= 1.1e-11
+        # each right-hand side takes the single-RHS solve's steps in its order: same bits
         xs1, st1 = lat.cg_solve(op, lat.pack_spinor(b), tol=1e-11)
-        assert abs(st1["iters"] - st["iters"]) <= 1
-        assert rel(xg, lat.spinor_numpy(xs1)) < 1e-9
+        assert st1["iters"] == st["iters"]
+        assert torch.equal(x, xs1)
 
 
 def test_batch_cg_mixed(setup):

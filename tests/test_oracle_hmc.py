@@ -154,6 +154,63 @@ def test_schedule_worked_example():
     assert newS[0] == exp["S1"]
     assert newS[1] == exp["S2"]
     assert schedule.is_symmetric(newT, newS)
+    # the example's first scheme is the 3-step leapfrog and its second the 1-step 2MN
+    T1, S1 = schedule.leapfrog(3)
+    assert T1 == inp["T1"] and S1 == inp["S1"]
+    T2, S2 = schedule.omelyan_2mn(1)
+    assert T2 == inp["T2"] and S2 == [float(x) for x in inp["S2"]]
+
+
+def _flow(newT, newS, sign, A, Bs):
+    """The integrator's map for step sizes sign * (T', S'): T[t] = exp(t A), S_j[s] =
+    exp(s B_j), applied in schedule order (each merged step: T then the S_j)."""
+    M = np.eye(A.shape[0])
+    for k, t in enumerate(newT):
+        M = sl.expm(sign * float(t) * A) @ M
+        for s, B in zip(newS, Bs):
+            M = sl.expm(sign * s[k] * B) @ M
+    return M
+
+
+def _reversible(newT, newS):
+    """Brute-force reversibility (App. B, time-step insertion theorem): running the
+    schedule with negated steps undoes it, Phi(-h) Phi(h) = 1, for a time generator A that
+    commutes with none of the space generators B_j, which commute among themselves (as
+    the momentum updates S_j do) but are otherwise independent."""
+    rng = np.random.default_rng(11)
+    n = 5
+    A = rng.standard_normal((n, n))
+    A = A - A.T
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Bs = [Q @ np.diag(rng.standard_normal(n)) @ Q.T for _ in newS]
+    M = _flow(newT, newS, -1.0, A, Bs) @ _flow(newT, newS, 1.0, A, Bs)
+    return np.max(np.abs(M - np.eye(n))) < 1e-10
+
+
+def test_is_symmetric_agrees_with_reversibility():
+    """is_symmetric (the mirror condition) is True exactly for the schedules whose flow
+    is undone by the negated flow: merged 2MN and leapfrog schemes, and False for each
+    plausible defect (one term's space steps not mirrored, time steps not mirrored, a
+    first-order scheme in the mix, a 1e-9 slip in one step)."""
+    lam = schedule.OMELYAN_LAMBDA
+    good = [schedule.merge(*zip(schedule.leapfrog(3), schedule.omelyan_2mn(1))),
+            schedule.merge(*zip(*[schedule.omelyan_2mn(n) for n in (2, 3, 5)]))]
+    bad = []
+    T, S = good[0]
+    bad.append((T, [S[0], [lam, 1 - 2 * lam, 0, 0, lam]]))                     # second row not mirrored
+    bad.append(([Fraction(0), Fraction(1, 6), Fraction(1, 3), Fraction(1, 6), Fraction(1, 3)], S))  # times
+    bad.append(schedule.merge([[0, Fraction(1)], schedule.omelyan_2mn(2)[0]],
+                              [[1 / 3, 2 / 3], schedule.omelyan_2mn(2)[1]]))     # S[h/3] T[h] S[2h/3]
+    T2, S2 = good[1]
+    S2 = [list(r) for r in S2]
+    k = next(i for i, v in enumerate(S2[1]) if v != 0)
+    S2[1][k] += 1e-9
+    bad.append((T2, S2))
+    for T, S in good:
+        assert _reversible(T, S) and schedule.is_symmetric(T, S)
+    for T, S in bad:
+        assert not _reversible(T, S)
+        assert not schedule.is_symmetric(T, S)
 
 
 @pytest.mark.parametrize("steps", [(10, 20, 40, 80), (10, 15, 40, 120), (3, 7, 11, 13)])
