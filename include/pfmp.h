@@ -168,6 +168,18 @@ int pfmp_apply_M(pfmp_ctx *ctx, int op, int dagger, const void *in, void *out, i
  * Mhat in is stored in FP16 as well). */
 int pfmp_apply_MdagM(pfmp_ctx *ctx, int op, const void *in, void *out, int prec);
 
+/* Khat as pfmp_apply_MdagM (prec PFMP_F64 or PFMP_F32, same kernels and bits) for callers
+ * that cannot allocate device memory: code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc.  The two intermediates live in a static 128 MiB device
+ * array (two spinor fields of one parity: Vh <= 349525 sites in FP64, e.g. 24^3 x 48;
+ * Vh <= 699050 in FP32), which each GPU holds until the process ends; its device address
+ * is looked up per GPU when a context is created.  No hipMalloc, hipFree or allocating
+ * library call is made (a stale clover slot is rebuilt into its existing buffers).
+ * Errors: PFMP_ERR_ARG for a lattice beyond the limit, null buffers or another precision.
+ * All contexts on one GPU share the array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller. */
+int pfmp_apply_MdagM_noalloc(pfmp_ctx *ctx, int op, const void *in, void *out, int prec);
+
 /* Product-form polynomial (paper App. A): out = norm * prod_k (Khat - z_k) in,
  * the factors applied in the order given (k = 0 first).  roots: n complex
  * numbers as 2n doubles (host); norm: complex (host).  chain: optional array of

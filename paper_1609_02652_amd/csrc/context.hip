@@ -261,6 +261,10 @@ extern "C" int pfmp_create(const int dims[4], int t_bc, void *stream, pfmp_ctx *
         pfmp_destroy(ctx);
         return PFMP_ERR_OOM;
     }
+    if (noalloc_scratch_init(ctx) != 0) {
+        pfmp_destroy(ctx);
+        return PFMP_ERR_HIP;
+    }
     *out = ctx;
     return 0;
 }

@@ -5,6 +5,8 @@
 //   hop_clovinv : out_o = [g5] A_oo^-1 D_oe [g5] in_e      (also plain D for tests)
 //   hop_xpay    : out_e = [g5] (A_ee [g5] x_e + a D_eo t_o), optional |out|^2 partials
 // Mhat = both stages (a = -kappa^2); Mhat^dag = the same with g5 on input and output.
+#include <mutex>
+
 #include "hop.h"
 
 namespace {
@@ -314,6 +316,64 @@ extern "C" int pfmp_apply_M(pfmp_ctx *ctx, int op, int dagger, const void *in, v
     }
     if (prec == PFMP_F16) return apply_f16(ctx, op, dagger, 0, in, out);
     return set_err(ctx, PFMP_ERR_ARG, "apply_M: unsupported precision");
+}
+
+// ------------------------------------------------------------------ allocation-free Khat
+//
+// Scratch of pfmp_apply_MdagM_noalloc: the even and odd intermediates of Khat in one
+// statically allocated device array (each GPU holds its own copy from module load until
+// the process ends).  Host code never passes the array's name to a kernel: its device
+// address on each GPU is looked up once, at context creation with that GPU current
+// (noalloc_scratch_init), and kept per device.
+constexpr size_t kScratchBytes = 128ull << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+int noalloc_scratch_init(pfmp_ctx *ctx)
+{
+    int dev = 0;
+    HIPCHK(ctx, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_err(ctx, PFMP_ERR_ARG, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        HIPCHK(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_err(ctx, PFMP_ERR_HIP, "scratch: no device address");
+        scratch_dev[dev] = p;
+    }
+    ctx->scratch = scratch_dev[dev];
+    return 0;
+}
+
+extern "C" int pfmp_apply_MdagM_noalloc(pfmp_ctx *ctx, int op, const void *in, void *out, int prec)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    if (op < 0 || op >= PFMP_MAX_OPS) return set_err(ctx, PFMP_ERR_ARG, "operator slot out of range");
+    if (!in || !out) return set_err(ctx, PFMP_ERR_ARG, "apply_MdagM_noalloc: null buffer");
+    if (prec != PFMP_F64 && prec != PFMP_F32)
+        return set_err(ctx, PFMP_ERR_ARG, "apply_MdagM_noalloc: FP64 or FP32 fields only");
+    const size_t field = (prec == PFMP_F64 ? sizeof(double) : sizeof(float)) * spinor_reals(ctx->g);
+    if (2 * field > kScratchBytes)
+        return set_err(ctx, PFMP_ERR_ARG, "apply_MdagM_noalloc: lattice too large for the 128 MiB scratch (two "
+                                          "spinor fields of one parity)");
+    if (!ctx->scratch) return set_err(ctx, PFMP_ERR_STATE, "apply_MdagM_noalloc: scratch not set up");
+    // a stale clover slot is rebuilt in place (its buffers exist from pfmp_set_operator)
+    if (!ctx->have_gauge) return set_err(ctx, PFMP_ERR_STATE, "no gauge field set");
+    if (!ctx->ops[op].valid) return set_err(ctx, PFMP_ERR_STATE, "operator slot not configured");
+    if (ctx->ops[op].stale && !(ctx->Fhat && ctx->ops[op].ldpart))
+        return set_err(ctx, PFMP_ERR_STATE, "apply_MdagM_noalloc: clover fields not allocated");
+    int rc = op_ready(ctx, op);
+    if (!rc) rc = gauge_f32_ready(ctx);
+    if (rc) return rc;
+    char *te = (char *)ctx->scratch, *to = te + field;
+    if (prec == PFMP_F64)
+        return op_apply_K(ctx, op, (const double2 *)in, (double2 *)out, (double2 *)te, (double2 *)to, nullptr);
+    return op_apply_K_f32(ctx, op, (const float2 *)in, (float2 *)out, (float2 *)te, (float2 *)to, nullptr);
 }
 
 extern "C" int pfmp_apply_MdagM(pfmp_ctx *ctx, int op, const void *in, void *out, int prec)

@@ -209,6 +209,7 @@ struct pfmp_ctx {
     double *red = nullptr;       // reduction partials
     double *red_host = nullptr;  // pinned host mirror of a few scalars
     double *scal = nullptr;      // device scalars for solvers
+    void *scratch = nullptr;     // this GPU's static scratch of pfmp_apply_MdagM_noalloc (device address)
     SolverWS *ws = nullptr;
     std::vector<double2 *> pool;   // FP64 spinor buffers for the HMC driver, grown on demand
     bool use_graphs = true;        // solver iterations replayed as HIP graphs
@@ -318,6 +319,9 @@ double2 *pool_get(pfmp_ctx *ctx, int idx);
 // polynomial (poly.hip)
 int poly_factor(pfmp_ctx *ctx, int op, const double2 *src, double2 z, double2 *dst, double2 *te, double2 *to);
 int scale_spinor(pfmp_ctx *ctx, double2 a, const double2 *x, double2 *y);
+// device address of the allocation-free entry point's static scratch on the current GPU
+// (dslash.hip), looked up once per device; called at context creation
+int noalloc_scratch_init(pfmp_ctx *ctx);
 // mixed precision (mixed.hip)
 int cg_solve_mixed(pfmp_ctx *ctx, int op, const void *b, void *x, const pfmp_solver_params *p,
                    pfmp_solver_stats *st);

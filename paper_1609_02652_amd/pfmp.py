@@ -146,6 +146,7 @@ def load():
         "pfmp_apply_clover": [vp, i, i, i, vp, vp],
         "pfmp_apply_M": [vp, i, i, vp, vp, i],
         "pfmp_apply_MdagM": [vp, i, vp, vp, i],
+        "pfmp_apply_MdagM_noalloc": [vp, i, vp, vp, i],
         "pfmp_cg_solve": [vp, i, vp, vp, vp, vp],
         "pfmp_cg_multishift": [vp, i, i, vp, vp, vp, vp, vp],
         "pfmp_dot": [vp, vp, vp, vp],
@@ -352,6 +353,11 @@ class Lattice:
     def apply_MdagM(self, op, x, prec=F64, out=None):
         out = self.field(FIELD_SPINOR, F32 if prec == F16 else prec, zero=False) if out is None else out
         self._chk(self.lib.pfmp_apply_MdagM(self.h, op, _ptr(x), _ptr(out), prec), "apply_MdagM")
+        return out
+
+    def apply_MdagM_noalloc(self, op, x, out, prec=F64):
+        """Khat through the allocation-free entry point (the caller passes out)."""
+        self._chk(self.lib.pfmp_apply_MdagM_noalloc(self.h, op, _ptr(x), _ptr(out), prec), "apply_MdagM_noalloc")
         return out
 
     # ---------------------------------------------------------------- solvers
