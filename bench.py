@@ -70,17 +70,28 @@ def time_kernel(lat, fn, reps):
 
 
 def batch_apply(lat, reps=20):
-    """Khat for the Hasenbusch chain's three operators plus a second source of the first
-    (4 right-hand sides) as one multi-RHS launch per stage, against 4 single-RHS Khat:
-    the time per right-hand side relative to a single one."""
+    """4-RHS Khat (one multi-RHS launch per stage) against 4 single-RHS Khat in FP64 and FP32,
+    for 4 sources of one operator and for the Hasenbusch chain's operators (kappa 0.1340,
+    0.1300, 0.1250, 0.1340), in the multi-rhs layout (each link load shared by the 4 rhs of a
+    lane pair) and in the workgroup-per-rhs layout: time per right-hand side relative to a
+    single one."""
     from paper_1609_02652_amd import synth
+    from paper_1609_02652_amd.pfmp import F64, F32
     lat.set_operator(2, 0.1250, CSW)
-    xs = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 40 + k)) for k in range(4)]
-    outs = [lat.field() for _ in range(4)]
-    t1 = time_kernel(lat, lambda: lat.apply_MdagM(0, xs[0], out=outs[0]), reps)
-    t4 = time_kernel(lat, lambda: lat.apply_MdagM_batch([0, 1, 2, 0], xs, outs), reps)
-    return {"nrhs": 4, "single_K_us": round(t1 * 1e6, 1), "batch_K_us": round(t4 * 1e6, 1),
-            "per_rhs_vs_single": round(t4 / 4 / t1, 3)}
+    res = {}
+    for pname, prec in (("f64", F64), ("f32", F32)):
+        xs = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 40 + k), prec=prec) for k in range(4)]
+        outs = [lat.field(prec=prec) for _ in range(4)]
+        t1 = time_kernel(lat, lambda: lat.apply_MdagM(0, xs[0], out=outs[0], prec=prec), reps)
+        for oname, ops in (("same_op", [0, 0, 0, 0]), ("chain", [0, 1, 2, 0])):
+            for multi in (True, False):
+                lat.batch_layout(multi)
+                t4 = time_kernel(lat, lambda: lat.apply_MdagM_batch(ops, xs, outs, prec=prec), reps)
+                res["%s_%s_%s" % (pname, oname, "multi" if multi else "wg")] = {
+                    "single_K_us": round(t1 * 1e6, 1), "batch_K_us": round(t4 * 1e6, 1),
+                    "per_rhs_vs_single": round(t4 / 4 / t1, 3)}
+        lat.batch_layout(True)
+    return res
 
 
 def hop_roofline(dims, U, reps=200, extra=None):
@@ -174,33 +185,85 @@ def copy_bandwidth(reps=20):
     return {"bytes": 2 * n * 8, "us": round(t * 1e6, 2), "GBps": round(2 * n * 8 / t / 1e9, 1)}
 
 
-def cpu_baseline(kmults_per_traj, budget_s=15.0):
-    """The oracle (plain C, FP64) on the host cores: Khat multiplications on a
-    16^3 x 32 field of the same operator, timed for about budget_s seconds and
-    scaled by the trajectory's count of Khat multiplications.  The oracle runs on
-    the seeded start field (its cost does not depend on the link values), so no
-    oracle input comes from the GPU path."""
+def host_info():
+    """CPU model and logical core count of the host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def oracle_cg_solve(threads=None):
+    """The oracle (plain C, FP64) solving one source of the solve workload: Khat (kappa 0.1340,
+    c_sw 1.6) on the seeded 16^3 x 32 start field, CG to 1e-10 from x = 0.  The oracle never sees
+    the GPU's thermalised field, so it solves on the seeded start field (the cost of an iteration
+    does not depend on the link values; the iteration count is stated).  threads: OpenMP threads
+    (the environment's default when None)."""
     import oracle
     from paper_1609_02652_amd import synth
     U = synth.random_gauge(DIMS, seed=0)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     op = oracle.Operator(DIMS, U, KAPPA, CSW)
     t_setup = time.perf_counter() - t0
-    v = synth.gaussian_spinor(op.Vh, 3)
-    n = 0
+    b = synth.gaussian_spinor(op.Vh, 1)
     t0 = time.perf_counter()
-    while True:
-        v = op.K(v)
-        v /= np.linalg.norm(v)
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    per_k = (time.perf_counter() - t0) / n
-    return {"value": per_k * kmults_per_traj, "unit": "s/trajectory", "cores": threads, "kind": "oracle",
-            "sample": "%d Khat multiplications of the oracle on the 16^3x32 fields (%.2f s each, %.1f s clover "
-                      "setup excluded), scaled by the %d Khat multiplications one trajectory spends"
-                      % (n, per_k, t_setup, kmults_per_traj)}
+    x, info = op.cg(b, tol=TOL)
+    t = time.perf_counter() - t0
+    res = float(np.linalg.norm(op.K(x) - b) / np.linalg.norm(b))
+    return {"s": round(t, 3), "setup_s": round(t_setup, 3), "iters": info["iters"], "true_res": res}
+
+
+def oracle_config1_trajectory():
+    """The correctness workload's trajectory on the oracle (4^4, kappa 0.120 / 0.110, c_sw
+    1.0, degree-4 filter, 2MN steps (10, 20, 40, 80), CG 1e-12), seconds."""
+    from oracle import hmc
+    from paper_1609_02652_amd import synth
+    dims = (4, 4, 4, 4)
+    U0 = synth.random_gauge(dims, seed=0)
+    terms = [dict(kind="poly", kappa=0.110, n=4, mu=1.2, nu=0.9, steps=40),
+             dict(kind="polycorr", kappa=0.110, n=4, mu=1.2, nu=0.9, steps=20),
+             dict(kind="ratio", kappa_num=0.110, kappa_den=0.120, steps=10)]
+    spec = dict(dims=dims, beta=5.6, csw=1.0, kappa=0.120, gauge_steps=80, terms=terms)
+    P0 = synth.gaussian_momenta(256, 100)
+    etas = [synth.gaussian_spinor(128, 20 + j) for j in range(3)]
+    t0 = time.perf_counter()
+    ref = hmc.trajectory(spec, U0, P0, etas, u=float(synth.uniform(200)[0]), tol=1e-12)
+    return {"s": round(time.perf_counter() - t0, 3), "dH": ref["dH"], "accept": bool(ref["accept"])}
+
+
+def cpu_full(args):
+    """The oracle on the host: one full CG solve of the solve workload (16^3 x 32, 1e-10) and
+    the full correctness-workload trajectory (4^4), each in a child process with 1 OpenMP
+    thread and with all host threads."""
+    import subprocess
+    out = dict(host_info())
+    counts = [1, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))]
+    for what in ("cg", "traj"):
+        for n in counts:
+            env = dict(os.environ, OMP_NUM_THREADS=str(n))
+            log("oracle %s with %d thread(s)" % (what, n))
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", what], env=env,
+                               capture_output=True, text=True, check=True)
+            out["%s_threads_%d" % (what, n)] = json.loads(r.stdout.strip().splitlines()[-1])
+            log("  %s" % out["%s_threads_%d" % (what, n)])
+    print(json.dumps({"cpu_full": out}), flush=True)
+
+
+def cpu_baseline():
+    """The oracle on the host cores: one full CG solve of the solve workload (16^3 x 32,
+    kappa 0.1340, 1e-10) with the host's OpenMP threads, in the headline's unit (s per solve)."""
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    r = oracle_cg_solve()
+    return dict({"value": r["s"], "unit": "s/solve", "cores": threads, "kind": "oracle",
+                 "sample": "one full CG solve to 1e-10 (source 1, seeded 16^3x32 start field, %s iterations, "
+                           "true residual %.1e; clover set-up %.1f s excluded)" % (r["iters"], r["true_res"],
+                                                                                  r["setup_s"])},
+                **host_info())
 
 
 def thermalise(lat, ntraj, gauge_steps=128, beta=BETA):
@@ -219,40 +282,72 @@ def thermalise(lat, ntraj, gauge_steps=128, beta=BETA):
     return {"trajectories": ntraj, "accept_rate": acc / max(ntraj, 1), "plaquette": round(plaq, 6)}
 
 
-def cg_bench(lat, nsrc):
-    """CG on Khat (kappa 0.1340) to 1e-10, one Gaussian source at a time, in FP64,
-    FP32 + FP64 reliable updates, and FP32 arithmetic with FP16 storage + FP64
-    reliable updates: median seconds, iterations and final FP64 residual."""
+def cg_bench(lat, nsrc, warmup=1):
+    """The solve workload: CG on Khat (kappa 0.1340) to 1e-10, one Gaussian source at a time,
+    in FP64, FP32 + FP64 reliable updates, and FP32 arithmetic with FP16 storage + FP64
+    reliable updates.  Per precision: `warmup` untimed solves, then exactly nsrc solves timed
+    together between two device synchronisations (mean seconds per solve); also the median
+    per solve, iterations, the worst FP64 true residual and the worst ||x - x_FP64|| / ||x_FP64||
+    over the same sources (FP64 solutions kept from the FP64 pass, compared outside the
+    timing)."""
     import torch
     from paper_1609_02652_amd import synth
     from paper_1609_02652_amd.pfmp import F64, F32, F16
     res = {}
     srcs = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 1 + s)) for s in range(nsrc)]
-    x = lat.field()
+    xs = [lat.field() for _ in range(nsrc)]
     x64 = []
     for name, prec in (("f64", F64), ("f32", F32), ("f16", F16)):
-        lat.cg_solve(0, srcs[0], x=x, tol=TOL, prec=prec)   # warm-up
-        rows = []
-        for k, b in enumerate(srcs):
+        for w in range(warmup):
+            lat.cg_solve(0, srcs[w % nsrc], x=xs[0], tol=TOL, prec=prec)
+        sts, per = [], []
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+        for k in range(nsrc):
+            t0 = time.perf_counter()
+            _, st = lat.cg_solve(0, srcs[k], x=xs[k], tol=TOL, prec=prec)
+            per.append(time.perf_counter() - t0)   # each solve ends on a host read of its residual
+            sts.append(st)
+        torch.cuda.synchronize()
+        t_all = time.perf_counter() - t_all
+        if prec == F64:
+            x64 = [x.clone() for x in xs]
+            errs = [0.0] * nsrc
+        else:
+            errs = [float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y)) for x, y in zip(xs, x64)]
+        res[name] = {"mean_s": round(t_all / nsrc, 6), "median_s": round(float(np.median(per)), 6),
+                     "iters": int(np.median([st["iters"] for st in sts])),
+                     "reliable_updates": int(np.median([st["reliable_updates"] for st in sts])),
+                     "max_true_res": float(max(st["true_res"] for st in sts)),
+                     "max_rel_err_vs_f64": float(max(errs))}
+        log("cg %s: %s" % (name, res[name]))
+    return res
+
+
+def cg_iteration_roofline(lat, Vh, reps=2):
+    """Per-iteration time of one CG solve (kappa 0.1340, 1e-10) in each precision on this
+    lattice, priced at CG_ITER_BYTES per even site against the 8 TB/s peak."""
+    import torch
+    from paper_1609_02652_amd import synth
+    from paper_1609_02652_amd.pfmp import F64, F32, F16
+    b = lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 1))
+    x = lat.field()
+    out = {}
+    for name, prec in (("f64", F64), ("f32", F32), ("f16", F16)):
+        lat.cg_solve(0, b, x=x, tol=TOL, prec=prec)
+        best = None
+        for _ in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             _, st = lat.cg_solve(0, b, x=x, tol=TOL, prec=prec)
             torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            # error of the solution against the FP64 solve of the same source (outside the timing)
-            if prec == F64:
-                x64.append(x.clone())
-                err = 0.0
-            else:
-                err = float(torch.linalg.vector_norm(x - x64[k]) / torch.linalg.vector_norm(x64[k]))
-            rows.append((dt, st["iters"], st["true_res"], st["reliable_updates"], err))
-        res[name] = {"median_s": round(float(np.median([r[0] for r in rows])), 5),
-                     "iters": int(np.median([r[1] for r in rows])),
-                     "reliable_updates": int(np.median([r[3] for r in rows])),
-                     "max_true_res": float(max(r[2] for r in rows)),
-                     "max_rel_err_vs_f64": float(max(r[4] for r in rows))}
-        log("cg %s: %s" % (name, res[name]))
-    return res
+            t = (time.perf_counter() - t0) / st["iters"]
+            best = t if best is None or t < best else best
+        gbs = CG_ITER_BYTES[name] * Vh / best / 1e9
+        out[name] = {"us_per_iter": round(best * 1e6, 1), "iters": st["iters"],
+                     "bytes_per_iter_site": CG_ITER_BYTES[name], "GBps": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 3)}
+    return out
 
 
 # Algorithmic bytes of one CG iteration per even site, from the I/O of its five kernels (each
@@ -278,7 +373,8 @@ def cg_roofline(cg, Vh):
     for k in ("f64", "f32", "f16"):
         b = cg[k]["iters"] * CG_ITER_BYTES[k] * Vh
         out[k] = {"bytes_per_iter_site": CG_ITER_BYTES[k], "GBps": round(b / cg[k]["median_s"] / 1e9, 1),
-                  "frac": round(b / cg[k]["median_s"] / 1e9 / HBM_PEAK_GBS, 3)}
+                  "frac": round(b / cg[k]["median_s"] / 1e9 / HBM_PEAK_GBS, 3),
+                  "note": "16^3x32: the working set stays in the 256 MB last-level cache"}
     return out
 
 
@@ -600,6 +696,244 @@ def integrator_bench(args):
     print(json.dumps({"integrator": out, "rows": ["gauge", "poly", "corr", "ratio"]}), flush=True)
 
 
+def ratio_sweep_bench(args):
+    """Integrator error against the ratio of step sizes (App. B: each term on its own,
+    arbitrary step size): the PF-MP action in the chosen mixed precision on the dynamically
+    thermalised field of --chain's start, the ratio term fixed at n_r steps and the filter
+    term at n_r x rho steps for rho from 1 to 6 in steps of 1/2 (integer rho: nested
+    schedules; the others interleave), correction and gauge scales fixed; <dH^2>/2 over the
+    same 8 inputs at every rho.  An integrator whose error grew with the cross terms of
+    non-nested schedules would show jumps at the non-integer rho."""
+    from paper_1609_02652_amd import synth, tuner
+    from paper_1609_02652_amd.pfmp import F16, Lattice
+    lat = Lattice(DIMS)
+    lat.set_gauge(synth.random_gauge(DIMS, seed=0))
+    thermalise(lat, args.therm)
+    lat.set_operator(0, KAPPA, CSW)
+    lat.set_operator(1, KAPPA_H, CSW)
+    log("autotune: %s" % lat.autotune(0))
+    n_g, n_c, n_r = 26, 8, 6
+    U0 = lat.get_gauge().clone()
+    rows = []
+    for twice in range(2, 13):
+        rho = twice / 2.0
+        n_p = int(round(n_r * rho))
+        sp = pfmp_spec(lat, steps=dict(poly=n_p, corr=n_c, ratio=n_r, gauge=n_g, det=0), solver_prec=F16)
+        dH, km = [], []
+        for k in range(8):
+            P = lat.pack_momenta(synth.gaussian_momenta(lat.V, 9300 + k))
+            etas = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 9400 + 3 * k + j)) for j in range(3)]
+            st = lat.trajectory(sp, P, etas, 0.0)
+            dH.append(st["dH"])
+            km.append(st["kmults"])
+            lat.set_gauge(U0)
+        m = tuner.mean_dH_estimate(dH)
+        rows.append({"rho": rho, "steps_gauge_poly_corr_ratio": [n_g, n_p, n_c, n_r], "nested": n_p % n_r == 0,
+                     "dH2_over_2": round(m, 6), "acc_from_dH2": round(tuner.acceptance_from_dH(m), 3),
+                     "kmults": int(np.mean(km))})
+        log("ratio sweep %s" % rows[-1])
+    lat.close()
+    print(json.dumps({"ratio_sweep": rows}), flush=True)
+
+
+def chain_bench(args):
+    """A Markov chain of PF-MP trajectories in the chosen mixed precision with the tuned step
+    counts (gauge, filter, correction, ratio) = (26, 14, 8, 11): after the quenched
+    thermalisation, args.chain_therm trajectories with the Metropolis step to bring the field
+    into equilibrium with the fermion action, then args.chain trajectories measured: P_acc,
+    <exp(-dH)> (1 in equilibrium), N_mat, and the cost C = N_mat / P_acc (eq. cost_func) with
+    the error of eq. error_corrected, tau_int measured on the chain (plaquette and accepts)."""
+    from paper_1609_02652_amd import synth, tuner
+    from paper_1609_02652_amd.pfmp import F16, Lattice
+    lat = Lattice(DIMS)
+    lat.set_gauge(synth.random_gauge(DIMS, seed=0))
+    thermalise(lat, args.therm)
+    lat.set_operator(0, KAPPA, CSW)
+    lat.set_operator(1, KAPPA_H, CSW)
+    log("autotune: %s" % lat.autotune(0))
+    steps = tuple(int(v) for v in args.chain_steps.split(","))
+    sp = pfmp_spec(lat, steps=dict(gauge=steps[0], poly=steps[1], corr=steps[2], ratio=steps[3], det=0),
+                   solver_prec=F16)
+    rows = []
+    t0 = time.perf_counter()
+    for k in range(args.chain_therm + args.chain):
+        P = lat.pack_momenta(synth.gaussian_momenta(lat.V, 20000 + k))
+        etas = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 30000 + 3 * k + j)) for j in range(3)]
+        st = lat.trajectory(sp, P, etas, float(synth.uniform(40000 + k)[0]))
+        plaq = 1.0 - lat.gauge_action(BETA) / (BETA * 6 * lat.V)
+        rows.append((st["dH"], int(st["accept"]), st["kmults"], plaq))
+        if k % 10 == 0 or k == args.chain_therm + args.chain - 1:
+            log("chain %d: dH %.4f accept %d plaquette %.5f (%.0f s)" % (k, st["dH"], st["accept"], plaq,
+                                                                         time.perf_counter() - t0))
+    lat.close()
+    meas = rows[args.chain_therm:]
+    dH = np.array([r[0] for r in meas])
+    acc = [r[1] for r in meas]
+    nmat = [r[2] for r in meas]
+    plaq = [r[3] for r in meas]
+    tau = max(tuner.tau_int(plaq), tuner.tau_int(acc), 0.5)
+    ex = np.exp(-dH)
+    C, dC = tuner.cost(nmat, acc, tau)
+    out = {"action": "PF-MP (filter p = 4, correction, ratio 0.1300/0.1340) + gauge, S_det on the gauge scale",
+           "steps_gauge_poly_corr_ratio": steps, "thermalisation_trajectories": args.chain_therm,
+           "measured_trajectories": len(meas), "accept_rate": round(float(np.mean(acc)), 4),
+           "exp_minus_dH": round(float(np.mean(ex)), 4),
+           "exp_minus_dH_err": round(tuner.corrected_error(ex, tau), 4),
+           "mean_dH": round(float(np.mean(dH)), 4), "nmat": round(float(np.mean(nmat)), 1),
+           "tau_int_plaquette": round(tuner.tau_int(plaq), 2), "tau_int_accept": round(tuner.tau_int(acc), 2),
+           "tau_int_used": round(tau, 2), "cost_C": round(C, 1), "cost_C_err": round(dC, 1),
+           "cost_C_rel_err": round(dC / C, 3), "plaquette": round(float(np.mean(plaq)), 6),
+           "seconds": round(time.perf_counter() - t0, 1)}
+    print(json.dumps({"chain": out}), flush=True)
+
+
+# ---- the light-quark trajectory workload: 48^3 x 96, beta 5.9, kappa 0.1370, c_sw 1.6,
+# Hasenbusch masses 0.120 / 0.130 / 0.135, filter nest (6, 20, 62) on J(0.120) (the nearest
+# degrees with the nested factorisation (p1 + 1) | (p2 + 1) that the workload's 16/32/64 lack),
+# four integrator scales, tau = 1, every solve to 1e-10.
+C5_DIMS = (48, 48, 48, 96)
+C5_BETA, C5_KAPPA, C5_CSW = 5.9, 0.1370, 1.6
+C5_HASEN = (0.120, 0.130, 0.135)
+C5_NEST = (6, 20, 62)
+
+
+def config5_spec(lat, steps, **kw):
+    """Slots 0 = K (0.1370), 1 = J (0.120, the filter nest), 2 = 0.130, 3 = 0.135.  Scales
+    (steps = gauge, filter, correction, ratios): {gauge + S_det}, {P_6, Q(20/6), Q(62/20)},
+    {correction [J P_62(J)]^-1, ratio J(0.120)/K(0.130)}, {ratios 0.130/0.135 and 0.135/0.1370}."""
+    n_g, n_p, n_c, n_r = steps[:4]
+    n_l = steps[4] if len(steps) > 4 else n_r   # optional: the lightest ratio on a scale of its own
+    p1, p2, p3 = C5_NEST
+    f = lambda kind, n, st, n1=0: dict(kind=kind, op=1, n=n, n1=n1, mu=1.2, nu=0.9, steps=st)
+    terms = [f("poly", p1, n_p), f("polyq", p2, n_p, p1), f("polyq", p3, n_p, p2), f("polycorr", p3, n_c),
+             dict(kind="ratio", op=1, op2=2, steps=n_c), dict(kind="ratio", op=2, op2=3, steps=n_r),
+             dict(kind="ratio", op=3, op2=0, steps=n_l)]
+    return lat.spec(C5_BETA, terms, n_g, det_op=0, tol=TOL, **kw)
+
+
+def config5_bench(args):
+    """One timed trajectory per mode (plain FP64 CG form; the chosen mixed-precision form) of
+    the light-quark workload from the same thermalised field and the same momenta, noise and
+    Metropolis uniform, after a parity check on sampled sites of the seeded start field."""
+    import torch
+    import oracle
+    from paper_1609_02652_amd import synth
+    from paper_1609_02652_amd.pfmp import Lattice, F64, F16
+    steps = tuple(int(v) for v in args.c5_steps.split(","))
+    dims = tuple(int(v) for v in args.c5_dims.split(","))
+    out = {"lattice": "x".join(map(str, dims)), "steps_gauge_filter_corr_ratio": steps}
+    t0 = time.perf_counter()
+    U = synth.random_gauge(dims, seed=0)
+    log("config5: seeded start field %.1f s" % (time.perf_counter() - t0))
+    lat = Lattice(dims)
+    lat.verbose(1)
+    lat.set_gauge(U)
+    lat.set_operator(0, C5_KAPPA, C5_CSW)
+    # parity on the seeded start field: Mhat and Mhat^dag on sampled sites against the oracle
+    psi = synth.gaussian_spinor(lat.Vh, 1)
+    x = lat.pack_spinor(psi)
+    rng = np.random.default_rng(4)
+    sites = np.unique(np.concatenate([[0, lat.Vh - 1], rng.choice(lat.Vh, 126, replace=False)]))
+    par = {}
+    for dag in (False, True):
+        got = lat.spinor_numpy(lat.apply_M(0, x, dagger=dag))[sites]
+        want = oracle.sample_sites(dims, U, C5_KAPPA, C5_CSW, psi, sites, "M", dagger=dag)
+        par["Mhat_dag" if dag else "Mhat"] = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    out["parity_seeded_field_sampled_sites"] = dict(par, sites=int(len(sites)))
+    log("config5 parity: %s" % par)
+    del U, x
+    torch.cuda.empty_cache()
+    # quenched thermalisation at beta 5.9: molecular dynamics trajectories, every one kept
+    sp_q = lat.spec(C5_BETA, [], args.c5_therm_steps, det_op=-1)
+    t0 = time.perf_counter()
+    for k in range(args.c5_therm):
+        st = lat.trajectory(sp_q, lat.pack_momenta(synth.gaussian_momenta(lat.V, 9000 + k)), [], 0.0)
+        plaq = 1.0 - lat.gauge_action(C5_BETA) / (C5_BETA * 6 * lat.V)
+        log("config5 thermalisation %d: dH %.2f plaquette %.5f" % (k, st["dH"], plaq))
+    out["thermalisation"] = {"trajectories": args.c5_therm, "gauge_steps": args.c5_therm_steps,
+                             "accept": "all (molecular-dynamics relaxation)", "plaquette": round(plaq, 6),
+                             "seconds": round(time.perf_counter() - t0, 1)}
+    for k, kap in enumerate(C5_HASEN):
+        lat.set_operator(1 + k, kap, C5_CSW)
+    out["autotune"] = lat.autotune(0)
+    log("config5 autotune %s" % out["autotune"])
+    # FP16-storage solver with FP16 or FP32 copies of links and clover: the faster on one solve at 0.1370
+    b = lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 2))
+    hl = {}
+    for on in (1, 0):
+        lat.half_links(on)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = lat.cg_solve(0, b, tol=TOL, prec=F16, maxiter=100000)
+        torch.cuda.synchronize()
+        hl[on] = (time.perf_counter() - t0, st["iters"])
+        log("config5 fp16-storage CG at kappa 0.1370, half links %d: %.2f s, %d iterations" % (on, *hl[on]))
+    half = 1 if hl[1][0] <= hl[0][0] else 0
+    lat.half_links(half)
+    out["cg_f16_kappa_0.1370"] = {"half_links_1": {"s": round(hl[1][0], 3), "iters": hl[1][1]},
+                                  "half_links_0": {"s": round(hl[0][0], 3), "iters": hl[0][1]}, "chosen": half}
+    U0 = lat.get_gauge().clone()
+    P = synth.gaussian_momenta(lat.V, 9500)
+    etas = [synth.gaussian_spinor(lat.Vh, 9600 + j) for j in range(7)]
+    u = float(synth.uniform(9700)[0])
+    # plain FP64 against the chosen form at this size without a whole trajectory: one CG solve
+    # on K(0.1370), and one force evaluation of every row of the action (all its solves) at
+    # the thermalised field with the heatbath's pseudofermions
+    cmp = {}
+    for name, prec in (("plain_f64", F64), ("chosen", F16)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = lat.cg_solve(0, b, tol=TOL, prec=prec, maxiter=100000)
+        torch.cuda.synchronize()
+        cmp["cg_kappa_0.1370_" + name] = {"s": round(time.perf_counter() - t0, 3), "iters": st["iters"],
+                                          "true_res": st["true_res"]}
+        log("config5 CG %s: %s" % (name, cmp["cg_kappa_0.1370_" + name]))
+    ed = [lat.pack_spinor(e) for e in etas]
+    phis = lat.heatbath(config5_spec(lat, steps, solver_prec=F16), ed)
+    for name, kw in (("plain_f64", {}), ("chosen", dict(solver_prec=F16))):
+        sp = config5_spec(lat, steps, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn = lat.force_norms(sp, phis)
+        torch.cuda.synchronize()
+        cmp["force_evaluation_" + name] = {"s": round(time.perf_counter() - t0, 3),
+                                           "max_force_rows": [round(float(v), 4) for v in fn[:, 0]]}
+        log("config5 force evaluation %s: %s" % (name, cmp["force_evaluation_" + name]))
+    cmp["cg_speedup"] = round(cmp["cg_kappa_0.1370_plain_f64"]["s"] / cmp["cg_kappa_0.1370_chosen"]["s"], 3)
+    cmp["force_evaluation_speedup"] = round(cmp["force_evaluation_plain_f64"]["s"] /
+                                            cmp["force_evaluation_chosen"]["s"], 3)
+    out["fp64_vs_chosen"] = cmp
+    del ed, phis
+    torch.cuda.empty_cache()
+    modes = [("chosen", dict(solver_prec=F16)), ("plain_f64", {})]
+    if args.c5_modes != "both":
+        modes = [m for m in modes if m[0] == args.c5_modes]
+    out["trajectory"] = {}
+    for name, kw in modes:
+        lat.set_gauge(U0)
+        sp = config5_spec(lat, steps, **kw)
+        Pd = lat.pack_momenta(P)
+        ed = [lat.pack_spinor(e) for e in etas]
+        torch.cuda.empty_cache()   # the library allocates outside torch's cache
+        log("config5 trajectory, %s" % name)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = lat.trajectory(sp, Pd, ed, u)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["trajectory"][name] = {"s": round(dt, 2), "dH": st["dH"], "accept": st["accept"],
+                                   "kmults": st["kmults"], "solver_iters": st["solver_iters"],
+                                   "nforce": list(st["nforce"][:8]), "H0": st["H0"]}
+        log("config5 %s: %.1f s, dH %.4f, accept %d, %d Khat multiplications" % (name, dt, st["dH"], st["accept"],
+                                                                                st["kmults"]))
+    if "chosen" in out["trajectory"] and "plain_f64" in out["trajectory"]:
+        c, f = out["trajectory"]["chosen"], out["trajectory"]["plain_f64"]
+        out["speedup_chosen_vs_f64"] = round(f["s"] / c["s"], 3)
+        out["dH_difference"] = c["dH"] - f["dH"]
+    lat.close()
+    print(json.dumps({"config5": out}), flush=True)
+
+
 def run_trajectories(lat, sp, steps, warmup, seed):
     """warmup untimed, then exactly `steps` timed trajectories on fresh momenta and
     pseudofermion sources; the links are restored after each so every mode sees
@@ -639,10 +973,9 @@ def run_trajectories(lat, sp, steps, warmup, seed):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=32, help="timed solves (sources) per precision")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sources", type=int, default=32)
     ap.add_argument("--therm", type=int, default=20, help="quenched thermalisation trajectories")
     ap.add_argument("--roofline-only", action="store_true",
                     help="time only the hopping kernels and a plain copy (for counter runs)")
@@ -656,10 +989,33 @@ def main():
     ap.add_argument("--zoo", action="store_true",
                     help="one trajectory of each of the paper's actions (PF-MP, 1MP, 2MP, 1PF, 2PF, 2PF-1MP, "
                          "1PF-2MP) in FP64 and in the chosen mixed precision")
+    ap.add_argument("--ratio-sweep", action="store_true",
+                    help="<dH^2>/2 against the filter / ratio step-size ratio (nested and interleaved schedules)")
+    ap.add_argument("--chain", type=int, default=0,
+                    help="a Markov chain of this many measured PF-MP trajectories (P_acc, <exp(-dH)>, cost C)")
+    ap.add_argument("--chain-therm", type=int, default=20, help="Metropolis trajectories before measuring")
+    ap.add_argument("--chain-steps", default="26,14,8,11", help="2MN steps: gauge, filter, correction, ratio")
+    ap.add_argument("--config5", action="store_true",
+                    help="the light-quark trajectory workload at 48^3 x 96: one trajectory per mode")
+    ap.add_argument("--c5-steps", default="24,8,4,3", help="2MN steps: gauge, filter, correction, ratios")
+    ap.add_argument("--c5-dims", default=",".join(map(str, C5_DIMS)), help="lattice (a smaller one for a dry run)")
+    ap.add_argument("--c5-therm", type=int, default=20, help="quenched thermalisation trajectories")
+    ap.add_argument("--c5-therm-steps", type=int, default=64, help="2MN steps of a thermalisation trajectory")
+    ap.add_argument("--c5-modes", default="both", choices=["both", "chosen", "plain_f64", "none"])
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="the oracle on the host: a full solve and the 4^4 trajectory, 1 thread and all threads")
+    ap.add_argument("--cpu-child", choices=["cg", "traj"], help=argparse.SUPPRESS)
     ap.add_argument("--trajectory-only", choices=["f64", "f32", "f16"],
                     help="thermalise, then run --warmup and --steps trajectories in one solver precision and "
                          "print their times (for kernel profiles of one trajectory)")
     args = ap.parse_args()
+    if args.cpu_child:
+        r = oracle_cg_solve() if args.cpu_child == "cg" else oracle_config1_trajectory()
+        print(json.dumps(dict(r, threads=int(os.environ.get("OMP_NUM_THREADS", "0")))), flush=True)
+        return
+    if args.cpu_full:
+        cpu_full(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -677,6 +1033,15 @@ def main():
         return
     if args.learned32:
         learned32_bench(args)
+        return
+    if args.config5:
+        config5_bench(args)
+        return
+    if args.ratio_sweep:
+        ratio_sweep_bench(args)
+        return
+    if args.chain > 0:
+        chain_bench(args)
         return
     from paper_1609_02652_amd import synth
     from paper_1609_02652_amd.pfmp import F64, F32, F16, Lattice
@@ -702,59 +1067,40 @@ def main():
     lat.set_operator(1, KAPPA_H, CSW)
     tune = lat.autotune(0)
     log("autotune: %s" % tune)
-    U = lat.get_gauge().cpu().numpy()
 
-    # ---- CG solves at 1e-10 in the three precisions
-    cg = cg_bench(lat, args.sources)
-    cg["roofline"] = cg_roofline(cg, lat.Vh)
-    log("cg roofline: %s" % cg["roofline"])
+    # ---- the headline: CG solves of the solve workload at 1e-10, warmup then exactly `steps`
+    # sources timed in each precision; the chosen form is the faster mixed-precision one
+    cg = cg_bench(lat, args.steps, args.warmup)
+    cg["roofline_16x16x16x32"] = cg_roofline(cg, lat.Vh)
+    chosen = min(("f32", "f16"), key=lambda k: cg[k]["mean_s"])
+    t_chosen = cg[chosen]["mean_s"]
+
+    # ---- context on the same field: the batched Hasenbusch-chain solve, the learned
+    # preconditioner, and the 16^3 x 32 PF-MP trajectory of the previous headline
     lat.set_operator(2, 0.1250, CSW)
     batched = batch_bench(lat)
-    try:
-        batched["force_eval_24x24x24x48"] = batched_force_bench()
-    except Exception as e:  # noqa: BLE001 -- report, do not hide
-        batched["force_eval_24x24x24x48"] = {"error": str(e)}
-    learned, W_net = learned_bench(lat, args.sources)
-    cg["learned_fcg"] = learned
-    cg["learned_gain_iters"] = round(1 - learned["fcg_iters"] / cg["f64"]["iters"], 3)
-    cg["learned_speedup_vs_f64"] = round(cg["f64"]["median_s"] / learned["fcg_median_s"], 3)
-    times = {"f32": cg["f32"]["median_s"], "f16": cg["f16"]["median_s"], "learned": learned["fcg_median_s"]}
-    chosen_prec = min(times, key=times.get)
-
-    # ---- trajectories: plain FP64 form, then the chosen form (timed value)
-    sp_plain = pfmp_spec(lat)
-    if chosen_prec == "learned":
-        sp_chosen = pfmp_spec(lat, ptnet=W_net)
-    else:
-        sp_chosen = pfmp_spec(lat, solver_prec={"f32": F32, "f16": F16}[chosen_prec])
-    t_plain, st_plain = run_trajectories(lat, sp_plain, args.steps, args.warmup, 100)
-    t_chosen, st_chosen = run_trajectories(lat, sp_chosen, args.steps, args.warmup, 100)
-    kmults = int(np.mean([s["kmults"] for s in st_plain]))
-
-    def traj_summary(t, sts):
-        return {"s_per_traj": round(t, 4), "accept_rate": float(np.mean([s["accept"] for s in sts])),
-                "dH": [round(s["dH"], 5) for s in sts], "kmults": int(np.mean([s["kmults"] for s in sts])),
-                "solver_iters": int(np.mean([s["solver_iters"] for s in sts]))}
-
-    # ---- the other uses of the three changes, one timed trajectory each on the same inputs
-    # (context for the chosen mode): the ratio solve and the correction term's z = 0 pole
-    # of each merged step as one multi-RHS solve in mixed precision, and every CG solve
-    # as the flexible CG with the trained network
-    variants = {}
-    for name, kw in (("mixed_batched", {"solver_prec": F16, "batch": True}), ("learned_fcg", {"ptnet": W_net})):
-        try:
-            t_v, st_v = run_trajectories(lat, pfmp_spec(lat, **kw), 1, args.warmup, 100)
-            variants[name] = traj_summary(t_v, st_v)
-        except Exception as e:  # noqa: BLE001 -- report, do not hide
-            variants[name] = {"error": str(e)}
+    learned, W_net = learned_bench(lat, 8)
+    learned["speedup_vs_f64_cg"] = round(cg["f64"]["median_s"] / learned["fcg_median_s"], 3)
+    learned["iters_saved_vs_f64_cg"] = round(1 - learned["fcg_iters"] / cg["f64"]["iters"], 3)
+    traj16 = {}
+    for name, kw in (("plain_f64", {}), ("chosen", {"solver_prec": F16 if chosen == "f16" else F32})):
+        t, sts = run_trajectories(lat, pfmp_spec(lat, **kw), 1, 1 if name == "chosen" else 0, 100)
+        traj16[name] = {"s_per_traj": round(t, 3), "dH": round(sts[0]["dH"], 5), "accept": sts[0]["accept"],
+                        "kmults": sts[0]["kmults"]}
+    traj16["speedup"] = round(traj16["plain_f64"]["s_per_traj"] / traj16["chosen"]["s_per_traj"], 3)
     lat.close()
+
+    # ---- the correctness-workload trajectory (4^4, kappa 0.120 / 0.110, degree-4 filter)
+    # in the plain FP64 form and the chosen form, on the same inputs
+    traj1 = config1_trajectories(F16 if chosen == "f16" else F32, args.warmup)
 
     # ---- dominant-kernel roofline (HIP events on the library stream).  The hop is
     # priced at the algorithmic bytes of one hop per output site, links as 8 x 18 reals
     # plus the input and output spinors (1,536 B in FP64); the kernel itself reads SU(3)
     # links as 2 rows (12 reals), so the bytes it must move are 1,152 B per site, also
     # reported.  The HBM figure is taken at 32^3 x 64, whose working set is far larger
-    # than the 256 MB Infinity Cache; the 16^3 x 32 workload lattice is reported beside.
+    # than the 256 MB Infinity Cache; the same lattice gives the CG iteration's roofline
+    # in each precision and the multi-RHS Khat.
     def roof_entry(dims, r):
         key = "x".join(map(str, dims))
         algo = r["Vh"] * (8 * 18 + 24 + 24) * 8
@@ -766,14 +1112,16 @@ def main():
                 "Mhat_us": round(r["t_M"] * 1e6, 2), "Mhat_GBps": round(r["bytes_M"] / r["t_M"] / 1e9, 1),
                 "tuning": r["tune"], "traffic": pmc_traffic(key)}
 
-    small = roof_entry(DIMS, hop_roofline(DIMS, U))
     big = (32, 32, 32, 64)
-    try:
-        rb = hop_roofline(big, synth.random_gauge(big, seed=5), reps=50, extra=batch_apply)
-        main_e = roof_entry(big, rb)
-        batched["apply_32x32x32x64"] = rb["extra"]
-    except Exception as e:  # noqa: BLE001 -- report, do not hide
-        main_e = dict(small, error_32x32x32x64=str(e))
+    extra32 = {}
+
+    def big_extra(lt):
+        extra32["cg_iteration_roofline"] = cg_iteration_roofline(lt, lt.Vh)
+        extra32["multi_rhs_Khat"] = batch_apply(lt)
+        return None
+
+    rb = hop_roofline(big, synth.random_gauge(big, seed=5), reps=50, extra=big_extra)
+    main_e = roof_entry(big, rb)
     roof = {"kernel": "hop D_oe, FP64 (k_hop_clovinv, plain), %s" % main_e["lattice"], "bound": "hbm",
             "achieved": main_e["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": main_e["frac"],
             "traffic": main_e["traffic"]}
@@ -781,55 +1129,93 @@ def main():
     roof["bytes_basis"] = ("algorithmic: links 8 x 18 + spinor in 24 + out 24 reals per output site (FP64); "
                            "moved: links read as 12 reals")
     roof["copy"] = copy_bandwidth()
-    roof["workload_lattice"] = dict(small, note="16^3x32 working set fits the 256 MB Infinity Cache")
+    roof["cg_iteration_32x32x32x64"] = extra32.get("cg_iteration_roofline")
 
     out = {
         "metric": "PF-MP trajectory s & CG solve s at 1e-10 resid, plain FP64 vs chosen; Dslash GB/s",
-        "value": round(t_chosen, 4),
-        "unit": "s/trajectory",
+        "value": round(t_chosen, 6),
+        "unit": "s/solve",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t_chosen * 1e3, 2),
+        "ms_per_step": round(t_chosen * 1e3, 3),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f32+f64", "f16": "f16-storage/f32+f64", "learned": "f64+f32-net"}[chosen_prec],
+        "dtype": {"f32": "f32+f64", "f16": "f16-storage/f32+f64"}[chosen],
         "data": "synthetic",
-        "config": {"workload": "PF-MP HMC trajectory on the 16^3x32 mixed-precision solve lattice: links from %d "
-                               "quenched HMC trajectories at beta=5.7 from the seeded start, clover kappa=0.1340 "
-                               "c_sw=1.6, Hasenbusch kappa'=0.1300, degree-4 filter (mu,nu)=(1.2,0.9), 2MN steps "
-                               "(ratio, correction, filter, S_det, gauge) = (20,20,120,120,480), every solve to 1e-10"
-                               % args.therm,
+        "config": {"workload": "mixed-precision solve benchmark: 16^3x32, links from %d quenched HMC "
+                               "trajectories at beta=5.7 from the seeded start, even-odd clover kappa=0.1340 "
+                               "c_sw=1.6, Gaussian sources one at a time, CG on Mhat^dag Mhat to 1e-10 with "
+                               "FP64 reliable updates; one step = one solve" % args.therm,
                    "lattice": "16x16x16x32",
-                   "mode": "chosen (fastest measured solver): %s for the ratio-term solves and the "
-                           "correction term's z = 0 pole, its complex poles by the FP64 multi-shift CG; "
-                           "filter-force chains in FP32; all actions, dH and the accept in FP64" % {"f32": "FP32 inner CG with FP64 reliable updates",
-                                               "f16": "FP16-storage inner CG with FP64 reliable updates",
-                                               "learned": "flexible CG with the trained PT-conv network"}[
-                               chosen_prec]},
-        "trajectory": {"chosen": traj_summary(t_chosen, st_chosen), "plain_f64": traj_summary(t_plain, st_plain),
-                       "speedup_vs_plain": round(t_plain / t_chosen, 3),
-                       "other_modes_one_trajectory": variants},
-        "cg_solve": dict(cg, tol=TOL, sources=args.sources),
+                   "mode": "chosen (the faster measured): %s" % {
+                       "f32": "FP32 inner CG with FP64 reliable updates",
+                       "f16": "FP32 arithmetic with FP16 spinor storage, FP64 reliable updates"}[chosen]},
+        "cg_solve": dict(cg, tol=TOL, sources=args.steps, chosen=chosen,
+                         speedup_chosen_vs_f64=round(cg["f64"]["mean_s"] / t_chosen, 3)),
+        "trajectory": {
+            "light_quark_48x48x48x96": "not in this line (minutes per trajectory): bench.py --config5, "
+                                       "results in profiles/config5_trajectory_48x48x48x96.md",
+            "correctness_workload_4x4x4x4": traj1,
+            "pfmp_16x16x16x32_context": traj16},
+        "multi_rhs_Khat_32x32x32x64": extra32.get("multi_rhs_Khat"),
+        "batched_chain_cg_16x16x16x32": batched,
+        "learned_preconditioner_16x16x16x32": learned,
         "paper_context": {
             "note": "the paper publishes work counts only (K multiplications per trajectory over acceptance), on "
                     "its own 16^3x32 Wilson ensemble at kappa 0.15825 with a modified BQCD; hardware, precision "
-                    "and times are not stated; context, not a target (bench.py --tune measures C here)",
+                    "and times are not stated; context, not a target",
             "cost_C_PF-MP": "29000 +- 1800 (Table 3.6, p = 4, kappa' = 0.155, steps (6, 20, 120, 480))",
             "cost_C_2MP": "31000 +- 2200 (Table 3.5)",
-            "cost_C_1MP": "43800 +- 3500 (Table 3.3)",
-            "cost_C_2PF": "47700 +- 3700 (Table 3.4)",
-            "cost_C_1PF": "87500 +- 7400 (Table 3.2)",
             "kmults_per_filter_force": "2p - 2 (Table 3.2)"},
-        "batched_solves": batched,
         "thermalisation": therm,
         "autotune": tune,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(kmults)
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+
+
+def config1_trajectories(prec, warmup, steps=3):
+    """The correctness workload's trajectory (4^4, periodic space, antiperiodic time; beta 5.6;
+    kappa 0.120, c_sw 1.0; Hasenbusch kappa' 0.110; degree-4 filter; 2MN steps (ratio,
+    correction, filter, gauge) = (10, 20, 40, 80); CG 1e-12) in the plain FP64 form and the
+    chosen form on the same seeded inputs: seconds per trajectory, dH and accept."""
+    import torch
+    from paper_1609_02652_amd import synth
+    from paper_1609_02652_amd.pfmp import Lattice
+    dims = (4, 4, 4, 4)
+    out = {}
+    for name, kw in (("plain_f64", {}), ("chosen", {"solver_prec": prec})):
+        lat = Lattice(dims)
+        lat.set_gauge(synth.random_gauge(dims, seed=0))
+        lat.set_operator(0, 0.120, 1.0)
+        lat.set_operator(1, 0.110, 1.0)
+        terms = [dict(kind="poly", op=1, n=4, mu=1.2, nu=0.9, steps=40),
+                 dict(kind="polycorr", op=1, n=4, mu=1.2, nu=0.9, steps=20),
+                 dict(kind="ratio", op=1, op2=0, steps=10)]
+        sp = lat.spec(5.6, terms, 80, det_op=0, tol=1e-12, **kw)
+        U0 = lat.get_gauge().clone()
+        sts, tot = [], 0.0
+        for k in range(warmup + steps):
+            P = lat.pack_momenta(synth.gaussian_momenta(lat.V, 100 + k))
+            etas = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 20 + 3 * k + j)) for j in range(3)]
+            lat.set_gauge(U0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = lat.trajectory(sp, P, etas, float(synth.uniform(200 + k)[0]))
+            torch.cuda.synchronize()
+            if k >= warmup:
+                tot += time.perf_counter() - t0
+                sts.append(st)
+        lat.close()
+        out[name] = {"s_per_traj": round(tot / steps, 4), "dH": [round(st["dH"], 10) for st in sts],
+                     "accept": [int(st["accept"]) for st in sts]}
+    out["speedup"] = round(out["plain_f64"]["s_per_traj"] / out["chosen"]["s_per_traj"], 3)
+    out["same_accept_decisions"] = out["plain_f64"]["accept"] == out["chosen"]["accept"]
+    return out
 
 
 if __name__ == "__main__":

@@ -137,6 +137,9 @@ int pfmp_set_graphs(pfmp_ctx *ctx, int on);
  * with a harder spectrum their rounding can cost iterations (both converge to the same
  * tolerance with FP64 reliable updates).  Applies to later solves. */
 int pfmp_set_half_links(pfmp_ctx *ctx, int on);
+/* level 1: pfmp_trajectory and pfmp_md_evolve print one line per phase and per merged
+ * step with fermion forces (solver iterations so far, seconds) to stderr; 0 (default): quiet. */
+int pfmp_set_verbose(pfmp_ctx *ctx, int level);
 int pfmp_get_link_reconstruct(pfmp_ctx *ctx, int *active);
 /* Configure slot op with (kappa, c_sw): builds A_ee, A_oo^-1 (per-site Cholesky
  * of the two 6x6 chiral blocks) and ln det A_oo.  Needs a gauge field.  Errors:
@@ -223,11 +226,18 @@ int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const double *z, const
 
 /* ---- multi-RHS batches (several pseudofermion solves at one gauge field) ------ */
 
-/* out_r = Khat_{ops[r]} in_r for nrhs <= 8 right-hand sides, each with its own
- * operator slot (all clover or all Wilson), in 4 launches: one workgroup per (site
- * block, rhs), the workgroups of one site block adjacent so that they share the links
- * through L2.  FP64 internal spinors. */
-int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *const *in, void *const *out);
+/* out_r = Khat_{ops[r]} in_r for nrhs <= 8 right-hand sides, each with its own operator
+ * slot (all clover or all Wilson), each bit for bit the single-RHS Khat.  Clover batches
+ * (default layout): a lane pair per site applies each leg's link, loaded once, to up to 4
+ * right-hand sides (4 launches per group of 4).  Wilson batches, or after
+ * pfmp_set_batch_layout(ctx, 0): one workgroup per (site block, rhs), the workgroups of one
+ * site block adjacent so that they share the links through L2 (4 launches).  prec
+ * PFMP_F64 or PFMP_F32 internal spinors (FP32: FP32 links and clover). */
+int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *const *in, void *const *out,
+                           int prec);
+/* layout of the batched clover stencils (apply and CG): 1 (default) up to 4 rhs per lane pair
+ * sharing each link load; 0 one workgroup per (site block, rhs).  Same results. */
+int pfmp_set_batch_layout(pfmp_ctx *ctx, int multi);
 /* CG for Khat_{ops[r]} x_r = b_r, r < nrhs <= 8, all iterated in the same launches;
  * a converged right-hand side stops.  b, x: FP64 internal spinors; st: nrhs records.
  * p->prec PFMP_F64: CG in FP64.  PFMP_F32 (and PFMP_F16, taken as FP32): defect

@@ -202,6 +202,199 @@ __global__ void k_b_update_p(Geom g, int nrhs, VecsT<C> rr, VecsT<C> p, const do
     p.out[r][e] = mk<C>(fmadd(beta, pv.x, rv.x), fmadd(beta, pv.y, rv.y));
 }
 
+// ---------------------------------------------------------------- one workgroup, NR rhs
+//
+// The same stages with the NR right-hand sides of a launch (rhs r0 .. r0 + NR - 1) in one
+// lane pair per site: each leg's link is loaded once and applied to the NR neighbour half
+// spinors, with the single-RHS leg arithmetic (leg_apply) for each, so every rhs gets the
+// bits of its single-RHS stage.  A converged rhs is skipped by the whole workgroup.
+
+// active right-hand sides of the launch (uniform in the workgroup)
+template <int NR>
+__device__ __forceinline__ void rhs_active(const double *__restrict__ st, int r0, bool *act)
+{
+#pragma unroll
+    for (int q = 0; q < NR; q++) act[q] = !st || st[8 * (r0 + q) + B_DONE] == 0;
+}
+
+template <int MU, int DIR, int LM, int NR, typename C, typename UL>
+__device__ __forceinline__ void legs_multi(const Geom &g, int pout, int i, const int *c, int hb,
+                                           const C *const *in, UL U, decltype(C::x) gs, const bool *act,
+                                           C (*up)[3], C (*loA)[3], C (*loB)[3])
+{
+    int s;
+    const int j = eo_neighbour(g, c, MU, DIR ? -1 : +1, &s);
+    const int qs = MU < 2 ? 3 - hb : 2 + hb;
+    const int lp = DIR ? 1 - pout : pout;
+    Leg<C, const C *, UL, LM> l[NR];
+    l[0].lk.template load<(LM >> 1) & 1>(lshift(U, ((long)(lp * 4 + MU) * 9) * g.Vh), g.Vh, DIR ? j : i);
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+        if (q > 0) l[q].lk = l[0].lk;
+        l[q].sg = (decltype(C::x))s;
+        if (act[q]) l[q].sp.load(in[q], g.Vh, j, 3 * hb, 3 * qs);
+    }
+#pragma unroll
+    for (int q = 0; q < NR; q++)
+        if (act[q]) leg_apply<MU, DIR, LM, C>(l[q], hb, gs, up[q], loA[q], loB[q]);
+}
+
+// D_hop in_q for the NR rhs (block hb of the result at output site i), as hop_pair
+template <int LM, int NR, typename C, typename UL>
+__device__ __forceinline__ void hop_multi(const Geom &g, int pout, int i, int hb, const C *const *in, UL U,
+                                          decltype(C::x) gs, const bool *act, C (*blk)[6])
+{
+    int c[4];
+    eo_coords(g, pout, i, c);
+    C up[NR][3], loA[NR][3], loB[NR][3];
+#pragma unroll
+    for (int q = 0; q < NR; q++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) up[q][a] = loA[q][a] = loB[q][a] = mk<C>(0, 0);
+    legs_multi<0, 0, LM, NR>(g, pout, i, c, hb, in, U, gs, act, up, loA, loB);
+    legs_multi<0, 1, LM, NR>(g, pout, i, c, hb, in, U, gs, act, up, loA, loB);
+    legs_multi<1, 0, LM, NR>(g, pout, i, c, hb, in, U, gs, act, up, loA, loB);
+    legs_multi<1, 1, LM, NR>(g, pout, i, c, hb, in, U, gs, act, up, loA, loB);
+    legs_multi<2, 0, LM, NR>(g, pout, i, c, hb, in, U, gs, act, up, loA, loB);
+    legs_multi<2, 1, LM, NR>(g, pout, i, c, hb, in, U, gs, act, up, loA, loB);
+    legs_multi<3, 0, LM, NR>(g, pout, i, c, hb, in, U, gs, act, up, loA, loB);
+    legs_multi<3, 1, LM, NR>(g, pout, i, c, hb, in, U, gs, act, up, loA, loB);
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+        C x[6];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            x[a] = hb ? up[q][a] : loB[q][a];
+            x[3 + a] = hb ? up[q][a] : loA[q][a];
+        }
+#pragma unroll
+        for (int k = 0; k < 6; k++) x[k] = mk<C>(pair_swap(x[k].x), pair_swap(x[k].y));
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            blk[q][a] = hb ? cadd(loA[q][a], x[a]) : up[q][a];
+            blk[q][3 + a] = hb ? cadd(loB[q][a], x[3 + a]) : x[a];
+        }
+    }
+}
+
+// out_r = [g5] A_oo^-1 D_oe [g5] in_r for r = r0 .. r0 + NR - 1
+template <typename C, typename R, int CLOV, int LM, int NR>
+__global__ __launch_bounds__(kBlock) void k_bm_clovinv(Geom g, BatchT<R> b, VecsT<C> v, const C *__restrict__ U,
+                                                       R gin, R gout, const double *__restrict__ st, int r0)
+{
+    const int tt = xcd_site(2 * g.Vh);
+    if (tt < 0) return;
+    bool act[NR];
+    rhs_active<NR>(st, r0, act);
+    const int i = tile_site(g, tt >> 1), hb = tt & 1;
+    C blk[NR][6];
+    hop_multi<LM, NR>(g, 1, i, hb, v.in + r0, U, gin, act, blk);
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+        if (!act[q]) continue;
+        if (CLOV) {
+            C tq[6];
+            clover_block<R, C>(b.clo[r0 + q], g.Vh, i, hb, blk[q], tq);
+            store_block(v.out[r0 + q], g.Vh, i, hb, gout, tq);
+        } else {
+            store_block(v.out[r0 + q], g.Vh, i, hb, gout, blk[q]);
+        }
+    }
+}
+
+// out_r = [g5] (A_ee [g5] x_r + a_r D_eo t_r); with partials, the |out_r|^2 partials
+template <typename C, typename R, int CLOV, int LM, int NR>
+__global__ __launch_bounds__(kBlock) void k_bm_xpay(Geom g, BatchT<R> b, VecsT<C> x, VecsT<C> t,
+                                                    const C *__restrict__ U, R gs, const double *__restrict__ st,
+                                                    double *__restrict__ partials, int r0)
+{
+    const int tt = xcd_site(2 * g.Vh);
+    bool act[NR];
+    rhs_active<NR>(st, r0, act);
+    double nrm[NR];
+#pragma unroll
+    for (int q = 0; q < NR; q++) nrm[q] = 0;
+    if (tt >= 0) {
+        const int i = tile_site(g, tt >> 1), hb = tt & 1;
+        C acc[NR][6];
+        hop_multi<LM, NR>(g, 0, i, hb, t.in + r0, U, (R)1, act, acc);
+#pragma unroll
+        for (int q = 0; q < NR; q++) {
+            if (!act[q]) continue;
+            C xv[6], ax[6];
+            load_block(x.in[r0 + q], g.Vh, i, hb, gs, xv);
+            if (CLOV) clover_block<R, C>(b.cle[r0 + q], g.Vh, i, hb, xv, ax);
+            const R a = b.a[r0 + q];
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                C base = CLOV ? ax[k] : xv[k];
+                acc[q][k] = mk<C>(fmadd(a, acc[q][k].x, base.x), fmadd(a, acc[q][k].y, base.y));
+                cnorm_acc(nrm[q], acc[q][k]);
+            }
+            store_block(x.out[r0 + q], g.Vh, i, hb, gs, acc[q]);
+        }
+    }
+    if (partials)
+#pragma unroll
+        for (int q = 0; q < NR; q++)
+            if (act[q]) {
+                const double v[1] = {nrm[q]};
+                partials_store_at<kBlock, 1>(v, partials + (long)(r0 + q) * b.pstride, xcd_block());
+            }
+}
+
+// CG stage 4 for the NR rhs (the single-RHS arithmetic), |r_r|^2 partials
+template <typename C, typename R, int CLOV, int LM, int NR>
+__global__ __launch_bounds__(kBlock) void k_bm_hop4(Geom g, BatchT<R> b, VecsT<C> t, VecsT<C> T, VecsT<C> p,
+                                                    VecsT<C> x, VecsT<C> rr, const C *__restrict__ U,
+                                                    const double *__restrict__ st, double *__restrict__ partials,
+                                                    int r0)
+{
+    const int tt = xcd_site(2 * g.Vh);
+    bool act[NR];
+    rhs_active<NR>(st, r0, act);
+    double nrm[NR];
+#pragma unroll
+    for (int q = 0; q < NR; q++) nrm[q] = 0;
+    if (tt >= 0) {
+        const int i = tile_site(g, tt >> 1), hb = tt & 1;
+        C acc[NR][6];
+        hop_multi<LM, NR>(g, 0, i, hb, T.in + r0, U, (R)1, act, acc);
+        const long Vh = g.Vh;
+#pragma unroll
+        for (int q = 0; q < NR; q++) {
+            if (!act[q]) continue;
+            const int r = r0 + q;
+            const double *s = st + 8 * r;
+            C tv[6], at[6];
+            load_block(t.in[r], g.Vh, i, hb, (R)-1, tv);
+            if (CLOV) clover_block<R, C>(b.cle[r], g.Vh, i, hb, tv, at);
+            const R alpha = (R)(s[B_RR] / s[B_PAP]), a = b.a[r];
+            const C *pp = p.in[r];
+            C *xx = x.out[r], *rv_ = rr.out[r];
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                C base = CLOV ? at[k] : tv[k];
+                C kp = mk<C>(fmadd(a, acc[q][k].x, base.x), fmadd(a, acc[q][k].y, base.y));
+                if (hb) kp = cneg(kp);
+                const long e = (long)(6 * hb + k) * Vh + i;
+                C pv = pp[e], xv = xx[e], rv = rv_[e];
+                xv.x = fmadd(alpha, pv.x, xv.x); xv.y = fmadd(alpha, pv.y, xv.y);
+                rv.x = fmadd(-alpha, kp.x, rv.x); rv.y = fmadd(-alpha, kp.y, rv.y);
+                xx[e] = xv;
+                rv_[e] = rv;
+                cnorm_acc(nrm[q], rv);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; q++)
+        if (act[q]) {
+            const double v[1] = {nrm[q]};
+            partials_store_at<kBlock, 1>(v, partials + (long)(r0 + q) * b.pstride, xcd_block());
+        }
+}
+
 // out = (FP32) (s * in); in FP64
 __global__ void k_b_narrow(long n, double s, const double2 *__restrict__ in, float2 *__restrict__ out)
 {
@@ -233,6 +426,34 @@ __global__ void k_b_accum(long n, double s, const float2 *__restrict__ e, double
             else hipLaunchKernelGGL((K<C, R, 0, 1>), grid, block, shm, stream, __VA_ARGS__);                \
         }                                                                                                 \
     } while (0)
+
+// launch the (C, R, clover, link mode, NR) instance of a multi-rhs kernel for the nr (1..4)
+// right-hand sides from r0; the grid covers the sites once (XCD-aware order)
+#define BM_LM(K, C, R, NR, grid, ...)                                                                      \
+    do {                                                                                                 \
+        if ((link_mode(ctx->g) & 1) == 0)                                                                \
+            hipLaunchKernelGGL((K<C, R, 1, 0, NR>), grid, dim3(kBlock), 0, ctx->stream, __VA_ARGS__);    \
+        else                                                                                             \
+            hipLaunchKernelGGL((K<C, R, 1, 1, NR>), grid, dim3(kBlock), 0, ctx->stream, __VA_ARGS__);    \
+    } while (0)
+#define BMLAUNCH(K, C, R, nr, grid, ...)                    \
+    do {                                                    \
+        switch (nr) {                                       \
+        case 1: BM_LM(K, C, R, 1, grid, __VA_ARGS__); break; \
+        case 2: BM_LM(K, C, R, 2, grid, __VA_ARGS__); break; \
+        case 3: BM_LM(K, C, R, 3, grid, __VA_ARGS__); break; \
+        default: BM_LM(K, C, R, 4, grid, __VA_ARGS__); break; \
+        }                                                   \
+    } while (0)
+constexpr int kMultiRhs = 4;   // right-hand sides per lane pair in the multi-rhs layout
+
+// the multi-rhs layout (each link load shared by up to 4 rhs in a lane) for clover batches
+// unless switched off (pfmp_set_batch_layout)
+template <typename R>
+static bool use_multi(const pfmp_ctx *ctx, const BatchT<R> &b)
+{
+    return ctx->batch_multi && b.clov[0];
+}
 
 static int make_batch(pfmp_ctx *ctx, int nrhs, const int *ops, BatchT<double> &b, BatchT<float> &bf)
 {
@@ -272,9 +493,47 @@ static VecsT<C> vecs(int n, const void *const *in, void *const *out)
     return v;
 }
 
-// out_r = Khat_r in_r for all r: 4 launches regardless of the number of rhs
+// out_r = Khat_r in_r for all r: 4 launches (multi-rhs layout: 4 per group of 4 rhs)
+template <typename C, typename R>
+static int apply_batch(pfmp_ctx *ctx, const BatchT<R> &b, const C *U, int nrhs, const void *const *in,
+                       void *const *out)
+{
+    const Geom &g = ctx->g;
+    std::vector<void *> te(nrhs), to(nrhs);
+    for (int r = 0; r < nrhs; r++) {
+        te[r] = pool_get(ctx, 1000 + r);
+        to[r] = pool_get(ctx, 1008 + r);
+        if (!te[r] || !to[r]) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
+    }
+    const VecsT<C> in_to = vecs<C>(nrhs, in, to.data()), in_te = vecs<C>(nrhs, in, te.data());
+    const VecsT<C> to_in = vecs<C>(nrhs, (const void *const *)to.data(), nullptr);
+    const VecsT<C> te_to = vecs<C>(nrhs, (const void *const *)te.data(), to.data());
+    const VecsT<C> te_out = vecs<C>(nrhs, (const void *const *)te.data(), out);
+    // Mhat in -> te (stage 1 to to, stage 2 to te), then Mhat^dag te -> out
+    if (use_multi(ctx, b)) {
+        dim3 grid(op_nparts(g));
+        for (int r0 = 0; r0 < nrhs; r0 += kMultiRhs) {
+            const int nr = std::min(kMultiRhs, nrhs - r0);
+            BMLAUNCH(k_bm_clovinv, C, R, nr, grid, g, b, in_to, U, (R)1, (R)1, (const double *)nullptr, r0);
+            BMLAUNCH(k_bm_xpay, C, R, nr, grid, g, b, in_te, to_in, U, (R)1, (const double *)nullptr,
+                     (double *)nullptr, r0);
+            BMLAUNCH(k_bm_clovinv, C, R, nr, grid, g, b, te_to, U, (R)-1, (R)1, (const double *)nullptr, r0);
+            BMLAUNCH(k_bm_xpay, C, R, nr, grid, g, b, te_out, to_in, U, (R)-1, (const double *)nullptr,
+                     (double *)nullptr, r0);
+        }
+    } else {
+        dim3 grid(((b.nsb * nrhs + 7) / 8) * 8), block(kBlock);
+        BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, in_to, U, (R)1, (R)1, nullptr);
+        BLAUNCH(k_b_xpay, C, R, b, grid, block, 0, ctx->stream, g, b, in_te, to_in, U, (R)1, nullptr, nullptr);
+        BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, te_to, U, (R)-1, (R)1, nullptr);
+        BLAUNCH(k_b_xpay, C, R, b, grid, block, 0, ctx->stream, g, b, te_out, to_in, U, (R)-1, nullptr, nullptr);
+    }
+    LAUNCHCHK(ctx);
+    return 0;
+}
+
 extern "C" int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *const *in,
-                                      void *const *out)
+                                      void *const *out, int prec)
 {
     if (!ctx) return PFMP_ERR_ARG;
     BatchT<double> b;
@@ -284,26 +543,18 @@ extern "C" int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, c
     if (!in || !out) return set_err(ctx, PFMP_ERR_ARG, "batch: null buffers");
     for (int r = 0; r < nrhs; r++)
         if (!in[r] || !out[r]) return set_err(ctx, PFMP_ERR_ARG, "batch: null buffer");
-    const Geom &g = ctx->g;
-    std::vector<void *> te(nrhs), to(nrhs);
-    for (int r = 0; r < nrhs; r++) {
-        te[r] = pool_get(ctx, 1000 + r);
-        to[r] = pool_get(ctx, 1008 + r);
-        if (!te[r] || !to[r]) return set_err(ctx, PFMP_ERR_OOM, "batch workspace");
+    if (prec == PFMP_F64) return apply_batch<double2, double>(ctx, b, ctx->U, nrhs, in, out);
+    if (prec == PFMP_F32) {
+        if ((rc = gauge_f32_ready(ctx))) return rc;
+        return apply_batch<float2, float>(ctx, bf, ctx->Uf, nrhs, in, out);
     }
-    dim3 grid(((b.nsb * nrhs + 7) / 8) * 8), block(kBlock);
-    using C = double2;
-    using R = double;
-    // Mhat in -> te (stage 1 to to, stage 2 to te), then Mhat^dag te -> out
-    BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, vecs<C>(nrhs, in, to.data()), ctx->U, 1.0,
-            1.0, nullptr);
-    BLAUNCH(k_b_xpay, C, R, b, grid, block, 0, ctx->stream, g, b, vecs<C>(nrhs, in, te.data()),
-            vecs<C>(nrhs, (const void *const *)to.data(), nullptr), ctx->U, 1.0, nullptr, nullptr);
-    BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b,
-            vecs<C>(nrhs, (const void *const *)te.data(), to.data()), ctx->U, -1.0, 1.0, nullptr);
-    BLAUNCH(k_b_xpay, C, R, b, grid, block, 0, ctx->stream, g, b, vecs<C>(nrhs, (const void *const *)te.data(), out),
-            vecs<C>(nrhs, (const void *const *)to.data(), nullptr), ctx->U, -1.0, nullptr, nullptr);
-    LAUNCHCHK(ctx);
+    return set_err(ctx, PFMP_ERR_ARG, "apply_MdagM_batch: FP64 or FP32 fields");
+}
+
+extern "C" int pfmp_set_batch_layout(pfmp_ctx *ctx, int multi)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    ctx->batch_multi = multi != 0;
     return 0;
 }
 
@@ -355,15 +606,36 @@ static int batch_cg_core(pfmp_ctx *ctx, const BatchT<R> &b, const void *const *b
     const VecsT<C> T1_to_T2 = vecs<C>(nrhs, (const void *const *)T1.data(), T2.data());
     const C *U = sizeof(R) == 8 ? (const C *)ctx->U : (const C *)ctx->Uf;
     int chunk = check_every > 0 ? check_every : 25;
-    // one iteration for all rhs: 7 launches with fixed arguments, replayed as a graph; each
-    // rhs takes the single-RHS CG's steps in its arithmetic and summation order
+    const bool multi = use_multi(ctx, b);
+    dim3 gridm(op_nparts(g));
+    // one iteration for all rhs: 7 launches with fixed arguments (4 more per further group of
+    // 4 rhs in the multi-rhs layout), replayed as a graph; each rhs takes the single-RHS CG's
+    // steps in its arithmetic and summation order
     auto iteration = [&]() -> int {
-        BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, p_to_T2, U, (R)1, (R)1, sc);
-        BLAUNCH(k_b_xpay, C, R, b, grid, block, 0, ctx->stream, g, b, p_to_T1, vT2, U, (R)1, sc, part_a);
+        if (multi) {
+            for (int r0 = 0; r0 < nrhs; r0 += kMultiRhs)
+                BMLAUNCH(k_bm_clovinv, C, R, std::min(kMultiRhs, nrhs - r0), gridm, g, b, p_to_T2, U, (R)1, (R)1,
+                         (const double *)sc, r0);
+            for (int r0 = 0; r0 < nrhs; r0 += kMultiRhs)
+                BMLAUNCH(k_bm_xpay, C, R, std::min(kMultiRhs, nrhs - r0), gridm, g, b, p_to_T1, vT2, U, (R)1,
+                         (const double *)sc, part_a, r0);
+        } else {
+            BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, p_to_T2, U, (R)1, (R)1, sc);
+            BLAUNCH(k_b_xpay, C, R, b, grid, block, 0, ctx->stream, g, b, p_to_T1, vT2, U, (R)1, sc, part_a);
+        }
         hipLaunchKernelGGL(k_b_pap, dim3(1), dim3(kFinishThreads), 0, ctx->stream, part_a, b.nsb, b.pstride, nrhs,
                            sc);
-        BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, T1_to_T2, U, (R)-1, (R)1, sc);
-        BLAUNCH(k_b_hop4, C, R, b, grid, block, 0, ctx->stream, g, b, vT1, vT2, vP, vX, vR, U, sc, part_b);
+        if (multi) {
+            for (int r0 = 0; r0 < nrhs; r0 += kMultiRhs)
+                BMLAUNCH(k_bm_clovinv, C, R, std::min(kMultiRhs, nrhs - r0), gridm, g, b, T1_to_T2, U, (R)-1, (R)1,
+                         (const double *)sc, r0);
+            for (int r0 = 0; r0 < nrhs; r0 += kMultiRhs)
+                BMLAUNCH(k_bm_hop4, C, R, std::min(kMultiRhs, nrhs - r0), gridm, g, b, vT1, vT2, vP, vX, vR, U,
+                         (const double *)sc, part_b, r0);
+        } else {
+            BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, T1_to_T2, U, (R)-1, (R)1, sc);
+            BLAUNCH(k_b_hop4, C, R, b, grid, block, 0, ctx->stream, g, b, vT1, vT2, vP, vX, vR, U, sc, part_b);
+        }
         hipLaunchKernelGGL(k_b_beta, dim3(1), dim3(kFinishThreads), 0, ctx->stream, part_b, b.nsb, b.pstride, nrhs,
                            sc);
         hipLaunchKernelGGL((k_b_update_p<C>), dim3(nblocks(n * nrhs, 256)), dim3(256), 0, ctx->stream, g, nrhs, vR,
@@ -385,6 +657,7 @@ static int batch_cg_core(pfmp_ctx *ctx, const BatchT<R> &b, const void *const *b
     for (const void *ptr : {(const void *)part_a, (const void *)part_b, (const void *)sc, (const void *)U})
         key_add(key, ptr);
     key_add(key, b.clov[0]);
+    key_add(key, (int)multi);
     for (;;) {
         bool all = true;
         for (int r = 0; r < nrhs; r++) all = all && init[8 * r + B_DONE] != 0;

@@ -118,6 +118,13 @@ extern "C" int pfmp_set_half_links(pfmp_ctx *ctx, int on)
     return 0;
 }
 
+extern "C" int pfmp_set_verbose(pfmp_ctx *ctx, int level)
+{
+    if (!ctx) return PFMP_ERR_ARG;
+    ctx->verbose = level;
+    return 0;
+}
+
 extern "C" int pfmp_set_graphs(pfmp_ctx *ctx, int on)
 {
     if (!ctx) return PFMP_ERR_ARG;

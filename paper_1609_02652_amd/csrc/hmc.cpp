@@ -19,7 +19,9 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <numeric>
 #include <vector>
 
@@ -149,7 +151,7 @@ int msolve(Ctx &X, int op, const std::vector<cd> &z, const void *b, std::vector<
            const void *x0 = nullptr)
 {
     int k0 = -1;
-    if (low_precision_mode(X) && z.size() > 1)
+    if (low_precision_mode(X))
         for (size_t k = 0; k < z.size(); k++)
             if (z[k] == cd(0.0)) k0 = (int)k;
     std::vector<double> zz;
@@ -160,11 +162,14 @@ int msolve(Ctx &X, int op, const std::vector<cd> &z, const void *b, std::vector<
         zz.push_back(z[k].imag());
         xv.push_back(xs[k]);
     }
-    pfmp_solver_params p{X.sp->tol, X.sp->maxiter > 0 ? X.sp->maxiter : 100000, PFMP_F64, 0.0, 0};
-    pfmp_solver_stats st{};
-    int rc = pfmp_cg_multishift(X.c, op, (int)xv.size(), zz.data(), b, xv.data(), &p, &st);
-    X.iters += st.iters;
-    X.mhalf += 2 * st.kmults;
+    int rc = 0;
+    if (!xv.empty()) {
+        pfmp_solver_params p{X.sp->tol, X.sp->maxiter > 0 ? X.sp->maxiter : 100000, PFMP_F64, 0.0, 0};
+        pfmp_solver_stats st{};
+        rc = pfmp_cg_multishift(X.c, op, (int)xv.size(), zz.data(), b, xv.data(), &p, &st);
+        X.iters += st.iters;
+        X.mhalf += 2 * st.kmults;
+    }
     if (rc || k0 < 0) return rc;
     if (x0) {
         HIPCHK(X.c, hipMemcpyAsync(xs[k0], x0, sizeof(double) * spinor_reals(X.c->g), hipMemcpyDeviceToDevice,
@@ -172,6 +177,36 @@ int msolve(Ctx &X, int op, const std::vector<cd> &z, const void *b, std::vector<
         return 0;
     }
     return solve(X, op, b, xs[k0]);
+}
+
+// Poles per multi-shift solve: each pole keeps its solution, its search direction and (for
+// the force) its Mhat image, so the poles of a high-degree filter run in groups that fit
+// kShiftBudget of device memory (a group of a large lattice, all poles at once on a small
+// one).  A group holds whole conjugate pairs, which the force pairs up.  Every pole stops on
+// its own residual, so its solution does not depend on the grouping.
+constexpr double kShiftBudget = 48.0 * (1ull << 30);
+
+std::vector<std::vector<int>> pole_groups(pfmp_ctx *ctx, const std::vector<cd> &z, bool pairs)
+{
+    const double vb = sizeof(double) * (double)spinor_reals(ctx->g);
+    const int G = std::max(2, (int)std::min<double>(1e6, kShiftBudget / (3.0 * vb)));
+    std::vector<std::vector<int>> groups(1);
+    std::vector<bool> done(z.size(), false);
+    for (size_t i = 0; i < z.size(); i++) {
+        if (done[i]) continue;
+        std::vector<int> mem{(int)i};
+        done[i] = true;
+        if (pairs) {
+            const int j = partner(z, (int)i);
+            if (!done[j]) {
+                mem.push_back(j);
+                done[j] = true;
+            }
+        }
+        if ((int)(groups.back().size() + mem.size()) > G && !groups.back().empty()) groups.emplace_back();
+        groups.back().insert(groups.back().end(), mem.begin(), mem.end());
+    }
+    return groups;
 }
 
 int applyM(Ctx &X, int op, int dag, const void *in, void *out, int prec = PFMP_F64)
@@ -226,14 +261,20 @@ int term_action(Ctx &X, const pfmp_term &t, const void *phi, double *S)
         roots_of(t, z, a);
         z.push_back(0.0);
         std::vector<cd> r = residues(z);
-        std::vector<double2 *> xs(z.size());
-        for (size_t k = 0; k < z.size(); k++)
-            if (!(xs[k] = pool_get(ctx, kChain + (int)k))) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
-        if ((rc = msolve(X, t.op, z, phi, xs))) return rc;
         cd s = 0;
-        for (size_t k = 0; k < z.size(); k++) {
-            s += r[k] * dot(X, phi, xs[k], rc);
-            if (rc) return rc;
+        for (const std::vector<int> &grp : pole_groups(ctx, z, false)) {
+            std::vector<cd> zg;
+            std::vector<double2 *> xs;
+            for (size_t q = 0; q < grp.size(); q++) {
+                zg.push_back(z[grp[q]]);
+                xs.push_back(pool_get(ctx, kChain + (int)q));
+                if (!xs.back()) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+            }
+            if ((rc = msolve(X, t.op, zg, phi, xs))) return rc;
+            for (size_t q = 0; q < grp.size(); q++) {
+                s += r[grp[q]] * dot(X, phi, xs[q], rc);
+                if (rc) return rc;
+            }
         }
         *S = (s / a).real();
         return 0;
@@ -268,18 +309,22 @@ int term_heatbath(Ctx &X, const pfmp_term &t, const void *eta, void *phi)
         roots_of(t, z, a);
         z.resize(z.size() / 2);
         std::vector<cd> r = residues(z);
-        std::vector<double2 *> xs(z.size());
-        for (size_t k = 0; k < z.size(); k++)
-            if (!(xs[k] = pool_get(ctx, kChain + (int)k))) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
-        if ((rc = msolve(X, t.op, z, eta, xs))) return rc;
-        double zero[2] = {0, 0};
         HIPCHK(ctx, hipMemsetAsync(phi, 0, sizeof(double) * spinor_reals(ctx->g), ctx->stream));
-        for (size_t k = 0; k < z.size(); k++) {
-            cd c = r[k] / std::sqrt(a);
-            double cc[2] = {c.real(), c.imag()}, one[2] = {1, 0};
-            if ((rc = pfmp_axpby(ctx, cc, xs[k], one, phi))) return rc;
+        for (const std::vector<int> &grp : pole_groups(ctx, z, false)) {
+            std::vector<cd> zg;
+            std::vector<double2 *> xs;
+            for (size_t q = 0; q < grp.size(); q++) {
+                zg.push_back(z[grp[q]]);
+                xs.push_back(pool_get(ctx, kChain + (int)q));
+                if (!xs.back()) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+            }
+            if ((rc = msolve(X, t.op, zg, eta, xs))) return rc;
+            for (size_t q = 0; q < grp.size(); q++) {
+                cd c = r[grp[q]] / std::sqrt(a);
+                double cc[2] = {c.real(), c.imag()}, one[2] = {1, 0};
+                if ((rc = pfmp_axpby(ctx, cc, xs[q], one, phi))) return rc;
+            }
         }
-        (void)zero;
         return 0;
     }
     case PFMP_TERM_POLYCORR: {
@@ -323,79 +368,98 @@ int term_force(Ctx &X, const pfmp_term &t, const void *phi, double eps, double *
         double a;
         roots_of(t, z, a);
         const int n = (int)z.size();
-        // eta_1..eta_n from roots z_1^*..z_{n-1}^*; chi_n..chi_1 from z_n..z_2 with norm a
-        std::vector<void *> E(n), C(n), WE(n), WC(n);
-        for (int k = 0; k < n; k++) {
-            E[k] = pool_get(ctx, kChain + k);
-            C[k] = pool_get(ctx, kChain + n + k);
-            WE[k] = pool_get(ctx, kChain + 2 * n + k);
-            WC[k] = pool_get(ctx, kChain + 3 * n + k);
-            if (!E[k] || !C[k] || !WE[k] || !WC[k]) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+        // chi_n..chi_1 from z_n..z_2 with norm a, all kept (C[k] = chi_{n-k}); eta_1 = phi and
+        // eta_{i+1} = (J - z_i^*) eta_i formed one at a time as i runs up, with the Mhat images
+        // of eta_i and chi_i and the force pairs of four i at a time in a ring of buffers: n + 12
+        // vectors instead of 4n.  In the mixed-precision modes the chains, their Mhat images and
+        // the force's odd-site intermediates are FP32 (FP32 links and clover); the force sums in
+        // FP64 and the filter action stays FP64.
+        const bool f32 = low_precision_mode(X);
+        const int prec = f32 ? PFMP_F32 : PFMP_F64;
+        constexpr int R = 4;
+        std::vector<void *> C(n), E(R), WE(R), WC(R);
+        for (int k = 0; k < n; k++)
+            if (!(C[k] = pool_get(ctx, kChain + k))) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+        for (int q = 0; q < R; q++) {
+            E[q] = pool_get(ctx, kChain + n + q);
+            WE[q] = pool_get(ctx, kChain + n + R + q);
+            WC[q] = pool_get(ctx, kChain + n + 2 * R + q);
+            if (!E[q] || !WE[q] || !WC[q]) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
         }
-        std::vector<cd> re(n - 1), rc_(n - 1);
-        for (int k = 0; k < n - 1; k++) {
-            re[k] = std::conj(z[k]);
-            rc_[k] = z[n - 1 - k];
-        }
-        if (low_precision_mode(X)) {
-            // the chains, their Mhat images and the force's odd-site intermediates in FP32
-            // (FP32 links and clover); the force sums in FP64 and the filter action stays FP64
-            std::vector<void *> E32(n), C32(n), WE32(n), WC32(n);
-            for (int k = 0; k < n; k++) {
-                E32[k] = pool_get(ctx, kChain + 4 * n + k);
-                C32[k] = pool_get(ctx, kChain + 5 * n + k);
-                WE32[k] = pool_get(ctx, kChain + 2 * n + k);   // FP32 in the FP64 mode's WE / WC
-                WC32[k] = pool_get(ctx, kChain + 3 * n + k);
-                if (!E32[k] || !C32[k] || !WE32[k] || !WC32[k]) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
-            }
-            void *phi32 = pool_get(ctx, kChain + 6 * n);
+        const void *src = phi;
+        if (f32) {
+            void *phi32 = pool_get(ctx, kChain + n + 3 * R);
             if (!phi32) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
             if ((rc = pfmp_convert_spinor(ctx, phi, PFMP_F64, phi32, PFMP_F32))) return rc;
-            if ((rc = poly(X, t.op, re, 1.0, phi32, E32[n - 1], E32.data(), PFMP_F32))) return rc;
-            if ((rc = poly(X, t.op, rc_, a, phi32, C32[n - 1], C32.data(), PFMP_F32))) return rc;
-            for (int i = 1; i <= n; i++) {
-                if ((rc = applyM(X, t.op, 0, E32[i - 1], WE32[i - 1], PFMP_F32))) return rc;
-                if ((rc = applyM(X, t.op, 0, C32[n - i], WC32[i - 1], PFMP_F32))) return rc;
-                pair(WE32[i - 1], C32[n - i], eps);
-                pair(WC32[i - 1], E32[i - 1], eps);
-            }
-            return fermion_force_f32(ctx, t.op, (int)XX.size(), XX.data(), YY.data(), cc.data(), F);
+            src = phi32;
         }
-        if ((rc = poly(X, t.op, re, 1.0, phi, E[n - 1], E.data()))) return rc;       // E[k] = eta_{k+1}
-        if ((rc = poly(X, t.op, rc_, a, phi, C[n - 1], C.data()))) return rc;        // C[k] = chi_{n-k}
+        std::vector<cd> rc_(n - 1);
+        for (int k = 0; k < n - 1; k++) rc_[k] = z[n - 1 - k];
+        if ((rc = poly(X, t.op, rc_, a, src, C[n - 1], C.data(), prec))) return rc;
+        const void *eta = src;
         for (int i = 1; i <= n; i++) {
-            void *eta = E[i - 1], *chi = C[n - i];
-            if ((rc = applyM(X, t.op, 0, eta, WE[i - 1]))) return rc;
-            if ((rc = applyM(X, t.op, 0, chi, WC[i - 1]))) return rc;
-            pair(WE[i - 1], chi, eps);
-            pair(WC[i - 1], eta, eps);
+            const int q = (i - 1) % R;
+            if (i > 1) {
+                std::vector<cd> one{std::conj(z[i - 2])};
+                if ((rc = poly(X, t.op, one, 1.0, eta, E[q], nullptr, prec))) return rc;
+                eta = E[q];
+            }
+            const void *chi = C[n - i];
+            if ((rc = applyM(X, t.op, 0, eta, WE[q], prec))) return rc;
+            if ((rc = applyM(X, t.op, 0, chi, WC[q], prec))) return rc;
+            pair(WE[q], chi, eps);
+            pair(WC[q], eta, eps);
+            if (q == R - 1 || i == n) {
+                rc = f32 ? fermion_force_f32(ctx, t.op, (int)XX.size(), XX.data(), YY.data(), cc.data(), F)
+                         : pfmp_fermion_force(ctx, t.op, (int)XX.size(), XX.data(), YY.data(), cc.data(), 0, F);
+                if (rc) return rc;
+                XX.clear();
+                YY.clear();
+                cc.clear();
+            }
         }
-        return pfmp_fermion_force(ctx, t.op, (int)XX.size(), XX.data(), YY.data(), cc.data(), 0, F);
+        return 0;
     }
     case PFMP_TERM_POLYCORR: {
         std::vector<cd> z;
         double a;
         roots_of(t, z, a);
         z.push_back(0.0);
-        const int m = (int)z.size();
         std::vector<cd> r = residues(z);
-        std::vector<double2 *> xs(m), wx(m);
-        for (int k = 0; k < m; k++) {
-            xs[k] = pool_get(ctx, kChain + k);
-            wx[k] = pool_get(ctx, kChain + m + k);
-            if (!xs[k] || !wx[k]) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+        const auto groups = pole_groups(ctx, z, true);
+        size_t G = 0;
+        for (const auto &grp : groups) G = std::max(G, grp.size());
+        for (const std::vector<int> &grp : groups) {
+            const int m = (int)grp.size();
+            std::vector<cd> zg(m);
+            std::vector<double2 *> xs(m), wx(m);
+            std::vector<int> slot(z.size(), -1);
+            for (int q = 0; q < m; q++) {
+                zg[q] = z[grp[q]];
+                slot[grp[q]] = q;
+                xs[q] = pool_get(ctx, kChain + q);
+                wx[q] = pool_get(ctx, kChain + (int)G + q);
+                if (!xs[q] || !wx[q]) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+            }
+            // the pole z = 0 is the last one; a presolved x for it belongs to its group only
+            const bool has0 = slot[z.size() - 1] >= 0;
+            if ((rc = msolve(X, t.op, zg, phi, xs, has0 ? presolved : nullptr))) return rc;
+            for (int q = 0; q < m; q++)
+                if ((rc = applyM(X, t.op, 0, xs[q], wx[q]))) return rc;
+            XX.clear();
+            YY.clear();
+            cc.clear();
+            for (int q = 0; q < m; q++) {
+                const int i = grp[q], j = slot[partner(z, i)];
+                cd c = -eps * r[i] / a;
+                // Re[c x_j^dag dJ x_i]
+                pair(wx[j], xs[q], c);
+                pair(wx[q], xs[j], std::conj(c));
+            }
+            if ((rc = pfmp_fermion_force(ctx, t.op, (int)XX.size(), XX.data(), YY.data(), cc.data(), 0, F)))
+                return rc;
         }
-        if ((rc = msolve(X, t.op, z, phi, xs, presolved))) return rc;
-        for (int k = 0; k < m; k++)
-            if ((rc = applyM(X, t.op, 0, xs[k], wx[k]))) return rc;
-        for (int i = 0; i < m; i++) {
-            int j = partner(z, i);
-            cd c = -eps * r[i] / a;
-            // Re[c x_j^dag dJ x_i]
-            pair(wx[j], xs[i], c);
-            pair(wx[i], xs[j], std::conj(c));
-        }
-        return pfmp_fermion_force(ctx, t.op, (int)XX.size(), XX.data(), YY.data(), cc.data(), 0, F);
+        return 0;
     }
     case PFMP_TERM_RATIO: {
         double2 *t0 = pool_get(ctx, kTmp), *x = pool_get(ctx, kTmp + 1), *mx = pool_get(ctx, kTmp + 2);
@@ -529,6 +593,7 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
     double *F = (double *)ws_alloc(ctx, sizeof(double) * mom_reals(ctx->g), 24);
     if (!F) return set_err(ctx, PFMP_ERR_OOM, "force buffer");
     const double tick = sp->tau / (double)L;
+    const auto t_md = std::chrono::steady_clock::now();
     if (st) {
         st->nsteps = nout;
         for (int j = 0; j < nt; j++) st->nforce[j] = 0;
@@ -668,6 +733,15 @@ static int md_evolve(Ctx &X, double *P, const void *const *phi, pfmp_traj_stats 
         }
         if ((rc = clover_force_flush(ctx, F))) return rc;
         if ((rc = pfmp_update_momenta(ctx, 1.0, F, P))) return rc;
+        if (ctx->verbose) {
+            std::string rows;
+            for (int j = 0; j < nrow; j++)
+                if (So[(size_t)j * cap + k] != 0.0) rows += (rows.empty() ? "" : ",") + std::to_string(j);
+            std::fprintf(stderr, "[pfmp] md step %d/%d rows %s: %lld solver iterations so far, %.1f s\n", k + 1, nout,
+                         rows.c_str(), X.iters,
+                         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_md).count());
+            std::fflush(stderr);
+        }
     }
     return 0;
 }
@@ -727,10 +801,18 @@ extern "C" int pfmp_trajectory(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const d
     std::vector<void *> phi(spec->nterms);
     for (int j = 0; j < spec->nterms; j++)
         if (!(phi[j] = pool_get(ctx, j))) return set_err(ctx, PFMP_ERR_OOM, "hmc pool");
+    auto phase = [&](const char *what) {
+        if (!ctx->verbose) return;
+        std::fprintf(stderr, "[pfmp] trajectory: %s, %lld solver iterations, %.1f s\n", what, X.iters,
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+        std::fflush(stderr);
+    };
     for (int j = 0; j < spec->nterms; j++)
         if ((rc = term_heatbath(X, spec->terms[j], eta[j], phi[j]))) return rc;
+    phase("heatbath done");
     double p0[PFMP_MAX_TERMS + 3] = {0}, p1[PFMP_MAX_TERMS + 3] = {0};
     if ((rc = hamiltonian(X, P, phi.data(), p0, spec->exact_start != 0))) return rc;
+    phase("H0 done");
     if (!spec->exact_start)
         for (int j = 0; j < spec->nterms; j++) {
             p0[3 + j] = dot(X, eta[j], eta[j], rc).real();
@@ -738,7 +820,9 @@ extern "C" int pfmp_trajectory(pfmp_ctx *ctx, const pfmp_hmc_spec *spec, const d
         }
     pfmp_traj_stats loc{};
     if ((rc = md_evolve(X, P, phi.data(), &loc))) return rc;
+    phase("molecular dynamics done");
     if ((rc = hamiltonian(X, P, phi.data(), p1, true))) return rc;
+    phase("H1 done");
     double H0 = 0, H1 = 0;
     for (int k = 0; k < spec->nterms + 3; k++) {
         H0 += p0[k];

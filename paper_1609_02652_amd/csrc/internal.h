@@ -214,6 +214,8 @@ struct pfmp_ctx {
     std::vector<double2 *> pool;   // FP64 spinor buffers for the HMC driver, grown on demand
     bool use_graphs = true;        // solver iterations replayed as HIP graphs
     bool half_links = true;        // FP16-storage solver reads the FP16 copies of links and clover
+    int verbose = 0;               // 1: the HMC driver prints its progress to stderr
+    bool batch_multi = true;       // batched clover stencils: up to 4 rhs per lane pair sharing link loads
     // clover-force insertions of several force terms summed into one field before a single
     // clover-force pass (set by the integrator for the terms due at one merged step)
     bool clover_defer = false;

@@ -167,6 +167,7 @@ def load():
         "pfmp_hamiltonian": [vp, vp, vp, vp, vp, vp],
         "pfmp_force_norms": [vp, vp, vp, vp],
         "pfmp_set_half_links": [vp, i],
+        "pfmp_set_verbose": [vp, i],
         "pfmp_md_evolve": [vp, vp, vp, vp, vp],
         "pfmp_trajectory": [vp, vp, vp, vp, d, vp, vp],
         "pfmp_set_link_reconstruct": [vp, i],
@@ -175,7 +176,8 @@ def load():
         "pfmp_autotune": [vp, i, vp],
         "pfmp_set_graphs": [vp, i],
         "pfmp_get_link_reconstruct": [vp, vp],
-        "pfmp_apply_MdagM_batch": [vp, i, vp, vp, vp],
+        "pfmp_apply_MdagM_batch": [vp, i, vp, vp, vp, i],
+        "pfmp_set_batch_layout": [vp, i],
         "pfmp_cg_solve_batch": [vp, i, vp, vp, vp, vp, vp],
         "pfmp_ptnet_apply": [vp, vp, vp, vp],
         "pfmp_ptnet_grad": [vp, vp, i, i, vp, vp, vp, vp],
@@ -281,6 +283,10 @@ class Lattice:
         """Visit order of the operator kernels: 0 memory order, zt > 0 groups of zt z-planes."""
         self._chk(self.lib.pfmp_set_site_order(self.h, int(zt)), "set_site_order")
 
+    def verbose(self, level=1):
+        """HMC driver progress lines on stderr (one per phase and per merged fermion step)."""
+        self._chk(self.lib.pfmp_set_verbose(self.h, int(level)), "set_verbose")
+
     def half_links(self, on):
         """FP16-storage solver: FP16 copies of links and clover (True, default) or FP32 ones."""
         self._chk(self.lib.pfmp_set_half_links(self.h, int(bool(on))), "set_half_links")
@@ -385,14 +391,19 @@ class Lattice:
                                               ctypes.byref(st)), "cg_multishift")
         return xs, st.as_dict(n)
 
-    def apply_MdagM_batch(self, ops, xs, outs=None):
+    def apply_MdagM_batch(self, ops, xs, outs=None, prec=F64):
         n = len(xs)
-        outs = [self.field(zero=False) for _ in range(n)] if outs is None else outs
+        outs = [self.field(prec=prec, zero=False) for _ in range(n)] if outs is None else outs
         o = (ctypes.c_int * n)(*ops)
         ip = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
         op_ = (ctypes.c_void_p * n)(*[x.data_ptr() for x in outs])
-        self._chk(self.lib.pfmp_apply_MdagM_batch(self.h, n, o, ip, op_), "apply_MdagM_batch")
+        self._chk(self.lib.pfmp_apply_MdagM_batch(self.h, n, o, ip, op_, prec), "apply_MdagM_batch")
         return outs
+
+    def batch_layout(self, multi):
+        """Batched clover stencils: up to 4 rhs per lane pair (True, default) or one
+        workgroup per (site block, rhs)."""
+        self._chk(self.lib.pfmp_set_batch_layout(self.h, int(bool(multi))), "set_batch_layout")
 
     def cg_solve_batch(self, ops, bs, xs=None, tol=1e-10, maxiter=10000, check_every=0, prec=F64):
         n = len(bs)

@@ -20,7 +20,8 @@ generators of ``synth``.
   stability limit of the coarse steps dH grows much faster than h^4).
 * Cost: C = N_mat / P_acc (eq. cost_func) with N_mat the K-multiplications per
   trajectory; errors sqrt(2 tau_int) sigma_p / sqrt(N) (eq. error_corrected) with the
-  paper's tau_int = 12.5, propagated to C.
+  paper's tau_int = 12.5 by default, or tau_int measured on the chain itself (tau_int(),
+  self-consistent window), propagated to C.
 """
 import math
 
@@ -65,6 +66,26 @@ def corrected_error(values, tau_int=TAU_INT):
     if len(v) < 2:
         return float("nan")
     return math.sqrt(2.0 * tau_int) * float(np.std(v, ddof=1)) / math.sqrt(len(v))
+
+
+def tau_int(series, c=5.0):
+    """Integrated autocorrelation time tau_int = 1/2 + sum_{t>=1} rho(t) of a Markov-chain
+    series (the convention of eq. error_corrected: sigma = sqrt(2 tau_int) sigma_p / sqrt(N)),
+    summed up to the first window W >= c tau_int(W) (self-consistent window)."""
+    v = np.asarray(series, dtype=float)
+    n = len(v)
+    if n < 4:
+        return float("nan")
+    d = v - v.mean()
+    var = float(np.dot(d, d)) / n
+    if var == 0:
+        return 0.5
+    tau = 0.5
+    for w in range(1, n // 2):
+        tau += float(np.dot(d[:-w], d[w:])) / (n * var)
+        if w >= c * tau:
+            return tau
+    return tau
 
 
 def cost(nmat, accepts, tau_int=TAU_INT):

@@ -405,3 +405,80 @@ def test_trajectory_failure_restores_start_field():
     assert np.array_equal(U_here, fresh.get_gauge().cpu().numpy())
     assert not np.array_equal(U_here, U1)
     fresh.close()
+
+
+# The structure of the light-quark trajectory workload (48^3 x 96): a three-level filter nest
+# on the heaviest J (P_2, Q = P_8 / P_2, Q = P_26 / P_8 and the correction [J P_26(J)]^-1; the
+# degrees of the workload's nest (6, 20, 62) scaled down with the same divisibility), three
+# Hasenbusch ratios down to the target K, S_det, and four integrator scales, on 4^4 against
+# the oracle.  Slots: 0 = K (0.120), 1 = 0.110, 2 = 0.100, 3 = 0.090 (the heaviest J).
+NEST_KAPPAS = {0: 0.120, 1: 0.110, 2: 0.100, 3: 0.090}
+NEST = [_poly("poly", 3, 2, 6), _poly("polyq", 3, 8, 6, n1=2), _poly("polyq", 3, 26, 6, n1=8),
+        _poly("polycorr", 3, 26, 4), dict(kind="ratio", op=3, op2=2, steps=4),
+        dict(kind="ratio", op=2, op2=1, steps=3), dict(kind="ratio", op=1, op2=0, steps=3)]
+
+
+def _nest_oracle_term(t):
+    o = {k: v for k, v in t.items() if k not in ("op", "op2")}
+    if t["kind"] == "ratio":
+        o["kappa_num"], o["kappa_den"] = NEST_KAPPAS[t["op"]], NEST_KAPPAS[t["op2"]]
+    else:
+        o["kappa"] = NEST_KAPPAS[t["op"]]
+    return o
+
+
+def _nest_lattice(U0):
+    lat = make_lattice(U0)
+    lat.set_operator(1, NEST_KAPPAS[1], CSW)
+    lat.set_operator(2, NEST_KAPPAS[2], CSW)
+    lat.set_operator(3, NEST_KAPPAS[3], CSW)
+    return lat
+
+
+def test_filter_nest_with_three_ratios_matches_oracle(U0):
+    """One trajectory of the three-level filter nest with three Hasenbusch ratios and four
+    integrator scales: H0, dH, accept, force counts, links and momenta against the oracle."""
+    P0 = synth.gaussian_momenta(256, 500)
+    etas = [synth.gaussian_spinor(128, 510 + j) for j in range(len(NEST))]
+    ospec = dict(dims=DIMS, beta=BETA, csw=CSW, kappa=NEST_KAPPAS[0], gauge_steps=12,
+                 terms=[_nest_oracle_term(t) for t in NEST])
+    ref = hmc.trajectory(ospec, U0, P0, etas, u=0.3, tol=1e-12)
+    lat = _nest_lattice(U0)
+    sp = lat.spec(BETA, NEST, 12, det_op=0, tol=1e-12, exact_start=True)
+    Pend = lat.pack_momenta(np.zeros((256, 4, 8)))
+    st = lat.trajectory(sp, lat.pack_momenta(P0), [lat.pack_spinor(e) for e in etas], 0.3, P_end=Pend)
+    Ug = lat.get_gauge().cpu().numpy()
+    Pg = lat.unpack_momenta(Pend).cpu().numpy()
+    print("nest: dH gpu %.12f oracle %.12f, max |dU| %.2e, max |dP| %.2e" % (
+        st["dH"], ref["dH"], np.max(np.abs(Ug - ref["U"])), np.max(np.abs(Pg - ref["P"]))), flush=True)
+    assert list(st["nforce"][:len(NEST) + 1]) == list(ref["nforce"])
+    assert abs(st["H0"] - ref["H0"]) < 1e-8 * abs(ref["H0"])
+    assert abs(st["dH"] - ref["dH"]) < 1e-10
+    assert st["accept"] == ref["accept"]
+    if st["accept"]:
+        assert np.max(np.abs(Ug - ref["U"])) < 1e-10
+    assert np.max(np.abs(Pg - ref["P"])) < 1e-8
+    lat.close()
+
+
+def test_filter_nest_mixed_modes_track_fp64(U0):
+    """The same nest in the chosen mixed-precision modes (FP16-storage and FP32 inner CG with
+    FP64 reliable updates, FP32 filter-force chains; actions and the accept in FP64) and with
+    batched ratio solves: dH within the FP32 force rounding of the FP64 trajectory."""
+    from paper_1609_02652_amd.pfmp import F32, F16
+    P0 = synth.gaussian_momenta(256, 501)
+    etas = [synth.gaussian_spinor(128, 520 + j) for j in range(len(NEST))]
+    res = {}
+    for name, kw in (("f64", {}), ("f32", dict(solver_prec=F32)), ("f16", dict(solver_prec=F16)),
+                     ("f64_batch", dict(batch=True)), ("f16_batch", dict(solver_prec=F16, batch=True))):
+        lat = _nest_lattice(U0)
+        sp = lat.spec(BETA, NEST, 12, det_op=0, tol=1e-12, exact_start=True, **kw)
+        st = lat.trajectory(sp, lat.pack_momenta(P0), [lat.pack_spinor(e) for e in etas], 0.0)
+        res[name] = (st["dH"], lat.get_gauge().cpu().numpy())
+        print("nest %s: dH %.12f, iters %d" % (name, st["dH"], st["solver_iters"]), flush=True)
+        lat.close()
+    dh0, U64 = res["f64"]
+    assert res["f64_batch"][0] == dh0 and np.array_equal(res["f64_batch"][1], U64)
+    for name in ("f32", "f16", "f16_batch"):
+        assert abs(res[name][0] - dh0) < 2e-5
+        assert np.max(np.abs(res[name][1] - U64)) < 1e-6

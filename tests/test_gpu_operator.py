@@ -181,6 +181,16 @@ def test_batch_apply_matches_single(setup):
     for op, x, o in zip(opl, psis, outs):
         single = lat.apply_MdagM(op, x)
         assert torch.equal(o, single)
+    # FP32 fields, both layouts (up to 4 rhs per lane pair sharing each link load, and one
+    # workgroup per site block and rhs), five rhs (a group of 4 and a group of 1)
+    from paper_1609_02652_amd.pfmp import F32
+    p32 = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 75 + k), prec=F32) for k in range(5)]
+    ol = [0, 2, 0, 2, 2]
+    for multi in (True, False):
+        lat.batch_layout(multi)
+        for r, o in enumerate(lat.apply_MdagM_batch(ol, p32, prec=F32)):
+            assert torch.equal(o, lat.apply_MdagM(ol[r], p32[r], prec=F32)), (multi, r)
+    lat.batch_layout(True)
 
 
 def test_batch_cg(setup):
@@ -196,6 +206,12 @@ def test_batch_cg(setup):
         xs1, st1 = lat.cg_solve(op, lat.pack_spinor(b), tol=1e-11)
         assert st1["iters"] == st["iters"]
         assert torch.equal(x, xs1)
+    # the other batch layout (one workgroup per site block and rhs): the same bits
+    lat.batch_layout(False)
+    xs2, sts2 = lat.cg_solve_batch(opl, [lat.pack_spinor(b) for b in bs], tol=1e-11, check_every=6)
+    lat.batch_layout(True)
+    for x, x2, st, st2 in zip(xs, xs2, sts, sts2):
+        assert st2["iters"] == st["iters"] and torch.equal(x, x2)
 
 
 def test_batch_cg_mixed(setup):

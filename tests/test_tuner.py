@@ -87,3 +87,19 @@ def test_tune_search_reaches_the_acceptance_window(monkeypatch):
         hist, best = T.tune([1.0, 2.0], c0, ntraj=2, rounds=8)
         m = tuner.mean_dH_estimate([t[0] for t in hist[best][2]])
         assert tuner.ACC_RANGE[0] <= tuner.acceptance_from_dH(m) <= tuner.ACC_RANGE[1], (c_star, c0, T.calls)
+
+
+def test_tau_int_of_an_ar1_chain():
+    """tau_int of an AR(1) chain x_t = phi x_{t-1} + e_t is (1 + phi) / (2 (1 - phi)) in the
+    convention sigma = sqrt(2 tau_int) sigma_p / sqrt(N); uncorrelated noise gives 1/2."""
+    rng = np.random.default_rng(3)
+    for phi in (0.0, 0.5, 0.8):
+        n = 200000
+        e = rng.standard_normal(n)
+        x = np.empty(n)
+        x[0] = e[0]
+        for t in range(1, n):
+            x[t] = phi * x[t - 1] + e[t]
+        want = (1 + phi) / (2 * (1 - phi))
+        got = tuner.tau_int(x)
+        assert abs(got - want) < 0.06 * want + 0.02, (phi, got, want)
