@@ -146,12 +146,22 @@ def roofline_only(reps):
     counters of the hopping kernel."""
     import torch
     from paper_1609_02652_amd import synth
+    from paper_1609_02652_amd.pfmp import F32, F16
     out = {}
+
+    def lowprec(lt):
+        # Khat with FP32 fields and with FP16 storage (the mixed solvers' stage kernels)
+        x32 = lt.pack_spinor(synth.gaussian_spinor(lt.Vh, 1), prec=F32)
+        o32 = lt.field(prec=F32)
+        return {"Khat_f32_us": round(time_kernel(lt, lambda: lt.apply_MdagM(0, x32, out=o32, prec=F32), reps) * 1e6, 2),
+                "Khat_f16_us": round(time_kernel(lt, lambda: lt.apply_MdagM(0, x32, out=o32, prec=F16), reps) * 1e6, 2)}
+
     for dims in (DIMS, (32, 32, 32, 64)):
-        r = hop_roofline(dims, synth.random_gauge(dims, seed=5), reps=reps)
-        out["x".join(map(str, dims))] = {"hop_us": round(r["t_hop"] * 1e6, 2), "tuning": r["tune"],
-                                         "hop_GBps": round(r["bytes_hop"] / r["t_hop"] / 1e9, 1),
-                                         "hop_bytes": r["bytes_hop"], "Mhat_us": round(r["t_M"] * 1e6, 2)}
+        r = hop_roofline(dims, synth.random_gauge(dims, seed=5), reps=reps, extra=lowprec)
+        out["x".join(map(str, dims))] = dict({"hop_us": round(r["t_hop"] * 1e6, 2), "tuning": r["tune"],
+                                              "hop_GBps": round(r["bytes_hop"] / r["t_hop"] / 1e9, 1),
+                                              "hop_bytes": r["bytes_hop"], "Mhat_us": round(r["t_M"] * 1e6, 2)},
+                                             **r["extra"])
     n = 256 * 1024 * 1024 // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
@@ -787,6 +797,60 @@ def chain_bench(args):
     print(json.dumps({"chain": out}), flush=True)
 
 
+def config3_bench(args):
+    """The batched force-evaluation workload: 24^3 x 48, links relaxed from the seeded start by
+    quenched molecular dynamics at beta 5.8, kappa 0.1360, c_sw 1.6, Hasenbusch chain J(0.120)
+    K(0.130)^-1 and J(0.130) K(0.136)^-1 with the filter nest (10, 32) on J(0.120) (the nearest
+    nested degrees to the workload's 16 / 32: (10 + 1) | (32 + 1)).  One 2MN step of every term at
+    tau = 0.02 (three force evaluations of each term at the same links per scale), in four
+    forms: FP64 one solve at a time; FP64 with the CG solves due at one merged step batched;
+    the chosen mixed precision one at a time (FP16-storage CG with FP64 reliable updates); and
+    mixed batched (FP32 batched CG inside FP64 defect correction, multi-RHS stencils sharing
+    each link load).  The correction term's z = 0 pole joins the batch in the mixed modes."""
+    import torch
+    from paper_1609_02652_amd import synth
+    from paper_1609_02652_amd.pfmp import Lattice, F64, F16
+    dims = (24, 24, 24, 48)
+    lat = Lattice(dims)
+    out = {"lattice": "x".join(map(str, dims))}
+    try:
+        lat.set_gauge(synth.random_gauge(dims, seed=0))
+        spq = lat.spec(5.8, [], 32, det_op=-1)
+        for k in range(args.c3_therm):
+            lat.trajectory(spq, lat.pack_momenta(synth.gaussian_momenta(lat.V, 9800 + k)), [], 0.0)
+        plaq = 1.0 - lat.gauge_action(5.8) / (5.8 * 6 * lat.V)
+        out["thermalisation"] = {"trajectories": args.c3_therm, "gauge_steps": 32, "plaquette": round(plaq, 6)}
+        for k, kap in enumerate((0.1360, 0.1200, 0.1300)):
+            lat.set_operator(k, kap, CSW)
+        out["tuning"] = lat.autotune(0)
+        f = lambda kind, n, n1=0: dict(kind=kind, op=1, n=n, n1=n1, mu=1.2, nu=0.9, steps=1)
+        terms = [f("poly", 10), f("polyq", 32, 10), f("polycorr", 32),
+                 dict(kind="ratio", op=1, op2=2, steps=1), dict(kind="ratio", op=2, op2=0, steps=1)]
+        U0 = lat.get_gauge().clone()
+        etas = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 9900 + j)) for j in range(len(terms))]
+        phis = lat.heatbath(lat.spec(5.8, terms, 1, det_op=0, solver_prec=F16), etas)
+        modes = {"f64_one_by_one": (F64, False), "f64_batched": (F64, True),
+                 "mixed_one_by_one": (F16, False), "mixed_batched": (F16, True)}
+        for name, (prec, batch) in list(modes.items()) * 2:   # the second pass of each is kept
+            sp = lat.spec(5.8, terms, 1, det_op=0, tau=0.02, batch=batch, solver_prec=prec)
+            P = lat.pack_momenta(synth.gaussian_momenta(lat.V, 9990))
+            lat.set_gauge(U0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = lat.md_evolve(sp, P, phis)
+            torch.cuda.synchronize()
+            out[name] = {"s": round(time.perf_counter() - t0, 4), "solver_iters": st["solver_iters"],
+                         "kmults": st["kmults"]}
+            log("config3 %s: %s" % (name, out[name]))
+        out["batched_speedup_f64"] = round(out["f64_one_by_one"]["s"] / out["f64_batched"]["s"], 3)
+        out["batched_speedup_mixed"] = round(out["mixed_one_by_one"]["s"] / out["mixed_batched"]["s"], 3)
+        out["chosen_vs_plain_f64"] = round(out["f64_one_by_one"]["s"] /
+                                           min(out["mixed_one_by_one"]["s"], out["mixed_batched"]["s"]), 3)
+    finally:
+        lat.close()
+    print(json.dumps({"config3": out}), flush=True)
+
+
 # ---- the light-quark trajectory workload: 48^3 x 96, beta 5.9, kappa 0.1370, c_sw 1.6,
 # Hasenbusch masses 0.120 / 0.130 / 0.135, filter nest (6, 20, 62) on J(0.120) (the nearest
 # degrees with the nested factorisation (p1 + 1) | (p2 + 1) that the workload's 16/32/64 lack),
@@ -989,6 +1053,11 @@ def main():
     ap.add_argument("--zoo", action="store_true",
                     help="one trajectory of each of the paper's actions (PF-MP, 1MP, 2MP, 1PF, 2PF, 2PF-1MP, "
                          "1PF-2MP) in FP64 and in the chosen mixed precision")
+    ap.add_argument("--cg-lattice", help="only the CG iteration roofline (FP64, FP32, FP16 storage) on this "
+                                          "lattice, e.g. 32,32,32,64 (seeded start field; for kernel profiles)")
+    ap.add_argument("--config3", action="store_true",
+                    help="the batched force-evaluation workload at 24^3 x 48 (one 2MN step, four forms)")
+    ap.add_argument("--c3-therm", type=int, default=20, help="quenched relaxation trajectories at beta 5.8")
     ap.add_argument("--ratio-sweep", action="store_true",
                     help="<dH^2>/2 against the filter / ratio step-size ratio (nested and interleaved schedules)")
     ap.add_argument("--chain", type=int, default=0,
@@ -1036,6 +1105,18 @@ def main():
         return
     if args.config5:
         config5_bench(args)
+        return
+    if args.cg_lattice:
+        dims = tuple(int(v) for v in args.cg_lattice.split(","))
+        from paper_1609_02652_amd import synth
+        lt = make_lattice(dims, synth.random_gauge(dims, seed=5))
+        tune = lt.autotune(0)
+        r = cg_iteration_roofline(lt, lt.Vh)
+        lt.close()
+        print(json.dumps({"cg_iteration_roofline": r, "lattice": args.cg_lattice, "tuning": tune}), flush=True)
+        return
+    if args.config3:
+        config3_bench(args)
         return
     if args.ratio_sweep:
         ratio_sweep_bench(args)
