@@ -11,6 +11,7 @@
 // A^-1 from a Cholesky factorisation, whose pivots also give ln det A.
 #include <hip/hip_fp16.h>
 
+#include "hop.h"
 #include "su3.h"
 
 namespace {
@@ -66,11 +67,28 @@ __global__ __launch_bounds__(kBlock) void k_fhat(Geom g, const double2 *__restri
 
 __device__ __forceinline__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c; }   // c <= r
 
-// FP16 copy of a clover field (round to nearest), for the FP16-storage inner solver
-__global__ void k_clover_half(long n, const float *__restrict__ a, __half *__restrict__ h)
+// FP16 copy of a clover field (round to nearest), for the FP16-storage inner solver:
+// thread (i, b) packs block b of site i from the FP32 planes (6 diagonal reals, 15 complex
+// entries) into its 72-byte record of 6 H3 at h[(2 i + b) * 6]
+__global__ void k_clover_half(long Vh, const float *__restrict__ a, H3 *__restrict__ h)
 {
-    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (t < n) h[t] = __float2half_rn(a[t]);
+    const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t >= 2 * Vh) return;
+    const long i = t >> 1;
+    const int b = (int)(t & 1);
+    H3 q[6];
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+        q[0].v[k] = __floats2half2_rn(a[(long)(b * 6 + 2 * k) * Vh + i], a[(long)(b * 6 + 2 * k + 1) * Vh + i]);
+    const float2 *off = reinterpret_cast<const float2 *>(a + 12 * Vh);
+#pragma unroll
+    for (int m = 0; m < 15; m++) {
+        const float2 o = off[(long)(b * 15 + m) * Vh + i];
+        q[1 + m / 3].v[m % 3] = __floats2half2_rn(o.x, o.y);
+    }
+    H3 *rec = h + t * 6;
+#pragma unroll
+    for (int u = 0; u < 6; u++) rec[u] = q[u];
 }
 
 // Chiral block b of A at parity p from F-hat: thread (b, i).  INV = 0 stores A
@@ -245,10 +263,9 @@ int clover_build(pfmp_ctx *ctx, int op)
     hipLaunchKernelGGL(k_clover_blocks<1>, dim3(nb), dim3(kBlock), 0, ctx->stream, g, 1, ctx->Fhat, kc, s.clov[1],
                        s.clovf[1], s.ldpart, bad);
     LAUNCHCHK(ctx);
-    const long nr = clover_reals(g);
     for (int p = 0; p < 2; p++)
-        hipLaunchKernelGGL(k_clover_half, dim3(nblocks(nr, 256)), dim3(256), 0, ctx->stream, nr, s.clovf[p],
-                           (__half *)s.clovh[p]);
+        hipLaunchKernelGGL(k_clover_half, dim3(nblocks(2L * g.Vh, 256)), dim3(256), 0, ctx->stream, (long)g.Vh,
+                           s.clovf[p], (H3 *)s.clovh[p]);
     LAUNCHCHK(ctx);
     s.ld_dirty = true;
     return 0;

@@ -166,13 +166,17 @@ __global__ void k_pack_gauge(Geom g, const double2 *__restrict__ in, double2 *__
         }
 }
 
-// FP32 and FP16 copies of the links (round to nearest)
-__global__ void k_gauge_f32(long n, const double2 *__restrict__ a, float2 *__restrict__ b, __half2 *__restrict__ h)
+// FP32 and FP16 copies of the links (round to nearest).  Element k of link l (9 Vh planes
+// per link, k = 3 row + column) at site i: plane (9 l + k) Vh + i in FP64 and FP32; in the
+// FP16 copy the row is one record, half2 9 l Vh + 3 row Vh + 3 i + column.
+__global__ void k_gauge_f32(long Vh, long n, const double2 *__restrict__ a, float2 *__restrict__ b,
+                            __half2 *__restrict__ h)
 {
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t < n) {
         b[t] = make_float2((float)a[t].x, (float)a[t].y);
-        h[t] = __floats2half2_rn((float)a[t].x, (float)a[t].y);
+        const long l = t / (9 * Vh), r = t - l * 9 * Vh, k = r / Vh, i = r - k * Vh;
+        h[l * 9 * Vh + (k / 3) * 3 * Vh + 3 * i + k % 3] = __floats2half2_rn((float)a[t].x, (float)a[t].y);
     }
 }
 
@@ -344,8 +348,8 @@ int gauge_f32_ready(pfmp_ctx *ctx)
 {
     if (!ctx->uf_stale) return 0;
     long n = gauge_reals(ctx->g) / 2;
-    hipLaunchKernelGGL(k_gauge_f32, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, n, ctx->U, ctx->Uf,
-                       (__half2 *)ctx->Uh);
+    hipLaunchKernelGGL(k_gauge_f32, dim3(nblocks(n, 256)), dim3(256), 0, ctx->stream, (long)ctx->g.Vh, n, ctx->U,
+                       ctx->Uf, (__half2 *)ctx->Uh);
     LAUNCHCHK(ctx);
     ctx->uf_stale = false;
     return 0;

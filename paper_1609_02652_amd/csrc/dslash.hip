@@ -226,7 +226,7 @@ static int apply_half(pfmp_ctx *ctx, int op, int dagger, int K, const float2 *in
     const size_t hb = 4L * 12 * g.Vh + 4L * g.Vh;
     void *b0 = ws_alloc(ctx, hb, 40), *b1 = ws_alloc(ctx, hb, 41), *b2 = ws_alloc(ctx, hb, 42);
     if (!b0 || !b1 || !b2) return set_err(ctx, PFMP_ERR_OOM, "workspace");
-    auto half = [&](void *p) { return HalfField{(__half2 *)p, (float *)((char *)p + 4L * 12 * g.Vh)}; };
+    auto half = [&](void *p) { return HalfField{(H3 *)p, (float *)((char *)p + 4L * 12 * g.Vh)}; };
     HalfField hin = half(b0), htmp = half(b1), hout = half(b2);
     const bool cl = op_has_clover(s);
     const float mk2 = (float)(-s.kappa * s.kappa);
@@ -255,8 +255,8 @@ static int apply_f16(pfmp_ctx *ctx, int op, int dagger, int K, const void *in, v
     if (ctx->half_links)
         return apply_half<HalfLinks, HalfClover>(ctx, op, dagger, K, (const float2 *)in, (float2 *)out,
                                                  HalfLinks{(const __half2 *)ctx->Uh},
-                                                 HalfClover{(const __half *)s.clovh[0]},
-                                                 HalfClover{(const __half *)s.clovh[1]});
+                                                 HalfClover{(const H3 *)s.clovh[0]},
+                                                 HalfClover{(const H3 *)s.clovh[1]});
     return apply_half<const float2 *, const float *>(ctx, op, dagger, K, (const float2 *)in, (float2 *)out, ctx->Uf,
                                                      s.clovf[0], s.clovf[1]);
 }

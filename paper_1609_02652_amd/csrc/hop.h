@@ -13,11 +13,21 @@
 
 #include "internal.h"
 
-// FP16 spinor storage (one parity): 12 half2 planes [12][Vh] plus one FP32 scale per
-// site; the stored values are v / scale with scale = max |Re|, |Im| over the site's 24
-// reals (IEEE binary16, round to nearest even), arithmetic in FP32.
+// FP16 records: three half2 (12 bytes) that one lane moves with a single dwordx3 load or
+// store.  Every FP16 field is laid out in such records, so a lane issues a quarter as many
+// memory instructions as with one half2 plane per component, and each instruction carries
+// three times the bytes: the loads in flight per wave, not the bytes, bound the FP16
+// stencils on a lattice larger than the last-level cache.
+struct __attribute__((aligned(4))) H3 {
+    __half2 v[3];
+};
+
+// FP16 spinor storage (one parity): the 3 colours of spin g of site i in record
+// h[g * Vh + i] (4 x 12 B per site), then one FP32 scale per site; the stored values are
+// v / scale with scale = max |Re|, |Im| over the site's 24 reals (IEEE binary16, round to
+// nearest even), arithmetic in FP32.
 struct HalfField {
-    __half2 *h;
+    H3 *h;
     float *s;
 };
 
@@ -25,10 +35,14 @@ __device__ __forceinline__ void load_spinor(const HalfField &f, int Vh, int i, f
 {
     const float sc = f.s[i];
 #pragma unroll
-    for (int k = 0; k < 12; k++) {
-        float2 a = __half22float2(f.h[(long)k * Vh + i]);
-        float m = k < 6 ? sc : sc * gs;
-        v[k] = make_float2(a.x * m, a.y * m);
+    for (int sp = 0; sp < 4; sp++) {
+        const H3 q = f.h[(long)sp * Vh + i];
+        const float m = sp < 2 ? sc : sc * gs;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const float2 x = __half22float2(q.v[a]);
+            v[3 * sp + a] = make_float2(x.x * m, x.y * m);
+        }
     }
 }
 
@@ -40,9 +54,12 @@ __device__ __forceinline__ void store_spinor(const HalfField &f, int Vh, int i, 
     const float inv = m > 0.f ? 1.f / m : 0.f;
     f.s[i] = m;
 #pragma unroll
-    for (int k = 0; k < 12; k++) {
-        float q = k < 6 ? inv : inv * gs;
-        f.h[(long)k * Vh + i] = __floats2half2_rn(v[k].x * q, v[k].y * q);
+    for (int sp = 0; sp < 4; sp++) {
+        const float q = sp < 2 ? inv : inv * gs;
+        H3 r;
+#pragma unroll
+        for (int a = 0; a < 3; a++) r.v[a] = __floats2half2_rn(v[3 * sp + a].x * q, v[3 * sp + a].y * q);
+        f.h[(long)sp * Vh + i] = r;
     }
 }
 
@@ -124,21 +141,14 @@ __device__ __forceinline__ float2 ld_stream(const float2 *p)
 
 // Link storage: a pointer to complex planes of the arithmetic type, or the FP16 copy
 // (HalfLinks; SU(3) entries have |u| <= 1, so binary16 needs no scale) read into FP32.
-// lload / lstream fetch element idx (lstream non-temporally where the type allows);
-// lshift offsets the base.
+// lload / lstream fetch element idx of the planes (lstream non-temporally); lshift
+// offsets the base.  FP16 links (HalfLinks) keep the offsets of the complex planes of one link (9 Vh half2
+// per link), but within a link row r of site i is the record at half2 3 r Vh + 3 i.
 struct HalfLinks {
     const __half2 *p;
 };
 template <typename C> __device__ __forceinline__ C lload(const C *__restrict__ U, long idx) { return U[idx]; }
 template <typename C> __device__ __forceinline__ C lstream(const C *__restrict__ U, long idx) { return ld_stream(U + idx); }
-template <typename C> __device__ __forceinline__ C lload(const HalfLinks &U, long idx)
-{
-    return __half22float2(U.p[idx]);
-}
-template <typename C> __device__ __forceinline__ C lstream(const HalfLinks &U, long idx)
-{
-    return __half22float2(U.p[idx]);
-}
 template <typename C> __device__ __forceinline__ const C *lshift(const C *U, long off) { return U + off; }
 __device__ __forceinline__ HalfLinks lshift(const HalfLinks &U, long off) { return HalfLinks{U.p + off}; }
 
@@ -166,21 +176,19 @@ struct SpinLeg {
     __device__ __forceinline__ C raw(int k) const { return v[k]; }
     __device__ __forceinline__ decltype(C::x) scale() const { return 1; }
 };
-// FP16: raw() gives the stored values, scale() the site's factor
+// FP16: raw() gives the stored values, scale() the site's factor; the two spins are one
+// record each (k0 and k1 are multiples of 3)
 template <>
 struct SpinLeg<float2, HalfField> {
-    __half2 v[6];
+    H3 v[2];
     float s;
     __device__ __forceinline__ void load(const HalfField &f, long Vh, int j, int k0, int k1)
     {
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            v[a] = f.h[(long)(k0 + a) * Vh + j];
-            v[3 + a] = f.h[(long)(k1 + a) * Vh + j];
-        }
+        v[0] = f.h[(long)(k0 / 3) * Vh + j];
+        v[1] = f.h[(long)(k1 / 3) * Vh + j];
         s = f.s[j];
     }
-    __device__ __forceinline__ float2 raw(int k) const { return __half22float2(v[k]); }
+    __device__ __forceinline__ float2 raw(int k) const { return __half22float2(v[k / 3].v[k % 3]); }
     __device__ __forceinline__ float scale() const { return s; }
 };
 
@@ -196,16 +204,17 @@ struct LinkLeg {
     }
     __device__ __forceinline__ C get(int k) const { return u[k]; }
 };
+// FP16 links: one record per row (N / 3 rows)
 template <int N>
 struct LinkLeg<float2, HalfLinks, N> {
-    __half2 u[N];
+    H3 u[N / 3];
     template <int ST>
     __device__ __forceinline__ void load(const HalfLinks &U, long stride, long site)
     {
 #pragma unroll
-        for (int k = 0; k < N; k++) u[k] = U.p[k * stride + site];
+        for (int r = 0; r < N / 3; r++) u[r] = reinterpret_cast<const H3 *>(U.p + 3 * r * stride)[site];
     }
-    __device__ __forceinline__ float2 get(int k) const { return __half22float2(u[k]); }
+    __device__ __forceinline__ float2 get(int k) const { return __half22float2(u[k / 3].v[k % 3]); }
 };
 
 // LM (link mode): bit 0 rebuild the third row, bit 1 streaming loads
@@ -375,9 +384,13 @@ __device__ __forceinline__ void load_block(const HalfField &f, int Vh, int i, in
 {
     const float sc = hb ? f.s[i] * gs : f.s[i];
 #pragma unroll
-    for (int k = 0; k < 6; k++) {
-        float2 a = __half22float2(f.h[(long)(6 * hb + k) * Vh + i]);
-        v[k] = make_float2(a.x * sc, a.y * sc);
+    for (int h = 0; h < 2; h++) {
+        const H3 q = f.h[(long)(2 * hb + h) * Vh + i];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const float2 x = __half22float2(q.v[a]);
+            v[3 * h + a] = make_float2(x.x * sc, x.y * sc);
+        }
     }
 }
 
@@ -398,28 +411,45 @@ __device__ __forceinline__ void store_block(const HalfField &f, int Vh, int i, i
     if (hb == 0) f.s[i] = m;
     const float q = hb ? inv * gs : inv;
 #pragma unroll
-    for (int k = 0; k < 6; k++) f.h[(long)(6 * hb + k) * Vh + i] = __floats2half2_rn(v[k].x * q, v[k].y * q);
+    for (int h = 0; h < 2; h++) {
+        H3 r;
+#pragma unroll
+        for (int a = 0; a < 3; a++) r.v[a] = __floats2half2_rn(v[3 * h + a].x * q, v[3 * h + a].y * q);
+        f.h[(long)(2 * hb + h) * Vh + i] = r;
+    }
 }
 
 // out[6] = (6x6 Hermitian block b of the clover field at site i) v[6]
-// Clover storage: real planes of the arithmetic type, or the FP16 copy (HalfClover,
-// entries of A and A^-1 are O(1)) read into FP32.  Same layout: 12 diagonal planes, then
-// 30 complex upper-triangle planes.
+// Clover storage: real planes of the arithmetic type (12 diagonal planes [b * 6 + k][Vh],
+// then 30 complex upper-triangle planes [b * 15 + m][Vh]), or the FP16 copy (HalfClover,
+// entries of A and A^-1 are O(1)) read into FP32: one 72-byte record of 6 H3 per block and
+// site at p[(2 i + b) * 6], the 6 diagonal reals as 3 half2, then the 15 complex entries.
 struct HalfClover {
-    const __half *p;
+    const H3 *p;
 };
-template <typename R> __device__ __forceinline__ R cl_diag(const R *__restrict__ cl, long idx) { return cl[idx]; }
-template <typename C, typename R> __device__ __forceinline__ C cl_off(const R *__restrict__ cl, long Vh, long idx)
+template <typename R, typename C>
+__device__ __forceinline__ void clover_fetch(const R *__restrict__ cl, int Vh, int i, int b, R *d, C *o)
 {
-    return reinterpret_cast<const C *>(cl + 12L * Vh)[idx];
+#pragma unroll
+    for (int k = 0; k < 6; k++) d[k] = cl[(long)(b * 6 + k) * Vh + i];
+    const C *off = reinterpret_cast<const C *>(cl + 12L * Vh);
+#pragma unroll
+    for (int m = 0; m < 15; m++) o[m] = off[(long)(b * 15 + m) * Vh + i];
 }
-template <typename R> __device__ __forceinline__ R cl_diag(const HalfClover &cl, long idx)
+__device__ __forceinline__ void clover_fetch(const HalfClover &cl, int, int i, int b, float *d, float2 *o)
 {
-    return __half2float(cl.p[idx]);
-}
-template <typename C> __device__ __forceinline__ C cl_off(const HalfClover &cl, long Vh, long idx)
-{
-    return __half22float2(reinterpret_cast<const __half2 *>(cl.p + 12L * Vh)[idx]);
+    H3 q[6];
+    const H3 *rec = cl.p + (long)(2 * i + b) * 6;
+#pragma unroll
+    for (int u = 0; u < 6; u++) q[u] = rec[u];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const float2 x = __half22float2(q[0].v[a]);
+        d[2 * a] = x.x;
+        d[2 * a + 1] = x.y;
+    }
+#pragma unroll
+    for (int m = 0; m < 15; m++) o[m] = __half22float2(q[1 + m / 3].v[m % 3]);
 }
 
 template <typename R, typename C, typename CL>
@@ -427,10 +457,7 @@ __device__ __forceinline__ void clover_block(CL cl, int Vh, int i, int b, const 
 {
     R d[6];
     C o[15];
-#pragma unroll
-    for (int k = 0; k < 6; k++) d[k] = cl_diag<R>(cl, (long)(b * 6 + k) * Vh + i);
-#pragma unroll
-    for (int m = 0; m < 15; m++) o[m] = cl_off<C>(cl, Vh, (long)(b * 15 + m) * Vh + i);
+    clover_fetch(cl, Vh, i, b, d, o);
 #pragma unroll
     for (int r = 0; r < 6; r++) out[r] = cscale(v[r], d[r]);
     int m = 0;

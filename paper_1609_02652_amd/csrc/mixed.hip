@@ -225,9 +225,9 @@ template <> struct Store<HalfField, true> {
     using UL = HalfLinks;
     using CL = HalfClover;
     static size_t bytes(long Vh) { return 4L * 12 * Vh + 4L * Vh; }
-    static HalfField make(void *p, long Vh) { return HalfField{(__half2 *)p, (float *)((char *)p + 4L * 12 * Vh)}; }
+    static HalfField make(void *p, long Vh) { return HalfField{(H3 *)p, (float *)((char *)p + 4L * 12 * Vh)}; }
     static UL links(const pfmp_ctx *ctx) { return HalfLinks{(const __half2 *)ctx->Uh}; }
-    static CL clover(const OpSlot &s, int p) { return HalfClover{(const __half *)s.clovh[p]}; }
+    static CL clover(const OpSlot &s, int p) { return HalfClover{(const H3 *)s.clovh[p]}; }
 };
 template <> struct Store<HalfField, false> {
     using In = HalfField;

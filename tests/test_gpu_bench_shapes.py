@@ -55,3 +55,29 @@ def test_operator_sampled_at_bench_shape(dims):
         lat.half_links(1)
     finally:
         lat.close()
+
+
+def test_operator_sampled_at_light_quark_shape():
+    """The light-quark trajectory lattice, 48^3 x 96 at kappa 0.1370, c_sw 1.6 (its lightest
+    operator), on the seeded start field: the FP64 Mhat and Mhat^dag in the launch
+    configuration the autotuner picks, against the oracle on sampled output sites."""
+    from paper_1609_02652_amd.pfmp import Lattice
+    dims, kappa = (48, 48, 48, 96), 0.1370
+    print("case", dims, kappa, flush=True)
+    U = synth.random_gauge(dims, seed=0)
+    lat = Lattice(dims)
+    try:
+        lat.set_gauge(U)
+        lat.set_operator(0, kappa, CSW)
+        print("tuning", lat.autotune(0), "links rebuilt", lat.link_reconstruct(), flush=True)
+        psi = synth.gaussian_spinor(lat.Vh, 1)
+        x = lat.pack_spinor(psi)
+        rng = np.random.default_rng(4)
+        sites = np.unique(np.concatenate([[0, lat.Vh - 1], rng.choice(lat.Vh, 126, replace=False)]))
+        for dag in (False, True):
+            got = lat.spinor_numpy(lat.apply_M(0, x, dagger=dag))[sites]
+            e = rel(got, oracle.sample_sites(dims, U, kappa, CSW, psi, sites, "M", dagger=dag))
+            print("Mhat%s rel err on the samples: %.3e" % ("^dag" if dag else "", e), flush=True)
+            assert e < 1e-12
+    finally:
+        lat.close()
