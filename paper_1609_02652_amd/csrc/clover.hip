@@ -68,24 +68,24 @@ __global__ __launch_bounds__(kBlock) void k_fhat(Geom g, const double2 *__restri
 __device__ __forceinline__ constexpr int tri(int r, int c) { return r * (r + 1) / 2 + c; }   // c <= r
 
 // FP16 copy of a clover field (round to nearest), for the FP16-storage inner solver:
-// thread (i, b) packs block b of site i from the FP32 planes (6 diagonal reals, 15 complex
-// entries) into its 72-byte record of 6 H3 at h[(2 i + b) * 6]
+// thread t = 2 i + b packs the FP32 record of block b of site i (6 diagonal reals, 15
+// complex entries) into its 72-byte record of 6 H3 at h[t * 6]
 __global__ void k_clover_half(long Vh, const float *__restrict__ a, H3 *__restrict__ h)
 {
     const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t >= 2 * Vh) return;
-    const long i = t >> 1;
-    const int b = (int)(t & 1);
+    float f[36];
+    const float4 *rf = reinterpret_cast<const float4 *>(a) + t * 9;
+#pragma unroll
+    for (int u = 0; u < 9; u++) {
+        const float4 v = rf[u];
+        f[4 * u] = v.x; f[4 * u + 1] = v.y; f[4 * u + 2] = v.z; f[4 * u + 3] = v.w;
+    }
     H3 q[6];
 #pragma unroll
-    for (int k = 0; k < 3; k++)
-        q[0].v[k] = __floats2half2_rn(a[(long)(b * 6 + 2 * k) * Vh + i], a[(long)(b * 6 + 2 * k + 1) * Vh + i]);
-    const float2 *off = reinterpret_cast<const float2 *>(a + 12 * Vh);
+    for (int k = 0; k < 3; k++) q[0].v[k] = __floats2half2_rn(f[2 * k], f[2 * k + 1]);
 #pragma unroll
-    for (int m = 0; m < 15; m++) {
-        const float2 o = off[(long)(b * 15 + m) * Vh + i];
-        q[1 + m / 3].v[m % 3] = __floats2half2_rn(o.x, o.y);
-    }
+    for (int m = 0; m < 15; m++) q[1 + m / 3].v[m % 3] = __floats2half2_rn(f[6 + 2 * m], f[7 + 2 * m]);
     H3 *rec = h + t * 6;
 #pragma unroll
     for (int u = 0; u < 6; u++) rec[u] = q[u];
@@ -94,7 +94,9 @@ __global__ void k_clover_half(long Vh, const float *__restrict__ a, H3 *__restri
 // Chiral block b of A at parity p from F-hat: thread (b, i).  INV = 0 stores A
 // (even sites); INV = 1 stores A^-1 from a packed Cholesky factorisation and sums
 // ln det A into per-block partials (odd sites).  Storage: 6 real diagonal entries
-// and the 15 upper off-diagonal entries (row-major) of each block, FP64 and FP32.
+// and the 15 upper off-diagonal entries (row-major) of each block; FP64 in planes (12
+// diagonal planes [b * 6 + k][Vh], 30 complex planes [b * 15 + m][Vh]), FP32 as one record
+// of 36 floats per block and site at (2 i + b) * 36 (nine 16-byte loads).
 // Each block is 1 + i kappa c_sw [[Gz, Gx - i Gy], [Gx + i Gy, -Gz]] with
 // Gx = s F_03 - F_12, Gy = s F_13 + F_02, Gz = s F_23 - F_01, s = +1 (b = 0) / -1 (b = 1).
 template <int INV>
@@ -134,19 +136,19 @@ __global__ __launch_bounds__(kBlock) void k_clover_blocks(Geom g, int p, const d
 
         double *dg = out + (long)(b * 6) * Vh + i;
         double2 *off = reinterpret_cast<double2 *>(out + 12L * Vh) + (long)(b * 15) * Vh + i;
-        float *dgf = outf + (long)(b * 6) * Vh + i;
-        float2 *offf = reinterpret_cast<float2 *>(outf + 12L * Vh) + (long)(b * 15) * Vh + i;
+        float rec[36];   // the FP32 record of the block: 6 diagonal reals, 15 complex entries
         if (!INV) {
             int m = 0;
 #pragma unroll
             for (int r = 0; r < 6; r++) {
                 dg[(long)r * Vh] = a[tri(r, r)].x;
-                dgf[(long)r * Vh] = (float)a[tri(r, r)].x;
+                rec[r] = (float)a[tri(r, r)].x;
 #pragma unroll
                 for (int q = r + 1; q < 6; q++, m++) {
                     double2 v = cconj(a[tri(q, r)]);
                     off[(long)m * Vh] = v;
-                    offf[(long)m * Vh] = make_float2((float)v.x, (float)v.y);
+                    rec[6 + 2 * m] = (float)v.x;
+                    rec[7 + 2 * m] = (float)v.y;
                 }
             }
         } else {
@@ -197,15 +199,19 @@ __global__ __launch_bounds__(kBlock) void k_clover_blocks(Geom g, int p, const d
                     y[r] = cscale(v, 1.0 / a[tri(r, r)].x);
                 }
                 dg[(long)c * Vh] = y[c].x;
-                dgf[(long)c * Vh] = (float)y[c].x;
+                rec[c] = (float)y[c].x;
 #pragma unroll
                 for (int r = 0; r < c; r++) {
                     const int m = r * 5 - r * (r - 1) / 2 + (c - r - 1);   // index of (r, c), r < c
                     off[(long)m * Vh] = y[r];
-                    offf[(long)m * Vh] = make_float2((float)y[r].x, (float)y[r].y);
+                    rec[6 + 2 * m] = (float)y[r].x;
+                    rec[7 + 2 * m] = (float)y[r].y;
                 }
             }
         }
+        float4 *rf = reinterpret_cast<float4 *>(outf) + (2L * i + b) * 9;
+#pragma unroll
+        for (int u = 0; u < 9; u++) rf[u] = make_float4(rec[4 * u], rec[4 * u + 1], rec[4 * u + 2], rec[4 * u + 3]);
     }
     if (INV) {
         __shared__ double sh[kBlock / 64];

@@ -166,17 +166,19 @@ __global__ void k_pack_gauge(Geom g, const double2 *__restrict__ in, double2 *__
         }
 }
 
-// FP32 and FP16 copies of the links (round to nearest).  Element k of link l (9 Vh planes
-// per link, k = 3 row + column) at site i: plane (9 l + k) Vh + i in FP64 and FP32; in the
-// FP16 copy the row is one record, half2 9 l Vh + 3 row Vh + 3 i + column.
+// FP32 and FP16 copies of the links, each the FP64 value rounded once to nearest (the FP16
+// copy is not rounded through FP32).  Element k of link l (9 Vh planes per link, k = 3 row +
+// column) at site i: plane (9 l + k) Vh + i in FP64; in the FP32 and FP16 copies the row is
+// one record, complex 9 l Vh + 3 row Vh + 3 i + column.
 __global__ void k_gauge_f32(long Vh, long n, const double2 *__restrict__ a, float2 *__restrict__ b,
                             __half2 *__restrict__ h)
 {
     long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (t < n) {
-        b[t] = make_float2((float)a[t].x, (float)a[t].y);
         const long l = t / (9 * Vh), r = t - l * 9 * Vh, k = r / Vh, i = r - k * Vh;
-        h[l * 9 * Vh + (k / 3) * 3 * Vh + 3 * i + k % 3] = __floats2half2_rn((float)a[t].x, (float)a[t].y);
+        const long o = l * 9 * Vh + (k / 3) * 3 * Vh + 3 * i + k % 3;
+        b[o] = make_float2((float)a[t].x, (float)a[t].y);
+        h[o] = __half2{_Float16_2{static_cast<_Float16>(a[t].x), static_cast<_Float16>(a[t].y)}};
     }
 }
 

@@ -139,11 +139,12 @@ __device__ __forceinline__ float2 ld_stream(const float2 *p)
     return make_float2(v.x, v.y);
 }
 
-// Link storage: a pointer to complex planes of the arithmetic type, or the FP16 copy
-// (HalfLinks; SU(3) entries have |u| <= 1, so binary16 needs no scale) read into FP32.
-// lload / lstream fetch element idx of the planes (lstream non-temporally); lshift
-// offsets the base.  FP16 links (HalfLinks) keep the offsets of the complex planes of one link (9 Vh half2
-// per link), but within a link row r of site i is the record at half2 3 r Vh + 3 i.
+// Link storage: a pointer to complex planes of the arithmetic type (FP64), the FP32 copy or the
+// FP16 copy (HalfLinks; SU(3) entries have |u| <= 1, so binary16 needs no scale) read into
+// FP32.  lload / lstream fetch element idx of the planes (lstream non-temporally); lshift
+// offsets the base.  Both copies keep the offsets of the complex planes of one link (9 Vh
+// complex per link), but within a link row r of site i is the record of 3 complex at complex
+// 3 r Vh + 3 i (24 bytes in FP32, 12 in FP16).
 struct HalfLinks {
     const __half2 *p;
 };
@@ -203,6 +204,30 @@ struct LinkLeg {
         for (int k = 0; k < N; k++) u[k] = ST ? lstream<C>(U, k * stride + site) : lload<C>(U, k * stride + site);
     }
     __device__ __forceinline__ C get(int k) const { return u[k]; }
+};
+// FP32 links: one 24-byte record per row (a dwordx4 and a dwordx2 load), or with streaming
+// loads (ST) three non-temporal complex loads per row
+struct __attribute__((aligned(8))) F3 {
+    float2 v[3];
+};
+template <int N>
+struct LinkLeg<float2, const float2 *, N> {
+    F3 u[N / 3];
+    template <int ST>
+    __device__ __forceinline__ void load(const float2 *U, long stride, long site)
+    {
+#pragma unroll
+        for (int r = 0; r < N / 3; r++) {
+            const F3 *row = reinterpret_cast<const F3 *>(U + 3 * r * stride) + site;
+            if (ST) {
+#pragma unroll
+                for (int c = 0; c < 3; c++) u[r].v[c] = ld_stream(row->v + c);
+            } else {
+                u[r] = *row;
+            }
+        }
+    }
+    __device__ __forceinline__ float2 get(int k) const { return u[k / 3].v[k % 3]; }
 };
 // FP16 links: one record per row (N / 3 rows)
 template <int N>
@@ -420,8 +445,9 @@ __device__ __forceinline__ void store_block(const HalfField &f, int Vh, int i, i
 }
 
 // out[6] = (6x6 Hermitian block b of the clover field at site i) v[6]
-// Clover storage: real planes of the arithmetic type (12 diagonal planes [b * 6 + k][Vh],
-// then 30 complex upper-triangle planes [b * 15 + m][Vh]), or the FP16 copy (HalfClover,
+// Clover storage: FP64 real planes (12 diagonal planes [b * 6 + k][Vh], then 30 complex
+// upper-triangle planes [b * 15 + m][Vh]); the FP32 copy as one 144-byte record per block
+// and site (6 diagonal reals, then the 15 complex entries); or the FP16 copy (HalfClover,
 // entries of A and A^-1 are O(1)) read into FP32: one 72-byte record of 6 H3 per block and
 // site at p[(2 i + b) * 6], the 6 diagonal reals as 3 half2, then the 15 complex entries.
 struct HalfClover {
@@ -435,6 +461,22 @@ __device__ __forceinline__ void clover_fetch(const R *__restrict__ cl, int Vh, i
     const C *off = reinterpret_cast<const C *>(cl + 12L * Vh);
 #pragma unroll
     for (int m = 0; m < 15; m++) o[m] = off[(long)(b * 15 + m) * Vh + i];
+}
+// FP32 clover: one record of 36 floats per block and site at (2 i + b) * 36, read as nine
+// 16-byte loads
+__device__ __forceinline__ void clover_fetch(const float *__restrict__ cl, int, int i, int b, float *d, float2 *o)
+{
+    float f[36];
+    const float4 *rf = reinterpret_cast<const float4 *>(cl) + (2L * i + b) * 9;
+#pragma unroll
+    for (int u = 0; u < 9; u++) {
+        const float4 v = rf[u];
+        f[4 * u] = v.x; f[4 * u + 1] = v.y; f[4 * u + 2] = v.z; f[4 * u + 3] = v.w;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k++) d[k] = f[k];
+#pragma unroll
+    for (int m = 0; m < 15; m++) o[m] = make_float2(f[6 + 2 * m], f[7 + 2 * m]);
 }
 __device__ __forceinline__ void clover_fetch(const HalfClover &cl, int, int i, int b, float *d, float2 *o)
 {

@@ -39,16 +39,17 @@ __device__ __forceinline__ void load_T(const Geom &g, const float2 *__restrict__
                                        float2 *u, float *sgn)
 {
     const int mu = d >> 1;
+    // FP32 link copy: row r of a link at site i is the record of 3 complex at 3 r Vh + 3 i
     if ((d & 1) == 0) {
-        const float2 *b = U + ((long)(p * 4 + mu) * 9) * g.Vh + i;
-        for (int k = 0; k < 9; k++) u[k] = b[(long)k * g.Vh];
+        const float2 *b = U + ((long)(p * 4 + mu) * 9) * g.Vh + 3L * i;
+        for (int k = 0; k < 9; k++) u[k] = b[(long)(k / 3) * 3 * g.Vh + k % 3];
         *sgn = (mu == 3 && c[3] == g.L[3] - 1) ? (float)g.tbc : 1.f;
     } else {
         int s;
         int j = eo_neighbour(g, c, mu, -1, &s);
-        const float2 *b = U + ((long)((1 - p) * 4 + mu) * 9) * g.Vh + j;
+        const float2 *b = U + ((long)((1 - p) * 4 + mu) * 9) * g.Vh + 3L * j;
         for (int a = 0; a < 3; a++)
-            for (int bb = 0; bb < 3; bb++) u[3 * a + bb] = fconj(b[(long)(3 * bb + a) * g.Vh]);
+            for (int bb = 0; bb < 3; bb++) u[3 * a + bb] = fconj(b[(long)bb * 3 * g.Vh + a]);
         *sgn = (float)s;
     }
 }
