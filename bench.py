@@ -70,11 +70,11 @@ def time_kernel(lat, fn, reps):
 
 
 def batch_apply(lat, reps=20):
-    """4-RHS Khat (one multi-RHS launch per stage) against 4 single-RHS Khat in FP64 and FP32,
-    for 4 sources of one operator and for the Hasenbusch chain's operators (kappa 0.1340,
-    0.1300, 0.1250, 0.1340), in the multi-rhs layout (each link load shared by the 4 rhs of a
-    lane pair) and in the workgroup-per-rhs layout: time per right-hand side relative to a
-    single one."""
+    """4-RHS Khat against 4 single-RHS Khat in FP64 and FP32, for 4 sources of one operator and
+    for the Hasenbusch chain's operators (kappa 0.1340, 0.1300, 0.1250, 0.1340), in the
+    multi-rhs layout (each link load shared by the rhs of a lane pair: the default group of 4,
+    and groups of 2) and in the workgroup-per-rhs layout: time per right-hand side relative to
+    a single one."""
     from paper_1609_02652_amd import synth
     from paper_1609_02652_amd.pfmp import F64, F32
     lat.set_operator(2, 0.1250, CSW)
@@ -84,10 +84,10 @@ def batch_apply(lat, reps=20):
         outs = [lat.field(prec=prec) for _ in range(4)]
         t1 = time_kernel(lat, lambda: lat.apply_MdagM(0, xs[0], out=outs[0], prec=prec), reps)
         for oname, ops in (("same_op", [0, 0, 0, 0]), ("chain", [0, 1, 2, 0])):
-            for multi in (True, False):
+            for multi, lname in ((1, "multi"), (2, "multi2"), (0, "wg")):
                 lat.batch_layout(multi)
                 t4 = time_kernel(lat, lambda: lat.apply_MdagM_batch(ops, xs, outs, prec=prec), reps)
-                res["%s_%s_%s" % (pname, oname, "multi" if multi else "wg")] = {
+                res["%s_%s_%s" % (pname, oname, lname)] = {
                     "single_K_us": round(t1 * 1e6, 1), "batch_K_us": round(t4 * 1e6, 1),
                     "per_rhs_vs_single": round(t4 / 4 / t1, 3)}
         lat.batch_layout(True)

@@ -114,9 +114,10 @@ int pfmp_set_link_reconstruct(pfmp_ctx *ctx, int allow);
  * t-slice, then the same planes of the next t-slice, and so on, so that the t
  * neighbours of a group are still in L2 when they are reused. */
 int pfmp_set_site_order(pfmp_ctx *ctx, int zt);
-/* Streaming (non-temporal) link loads in the hopping kernels: on = 1 keeps the links,
+/* Streaming (non-temporal) link loads in the FP64 hopping kernels: on = 1 keeps the links,
  * read once per launch, from displacing the neighbour spinors in the caches.  The
- * default is on when the FP64 gauge field exceeds 128 MiB. */
+ * default is on when the FP64 gauge field exceeds 128 MiB.  The FP32 and FP16 link copies
+ * (records) are always read with cached loads. */
 int pfmp_set_link_streaming(pfmp_ctx *ctx, int on);
 typedef struct {
     int zt;          /* chosen site visit order (pfmp_set_site_order) */
@@ -235,8 +236,10 @@ int pfmp_cg_multishift(pfmp_ctx *ctx, int op, int nshift, const double *z, const
  * PFMP_F64 or PFMP_F32 internal spinors (FP32: FP32 links and clover). */
 int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, const void *const *in, void *const *out,
                            int prec);
-/* layout of the batched clover stencils (apply and CG): 1 (default) up to 4 rhs per lane pair
- * sharing each link load; 0 one workgroup per (site block, rhs).  Same results. */
+/* layout of the batched clover stencils (apply and CG): 1 (default) the default group of rhs
+ * per lane pair sharing each link load (4); 2 or 4 groups of that many rhs per lane pair;
+ * 0 one workgroup per (site block, rhs).  Same results in every layout.  Other values:
+ * PFMP_ERR_ARG. */
 int pfmp_set_batch_layout(pfmp_ctx *ctx, int multi);
 /* CG for Khat_{ops[r]} x_r = b_r, r < nrhs <= 8, all iterated in the same launches;
  * a converged right-hand side stops.  b, x: FP64 internal spinors; st: nrhs records.

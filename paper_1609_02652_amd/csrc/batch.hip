@@ -217,6 +217,17 @@ __device__ __forceinline__ void rhs_active(const double *__restrict__ st, int r0
     for (int q = 0; q < NR; q++) act[q] = !st || st[8 * (r0 + q) + B_DONE] == 0;
 }
 
+// the clover blocks of a launch's rhs: fetched once when every rhs of the launch uses the same
+// field (one operator), else per rhs (uniform in the workgroup)
+template <int NR, typename R>
+__device__ __forceinline__ bool clover_shared(const R *const *cl, int r0)
+{
+    bool same = true;
+#pragma unroll
+    for (int q = 1; q < NR; q++) same = same && cl[r0 + q] == cl[r0];
+    return same;
+}
+
 template <int MU, int DIR, int LM, int NR, typename C, typename UL>
 __device__ __forceinline__ void legs_multi(const Geom &g, int pout, int i, const int *c, int hb,
                                            const C *const *in, UL U, decltype(C::x) gs, const bool *act,
@@ -289,12 +300,17 @@ __global__ __launch_bounds__(kBlock) void k_bm_clovinv(Geom g, BatchT<R> b, Vecs
     const int i = tile_site(g, tt >> 1), hb = tt & 1;
     C blk[NR][6];
     hop_multi<LM, NR>(g, 1, i, hb, v.in + r0, U, gin, act, blk);
+    const bool same = clover_shared<NR>(b.clo, r0);
+    R d[6];
+    C o[15];
+    if (CLOV && same) clover_fetch(b.clo[r0], g.Vh, i, hb, d, o);
 #pragma unroll
     for (int q = 0; q < NR; q++) {
         if (!act[q]) continue;
         if (CLOV) {
             C tq[6];
-            clover_block<R, C>(b.clo[r0 + q], g.Vh, i, hb, blk[q], tq);
+            if (!same) clover_fetch(b.clo[r0 + q], g.Vh, i, hb, d, o);
+            clover_mul(d, o, blk[q], tq);
             store_block(v.out[r0 + q], g.Vh, i, hb, gout, tq);
         } else {
             store_block(v.out[r0 + q], g.Vh, i, hb, gout, blk[q]);
@@ -318,12 +334,19 @@ __global__ __launch_bounds__(kBlock) void k_bm_xpay(Geom g, BatchT<R> b, VecsT<C
         const int i = tile_site(g, tt >> 1), hb = tt & 1;
         C acc[NR][6];
         hop_multi<LM, NR>(g, 0, i, hb, t.in + r0, U, (R)1, act, acc);
+        const bool same = clover_shared<NR>(b.cle, r0);
+        R d[6];
+        C o[15];
+        if (CLOV && same) clover_fetch(b.cle[r0], g.Vh, i, hb, d, o);
 #pragma unroll
         for (int q = 0; q < NR; q++) {
             if (!act[q]) continue;
             C xv[6], ax[6];
             load_block(x.in[r0 + q], g.Vh, i, hb, gs, xv);
-            if (CLOV) clover_block<R, C>(b.cle[r0 + q], g.Vh, i, hb, xv, ax);
+            if (CLOV) {
+                if (!same) clover_fetch(b.cle[r0 + q], g.Vh, i, hb, d, o);
+                clover_mul(d, o, xv, ax);
+            }
             const R a = b.a[r0 + q];
 #pragma unroll
             for (int k = 0; k < 6; k++) {
@@ -361,6 +384,10 @@ __global__ __launch_bounds__(kBlock) void k_bm_hop4(Geom g, BatchT<R> b, VecsT<C
         C acc[NR][6];
         hop_multi<LM, NR>(g, 0, i, hb, T.in + r0, U, (R)1, act, acc);
         const long Vh = g.Vh;
+        const bool same = clover_shared<NR>(b.cle, r0);
+        R d[6];
+        C o[15];
+        if (CLOV && same) clover_fetch(b.cle[r0], g.Vh, i, hb, d, o);
 #pragma unroll
         for (int q = 0; q < NR; q++) {
             if (!act[q]) continue;
@@ -368,7 +395,10 @@ __global__ __launch_bounds__(kBlock) void k_bm_hop4(Geom g, BatchT<R> b, VecsT<C
             const double *s = st + 8 * r;
             C tv[6], at[6];
             load_block(t.in[r], g.Vh, i, hb, (R)-1, tv);
-            if (CLOV) clover_block<R, C>(b.cle[r], g.Vh, i, hb, tv, at);
+            if (CLOV) {
+                if (!same) clover_fetch(b.cle[r], g.Vh, i, hb, d, o);
+                clover_mul(d, o, tv, at);
+            }
             const R alpha = (R)(s[B_RR] / s[B_PAP]), a = b.a[r];
             const C *pp = p.in[r];
             C *xx = x.out[r], *rv_ = rr.out[r];
@@ -445,7 +475,13 @@ __global__ void k_b_accum(long n, double s, const float2 *__restrict__ e, double
         default: BM_LM(K, C, R, 4, grid, __VA_ARGS__); break; \
         }                                                   \
     } while (0)
-constexpr int kMultiRhs = 4;   // right-hand sides per lane pair in the multi-rhs layout
+// right-hand sides per lane pair in the multi-rhs layout (at most 4): the context's choice, or
+// by default 4 in FP32 and FP64
+template <typename R>
+static int multi_group(const pfmp_ctx *ctx)
+{
+    return ctx->batch_multi == 2 || ctx->batch_multi == 4 ? ctx->batch_multi : 4;
+}
 
 // the multi-rhs layout (each link load shared by up to 4 rhs in a lane) for clover batches
 // unless switched off (pfmp_set_batch_layout)
@@ -512,8 +548,9 @@ static int apply_batch(pfmp_ctx *ctx, const BatchT<R> &b, const C *U, int nrhs, 
     // Mhat in -> te (stage 1 to to, stage 2 to te), then Mhat^dag te -> out
     if (use_multi(ctx, b)) {
         dim3 grid(op_nparts(g));
-        for (int r0 = 0; r0 < nrhs; r0 += kMultiRhs) {
-            const int nr = std::min(kMultiRhs, nrhs - r0);
+        const int mg = multi_group<R>(ctx);
+        for (int r0 = 0; r0 < nrhs; r0 += mg) {
+            const int nr = std::min(mg, nrhs - r0);
             BMLAUNCH(k_bm_clovinv, C, R, nr, grid, g, b, in_to, U, (R)1, (R)1, (const double *)nullptr, r0);
             BMLAUNCH(k_bm_xpay, C, R, nr, grid, g, b, in_te, to_in, U, (R)1, (const double *)nullptr,
                      (double *)nullptr, r0);
@@ -554,7 +591,9 @@ extern "C" int pfmp_apply_MdagM_batch(pfmp_ctx *ctx, int nrhs, const int *ops, c
 extern "C" int pfmp_set_batch_layout(pfmp_ctx *ctx, int multi)
 {
     if (!ctx) return PFMP_ERR_ARG;
-    ctx->batch_multi = multi != 0;
+    if (multi != 0 && multi != 1 && multi != 2 && multi != 4)
+        return set_err(ctx, PFMP_ERR_ARG, "batch layout: 0, 1, 2 or 4");
+    ctx->batch_multi = multi;
     return 0;
 }
 
@@ -607,17 +646,18 @@ static int batch_cg_core(pfmp_ctx *ctx, const BatchT<R> &b, const void *const *b
     const C *U = sizeof(R) == 8 ? (const C *)ctx->U : (const C *)ctx->Uf;
     int chunk = check_every > 0 ? check_every : 25;
     const bool multi = use_multi(ctx, b);
+    const int mg = multi_group<R>(ctx);
     dim3 gridm(op_nparts(g));
     // one iteration for all rhs: 7 launches with fixed arguments (4 more per further group of
     // 4 rhs in the multi-rhs layout), replayed as a graph; each rhs takes the single-RHS CG's
     // steps in its arithmetic and summation order
     auto iteration = [&]() -> int {
         if (multi) {
-            for (int r0 = 0; r0 < nrhs; r0 += kMultiRhs)
-                BMLAUNCH(k_bm_clovinv, C, R, std::min(kMultiRhs, nrhs - r0), gridm, g, b, p_to_T2, U, (R)1, (R)1,
+            for (int r0 = 0; r0 < nrhs; r0 += mg)
+                BMLAUNCH(k_bm_clovinv, C, R, std::min(mg, nrhs - r0), gridm, g, b, p_to_T2, U, (R)1, (R)1,
                          (const double *)sc, r0);
-            for (int r0 = 0; r0 < nrhs; r0 += kMultiRhs)
-                BMLAUNCH(k_bm_xpay, C, R, std::min(kMultiRhs, nrhs - r0), gridm, g, b, p_to_T1, vT2, U, (R)1,
+            for (int r0 = 0; r0 < nrhs; r0 += mg)
+                BMLAUNCH(k_bm_xpay, C, R, std::min(mg, nrhs - r0), gridm, g, b, p_to_T1, vT2, U, (R)1,
                          (const double *)sc, part_a, r0);
         } else {
             BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, p_to_T2, U, (R)1, (R)1, sc);
@@ -626,11 +666,11 @@ static int batch_cg_core(pfmp_ctx *ctx, const BatchT<R> &b, const void *const *b
         hipLaunchKernelGGL(k_b_pap, dim3(1), dim3(kFinishThreads), 0, ctx->stream, part_a, b.nsb, b.pstride, nrhs,
                            sc);
         if (multi) {
-            for (int r0 = 0; r0 < nrhs; r0 += kMultiRhs)
-                BMLAUNCH(k_bm_clovinv, C, R, std::min(kMultiRhs, nrhs - r0), gridm, g, b, T1_to_T2, U, (R)-1, (R)1,
+            for (int r0 = 0; r0 < nrhs; r0 += mg)
+                BMLAUNCH(k_bm_clovinv, C, R, std::min(mg, nrhs - r0), gridm, g, b, T1_to_T2, U, (R)-1, (R)1,
                          (const double *)sc, r0);
-            for (int r0 = 0; r0 < nrhs; r0 += kMultiRhs)
-                BMLAUNCH(k_bm_hop4, C, R, std::min(kMultiRhs, nrhs - r0), gridm, g, b, vT1, vT2, vP, vX, vR, U,
+            for (int r0 = 0; r0 < nrhs; r0 += mg)
+                BMLAUNCH(k_bm_hop4, C, R, std::min(mg, nrhs - r0), gridm, g, b, vT1, vT2, vP, vX, vR, U,
                          (const double *)sc, part_b, r0);
         } else {
             BLAUNCH(k_b_clovinv, C, R, b, grid, block, 0, ctx->stream, g, b, T1_to_T2, U, (R)-1, (R)1, sc);
@@ -658,6 +698,7 @@ static int batch_cg_core(pfmp_ctx *ctx, const BatchT<R> &b, const void *const *b
         key_add(key, ptr);
     key_add(key, b.clov[0]);
     key_add(key, (int)multi);
+    key_add(key, mg);
     for (;;) {
         bool all = true;
         for (int r = 0; r < nrhs; r++) all = all && init[8 * r + B_DONE] != 0;

@@ -205,8 +205,9 @@ struct LinkLeg {
     }
     __device__ __forceinline__ C get(int k) const { return u[k]; }
 };
-// FP32 links: one 24-byte record per row (a dwordx4 and a dwordx2 load), or with streaming
-// loads (ST) three non-temporal complex loads per row
+// FP32 links: one 24-byte record per row (a dwordx4 and a dwordx2 load).  The loads stay
+// cached in every link mode: at 32^3 x 64 non-temporal record loads made the FP32 CG
+// iteration 4 % and the FP16-storage one with FP32 links 5 % slower than cached ones.
 struct __attribute__((aligned(8))) F3 {
     float2 v[3];
 };
@@ -217,15 +218,7 @@ struct LinkLeg<float2, const float2 *, N> {
     __device__ __forceinline__ void load(const float2 *U, long stride, long site)
     {
 #pragma unroll
-        for (int r = 0; r < N / 3; r++) {
-            const F3 *row = reinterpret_cast<const F3 *>(U + 3 * r * stride) + site;
-            if (ST) {
-#pragma unroll
-                for (int c = 0; c < 3; c++) u[r].v[c] = ld_stream(row->v + c);
-            } else {
-                u[r] = *row;
-            }
-        }
+        for (int r = 0; r < N / 3; r++) u[r] = reinterpret_cast<const F3 *>(U + 3 * r * stride)[site];
     }
     __device__ __forceinline__ float2 get(int k) const { return u[k / 3].v[k % 3]; }
 };
@@ -494,12 +487,10 @@ __device__ __forceinline__ void clover_fetch(const HalfClover &cl, int, int i, i
     for (int m = 0; m < 15; m++) o[m] = __half22float2(q[1 + m / 3].v[m % 3]);
 }
 
-template <typename R, typename C, typename CL>
-__device__ __forceinline__ void clover_block(CL cl, int Vh, int i, int b, const C *v, C *out)
+// out = (block with diagonal d and upper triangle o) v
+template <typename R, typename C>
+__device__ __forceinline__ void clover_mul(const R *d, const C *o, const C *v, C *out)
 {
-    R d[6];
-    C o[15];
-    clover_fetch(cl, Vh, i, b, d, o);
 #pragma unroll
     for (int r = 0; r < 6; r++) out[r] = cscale(v[r], d[r]);
     int m = 0;
@@ -510,6 +501,15 @@ __device__ __forceinline__ void clover_block(CL cl, int Vh, int i, int b, const 
             cfma(out[r], o[m], v[q]);
             cfmac(out[q], o[m], v[r]);
         }
+}
+
+template <typename R, typename C, typename CL>
+__device__ __forceinline__ void clover_block(CL cl, int Vh, int i, int b, const C *v, C *out)
+{
+    R d[6];
+    C o[15];
+    clover_fetch(cl, Vh, i, b, d, o);
+    clover_mul(d, o, v, out);
 }
 
 template <typename R, typename C, typename CL>

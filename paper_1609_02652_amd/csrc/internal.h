@@ -215,7 +215,8 @@ struct pfmp_ctx {
     bool use_graphs = true;        // solver iterations replayed as HIP graphs
     bool half_links = true;        // FP16-storage solver reads the FP16 copies of links and clover
     int verbose = 0;               // 1: the HMC driver prints its progress to stderr
-    bool batch_multi = true;       // batched clover stencils: up to 4 rhs per lane pair sharing link loads
+    int batch_multi = 1;           // batched clover stencils: 0 one workgroup per (site block, rhs); 1 the
+                                   // default group of rhs per lane pair sharing link loads; 2 or 4 that group
     // clover-force insertions of several force terms summed into one field before a single
     // clover-force pass (set by the integrator for the terms due at one merged step)
     bool clover_defer = false;

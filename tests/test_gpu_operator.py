@@ -181,16 +181,25 @@ def test_batch_apply_matches_single(setup):
     for op, x, o in zip(opl, psis, outs):
         single = lat.apply_MdagM(op, x)
         assert torch.equal(o, single)
-    # FP32 fields, both layouts (up to 4 rhs per lane pair sharing each link load, and one
-    # workgroup per site block and rhs), five rhs (a group of 4 and a group of 1)
+    # FP32 fields, every layout (groups of 4 and of 2 rhs per lane pair sharing each link load,
+    # and one workgroup per site block and rhs), five rhs with mixed operators and with one
+    # operator for a whole group (its clover blocks fetched once for the group)
     from paper_1609_02652_amd.pfmp import F32
     p32 = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 75 + k), prec=F32) for k in range(5)]
-    ol = [0, 2, 0, 2, 2]
-    for multi in (True, False):
+    for ol in ([0, 2, 0, 2, 2], [0, 0, 0, 0, 2]):
+        for multi in (1, 4, 2, 0):
+            lat.batch_layout(multi)
+            for r, o in enumerate(lat.apply_MdagM_batch(ol, p32, prec=F32)):
+                assert torch.equal(o, lat.apply_MdagM(ol[r], p32[r], prec=F32)), (ol, multi, r)
+    # FP64, one operator for a group of 4
+    p64 = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 85 + k)) for k in range(4)]
+    for multi in (4, 2):
         lat.batch_layout(multi)
-        for r, o in enumerate(lat.apply_MdagM_batch(ol, p32, prec=F32)):
-            assert torch.equal(o, lat.apply_MdagM(ol[r], p32[r], prec=F32)), (multi, r)
+        for r, o in enumerate(lat.apply_MdagM_batch([2, 2, 2, 2], p64)):
+            assert torch.equal(o, lat.apply_MdagM(2, p64[r])), (multi, r)
     lat.batch_layout(True)
+    with pytest.raises(Exception):
+        lat.batch_layout(3)
 
 
 def test_batch_cg(setup):
@@ -206,12 +215,14 @@ def test_batch_cg(setup):
         xs1, st1 = lat.cg_solve(op, lat.pack_spinor(b), tol=1e-11)
         assert st1["iters"] == st["iters"]
         assert torch.equal(x, xs1)
-    # the other batch layout (one workgroup per site block and rhs): the same bits
-    lat.batch_layout(False)
-    xs2, sts2 = lat.cg_solve_batch(opl, [lat.pack_spinor(b) for b in bs], tol=1e-11, check_every=6)
+    # the other batch layouts (groups of 2 rhs per lane pair; one workgroup per site block and
+    # rhs): the same bits
+    for multi in (2, 0):
+        lat.batch_layout(multi)
+        xs2, sts2 = lat.cg_solve_batch(opl, [lat.pack_spinor(b) for b in bs], tol=1e-11, check_every=6)
+        for x, x2, st, st2 in zip(xs, xs2, sts, sts2):
+            assert st2["iters"] == st["iters"] and torch.equal(x, x2), multi
     lat.batch_layout(True)
-    for x, x2, st, st2 in zip(xs, xs2, sts, sts2):
-        assert st2["iters"] == st["iters"] and torch.equal(x, x2)
 
 
 def test_batch_cg_mixed(setup):
