@@ -132,7 +132,8 @@ __global__ __launch_bounds__(kFinishThreads) void k_m_finish_rr(const double *__
     }
 }
 
-// p = r + beta p (per site: FP16 storage needs the site's 24 reals for its scale).  With
+// p = r + beta p, two lanes per site (lane hb: chiral block hb; FP16 storage takes the site's
+// scale over both lanes' blocks, so the stored values are those of a one-lane update).  With
 // part_rr (INL): every block forms |r+|^2 from the stage-4 partials and takes the stop
 // decision from it and the iteration count M_ITNEXT (written by stage 4), the same in every
 // block, and skips the update on a stop, which the restart after a reliable update relies
@@ -159,17 +160,18 @@ __global__ __launch_bounds__(kBlock) void k_m_update_p(Geom g, const float2 *__r
         }
         if (done) return;
     }
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.Vh) return;
-    float2 rv[12], pv[12];
-    load_spinor(r, g.Vh, i, 1.f, rv);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t >> 1, hb = t & 1;
+    if (i >= g.Vh) return;   // both lanes of a pair leave together
+    float2 rv[6], pv[6];
+    load_block(r, g.Vh, i, hb, 1.f, rv);
     if (st) {
         const float b = (float)bd;
-        load_spinor(p, g.Vh, i, 1.f, pv);
+        load_block(p, g.Vh, i, hb, 1.f, pv);
 #pragma unroll
-        for (int k = 0; k < 12; k++) rv[k] = make_float2(fmadd(b, pv[k].x, rv[k].x), fmadd(b, pv[k].y, rv[k].y));
+        for (int k = 0; k < 6; k++) rv[k] = make_float2(fmadd(b, pv[k].x, rv[k].x), fmadd(b, pv[k].y, rv[k].y));
     }
-    store_spinor(p, g.Vh, i, 1.f, rv);
+    store_block(p, g.Vh, i, hb, 1.f, rv);
 }
 
 // x += xs (FP64 += FP32), xs = 0
@@ -288,7 +290,7 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
     }
     // r = b, rs = (float) b, p = rs
     hipLaunchKernelGGL(k_m_residual, dim3(ctx->nblk_red), dim3(kRedBlock), 0, ctx->stream, n, b, Kx, rs, ctx->red);
-    hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
+    hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(2L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
                        (double *)nullptr, (const double *)nullptr, 0);
     hipLaunchKernelGGL(k_m_restart, dim3(1), dim3(kRedBlock), 0, ctx->stream, ctx->red, ctx->nblk_red, tol2bb,
                        delta * delta, prm->maxiter, 1, sc);
@@ -320,7 +322,7 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
 #undef MHOP4
         if (!inl)
             hipLaunchKernelGGL(k_m_finish_rr, dim3(1), dim3(kFinishThreads), 0, ctx->stream, part_b, nb, sc);
-        hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
+        hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(2L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
                            sc, inl ? (const double *)part_b : (const double *)nullptr, nb);
         LAUNCHCHK(ctx);
         return 0;
@@ -358,7 +360,7 @@ static int mixed_impl(pfmp_ctx *ctx, int op, const void *b_, void *x_, const pfm
         if (rr <= tol2bb || h[M_DONE] == 2) break;
         hipLaunchKernelGGL(k_m_restart, dim3(1), dim3(kRedBlock), 0, ctx->stream, ctx->red, ctx->nblk_red, tol2bb,
                            delta * delta, prm->maxiter, 0, sc);
-        hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
+        hipLaunchKernelGGL((k_m_update_p<S>), dim3(nblocks(2L * g.Vh, kBlock)), dim3(kBlock), 0, ctx->stream, g, rs, ps,
                            sc, (const double *)nullptr, 0);
         LAUNCHCHK(ctx);
         // the next chunk: about as long as the last stretch between reliable updates

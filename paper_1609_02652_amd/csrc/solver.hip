@@ -209,8 +209,10 @@ __global__ __launch_bounds__(kRedBlock) void k_cg_update_p(long n, const double2
     } else {
         b = st[S_BETA];
     }
-    const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (e < n) {
+    // six complex numbers per lane (grid-stride), so that a sixth as many workgroups form the
+    // inline total
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += stride) {
         double2 rv = r[e], pv = p[e];
         p[e] = make_double2(fmadd(b, pv.x, rv.x), fmadd(b, pv.y, rv.y));
     }
@@ -431,10 +433,10 @@ extern "C" int pfmp_cg_solve(pfmp_ctx *ctx, int op, const void *b_, void *x_, co
             hipLaunchKernelGGL(k_cg_finish_rr, dim3(1), dim3(kFinishThreads), 0, ctx->stream, B.part_b, nb,
                                ctx->scal);
         if (inl)
-            hipLaunchKernelGGL(k_cg_update_p<1>, dim3(nblocks(n, kRedBlock)), dim3(kRedBlock), 0, ctx->stream, n,
+            hipLaunchKernelGGL(k_cg_update_p<1>, dim3(nblocks((n + 5) / 6, kRedBlock)), dim3(kRedBlock), 0, ctx->stream, n,
                                B.r, B.p, ctx->scal, B.part_b, nb);
         else
-            hipLaunchKernelGGL(k_cg_update_p<0>, dim3(nblocks(n, kRedBlock)), dim3(kRedBlock), 0, ctx->stream, n,
+            hipLaunchKernelGGL(k_cg_update_p<0>, dim3(nblocks((n + 5) / 6, kRedBlock)), dim3(kRedBlock), 0, ctx->stream, n,
                                B.r, B.p, ctx->scal, B.part_b, nb);
         LAUNCHCHK(ctx);
         return 0;
