@@ -933,7 +933,7 @@ def config5_bench(args):
     # on K(0.1370), and one force evaluation of every row of the action (all its solves) at
     # the thermalised field with the heatbath's pseudofermions
     cmp = {}
-    for name, prec in (("plain_f64", F64), ("chosen", F16)):
+    for name, prec in (() if args.c5_no_compare else (("plain_f64", F64), ("chosen", F16))):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, st = lat.cg_solve(0, b, tol=TOL, prec=prec, maxiter=100000)
@@ -942,8 +942,8 @@ def config5_bench(args):
                                           "true_res": st["true_res"]}
         log("config5 CG %s: %s" % (name, cmp["cg_kappa_0.1370_" + name]))
     ed = [lat.pack_spinor(e) for e in etas]
-    phis = lat.heatbath(config5_spec(lat, steps, solver_prec=F16), ed)
-    for name, kw in (("plain_f64", {}), ("chosen", dict(solver_prec=F16))):
+    phis = lat.heatbath(config5_spec(lat, steps, solver_prec=F16), ed) if not args.c5_no_compare else None
+    for name, kw in (() if args.c5_no_compare else (("plain_f64", {}), ("chosen", dict(solver_prec=F16)))):
         sp = config5_spec(lat, steps, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -952,10 +952,11 @@ def config5_bench(args):
         cmp["force_evaluation_" + name] = {"s": round(time.perf_counter() - t0, 3),
                                            "max_force_rows": [round(float(v), 4) for v in fn[:, 0]]}
         log("config5 force evaluation %s: %s" % (name, cmp["force_evaluation_" + name]))
-    cmp["cg_speedup"] = round(cmp["cg_kappa_0.1370_plain_f64"]["s"] / cmp["cg_kappa_0.1370_chosen"]["s"], 3)
-    cmp["force_evaluation_speedup"] = round(cmp["force_evaluation_plain_f64"]["s"] /
-                                            cmp["force_evaluation_chosen"]["s"], 3)
-    out["fp64_vs_chosen"] = cmp
+    if cmp:
+        cmp["cg_speedup"] = round(cmp["cg_kappa_0.1370_plain_f64"]["s"] / cmp["cg_kappa_0.1370_chosen"]["s"], 3)
+        cmp["force_evaluation_speedup"] = round(cmp["force_evaluation_plain_f64"]["s"] /
+                                                cmp["force_evaluation_chosen"]["s"], 3)
+        out["fp64_vs_chosen"] = cmp
     del ed, phis
     torch.cuda.empty_cache()
     modes = [("chosen", dict(solver_prec=F16)), ("plain_f64", {})]
@@ -1060,6 +1061,8 @@ def main():
     ap.add_argument("--c5-therm", type=int, default=20, help="quenched thermalisation trajectories")
     ap.add_argument("--c5-therm-steps", type=int, default=64, help="2MN steps of a thermalisation trajectory")
     ap.add_argument("--c5-modes", default="both", choices=["both", "chosen", "plain_f64", "none"])
+    ap.add_argument("--c5-no-compare", action="store_true",
+                    help="skip the FP64-against-chosen CG and force-evaluation comparison")
     ap.add_argument("--cpu-full", action="store_true",
                     help="the oracle on the host: a full solve and the 4^4 trajectory, 1 thread and all threads")
     ap.add_argument("--cpu-child", choices=["cg", "traj"], help=argparse.SUPPRESS)
