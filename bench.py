@@ -885,7 +885,7 @@ def config5_bench(args):
     from paper_1609_02652_amd.pfmp import Lattice, F64, F16
     steps = tuple(int(v) for v in args.c5_steps.split(","))
     dims = tuple(int(v) for v in args.c5_dims.split(","))
-    out = {"lattice": "x".join(map(str, dims)), "steps_gauge_filter_corr_ratio": steps}
+    out = {"lattice": "x".join(map(str, dims)), "steps_gauge_filter_corr_ratio": steps, "tau": args.c5_tau}
     t0 = time.perf_counter()
     U = synth.random_gauge(dims, seed=0)
     log("config5: seeded start field %.1f s" % (time.perf_counter() - t0))
@@ -965,7 +965,7 @@ def config5_bench(args):
     out["trajectory"] = {}
     for name, kw in modes:
         lat.set_gauge(U0)
-        sp = config5_spec(lat, steps, **kw)
+        sp = config5_spec(lat, steps, tau=args.c5_tau, **kw)
         Pd = lat.pack_momenta(P)
         ed = [lat.pack_spinor(e) for e in etas]
         torch.cuda.empty_cache()   # the library allocates outside torch's cache
@@ -1061,6 +1061,7 @@ def main():
     ap.add_argument("--c5-therm", type=int, default=20, help="quenched thermalisation trajectories")
     ap.add_argument("--c5-therm-steps", type=int, default=64, help="2MN steps of a thermalisation trajectory")
     ap.add_argument("--c5-modes", default="both", choices=["both", "chosen", "plain_f64", "none"])
+    ap.add_argument("--c5-tau", type=float, default=1.0, help="trajectory length of the timed trajectories")
     ap.add_argument("--c5-no-compare", action="store_true",
                     help="skip the FP64-against-chosen CG and force-evaluation comparison")
     ap.add_argument("--cpu-full", action="store_true",
