@@ -476,8 +476,7 @@ __global__ void k_b_accum(long n, double s, const float2 *__restrict__ e, double
         }                                                   \
     } while (0)
 // right-hand sides per lane pair in the multi-rhs layout (at most 4): the context's choice, or
-// by default 4 in FP32 and FP64
-template <typename R>
+// by default 4 (measured fastest in FP32 and FP64)
 static int multi_group(const pfmp_ctx *ctx)
 {
     return ctx->batch_multi == 2 || ctx->batch_multi == 4 ? ctx->batch_multi : 4;
@@ -548,7 +547,7 @@ static int apply_batch(pfmp_ctx *ctx, const BatchT<R> &b, const C *U, int nrhs, 
     // Mhat in -> te (stage 1 to to, stage 2 to te), then Mhat^dag te -> out
     if (use_multi(ctx, b)) {
         dim3 grid(op_nparts(g));
-        const int mg = multi_group<R>(ctx);
+        const int mg = multi_group(ctx);
         for (int r0 = 0; r0 < nrhs; r0 += mg) {
             const int nr = std::min(mg, nrhs - r0);
             BMLAUNCH(k_bm_clovinv, C, R, nr, grid, g, b, in_to, U, (R)1, (R)1, (const double *)nullptr, r0);
@@ -646,7 +645,7 @@ static int batch_cg_core(pfmp_ctx *ctx, const BatchT<R> &b, const void *const *b
     const C *U = sizeof(R) == 8 ? (const C *)ctx->U : (const C *)ctx->Uf;
     int chunk = check_every > 0 ? check_every : 25;
     const bool multi = use_multi(ctx, b);
-    const int mg = multi_group<R>(ctx);
+    const int mg = multi_group(ctx);
     dim3 gridm(op_nparts(g));
     // one iteration for all rhs: 7 launches with fixed arguments (4 more per further group of
     // 4 rhs in the multi-rhs layout), replayed as a graph; each rhs takes the single-RHS CG's

@@ -403,8 +403,7 @@ class Lattice:
     def batch_layout(self, multi):
         """Batched clover stencils: True / 1 the default group of rhs per lane pair, 2 or 4
         that many rhs per lane pair, False / 0 one workgroup per (site block, rhs)."""
-        m = int(multi) if not isinstance(multi, bool) else int(multi)
-        self._chk(self.lib.pfmp_set_batch_layout(self.h, m), "set_batch_layout")
+        self._chk(self.lib.pfmp_set_batch_layout(self.h, int(multi)), "set_batch_layout")
 
     def cg_solve_batch(self, ops, bs, xs=None, tol=1e-10, maxiter=10000, check_every=0, prec=F64):
         n = len(bs)
