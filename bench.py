@@ -1233,6 +1233,8 @@ def main():
         "trajectory": {
             "light_quark_48x48x48x96": "not in this line (minutes per trajectory): bench.py --config5, "
                                        "results in profiles/config5_trajectory_48x48x48x96.md",
+            "markov_chain_16x16x16x32": "not in this line (300 trajectories, 6 minutes): bench.py --chain 300, "
+                                        "P_acc, <exp(-dH)> and the cost C in profiles/pfmp_chain_16x16x16x32.md",
             "correctness_workload_4x4x4x4": traj1,
             "pfmp_16x16x16x32_context": traj16},
         "multi_rhs_Khat_32x32x32x64": extra32.get("multi_rhs_Khat"),
