@@ -69,7 +69,10 @@ def time_kernel(lat, fn, reps):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def batch_apply(lat, reps=20):
+BATCH_LAYOUTS = ((1, "multi"), (2, "multi2"), (0, "wg"))
+
+
+def batch_apply(lat, reps=20, layouts=BATCH_LAYOUTS):
     """4-RHS Khat against 4 single-RHS Khat in FP64 and FP32, for 4 sources of one operator and
     for the Hasenbusch chain's operators (kappa 0.1340, 0.1300, 0.1250, 0.1340), in the
     multi-rhs layout (each link load shared by the rhs of a lane pair: the default group of 4,
@@ -84,7 +87,7 @@ def batch_apply(lat, reps=20):
         outs = [lat.field(prec=prec) for _ in range(4)]
         t1 = time_kernel(lat, lambda: lat.apply_MdagM(0, xs[0], out=outs[0], prec=prec), reps)
         for oname, ops in (("same_op", [0, 0, 0, 0]), ("chain", [0, 1, 2, 0])):
-            for multi, lname in ((1, "multi"), (2, "multi2"), (0, "wg")):
+            for multi, lname in layouts:
                 lat.batch_layout(multi)
                 t4 = time_kernel(lat, lambda: lat.apply_MdagM_batch(ops, xs, outs, prec=prec), reps)
                 res["%s_%s_%s" % (pname, oname, lname)] = {
@@ -174,6 +177,24 @@ def roofline_only(reps):
     e1.synchronize()
     t = e0.elapsed_time(e1) / 1e3 / reps
     out["copy_256MiB"] = {"us": round(t * 1e6, 2), "GBps_read_plus_write": round(2 * n * 8 / t / 1e9, 1)}
+    print(json.dumps(out), flush=True)
+
+
+def batch_only(reps, zts=None):
+    """Only the multi-RHS Khat comparison at 32^3x64 (after autotuning) and a plain copy of
+    known size, for hardware-counter runs on the batched stencils.  zts: also repeat the
+    comparison (groups of 4 rhs per lane pair) under each of these site visit orders."""
+    from paper_1609_02652_amd import synth
+    big = (32, 32, 32, 64)
+    lat = make_lattice(big, synth.random_gauge(big, seed=5))
+    out = {"tuning": lat.autotune(0)}
+    out["multi_rhs_Khat_32x32x32x64"] = batch_apply(lat, reps)
+    for zt in zts or ():
+        lat.site_order(zt)
+        out["site_order_zt%d" % zt] = r = batch_apply(lat, reps, layouts=BATCH_LAYOUTS[:1])
+        log("zt %d: %s" % (zt, r))
+    lat.close()
+    out["copy_256MiB"] = copy_bandwidth(reps)
     print(json.dumps(out), flush=True)
 
 
@@ -862,7 +883,7 @@ C5_HASEN = (0.120, 0.130, 0.135)
 C5_NEST = (6, 20, 62)
 
 
-def config5_spec(lat, steps, **kw):
+def config5_spec(lat, steps, tol=TOL, **kw):
     """Slots 0 = K (0.1370), 1 = J (0.120, the filter nest), 2 = 0.130, 3 = 0.135.  Scales
     (steps = gauge, filter, correction, ratios): {gauge + S_det}, {P_6, Q(20/6), Q(62/20)},
     {correction [J P_62(J)]^-1, ratio J(0.120)/K(0.130)}, {ratios 0.130/0.135 and 0.135/0.1370}."""
@@ -873,7 +894,24 @@ def config5_spec(lat, steps, **kw):
     terms = [f("poly", p1, n_p), f("polyq", p2, n_p, p1), f("polyq", p3, n_p, p2), f("polycorr", p3, n_c),
              dict(kind="ratio", op=1, op2=2, steps=n_c), dict(kind="ratio", op=2, op2=3, steps=n_r),
              dict(kind="ratio", op=3, op2=0, steps=n_l)]
-    return lat.spec(C5_BETA, terms, n_g, det_op=0, tol=TOL, **kw)
+    return lat.spec(C5_BETA, terms, n_g, det_op=0, tol=tol, **kw)
+
+
+def config5_action_check(lat, steps, P, ed):
+    """Accuracy of the action evaluation at this volume: the heatbath (chosen solver, the
+    trajectories' tolerance) makes S_j(phi_j) = eta_j^dag eta_j; each S_j is then evaluated
+    with plain FP64 solves to 1e-10 and 1e-13 and with the chosen solver to 1e-10."""
+    from paper_1609_02652_amd.pfmp import F64, F16
+    eta2 = [lat.dot(e, e).real for e in ed]
+    phis = lat.heatbath(config5_spec(lat, steps, solver_prec=F16), ed)
+    out = {"eta_dag_eta": eta2}
+    for name, tol, prec in (("plain_f64_1e-10", 1e-10, F64), ("chosen_1e-10", 1e-10, F16),
+                            ("plain_f64_1e-13", 1e-13, F64)):
+        _, parts = lat.hamiltonian(config5_spec(lat, steps, tol=tol, solver_prec=prec), P, phis)
+        d = [a - b for a, b in zip(parts[3:], eta2)]
+        out[name] = {"S_minus_eta_dag_eta": d, "max_abs": max(abs(v) for v in d)}
+        log("config5 actions, %s: max |S_j - eta_j^dag eta_j| = %.3g" % (name, out[name]["max_abs"]))
+    return out
 
 
 def config5_bench(args):
@@ -958,6 +996,9 @@ def config5_bench(args):
                                                 cmp["force_evaluation_chosen"]["s"], 3)
         out["fp64_vs_chosen"] = cmp
     del ed, phis
+    if args.c5_action_check:
+        out["action_check"] = config5_action_check(lat, steps, lat.pack_momenta(P),
+                                                   [lat.pack_spinor(e) for e in etas])
     torch.cuda.empty_cache()
     modes = [("chosen", dict(solver_prec=F16)), ("plain_f64", {})]
     if args.c5_modes != "both":
@@ -1033,6 +1074,10 @@ def main():
     ap.add_argument("--therm", type=int, default=20, help="quenched thermalisation trajectories")
     ap.add_argument("--roofline-only", action="store_true",
                     help="time only the hopping kernels and a plain copy (for counter runs)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="time only the multi-RHS Khat comparison at 32^3 x 64 and a plain copy (for counter runs)")
+    ap.add_argument("--batch-zt", help="with --batch-only: repeat the comparison under these site visit orders, "
+                                       "e.g. 0,1,2,4,8,16")
     ap.add_argument("--tune", action="store_true",
                     help="the paper's step-size tuning (F_i h_i = const, P_acc in [0.65, 0.75]) and cost "
                          "C = N_mat / P_acc for the PF-MP action")
@@ -1062,6 +1107,9 @@ def main():
     ap.add_argument("--c5-therm-steps", type=int, default=64, help="2MN steps of a thermalisation trajectory")
     ap.add_argument("--c5-modes", default="both", choices=["both", "chosen", "plain_f64", "none"])
     ap.add_argument("--c5-tau", type=float, default=1.0, help="trajectory length of the timed trajectories")
+    ap.add_argument("--c5-action-check", action="store_true",
+                    help="after the set-up: each action term at the heatbath field solved to 1e-10 and 1e-13 "
+                         "against eta^dag eta")
     ap.add_argument("--c5-no-compare", action="store_true",
                     help="skip the FP64-against-chosen CG and force-evaluation comparison")
     ap.add_argument("--cpu-full", action="store_true",
@@ -1083,6 +1131,9 @@ def main():
         sys.exit(2)
     if args.roofline_only:
         roofline_only(max(args.steps, 10))
+        return
+    if args.batch_only:
+        batch_only(max(args.steps, 10), [int(v) for v in args.batch_zt.split(",")] if args.batch_zt else None)
         return
     if args.zoo:
         zoo_bench(args)
@@ -1231,8 +1282,9 @@ def main():
         "cg_solve": dict(cg, tol=TOL, sources=args.steps, chosen=chosen,
                          speedup_chosen_vs_f64=round(cg["f64"]["mean_s"] / t_chosen, 3)),
         "trajectory": {
-            "light_quark_48x48x48x96": "not in this line (minutes per trajectory): bench.py --config5, "
-                                       "results in profiles/config5_trajectory_48x48x48x96.md",
+            "light_quark_48x48x48x96": "not in this line (7-14 minutes per trajectory): bench.py --config5, "
+                                       "plain FP64 and chosen trajectories with dH and the accept decisions "
+                                       "in profiles/config5_trajectory_48x48x48x96.md",
             "markov_chain_16x16x16x32": "not in this line (300 trajectories, 6 minutes): bench.py --chain 300, "
                                         "P_acc, <exp(-dH)> and the cost C in profiles/pfmp_chain_16x16x16x32.md",
             "correctness_workload_4x4x4x4": traj1,
