@@ -217,6 +217,39 @@ __device__ __forceinline__ void rhs_active(const double *__restrict__ st, int r0
     for (int q = 0; q < NR; q++) act[q] = !st || st[8 * (r0 + q) + B_DONE] == 0;
 }
 
+// Memory hints of the multi-rhs kernels.  Their outputs, the spinors read only at the site itself
+// and (FP64, when the context streams links) the links are touched once per launch, so they go
+// through non-temporal loads and stores, leaving L2 to the neighbour spinors, which four
+// right-hand sides make four times as large (32^3 x 64, 4 rhs: FP64 K-hat per rhs 0.665 -> 0.618
+// of a single one, FP32 0.660 -> 0.647, the same bits).
+__device__ __forceinline__ void st_stream(double2 *p, double2 v)
+{
+    nt_d2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_d2 *>(p));
+}
+__device__ __forceinline__ void st_stream(float2 *p, float2 v)
+{
+    nt_f2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_f2 *>(p));
+}
+template <typename C>
+__device__ __forceinline__ void store_block_stream(C *__restrict__ f, int Vh, int i, int hb, decltype(C::x) gs,
+                                                   const C *v)
+{
+#pragma unroll
+    for (int k = 0; k < 6; k++) st_stream(f + (long)(6 * hb + k) * Vh + i, hb ? cscale(v[k], gs) : v[k]);
+}
+template <typename C>
+__device__ __forceinline__ void load_block_stream(const C *__restrict__ f, int Vh, int i, int hb, decltype(C::x) gs,
+                                                  C *v)
+{
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        C a = ld_stream(f + (long)(6 * hb + k) * Vh + i);
+        v[k] = hb ? cscale(a, gs) : a;
+    }
+}
+
 // the clover blocks of a launch's rhs: fetched once when every rhs of the launch uses the same
 // field (one operator), else per rhs (uniform in the workgroup)
 template <int NR, typename R>
@@ -311,9 +344,9 @@ __global__ __launch_bounds__(kBlock) void k_bm_clovinv(Geom g, BatchT<R> b, Vecs
             C tq[6];
             if (!same) clover_fetch(b.clo[r0 + q], g.Vh, i, hb, d, o);
             clover_mul(d, o, blk[q], tq);
-            store_block(v.out[r0 + q], g.Vh, i, hb, gout, tq);
+            store_block_stream(v.out[r0 + q], g.Vh, i, hb, gout, tq);
         } else {
-            store_block(v.out[r0 + q], g.Vh, i, hb, gout, blk[q]);
+            store_block_stream(v.out[r0 + q], g.Vh, i, hb, gout, blk[q]);
         }
     }
 }
@@ -342,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_bm_xpay(Geom g, BatchT<R> b, VecsT<C
         for (int q = 0; q < NR; q++) {
             if (!act[q]) continue;
             C xv[6], ax[6];
-            load_block(x.in[r0 + q], g.Vh, i, hb, gs, xv);
+            load_block_stream(x.in[r0 + q], g.Vh, i, hb, gs, xv);
             if (CLOV) {
                 if (!same) clover_fetch(b.cle[r0 + q], g.Vh, i, hb, d, o);
                 clover_mul(d, o, xv, ax);
@@ -354,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_bm_xpay(Geom g, BatchT<R> b, VecsT<C
                 acc[q][k] = mk<C>(fmadd(a, acc[q][k].x, base.x), fmadd(a, acc[q][k].y, base.y));
                 cnorm_acc(nrm[q], acc[q][k]);
             }
-            store_block(x.out[r0 + q], g.Vh, i, hb, gs, acc[q]);
+            store_block_stream(x.out[r0 + q], g.Vh, i, hb, gs, acc[q]);
         }
     }
     if (partials)
@@ -394,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_bm_hop4(Geom g, BatchT<R> b, VecsT<C
             const int r = r0 + q;
             const double *s = st + 8 * r;
             C tv[6], at[6];
-            load_block(t.in[r], g.Vh, i, hb, (R)-1, tv);
+            load_block_stream(t.in[r], g.Vh, i, hb, (R)-1, tv);
             if (CLOV) {
                 if (!same) clover_fetch(b.cle[r], g.Vh, i, hb, d, o);
                 clover_mul(d, o, tv, at);
@@ -408,11 +441,11 @@ __global__ __launch_bounds__(kBlock) void k_bm_hop4(Geom g, BatchT<R> b, VecsT<C
                 C kp = mk<C>(fmadd(a, acc[q][k].x, base.x), fmadd(a, acc[q][k].y, base.y));
                 if (hb) kp = cneg(kp);
                 const long e = (long)(6 * hb + k) * Vh + i;
-                C pv = pp[e], xv = xx[e], rv = rv_[e];
+                C pv = ld_stream(pp + e), xv = ld_stream(xx + e), rv = ld_stream(rv_ + e);
                 xv.x = fmadd(alpha, pv.x, xv.x); xv.y = fmadd(alpha, pv.y, xv.y);
                 rv.x = fmadd(-alpha, kp.x, rv.x); rv.y = fmadd(-alpha, kp.y, rv.y);
-                xx[e] = xv;
-                rv_[e] = rv;
+                st_stream(xx + e, xv);
+                st_stream(rv_ + e, rv);
                 cnorm_acc(nrm[q], rv);
             }
         }
@@ -441,8 +474,8 @@ __global__ void k_b_accum(long n, double s, const float2 *__restrict__ e, double
 
 }  // namespace
 
-// launch the (C, R, CLOV, link mode) instance of a batch stencil kernel.  Link loads are
-// never streaming here: the n workgroups of a site block read the same links, and the
+// launch the (C, R, CLOV, link mode) instance of a workgroup-per-rhs stencil kernel.  Link
+// loads are never streaming here: the n workgroups of a site block read the same links, and the
 // copy the first one brings into L2 is what the others reuse (on 32^3 x 64, 4
 // right-hand sides: 0.85 of the single-RHS time per rhs, against 1.0 with streaming).
 #define BLAUNCH(K, C, R, b, grid, block, shm, stream, ...)                                                   \
@@ -458,13 +491,19 @@ __global__ void k_b_accum(long n, double s, const float2 *__restrict__ e, double
     } while (0)
 
 // launch the (C, R, clover, link mode, NR) instance of a multi-rhs kernel for the nr (1..4)
-// right-hand sides from r0; the grid covers the sites once (XCD-aware order)
-#define BM_LM(K, C, R, NR, grid, ...)                                                                      \
-    do {                                                                                                 \
-        if ((link_mode(ctx->g) & 1) == 0)                                                                \
-            hipLaunchKernelGGL((K<C, R, 1, 0, NR>), grid, dim3(kBlock), 0, ctx->stream, __VA_ARGS__);    \
-        else                                                                                             \
-            hipLaunchKernelGGL((K<C, R, 1, 1, NR>), grid, dim3(kBlock), 0, ctx->stream, __VA_ARGS__);    \
+// right-hand sides from r0, in the context's link mode (each link is read once per site here,
+// so the FP64 links stream when the context streams them); the grid covers the sites once
+// (XCD-aware order)
+#define BM_LM_ONE(K, C, R, NR, LMV, grid, ...) \
+    hipLaunchKernelGGL((K<C, R, 1, LMV, NR>), grid, dim3(kBlock), 0, ctx->stream, __VA_ARGS__)
+#define BM_LM(K, C, R, NR, grid, ...)                                 \
+    do {                                                            \
+        switch (link_mode(ctx->g)) {                                \
+        case 0: BM_LM_ONE(K, C, R, NR, 0, grid, __VA_ARGS__); break;  \
+        case 1: BM_LM_ONE(K, C, R, NR, 1, grid, __VA_ARGS__); break;  \
+        case 2: BM_LM_ONE(K, C, R, NR, 2, grid, __VA_ARGS__); break;  \
+        default: BM_LM_ONE(K, C, R, NR, 3, grid, __VA_ARGS__); break; \
+        }                                                           \
     } while (0)
 #define BMLAUNCH(K, C, R, nr, grid, ...)                    \
     do {                                                    \
