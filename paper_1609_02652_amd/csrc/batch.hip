@@ -217,38 +217,11 @@ __device__ __forceinline__ void rhs_active(const double *__restrict__ st, int r0
     for (int q = 0; q < NR; q++) act[q] = !st || st[8 * (r0 + q) + B_DONE] == 0;
 }
 
-// Memory hints of the multi-rhs kernels.  Their outputs, the spinors read only at the site itself
-// and (FP64, when the context streams links) the links are touched once per launch, so they go
-// through non-temporal loads and stores, leaving L2 to the neighbour spinors, which four
-// right-hand sides make four times as large (32^3 x 64, 4 rhs: FP64 K-hat per rhs 0.665 -> 0.618
-// of a single one, FP32 0.660 -> 0.647, the same bits).
-__device__ __forceinline__ void st_stream(double2 *p, double2 v)
-{
-    nt_d2 w = {v.x, v.y};
-    __builtin_nontemporal_store(w, reinterpret_cast<nt_d2 *>(p));
-}
-__device__ __forceinline__ void st_stream(float2 *p, float2 v)
-{
-    nt_f2 w = {v.x, v.y};
-    __builtin_nontemporal_store(w, reinterpret_cast<nt_f2 *>(p));
-}
-template <typename C>
-__device__ __forceinline__ void store_block_stream(C *__restrict__ f, int Vh, int i, int hb, decltype(C::x) gs,
-                                                   const C *v)
-{
-#pragma unroll
-    for (int k = 0; k < 6; k++) st_stream(f + (long)(6 * hb + k) * Vh + i, hb ? cscale(v[k], gs) : v[k]);
-}
-template <typename C>
-__device__ __forceinline__ void load_block_stream(const C *__restrict__ f, int Vh, int i, int hb, decltype(C::x) gs,
-                                                  C *v)
-{
-#pragma unroll
-    for (int k = 0; k < 6; k++) {
-        C a = ld_stream(f + (long)(6 * hb + k) * Vh + i);
-        v[k] = hb ? cscale(a, gs) : a;
-    }
-}
+// Memory hints of the multi-rhs kernels: when the context streams links (large lattices), their
+// outputs, the spinors read only at the site itself and the FP64 links, all touched once per
+// launch, go through non-temporal loads and stores, leaving L2 to the neighbour spinors, which
+// four right-hand sides make four times as large (32^3 x 64, 4 rhs: FP64 K-hat per rhs 0.665 ->
+// 0.617 of a single one, FP32 0.660 -> 0.637, the same bits).
 
 // the clover blocks of a launch's rhs: fetched once when every rhs of the launch uses the same
 // field (one operator), else per rhs (uniform in the workgroup)
@@ -344,9 +317,9 @@ __global__ __launch_bounds__(kBlock) void k_bm_clovinv(Geom g, BatchT<R> b, Vecs
             C tq[6];
             if (!same) clover_fetch(b.clo[r0 + q], g.Vh, i, hb, d, o);
             clover_mul(d, o, blk[q], tq);
-            store_block_stream(v.out[r0 + q], g.Vh, i, hb, gout, tq);
+            store_block_st<(LM >> 1) & 1>(v.out[r0 + q], g.Vh, i, hb, gout, tq);
         } else {
-            store_block_stream(v.out[r0 + q], g.Vh, i, hb, gout, blk[q]);
+            store_block_st<(LM >> 1) & 1>(v.out[r0 + q], g.Vh, i, hb, gout, blk[q]);
         }
     }
 }
@@ -375,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_bm_xpay(Geom g, BatchT<R> b, VecsT<C
         for (int q = 0; q < NR; q++) {
             if (!act[q]) continue;
             C xv[6], ax[6];
-            load_block_stream(x.in[r0 + q], g.Vh, i, hb, gs, xv);
+            load_block_st<(LM >> 1) & 1>(x.in[r0 + q], g.Vh, i, hb, gs, xv);
             if (CLOV) {
                 if (!same) clover_fetch(b.cle[r0 + q], g.Vh, i, hb, d, o);
                 clover_mul(d, o, xv, ax);
@@ -387,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_bm_xpay(Geom g, BatchT<R> b, VecsT<C
                 acc[q][k] = mk<C>(fmadd(a, acc[q][k].x, base.x), fmadd(a, acc[q][k].y, base.y));
                 cnorm_acc(nrm[q], acc[q][k]);
             }
-            store_block_stream(x.out[r0 + q], g.Vh, i, hb, gs, acc[q]);
+            store_block_st<(LM >> 1) & 1>(x.out[r0 + q], g.Vh, i, hb, gs, acc[q]);
         }
     }
     if (partials)
@@ -427,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_bm_hop4(Geom g, BatchT<R> b, VecsT<C
             const int r = r0 + q;
             const double *s = st + 8 * r;
             C tv[6], at[6];
-            load_block_stream(t.in[r], g.Vh, i, hb, (R)-1, tv);
+            load_block_st<(LM >> 1) & 1>(t.in[r], g.Vh, i, hb, (R)-1, tv);
             if (CLOV) {
                 if (!same) clover_fetch(b.cle[r], g.Vh, i, hb, d, o);
                 clover_mul(d, o, tv, at);
@@ -441,11 +414,12 @@ __global__ __launch_bounds__(kBlock) void k_bm_hop4(Geom g, BatchT<R> b, VecsT<C
                 C kp = mk<C>(fmadd(a, acc[q][k].x, base.x), fmadd(a, acc[q][k].y, base.y));
                 if (hb) kp = cneg(kp);
                 const long e = (long)(6 * hb + k) * Vh + i;
-                C pv = ld_stream(pp + e), xv = ld_stream(xx + e), rv = ld_stream(rv_ + e);
+                C pv = ld_st<(LM >> 1) & 1>(pp + e), xv = ld_st<(LM >> 1) & 1>(xx + e),
+                  rv = ld_st<(LM >> 1) & 1>(rv_ + e);
                 xv.x = fmadd(alpha, pv.x, xv.x); xv.y = fmadd(alpha, pv.y, xv.y);
                 rv.x = fmadd(-alpha, kp.x, rv.x); rv.y = fmadd(-alpha, kp.y, rv.y);
-                st_stream(xx + e, xv);
-                st_stream(rv_ + e, rv);
+                st_st<(LM >> 1) & 1>(xx + e, xv);
+                st_st<(LM >> 1) & 1>(rv_ + e, rv);
                 cnorm_acc(nrm[q], rv);
             }
         }

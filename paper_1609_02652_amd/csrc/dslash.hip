@@ -27,9 +27,9 @@ __global__ __launch_bounds__(kBlock) void k_hop_clovinv(Geom g, int pout, const 
     if (CLOV) {
         C t[6];
         clover_block<R, C>(cl, g.Vh, i, hb, blk, t);
-        store_block(out, g.Vh, i, hb, gout, t);
+        store_block_st<(LM >> 1) & 1>(out, g.Vh, i, hb, gout, t);
     } else {
-        store_block(out, g.Vh, i, hb, gout, blk);
+        store_block_st<(LM >> 1) & 1>(out, g.Vh, i, hb, gout, blk);
     }
 }
 
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const X x
         const int i = tile_site(g, tt >> 1), hb = tt & 1;
         C acc[6], xv[6], ax[6];
         hop_pair<LM, C>(g, pout, i, hb, t, U, (R)1, acc);
-        load_block(x, g.Vh, i, hb, gs, xv);
+        load_block_st<(LM >> 1) & 1>(x, g.Vh, i, hb, gs, xv);
         if (CLOV) clover_block<R, C>(cl, g.Vh, i, hb, xv, ax);
 #pragma unroll
         for (int k = 0; k < 6; k++) {
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_hop_xpay(Geom g, int pout, const X x
             acc[k] = mk<C>(fmadd(a, acc[k].x, base.x), fmadd(a, acc[k].y, base.y));
             if (NORM) cnorm_acc(nrm, acc[k]);
         }
-        store_block(out, g.Vh, i, hb, gs, acc);
+        store_block_st<(LM >> 1) & 1>(out, g.Vh, i, hb, gs, acc);
     }
     if (NORM) {
         const double v[1] = {nrm};

@@ -487,6 +487,58 @@ __device__ __forceinline__ void clover_fetch(const HalfClover &cl, int, int i, i
     for (int m = 0; m < 15; m++) o[m] = __half22float2(q[1 + m / 3].v[m % 3]);
 }
 
+// Non-temporal variants (ST = 1) for data a launch touches once: on lattices whose links
+// stream (the gauge field beyond the last-level cache) the outputs and the site-local inputs
+// of the stencil kernels go the same way, leaving L2 to the neighbour spinors, which are read
+// up to eight times (32^3 x 64: FP64 hop 280 -> 259 us, the same bits).  FP16 records keep
+// cached accesses.
+__device__ __forceinline__ void st_stream(double2 *p, double2 v)
+{
+    nt_d2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_d2 *>(p));
+}
+__device__ __forceinline__ void st_stream(float2 *p, float2 v)
+{
+    nt_f2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_f2 *>(p));
+}
+template <int ST, typename C>
+__device__ __forceinline__ C ld_st(const C *p)
+{
+    return ST ? ld_stream(p) : *p;
+}
+template <int ST, typename C>
+__device__ __forceinline__ void st_st(C *p, C v)
+{
+    if (ST) st_stream(p, v);
+    else *p = v;
+}
+template <int ST, typename C>
+__device__ __forceinline__ void load_block_st(const C *__restrict__ f, int Vh, int i, int hb, decltype(C::x) gs, C *v)
+{
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        C a = ld_st<ST>(f + (long)(6 * hb + k) * Vh + i);
+        v[k] = hb ? cscale(a, gs) : a;
+    }
+}
+template <int ST>
+__device__ __forceinline__ void load_block_st(const HalfField &f, int Vh, int i, int hb, float gs, float2 *v)
+{
+    load_block(f, Vh, i, hb, gs, v);
+}
+template <int ST, typename C>
+__device__ __forceinline__ void store_block_st(C *__restrict__ f, int Vh, int i, int hb, decltype(C::x) gs, const C *v)
+{
+#pragma unroll
+    for (int k = 0; k < 6; k++) st_st<ST>(f + (long)(6 * hb + k) * Vh + i, hb ? cscale(v[k], gs) : v[k]);
+}
+template <int ST>
+__device__ __forceinline__ void store_block_st(const HalfField &f, int Vh, int i, int hb, float gs, const float2 *v)
+{
+    store_block(f, Vh, i, hb, gs, v);
+}
+
 // out = (block with diagonal d and upper triangle o) v
 template <typename R, typename C>
 __device__ __forceinline__ void clover_mul(const R *d, const C *o, const C *v, C *out)

@@ -86,8 +86,11 @@ __global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T,
         const int i = tile_site(g, tt >> 1), hb = tt & 1;
         float2 acc[6], tv[6], at[6], pp[6];
         hop_pair<LM, float2>(g, 0, i, hb, T, U, 1.f, acc);
-        load_block(t, g.Vh, i, hb, -1.f, tv);
-        load_block(p, g.Vh, i, hb, 1.f, pp);
+        // site-local vectors: non-temporal when the links stream (large lattices; FP16
+        // records stay cached)
+        constexpr int ST = (LM >> 1) & 1;
+        load_block_st<ST>(t, g.Vh, i, hb, -1.f, tv);
+        load_block_st<ST>(p, g.Vh, i, hb, 1.f, pp);
         if (CLOV) clover_block<float, float2>(cl, g.Vh, i, hb, tv, at);
         const float alpha = (float)alpha_d;
         const long Vh = g.Vh;
@@ -97,11 +100,11 @@ __global__ __launch_bounds__(kBlock) void k_m_hop4(Geom g, const S t, const S T,
             float2 kp = make_float2(fmadd(a, acc[k].x, base.x), fmadd(a, acc[k].y, base.y));
             if (hb) kp = cneg(kp);
             const long e = (long)(6 * hb + k) * Vh + i;
-            float2 pv = pp[k], xv = x[e], rv = r[e];
+            float2 pv = pp[k], xv = ld_st<ST>(x + e), rv = ld_st<ST>(r + e);
             xv.x = fmadd(alpha, pv.x, xv.x); xv.y = fmadd(alpha, pv.y, xv.y);
             rv.x = fmadd(-alpha, kp.x, rv.x); rv.y = fmadd(-alpha, kp.y, rv.y);
-            x[e] = xv;
-            r[e] = rv;
+            st_st<ST>(x + e, xv);
+            st_st<ST>(r + e, rv);
             cnorm_acc(nrm, rv);
         }
     }

@@ -119,7 +119,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
         const int i = tile_site(g, tt >> 1), hb = tt & 1;
         double2 acc[6], tv[6], at[6];
         hop_pair<LM, double2>(g, 0, i, hb, T, U, 1.0, acc);
-        load_block(t, g.Vh, i, hb, -1.0, tv);
+        // site-local vectors: non-temporal when the links stream (large lattices)
+        constexpr int ST = (LM >> 1) & 1;
+        load_block_st<ST>(t, g.Vh, i, hb, -1.0, tv);
         if (CLOV) clover_block<double, double2>(cl, g.Vh, i, hb, tv, at);
         const long Vh = g.Vh;
 #pragma unroll
@@ -128,11 +130,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_hop4(Geom g, const double2 *__res
             double2 kp = make_double2(fmadd(a, acc[k].x, base.x), fmadd(a, acc[k].y, base.y));
             if (hb) kp = cneg(kp);
             const long e = (long)(6 * hb + k) * Vh + i;
-            double2 pv = p[e], xv = x[e], rv = r[e];
+            double2 pv = ld_st<ST>(p + e), xv = ld_st<ST>(x + e), rv = ld_st<ST>(r + e);
             xv.x = fmadd(alpha, pv.x, xv.x); xv.y = fmadd(alpha, pv.y, xv.y);
             rv.x = fmadd(-alpha, kp.x, rv.x); rv.y = fmadd(-alpha, kp.y, rv.y);
-            x[e] = xv;
-            r[e] = rv;
+            st_st<ST>(x + e, xv);
+            st_st<ST>(r + e, rv);
             cnorm_acc(nrm, rv);
         }
     }
