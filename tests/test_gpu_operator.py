@@ -337,6 +337,34 @@ def test_link_streaming_bitwise(setup):
         assert np.array_equal(a, b)
 
 
+def test_streaming_hints_bitwise_mixed_and_batch(setup):
+    """With streaming link loads the stencils also store their outputs, and read their
+    site-local vectors, non-temporally; these are cache hints only: the mixed-precision
+    solves (FP32 and FP16 storage), the multi-rhs K-hat (FP64, FP32) and a batched CG give
+    the same bits either way."""
+    dims, U, lat, ops = setup
+    from paper_1609_02652_amd.pfmp import F64, F32, F16
+    f = lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 31))
+    srcs = [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 32 + k)) for k in range(4)]
+    srcs32 = [lat.convert_spinor(s, F64, F32) for s in srcs]
+    out = []
+    for stream in (0, 1):
+        lat.link_streaming(stream)
+        r = []
+        for prec in (F32, F16):
+            x, st = lat.cg_solve(0, f, tol=1e-10, prec=prec)
+            r += [x.cpu().numpy(), st["iters"]]
+        r += [o.cpu().numpy() for o in lat.apply_MdagM_batch([0, 0, 2, 0], srcs)]
+        r += [o.cpu().numpy() for o in lat.apply_MdagM_batch([0, 2, 2, 0], srcs32, prec=F32)]
+        xs, sts = lat.cg_solve_batch([0, 2], srcs[:2], tol=1e-10)
+        r += [x.cpu().numpy() for x in xs] + [s["iters"] for s in sts]
+        out.append(r)
+    lat.link_streaming(0)
+    assert len(out[0]) == len(out[1])
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
 def test_graph_replay_matches_eager(setup):
     """Solver iterations replayed as HIP graphs give the eager launches' results bit for
     bit, for several solves in a row (each replaying graphs captured earlier), with
