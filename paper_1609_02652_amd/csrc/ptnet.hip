@@ -819,6 +819,7 @@ extern "C" int pfmp_ptnet_grad(pfmp_ctx *ctx, const double *W, int op, int npair
     std::vector<double> acc(2 * NW, 0.0);
     double tot = 0;
     std::vector<double> tmp(2 * NW);   // holds either the A2|A0 block (800) or the A1 block (768)
+    static_assert(NW1 <= NW && NW2 + NW0 <= NW, "tmp holds the A1 block or the A2|A0 block");
     for (int p = 0; p < npairs; p++) {
         const double2 *r = (const double2 *)R[p];
         double nr = host_norm(ctx, r, &rc);
