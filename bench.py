@@ -923,7 +923,8 @@ def config5_bench(args):
     from paper_1609_02652_amd.pfmp import Lattice, F64, F16
     steps = tuple(int(v) for v in args.c5_steps.split(","))
     dims = tuple(int(v) for v in args.c5_dims.split(","))
-    out = {"lattice": "x".join(map(str, dims)), "steps_gauge_filter_corr_ratio": steps, "tau": args.c5_tau}
+    out = {"lattice": "x".join(map(str, dims)), "steps_gauge_filter_corr_ratio": steps, "tau": args.c5_tau,
+           "tol": args.c5_tol}
     t0 = time.perf_counter()
     U = synth.random_gauge(dims, seed=0)
     log("config5: seeded start field %.1f s" % (time.perf_counter() - t0))
@@ -1006,7 +1007,7 @@ def config5_bench(args):
     out["trajectory"] = {}
     for name, kw in modes:
         lat.set_gauge(U0)
-        sp = config5_spec(lat, steps, tau=args.c5_tau, **kw)
+        sp = config5_spec(lat, steps, tol=args.c5_tol, tau=args.c5_tau, **kw)
         Pd = lat.pack_momenta(P)
         ed = [lat.pack_spinor(e) for e in etas]
         torch.cuda.empty_cache()   # the library allocates outside torch's cache
@@ -1107,6 +1108,8 @@ def main():
     ap.add_argument("--c5-therm-steps", type=int, default=64, help="2MN steps of a thermalisation trajectory")
     ap.add_argument("--c5-modes", default="both", choices=["both", "chosen", "plain_f64", "none"])
     ap.add_argument("--c5-tau", type=float, default=1.0, help="trajectory length of the timed trajectories")
+    ap.add_argument("--c5-tol", type=float, default=TOL, help="relative residual of every solve of the timed "
+                                                              "trajectories")
     ap.add_argument("--c5-action-check", action="store_true",
                     help="after the set-up: each action term at the heatbath field solved to 1e-10 and 1e-13 "
                          "against eta^dag eta")
