@@ -98,6 +98,24 @@ def test_term_heatbath_and_force(U0, term):
         assert abs(F[link // 4, link % 4, a] - ref) < 2e-6 * max(1, abs(ref))
 
 
+HIGH_DEGREE = [dict(kind="polyq", kappa=0.120, n=62, n1=20, mu=1.2, nu=0.9),
+               dict(kind="polycorr", kappa=0.120, n=20, mu=1.2, nu=0.9)]
+
+
+@pytest.mark.parametrize("term", HIGH_DEGREE, ids=["polyq62_20", "polycorr20"])
+def test_high_degree_filter_force(U0, term):
+    """The filter nest's degrees (the quotient Q(62/20), a degree-20 correction): the forces
+    still differentiate the actions.  The step of the differences is larger than above
+    because a degree-62 product loses a few more digits of the action to rounding."""
+    ops = hmc.Ops(DIMS, U0, 1.6)
+    phi = hmc.heatbath(ops, term, synth.gaussian_spinor(VH, 30))
+    F = hmc.force(ops, term, phi, 1e-13)
+    fun = lambda U: hmc.action(hmc.Ops(DIMS, U, 1.6), term, phi, 1e-13)
+    for link, a in SAMPLES[:3]:
+        ref = fd(fun, U0, link, a, eps=3e-3)
+        assert abs(F[link // 4, link % 4, a] - ref) < 1e-4 * abs(ref) + 1e-8
+
+
 def test_polynomial_force_matrix_count(U0):
     """The incremental construction of eq. force_poly costs 2p - 2 K-mults (Table 3.2)."""
     g = json.load(open(os.path.join(GOLD, "poly_force_counts.json")))
