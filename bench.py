@@ -1019,7 +1019,9 @@ def config5_bench(args):
         dt = time.perf_counter() - t0
         out["trajectory"][name] = {"s": round(dt, 2), "dH": st["dH"], "accept": st["accept"],
                                    "kmults": st["kmults"], "solver_iters": st["solver_iters"],
-                                   "nforce": list(st["nforce"][:8]), "H0": st["H0"]}
+                                   "nforce": list(st["nforce"][:8]), "H0": st["H0"],
+                                   # change of each part of H (kinetic, S_G, S_det, the terms)
+                                   "dparts": [b - a for a, b in zip(st["parts0"], st["parts1"])]}
         log("config5 %s: %.1f s, dH %.4f, accept %d, %d Khat multiplications" % (name, dt, st["dH"], st["accept"],
                                                                                 st["kmults"]))
     if "chosen" in out["trajectory"] and "plain_f64" in out["trajectory"]:
