@@ -74,3 +74,26 @@ def test_cg_iteration_bytes(prec, real_bytes):
     stage4 = links + 3 * spinor + clover + 4 * spinor
     update = 3 * spinor
     assert bench.CG_ITER_BYTES[prec] == real_bytes * (2 * stage1 + stage2 + stage4 + update)
+
+
+def test_light_quark_spec():
+    """The light-quark workload's action: the filter nest (6, 20, 62) on the 0.120 slot, its
+    correction with the first ratio on one scale, the lightest ratio on a scale of its own,
+    S_det of the 0.1370 slot, and the tolerance passed through."""
+    from paper_1609_02652_amd.pfmp import Lattice, TERM_KINDS
+
+    class Stub:
+        spec = staticmethod(Lattice.spec)
+
+    sp = bench.config5_spec(Stub(), (32, 8, 4, 16, 48), tol=1e-12, tau=0.5)
+    kinds = {v: k for k, v in TERM_KINDS.items()}
+    got = [(kinds[sp.terms[j].kind], sp.terms[j].op, sp.terms[j].op2, sp.terms[j].n, sp.terms[j].n1,
+            sp.terms[j].steps) for j in range(sp.nterms)]
+    assert got == [("poly", 1, -1, 6, 0, 8), ("polyq", 1, -1, 20, 6, 8), ("polyq", 1, -1, 62, 20, 8),
+                   ("polycorr", 1, -1, 62, 0, 4), ("ratio", 1, 2, 0, 0, 4), ("ratio", 2, 3, 0, 0, 16),
+                   ("ratio", 3, 0, 0, 0, 48)]
+    assert (sp.gauge_steps, sp.det_op, sp.tol, sp.tau, sp.beta) == (32, 0, 1e-12, 0.5, bench.C5_BETA)
+    assert bench.C5_HASEN == (0.120, 0.130, 0.135) and bench.C5_KAPPA == 0.1370
+    # (p1 + 1) | (p2 + 1) for every level of the nest (App. A factorisation)
+    p = bench.C5_NEST
+    assert all((p[k + 1] + 1) % (p[k] + 1) == 0 for k in range(len(p) - 1))
