@@ -1211,7 +1211,7 @@ def main():
     # preconditioner, and the 16^3 x 32 PF-MP trajectory of the previous headline
     lat.set_operator(2, 0.1250, CSW)
     batched = batch_bench(lat)
-    learned, W_net = learned_bench(lat, 8)
+    learned, _ = learned_bench(lat, 8)
     learned["speedup_vs_f64_cg"] = round(cg["f64"]["median_s"] / learned["fcg_median_s"], 3)
     learned["iters_saved_vs_f64_cg"] = round(1 - learned["fcg_iters"] / cg["f64"]["iters"], 3)
     traj16 = {}
