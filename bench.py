@@ -964,6 +964,23 @@ def config5_bench(args):
     lat.half_links(half)
     out["cg_f16_kappa_0.1370"] = {"half_links_1": {"s": round(hl[1][0], 3), "iters": hl[1][1]},
                                   "half_links_0": {"s": round(hl[0][0], 3), "iters": hl[0][1]}, "chosen": half}
+    # optional relaxation with the fermions: molecular-dynamics trajectories of the full action
+    # (chosen mode, the timed trajectories' steps and length, every one kept), so that the timed
+    # ones start nearer the equilibrium of the dynamical action than the quenched field does
+    if args.c5_dyn_therm:
+        sp_d = config5_spec(lat, steps, tol=args.c5_tol, tau=args.c5_tau, solver_prec=F16)
+        t0 = time.perf_counter()
+        for k in range(args.c5_dyn_therm):
+            # heatbath, then the molecular dynamics alone: the evolved field is kept whatever dH
+            phis_k = lat.heatbath(sp_d, [lat.pack_spinor(synth.gaussian_spinor(lat.Vh, 9200 + 7 * k + j))
+                                         for j in range(7)])
+            st = lat.md_evolve(sp_d, lat.pack_momenta(synth.gaussian_momenta(lat.V, 9100 + k)), phis_k)
+            del phis_k
+            plaq = 1.0 - lat.gauge_action(C5_BETA) / (C5_BETA * 6 * lat.V)
+            log("config5 relaxation with the fermions %d: %d solver iterations, plaquette %.5f"
+                % (k, st["solver_iters"], plaq))
+        out["dynamical_relaxation"] = {"trajectories": args.c5_dyn_therm, "plaquette": round(plaq, 6),
+                                       "seconds": round(time.perf_counter() - t0, 1)}
     U0 = lat.get_gauge().clone()
     P = synth.gaussian_momenta(lat.V, 9500)
     etas = [synth.gaussian_spinor(lat.Vh, 9600 + j) for j in range(7)]
@@ -1112,6 +1129,9 @@ def main():
     ap.add_argument("--c5-tau", type=float, default=1.0, help="trajectory length of the timed trajectories")
     ap.add_argument("--c5-tol", type=float, default=TOL, help="relative residual of every solve of the timed "
                                                               "trajectories")
+    ap.add_argument("--c5-dyn-therm", type=int, default=0,
+                    help="molecular-dynamics trajectories of the full action (chosen mode, every one kept) "
+                         "before the timed ones")
     ap.add_argument("--c5-action-check", action="store_true",
                     help="after the set-up: each action term at the heatbath field solved to 1e-10 and 1e-13 "
                          "against eta^dag eta")
